@@ -1,0 +1,204 @@
+"""Throughput of the bispectrum-multipole hot path on one MI355X.
+
+One step = one full measurement (weights, y-weighted TSC+interlaced assignment,
+forward FFTs, shell filters, inverse FFTs, 3j-weighted reduction, normalisation)
+of one 256^3 mock, with its catalogue already resident in HBM:
+  box L = 1000 Mpc/h, 256^3 grid, TSC + interlacing, local LOS from an observer
+  1500 Mpc/h below the box centre, 20 shells of dk = 0.01 h/Mpc from 0,
+  B_000 (210 pairs k1 <= k2) and B_202 (400 pairs), particles log-uniform in
+  [3e5, 3e6] (seeded lognormal + Kaiser mocks; steps cycle over the mocks).
+
+Prints one JSON line with throughput (mocks/s), the roofline of the dominant
+kernel (algorithmic bytes per launch / its mean duration from HIP events on the
+launch stream) and the FP64 oracle timed on a bounded sample on the host.
+"""
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+WORKLOAD = dict(n=256, box_len=1000.0, n_bins=20, dk=0.01, k_min=0.0, multipoles=[(0, 0, 0), (2, 0, 2)],
+                assign_p=3, interlace=True, los="local", observer=(500.0, 500.0, -1000.0), box_mode=True,
+                precision="f32", pair_mode="paper")
+SEEDS = [48, 49, 50, 51]
+KERNEL_SOURCES = {  # which source file holds each stage's kernel
+    "assign": "assign.hip", "fwd_z": "fft.hip", "fwd_y": "fft.hip", "fwd_x": "fft.hip",
+    "invF_z": "fft.hip", "invF_y": "fft.hip", "invF_x": "fft.hip", "invG_z": "fft.hip",
+    "invG_y": "fft.hip", "invG_x": "fft.hip", "reduce": "reduce.hip"}
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def stage_bytes(info, copies, n_particles, esz=4):
+    """Algorithmic HBM bytes per launch of each single-kernel stage: every input
+    read once and every output written once in the stated layout."""
+    c = 2 * esz
+    N, M = info.n, info.m
+    PG, PF = 2 * info.r_g + 1, 2 * info.r_f + 1
+    ng = info.n_grids
+    nbc = copies * ng
+    nf = info.n_fslots * WORKLOAD["n_bins"]
+    return {
+        "assign": nbc * N ** 3 * c + 12 * n_particles,
+        "fwd_z": nbc * N ** 3 * c + nbc * N * N * PG * c,
+        "fwd_y": nbc * N * N * PG * c + nbc * N * PG * PG * c,
+        "fwd_x": nbc * N * PG * PG * c + nbc * PG ** 3 * c,
+        "invF_z": PF ** 3 * c + nf * PF * PF * M * c,
+        "invF_y": nf * PF * PF * M * c + nf * PF * M * M * c,
+        "invF_x": nf * PF * M * M * c + nf * M ** 3 * c,
+        "invG_z": ng * PG ** 3 * c + ng * PG * PG * M * c,
+        "invG_y": ng * PG * PG * M * c + ng * PG * M * M * c,
+        "invG_x": ng * PG * M * M * c + ng * M ** 3 * c,
+        "reduce": (nf + ng) * M ** 3 * c,
+    }
+
+
+def source_hash(fname):
+    with open(os.path.join(ROOT, "paper_1803_02132_amd", "csrc", fname), "rb") as fh:
+        return hashlib.sha256(fh.read()).hexdigest()[:16]
+
+
+def load_traffic(stage, bytes_alg):
+    """HBM bytes per launch from committed rocprofv3 counter summaries, if they
+    were taken on the current kernel source; else None."""
+    path = os.path.join(ROOT, "profiles", f"traffic_{stage}.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        rec = json.load(fh)
+    if rec.get("source_sha256_16") != source_hash(KERNEL_SOURCES[stage]):
+        return None
+    return rec.get("hbm_bytes_per_launch")
+
+
+def cpu_baseline(cat, threads=1):
+    """The FP64 oracle on a bounded sample of one mock, scaled to one mock.
+
+    Timed pieces: the front end (weights, all channel assignments, FFTs,
+    deconvolution) on the whole mock; one G field; one F field; and a one-pair
+    reduction (both multipoles) from which the per-pair cost follows. One mock
+    = front + 6 G + 120 F + 400 pair evaluations (every (b1, b2) for both
+    multipoles)."""
+    from threadpoolctl import threadpool_limits
+    from oracle import estimator as est
+    w = WORKLOAD
+    plan = est.Plan(n=w["n"], box_len=w["box_len"], multipoles=w["multipoles"], n_bins=w["n_bins"],
+                    dk=w["dk"], k_min=w["k_min"], assign_p=w["assign_p"], interlace=w["interlace"],
+                    los=w["los"], observer=w["observer"], box_mode=w["box_mode"])
+    with threadpool_limits(limits=threads):
+        t0 = time.perf_counter()
+        grids, info = est.assign_channels(plan, cat)
+        spec = est.spectra(plan, grids)
+        del grids
+        t_front = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        est.g_field(plan, spec, 2, 1)
+        t_g = time.perf_counter() - t0
+        bg = est.bin_grid(plan)
+        units = est.mode_unit_vectors(plan)
+        nm = est.nmode(plan)
+        t0 = time.perf_counter()
+        est.f_field(plan, spec, 2, 1, 10, bg, units, nm)
+        t_f = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        est.reduce_fft(plan, spec, info["I"], pairs=[(10, 10)])
+        t_pair_total = time.perf_counter() - t0
+    n_g = 6              # G_0^0 and G_2^M, M = -2..2
+    n_f_per_shell = 6    # F_0^0 and F_2^m, m = -2..2
+    t_pair = max(t_pair_total - n_g * t_g - n_f_per_shell * t_f, 0.0)
+    sec = t_front + n_g * t_g + w["n_bins"] * n_f_per_shell * t_f + w["n_bins"] ** 2 * t_pair
+    sample_s = t_front + t_g + t_f + t_pair_total
+    return {"value": 1.0 / sec, "unit": "mocks/s", "cores": threads, "kind": "oracle",
+            "sample": (f"FP64 NumPy oracle, {threads} thread(s): front end on the whole mock "
+                       f"({t_front:.1f} s), one G field ({t_g:.2f} s), one F field ({t_f:.2f} s), one "
+                       f"shell pair for both multipoles ({t_pair_total:.1f} s incl. its 6 G and 6 F fields); "
+                       f"one mock = front + 6 G + 120 F + 400 pairs = {sec:.0f} s; "
+                       f"sample took {sample_s:.0f} s")}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=40)
+    ap.add_argument("--warmup", type=int, default=4)
+    ap.add_argument("--mocks", type=int, default=len(SEEDS))
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the path shards by mock "
+              "across GPUs without communication, see DESIGN.md", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_1803_02132_amd as tsb
+    from mocks.lognormal import workload
+
+    torch.cuda.set_device(0)
+    seeds = SEEDS[:max(1, args.mocks)]
+    cats, devs = [], []
+    for s in seeds:
+        spec, cat = workload("box256", seed=s)
+        cats.append(cat)
+        devs.append(tsb.catalog_to_device(cat))
+        log(f"mock seed {s}: {len(cat['pos'])} particles")
+    plan = tsb.Plan(**WORKLOAD)
+    info = plan.info
+    log(f"plan: N={info.n} M={info.m} r_f={info.r_f} r_g={info.r_g} outputs={info.n_outputs} "
+        f"workspace={info.workspace_bytes / 1e9:.2f} GB")
+    for i in range(args.warmup):
+        plan.measure(devs[i % len(devs)])
+    tsb.abi.tsb_plan_set_profiling(plan.handle, True)
+    tsb.abi.tsb_plan_stage_times(plan.handle, reset=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        plan.measure(devs[i % len(devs)])
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    elapsed = t1 - t0
+    value = args.steps / elapsed
+    times = tsb.abi.tsb_plan_stage_times(plan.handle)
+    n_mean = float(np.mean([len(c["pos"]) for c in cats]))
+    bytes_alg = stage_bytes(info, 2, n_mean)
+    per_launch = {k: (ms / calls if calls else 0.0) for k, (ms, calls) in times.items()}
+    log("stage mean ms per launch: " + ", ".join(f"{k}={v:.3f}" for k, v in per_launch.items()))
+    dom = max((k for k in bytes_alg), key=lambda k: times[k][0])
+    dur_s = per_launch[dom] * 1e-3
+    achieved = bytes_alg[dom] / dur_s / 1e9
+    traffic = load_traffic(dom, bytes_alg[dom])
+    roof = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+            "bytes_per_launch": int(bytes_alg[dom]), "mean_launch_ms": round(per_launch[dom], 4)}
+    out = {
+        "metric": "mocks/sec for B_000+B_202 all k-bin pairs at 256^3",
+        "value": round(value, 3), "unit": "mocks/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(1e3 * elapsed / args.steps, 3), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": ("256^3 box, L=1000 Mpc/h, TSC+interlacing, local LOS from an observer 1500 Mpc/h "
+                                "below the centre, 20 shells dk=0.01 h/Mpc, B_000 (210 pairs) + B_202 (400 pairs), "
+                                "seeded lognormal+Kaiser mocks, N_p log-uniform in [3e5, 3e6]"),
+                   "seeds": seeds, "n_particles_mean": int(n_mean), "reduction_grid": info.m},
+        "roofline": roof,
+        "stage_ms": {k: round(v, 4) for k, v in per_launch.items()},
+    }
+    if not args.no_cpu_baseline:
+        log("timing the oracle on the host ...")
+        out["cpu_baseline"] = cpu_baseline(cats[0])
+    else:
+        out["cpu_baseline"] = None
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

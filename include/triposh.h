@@ -1,0 +1,203 @@
+/*
+ * triposh.h -- C ABI of the MI355X (gfx950) bispectrum-multipole library.
+ *
+ * Computes the decomposed bispectrum multipoles B_{l1 l2 L}(k1, k2) of a
+ * weighted particle catalogue with the FFT-based estimator of Sugiyama, Saito,
+ * Beutler & Seo, arXiv:1803.02132:
+ *   - y-weighted density fields dn_L^M(x) = y_L^M*(x^) dn(x)       (Sec. 4.1, eq. 34)
+ *   - mass assignment and W_mass deconvolution                      (Sec. 4.2, eq. 39)
+ *   - F_l^m(x;k) and G_L^M(x) by inverse FFTs                       (Sec. 4.2, eq. 42)
+ *   - B = H sum_{m1 m2 M} 3j (N/I) int d3x F F G                    (Sec. 4.2, eq. 41;
+ *                                                                     Sec. 4.4, eq. 51)
+ *   - normalisation I                                               (Sec. 4.2, eq. 37; Sec. 4.4)
+ *
+ * Conventions fixed by the library where the paper is silent:
+ *   - grid nodes sit at origin + j * L/N (j = 0..N-1 per axis), periodic;
+ *     grid coordinate u = (x - origin) * (N / L) evaluated in FP64;
+ *   - assignment kernels NGP/CIC/TSC of Hockney & Eastwood (App. C);
+ *   - interlacing: second grid from particles shifted by +L/(2N) per axis,
+ *     combined as (D1 + e^{i pi (nx+ny+nz)/N} D2)/2 before dividing by W_mass;
+ *   - k-shells [k_min + b dk, k_min + (b+1) dk) in |k| (eq. 38), membership
+ *     floor((k_f sqrt(n^2) - k_min)/dk) per integer n^2 in FP64, DC excluded;
+ *   - modes with an index component equal to N/2 are zero in every field;
+ *   - periodic box (box_mode = 1): dn = n - nbar with nbar = sum w / V, i.e.
+ *     (sum w / N^3) y_L^M*(x^_node) is subtracted at every node, the DC mode
+ *     of dn_0^0 is zero, and I = (sum w)^3 / V^2;
+ *   - survey (box_mode = 0): dn = data - alpha randoms with
+ *     alpha = sum_data w / sum_rand w (Sec. 4.1), I = v_c sum_j (alpha R_j/v_c)^3
+ *     with R the randoms assigned on the first grid;
+ *   - FKP weight (Sec. 5.2, eq. 53): w = w_c / (1 + nbar P0) when P0 > 0 and
+ *     the catalogue carries nbar; otherwise w = w_c.
+ *
+ * Every call returns 0 (TSB_OK) or a negative tsb_status; nothing throws across
+ * the ABI. tsb_last_error() returns a thread-local message for the last failure.
+ * All device work is enqueued on the caller's HIP stream; calls that return
+ * results to host memory synchronise that stream before returning.
+ * Calls on one plan must not overlap (a plan owns one workspace).
+ */
+#ifndef TRIPOSH_H
+#define TRIPOSH_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  TSB_OK = 0,
+  TSB_E_ARG = -1,          /* NULL pointer, size or value out of range */
+  TSB_E_UNSUPPORTED = -2,  /* valid request the library does not implement */
+  TSB_E_NOMEM = -3,        /* device allocation failed */
+  TSB_E_INPUT = -4,        /* bad particle data: NaN/Inf position or weight,
+                              survey particle outside the box, particle on the observer */
+  TSB_E_DEVICE = -5        /* a HIP call failed */
+} tsb_status;
+
+enum { TSB_LOS_GLOBAL = 0, TSB_LOS_LOCAL = 1 };
+enum { TSB_NGP = 1, TSB_CIC = 2, TSB_TSC = 3 };
+enum { TSB_FP32 = 0, TSB_FP64 = 1 };
+enum { TSB_PAIRS_PAPER = 0,      /* b1 <= b2 when l1 == l2, else every (b1, b2) (Sec. 5.2) */
+       TSB_PAIRS_UPPER = 1,      /* b1 <= b2 */
+       TSB_PAIRS_DIAGONAL = 2,   /* b1 == b2 (Sec. 4.4, "diagonal" measurement) */
+       TSB_PAIRS_ALL = 3 };
+
+/* Measurement grid (Sec. 4.2; Sec. 5.2 "Prescription"). */
+typedef struct {
+  int32_t n;          /* grid points per side N: 2^a 3^b, 16 <= N <= 1024, N % 4 == 0 */
+  double box_len;     /* side L of the cubic box, > 0 */
+  double origin[3];   /* position of node (0,0,0) */
+  int32_t assign_p;   /* TSB_NGP, TSB_CIC or TSB_TSC: W_mass exponent p (eq. 39) */
+  int32_t interlace;  /* 0 or 1 */
+} tsb_grid;
+
+/* Line of sight (Sec. 2; Sec. 4.2 local vertex x^3; Sec. 4.4 global). */
+typedef struct {
+  int32_t kind;        /* TSB_LOS_GLOBAL or TSB_LOS_LOCAL */
+  double dir[3];       /* global: LOS direction (normalised by the library) */
+  double observer[3];  /* local: observer position; the LOS of a particle is
+                          the unit vector from the observer to it */
+} tsb_los;
+
+/* Linear k-shells (eq. 38): [k_min + b dk, k_min + (b+1) dk), b = 0..n_bins-1.
+ * Every shell must lie below the Nyquist frequency pi N / L. */
+typedef struct {
+  int32_t n_bins;     /* 1..64 */
+  double k_min;       /* >= 0 */
+  double dk;          /* > 0 */
+} tsb_kbins;
+
+/* One multipole (l1, l2, L) (Sec. 2, eq. 11). Accepted when L is even,
+ * |l1-l2| <= L <= l1+l2, l1+l2+L is even (Table 1) and l1, l2, L <= 8;
+ * l1 < l2 is accepted (the transpose of (l2, l1, L)). */
+typedef struct {
+  int32_t l1, l2, L;
+} tsb_multipole;
+
+typedef struct {
+  int32_t precision;  /* TSB_FP32: fields and FFTs in FP32, reduction, 3j and
+                         normalisation in FP64; TSB_FP64: FP64 throughout */
+  int32_t pair_mode;  /* TSB_PAIRS_* */
+  int32_t box_mode;   /* 1: periodic box without randoms; 0: survey with randoms */
+  double P0;          /* FKP P0; <= 0 disables the FKP factor */
+} tsb_options;
+
+/* Particle catalogue: structure of arrays in DEVICE memory of the current
+ * device, owned by the caller and only read. w and nbar may be NULL
+ * (w_c = 1; no FKP factor). n may be 0. */
+typedef struct {
+  const float* x;
+  const float* y;
+  const float* z;
+  const float* w;
+  const float* nbar;
+  int64_t n;
+} tsb_catalog;
+
+/* Derived sizes of a plan. */
+typedef struct {
+  int32_t n;               /* measurement grid N */
+  int32_t m;               /* reduction grid M (<= N): the estimator's sum over
+                              cells is evaluated exactly on an M^3 grid when the
+                              shells and G are band-limited (see DESIGN) */
+  int32_t r_f;             /* largest |n_i| of any mode in any shell */
+  int32_t r_g;             /* largest |n_i| of the modes G needs */
+  int32_t n_channels;      /* real y-weighted density channels per grid */
+  int32_t n_fields_f;      /* real F fields per shell */
+  int32_t n_fields_g;      /* real G fields */
+  int32_t n_outputs;       /* (multipole, b1, b2) entries computed */
+  int32_t n_grids;         /* complex grids per assignment copy (two real channels each) */
+  int32_t n_fslots;        /* complex F transforms per shell */
+  int64_t workspace_bytes; /* device memory held by the plan */
+} tsb_plan_info;
+
+typedef struct tsb_plan tsb_plan;
+
+/* Validate the request and build a plan on the current device: term list
+ * (3j weights), shell table, N_mode, buffers. On success *out owns device
+ * memory until tsb_plan_destroy. Errors: TSB_E_ARG (NULL pointers, sizes),
+ * TSB_E_UNSUPPORTED (N not 2^a 3^b, multipole outside Table 1's rules, shells
+ * reaching the Nyquist frequency, l > 8), TSB_E_NOMEM, TSB_E_DEVICE. */
+int tsb_plan_create(const tsb_grid* grid, const tsb_los* los, const tsb_kbins* bins,
+                    const tsb_multipole* multipoles, int32_t n_multipoles,
+                    const tsb_options* options, tsb_plan** out);
+
+int tsb_plan_destroy(tsb_plan* plan);
+
+/* Host-only: validate a request exactly as tsb_plan_create does and report its
+ * derived sizes (info, may be NULL) and N_mode per shell (nmode, n_bins
+ * entries, may be NULL) without touching any device. Same error codes. */
+int tsb_plan_query(const tsb_grid* grid, const tsb_los* los, const tsb_kbins* bins,
+                   const tsb_multipole* multipoles, int32_t n_multipoles,
+                   const tsb_options* options, tsb_plan_info* info, int64_t* nmode);
+
+int tsb_plan_get_info(const tsb_plan* plan, tsb_plan_info* info);
+
+/* N_mode(b) (eq. 38) and the mean |k| of each shell, into caller-owned host
+ * arrays of n_bins entries (k_eff may be NULL). */
+int tsb_plan_nmode(const tsb_plan* plan, int64_t* nmode, double* k_eff);
+
+/* The full hot path: weights, y-weighted assignment, forward FFTs, shell
+ * filters, inverse FFTs, 3j-weighted reduction, normalisation.
+ *   data     catalogue (device);
+ *   randoms  catalogue (device), required iff box_mode == 0, else ignored;
+ *   stream   hipStream_t (NULL: the default stream);
+ *   B_out    host array [n_multipoles][n_bins][n_bins] (b2 fastest); entries
+ *            outside the plan's pair set are NaN; real part of eq. 41;
+ *   I_out    host scalar, the normalisation I (may be NULL);
+ *   alpha_out host scalar, alpha (0 in box mode) (may be NULL).
+ * Synchronises the stream. Errors: TSB_E_ARG, TSB_E_INPUT, TSB_E_DEVICE. */
+int tsb_measure(tsb_plan* plan, const tsb_catalog* data, const tsb_catalog* randoms,
+                void* stream, double* B_out, double* I_out, double* alpha_out);
+
+/* Stage entry point for checking the assignment: writes the y-weighted,
+ * mean-subtracted density grids (before any FFT) into the caller-owned
+ * device buffer grids_out, laid out [copy][channel][ix][iy][iz] with iz
+ * fastest, copy = 0 (first grid) or 1 (interlaced grid, if enabled), and
+ * channel c = 0..n_channels-1 in the order reported by tsb_plan_channel.
+ * Element type: float (TSB_FP32) or double (TSB_FP64). Synchronises. */
+int tsb_assign(tsb_plan* plan, const tsb_catalog* data, const tsb_catalog* randoms,
+               void* stream, void* grids_out);
+
+/* Which real channel c holds: y-weight of multipole L, azimuth M >= 0, and
+ * part (0: Re of w y_L^M*, 1: Im of w y_L^M*). */
+int tsb_plan_channel(const tsb_plan* plan, int32_t c, int32_t* L, int32_t* M, int32_t* part);
+
+/* Stage timing. With profiling enabled, every later tsb_measure records HIP
+ * events around each stage on the caller's stream and accumulates the elapsed
+ * times. Stages (index: name): 0 weights, 1 bucket, 2 assign, 3 fwd_z, 4 fwd_y,
+ * 5 fwd_x, 6 combine, 7 invF_z, 8 invF_y, 9 invF_x, 10 invG_z, 11 invG_y,
+ * 12 invG_x, 13 reduce, 14 reduce_final. Each of 3..13 is one kernel launch per
+ * measurement (13: one per block of 4096 outputs). tsb_plan_stage_times writes
+ * up to n entries of accumulated milliseconds and call counts (either array may
+ * be NULL) and, with reset != 0, clears the accumulators. */
+int tsb_plan_set_profiling(tsb_plan* plan, int32_t enable);
+int tsb_plan_stage_times(tsb_plan* plan, int32_t n, double* ms, int64_t* calls, int32_t reset);
+
+const char* tsb_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TRIPOSH_H */

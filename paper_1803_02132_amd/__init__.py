@@ -1,0 +1,110 @@
+"""MI355X (gfx950) bispectrum multipoles B_{l1 l2 L}(k1, k2) with the FFT-based
+TripoSH estimator of arXiv:1803.02132.
+
+The computation lives in libtriposh.so (hand-written HIP kernels behind the C
+ABI of include/triposh.h). This package holds the ctypes binding (``abi``) and
+``Plan``, which only marshals arguments: torch provides device memory and the
+stream.
+"""
+import numpy as np
+
+from . import abi
+from .abi import TsbError
+
+__all__ = ["Plan", "TsbError", "abi", "catalog_to_device"]
+
+_PAIR = {"paper": abi.TSB_PAIRS_PAPER, "upper": abi.TSB_PAIRS_UPPER, "diagonal": abi.TSB_PAIRS_DIAGONAL,
+         "all": abi.TSB_PAIRS_ALL}
+
+
+def _request(n, box_len, multipoles, n_bins, dk, k_min=0.0, origin=(0.0, 0.0, 0.0), assign_p=3,
+             interlace=False, los="local", los_dir=(0.0, 0.0, 1.0), observer=(0.0, 0.0, 0.0), box_mode=True,
+             P0=0.0, precision="f32", pair_mode="paper"):
+    grid = abi.tsb_grid(int(n), float(box_len), (abi.ctypes.c_double * 3)(*origin), int(assign_p), int(bool(interlace)))
+    lo = abi.tsb_los(abi.TSB_LOS_LOCAL if los == "local" else abi.TSB_LOS_GLOBAL,
+                     (abi.ctypes.c_double * 3)(*los_dir), (abi.ctypes.c_double * 3)(*observer))
+    bins = abi.tsb_kbins(int(n_bins), float(k_min), float(dk))
+    mps = [abi.tsb_multipole(*map(int, m)) for m in multipoles]
+    opts = abi.tsb_options(abi.TSB_FP64 if precision == "f64" else abi.TSB_FP32, _PAIR[pair_mode],
+                           int(bool(box_mode)), float(P0))
+    return grid, lo, bins, mps, opts
+
+
+def query(**kw):
+    """Host-only validation and sizes of a request (no device needed)."""
+    grid, lo, bins, mps, opts = _request(**kw)
+    info, nmode = abi.tsb_plan_query(grid, lo, bins, mps, opts, bins.n_bins)
+    return info, np.array(nmode, dtype=np.int64)
+
+
+def catalog_to_device(cat, device="cuda"):
+    """Host catalogue dict (pos (N,3) float32, optional w, nbar) -> dict of
+    contiguous float32 torch tensors on the device (kept alive by the caller)."""
+    import torch
+    pos = np.ascontiguousarray(np.asarray(cat["pos"], np.float32).T)
+    out = {k: torch.from_numpy(np.ascontiguousarray(pos[i])).to(device) for i, k in enumerate("xyz")}
+    for k in ("w", "nbar"):
+        v = cat.get(k)
+        out[k] = None if v is None else torch.from_numpy(np.ascontiguousarray(np.asarray(v, np.float32))).to(device)
+    return out
+
+
+def _cat_struct(dev):
+    if dev is None:
+        return None
+
+    def ptr(t):
+        return None if t is None else t.data_ptr()
+
+    return abi.tsb_catalog(ptr(dev["x"]), ptr(dev["y"]), ptr(dev["z"]), ptr(dev.get("w")), ptr(dev.get("nbar")),
+                           int(dev["x"].numel()))
+
+
+class Plan:
+    """A measurement plan on the current device (see tsb_plan_create)."""
+
+    def __init__(self, **kw):
+        self.request = dict(kw)
+        grid, lo, bins, mps, opts = _request(**kw)
+        self.n_bins = bins.n_bins
+        self.multipoles = [tuple(map(int, m)) for m in kw["multipoles"]]
+        self.handle = abi.tsb_plan_create(grid, lo, bins, mps, opts)
+        self.info = abi.tsb_plan_get_info(self.handle)
+        self.nmode, self.k_eff = abi.tsb_plan_nmode(self.handle, self.n_bins)
+        self.precision = kw.get("precision", "f32")
+
+    def channels(self):
+        return [abi.tsb_plan_channel(self.handle, c) for c in range(self.info.n_channels)]
+
+    def measure(self, data_dev, randoms_dev=None, stream=None):
+        """Run the hot path on device catalogues (dicts of torch tensors).
+        Returns dict(B=(n_mult, n_bins, n_bins) float64, I, alpha)."""
+        import torch
+        s = torch.cuda.current_stream() if stream is None else stream
+        B = np.empty((len(self.multipoles), self.n_bins, self.n_bins), dtype=np.float64)
+        I, alpha = abi.tsb_measure(self.handle, _cat_struct(data_dev), _cat_struct(randoms_dev),
+                                   s.cuda_stream, B.ctypes.data)
+        return {"B": B, "I": I, "alpha": alpha}
+
+    def assign(self, data_dev, randoms_dev=None, stream=None):
+        """Assignment stage only: grids [copies][channel][N][N][N] as a torch tensor."""
+        import torch
+        s = torch.cuda.current_stream() if stream is None else stream
+        copies = 1 + int(bool(self.request.get("interlace", False)))
+        n = self.info.n
+        dt = torch.float64 if self.precision == "f64" else torch.float32
+        out = torch.empty((copies, self.info.n_channels, n, n, n), dtype=dt, device="cuda")
+        abi.tsb_assign(self.handle, _cat_struct(data_dev), _cat_struct(randoms_dev), s.cuda_stream,
+                       out.data_ptr())
+        return out
+
+    def close(self):
+        if getattr(self, "handle", None) is not None:
+            abi.tsb_plan_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

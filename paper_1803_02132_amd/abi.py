@@ -1,0 +1,178 @@
+"""ctypes binding of include/triposh.h: the C entry points under the same names,
+argument marshalling only. Every computation runs in libtriposh.so; if the
+library is missing this module raises on import."""
+import ctypes
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libtriposh.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is missing: build it with __graft_entry__.build() "
+                      "(or python -m paper_1803_02132_amd.build)")
+_lib = ctypes.CDLL(LIB_PATH)
+
+TSB_OK, TSB_E_ARG, TSB_E_UNSUPPORTED, TSB_E_NOMEM, TSB_E_INPUT, TSB_E_DEVICE = 0, -1, -2, -3, -4, -5
+TSB_LOS_GLOBAL, TSB_LOS_LOCAL = 0, 1
+TSB_NGP, TSB_CIC, TSB_TSC = 1, 2, 3
+TSB_FP32, TSB_FP64 = 0, 1
+TSB_PAIRS_PAPER, TSB_PAIRS_UPPER, TSB_PAIRS_DIAGONAL, TSB_PAIRS_ALL = 0, 1, 2, 3
+
+_STATUS = {TSB_E_ARG: "TSB_E_ARG", TSB_E_UNSUPPORTED: "TSB_E_UNSUPPORTED", TSB_E_NOMEM: "TSB_E_NOMEM",
+           TSB_E_INPUT: "TSB_E_INPUT", TSB_E_DEVICE: "TSB_E_DEVICE"}
+
+
+class TsbError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{_STATUS.get(code, code)}: {msg}")
+        self.code = code
+
+
+class tsb_grid(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32), ("box_len", ctypes.c_double), ("origin", ctypes.c_double * 3),
+                ("assign_p", ctypes.c_int32), ("interlace", ctypes.c_int32)]
+
+
+class tsb_los(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("dir", ctypes.c_double * 3), ("observer", ctypes.c_double * 3)]
+
+
+class tsb_kbins(ctypes.Structure):
+    _fields_ = [("n_bins", ctypes.c_int32), ("k_min", ctypes.c_double), ("dk", ctypes.c_double)]
+
+
+class tsb_multipole(ctypes.Structure):
+    _fields_ = [("l1", ctypes.c_int32), ("l2", ctypes.c_int32), ("L", ctypes.c_int32)]
+
+
+class tsb_options(ctypes.Structure):
+    _fields_ = [("precision", ctypes.c_int32), ("pair_mode", ctypes.c_int32), ("box_mode", ctypes.c_int32),
+                ("P0", ctypes.c_double)]
+
+
+class tsb_catalog(ctypes.Structure):
+    _fields_ = [("x", ctypes.c_void_p), ("y", ctypes.c_void_p), ("z", ctypes.c_void_p),
+                ("w", ctypes.c_void_p), ("nbar", ctypes.c_void_p), ("n", ctypes.c_int64)]
+
+
+class tsb_plan_info(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32), ("m", ctypes.c_int32), ("r_f", ctypes.c_int32), ("r_g", ctypes.c_int32),
+                ("n_channels", ctypes.c_int32), ("n_fields_f", ctypes.c_int32), ("n_fields_g", ctypes.c_int32),
+                ("n_outputs", ctypes.c_int32), ("n_grids", ctypes.c_int32), ("n_fslots", ctypes.c_int32),
+                ("workspace_bytes", ctypes.c_int64)]
+
+
+_P = ctypes.POINTER
+_lib.tsb_last_error.restype = ctypes.c_char_p
+_lib.tsb_last_error.argtypes = []
+_lib.tsb_plan_create.restype = ctypes.c_int
+_lib.tsb_plan_create.argtypes = [_P(tsb_grid), _P(tsb_los), _P(tsb_kbins), _P(tsb_multipole), ctypes.c_int32,
+                                 _P(tsb_options), _P(ctypes.c_void_p)]
+_lib.tsb_plan_query.restype = ctypes.c_int
+_lib.tsb_plan_query.argtypes = [_P(tsb_grid), _P(tsb_los), _P(tsb_kbins), _P(tsb_multipole), ctypes.c_int32,
+                                _P(tsb_options), _P(tsb_plan_info), _P(ctypes.c_int64)]
+_lib.tsb_plan_destroy.restype = ctypes.c_int
+_lib.tsb_plan_destroy.argtypes = [ctypes.c_void_p]
+_lib.tsb_plan_get_info.restype = ctypes.c_int
+_lib.tsb_plan_get_info.argtypes = [ctypes.c_void_p, _P(tsb_plan_info)]
+_lib.tsb_plan_nmode.restype = ctypes.c_int
+_lib.tsb_plan_nmode.argtypes = [ctypes.c_void_p, _P(ctypes.c_int64), _P(ctypes.c_double)]
+_lib.tsb_plan_channel.restype = ctypes.c_int
+_lib.tsb_plan_channel.argtypes = [ctypes.c_void_p, ctypes.c_int32, _P(ctypes.c_int32), _P(ctypes.c_int32),
+                                  _P(ctypes.c_int32)]
+_lib.tsb_measure.restype = ctypes.c_int
+_lib.tsb_measure.argtypes = [ctypes.c_void_p, _P(tsb_catalog), _P(tsb_catalog), ctypes.c_void_p,
+                             _P(ctypes.c_double), _P(ctypes.c_double), _P(ctypes.c_double)]
+_lib.tsb_assign.restype = ctypes.c_int
+_lib.tsb_assign.argtypes = [ctypes.c_void_p, _P(tsb_catalog), _P(tsb_catalog), ctypes.c_void_p, ctypes.c_void_p]
+
+_lib.tsb_plan_set_profiling.restype = ctypes.c_int
+_lib.tsb_plan_set_profiling.argtypes = [ctypes.c_void_p, ctypes.c_int32]
+_lib.tsb_plan_stage_times.restype = ctypes.c_int
+_lib.tsb_plan_stage_times.argtypes = [ctypes.c_void_p, ctypes.c_int32, _P(ctypes.c_double), _P(ctypes.c_int64),
+                                      ctypes.c_int32]
+
+STAGES = ["weights", "bucket", "assign", "fwd_z", "fwd_y", "fwd_x", "combine", "invF_z", "invF_y", "invF_x",
+          "invG_z", "invG_y", "invG_x", "reduce", "reduce_final"]
+
+EXPORTED = ["tsb_plan_set_profiling", "tsb_plan_stage_times", "tsb_plan_create", "tsb_plan_destroy", "tsb_plan_query", "tsb_plan_get_info", "tsb_plan_nmode",
+            "tsb_measure", "tsb_assign", "tsb_plan_channel", "tsb_last_error"]
+
+
+def tsb_last_error():
+    return _lib.tsb_last_error().decode()
+
+
+def _check(rc):
+    if rc != TSB_OK:
+        raise TsbError(rc, tsb_last_error())
+    return rc
+
+
+def tsb_plan_create(grid, los, bins, multipoles, options):
+    arr = (tsb_multipole * len(multipoles))(*multipoles)
+    h = ctypes.c_void_p()
+    _check(_lib.tsb_plan_create(ctypes.byref(grid), ctypes.byref(los), ctypes.byref(bins), arr,
+                                len(multipoles), ctypes.byref(options), ctypes.byref(h)))
+    return h
+
+
+def tsb_plan_query(grid, los, bins, multipoles, options, n_bins):
+    arr = (tsb_multipole * len(multipoles))(*multipoles)
+    info = tsb_plan_info()
+    nm = (ctypes.c_int64 * n_bins)()
+    _check(_lib.tsb_plan_query(ctypes.byref(grid), ctypes.byref(los), ctypes.byref(bins), arr,
+                               len(multipoles), ctypes.byref(options), ctypes.byref(info), nm))
+    return info, list(nm)
+
+
+def tsb_plan_destroy(h):
+    return _check(_lib.tsb_plan_destroy(h))
+
+
+def tsb_plan_get_info(h):
+    info = tsb_plan_info()
+    _check(_lib.tsb_plan_get_info(h, ctypes.byref(info)))
+    return info
+
+
+def tsb_plan_nmode(h, n_bins):
+    nm = (ctypes.c_int64 * n_bins)()
+    ke = (ctypes.c_double * n_bins)()
+    _check(_lib.tsb_plan_nmode(h, nm, ke))
+    return list(nm), list(ke)
+
+
+def tsb_plan_channel(h, c):
+    L, M, part = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+    _check(_lib.tsb_plan_channel(h, c, ctypes.byref(L), ctypes.byref(M), ctypes.byref(part)))
+    return L.value, M.value, part.value
+
+
+def tsb_measure(h, data, randoms, stream, B_out_ptr):
+    """data / randoms: tsb_catalog (randoms may be None); B_out_ptr: pointer to a
+    host double buffer. Returns (I, alpha)."""
+    I = ctypes.c_double()
+    alpha = ctypes.c_double()
+    _check(_lib.tsb_measure(h, ctypes.byref(data), ctypes.byref(randoms) if randoms is not None else None,
+                            stream, ctypes.cast(B_out_ptr, _P(ctypes.c_double)), ctypes.byref(I),
+                            ctypes.byref(alpha)))
+    return I.value, alpha.value
+
+
+def tsb_assign(h, data, randoms, stream, grids_out_ptr):
+    return _check(_lib.tsb_assign(h, ctypes.byref(data), ctypes.byref(randoms) if randoms is not None else None,
+                                  stream, grids_out_ptr))
+
+
+def tsb_plan_set_profiling(h, enable):
+    return _check(_lib.tsb_plan_set_profiling(h, int(bool(enable))))
+
+
+def tsb_plan_stage_times(h, reset=False):
+    """{stage name: (accumulated ms, launches)}"""
+    n = len(STAGES)
+    ms = (ctypes.c_double * n)()
+    calls = (ctypes.c_int64 * n)()
+    _check(_lib.tsb_plan_stage_times(h, n, ms, calls, int(bool(reset))))
+    return {STAGES[i]: (ms[i], calls[i]) for i in range(n)}

@@ -1,0 +1,461 @@
+// Batched 3D FFTs as three 1D passes, each a workgroup-per-line-block kernel:
+// a block of lines is loaded into LDS with coalesced reads (consecutive lines
+// are adjacent in memory for the strided axes), transformed by an in-LDS
+// Stockham autosort FFT (radix 4, 2 and 3), and written back. Passes read and
+// write only the stored ("pruned") part of each axis: the forward transform
+// keeps frequencies |n_i| <= R, the inverse starts from them.
+//
+// Forward (Sec. 2 sign convention e^{-ik.x}): grids -> spectra cube, then the
+// interlace combination and W_mass deconvolution (Sec. 4.2, eq. 39).
+// Inverse (eq. 42): F_l^m(x; k) from the shell-filtered spectrum, G_L^M(x)
+// from the band-limited spectrum, on the reduction grid M.
+#include <cmath>
+
+#include "tsb_internal.h"
+
+namespace tsb {
+
+namespace {
+
+constexpr int kMaxParts = 2;
+
+template <typename T>
+struct PassArgs {
+  typedef typename cplx<T>::type T2;
+  const T2* in;
+  T2* out;
+  const T2* tw;            // e^{-2 pi i k / N}, k < N
+  int64_t in_bs, out_bs;   // batch strides (elements)
+  int64_t in_sa, in_sb, in_se, out_sa, out_sb, out_se;
+  int nbatch, dA, dB;      // lines indexed (batch, a, b)
+  int in_cnt, out_cnt;     // stored entries along the axis
+  int in_off, out_off;     // stored entry e <-> frequency / position e - off (mod N)
+  int N, dir;              // FFT length; -1 forward, +1 inverse
+  int lpw;                 // lines per workgroup (consecutive b)
+  int contiguous;          // element stride 1 (else b stride 1)
+  // pre-operation on loaded values
+  int pre;                 // 0 none, 1 band mask |n|^2 <= n2max, 2 shell filter
+  int offA, offB, offE;    // frequency = index - off for a, b, e
+  int64_t n2max;
+  const int* bin_lut;      // shell of n^2 (n^2 <= lut_max), -1 none
+  int64_t lut_max;
+  const FKind* kinds;
+  int nkinds;
+  double ynorm[45];
+};
+
+template <typename T2, typename T>
+__device__ inline T2 cmul(T2 a, T2 b) {
+  T2 r;
+  r.x = a.x * b.x - a.y * b.y;
+  r.y = a.x * b.y + a.y * b.x;
+  return r;
+}
+
+template <typename T>
+__device__ inline typename cplx<T>::type shell_value(const PassArgs<T>& a, int batch, int na, int nb,
+                                                     int ne, typename cplx<T>::type v) {
+  // F slot input (eq. 42 with eq. 38): sum_parts factor * y_l^m*(k^) * dn(k) on shell b
+  typedef typename cplx<T>::type T2;
+  T2 zero;
+  zero.x = 0;
+  zero.y = 0;
+  const int64_t n2 = (int64_t)na * na + (int64_t)nb * nb + (int64_t)ne * ne;
+  if (n2 == 0 || n2 > a.lut_max) return zero;
+  const int bin = a.bin_lut[n2];
+  if (bin != batch / a.nkinds) return zero;
+  const FKind k = a.kinds[batch % a.nkinds];
+  const double r = sqrt((double)n2);
+  const double ux = na / r, uy = nb / r, uz = ne / r;
+  double fr = 0.0, fi = 0.0;
+  for (int p = 0; p < k.nparts; ++p) {
+    double yr, yi;
+    ylm_pos_m(k.part[p].l, k.part[p].m, ux, uy, uz, a.ynorm, &yr, &yi);
+    // factor * conj(y)
+    fr += k.part[p].fr * yr + k.part[p].fi * yi;
+    fi += k.part[p].fi * yr - k.part[p].fr * yi;
+  }
+  T2 o;
+  o.x = (T)(fr * (double)v.x - fi * (double)v.y);
+  o.y = (T)(fr * (double)v.y + fi * (double)v.x);
+  return o;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kBlock) fft_pass_kernel(PassArgs<T> a) {
+  typedef typename cplx<T>::type T2;
+  extern __shared__ char smem[];
+  const int N = a.N, NP = a.N + 1;
+  T2* buf0 = (T2*)smem;
+  T2* buf1 = buf0 + (size_t)a.lpw * NP;
+  const int nbb = (a.dB + a.lpw - 1) / a.lpw;
+  const int64_t blk = blockIdx.x;
+  const int bb = (int)(blk % nbb);
+  const int64_t rest = blk / nbb;
+  const int ia = (int)(rest % a.dA);
+  const int batch = (int)(rest / a.dA);
+  const int b0 = bb * a.lpw;
+  const int nl = min(a.lpw, a.dB - b0);
+  const int tid = threadIdx.x;
+
+  T2 zero;
+  zero.x = 0;
+  zero.y = 0;
+  if (a.in_cnt < N)
+    for (int i = tid; i < nl * NP; i += kBlock) buf0[i] = zero;
+  __syncthreads();
+
+  // ---- load ------------------------------------------------------------------
+  const T2* inb = a.in + (int64_t)batch * a.in_bs + (int64_t)ia * a.in_sa;
+  for (int idx = tid; idx < nl * a.in_cnt; idx += kBlock) {
+    int j, e;
+    if (a.contiguous) {
+      j = idx / a.in_cnt;
+      e = idx - j * a.in_cnt;
+    } else {
+      e = idx / nl;
+      j = idx - e * nl;
+    }
+    T2 v = inb[(int64_t)(b0 + j) * a.in_sb + (int64_t)e * a.in_se];
+    if (a.pre) {
+      const int na = ia - a.offA, nb = b0 + j - a.offB, ne = e - a.offE;
+      if (a.pre == 1) {
+        const int64_t n2 = (int64_t)na * na + (int64_t)nb * nb + (int64_t)ne * ne;
+        if (n2 > a.n2max) v = zero;
+      } else {
+        v = shell_value<T>(a, batch, na, nb, ne, v);
+      }
+    }
+    int pos = e - a.in_off;
+    if (pos < 0) pos += N;
+    buf0[j * NP + pos] = v;
+  }
+  __syncthreads();
+
+  // ---- Stockham stages ----------------------------------------------------------
+  T2* src = buf0;
+  T2* dst = buf1;
+  int Ns = 1, rem = N;
+  const T sgn = (T)a.dir;
+  while (Ns < N) {
+    const int r = (rem % 4 == 0) ? 4 : ((rem % 2 == 0) ? 2 : 3);
+    const int nbf = N / r;
+    const int tstride = N / (Ns * r);
+    for (int idx = tid; idx < nl * nbf; idx += kBlock) {
+      const int line = idx / nbf;
+      const int jj = idx - line * nbf;
+      const T2* s = src + line * NP;
+      T2* d = dst + line * NP;
+      const int k = jj % Ns;
+      T2 v[4];
+      for (int t = 0; t < r; ++t) v[t] = s[jj + t * nbf];
+      if (k) {
+        for (int t = 1; t < r; ++t) {
+          T2 w = a.tw[t * k * tstride];
+          if (a.dir > 0) w.y = -w.y;   // tw holds e^{-i...}; the inverse uses its conjugate
+          v[t] = cmul<T2, T>(v[t], w);
+        }
+      }
+      if (r == 4) {
+        T2 t0, t1, t2, t3;
+        t0.x = v[0].x + v[2].x; t0.y = v[0].y + v[2].y;
+        t1.x = v[0].x - v[2].x; t1.y = v[0].y - v[2].y;
+        t2.x = v[1].x + v[3].x; t2.y = v[1].y + v[3].y;
+        // (v1 - v3) * (sgn i)
+        const T dx = v[1].x - v[3].x, dy = v[1].y - v[3].y;
+        t3.x = -sgn * dy;
+        t3.y = sgn * dx;
+        v[0].x = t0.x + t2.x; v[0].y = t0.y + t2.y;
+        v[2].x = t0.x - t2.x; v[2].y = t0.y - t2.y;
+        v[1].x = t1.x + t3.x; v[1].y = t1.y + t3.y;
+        v[3].x = t1.x - t3.x; v[3].y = t1.y - t3.y;
+      } else if (r == 2) {
+        const T2 t0 = v[0];
+        v[0].x = t0.x + v[1].x; v[0].y = t0.y + v[1].y;
+        v[1].x = t0.x - v[1].x; v[1].y = t0.y - v[1].y;
+      } else {
+        const T c = (T)0.86602540378443864676;   // sqrt(3)/2
+        T2 sm, df;
+        sm.x = v[1].x + v[2].x; sm.y = v[1].y + v[2].y;
+        df.x = v[1].x - v[2].x; df.y = v[1].y - v[2].y;
+        T2 m;
+        m.x = v[0].x - (T)0.5 * sm.x;
+        m.y = v[0].y - (T)0.5 * sm.y;
+        // sgn i c (v1 - v2)
+        const T ux = -sgn * c * df.y, uy = sgn * c * df.x;
+        v[0].x = v[0].x + sm.x; v[0].y = v[0].y + sm.y;
+        v[1].x = m.x + ux; v[1].y = m.y + uy;
+        v[2].x = m.x - ux; v[2].y = m.y - uy;
+      }
+      const int ob = (jj / Ns) * Ns * r + k;
+      for (int t = 0; t < r; ++t) d[ob + t * Ns] = v[t];
+    }
+    __syncthreads();
+    T2* tmp = src;
+    src = dst;
+    dst = tmp;
+    Ns *= r;
+    rem /= r;
+  }
+
+  // ---- store -------------------------------------------------------------------
+  T2* outb = a.out + (int64_t)batch * a.out_bs + (int64_t)ia * a.out_sa;
+  for (int idx = tid; idx < nl * a.out_cnt; idx += kBlock) {
+    int j, e;
+    if (a.contiguous) {
+      j = idx / a.out_cnt;
+      e = idx - j * a.out_cnt;
+    } else {
+      e = idx / nl;
+      j = idx - e * nl;
+    }
+    int pos = e - a.out_off;
+    if (pos < 0) pos += N;
+    outb[(int64_t)(b0 + j) * a.out_sb + (int64_t)e * a.out_se] = src[j * NP + pos];
+  }
+}
+
+// Interlace combination and W_mass deconvolution on the stored cube
+// (Sec. 4.2, eq. 39): S = (D1 + e^{i pi (nx+ny+nz)/N} D2)/2 / prod sinc(pi n_i/N)^p;
+// in box mode the DC mode of dn_0^0 (real part of grid 0) is zero.
+template <typename T>
+__global__ void __launch_bounds__(kBlock) combine_kernel(const typename cplx<T>::type* t3,
+                                                         typename cplx<T>::type* spec, int ngrid,
+                                                         int copies, int R, int N, int p, int box_mode) {
+  typedef typename cplx<T>::type T2;
+  const int P = 2 * R + 1;
+  const int64_t P3 = (int64_t)P * P * P;
+  const int64_t total = (int64_t)ngrid * P3;
+  for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < total; i += (int64_t)gridDim.x * kBlock) {
+    const int g = (int)(i / P3);
+    const int64_t m = i % P3;
+    const int nx = (int)(m / ((int64_t)P * P)) - R, ny = (int)((m / P) % P) - R, nz = (int)(m % P) - R;
+    const T2 v1 = t3[i];
+    double re = v1.x, im = v1.y;
+    if (copies == 2) {
+      const T2 v2 = t3[(int64_t)ngrid * P3 + i];
+      double s, c;
+      sincospi((double)(nx + ny + nz) / (double)N, &s, &c);
+      re = 0.5 * (re + c * (double)v2.x - s * (double)v2.y);
+      im = 0.5 * (im + c * (double)v2.y + s * (double)v2.x);
+    }
+    double W = 1.0;
+    const int n3[3] = {nx, ny, nz};
+    for (int ax = 0; ax < 3; ++ax) {
+      if (n3[ax] == 0) continue;
+      const double x = (double)n3[ax] / (double)N;
+      const double sc = sinpi(x) / (M_PI * x);
+      double wp = sc;
+      for (int k = 1; k < p; ++k) wp *= sc;
+      W *= wp;
+    }
+    re /= W;
+    im /= W;
+    if (box_mode && g == 0 && nx == 0 && ny == 0 && nz == 0) re = 0.0;
+    T2 o;
+    o.x = (T)re;
+    o.y = (T)im;
+    spec[i] = o;
+  }
+}
+
+// dn_0^0 on the F cube from the (0,0)-carrying grid 0: (S0(n) + conj(S0(-n)))/2.
+template <typename T>
+__global__ void __launch_bounds__(kBlock) dcube_kernel(const typename cplx<T>::type* spec0,
+                                                       typename cplx<T>::type* dc, int RG, int RF) {
+  typedef typename cplx<T>::type T2;
+  const int PG = 2 * RG + 1, PF = 2 * RF + 1;
+  const int64_t total = (int64_t)PF * PF * PF;
+  for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < total; i += (int64_t)gridDim.x * kBlock) {
+    const int nx = (int)(i / ((int64_t)PF * PF)) - RF, ny = (int)((i / PF) % PF) - RF, nz = (int)(i % PF) - RF;
+    const int64_t ip = ((int64_t)(nx + RG) * PG + (ny + RG)) * PG + (nz + RG);
+    const int64_t im = ((int64_t)(-nx + RG) * PG + (-ny + RG)) * PG + (-nz + RG);
+    const T2 a = spec0[ip], b = spec0[im];
+    T2 o;
+    o.x = (T)0.5 * (a.x + b.x);
+    o.y = (T)0.5 * (a.y - b.y);
+    dc[i] = o;
+  }
+}
+
+int pick_lpw(int N, int esz) {
+  // two LDS line buffers of (N+1) complex each, at most 64 KiB
+  int lpw = 16;
+  while (lpw > 1 && (int64_t)2 * lpw * (N + 1) * 2 * esz > 65536) lpw /= 2;
+  return lpw;
+}
+
+template <typename T>
+int launch_pass(Plan& P, int stage, PassArgs<T>& a, hipStream_t s) {
+  typedef typename cplx<T>::type T2;
+  if (a.nbatch <= 0 || a.dA <= 0 || a.dB <= 0) return TSB_OK;
+  a.lpw = pick_lpw(a.N, sizeof(T));
+  const int64_t nbb = (a.dB + a.lpw - 1) / a.lpw;
+  const int64_t blocks = (int64_t)a.nbatch * a.dA * nbb;
+  if (blocks > 2147483647LL) return fail(TSB_E_UNSUPPORTED, "FFT pass too large");
+  const size_t lds = (size_t)2 * a.lpw * (a.N + 1) * sizeof(T2);
+  prof_begin(P, stage, s);
+  hipLaunchKernelGGL(fft_pass_kernel<T>, dim3((unsigned)blocks), dim3(kBlock), lds, s, a);
+  prof_end(P, stage, s);
+  TSB_HIP(hipGetLastError());
+  return TSB_OK;
+}
+
+int grid_blocks(int64_t n) {
+  int64_t b = (n + kBlock - 1) / kBlock;
+  if (b > 8192) b = 8192;
+  return (int)(b < 1 ? 1 : b);
+}
+
+template <typename T>
+int forward_impl(Plan& P, hipStream_t s) {
+  typedef typename cplx<T>::type T2;
+  const int N = P.N, PG = P.PG, RG = P.RG;
+  const int nbc = P.copies * (int)P.grids.size();
+  const int64_t N2 = (int64_t)N * N, N3 = N2 * N;
+  int rc;
+  // z (contiguous): [nbc][N][N][N] -> [nbc][N][N][PG]
+  {
+    PassArgs<T> a{};
+    a.in = (const T2*)P.d_grid;
+    a.out = (T2*)P.d_t1;
+    a.tw = (const T2*)P.d_tw_n;
+    a.nbatch = nbc; a.dA = N; a.dB = N;
+    a.in_bs = N3; a.in_sa = N2; a.in_sb = N; a.in_se = 1;
+    a.out_bs = N2 * PG; a.out_sa = (int64_t)N * PG; a.out_sb = PG; a.out_se = 1;
+    a.in_cnt = N; a.in_off = 0; a.out_cnt = PG; a.out_off = RG;
+    a.N = N; a.dir = -1; a.contiguous = 1;
+    if ((rc = launch_pass<T>(P, kStFwdZ, a, s))) return rc;
+  }
+  // y (strided): [nbc][N][N][PG] -> [nbc][N][PG][PG]
+  {
+    PassArgs<T> a{};
+    a.in = (const T2*)P.d_t1;
+    a.out = (T2*)P.d_t2;
+    a.tw = (const T2*)P.d_tw_n;
+    a.nbatch = nbc; a.dA = N; a.dB = PG;
+    a.in_bs = N2 * PG; a.in_sa = (int64_t)N * PG; a.in_sb = 1; a.in_se = PG;
+    a.out_bs = (int64_t)N * PG * PG; a.out_sa = (int64_t)PG * PG; a.out_sb = 1; a.out_se = PG;
+    a.in_cnt = N; a.in_off = 0; a.out_cnt = PG; a.out_off = RG;
+    a.N = N; a.dir = -1; a.contiguous = 0;
+    if ((rc = launch_pass<T>(P, kStFwdY, a, s))) return rc;
+  }
+  // x (strided): [nbc][N][PG][PG] -> [nbc][PG][PG][PG]
+  {
+    PassArgs<T> a{};
+    a.in = (const T2*)P.d_t2;
+    a.out = (T2*)P.d_t3;
+    a.tw = (const T2*)P.d_tw_n;
+    a.nbatch = nbc; a.dA = PG; a.dB = PG;
+    a.in_bs = (int64_t)N * PG * PG; a.in_sa = PG; a.in_sb = 1; a.in_se = (int64_t)PG * PG;
+    a.out_bs = (int64_t)PG * PG * PG; a.out_sa = PG; a.out_sb = 1; a.out_se = (int64_t)PG * PG;
+    a.in_cnt = N; a.in_off = 0; a.out_cnt = PG; a.out_off = RG;
+    a.N = N; a.dir = -1; a.contiguous = 0;
+    if ((rc = launch_pass<T>(P, kStFwdX, a, s))) return rc;
+  }
+  const int64_t total = (int64_t)P.grids.size() * PG * PG * PG;
+  prof_begin(P, kStCombine, s);
+  hipLaunchKernelGGL(combine_kernel<T>, dim3(grid_blocks(total)), dim3(kBlock), 0, s, (const T2*)P.d_t3,
+                     (T2*)P.d_spec, (int)P.grids.size(), P.copies, RG, N, P.p, P.box_mode);
+  const int64_t pf3 = (int64_t)P.PF * P.PF * P.PF;
+  hipLaunchKernelGGL(dcube_kernel<T>, dim3(grid_blocks(pf3)), dim3(kBlock), 0, s, (const T2*)P.d_spec,
+                     (T2*)P.d_dcube, RG, P.RF);
+  prof_end(P, kStCombine, s);
+  TSB_HIP(hipGetLastError());
+  return TSB_OK;
+}
+
+// One inverse 3D transform chain on the M grid, from a cube of half-width R
+// (stored entries 2R+1 per axis) to full complex fields [nbatch][M^3].
+template <typename T>
+int inverse_chain(Plan& P, int stage0, const typename cplx<T>::type* cube, int64_t cube_bs, int nbatch,
+                  int R, PassArgs<T> pre, typename cplx<T>::type* fields, hipStream_t s) {
+  typedef typename cplx<T>::type T2;
+  const int M = P.M, PR = 2 * R + 1;
+  const int64_t M2 = (int64_t)M * M;
+  int rc;
+  // z (contiguous) with the pre-operation: [b][PR][PR][PR] -> [b][PR][PR][M]
+  {
+    PassArgs<T> a = pre;
+    a.in = cube;
+    a.out = (T2*)P.d_u1;
+    a.tw = (const T2*)P.d_tw_m;
+    a.nbatch = nbatch; a.dA = PR; a.dB = PR;
+    a.in_bs = cube_bs; a.in_sa = (int64_t)PR * PR; a.in_sb = PR; a.in_se = 1;
+    a.out_bs = (int64_t)PR * PR * M; a.out_sa = (int64_t)PR * M; a.out_sb = M; a.out_se = 1;
+    a.in_cnt = PR; a.in_off = R; a.out_cnt = M; a.out_off = 0;
+    a.offA = R; a.offB = R; a.offE = R;
+    a.N = M; a.dir = 1; a.contiguous = 1;
+    if ((rc = launch_pass<T>(P, stage0, a, s))) return rc;
+  }
+  // y (strided): [b][PR][PR][M] -> [b][PR][M][M]
+  {
+    PassArgs<T> a{};
+    a.in = (const T2*)P.d_u1;
+    a.out = (T2*)P.d_u2;
+    a.tw = (const T2*)P.d_tw_m;
+    a.nbatch = nbatch; a.dA = PR; a.dB = M;
+    a.in_bs = (int64_t)PR * PR * M; a.in_sa = (int64_t)PR * M; a.in_sb = 1; a.in_se = M;
+    a.out_bs = (int64_t)PR * M2; a.out_sa = M2; a.out_sb = 1; a.out_se = M;
+    a.in_cnt = PR; a.in_off = R; a.out_cnt = M; a.out_off = 0;
+    a.N = M; a.dir = 1; a.contiguous = 0;
+    if ((rc = launch_pass<T>(P, stage0 + 1, a, s))) return rc;
+  }
+  // x (strided): [b][PR][M][M] -> [b][M][M][M]
+  {
+    PassArgs<T> a{};
+    a.in = (const T2*)P.d_u2;
+    a.out = fields;
+    a.tw = (const T2*)P.d_tw_m;
+    a.nbatch = nbatch; a.dA = M; a.dB = M;
+    a.in_bs = (int64_t)PR * M2; a.in_sa = M; a.in_sb = 1; a.in_se = M2;
+    a.out_bs = M2 * M; a.out_sa = M; a.out_sb = 1; a.out_se = M2;
+    a.in_cnt = PR; a.in_off = R; a.out_cnt = M; a.out_off = 0;
+    a.N = M; a.dir = 1; a.contiguous = 0;
+    if ((rc = launch_pass<T>(P, stage0 + 2, a, s))) return rc;
+  }
+  return TSB_OK;
+}
+
+template <typename T>
+int inverse_impl(Plan& P, hipStream_t s) {
+  typedef typename cplx<T>::type T2;
+  const int64_t M3 = (int64_t)P.M * P.M * P.M;
+  const int nf = P.nb * (int)P.fkinds.size();
+  T2* fields = (T2*)P.d_fields;
+  int rc;
+  // F slots: shell filter of dn_0^0 times y_l^m*(k^) (eq. 42)
+  {
+    PassArgs<T> pre{};
+    pre.pre = 2;
+    pre.bin_lut = P.d_bin_lut;
+    pre.lut_max = (int64_t)P.bin_lut.size() - 1;
+    pre.kinds = P.d_fkinds;
+    pre.nkinds = (int)P.fkinds.size();
+    ylm_norm_table(pre.ynorm);
+    if ((rc = inverse_chain<T>(P, kStInvFZ, (const T2*)P.d_dcube, 0, nf, P.RF, pre, fields, s))) return rc;
+  }
+  // G grids: band-limited spectra (eq. 42)
+  {
+    PassArgs<T> pre{};
+    pre.pre = P.n2maxG >= 0 ? 1 : 0;
+    pre.n2max = P.n2maxG;
+    const int64_t pg3 = (int64_t)P.PG * P.PG * P.PG;
+    if ((rc = inverse_chain<T>(P, kStInvGZ, (const T2*)P.d_spec, pg3, (int)P.grids.size(), P.RG, pre,
+                               fields + (int64_t)nf * M3, s)))
+      return rc;
+  }
+  return TSB_OK;
+}
+
+}  // namespace
+
+int run_forward(Plan& P, hipStream_t s) {
+  return P.precision == TSB_FP64 ? forward_impl<double>(P, s) : forward_impl<float>(P, s);
+}
+
+int run_inverse(Plan& P, hipStream_t s) {
+  return P.precision == TSB_FP64 ? inverse_impl<double>(P, s) : inverse_impl<float>(P, s);
+}
+
+}  // namespace tsb

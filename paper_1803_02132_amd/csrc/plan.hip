@@ -1,0 +1,384 @@
+// Host-side planning: validation, k-shells, the reduction grid, channel and
+// slot layout, and the real expansion of the 3j-weighted m-sum of eq. 41.
+#include <algorithm>
+#include <cmath>
+#include <complex>
+#include <map>
+#include <tuple>
+
+#include "tsb_internal.h"
+
+namespace tsb {
+
+namespace {
+
+typedef std::complex<double> cd;
+
+long double lfact(int n) {
+  long double r = 1.0L;
+  for (int i = 2; i <= n; ++i) r *= (long double)i;
+  return r;
+}
+
+// Wigner 3j symbol by Racah's formula in extended precision (Sec. 2, eq. 11).
+double three_j(int j1, int j2, int j3, int m1, int m2, int m3) {
+  if (m1 + m2 + m3 != 0) return 0.0;
+  if (std::abs(m1) > j1 || std::abs(m2) > j2 || std::abs(m3) > j3) return 0.0;
+  if (j3 < std::abs(j1 - j2) || j3 > j1 + j2) return 0.0;
+  int kmin = std::max({0, j2 - j3 - m1, j1 - j3 + m2});
+  int kmax = std::min({j1 + j2 - j3, j1 - m1, j2 + m2});
+  long double s = 0.0L;
+  for (int k = kmin; k <= kmax; ++k) {
+    long double den = lfact(k) * lfact(j3 - j2 + k + m1) * lfact(j3 - j1 + k - m2) *
+                      lfact(j1 + j2 - j3 - k) * lfact(j1 - k - m1) * lfact(j2 - k + m2);
+    s += ((k % 2) ? -1.0L : 1.0L) / den;
+  }
+  long double tri = lfact(j1 + j2 - j3) * lfact(j1 - j2 + j3) * lfact(-j1 + j2 + j3) /
+                    lfact(j1 + j2 + j3 + 1);
+  long double f = lfact(j1 + m1) * lfact(j1 - m1) * lfact(j2 + m2) * lfact(j2 - m2) *
+                  lfact(j3 + m3) * lfact(j3 - m3);
+  long double v = std::sqrt(tri * f) * s;
+  int ph = j1 - j2 - m3;
+  if (((ph % 2) + 2) % 2) v = -v;
+  return (double)v;
+}
+
+bool is_2a3b(int n) {
+  if (n <= 0) return false;
+  while (n % 2 == 0) n /= 2;
+  while (n % 3 == 0) n /= 3;
+  return n == 1;
+}
+
+// y_L^M(d) for any M via y^{-M} = (-1)^M conj(y^M), with the device routine.
+cd ylm_any(int l, int m, const double* d, const double* norm) {
+  double re, im;
+  ylm_pos_m(l, std::abs(m), d[0], d[1], d[2], norm, &re, &im);
+  cd v(re, im);
+  if (m < 0) v = ((std::abs(m) % 2) ? -1.0 : 1.0) * std::conj(v);
+  return v;
+}
+
+}  // namespace
+
+void ylm_norm_table(double* norm) {
+  for (int l = 0; l <= kMaxEll; ++l)
+    for (int m = 0; m <= l; ++m) {
+      long double r = std::sqrt(lfact(l - m) / lfact(l + m));
+      norm[l * (l + 1) / 2 + m] = (double)((m % 2) ? -r : r);
+    }
+}
+
+int plan_build(Plan& P) {
+  const int N = P.N;
+  if (N < 16 || N > 1024 || N % 4 != 0 || !is_2a3b(N))
+    return fail(TSB_E_UNSUPPORTED, "grid size N must be 2^a 3^b with 16 <= N <= 1024 and N % 4 == 0");
+  if (!(P.L > 0) || !std::isfinite(P.L)) return fail(TSB_E_ARG, "box_len must be positive");
+  if (P.p < 1 || P.p > 3) return fail(TSB_E_ARG, "assign_p must be 1 (NGP), 2 (CIC) or 3 (TSC)");
+  if (P.interlace != 0 && P.interlace != 1) return fail(TSB_E_ARG, "interlace must be 0 or 1");
+  if (P.nb < 1 || P.nb > kMaxBins) return fail(TSB_E_ARG, "n_bins must be in 1..64");
+  if (!(P.dk > 0) || !(P.kmin >= 0)) return fail(TSB_E_ARG, "need dk > 0 and k_min >= 0");
+  if (P.mult.empty()) return fail(TSB_E_ARG, "no multipoles");
+  if (P.los_kind != TSB_LOS_GLOBAL && P.los_kind != TSB_LOS_LOCAL)
+    return fail(TSB_E_ARG, "los kind must be global (0) or local (1)");
+  if (P.precision != TSB_FP32 && P.precision != TSB_FP64) return fail(TSB_E_ARG, "precision");
+  if (P.pair_mode < 0 || P.pair_mode > 3) return fail(TSB_E_ARG, "pair_mode");
+  for (auto& mp : P.mult) {
+    int l1 = mp.l1, l2 = mp.l2, L = mp.L;
+    if (l1 < 0 || l2 < 0 || L < 0 || l1 > kMaxEll || l2 > kMaxEll || L > kMaxEll)
+      return fail(TSB_E_UNSUPPORTED, "l1, l2, L must be in 0..8");
+    // Table 1 (Sec. 2): L even, triangle rule, l1 + l2 + L even
+    if (L % 2 || L < std::abs(l1 - l2) || L > l1 + l2 || (l1 + l2 + L) % 2)
+      return fail(TSB_E_UNSUPPORTED, "multipole outside the allowed set of Table 1");
+  }
+  if (P.los_kind == TSB_LOS_GLOBAL) {
+    double n2 = P.los_dir[0] * P.los_dir[0] + P.los_dir[1] * P.los_dir[1] + P.los_dir[2] * P.los_dir[2];
+    if (!(n2 > 0)) return fail(TSB_E_ARG, "global LOS direction is zero");
+    double s = 1.0 / std::sqrt(n2);
+    for (int a = 0; a < 3; ++a) P.los_dir[a] *= s;
+  }
+  P.copies = 1 + P.interlace;
+
+  // ---- k-shells (eq. 38): bin of every integer n^2 ---------------------------
+  const double kf = 2.0 * M_PI / P.L;
+  const int64_t h = N / 2;
+  const int64_t n2all = 3 * h * h;
+  std::vector<int> lut(n2all + 1, -1);
+  int64_t n2maxF = 0;
+  for (int64_t n2 = 1; n2 <= n2all; ++n2) {
+    double b = std::floor((kf * std::sqrt((double)n2) - P.kmin) / P.dk);
+    if (b >= 0 && b < P.nb) {
+      lut[n2] = (int)b;
+      n2maxF = n2;
+    }
+  }
+  if (n2maxF == 0) return fail(TSB_E_UNSUPPORTED, "no grid mode falls in any k-shell");
+  // no shell may hold a mode with an index component of N/2 (those are zeroed)
+  for (int64_t n2 = h * h; n2 <= n2all; ++n2)
+    if (lut[n2] >= 0) return fail(TSB_E_UNSUPPORTED, "k-shells reach the Nyquist frequency");
+  P.n2maxF = n2maxF;
+  int RF = (int)std::floor(std::sqrt((double)n2maxF));
+  while ((int64_t)(RF + 1) * (RF + 1) <= n2maxF) ++RF;
+  while ((int64_t)RF * RF > n2maxF) --RF;
+  P.RF = RF;
+  P.bin_lut.assign(lut.begin(), lut.begin() + (3 * (int64_t)RF * RF + 1));
+
+  // ---- reduction grid ---------------------------------------------------------
+  // With every shell inside |n| <= sqrt(n2maxF), F1 F2 only meets G at modes with
+  // |n3| <= 2 sqrt(n2maxF). If 2 RF < N/2 no F pair wraps on the N grid, and the
+  // sum over cells of F F G equals (N/M)^3 times the same sum on any M grid with
+  // M > 2 RF + RG: then no closed triangle aliases onto another.
+  if (4 * RF < N) {
+    P.n2maxG = 4 * n2maxF;
+    int RG = (int)std::floor(2.0 * std::sqrt((double)n2maxF));
+    while ((int64_t)(RG + 1) * (RG + 1) <= P.n2maxG) ++RG;
+    while ((int64_t)RG * RG > P.n2maxG) --RG;
+    RG = std::min(RG, N / 2 - 1);
+    P.RG = RG;
+    int mmin = 2 * RF + RG + 1;
+    int M = N;
+    for (int a = 4; a <= N; a *= 2)
+      for (int b = a; b <= N; b *= 3)
+        if (b >= mmin && b < M && b % 4 == 0) M = b;
+    P.M = M;
+  } else {
+    P.n2maxG = -1;
+    P.RG = N / 2 - 1;
+    P.M = N;
+  }
+  P.PF = 2 * P.RF + 1;
+  P.PG = 2 * P.RG + 1;
+
+  // N_mode and mean |k| per shell (all modes of a shell are in the F cube)
+  P.nmode.assign(P.nb, 0);
+  P.keff.assign(P.nb, 0.0);
+  for (int x = -RF; x <= RF; ++x)
+    for (int y = -RF; y <= RF; ++y)
+      for (int z = -RF; z <= RF; ++z) {
+        int64_t n2 = (int64_t)x * x + (int64_t)y * y + (int64_t)z * z;
+        if (n2 > n2maxF) continue;
+        int b = P.bin_lut[n2];
+        if (b < 0) continue;
+        P.nmode[b] += 1;
+        P.keff[b] += kf * std::sqrt((double)n2);
+      }
+  for (int b = 0; b < P.nb; ++b) P.keff[b] = P.nmode[b] ? P.keff[b] / P.nmode[b] : NAN;
+
+  // ---- channels and complex grids ------------------------------------------------
+  std::vector<int> Ls{0};
+  if (P.los_kind == TSB_LOS_LOCAL)
+    for (auto& mp : P.mult)
+      if (std::find(Ls.begin(), Ls.end(), mp.L) == Ls.end()) Ls.push_back(mp.L);
+  std::sort(Ls.begin(), Ls.end());
+  P.chans.clear();
+  P.grids.clear();
+  std::vector<int> m0;
+  for (int L : Ls) {
+    m0.push_back((int)P.chans.size());
+    P.chans.push_back({L, 0, 0});
+  }
+  for (size_t i = 0; i < m0.size(); i += 2)
+    P.grids.push_back({m0[i], i + 1 < m0.size() ? m0[i + 1] : -1});
+  for (int L : Ls)
+    for (int M = 1; M <= L; ++M) {
+      int c = (int)P.chans.size();
+      P.chans.push_back({L, M, 0});
+      P.chans.push_back({L, M, 1});
+      P.grids.push_back({c, c + 1});
+    }
+  // (L, M, part) -> G component (grid, part)
+  std::map<std::tuple<int, int, int>, int> gkey;
+  P.gcomp.clear();
+  for (int g = 0; g < (int)P.grids.size(); ++g) {
+    for (int part = 0; part < 2; ++part) {
+      int c = part ? P.grids[g].im : P.grids[g].re;
+      if (c < 0) continue;
+      const RealChannel& ch = P.chans[c];
+      gkey[std::make_tuple(ch.L, ch.M, ch.part)] = (int)P.gcomp.size();
+      P.gcomp.push_back({g, part});
+    }
+  }
+
+  // ---- expansion of Re sum_{m1 m2 M} 3j F F G into real triple products --------
+  double norm[64];
+  ylm_norm_table(norm);
+  // logical F components: (l, |m|, part); part 0/1 = Re/Im of F_l^m (m > 0),
+  // part 0 = the real field f_l = c_l F_l^0 (m = 0, c_l = 1 for even l, -i for odd l)
+  typedef std::tuple<int, int, int> LKey;
+  std::map<std::tuple<int, LKey, LKey, int>, double> acc;   // (mu, f1, f2, g) -> coef
+  auto ffactor = [](int l, int m) {
+    std::vector<std::pair<LKey, cd>> out;
+    int am = std::abs(m);
+    if (m == 0) {
+      cd inv_c = (l % 2) ? cd(0, 1) : cd(1, 0);   // 1/c_l
+      out.push_back({LKey(l, 0, 0), inv_c});
+    } else if (m > 0) {
+      out.push_back({LKey(l, am, 0), cd(1, 0)});
+      out.push_back({LKey(l, am, 1), cd(0, 1)});
+    } else {
+      double s = ((l + am) % 2) ? -1.0 : 1.0;    // F^{-m} = (-1)^{l+m} conj(F^m)
+      out.push_back({LKey(l, am, 0), cd(s, 0)});
+      out.push_back({LKey(l, am, 1), cd(0, -s)});
+    }
+    return out;
+  };
+  auto gfactor = [&](int L, int M) {
+    std::vector<std::pair<int, cd>> out;
+    if (P.los_kind == TSB_LOS_GLOBAL) {
+      // Sec. 4.4 with a general direction: G_L^M = y_L^M*(d) G_0^0
+      cd y = std::conj(ylm_any(L, M, P.los_dir, norm));
+      if (std::abs(y) > 1e-15) out.push_back({gkey.at(std::make_tuple(0, 0, 0)), y});
+      return out;
+    }
+    int aM = std::abs(M);
+    if (M == 0) {
+      out.push_back({gkey.at(std::make_tuple(L, 0, 0)), cd(1, 0)});
+    } else if (M > 0) {
+      out.push_back({gkey.at(std::make_tuple(L, aM, 0)), cd(1, 0)});
+      out.push_back({gkey.at(std::make_tuple(L, aM, 1)), cd(0, 1)});
+    } else {
+      double s = (aM % 2) ? -1.0 : 1.0;          // G^{-M} = (-1)^M conj(G^M)
+      out.push_back({gkey.at(std::make_tuple(L, aM, 0)), cd(s, 0)});
+      out.push_back({gkey.at(std::make_tuple(L, aM, 1)), cd(0, -s)});
+    }
+    return out;
+  };
+  P.mu_pref.assign(P.mult.size(), 0.0);
+  for (int mu = 0; mu < (int)P.mult.size(); ++mu) {
+    int l1 = P.mult[mu].l1, l2 = P.mult[mu].l2, L = P.mult[mu].L;
+    P.mu_pref[mu] = (double)((2 * l1 + 1) * (2 * l2 + 1) * (2 * L + 1)) * three_j(l1, l2, L, 0, 0, 0);
+    for (int m1 = -l1; m1 <= l1; ++m1)
+      for (int m2 = -l2; m2 <= l2; ++m2) {
+        int M = -m1 - m2;
+        if (std::abs(M) > L) continue;
+        double w = three_j(l1, l2, L, m1, m2, M);
+        if (w == 0.0) continue;
+        for (auto& a : ffactor(l1, m1))
+          for (auto& b : ffactor(l2, m2))
+            for (auto& c : gfactor(L, M)) {
+              double re = (w * a.second * b.second * c.second).real();
+              acc[std::make_tuple(mu, a.first, b.first, c.first)] += re;
+            }
+      }
+  }
+  // keep the non-vanishing real terms and the F components they use
+  std::map<LKey, int> used;
+  std::vector<std::tuple<int, LKey, LKey, int, double>> kept;
+  for (auto& kv : acc) {
+    if (std::abs(kv.second) < 1e-13) continue;
+    kept.push_back(std::make_tuple(std::get<0>(kv.first), std::get<1>(kv.first),
+                                   std::get<2>(kv.first), std::get<3>(kv.first), kv.second));
+    used[std::get<1>(kv.first)] = 1;
+    used[std::get<2>(kv.first)] = 1;
+  }
+  // F slot kinds: one complex slot per (l, m > 0); real m = 0 fields packed in pairs
+  P.fkinds.clear();
+  P.fcomp.clear();
+  std::map<LKey, int> fidx;
+  std::vector<int> m0l;
+  std::vector<std::pair<int, int>> mpos;
+  for (auto& kv : used) {
+    int l = std::get<0>(kv.first), m = std::get<1>(kv.first);
+    if (m == 0) {
+      m0l.push_back(l);
+    } else if (std::find(mpos.begin(), mpos.end(), std::make_pair(l, m)) == mpos.end()) {
+      mpos.push_back({l, m});
+    }
+  }
+  for (size_t i = 0; i < m0l.size(); i += 2) {
+    FKind k{};
+    int la = m0l[i];
+    cd ca = (la % 2) ? cd(0, -1) : cd(1, 0);
+    k.part[0] = {la, 0, ca.real(), ca.imag()};
+    k.nparts = 1;
+    int kind = (int)P.fkinds.size();
+    fidx[LKey(la, 0, 0)] = (int)P.fcomp.size();
+    P.fcomp.push_back({kind, 0});
+    if (i + 1 < m0l.size()) {
+      int lb = m0l[i + 1];
+      cd cb = ((lb % 2) ? cd(0, -1) : cd(1, 0)) * cd(0, 1);   // i c_lb
+      k.part[1] = {lb, 0, cb.real(), cb.imag()};
+      k.nparts = 2;
+      fidx[LKey(lb, 0, 0)] = (int)P.fcomp.size();
+      P.fcomp.push_back({kind, 1});
+    }
+    P.fkinds.push_back(k);
+  }
+  for (auto& lm : mpos) {
+    FKind k{};
+    k.part[0] = {lm.first, lm.second, 1.0, 0.0};
+    k.nparts = 1;
+    int kind = (int)P.fkinds.size();
+    for (int part = 0; part < 2; ++part) {
+      LKey key(lm.first, lm.second, part);
+      fidx[key] = (int)P.fcomp.size();
+      P.fcomp.push_back({kind, part});
+    }
+    P.fkinds.push_back(k);
+  }
+  // terms sorted by (mu, f2): one Q group per (mu, f2)
+  P.terms.clear();
+  for (auto& t : kept)
+    P.terms.push_back({std::get<0>(t), fidx.at(std::get<1>(t)), fidx.at(std::get<2>(t)),
+                       std::get<3>(t), std::get<4>(t)});
+  std::sort(P.terms.begin(), P.terms.end(), [](const Term& a, const Term& b) {
+    return std::tie(a.mu, a.f2, a.f1, a.g) < std::tie(b.mu, b.f2, b.f1, b.g);
+  });
+  P.qgroups.clear();
+  for (int t = 0; t < (int)P.terms.size(); ++t) {
+    if (P.qgroups.empty() || P.qgroups.back().mu != P.terms[t].mu || P.qgroups.back().f2 != P.terms[t].f2)
+      P.qgroups.push_back({P.terms[t].mu, P.terms[t].f2, t, t + 1});
+    else
+      P.qgroups.back().t1 = t + 1;
+  }
+  // outputs (mu, b1, b2) of the requested pair set
+  P.outs.clear();
+  P.out_norm.clear();
+  const double M3 = (double)P.M * P.M * P.M;
+  for (int mu = 0; mu < (int)P.mult.size(); ++mu) {
+    int q0 = -1, q1 = -1;
+    for (int q = 0; q < (int)P.qgroups.size(); ++q)
+      if (P.qgroups[q].mu == mu) {
+        if (q0 < 0) q0 = q;
+        q1 = q + 1;
+      }
+    if (q0 < 0) q0 = q1 = 0;   // every term vanishes: B = 0
+    bool same = P.mult[mu].l1 == P.mult[mu].l2;
+    for (int b1 = 0; b1 < P.nb; ++b1)
+      for (int b2 = 0; b2 < P.nb; ++b2) {
+        bool want;
+        switch (P.pair_mode) {
+          case TSB_PAIRS_PAPER: want = same ? (b1 <= b2) : true; break;
+          case TSB_PAIRS_UPPER: want = b1 <= b2; break;
+          case TSB_PAIRS_DIAGONAL: want = b1 == b2; break;
+          default: want = true;
+        }
+        if (!want || P.nmode[b1] == 0 || P.nmode[b2] == 0) continue;
+        P.outs.push_back({mu, b1, b2, q0, q1});
+        P.out_norm.push_back(P.mu_pref[mu] / ((double)P.nmode[b1] * (double)P.nmode[b2] * M3));
+      }
+  }
+
+  // ---- assignment tile and reduction chunk ---------------------------------------
+  const int nchx = (int)P.chans.size() + (P.box_mode ? 0 : 1);
+  if (N % 8 == 0 && N / 8 >= 3 && (int64_t)P.copies * nchx * 512 * 8 <= 65536)
+    P.T = 8;
+  else
+    P.T = 4;
+  P.NT = N / P.T;
+  if ((int64_t)P.copies * nchx * P.T * P.T * P.T * 8 > 160 * 1024)
+    return fail(TSB_E_UNSUPPORTED, "too many channels for the assignment tile");
+  const int esz = P.precision == TSB_FP64 ? 8 : 4;
+  const int64_t per_cell = (int64_t)P.nb * (int64_t)P.fcomp.size() + (int64_t)P.gcomp.size() +
+                           (int64_t)P.qgroups.size() * P.nb;
+  int C = 64;
+  while (C > 4 && per_cell * C * esz > 65536) C /= 2;
+  if (per_cell * C * esz > 160 * 1024)
+    return fail(TSB_E_UNSUPPORTED, "too many fields for the reduction tile");
+  P.red_chunk = C;
+  const int64_t nchunks = (int64_t)P.M * P.M * P.M / C;
+  P.red_wg = (int)std::min<int64_t>(nchunks, 1024);
+  return TSB_OK;
+}
+
+}  // namespace tsb

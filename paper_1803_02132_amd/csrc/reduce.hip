@@ -1,0 +1,166 @@
+// The 3j-weighted triple-product reduction (Sec. 4.2, eq. 41; Sec. 4.4, eq. 51):
+//   B_mu(b1, b2) = N H / (I N_mode(b1) N_mode(b2) M^3)
+//                  * sum_q sum_x Q_q(x; b1) f2_q(x; b2),
+//   Q_q(x; b1)  = sum_t coef_t f1_t(x; b1) g_t(x),
+// where the real fields f (parts of the F slots) and g (parts of the G grids)
+// come from the inverse transforms and the terms (coef, f1, f2, g) are the
+// real expansion of sum_{m1 m2 M} 3j F_l1^m1 F_l2^m2 G_L^M.
+//
+// Each workgroup walks a fixed set of cell chunks; a chunk's field values are
+// staged in LDS, Q is formed in LDS, and every thread accumulates its outputs
+// in FP64 registers. Per-workgroup partial sums are combined in a fixed order,
+// so the result does not depend on scheduling.
+#include "tsb_internal.h"
+
+namespace tsb {
+
+namespace {
+
+constexpr int kOutPerThread = 16;   // outputs per thread per launch
+
+template <typename T>
+struct RedArgs {
+  typedef typename cplx<T>::type T2;
+  const T2* fields;        // F slots [nb * nkinds][M^3] then G grids [ngrid][M^3]
+  int64_t M3;
+  int nb, nkinds, ngrid;
+  int nfc, ngc, nq;
+  const Component* fcomp;
+  const Component* gcomp;
+  const Term* terms;
+  const QGroup* qg;
+  const OutEntry* outs;
+  int out0, nout;          // outputs [out0, out0 + nout) in this launch
+  int nout_all;            // row length of partials
+  int chunk;               // cells per chunk
+  int64_t nchunks;
+  double* partials;        // [gridDim][nout_all]
+};
+
+template <typename T>
+__global__ void __launch_bounds__(kBlock) reduce_kernel(RedArgs<T> a) {
+  typedef typename cplx<T>::type T2;
+  extern __shared__ char smem[];
+  const int C = a.chunk;
+  T* Fv = (T*)smem;                              // [nb][nfc][C]
+  T* Gv = Fv + (size_t)a.nb * a.nfc * C;         // [ngc][C]
+  T* Qv = Gv + (size_t)a.ngc * C;                // [nq][nb][C]
+  const int tid = threadIdx.x;
+  double acc[kOutPerThread];
+#pragma unroll
+  for (int r = 0; r < kOutPerThread; ++r) acc[r] = 0.0;
+
+  for (int64_t ch = blockIdx.x; ch < a.nchunks; ch += gridDim.x) {
+    const int64_t c0 = ch * C;
+    // stage F slot parts: one complex load feeds up to two components
+    const int nslot = a.nb * a.nkinds;
+    for (int idx = tid; idx < nslot * C; idx += kBlock) {
+      const int slot = idx / C, c = idx - slot * C;
+      const T2 v = a.fields[(int64_t)slot * a.M3 + c0 + c];
+      const int b = slot / a.nkinds, k = slot - b * a.nkinds;
+      for (int f = 0; f < a.nfc; ++f)
+        if (a.fcomp[f].slot == k) Fv[((size_t)b * a.nfc + f) * C + c] = a.fcomp[f].part ? v.y : v.x;
+    }
+    for (int idx = tid; idx < a.ngrid * C; idx += kBlock) {
+      const int g = idx / C, c = idx - g * C;
+      const T2 v = a.fields[((int64_t)nslot + g) * a.M3 + c0 + c];
+      for (int f = 0; f < a.ngc; ++f)
+        if (a.gcomp[f].slot == g) Gv[(size_t)f * C + c] = a.gcomp[f].part ? v.y : v.x;
+    }
+    __syncthreads();
+    // Q_q(x; b1)
+    for (int idx = tid; idx < a.nq * a.nb * C; idx += kBlock) {
+      const int c = idx % C;
+      const int qb = idx / C;
+      const int b1 = qb % a.nb, q = qb / a.nb;
+      const QGroup g = a.qg[q];
+      double s = 0.0;
+      for (int t = g.t0; t < g.t1; ++t) {
+        const Term tm = a.terms[t];
+        s += tm.coef * (double)Fv[((size_t)b1 * a.nfc + tm.f1) * C + c] * (double)Gv[(size_t)tm.g * C + c];
+      }
+      Qv[((size_t)q * a.nb + b1) * C + c] = (T)s;
+    }
+    __syncthreads();
+    // sum over the chunk's cells for every output of this thread
+#pragma unroll
+    for (int r = 0; r < kOutPerThread; ++r) {
+      const int o = tid + r * kBlock;
+      if (o >= a.nout) break;
+      const OutEntry e = a.outs[a.out0 + o];
+      double s = 0.0;
+      for (int q = e.q0; q < e.q1; ++q) {
+        const T* qr = Qv + ((size_t)q * a.nb + e.b1) * C;
+        const T* fr = Fv + ((size_t)e.b2 * a.nfc + a.qg[q].f2) * C;
+        for (int c = 0; c < C; ++c) s += (double)qr[c] * (double)fr[c];
+      }
+      acc[r] += s;
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int r = 0; r < kOutPerThread; ++r) {
+    const int o = tid + r * kBlock;
+    if (o < a.nout) a.partials[(size_t)blockIdx.x * a.nout_all + a.out0 + o] = acc[r];
+  }
+}
+
+__global__ void __launch_bounds__(kBlock) reduce_final_kernel(const double* partials, int nwg, int nout,
+                                                              const double* norm, const DevScalars* scal,
+                                                              double* B) {
+  const int o = blockIdx.x * kBlock + threadIdx.x;
+  if (o >= nout) return;
+  double s = 0.0;
+  for (int w = 0; w < nwg; ++w) s += partials[(size_t)w * nout + o];   // fixed order
+  B[o] = s * norm[o] / scal->I;
+}
+
+template <typename T>
+int reduce_impl(Plan& P, hipStream_t s) {
+  typedef typename cplx<T>::type T2;
+  RedArgs<T> a{};
+  a.fields = (const T2*)P.d_fields;
+  a.M3 = (int64_t)P.M * P.M * P.M;
+  a.nb = P.nb;
+  a.nkinds = (int)P.fkinds.size();
+  a.ngrid = (int)P.grids.size();
+  a.nfc = (int)P.fcomp.size();
+  a.ngc = (int)P.gcomp.size();
+  a.nq = (int)P.qgroups.size();
+  a.fcomp = P.d_fcomp;
+  a.gcomp = P.d_gcomp;
+  a.terms = P.d_terms;
+  a.qg = P.d_qgroups;
+  a.outs = P.d_outs;
+  a.chunk = P.red_chunk;
+  a.nchunks = a.M3 / P.red_chunk;
+  a.partials = P.d_partials;
+  const size_t lds = sizeof(T) * (size_t)P.red_chunk *
+                     ((size_t)a.nb * a.nfc + a.ngc + (size_t)a.nq * a.nb);
+  const int nout_all = (int)P.outs.size();
+  const int per_launch = kOutPerThread * kBlock;
+  a.nout_all = nout_all;
+  prof_begin(P, kStReduce, s);
+  for (int o0 = 0; o0 < nout_all; o0 += per_launch) {
+    a.out0 = o0;
+    a.nout = std::min(per_launch, nout_all - o0);
+    hipLaunchKernelGGL(reduce_kernel<T>, dim3(P.red_wg), dim3(kBlock), lds, s, a);
+  }
+  prof_end(P, kStReduce, s);
+  prof_begin(P, kStReduceFinal, s);
+  hipLaunchKernelGGL(reduce_final_kernel, dim3((nout_all + kBlock - 1) / kBlock), dim3(kBlock), 0, s,
+                     (const double*)P.d_partials, P.red_wg, nout_all, (const double*)P.d_out_norm,
+                     (const DevScalars*)P.d_scal, P.d_B);
+  prof_end(P, kStReduceFinal, s);
+  TSB_HIP(hipGetLastError());
+  return TSB_OK;
+}
+
+}  // namespace
+
+int run_reduce(Plan& P, hipStream_t s) {
+  if (P.outs.empty()) return TSB_OK;
+  return P.precision == TSB_FP64 ? reduce_impl<double>(P, s) : reduce_impl<float>(P, s);
+}
+
+}  // namespace tsb

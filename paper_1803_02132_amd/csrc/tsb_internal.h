@@ -1,0 +1,221 @@
+// Internal declarations of the gfx950 bispectrum-multipole library.
+// The public contract is include/triposh.h; everything here is private.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/triposh.h"
+
+namespace tsb {
+
+constexpr int kMaxEll = 8;          // largest l1, l2, L accepted
+constexpr int kMaxBins = 64;
+constexpr int kBlock = 256;          // threads per workgroup of every kernel
+
+// ---------------------------------------------------------------------------
+// error reporting
+
+void set_error(const std::string& msg);
+int fail(int code, const std::string& msg);
+
+#define TSB_HIP(call)                                                              \
+  do {                                                                             \
+    hipError_t e_ = (call);                                                        \
+    if (e_ != hipSuccess)                                                          \
+      return ::tsb::fail(TSB_E_DEVICE, std::string(#call) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+// ---------------------------------------------------------------------------
+// plan description
+
+// One real y-weighted density channel: weight w * Re(y_L^M*) (part 0) or
+// w * Im(y_L^M*) (part 1) for M >= 0 (eq. 34). Negative M follow from
+// dn_L^{-M}(x) = (-1)^M conj(dn_L^M(x)).
+struct RealChannel { int L, M, part; };
+
+// Two real channels transformed together as one complex grid (re + i im).
+struct ComplexGrid { int re, im; };  // indices into channels; im = -1: none
+
+// Input of one F slot (Sec. 4.2, eq. 42): sum over parts of
+//   (fr + i fi) * y_l^m*(k^) * dn(k) restricted to one shell.
+struct FPart { int l, m; double fr, fi; };
+struct FKind { int nparts; FPart part[2]; };
+
+// A real field used by the reduction: part (0 re, 1 im) of F slot kind
+// ``slot`` (F component) or of G grid ``slot`` (G component).
+struct Component { int slot, part; };
+
+// One real triple product of the expanded m-sum of eq. 41:
+// coef * f1(x; b1) * f2(x; b2) * g(x).
+struct Term { int mu, f1, f2, g; double coef; };
+
+// Device-side constants of the reduction.
+struct QGroup { int mu, f2, t0, t1; };        // Q_q(x;b1) = sum_{t0<=t<t1} coef f1 g
+struct OutEntry { int mu, b1, b2, q0, q1; };  // B(mu,b1,b2) = sum_{q0<=q<q1} sum_x Q_q(b1) f2_q(b2)
+
+// Scalars computed on the device during a measurement.
+struct DevScalars {
+  double sum_w, sum_w_ran, sum_abs, sum_abs_ran;
+  double alpha, scale, inv_scale, mean_cell, I;
+  int err;        // bit 0: non-finite input, bit 1: outside the box (survey),
+                  // bit 2: particle on the observer
+  int pad;
+};
+
+enum Stage {
+  kStWeights = 0, kStBucket, kStAssign, kStFwdZ, kStFwdY, kStFwdX, kStCombine,
+  kStInvFZ, kStInvFY, kStInvFX, kStInvGZ, kStInvGY, kStInvGX, kStReduce, kStReduceFinal, kNumStages
+};
+
+struct Plan {
+  // request
+  int N = 0;
+  double L = 0, origin[3] = {0, 0, 0};
+  int p = 3, interlace = 0;
+  int los_kind = TSB_LOS_LOCAL;
+  double los_dir[3] = {0, 0, 1}, observer[3] = {0, 0, 0};
+  int nb = 0;
+  double kmin = 0, dk = 0;
+  std::vector<tsb_multipole> mult;
+  int precision = TSB_FP32, pair_mode = TSB_PAIRS_PAPER, box_mode = 1;
+  double P0 = 0;
+  int device = 0;
+
+  // derived geometry
+  int M = 0;            // reduction grid
+  int RF = 0, RG = 0;   // cube half-widths of F inputs and of spectra / G inputs
+  int PF = 0, PG = 0;   // 2R+1
+  int64_t n2maxF = 0;   // largest |n|^2 in any shell
+  int64_t n2maxG = -1;  // G band limit on |n|^2 (-1: whole cube)
+  int T = 8, NT = 0;    // assignment tile side and tiles per axis
+  int copies = 1;       // 1 + interlace
+  std::vector<int> bin_lut;       // bin of n^2 for n^2 in [0, 3 RF^2]; -1 none
+  std::vector<int64_t> nmode;
+  std::vector<double> keff;
+
+  // channels, slots, terms
+  std::vector<RealChannel> chans;
+  std::vector<ComplexGrid> grids;
+  std::vector<FKind> fkinds;
+  std::vector<Component> fcomp, gcomp;
+  std::vector<Term> terms;
+  std::vector<QGroup> qgroups;
+  std::vector<OutEntry> outs;
+  std::vector<double> out_norm;   // per output: N H / (Nm1 Nm2 M^3) (divided by I on device)
+  std::vector<double> mu_pref;
+
+  // device buffers (owned)
+  void* d_grid = nullptr;     // [copies][ngrid][N^3] complex
+  void* d_t1 = nullptr;       // forward z-pass   [copies*ngrid][N][N][PG]
+  void* d_t2 = nullptr;       // forward y-pass   [copies*ngrid][N][PG][PG]
+  void* d_t3 = nullptr;       // forward x-pass   [copies*ngrid][PG][PG][PG]
+  void* d_spec = nullptr;     // combined spectra [ngrid][PG^3]
+  void* d_dcube = nullptr;    // dn_0^0 on the F cube [PF^3]
+  void* d_u1 = nullptr;       // inverse z-pass (F then G)
+  void* d_u2 = nullptr;       // inverse y-pass
+  void* d_fields = nullptr;   // F slots then G slots, [nslots][M^3] complex
+  void* d_tw_n = nullptr;     // twiddles e^{-2 pi i k/N}
+  void* d_tw_m = nullptr;     // twiddles e^{-2 pi i k/M}
+  int* d_bin_lut = nullptr;
+  FKind* d_fkinds = nullptr;
+  Component* d_fcomp = nullptr;
+  Component* d_gcomp = nullptr;
+  Term* d_terms = nullptr;
+  QGroup* d_qgroups = nullptr;
+  OutEntry* d_outs = nullptr;
+  double* d_out_norm = nullptr;
+  double* d_partials = nullptr;
+  double* d_B = nullptr;
+  DevScalars* d_scal = nullptr;
+  double* d_sum_partials = nullptr;   // per-block partial sums (prep and I)
+  int* d_tile_count = nullptr;
+  int* d_tile_start = nullptr;
+  int* d_tile_cursor = nullptr;
+  int* d_keys = nullptr;
+  int* d_sorted = nullptr;
+  int64_t particle_cap = 0;
+  int red_chunk = 64, red_wg = 1024;
+  int64_t bytes = 0;
+
+  // stage timing (HIP events on the measurement stream)
+  bool prof = false;
+  hipEvent_t ev[kNumStages][2] = {};
+  bool ev_pending[kNumStages] = {};
+  double stage_ms[kNumStages] = {};
+  int64_t stage_calls[kNumStages] = {};
+};
+
+// Bracket a stage with events when profiling is on (errors ignored: timing only).
+inline void prof_begin(Plan& P, int st, hipStream_t s) {
+  if (P.prof && P.ev[st][0]) (void)hipEventRecord(P.ev[st][0], s);
+}
+inline void prof_end(Plan& P, int st, hipStream_t s) {
+  if (P.prof && P.ev[st][1]) {
+    (void)hipEventRecord(P.ev[st][1], s);
+    P.ev_pending[st] = true;
+  }
+}
+
+int plan_build(Plan& P);   // host planning (plan.hip)
+// (-1)^m sqrt((l-m)!/(l+m)!) at index l(l+1)/2 + m, l <= kMaxEll (45 entries)
+void ylm_norm_table(double* norm);
+int plan_alloc(Plan& P, bool dry = false);   // device buffers (api.hip); dry: sizes only
+void plan_free(Plan& P);
+
+// ---------------------------------------------------------------------------
+// launchers (each enqueues on ``s``; returns TSB_OK or an error code)
+
+int run_prep(Plan& P, const tsb_catalog* data, const tsb_catalog* rand, hipStream_t s);
+int run_assign(Plan& P, const tsb_catalog* data, const tsb_catalog* rand, hipStream_t s);
+int run_forward(Plan& P, hipStream_t s);
+int run_inverse(Plan& P, hipStream_t s);
+int run_reduce(Plan& P, hipStream_t s);
+int run_unpack_grids(Plan& P, void* out, hipStream_t s);
+
+// ---------------------------------------------------------------------------
+// device helpers
+
+template <typename T> struct cplx;
+template <> struct cplx<float> { typedef float2 type; };
+template <> struct cplx<double> { typedef double2 type; };
+
+// Normalised harmonic y_l^m(u) for m >= 0 at a unit vector u (App. A, eq. A3),
+// written without dividing by sin(theta):
+//   y_l^m = (-1)^m sqrt((l-m)!/(l+m)!) Q_l^m(z) (x + i y)^m,
+// with Q_l^m = d^m P_l / dz^m from the recurrence
+//   Q_m^m = (2m-1)!!,  Q_{m+1}^m = (2m+1) z Q_m^m,
+//   (l-m) Q_l^m = (2l-1) z Q_{l-1}^m - (l+m-1) Q_{l-2}^m.
+// ``norm`` holds (-1)^m sqrt((l-m)!/(l+m)!) for (l, m) at index l*(l+1)/2 + m.
+__host__ __device__ inline void ylm_pos_m(int l, int m, double x, double y, double z,
+                                          const double* norm, double* re, double* im) {
+  double q_mm = 1.0;
+  for (int i = 1; i <= m; ++i) q_mm *= (2.0 * i - 1.0);
+  double q;
+  if (l == m) {
+    q = q_mm;
+  } else {
+    double qa = q_mm, qb = (2.0 * m + 1.0) * z * q_mm;
+    for (int ll = m + 2; ll <= l; ++ll) {
+      double qc = ((2.0 * ll - 1.0) * z * qb - (ll + m - 1.0) * qa) / (double)(ll - m);
+      qa = qb;
+      qb = qc;
+    }
+    q = qb;
+  }
+  // (x + i y)^m
+  double pr = 1.0, pi = 0.0;
+  for (int i = 0; i < m; ++i) {
+    double t = pr * x - pi * y;
+    pi = pr * y + pi * x;
+    pr = t;
+  }
+  double c = norm[l * (l + 1) / 2 + m] * q;
+  *re = c * pr;
+  *im = c * pi;
+}
+
+}  // namespace tsb
