@@ -32,36 +32,41 @@ WORKLOAD = dict(n=256, box_len=1000.0, n_bins=20, dk=0.01, k_min=0.0, multipoles
 SEEDS = [48, 49, 50, 51]
 KERNEL_SOURCES = {  # which source file holds each stage's kernel
     "assign": "assign.hip", "fwd_z": "fft.hip", "fwd_y": "fft.hip", "fwd_x": "fft.hip",
-    "invF_z": "fft.hip", "invF_y": "fft.hip", "invF_x": "fft.hip", "invG_z": "fft.hip",
-    "invG_y": "fft.hip", "invG_x": "fft.hip", "reduce": "reduce.hip"}
+    "invF_x": "fft.hip", "invF_y": "fft.hip", "invF_z": "fft.hip", "invG_x": "fft.hip",
+    "invG_y": "fft.hip", "invG_z": "fft.hip", "reduce": "fused.hip"}
 
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def stage_bytes(info, copies, n_particles, esz=4):
+def stage_bytes(info, copies, n_particles, fused=True, esz=4):
     """Algorithmic HBM bytes per launch of each single-kernel stage: every input
-    read once and every output written once in the stated layout."""
+    read once and every output written once in the stated layout (particle
+    records: 12 B of position plus 4 B per channel)."""
     c = 2 * esz
     N, M = info.n, info.m
     PG, PF = 2 * info.r_g + 1, 2 * info.r_f + 1
     ng = info.n_grids
     nbc = copies * ng
     nf = info.n_fslots * WORKLOAD["n_bins"]
-    return {
-        "assign": nbc * N ** 3 * c + 12 * n_particles,
+    out = {
+        "assign": nbc * N ** 3 * c + (24 + 4 * info.n_channels) * n_particles,
         "fwd_z": nbc * N ** 3 * c + nbc * N * N * PG * c,
         "fwd_y": nbc * N * N * PG * c + nbc * N * PG * PG * c,
         "fwd_x": nbc * N * PG * PG * c + nbc * PG ** 3 * c,
-        "invF_z": PF ** 3 * c + nf * PF * PF * M * c,
-        "invF_y": nf * PF * PF * M * c + nf * PF * M * M * c,
-        "invF_x": nf * PF * M * M * c + nf * M ** 3 * c,
-        "invG_z": ng * PG ** 3 * c + ng * PG * PG * M * c,
-        "invG_y": ng * PG * PG * M * c + ng * PG * M * M * c,
-        "invG_x": ng * PG * M * M * c + ng * M ** 3 * c,
-        "reduce": (nf + ng) * M ** 3 * c,
+        "invF_x": PF ** 3 * c + nf * M * PF * PF * c,
+        "invF_y": nf * M * PF * PF * c + nf * M * M * PF * c,
+        "invG_x": ng * PG ** 3 * c + ng * M * PG * PG * c,
+        "invG_y": ng * M * PG * PG * c + ng * M * M * PG * c,
+        "invG_z": ng * M * M * PG * c + ng * M ** 3 * c,
     }
+    if fused:   # last F transform inside the reduction: reads the y-pass output and G
+        out["reduce"] = nf * M * M * PF * c + ng * M ** 3 * c
+    else:
+        out["invF_z"] = nf * M * M * PF * c + nf * M ** 3 * c
+        out["reduce"] = (nf + ng) * M ** 3 * c
+    return out
 
 
 def source_hash(fname):
@@ -102,18 +107,22 @@ def cpu_baseline(cat, threads=1):
         spec = est.spectra(plan, grids)
         del grids
         t_front = time.perf_counter() - t0
+        log(f"oracle front end: {t_front:.1f} s")
         t0 = time.perf_counter()
         est.g_field(plan, spec, 2, 1)
         t_g = time.perf_counter() - t0
+        log(f"oracle G field: {t_g:.2f} s")
         bg = est.bin_grid(plan)
         units = est.mode_unit_vectors(plan)
         nm = est.nmode(plan)
         t0 = time.perf_counter()
         est.f_field(plan, spec, 2, 1, 10, bg, units, nm)
         t_f = time.perf_counter() - t0
+        log(f"oracle F field: {t_f:.2f} s")
         t0 = time.perf_counter()
         est.reduce_fft(plan, spec, info["I"], pairs=[(10, 10)])
         t_pair_total = time.perf_counter() - t0
+        log(f"oracle one shell pair: {t_pair_total:.1f} s")
     n_g = 6              # G_0^0 and G_2^M, M = -2..2
     n_f_per_shell = 6    # F_0^0 and F_2^m, m = -2..2
     t_pair = max(t_pair_total - n_g * t_g - n_f_per_shell * t_f, 0.0)
@@ -170,7 +179,8 @@ def main():
     value = args.steps / elapsed
     times = tsb.abi.tsb_plan_stage_times(plan.handle)
     n_mean = float(np.mean([len(c["pos"]) for c in cats]))
-    bytes_alg = stage_bytes(info, 2, n_mean)
+    fused = times["invF_z"][1] == 0
+    bytes_alg = stage_bytes(info, 2, n_mean, fused=fused)
     per_launch = {k: (ms / calls if calls else 0.0) for k, (ms, calls) in times.items()}
     log("stage mean ms per launch: " + ", ".join(f"{k}={v:.3f}" for k, v in per_launch.items()))
     dom = max((k for k in bytes_alg), key=lambda k: times[k][0])

@@ -100,6 +100,9 @@ typedef struct {
   int32_t pair_mode;  /* TSB_PAIRS_* */
   int32_t box_mode;   /* 1: periodic box without randoms; 0: survey with randoms */
   double P0;          /* FKP P0; <= 0 disables the FKP factor */
+  int32_t unfused;    /* 0: run the last F transform inside the reduction when the
+                         plan fits (default); 1: always write the F fields and
+                         reduce separately (same result to rounding) */
 } tsb_options;
 
 /* Particle catalogue: structure of arrays in DEVICE memory of the current
@@ -186,9 +189,10 @@ int tsb_plan_channel(const tsb_plan* plan, int32_t c, int32_t* L, int32_t* M, in
 /* Stage timing. With profiling enabled, every later tsb_measure records HIP
  * events around each stage on the caller's stream and accumulates the elapsed
  * times. Stages (index: name): 0 weights, 1 bucket, 2 assign, 3 fwd_z, 4 fwd_y,
- * 5 fwd_x, 6 combine, 7 invF_z, 8 invF_y, 9 invF_x, 10 invG_z, 11 invG_y,
- * 12 invG_x, 13 reduce, 14 reduce_final. Each of 3..13 is one kernel launch per
- * measurement (13: one per block of 4096 outputs). tsb_plan_stage_times writes
+ * 5 fwd_x, 6 combine, 7 invF_x, 8 invF_y, 9 invF_z, 10 invG_x, 11 invG_y,
+ * 12 invG_z, 13 reduce, 14 reduce_final. Each of 3..13 is one kernel launch per
+ * measurement (13: one per block of 4096 outputs; when the last F transform
+ * runs inside the reduction, stage 9 is empty and 13 covers both). tsb_plan_stage_times writes
  * up to n entries of accumulated milliseconds and call counts (either array may
  * be NULL) and, with reset != 0, clears the accumulators. */
 int tsb_plan_set_profiling(tsb_plan* plan, int32_t enable);

@@ -19,14 +19,14 @@ _PAIR = {"paper": abi.TSB_PAIRS_PAPER, "upper": abi.TSB_PAIRS_UPPER, "diagonal":
 
 def _request(n, box_len, multipoles, n_bins, dk, k_min=0.0, origin=(0.0, 0.0, 0.0), assign_p=3,
              interlace=False, los="local", los_dir=(0.0, 0.0, 1.0), observer=(0.0, 0.0, 0.0), box_mode=True,
-             P0=0.0, precision="f32", pair_mode="paper"):
+             P0=0.0, precision="f32", pair_mode="paper", unfused=False):
     grid = abi.tsb_grid(int(n), float(box_len), (abi.ctypes.c_double * 3)(*origin), int(assign_p), int(bool(interlace)))
     lo = abi.tsb_los(abi.TSB_LOS_LOCAL if los == "local" else abi.TSB_LOS_GLOBAL,
                      (abi.ctypes.c_double * 3)(*los_dir), (abi.ctypes.c_double * 3)(*observer))
     bins = abi.tsb_kbins(int(n_bins), float(k_min), float(dk))
     mps = [abi.tsb_multipole(*map(int, m)) for m in multipoles]
     opts = abi.tsb_options(abi.TSB_FP64 if precision == "f64" else abi.TSB_FP32, _PAIR[pair_mode],
-                           int(bool(box_mode)), float(P0))
+                           int(bool(box_mode)), float(P0), int(bool(unfused)))
     return grid, lo, bins, mps, opts
 
 

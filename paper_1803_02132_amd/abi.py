@@ -47,7 +47,7 @@ class tsb_multipole(ctypes.Structure):
 
 class tsb_options(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int32), ("pair_mode", ctypes.c_int32), ("box_mode", ctypes.c_int32),
-                ("P0", ctypes.c_double)]
+                ("P0", ctypes.c_double), ("unfused", ctypes.c_int32)]
 
 
 class tsb_catalog(ctypes.Structure):
@@ -92,8 +92,8 @@ _lib.tsb_plan_stage_times.restype = ctypes.c_int
 _lib.tsb_plan_stage_times.argtypes = [ctypes.c_void_p, ctypes.c_int32, _P(ctypes.c_double), _P(ctypes.c_int64),
                                       ctypes.c_int32]
 
-STAGES = ["weights", "bucket", "assign", "fwd_z", "fwd_y", "fwd_x", "combine", "invF_z", "invF_y", "invF_x",
-          "invG_z", "invG_y", "invG_x", "reduce", "reduce_final"]
+STAGES = ["weights", "bucket", "assign", "fwd_z", "fwd_y", "fwd_x", "combine", "invF_x", "invF_y", "invF_z",
+          "invG_x", "invG_y", "invG_z", "reduce", "reduce_final"]
 
 EXPORTED = ["tsb_plan_set_profiling", "tsb_plan_stage_times", "tsb_plan_create", "tsb_plan_destroy", "tsb_plan_query", "tsb_plan_get_info", "tsb_plan_nmode",
             "tsb_measure", "tsb_assign", "tsb_plan_channel", "tsb_last_error"]

@@ -4,7 +4,7 @@ import subprocess
 import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-SOURCES = ["plan.hip", "assign.hip", "fft.hip", "reduce.hip", "api.hip"]
+SOURCES = ["plan.hip", "assign.hip", "fft.hip", "fused.hip", "reduce.hip", "api.hip"]
 LIB = os.path.join(HERE, "libtriposh.so")
 
 FLAGS = [

@@ -79,11 +79,15 @@ int plan_alloc(Plan& P, bool dry) {
   ALLOC(P.d_dcube, PF * PF * PF * c);
   ALLOC(P.d_u1, std::max(nf * PF * PF * M, ng * PG * PG * M) * c);
   ALLOC(P.d_u2, std::max(nf * PF * M * M, ng * PG * M * M) * c);
-  ALLOC(P.d_fields, (nf + ng) * M * M * M * c);
+  ALLOC(P.d_fields, ((P.fused ? 0 : nf) + ng) * M * M * M * c);
   const int64_t ntiles = (int64_t)P.NT * P.NT * P.NT;
   ALLOC(P.d_tile_count, ntiles * 4);
   ALLOC(P.d_tile_start, ntiles * 4);
   ALLOC(P.d_tile_cursor, ntiles * 4);
+  ALLOC(P.d_tile_ndense, ntiles * 4);
+  ALLOC(P.d_dense_off, ntiles * 4);
+  ALLOC(P.d_dense_desc, ntiles * 64 * 16);
+  ALLOC(P.d_dense_bits, ntiles * (8 * (int64_t)P.T * P.T * P.T / 32) * 4);
   ALLOC(P.d_scal, (int64_t)sizeof(DevScalars));
   ALLOC(P.d_sum_partials, std::max<int64_t>(ntiles, 4 * 512) * 8);
   ALLOC(P.d_partials, (int64_t)P.red_wg * std::max<int64_t>((int64_t)P.outs.size(), 1) * 8);
@@ -100,6 +104,7 @@ int plan_alloc(Plan& P, bool dry) {
   if ((rc = upload(&P.d_qgroups, P.qgroups, B, dry))) return rc;
   if ((rc = upload(&P.d_outs, P.outs, B, dry))) return rc;
   if ((rc = upload(&P.d_out_norm, P.out_norm, B, dry))) return rc;
+  if ((rc = upload(&P.d_f2idx, P.f2idx, B, dry))) return rc;
   return TSB_OK;
 }
 
@@ -110,7 +115,9 @@ void plan_free(Plan& P) {
   void* ptrs[] = {P.d_grid, P.d_t1, P.d_t2, P.d_t3, P.d_spec, P.d_dcube, P.d_u1, P.d_u2, P.d_fields,
                   P.d_tw_n, P.d_tw_m, P.d_bin_lut, P.d_fkinds, P.d_fcomp, P.d_gcomp, P.d_terms,
                   P.d_qgroups, P.d_outs, P.d_out_norm, P.d_partials, P.d_B, P.d_scal, P.d_sum_partials,
-                  P.d_tile_count, P.d_tile_start, P.d_tile_cursor, P.d_keys, P.d_sorted};
+                  P.d_tile_count, P.d_tile_start, P.d_tile_cursor, P.d_keys, P.d_rec_u, P.d_rec_c,
+                  P.d_f2idx, P.d_perm, P.d_tile_ndense, P.d_dense_off, P.d_dense_desc, P.d_dense_bits,
+                  P.d_dense_contrib};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
 }
@@ -120,16 +127,29 @@ namespace {
 int ensure_particles(Plan& P, int64_t n) {
   if (n <= P.particle_cap) return TSB_OK;
   if (n > 2147483647LL) return fail(TSB_E_UNSUPPORTED, "more than 2^31-1 particles");
-  if (P.d_keys) (void)hipFree(P.d_keys);
-  if (P.d_sorted) (void)hipFree(P.d_sorted);
-  P.d_keys = P.d_sorted = nullptr;
-  P.bytes -= 8 * P.particle_cap;
-  P.particle_cap = 0;
-  const int64_t cap = std::max<int64_t>(n, 1024);
+  const int64_t nchx = (int64_t)P.chans.size() + (P.box_mode ? 0 : 1);
+  const int64_t esz = P.precision == TSB_FP64 ? 8 : 4;
+  const int64_t per = 4 + 4 + 24 + nchx * esz;   // key, permutation, u, channel weights
+  const int64_t ntiles = (int64_t)P.NT * P.NT * P.NT;
+  const int64_t np3 = (int64_t)P.p * P.p * P.p;
+  const int64_t per_group = (int64_t)P.copies * np3 * nchx * 8;
+  for (void* p : {(void*)P.d_keys, (void*)P.d_perm, P.d_rec_u, P.d_rec_c, P.d_dense_contrib})
+    if (p) (void)hipFree(p);
+  P.d_keys = P.d_perm = nullptr;
+  P.d_rec_u = P.d_rec_c = P.d_dense_contrib = nullptr;
+  P.bytes -= per * P.particle_cap + per_group * P.dense_cap;
+  P.particle_cap = P.dense_cap = 0;
+  const int64_t cap = std::max<int64_t>(n + n / 8, 1024);
+  // moment groups hold at least 8 particles each and at most 64 per tile
+  const int64_t gcap = std::min<int64_t>(ntiles * 64, cap / 8 + 1);
   int rc;
   if ((rc = dalloc((void**)&P.d_keys, cap * 4, P.bytes, false))) return rc;
-  if ((rc = dalloc((void**)&P.d_sorted, cap * 4, P.bytes, false))) return rc;
+  if ((rc = dalloc((void**)&P.d_perm, cap * 4, P.bytes, false))) return rc;
+  if ((rc = dalloc(&P.d_rec_u, cap * 24, P.bytes, false))) return rc;
+  if ((rc = dalloc(&P.d_rec_c, cap * nchx * esz, P.bytes, false))) return rc;
+  if ((rc = dalloc(&P.d_dense_contrib, gcap * per_group, P.bytes, false))) return rc;
   P.particle_cap = cap;
+  P.dense_cap = gcap;
   return TSB_OK;
 }
 
@@ -223,6 +243,7 @@ static int copy_request(Plan& P, const tsb_grid* grid, const tsb_los* los, const
   P.pair_mode = options->pair_mode;
   P.box_mode = options->box_mode ? 1 : 0;
   P.P0 = options->P0;
+  P.unfused = options->unfused ? 1 : 0;
   return plan_build(P);
 }
 
@@ -345,7 +366,14 @@ int tsb_measure(tsb_plan* plan, const tsb_catalog* data, const tsb_catalog* rand
   if ((rc = run_front(P, data, randoms, s))) return rc;
   if ((rc = run_forward(P, s))) return rc;
   if ((rc = run_inverse(P, s))) return rc;
-  if ((rc = run_reduce(P, s))) return rc;
+  if (P.fused) {
+    if (!P.outs.empty()) {
+      if ((rc = run_fused(P, s))) return rc;
+      if ((rc = run_reduce_final(P, s))) return rc;
+    }
+  } else if ((rc = run_reduce(P, s))) {
+    return rc;
+  }
   std::vector<double> hb(P.outs.size());
   DevScalars h{};
   if (!hb.empty()) TSB_HIP(hipMemcpyAsync(hb.data(), P.d_B, hb.size() * 8, hipMemcpyDeviceToHost, s));

@@ -18,6 +18,8 @@ namespace {
 constexpr int kMaxCh = 48;       // real channels (+1 randoms channel in survey mode)
 constexpr int kMaxGrids = 32;
 constexpr int kPrepBlocks = 512;
+constexpr int kDenseMin = 8;     // particles sharing a (cell, half-cell octant) that go by moments
+constexpr int kMaxDense = 64;    // moment groups per tile (further groups stay on the direct path)
 
 struct CatPtrs {
   const float *x, *y, *z, *w, *nbar;
@@ -140,7 +142,6 @@ struct BucketArgs {
   int* cursor;
   const int* start;
   int* keys;
-  int* sorted;
 };
 
 __device__ inline int cell_of(double u, int N) {
@@ -192,13 +193,341 @@ __global__ void __launch_bounds__(1024) scan_kernel(const int* in, int* out, int
   }
 }
 
-__global__ void __launch_bounds__(kBlock) bucket_fill_kernel(BucketArgs a) {
-  const int64_t ntot = a.d.n + a.r.n;
+// Channel layout shared by the record and tile kernels.
+struct ChanInfo {
+  int nch;                     // real channels (the survey randoms channel is nch)
+  int local;
+  double obs[3];
+  int chL[kMaxCh], chM[kMaxCh], chPart[kMaxCh];
+  double ynorm[45];
+};
+
+template <int NCH>
+__device__ inline void channel_values(const ChanInfo& ci, double x, double y, double z, double w, bool ran,
+                                      double alpha, double* cv) {
+  // c = w y_L^M*(x^) (eq. 34); randoms carry -alpha (eq. 34); survey mode adds
+  // the randoms channel (weight w, randoms only) used by the normalisation
+  double ux = 0.0, uy = 0.0, uz = 1.0;
+  if (ci.local) {
+    const double dx = x - ci.obs[0], dy = y - ci.obs[1], dz = z - ci.obs[2];
+    const double r = sqrt(dx * dx + dy * dy + dz * dz);
+    if (r > 0.0) {
+      ux = dx / r;
+      uy = dy / r;
+      uz = dz / r;
+    }
+  }
+  const double s = ran ? -alpha * w : w;
+#pragma unroll
+  for (int c = 0; c < NCH; ++c) {
+    if (c >= ci.nch) {
+      cv[c] = (c == ci.nch && ran) ? w : 0.0;
+      continue;
+    }
+    double re = 1.0, im = 0.0;
+    if (ci.local) ylm_pos_m(ci.chL[c], ci.chM[c], ux, uy, uz, ci.ynorm, &re, &im);
+    // Re(y*) = Re(y), Im(y*) = -Im(y)
+    cv[c] = s * (ci.chPart[c] ? -im : re);
+  }
+}
+
+// Particle records in bucket order: grid coordinate u (FP64; NaN marks a
+// particle that takes no part) and its channel weights.
+template <typename T>
+struct Records {
+  double* ux;
+  double* uy;
+  double* uz;
+  T* cv;                       // [nchx][cap]
+  int64_t cap;
+};
+
+template <typename T, int NCH>
+struct FillArgs {
+  BucketArgs b;
+  ChanInfo ci;
+  Records<T> rec;
+  double P0;
+  int box_mode, nchx;
+  const DevScalars* scal;
+};
+
+template <typename T, int NCH>
+__global__ void __launch_bounds__(kBlock) bucket_fill_kernel(FillArgs<T, NCH> a) {
+  const int64_t ntot = a.b.d.n + a.b.r.n;
+  const double alpha = a.scal->alpha;
+  const int N = a.b.N;
   for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < ntot;
        i += (int64_t)gridDim.x * kBlock) {
-    const int key = a.keys[i];
-    const int slot = a.start[key] + atomicAdd(&a.cursor[key], 1);
-    a.sorted[slot] = (int)i;
+    const int key = a.b.keys[i];
+    const int slot = a.b.start[key] + atomicAdd(&a.b.cursor[key], 1);
+    const bool ran = i >= a.b.d.n;
+    const CatPtrs& c = ran ? a.b.r : a.b.d;
+    const int64_t j = ran ? i - a.b.d.n : i;
+    const double x = c.x[j], y = c.y[j], z = c.z[j];
+    const double w = particle_weight(c, j, a.P0);
+    double u[3] = {(x - a.b.origin[0]) * a.b.inv_h, (y - a.b.origin[1]) * a.b.inv_h,
+                   (z - a.b.origin[2]) * a.b.inv_h};
+    bool ok = isfinite(u[0]) && isfinite(u[1]) && isfinite(u[2]) && isfinite(w);
+    for (int ax = 0; ax < 3 && ok; ++ax) {
+      if (u[ax] < 0.0 || u[ax] >= N) {
+        if (!a.box_mode) ok = false;   // reported by the weight pass
+        else u[ax] -= N * floor(u[ax] / N);
+      }
+    }
+    a.rec.ux[slot] = ok ? u[0] : NAN;
+    a.rec.uy[slot] = u[1];
+    a.rec.uz[slot] = u[2];
+    double cv[NCH];
+    channel_values<NCH>(a.ci, x, y, z, ok ? w : 0.0, ran, alpha, cv);
+#pragma unroll
+    for (int ch = 0; ch < NCH; ++ch)
+      if (ch < a.nchx) a.rec.cv[(int64_t)ch * a.rec.cap + slot] = (T)cv[ch];
+  }
+}
+
+// ----------------------------------------------------------------------------
+// dense groups: particles of one cell and one half-cell octant share the
+// stencil nodes of both interlaced grids, and their order-p weights are
+// polynomials (degree <= 2) in the in-cell offset f = u - floor(u). Such a
+// group is reduced once to the moments sum_i c_i f_x^a f_y^b f_z^c (a,b,c <= 2,
+// 64-bit fixed point, order-independent) and its node contributions follow
+// from the moments. This removes the serialised LDS atomics of crowded cells.
+
+struct GroupDesc { int start, count, key, pad; };
+
+// Key (local cell * 8 + octant) of a record in the tile at (ox, oy, oz), or -1
+// when the record is invalid or its stencils are not the group's canonical
+// ones (then it stays on the direct path).
+__device__ inline int group_key(const double* u, const int* o, int T, int p, int copies) {
+  if (!isfinite(u[0]) || !isfinite(u[1]) || !isfinite(u[2])) return -1;
+  int cell = 0, oct = 0;
+  for (int ax = 0; ax < 3; ++ax) {
+    const double c = floor(u[ax]);
+    const int bit = (int)(floor(u[ax] + 0.5) - c);
+    if (bit != 0 && bit != 1) return -1;
+    if (copies == 2 && p != 2) {
+      // second grid: nearest node of u + 1/2 must be c + 1 (as evaluated by the direct path)
+      if (floor((u[ax] + 0.5) + 0.5) != c + 1.0) return -1;
+    }
+    const int l = (int)c - o[ax];
+    if (l < 0 || l >= T) return -1;
+    cell = cell * T + l;
+    oct = oct * 2 + bit;
+  }
+  return cell * 8 + oct;
+}
+
+// Base node (relative to the cell) and weight polynomials w_s(f) = a0 + a1 f + a2 f^2
+// of the order-p kernel on one axis, for grid copy g and octant bit.
+__device__ inline int axis_poly(int p, int g, int bit, double (*cf)[3]) {
+  if (p == 3) {
+    if (g == 0) {
+      const double e = 0.5 + bit, h = 0.5 - bit;
+      cf[0][0] = 0.5 * e * e; cf[0][1] = -e; cf[0][2] = 0.5;
+      cf[1][0] = 0.75 - bit; cf[1][1] = 2.0 * bit; cf[1][2] = -1.0;
+      cf[2][0] = 0.5 * h * h; cf[2][1] = h; cf[2][2] = 0.5;
+      return bit - 1;
+    }
+    cf[0][0] = 0.5; cf[0][1] = -1.0; cf[0][2] = 0.5;
+    cf[1][0] = 0.5; cf[1][1] = 1.0; cf[1][2] = -1.0;
+    cf[2][0] = 0.0; cf[2][1] = 0.0; cf[2][2] = 0.5;
+    return 0;
+  }
+  if (p == 2) {
+    if (g == 0) {
+      cf[0][0] = 1.0; cf[0][1] = -1.0; cf[0][2] = 0.0;
+      cf[1][0] = 0.0; cf[1][1] = 1.0; cf[1][2] = 0.0;
+      return 0;
+    }
+    cf[0][0] = 0.5 + bit; cf[0][1] = -1.0; cf[0][2] = 0.0;
+    cf[1][0] = 0.5 - bit; cf[1][1] = 1.0; cf[1][2] = 0.0;
+    return bit;
+  }
+  cf[0][0] = 1.0; cf[0][1] = 0.0; cf[0][2] = 0.0;
+  return g == 0 ? bit : 1;
+}
+
+// Base node offset (relative to the cell) of axis_poly's stencil.
+__device__ inline int axis_base(int p, int g, int bit) {
+  if (p == 3) return g == 0 ? bit - 1 : 0;
+  if (p == 2) return g == 0 ? 0 : bit;
+  return g == 0 ? bit : 1;
+}
+
+struct SortArgs {
+  const int* start;
+  const int* count;
+  const double* ux;
+  const double* uy;
+  const double* uz;
+  int T, NT, p, copies, words;
+  int* perm;        // records in (cell, octant) order within each tile
+  int* ndense;      // [ntiles]
+  GroupDesc* desc;  // [ntiles][kMaxDense]
+  unsigned* bits;   // [ntiles][words]: key is a moment group
+};
+
+// exclusive scan of n ints in LDS by one workgroup (in place), returns the total
+__device__ inline int block_scan(int* v, int n, int* tmp) {
+  const int t = threadIdx.x;
+  const int per = (n + kBlock - 1) / kBlock;
+  const int b0 = t * per, b1 = min(n, b0 + per);
+  int s = 0;
+  for (int i = b0; i < b1; ++i) s += v[i];
+  tmp[t] = s;
+  __syncthreads();
+  for (int off = 1; off < kBlock; off <<= 1) {
+    const int x = t >= off ? tmp[t - off] : 0;
+    __syncthreads();
+    tmp[t] += x;
+    __syncthreads();
+  }
+  int run = tmp[t] - s;
+  const int total = tmp[kBlock - 1];
+  __syncthreads();
+  for (int i = b0; i < b1; ++i) {
+    const int c = v[i];
+    v[i] = run;
+    run += c;
+  }
+  __syncthreads();
+  return total;
+}
+
+__global__ void __launch_bounds__(kBlock) tile_sort_kernel(SortArgs a) {
+  extern __shared__ int sh[];
+  const int nkeys = 8 * a.T * a.T * a.T;
+  int* cnt = sh;                    // [nkeys + 1], last bin: direct path
+  int* pos = cnt + nkeys + 1;       // [nkeys + 1]
+  int* flag = pos + nkeys + 1;      // [nkeys]
+  unsigned* bw = (unsigned*)(flag + nkeys);   // [words]
+  __shared__ int tmp[kBlock];
+  const int tile = blockIdx.x;
+  const int o[3] = {tile / (a.NT * a.NT) * a.T, (tile / a.NT) % a.NT * a.T, tile % a.NT * a.T};
+  const int st = a.start[tile], n = a.count[tile];
+  for (int i = threadIdx.x; i <= nkeys; i += kBlock) cnt[i] = 0;
+  for (int i = threadIdx.x; i < a.words; i += kBlock) bw[i] = 0u;
+  __syncthreads();
+  for (int i = threadIdx.x; i < n; i += kBlock) {
+    const double u[3] = {a.ux[st + i], a.uy[st + i], a.uz[st + i]};
+    const int k = group_key(u, o, a.T, a.p, a.copies);
+    atomicAdd(&cnt[k < 0 ? nkeys : k], 1);
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i <= nkeys; i += kBlock) {
+    pos[i] = cnt[i];
+    if (i < nkeys) flag[i] = cnt[i] >= kDenseMin ? 1 : 0;
+  }
+  __syncthreads();
+  block_scan(pos, nkeys + 1, tmp);
+  // the first kMaxDense qualifying keys in key order become moment groups
+  const int nd = block_scan(flag, nkeys, tmp);
+  for (int k = threadIdx.x; k < nkeys; k += kBlock) {
+    if (cnt[k] < kDenseMin) continue;
+    const int r = flag[k];
+    if (r >= kMaxDense) continue;
+    GroupDesc d;
+    d.start = st + pos[k];
+    d.count = cnt[k];
+    d.key = k;
+    d.pad = 0;
+    a.desc[(size_t)tile * kMaxDense + r] = d;
+    atomicOr(&bw[k >> 5], 1u << (k & 31));
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) a.ndense[tile] = min(nd, kMaxDense);
+  for (int i = threadIdx.x; i < a.words; i += kBlock) a.bits[(size_t)tile * a.words + i] = bw[i];
+  // scatter the record indices into key order (order inside a key is immaterial)
+  for (int i = threadIdx.x; i <= nkeys; i += kBlock) cnt[i] = 0;
+  __syncthreads();
+  for (int i = threadIdx.x; i < n; i += kBlock) {
+    const double u[3] = {a.ux[st + i], a.uy[st + i], a.uz[st + i]};
+    int k = group_key(u, o, a.T, a.p, a.copies);
+    if (k < 0) k = nkeys;
+    const int slot = pos[k] + atomicAdd(&cnt[k], 1);
+    a.perm[st + slot] = st + i;
+  }
+}
+
+template <typename T>
+struct MomentArgs {
+  const int* dense_off;    // exclusive scan of ndense over tiles
+  const int* ndense;
+  const GroupDesc* desc;
+  const int* perm;
+  Records<T> rec;
+  int ntiles, tile, NT, p, copies, nchx;   // tile: assignment tile side
+  const DevScalars* scal;
+  long long* contrib;      // [group][copies][p^3][nchx]
+};
+
+// one wavefront (= one workgroup of 64) per moment group
+template <typename T>
+__global__ void __launch_bounds__(64) dense_moment_kernel(MomentArgs<T> a) {
+  __shared__ long long part[64][27];
+  __shared__ double mom[27];
+  const int lane = threadIdx.x;
+  const int total = a.dense_off[a.ntiles - 1] + a.ndense[a.ntiles - 1];
+  const int gidx = blockIdx.x;
+  if (gidx >= total) return;   // the whole workgroup leaves together
+  int lo = 0, hi = a.ntiles;     // dense_off[lo] <= gidx < dense_off[hi]
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (a.dense_off[mid] <= gidx) lo = mid;
+    else hi = mid;
+  }
+  const int tile = lo;
+  const GroupDesc d = a.desc[(size_t)tile * kMaxDense + (gidx - a.dense_off[tile])];
+  const int cellk = d.key >> 3, oct = d.key & 7;
+  const int ts = a.tile;
+  const double c[3] = {(double)(tile / (a.NT * a.NT) * ts + cellk / (ts * ts)),
+                       (double)((tile / a.NT) % a.NT * ts + (cellk / ts) % ts),
+                       (double)(tile % a.NT * ts + cellk % ts)};
+  const int bits[3] = {(oct >> 2) & 1, (oct >> 1) & 1, oct & 1};
+  const double scale = a.scal->scale, inv_scale = a.scal->inv_scale;
+  const int np = a.p * a.p * a.p;
+  for (int ch = 0; ch < a.nchx; ++ch) {
+    long long m[27];
+#pragma unroll
+    for (int j = 0; j < 27; ++j) m[j] = 0;
+    for (int i = lane; i < d.count; i += 64) {
+      const int r = a.perm[d.start + i];
+      const double cv = (double)a.rec.cv[(int64_t)ch * a.rec.cap + r];
+      const double f[3] = {a.rec.ux[r] - c[0], a.rec.uy[r] - c[1], a.rec.uz[r] - c[2]};
+      const double px[3] = {1.0, f[0], f[0] * f[0]}, py[3] = {1.0, f[1], f[1] * f[1]},
+                   pz[3] = {1.0, f[2], f[2] * f[2]};
+#pragma unroll
+      for (int ia = 0; ia < 3; ++ia)
+#pragma unroll
+        for (int ib = 0; ib < 3; ++ib)
+#pragma unroll
+          for (int ic = 0; ic < 3; ++ic) m[(ia * 3 + ib) * 3 + ic] += llrint(cv * px[ia] * py[ib] * pz[ic] * scale);
+    }
+#pragma unroll
+    for (int j = 0; j < 27; ++j) part[lane][j] = m[j];
+    __syncthreads();
+    if (lane < 27) {
+      long long sum = 0;
+      for (int l = 0; l < 64; ++l) sum += part[l][lane];
+      mom[lane] = (double)sum * inv_scale;
+    }
+    __syncthreads();
+    // node contributions of both grid copies
+    for (int item = lane; item < a.copies * np; item += 64) {
+      const int g = item / np, nd = item % np;
+      const int sx = nd / (a.p * a.p), sy = (nd / a.p) % a.p, sz = nd % a.p;
+      double cx[3][3], cy[3][3], cz[3][3];
+      axis_poly(a.p, g, bits[0], cx);
+      axis_poly(a.p, g, bits[1], cy);
+      axis_poly(a.p, g, bits[2], cz);
+      double v = 0.0;
+      for (int ia = 0; ia < 3; ++ia)
+        for (int ib = 0; ib < 3; ++ib)
+          for (int ic = 0; ic < 3; ++ic) v += cx[sx][ia] * cy[sy][ib] * cz[sz][ic] * mom[(ia * 3 + ib) * 3 + ic];
+      a.contrib[(((size_t)gidx * a.copies + g) * np + nd) * a.nchx + ch] = llrint(v * scale);
+    }
+    __syncthreads();
   }
 }
 
@@ -206,20 +535,23 @@ __global__ void __launch_bounds__(kBlock) bucket_fill_kernel(BucketArgs a) {
 // tile assignment
 
 struct TileArgs {
-  CatPtrs d, r;
-  double P0, inv_h, h, origin[3], obs[3];
-  int N, T, NT, p, copies, box_mode, local;
-  int nch;                     // real channels (the survey randoms channel is nch)
-  int chL[kMaxCh], chM[kMaxCh], chPart[kMaxCh];
+  double inv_h, h, origin[3];
+  int N, T, NT, p, copies, box_mode;
+  ChanInfo ci;
   int ngrid;
   int gre[kMaxGrids], gim[kMaxGrids];
-  double ynorm[45];
   const int* start;
   const int* count;
-  const int* sorted;
   const DevScalars* scal;
   void* out;                   // [copies][ngrid][N^3] complex
   double* tile_I;              // survey: per-tile sum of (alpha R)^3
+  // moment groups
+  const int* ndense;
+  const int* dense_off;
+  const GroupDesc* desc;
+  const unsigned* bits;
+  int words;
+  const long long* contrib;
 };
 
 // Per-axis stencil of the order-p kernel (Hockney & Eastwood) at grid
@@ -242,136 +574,172 @@ __device__ inline int axis_stencil(double u, int p, double* wt) {
   return (int)j - 1;
 }
 
-template <int NCH>
-__device__ inline void channel_values(const TileArgs& a, double x, double y, double z, double w,
-                                      bool ran, double alpha, double* cv) {
-  // c = w y_L^M*(x^) (eq. 34); randoms carry -alpha (eq. 34), plus the
-  // unweighted-by-y randoms channel for the normalisation (survey mode)
-  double ux = 0.0, uy = 0.0, uz = 1.0;
-  if (a.local) {
-    const double dx = x - a.obs[0], dy = y - a.obs[1], dz = z - a.obs[2];
-    const double r = sqrt(dx * dx + dy * dy + dz * dz);
-    if (r > 0.0) {
-      ux = dx / r;
-      uy = dy / r;
-      uz = dz / r;
-    }
-  }
-  const double s = ran ? -alpha * w : w;
-#pragma unroll
-  for (int c = 0; c < NCH; ++c) {
-    if (c >= a.nch) {
-      cv[c] = (c == a.nch && ran) ? w : 0.0;
-      continue;
-    }
-    double re = 1.0, im = 0.0;
-    if (a.local) ylm_pos_m(a.chL[c], a.chM[c], ux, uy, uz, a.ynorm, &re, &im);
-    // Re(y*) = Re(y), Im(y*) = -Im(y)
-    cv[c] = s * (a.chPart[c] ? -im : re);
-  }
-}
-
 // Box mode (periodic, no randoms): dn = n - nbar subtracts the mean weight per
 // cell times y_L^M*(x^_node) from channel ch.
-__device__ inline double node_term(const TileArgs& a, int ch, double mean, double ux, double uy,
-                                   double uz) {
+__device__ inline double node_term(const ChanInfo& ci, int ch, double mean, double ux, double uy, double uz) {
   double re = 1.0, im = 0.0;
-  if (a.local) ylm_pos_m(a.chL[ch], a.chM[ch], ux, uy, uz, a.ynorm, &re, &im);
-  return mean * (a.chPart[ch] ? -im : re);
+  if (ci.local) ylm_pos_m(ci.chL[ch], ci.chM[ch], ux, uy, uz, ci.ynorm, &re, &im);
+  return mean * (ci.chPart[ch] ? -im : re);
 }
 
 template <typename T, int NCH>
-__global__ void __launch_bounds__(kBlock) assign_tile_kernel(TileArgs a) {
+__global__ void __launch_bounds__(kBlock) assign_tile_kernel(TileArgs a, Records<T> rec) {
   typedef typename cplx<T>::type T2;
   extern __shared__ unsigned long long acc[];   // [copies][nchx][T^3]
+  __shared__ int nb_start[27];
+  __shared__ int nb_off[28];
+  __shared__ int nb_tile[27];
+  __shared__ int nb_org[27][3];
+  __shared__ int nb_goff[28];                   // prefix of the neighbours' moment-group items
   const int T3 = a.T * a.T * a.T;
-  const int nchx = a.nch + (a.box_mode ? 0 : 1);
+  const int nch = a.ci.nch;
+  const int nchx = nch + (a.box_mode ? 0 : 1);
   const int tile = blockIdx.x;
   const int tx = tile / (a.NT * a.NT), ty = (tile / a.NT) % a.NT, tz = tile % a.NT;
   const int ox = tx * a.T, oy = ty * a.T, oz = tz * a.T;
+  const int N = a.N;
   for (int i = threadIdx.x; i < a.copies * nchx * T3; i += kBlock) acc[i] = 0ull;
-  __syncthreads();
-  const double scale = a.scal->scale;
-  const double alpha = a.scal->alpha;
-
-  // neighbouring tiles, each visited once even when NT < 3 wraps them together
-  for (int nb = 0; nb < 27; ++nb) {
-    const int dx = nb / 9 - 1, dy = (nb / 3) % 3 - 1, dz = nb % 3 - 1;
-    const int nx = (tx + dx + a.NT) % a.NT, ny = (ty + dy + a.NT) % a.NT, nz = (tz + dz + a.NT) % a.NT;
+  // the 27 neighbouring tiles, each once even when NT < 3 wraps them together
+  if (threadIdx.x < 27) {
+    const int nb = threadIdx.x;
+    const int nx = (tx + nb / 9 - 1 + a.NT) % a.NT, ny = (ty + (nb / 3) % 3 - 1 + a.NT) % a.NT,
+              nz = (tz + nb % 3 - 1 + a.NT) % a.NT;
     bool dup = false;
     for (int pb = 0; pb < nb && !dup; ++pb) {
       const int ex = (tx + pb / 9 - 1 + a.NT) % a.NT, ey = (ty + (pb / 3) % 3 - 1 + a.NT) % a.NT,
                 ez = (tz + pb % 3 - 1 + a.NT) % a.NT;
       dup = (ex == nx && ey == ny && ez == nz);
     }
-    if (dup) continue;
     const int nt = (nx * a.NT + ny) * a.NT + nz;
-    const int st = a.start[nt], cnt = a.count[nt];
-    for (int k = threadIdx.x; k < cnt; k += kBlock) {
-      const int pid = a.sorted[st + k];
-      const bool ran = pid >= a.d.n;
-      const CatPtrs& c = ran ? a.r : a.d;
-      const int64_t j = ran ? (int64_t)pid - a.d.n : (int64_t)pid;
-      const double x = c.x[j], y = c.y[j], z = c.z[j];
-      const double w = particle_weight(c, j, a.P0);
-      double u[3] = {(x - a.origin[0]) * a.inv_h, (y - a.origin[1]) * a.inv_h,
-                     (z - a.origin[2]) * a.inv_h};
-      bool ok = isfinite(u[0]) && isfinite(u[1]) && isfinite(u[2]) && isfinite(w);
-      for (int ax = 0; ax < 3 && ok; ++ax) {
-        if (u[ax] < 0.0 || u[ax] >= a.N) {
-          if (!a.box_mode) ok = false;   // reported by the weight pass
-          else u[ax] -= a.N * floor(u[ax] / a.N);
+    nb_start[nb] = a.start[nt];
+    nb_off[nb + 1] = dup ? 0 : a.count[nt];
+    nb_tile[nb] = nt;
+    nb_org[nb][0] = nx * a.T;
+    nb_org[nb][1] = ny * a.T;
+    nb_org[nb][2] = nz * a.T;
+    nb_goff[nb + 1] = dup ? 0 : a.ndense[nt];
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    nb_off[0] = 0;
+    nb_goff[0] = 0;
+    for (int k = 0; k < 27; ++k) {
+      nb_off[k + 1] += nb_off[k];
+      nb_goff[k + 1] += nb_goff[k];
+    }
+  }
+  __syncthreads();
+  const double scale = a.scal->scale;
+  const int total = nb_off[27];
+  for (int idx = threadIdx.x; idx < total; idx += kBlock) {
+    int lo = 0, hi = 27;   // nb_off[lo] <= idx < nb_off[hi]
+    while (hi - lo > 1) {
+      const int mid = (lo + hi) >> 1;
+      if (nb_off[mid] <= idx) lo = mid;
+      else hi = mid;
+    }
+    const int64_t slot = nb_start[lo] + (idx - nb_off[lo]);
+    const double u[3] = {rec.ux[slot], rec.uy[slot], rec.uz[slot]};
+    if (!isfinite(u[0])) continue;
+    {
+      // particles of their tile's moment groups arrive through the group sums below
+      const int key = group_key(u, nb_org[lo], a.T, a.p, a.copies);
+      if (key >= 0 && (a.bits[(size_t)nb_tile[lo] * a.words + (key >> 5)] >> (key & 31) & 1u)) continue;
+    }
+    bool have = false;
+    double cv[NCH];
+    for (int g = 0; g < a.copies; ++g) {
+      double wt[3][3];
+      int lo3[3], msk[3];
+      bool any = true;
+      const int o3[3] = {ox, oy, oz};
+      for (int ax = 0; ax < 3; ++ax) {
+        lo3[ax] = axis_stencil(u[ax] + 0.5 * g, a.p, wt[ax]);
+        msk[ax] = 0;
+        for (int s = 0; s < a.p; ++s) {
+          int jj = lo3[ax] + s;
+          if (jj < 0) jj += N;
+          if (jj >= N) jj -= N;
+          const int l = jj - o3[ax];
+          if (l >= 0 && l < a.T) msk[ax] |= 1 << s;
         }
+        any = any && msk[ax];
       }
-      if (!ok) continue;
-      double cv[NCH];
-      bool have = false;
-      for (int g = 0; g < a.copies; ++g) {
-        double wt[3][3];
-        int lo[3], msk[3];
-        bool any = true;
-        for (int ax = 0; ax < 3; ++ax) {
-          const double ug = u[ax] + 0.5 * g;
-          lo[ax] = axis_stencil(ug, a.p, wt[ax]);
-          const int o = ax == 0 ? ox : (ax == 1 ? oy : oz);
-          msk[ax] = 0;
-          for (int s = 0; s < a.p; ++s) {
-            int jj = (lo[ax] + s) % a.N;
-            if (jj < 0) jj += a.N;
-            const int l = jj - o;
-            if (l >= 0 && l < a.T) msk[ax] |= 1 << s;
-          }
-          any = any && msk[ax];
-        }
-        if (!any) continue;
-        if (!have) {
-          channel_values<NCH>(a, x, y, z, w, ran, alpha, cv);
-          have = true;
-        }
-        for (int sx = 0; sx < a.p; ++sx) {
-          if (!(msk[0] >> sx & 1)) continue;
-          const int lx = ((lo[0] + sx) % a.N + a.N) % a.N - ox;
-          for (int sy = 0; sy < a.p; ++sy) {
-            if (!(msk[1] >> sy & 1)) continue;
-            const int ly = ((lo[1] + sy) % a.N + a.N) % a.N - oy;
-            const double wxy = wt[0][sx] * wt[1][sy];
-            for (int sz = 0; sz < a.p; ++sz) {
-              if (!(msk[2] >> sz & 1)) continue;
-              const int lz = ((lo[2] + sz) % a.N + a.N) % a.N - oz;
-              const double W = wxy * wt[2][sz];
-              const int cell = (lx * a.T + ly) * a.T + lz;
-              unsigned long long* base = acc + (size_t)g * nchx * T3 + cell;
+      if (!any) continue;
+      if (!have) {
 #pragma unroll
-              for (int ch = 0; ch < NCH; ++ch) {
-                if (ch >= nchx) break;
-                if (ch == a.nch && g != 0) break;
-                const double v = cv[ch] * W;
-                if (v != 0.0)
-                  atomicAdd(base + (size_t)ch * T3, (unsigned long long)llrint(v * scale));
-              }
+        for (int ch = 0; ch < NCH; ++ch) cv[ch] = ch < nchx ? (double)rec.cv[(int64_t)ch * rec.cap + slot] : 0.0;
+        have = true;
+      }
+      for (int sx = 0; sx < a.p; ++sx) {
+        if (!(msk[0] >> sx & 1)) continue;
+        int jx = lo3[0] + sx;
+        jx += jx < 0 ? N : (jx >= N ? -N : 0);
+        const int lx = jx - ox;
+        for (int sy = 0; sy < a.p; ++sy) {
+          if (!(msk[1] >> sy & 1)) continue;
+          int jy = lo3[1] + sy;
+          jy += jy < 0 ? N : (jy >= N ? -N : 0);
+          const int ly = jy - oy;
+          const double wxy = wt[0][sx] * wt[1][sy];
+          for (int sz = 0; sz < a.p; ++sz) {
+            if (!(msk[2] >> sz & 1)) continue;
+            int jz = lo3[2] + sz;
+            jz += jz < 0 ? N : (jz >= N ? -N : 0);
+            const int lz = jz - oz;
+            const double W = wxy * wt[2][sz];
+            const int cell = (lx * a.T + ly) * a.T + lz;
+            unsigned long long* base = acc + (size_t)g * nchx * T3 + cell;
+#pragma unroll
+            for (int ch = 0; ch < NCH; ++ch) {
+              if (ch >= nchx) break;
+              if (ch == nch && g != 0) break;
+              const double v = cv[ch] * W;
+              if (v != 0.0) atomicAdd(base + (size_t)ch * T3, (unsigned long long)llrint(v * scale));
             }
           }
         }
+      }
+    }
+  }
+  // moment groups of the neighbouring tiles: add their node sums that fall here
+  {
+    const int np = a.p * a.p * a.p;
+    const int per_group = a.copies * np;
+    const int gtotal = nb_goff[27] * per_group;
+    for (int item = threadIdx.x; item < gtotal; item += kBlock) {
+      const int gi = item / per_group, rest = item - gi * per_group;
+      const int g = rest / np, nd = rest - g * np;
+      int lo = 0, hi = 27;
+      while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (nb_goff[mid] <= gi) lo = mid;
+        else hi = mid;
+      }
+      const int nt = nb_tile[lo];
+      const int j = gi - nb_goff[lo];
+      const GroupDesc d = a.desc[(size_t)nt * kMaxDense + j];
+      const int cellk = d.key >> 3, oct = d.key & 7;
+      const int sv[3] = {nd / (a.p * a.p), (nd / a.p) % a.p, nd % a.p};
+      const int loc[3] = {cellk / (a.T * a.T), (cellk / a.T) % a.T, cellk % a.T};
+      const int o3[3] = {ox, oy, oz};
+      int l3[3];
+      bool inside = true;
+      for (int ax = 0; ax < 3; ++ax) {
+        const int bit = (oct >> (2 - ax)) & 1;
+        int jj = nb_org[lo][ax] + loc[ax] + axis_base(a.p, g, bit) + sv[ax];
+        jj += jj < 0 ? N : (jj >= N ? -N : 0);
+        l3[ax] = jj - o3[ax];
+        inside = inside && l3[ax] >= 0 && l3[ax] < a.T;
+      }
+      if (!inside) continue;
+      const int cell = (l3[0] * a.T + l3[1]) * a.T + l3[2];
+      const long long* cb = a.contrib + (((size_t)(a.dense_off[nt] + j) * a.copies + g) * np + nd) * nchx;
+      unsigned long long* base = acc + (size_t)g * nchx * T3 + cell;
+      for (int ch = 0; ch < nchx; ++ch) {
+        if (ch == nch && g != 0) break;
+        const long long v = cb[ch];
+        if (v != 0) atomicAdd(base + (size_t)ch * T3, (unsigned long long)v);
       }
     }
   }
@@ -381,16 +749,16 @@ __global__ void __launch_bounds__(kBlock) assign_tile_kernel(TileArgs a) {
   const double inv_scale = a.scal->inv_scale;
   const double mean = a.scal->mean_cell;
   T2* out = (T2*)a.out;
-  const size_t N3 = (size_t)a.N * a.N * a.N;
+  const size_t N3 = (size_t)N * N * N;
   for (int i = threadIdx.x; i < a.copies * T3; i += kBlock) {
     const int g = i / T3, cell = i % T3;
     const int lx = cell / (a.T * a.T), ly = (cell / a.T) % a.T, lz = cell % a.T;
     const int ix = ox + lx, iy = oy + ly, iz = oz + lz;
     double ux = 0.0, uy = 0.0, uz = 1.0;
-    if (a.box_mode && a.local) {
-      const double px = a.origin[0] + (ix - 0.5 * g) * a.h - a.obs[0];
-      const double py = a.origin[1] + (iy - 0.5 * g) * a.h - a.obs[1];
-      const double pz = a.origin[2] + (iz - 0.5 * g) * a.h - a.obs[2];
+    if (a.box_mode && a.ci.local) {
+      const double px = a.origin[0] + (ix - 0.5 * g) * a.h - a.ci.obs[0];
+      const double py = a.origin[1] + (iy - 0.5 * g) * a.h - a.ci.obs[1];
+      const double pz = a.origin[2] + (iz - 0.5 * g) * a.h - a.ci.obs[2];
       const double r = sqrt(px * px + py * py + pz * pz);
       if (r > 0.0) {
         ux = px / r;
@@ -398,14 +766,14 @@ __global__ void __launch_bounds__(kBlock) assign_tile_kernel(TileArgs a) {
         uz = pz / r;
       }
     }
-    const size_t lin = ((size_t)ix * a.N + iy) * a.N + iz;
+    const size_t lin = ((size_t)ix * N + iy) * N + iz;
     for (int gr = 0; gr < a.ngrid; ++gr) {
       const int cre = a.gre[gr], cim = a.gim[gr];
       double vre = (double)(long long)acc[((size_t)g * nchx + cre) * T3 + cell] * inv_scale;
       double vim = cim >= 0 ? (double)(long long)acc[((size_t)g * nchx + cim) * T3 + cell] * inv_scale : 0.0;
       if (a.box_mode) {
-        vre -= node_term(a, cre, mean, ux, uy, uz);
-        if (cim >= 0) vim -= node_term(a, cim, mean, ux, uy, uz);
+        vre -= node_term(a.ci, cre, mean, ux, uy, uz);
+        if (cim >= 0) vim -= node_term(a.ci, cim, mean, ux, uy, uz);
       }
       T2 o;
       o.x = (T)vre;
@@ -416,9 +784,10 @@ __global__ void __launch_bounds__(kBlock) assign_tile_kernel(TileArgs a) {
   if (!a.box_mode) {
     // Sec. 4.2, eq. 37: partial of sum_j (alpha R_j)^3 over this tile (first grid)
     __shared__ double sh[kBlock];
+    const double alpha = a.scal->alpha;
     double s = 0.0;
     for (int cell = threadIdx.x; cell < T3; cell += kBlock) {
-      const double R = (double)(long long)acc[(size_t)a.nch * T3 + cell] * inv_scale;
+      const double R = (double)(long long)acc[(size_t)nch * T3 + cell] * inv_scale;
       const double v = alpha * R;
       s += v * v * v;
     }
@@ -516,6 +885,109 @@ int run_prep(Plan& P, const tsb_catalog* data, const tsb_catalog* rand, hipStrea
   return TSB_OK;
 }
 
+template <typename T, int NCH>
+int assign_impl(Plan& P, const BucketArgs& b, const ChanInfo& ci, hipStream_t s) {
+  const int ntiles = P.NT * P.NT * P.NT;
+  const int64_t ntot = b.d.n + b.r.n;
+  const int nchx = ci.nch + (P.box_mode ? 0 : 1);
+  Records<T> rec;
+  rec.cap = P.particle_cap;
+  rec.ux = (double*)P.d_rec_u;
+  rec.uy = rec.ux + rec.cap;
+  rec.uz = rec.uy + rec.cap;
+  rec.cv = (T*)P.d_rec_c;
+  if (ntot > 0) {
+    FillArgs<T, NCH> f;
+    f.b = b;
+    f.ci = ci;
+    f.rec = rec;
+    f.P0 = P.P0;
+    f.box_mode = P.box_mode;
+    f.nchx = nchx;
+    f.scal = P.d_scal;
+    hipLaunchKernelGGL((bucket_fill_kernel<T, NCH>), dim3(grid_blocks(ntot)), dim3(kBlock), 0, s, f);
+  }
+  // moment groups: per-tile sort by (cell, octant), then one wavefront per group
+  const int words = 8 * P.T * P.T * P.T / 32;
+  {
+    SortArgs so;
+    so.start = P.d_tile_start;
+    so.count = P.d_tile_count;
+    so.ux = rec.ux;
+    so.uy = rec.uy;
+    so.uz = rec.uz;
+    so.T = P.T;
+    so.NT = P.NT;
+    so.p = P.p;
+    so.copies = P.copies;
+    so.words = words;
+    so.perm = P.d_perm;
+    so.ndense = P.d_tile_ndense;
+    so.desc = (GroupDesc*)P.d_dense_desc;
+    so.bits = (unsigned*)P.d_dense_bits;
+    const int nkeys = 8 * P.T * P.T * P.T;
+    const size_t lds = (size_t)(3 * nkeys + 2) * sizeof(int) + (size_t)words * sizeof(unsigned);
+    hipLaunchKernelGGL(tile_sort_kernel, dim3(ntiles), dim3(kBlock), lds, s, so);
+    hipLaunchKernelGGL(scan_kernel, dim3(1), dim3(1024), 0, s, (const int*)P.d_tile_ndense, P.d_dense_off, ntiles);
+    MomentArgs<T> m;
+    m.dense_off = P.d_dense_off;
+    m.ndense = P.d_tile_ndense;
+    m.desc = (const GroupDesc*)P.d_dense_desc;
+    m.perm = P.d_perm;
+    m.rec = rec;
+    m.ntiles = ntiles;
+    m.tile = P.T;
+    m.NT = P.NT;
+    m.p = P.p;
+    m.copies = P.copies;
+    m.nchx = nchx;
+    m.scal = P.d_scal;
+    m.contrib = (long long*)P.d_dense_contrib;
+    const int64_t groups = std::min<int64_t>((int64_t)ntiles * kMaxDense, ntot / kDenseMin + 1);
+    hipLaunchKernelGGL(dense_moment_kernel<T>, dim3((unsigned)groups), dim3(64), 0, s, m);
+  }
+  prof_end(P, kStBucket, s);
+
+  TileArgs a{};
+  a.inv_h = (double)P.N / P.L;
+  a.h = P.L / (double)P.N;
+  for (int i = 0; i < 3; ++i) a.origin[i] = P.origin[i];
+  a.N = P.N;
+  a.T = P.T;
+  a.NT = P.NT;
+  a.p = P.p;
+  a.copies = P.copies;
+  a.box_mode = P.box_mode;
+  a.ci = ci;
+  a.ngrid = (int)P.grids.size();
+  for (int g = 0; g < a.ngrid; ++g) {
+    a.gre[g] = P.grids[g].re;
+    a.gim[g] = P.grids[g].im;
+  }
+  a.start = P.d_tile_start;
+  a.count = P.d_tile_count;
+  a.scal = P.d_scal;
+  a.out = P.d_grid;
+  a.tile_I = P.d_sum_partials;
+  a.ndense = P.d_tile_ndense;
+  a.dense_off = P.d_dense_off;
+  a.desc = (const GroupDesc*)P.d_dense_desc;
+  a.bits = (const unsigned*)P.d_dense_bits;
+  a.words = words;
+  a.contrib = (const long long*)P.d_dense_contrib;
+  const size_t lds = (size_t)P.copies * nchx * P.T * P.T * P.T * sizeof(unsigned long long);
+  prof_begin(P, kStAssign, s);
+  hipLaunchKernelGGL((assign_tile_kernel<T, NCH>), dim3(ntiles), dim3(kBlock), lds, s, a, rec);
+  if (!P.box_mode) {
+    const double vc = P.L * P.L * P.L / ((double)P.N * P.N * P.N);
+    hipLaunchKernelGGL(norm_final_kernel, dim3(1), dim3(kBlock), 0, s, (const double*)P.d_sum_partials,
+                       ntiles, P.d_scal, vc);
+  }
+  prof_end(P, kStAssign, s);
+  TSB_HIP(hipGetLastError());
+  return TSB_OK;
+}
+
 int run_assign(Plan& P, const tsb_catalog* data, const tsb_catalog* rand, hipStream_t s) {
   const int ntiles = P.NT * P.NT * P.NT;
   BucketArgs b{};
@@ -530,7 +1002,6 @@ int run_assign(Plan& P, const tsb_catalog* data, const tsb_catalog* rand, hipStr
   b.cursor = P.d_tile_cursor;
   b.start = P.d_tile_start;
   b.keys = P.d_keys;
-  b.sorted = P.d_sorted;
   const int64_t ntot = b.d.n + b.r.n;
   prof_begin(P, kStBucket, s);
   hipLaunchKernelGGL(zero_ints_kernel, dim3(grid_blocks(ntiles)), dim3(kBlock), 0, s, P.d_tile_count, (int64_t)ntiles);
@@ -538,69 +1009,23 @@ int run_assign(Plan& P, const tsb_catalog* data, const tsb_catalog* rand, hipStr
   if (ntot > 0)
     hipLaunchKernelGGL(bucket_count_kernel, dim3(grid_blocks(ntot)), dim3(kBlock), 0, s, b);
   hipLaunchKernelGGL(scan_kernel, dim3(1), dim3(1024), 0, s, (const int*)P.d_tile_count, P.d_tile_start, ntiles);
-  if (ntot > 0)
-    hipLaunchKernelGGL(bucket_fill_kernel, dim3(grid_blocks(ntot)), dim3(kBlock), 0, s, b);
-  prof_end(P, kStBucket, s);
 
-  TileArgs a{};
-  a.d = b.d;
-  a.r = b.r;
-  a.P0 = P.P0;
-  a.inv_h = (double)P.N / P.L;
-  a.h = P.L / (double)P.N;
-  for (int i = 0; i < 3; ++i) {
-    a.origin[i] = P.origin[i];
-    a.obs[i] = P.observer[i];
+  ChanInfo ci{};
+  ci.nch = (int)P.chans.size();
+  if (ci.nch + 1 > kMaxCh || (int)P.grids.size() > kMaxGrids) return fail(TSB_E_UNSUPPORTED, "too many channels");
+  ci.local = P.los_kind == TSB_LOS_LOCAL;
+  for (int i = 0; i < 3; ++i) ci.obs[i] = P.observer[i];
+  for (int c = 0; c < ci.nch; ++c) {
+    ci.chL[c] = P.chans[c].L;
+    ci.chM[c] = P.chans[c].M;
+    ci.chPart[c] = P.chans[c].part;
   }
-  a.N = P.N;
-  a.T = P.T;
-  a.NT = P.NT;
-  a.p = P.p;
-  a.copies = P.copies;
-  a.box_mode = P.box_mode;
-  a.local = P.los_kind == TSB_LOS_LOCAL;
-  a.nch = (int)P.chans.size();
-  if (a.nch + 1 > kMaxCh || (int)P.grids.size() > kMaxGrids)
-    return fail(TSB_E_UNSUPPORTED, "too many channels");
-  for (int c = 0; c < a.nch; ++c) {
-    a.chL[c] = P.chans[c].L;
-    a.chM[c] = P.chans[c].M;
-    a.chPart[c] = P.chans[c].part;
-  }
-  a.ngrid = (int)P.grids.size();
-  for (int g = 0; g < a.ngrid; ++g) {
-    a.gre[g] = P.grids[g].re;
-    a.gim[g] = P.grids[g].im;
-  }
-  ylm_norm_table(a.ynorm);
-  a.start = P.d_tile_start;
-  a.count = P.d_tile_count;
-  a.sorted = P.d_sorted;
-  a.scal = P.d_scal;
-  a.out = P.d_grid;
-  a.tile_I = P.d_sum_partials;
-  const int nchx = a.nch + (P.box_mode ? 0 : 1);
-  const size_t lds = (size_t)P.copies * nchx * P.T * P.T * P.T * sizeof(unsigned long long);
+  ylm_norm_table(ci.ynorm);
+  const int nchx = ci.nch + (P.box_mode ? 0 : 1);
   const bool f64 = P.precision == TSB_FP64;
-  prof_begin(P, kStAssign, s);
-  if (nchx <= 8) {
-    if (f64) hipLaunchKernelGGL((assign_tile_kernel<double, 8>), dim3(ntiles), dim3(kBlock), lds, s, a);
-    else hipLaunchKernelGGL((assign_tile_kernel<float, 8>), dim3(ntiles), dim3(kBlock), lds, s, a);
-  } else if (nchx <= 16) {
-    if (f64) hipLaunchKernelGGL((assign_tile_kernel<double, 16>), dim3(ntiles), dim3(kBlock), lds, s, a);
-    else hipLaunchKernelGGL((assign_tile_kernel<float, 16>), dim3(ntiles), dim3(kBlock), lds, s, a);
-  } else {
-    if (f64) hipLaunchKernelGGL((assign_tile_kernel<double, kMaxCh>), dim3(ntiles), dim3(kBlock), lds, s, a);
-    else hipLaunchKernelGGL((assign_tile_kernel<float, kMaxCh>), dim3(ntiles), dim3(kBlock), lds, s, a);
-  }
-  if (!P.box_mode) {
-    const double vc = P.L * P.L * P.L / ((double)P.N * P.N * P.N);
-    hipLaunchKernelGGL(norm_final_kernel, dim3(1), dim3(kBlock), 0, s, (const double*)P.d_sum_partials,
-                       ntiles, P.d_scal, vc);
-  }
-  prof_end(P, kStAssign, s);
-  TSB_HIP(hipGetLastError());
-  return TSB_OK;
+  if (nchx <= 8) return f64 ? assign_impl<double, 8>(P, b, ci, s) : assign_impl<float, 8>(P, b, ci, s);
+  if (nchx <= 16) return f64 ? assign_impl<double, 16>(P, b, ci, s) : assign_impl<float, 16>(P, b, ci, s);
+  return f64 ? assign_impl<double, kMaxCh>(P, b, ci, s) : assign_impl<float, kMaxCh>(P, b, ci, s);
 }
 
 int run_unpack_grids(Plan& P, void* out, hipStream_t s) {

@@ -12,6 +12,7 @@
 #include <cmath>
 
 #include "tsb_internal.h"
+#include "fft_reg.h"
 
 namespace tsb {
 
@@ -36,6 +37,7 @@ struct PassArgs {
   // pre-operation on loaded values
   int pre;                 // 0 none, 1 band mask |n|^2 <= n2max, 2 shell filter
   int offA, offB, offE;    // frequency = index - off for a, b, e
+  int axA, axB, axE;       // which Cartesian axis (0 x, 1 y, 2 z) a, b and e index
   int64_t n2max;
   const int* bin_lut;      // shell of n^2 (n^2 <= lut_max), -1 none
   int64_t lut_max;
@@ -53,20 +55,24 @@ __device__ inline T2 cmul(T2 a, T2 b) {
 }
 
 template <typename T>
-__device__ inline typename cplx<T>::type shell_value(const PassArgs<T>& a, int batch, int na, int nb,
-                                                     int ne, typename cplx<T>::type v) {
+__device__ inline typename cplx<T>::type shell_value(const PassArgs<T>& a, int batch, int fa, int fb,
+                                                     int fe, typename cplx<T>::type v) {
   // F slot input (eq. 42 with eq. 38): sum_parts factor * y_l^m*(k^) * dn(k) on shell b
   typedef typename cplx<T>::type T2;
   T2 zero;
   zero.x = 0;
   zero.y = 0;
-  const int64_t n2 = (int64_t)na * na + (int64_t)nb * nb + (int64_t)ne * ne;
+  const int64_t n2 = (int64_t)fa * fa + (int64_t)fb * fb + (int64_t)fe * fe;
   if (n2 == 0 || n2 > a.lut_max) return zero;
   const int bin = a.bin_lut[n2];
   if (bin != batch / a.nkinds) return zero;
   const FKind k = a.kinds[batch % a.nkinds];
   const double r = sqrt((double)n2);
-  const double ux = na / r, uy = nb / r, uz = ne / r;
+  double u[3];
+  u[a.axA] = fa / r;
+  u[a.axB] = fb / r;
+  u[a.axE] = fe / r;
+  const double ux = u[0], uy = u[1], uz = u[2];
   double fr = 0.0, fi = 0.0;
   for (int p = 0; p < k.nparts; ++p) {
     double yr, yi;
@@ -80,6 +86,25 @@ __device__ inline typename cplx<T>::type shell_value(const PassArgs<T>& a, int b
   o.y = (T)(fr * (double)v.y + fi * (double)v.x);
   return o;
 }
+
+template <typename T>
+__device__ inline typename cplx<T>::type apply_pre(const PassArgs<T>& a, int batch, int ia, int ib, int e,
+                                                   typename cplx<T>::type v) {
+  typedef typename cplx<T>::type T2;
+  const int fa = ia - a.offA, fb = ib - a.offB, fe = e - a.offE;
+  if (a.pre == 1) {
+    const int64_t n2 = (int64_t)fa * fa + (int64_t)fb * fb + (int64_t)fe * fe;
+    if (n2 > a.n2max) {
+      T2 z;
+      z.x = 0;
+      z.y = 0;
+      return z;
+    }
+    return v;
+  }
+  return shell_value<T>(a, batch, fa, fb, fe, v);
+}
+
 
 template <typename T>
 __global__ void __launch_bounds__(kBlock) fft_pass_kernel(PassArgs<T> a) {
@@ -117,15 +142,7 @@ __global__ void __launch_bounds__(kBlock) fft_pass_kernel(PassArgs<T> a) {
       j = idx - e * nl;
     }
     T2 v = inb[(int64_t)(b0 + j) * a.in_sb + (int64_t)e * a.in_se];
-    if (a.pre) {
-      const int na = ia - a.offA, nb = b0 + j - a.offB, ne = e - a.offE;
-      if (a.pre == 1) {
-        const int64_t n2 = (int64_t)na * na + (int64_t)nb * nb + (int64_t)ne * ne;
-        if (n2 > a.n2max) v = zero;
-      } else {
-        v = shell_value<T>(a, batch, na, nb, ne, v);
-      }
-    }
+    if (a.pre) v = apply_pre<T>(a, batch, ia, b0 + j, e, v);
     int pos = e - a.in_off;
     if (pos < 0) pos += N;
     buf0[j * NP + pos] = v;
@@ -278,6 +295,95 @@ __global__ void __launch_bounds__(kBlock) dcube_kernel(const typename cplx<T>::t
   }
 }
 
+
+// Four-step transform of lines of length N = N1 N2 (Sec. 2 sign convention):
+// x[n1 + N1 n2] -> N2-point DFTs over n2 (per n1, in registers) -> twiddle
+// W_N^{n1 k2} -> one LDS transpose -> N1-point DFTs over n1 (per k2) ->
+// X[k2 + N2 k1]. Lines in a workgroup are consecutive in b; loads and stores
+// walk the memory-contiguous index fastest.
+template <typename T, int N1, int N2>
+__global__ void __launch_bounds__(kBlock) fft4_kernel(PassArgs<T> a) {
+  typedef typename cplx<T>::type T2;
+  constexpr int N = N1 * N2;
+  constexpr int LS = N2 * (N1 + 1) + 1;   // LDS line stride (odd: lines start in different banks)
+  extern __shared__ char smem[];
+  T2* lds = (T2*)smem;
+  const int nbb = (a.dB + a.lpw - 1) / a.lpw;
+  const int64_t blk = blockIdx.x;
+  const int bb = (int)(blk % nbb);
+  const int64_t rest = blk / nbb;
+  const int ia = (int)(rest % a.dA);
+  const int batch = (int)(rest / a.dA);
+  const int b0 = bb * a.lpw;
+  const int nl = min(a.lpw, a.dB - b0);
+  const T2* inb = a.in + (int64_t)batch * a.in_bs + (int64_t)ia * a.in_sa;
+  T2* outb = a.out + (int64_t)batch * a.out_bs + (int64_t)ia * a.out_sa;
+
+  // ---- step A: N2-point transforms of the strided subsequences ---------------
+  for (int task = threadIdx.x; task < nl * N1; task += kBlock) {
+    int j, n1;
+    if (a.contiguous) {
+      j = task / N1;
+      n1 = task - j * N1;
+    } else {
+      n1 = task / nl;
+      j = task - n1 * nl;
+    }
+    T2 v[N2];
+#pragma unroll
+    for (int n2 = 0; n2 < N2; ++n2) {
+      const int pos = n1 + N1 * n2;        // position in the line
+      int e = pos + a.in_off;               // stored entry holding it
+      if (e >= N) e -= N;
+      T2 x;
+      x.x = 0;
+      x.y = 0;
+      if (e < a.in_cnt) {
+        x = inb[(int64_t)(b0 + j) * a.in_sb + (int64_t)e * a.in_se];
+        if (a.pre) x = apply_pre<T>(a, batch, ia, b0 + j, e, x);
+      }
+      v[n2] = x;
+    }
+    reg_fft<T, T2, N2>(v, a.dir);
+    T2* line = lds + j * LS;
+#pragma unroll
+    for (int i = 0; i < N2; ++i) {
+      const int k2 = bit_reverse<N2>(i);
+      T2 w = a.tw[(n1 * k2) % N];
+      if (a.dir > 0) w.y = -w.y;
+      T2 o;
+      o.x = v[i].x * w.x - v[i].y * w.y;
+      o.y = v[i].x * w.y + v[i].y * w.x;
+      line[k2 * (N1 + 1) + n1] = o;
+    }
+  }
+  __syncthreads();
+
+  // ---- step C: N1-point transforms across n1 -----------------------------------
+  for (int task = threadIdx.x; task < nl * N2; task += kBlock) {
+    int j, k2;
+    if (a.contiguous) {
+      j = task / N2;
+      k2 = task - j * N2;
+    } else {
+      k2 = task / nl;
+      j = task - k2 * nl;
+    }
+    const T2* line = lds + j * LS + k2 * (N1 + 1);
+    T2 u[N1];
+#pragma unroll
+    for (int n1 = 0; n1 < N1; ++n1) u[n1] = line[n1];
+    reg_fft<T, T2, N1>(u, a.dir);
+#pragma unroll
+    for (int i = 0; i < N1; ++i) {
+      const int k = k2 + N2 * bit_reverse<N1>(i);   // output position
+      int e = k + a.out_off;                          // stored entry
+      if (e >= N) e -= N;
+      if (e < a.out_cnt) outb[(int64_t)(b0 + j) * a.out_sb + (int64_t)e * a.out_se] = u[i];
+    }
+  }
+}
+
 int pick_lpw(int N, int esz) {
   // two LDS line buffers of (N+1) complex each, at most 64 KiB
   int lpw = 16;
@@ -285,18 +391,47 @@ int pick_lpw(int N, int esz) {
   return lpw;
 }
 
+template <typename T, int N1, int N2>
+int launch_fft4(PassArgs<T>& a, hipStream_t s) {
+  typedef typename cplx<T>::type T2;
+  constexpr int LS = N2 * (N1 + 1) + 1;
+  int lpw = 64;
+  while (lpw > 1 && (int64_t)lpw * LS * (int64_t)sizeof(T2) > 40 * 1024) lpw /= 2;
+  a.lpw = lpw;
+  const int64_t nbb = (a.dB + a.lpw - 1) / a.lpw;
+  const int64_t blocks = (int64_t)a.nbatch * a.dA * nbb;
+  if (blocks > 2147483647LL) return fail(TSB_E_UNSUPPORTED, "FFT pass too large");
+  const size_t lds = (size_t)lpw * LS * sizeof(T2);
+  hipLaunchKernelGGL((fft4_kernel<T, N1, N2>), dim3((unsigned)blocks), dim3(kBlock), lds, s, a);
+  return TSB_OK;
+}
+
 template <typename T>
 int launch_pass(Plan& P, int stage, PassArgs<T>& a, hipStream_t s) {
   typedef typename cplx<T>::type T2;
   if (a.nbatch <= 0 || a.dA <= 0 || a.dB <= 0) return TSB_OK;
-  a.lpw = pick_lpw(a.N, sizeof(T));
-  const int64_t nbb = (a.dB + a.lpw - 1) / a.lpw;
-  const int64_t blocks = (int64_t)a.nbatch * a.dA * nbb;
-  if (blocks > 2147483647LL) return fail(TSB_E_UNSUPPORTED, "FFT pass too large");
-  const size_t lds = (size_t)2 * a.lpw * (a.N + 1) * sizeof(T2);
   prof_begin(P, stage, s);
-  hipLaunchKernelGGL(fft_pass_kernel<T>, dim3((unsigned)blocks), dim3(kBlock), lds, s, a);
+  int rc = TSB_OK;
+  switch (a.N) {
+    case 16: rc = launch_fft4<T, 4, 4>(a, s); break;
+    case 32: rc = launch_fft4<T, 4, 8>(a, s); break;
+    case 64: rc = launch_fft4<T, 8, 8>(a, s); break;
+    case 128: rc = launch_fft4<T, 8, 16>(a, s); break;
+    case 256: rc = launch_fft4<T, 16, 16>(a, s); break;
+    case 512: rc = launch_fft4<T, 16, 32>(a, s); break;
+    case 1024: rc = launch_fft4<T, 32, 32>(a, s); break;
+    default: {
+      // lengths with a factor 3: LDS Stockham radix 4/2/3
+      a.lpw = pick_lpw(a.N, sizeof(T));
+      const int64_t nbb = (a.dB + a.lpw - 1) / a.lpw;
+      const int64_t blocks = (int64_t)a.nbatch * a.dA * nbb;
+      if (blocks > 2147483647LL) return fail(TSB_E_UNSUPPORTED, "FFT pass too large");
+      const size_t lds = (size_t)2 * a.lpw * (a.N + 1) * sizeof(T2);
+      hipLaunchKernelGGL(fft_pass_kernel<T>, dim3((unsigned)blocks), dim3(kBlock), lds, s, a);
+    }
+  }
   prof_end(P, stage, s);
+  if (rc) return rc;
   TSB_HIP(hipGetLastError());
   return TSB_OK;
 }
@@ -366,52 +501,55 @@ int forward_impl(Plan& P, hipStream_t s) {
 }
 
 // One inverse 3D transform chain on the M grid, from a cube of half-width R
-// (stored entries 2R+1 per axis) to full complex fields [nbatch][M^3].
+// (stored entries 2R+1 per axis, [qx][qy][qz]) to full complex fields
+// [nbatch][M^3]. Order x, y, z: the last and largest pass runs along the
+// contiguous axis.
 template <typename T>
 int inverse_chain(Plan& P, int stage0, const typename cplx<T>::type* cube, int64_t cube_bs, int nbatch,
-                  int R, PassArgs<T> pre, typename cplx<T>::type* fields, hipStream_t s) {
+                  int R, PassArgs<T> pre, typename cplx<T>::type* fields, bool last_pass, hipStream_t s) {
   typedef typename cplx<T>::type T2;
   const int M = P.M, PR = 2 * R + 1;
-  const int64_t M2 = (int64_t)M * M;
+  const int64_t M2 = (int64_t)M * M, PR2 = (int64_t)PR * PR;
   int rc;
-  // z (contiguous) with the pre-operation: [b][PR][PR][PR] -> [b][PR][PR][M]
+  // x with the pre-operation: [b][qx][qy][qz] -> [b][x][qy][qz]
   {
     PassArgs<T> a = pre;
     a.in = cube;
     a.out = (T2*)P.d_u1;
     a.tw = (const T2*)P.d_tw_m;
     a.nbatch = nbatch; a.dA = PR; a.dB = PR;
-    a.in_bs = cube_bs; a.in_sa = (int64_t)PR * PR; a.in_sb = PR; a.in_se = 1;
-    a.out_bs = (int64_t)PR * PR * M; a.out_sa = (int64_t)PR * M; a.out_sb = M; a.out_se = 1;
+    a.in_bs = cube_bs; a.in_sa = PR; a.in_sb = 1; a.in_se = PR2;
+    a.out_bs = (int64_t)M * PR2; a.out_sa = PR; a.out_sb = 1; a.out_se = PR2;
     a.in_cnt = PR; a.in_off = R; a.out_cnt = M; a.out_off = 0;
     a.offA = R; a.offB = R; a.offE = R;
-    a.N = M; a.dir = 1; a.contiguous = 1;
+    a.axA = 1; a.axB = 2; a.axE = 0;
+    a.N = M; a.dir = 1; a.contiguous = 0;
     if ((rc = launch_pass<T>(P, stage0, a, s))) return rc;
   }
-  // y (strided): [b][PR][PR][M] -> [b][PR][M][M]
+  // y: [b][x][qy][qz] -> [b][x][y][qz]
   {
     PassArgs<T> a{};
     a.in = (const T2*)P.d_u1;
     a.out = (T2*)P.d_u2;
     a.tw = (const T2*)P.d_tw_m;
-    a.nbatch = nbatch; a.dA = PR; a.dB = M;
-    a.in_bs = (int64_t)PR * PR * M; a.in_sa = (int64_t)PR * M; a.in_sb = 1; a.in_se = M;
-    a.out_bs = (int64_t)PR * M2; a.out_sa = M2; a.out_sb = 1; a.out_se = M;
+    a.nbatch = nbatch; a.dA = M; a.dB = PR;
+    a.in_bs = (int64_t)M * PR2; a.in_sa = PR2; a.in_sb = 1; a.in_se = PR;
+    a.out_bs = M2 * PR; a.out_sa = (int64_t)M * PR; a.out_sb = 1; a.out_se = PR;
     a.in_cnt = PR; a.in_off = R; a.out_cnt = M; a.out_off = 0;
     a.N = M; a.dir = 1; a.contiguous = 0;
     if ((rc = launch_pass<T>(P, stage0 + 1, a, s))) return rc;
   }
-  // x (strided): [b][PR][M][M] -> [b][M][M][M]
-  {
+  // z (contiguous): [b][x][y][qz] -> [b][x][y][z]
+  if (last_pass) {
     PassArgs<T> a{};
     a.in = (const T2*)P.d_u2;
     a.out = fields;
     a.tw = (const T2*)P.d_tw_m;
     a.nbatch = nbatch; a.dA = M; a.dB = M;
-    a.in_bs = (int64_t)PR * M2; a.in_sa = M; a.in_sb = 1; a.in_se = M2;
-    a.out_bs = M2 * M; a.out_sa = M; a.out_sb = 1; a.out_se = M2;
+    a.in_bs = M2 * PR; a.in_sa = (int64_t)M * PR; a.in_sb = PR; a.in_se = 1;
+    a.out_bs = M2 * M; a.out_sa = M2; a.out_sb = M; a.out_se = 1;
     a.in_cnt = PR; a.in_off = R; a.out_cnt = M; a.out_off = 0;
-    a.N = M; a.dir = 1; a.contiguous = 0;
+    a.N = M; a.dir = 1; a.contiguous = 1;
     if ((rc = launch_pass<T>(P, stage0 + 2, a, s))) return rc;
   }
   return TSB_OK;
@@ -424,6 +562,17 @@ int inverse_impl(Plan& P, hipStream_t s) {
   const int nf = P.nb * (int)P.fkinds.size();
   T2* fields = (T2*)P.d_fields;
   int rc;
+  // G grids first: band-limited spectra (eq. 42). The F chain runs last so that,
+  // with the fused reduction, its y-pass output is still in d_u2 afterwards.
+  {
+    PassArgs<T> pre{};
+    pre.pre = P.n2maxG >= 0 ? 1 : 0;
+    pre.n2max = P.n2maxG;
+    const int64_t pg3 = (int64_t)P.PG * P.PG * P.PG;
+    if ((rc = inverse_chain<T>(P, kStInvGX, (const T2*)P.d_spec, pg3, (int)P.grids.size(), P.RG, pre,
+                               fields + P.g_offset, true, s)))
+      return rc;
+  }
   // F slots: shell filter of dn_0^0 times y_l^m*(k^) (eq. 42)
   {
     PassArgs<T> pre{};
@@ -433,16 +582,8 @@ int inverse_impl(Plan& P, hipStream_t s) {
     pre.kinds = P.d_fkinds;
     pre.nkinds = (int)P.fkinds.size();
     ylm_norm_table(pre.ynorm);
-    if ((rc = inverse_chain<T>(P, kStInvFZ, (const T2*)P.d_dcube, 0, nf, P.RF, pre, fields, s))) return rc;
-  }
-  // G grids: band-limited spectra (eq. 42)
-  {
-    PassArgs<T> pre{};
-    pre.pre = P.n2maxG >= 0 ? 1 : 0;
-    pre.n2max = P.n2maxG;
-    const int64_t pg3 = (int64_t)P.PG * P.PG * P.PG;
-    if ((rc = inverse_chain<T>(P, kStInvGZ, (const T2*)P.d_spec, pg3, (int)P.grids.size(), P.RG, pre,
-                               fields + (int64_t)nf * M3, s)))
+    // with the fused reduction the z pass of F happens inside the reduction
+    if ((rc = inverse_chain<T>(P, kStInvFX, (const T2*)P.d_dcube, 0, nf, P.RF, pre, fields, !P.fused, s)))
       return rc;
   }
   return TSB_OK;

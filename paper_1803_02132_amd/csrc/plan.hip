@@ -372,12 +372,21 @@ int plan_build(Plan& P) {
   const int64_t per_cell = (int64_t)P.nb * (int64_t)P.fcomp.size() + (int64_t)P.gcomp.size() +
                            (int64_t)P.qgroups.size() * P.nb;
   int C = 64;
-  while (C > 4 && per_cell * C * esz > 65536) C /= 2;
-  if (per_cell * C * esz > 160 * 1024)
+  while (C > 4 && per_cell * (C + 1) * esz > 65536) C /= 2;
+  if (per_cell * (C + 1) * esz > 160 * 1024)
     return fail(TSB_E_UNSUPPORTED, "too many fields for the reduction tile");
   P.red_chunk = C;
   const int64_t nchunks = (int64_t)P.M * P.M * P.M / C;
   P.red_wg = (int)std::min<int64_t>(nchunks, 1024);
+
+  // right factors of the contraction and the fused path
+  P.f2idx.assign(P.fcomp.size(), -1);
+  P.nf2 = 0;
+  for (auto& q : P.qgroups)
+    if (P.f2idx[q.f2] < 0) P.f2idx[q.f2] = P.nf2++;
+  plan_fused(P);
+  if (P.fused) P.red_wg = (int)std::min<int64_t>((int64_t)P.M * P.M, 1024);
+  P.g_offset = P.fused ? 0 : (int64_t)P.nb * (int64_t)P.fkinds.size() * P.M * P.M * P.M;
   return TSB_OK;
 }
 

@@ -34,7 +34,7 @@ struct RedArgs {
   int nout_all;            // row length of partials
   int chunk;               // cells per chunk
   int64_t nchunks;
-  double* partials;        // [gridDim][nout_all]
+  double* partials;        // [nout_all][gridDim]
 };
 
 template <typename T>
@@ -42,9 +42,10 @@ __global__ void __launch_bounds__(kBlock) reduce_kernel(RedArgs<T> a) {
   typedef typename cplx<T>::type T2;
   extern __shared__ char smem[];
   const int C = a.chunk;
-  T* Fv = (T*)smem;                              // [nb][nfc][C]
-  T* Gv = Fv + (size_t)a.nb * a.nfc * C;         // [ngc][C]
-  T* Qv = Gv + (size_t)a.ngc * C;                // [nq][nb][C]
+  const int CP = C + 1;                          // odd row pitch: rows start in different banks
+  T* Fv = (T*)smem;                              // [nb][nfc][CP]
+  T* Gv = Fv + (size_t)a.nb * a.nfc * CP;        // [ngc][CP]
+  T* Qv = Gv + (size_t)a.ngc * CP;               // [nq][nb][CP]
   const int tid = threadIdx.x;
   double acc[kOutPerThread];
 #pragma unroll
@@ -59,13 +60,13 @@ __global__ void __launch_bounds__(kBlock) reduce_kernel(RedArgs<T> a) {
       const T2 v = a.fields[(int64_t)slot * a.M3 + c0 + c];
       const int b = slot / a.nkinds, k = slot - b * a.nkinds;
       for (int f = 0; f < a.nfc; ++f)
-        if (a.fcomp[f].slot == k) Fv[((size_t)b * a.nfc + f) * C + c] = a.fcomp[f].part ? v.y : v.x;
+        if (a.fcomp[f].slot == k) Fv[((size_t)b * a.nfc + f) * CP + c] = a.fcomp[f].part ? v.y : v.x;
     }
     for (int idx = tid; idx < a.ngrid * C; idx += kBlock) {
       const int g = idx / C, c = idx - g * C;
       const T2 v = a.fields[((int64_t)nslot + g) * a.M3 + c0 + c];
       for (int f = 0; f < a.ngc; ++f)
-        if (a.gcomp[f].slot == g) Gv[(size_t)f * C + c] = a.gcomp[f].part ? v.y : v.x;
+        if (a.gcomp[f].slot == g) Gv[(size_t)f * CP + c] = a.gcomp[f].part ? v.y : v.x;
     }
     __syncthreads();
     // Q_q(x; b1)
@@ -77,9 +78,9 @@ __global__ void __launch_bounds__(kBlock) reduce_kernel(RedArgs<T> a) {
       double s = 0.0;
       for (int t = g.t0; t < g.t1; ++t) {
         const Term tm = a.terms[t];
-        s += tm.coef * (double)Fv[((size_t)b1 * a.nfc + tm.f1) * C + c] * (double)Gv[(size_t)tm.g * C + c];
+        s += tm.coef * (double)Fv[((size_t)b1 * a.nfc + tm.f1) * CP + c] * (double)Gv[(size_t)tm.g * CP + c];
       }
-      Qv[((size_t)q * a.nb + b1) * C + c] = (T)s;
+      Qv[((size_t)q * a.nb + b1) * CP + c] = (T)s;
     }
     __syncthreads();
     // sum over the chunk's cells for every output of this thread
@@ -90,8 +91,8 @@ __global__ void __launch_bounds__(kBlock) reduce_kernel(RedArgs<T> a) {
       const OutEntry e = a.outs[a.out0 + o];
       double s = 0.0;
       for (int q = e.q0; q < e.q1; ++q) {
-        const T* qr = Qv + ((size_t)q * a.nb + e.b1) * C;
-        const T* fr = Fv + ((size_t)e.b2 * a.nfc + a.qg[q].f2) * C;
+        const T* qr = Qv + ((size_t)q * a.nb + e.b1) * CP;
+        const T* fr = Fv + ((size_t)e.b2 * a.nfc + a.qg[q].f2) * CP;
         for (int c = 0; c < C; ++c) s += (double)qr[c] * (double)fr[c];
       }
       acc[r] += s;
@@ -101,25 +102,34 @@ __global__ void __launch_bounds__(kBlock) reduce_kernel(RedArgs<T> a) {
 #pragma unroll
   for (int r = 0; r < kOutPerThread; ++r) {
     const int o = tid + r * kBlock;
-    if (o < a.nout) a.partials[(size_t)blockIdx.x * a.nout_all + a.out0 + o] = acc[r];
+    if (o < a.nout) a.partials[(size_t)(a.out0 + o) * gridDim.x + blockIdx.x] = acc[r];
   }
 }
 
-__global__ void __launch_bounds__(kBlock) reduce_final_kernel(const double* partials, int nwg, int nout,
+// One block per output: each thread sums a fixed subset of the workgroup
+// partials, then a fixed-shape tree; the order never depends on scheduling.
+__global__ void __launch_bounds__(kBlock) reduce_final_kernel(const double* partials, int nwg,
                                                               const double* norm, const DevScalars* scal,
                                                               double* B) {
-  const int o = blockIdx.x * kBlock + threadIdx.x;
-  if (o >= nout) return;
+  __shared__ double sh[kBlock];
+  const int o = blockIdx.x;
+  const double* row = partials + (size_t)o * nwg;
   double s = 0.0;
-  for (int w = 0; w < nwg; ++w) s += partials[(size_t)w * nout + o];   // fixed order
-  B[o] = s * norm[o] / scal->I;
+  for (int w = threadIdx.x; w < nwg; w += kBlock) s += row[w];
+  sh[threadIdx.x] = s;
+  __syncthreads();
+  for (int st = kBlock / 2; st > 0; st >>= 1) {
+    if (threadIdx.x < st) sh[threadIdx.x] += sh[threadIdx.x + st];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) B[o] = sh[0] * norm[o] / scal->I;
 }
 
 template <typename T>
 int reduce_impl(Plan& P, hipStream_t s) {
   typedef typename cplx<T>::type T2;
   RedArgs<T> a{};
-  a.fields = (const T2*)P.d_fields;
+  a.fields = (const T2*)P.d_fields;   // F slots at 0, G grids at P.g_offset
   a.M3 = (int64_t)P.M * P.M * P.M;
   a.nb = P.nb;
   a.nkinds = (int)P.fkinds.size();
@@ -135,7 +145,7 @@ int reduce_impl(Plan& P, hipStream_t s) {
   a.chunk = P.red_chunk;
   a.nchunks = a.M3 / P.red_chunk;
   a.partials = P.d_partials;
-  const size_t lds = sizeof(T) * (size_t)P.red_chunk *
+  const size_t lds = sizeof(T) * (size_t)(P.red_chunk + 1) *
                      ((size_t)a.nb * a.nfc + a.ngc + (size_t)a.nq * a.nb);
   const int nout_all = (int)P.outs.size();
   const int per_launch = kOutPerThread * kBlock;
@@ -147,16 +157,22 @@ int reduce_impl(Plan& P, hipStream_t s) {
     hipLaunchKernelGGL(reduce_kernel<T>, dim3(P.red_wg), dim3(kBlock), lds, s, a);
   }
   prof_end(P, kStReduce, s);
+  TSB_HIP(hipGetLastError());
+  return run_reduce_final(P, s);
+}
+
+}  // namespace
+
+int run_reduce_final(Plan& P, hipStream_t s) {
+  const int nout_all = (int)P.outs.size();
+  if (nout_all == 0) return TSB_OK;
   prof_begin(P, kStReduceFinal, s);
-  hipLaunchKernelGGL(reduce_final_kernel, dim3((nout_all + kBlock - 1) / kBlock), dim3(kBlock), 0, s,
-                     (const double*)P.d_partials, P.red_wg, nout_all, (const double*)P.d_out_norm,
-                     (const DevScalars*)P.d_scal, P.d_B);
+  hipLaunchKernelGGL(reduce_final_kernel, dim3(nout_all), dim3(kBlock), 0, s, (const double*)P.d_partials,
+                     P.red_wg, (const double*)P.d_out_norm, (const DevScalars*)P.d_scal, P.d_B);
   prof_end(P, kStReduceFinal, s);
   TSB_HIP(hipGetLastError());
   return TSB_OK;
 }
-
-}  // namespace
 
 int run_reduce(Plan& P, hipStream_t s) {
   if (P.outs.empty()) return TSB_OK;

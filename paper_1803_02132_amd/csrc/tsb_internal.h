@@ -68,7 +68,7 @@ struct DevScalars {
 
 enum Stage {
   kStWeights = 0, kStBucket, kStAssign, kStFwdZ, kStFwdY, kStFwdX, kStCombine,
-  kStInvFZ, kStInvFY, kStInvFX, kStInvGZ, kStInvGY, kStInvGX, kStReduce, kStReduceFinal, kNumStages
+  kStInvFX, kStInvFY, kStInvFZ, kStInvGX, kStInvGY, kStInvGZ, kStReduce, kStReduceFinal, kNumStages
 };
 
 struct Plan {
@@ -81,7 +81,7 @@ struct Plan {
   int nb = 0;
   double kmin = 0, dk = 0;
   std::vector<tsb_multipole> mult;
-  int precision = TSB_FP32, pair_mode = TSB_PAIRS_PAPER, box_mode = 1;
+  int precision = TSB_FP32, pair_mode = TSB_PAIRS_PAPER, box_mode = 1, unfused = 0;
   double P0 = 0;
   int device = 0;
 
@@ -136,10 +136,26 @@ struct Plan {
   int* d_tile_start = nullptr;
   int* d_tile_cursor = nullptr;
   int* d_keys = nullptr;
-  int* d_sorted = nullptr;
+  int* d_perm = nullptr;      // records in (cell, octant) order within each tile
+  int* d_tile_ndense = nullptr;
+  int* d_dense_off = nullptr;
+  void* d_dense_desc = nullptr;     // [tiles][64] moment-group descriptors
+  void* d_dense_bits = nullptr;     // [tiles][8 T^3 / 32] moment-group keys
+  void* d_dense_contrib = nullptr;  // [groups][copies][p^3][nchx] fixed-point node sums
+  int64_t dense_cap = 0;
+  void* d_rec_u = nullptr;    // particle records in bucket order: u (3 x double)
+  void* d_rec_c = nullptr;    //   and channel weights [nchx][cap] (plan precision)
   int64_t particle_cap = 0;
   int red_chunk = 64, red_wg = 1024;
   int64_t bytes = 0;
+
+  // fused last F pass + reduction
+  bool fused = false;
+  int fused_bpg = 1;            // shells per group inside the fused kernel
+  int nf2 = 0;                  // F components used as right factors
+  std::vector<int> f2idx;       // per F component: its right-factor row or -1
+  int* d_f2idx = nullptr;
+  int64_t g_offset = 0;         // element offset of the G grids in d_fields
 
   // stage timing (HIP events on the measurement stream)
   bool prof = false;
@@ -174,6 +190,9 @@ int run_assign(Plan& P, const tsb_catalog* data, const tsb_catalog* rand, hipStr
 int run_forward(Plan& P, hipStream_t s);
 int run_inverse(Plan& P, hipStream_t s);
 int run_reduce(Plan& P, hipStream_t s);
+int run_reduce_final(Plan& P, hipStream_t s);
+void plan_fused(Plan& P);                   // fused.hip
+int run_fused(Plan& P, hipStream_t s);
 int run_unpack_grids(Plan& P, void* out, hipStream_t s);
 
 // ---------------------------------------------------------------------------

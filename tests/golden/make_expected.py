@@ -1,0 +1,57 @@
+"""Write the oracle's expected multipoles for the full-size GPU parity tests.
+
+Calls only the FP64 oracle and the seeded mock generator; nothing here comes
+from the HIP path. Run from the repository root:
+    python tests/golden/make_expected.py
+Outputs (small .npz files next to this script):
+  box128_seed0.npz   every pair of the 128^3 box workload (500k particles,
+                     Kaiser along a local LOS, TSC + interlacing, 000 110 202 112)
+  box256_seed48.npz  sampled shell pairs of one 256^3 throughput mock (000, 202)
+Each file also stores a checksum of the generated catalogue so the tests can
+confirm they regenerated the same input.
+"""
+import os
+import sys
+import time
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(os.path.dirname(HERE))
+sys.path.insert(0, ROOT)
+
+from mocks.lognormal import WORKLOADS, workload  # noqa: E402
+from oracle import estimator as est  # noqa: E402
+
+SAMPLED_PAIRS_256 = [(0, 0), (0, 19), (3, 7), (7, 3), (9, 9), (12, 18), (18, 12), (19, 19)]
+
+
+def catalogue_checksum(cat):
+    p = np.asarray(cat["pos"], np.float64)
+    return np.array([len(p), p.sum(), (p * p).sum()])
+
+
+def oracle_plan(spec):
+    return est.Plan(n=spec["n"], box_len=spec["box_len"], multipoles=spec["multipoles"], n_bins=spec["n_bins"],
+                    dk=spec["dk"], k_min=spec["k_min"], assign_p=spec["assign_p"], interlace=spec["interlace"],
+                    los=spec["los"], observer=spec.get("observer", (0.0, 0.0, 0.0)), box_mode=True)
+
+
+def main():
+    t0 = time.time()
+    spec, cat = workload("box128", seed=0)
+    res = est.measure(oracle_plan(spec), cat)
+    np.savez(os.path.join(HERE, "box128_seed0.npz"), B=res["B"], B_imag=res["B_imag"], I=res["I"],
+             nmode=res["nmode"], checksum=catalogue_checksum(cat))
+    print(f"box128 done in {time.time() - t0:.0f} s", flush=True)
+
+    t0 = time.time()
+    spec, cat = workload("box256", seed=48)
+    res = est.measure(oracle_plan(spec), cat, pairs=SAMPLED_PAIRS_256)
+    np.savez(os.path.join(HERE, "box256_seed48.npz"), B=res["B"], B_imag=res["B_imag"], I=res["I"],
+             nmode=res["nmode"], pairs=np.array(SAMPLED_PAIRS_256), checksum=catalogue_checksum(cat))
+    print(f"box256 done in {time.time() - t0:.0f} s", flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -106,15 +106,16 @@ def test_box32_fp64_global_los():
     assert np.all(err <= 1e-9)
 
 
+@pytest.mark.parametrize("unfused", [False, True])
 @pytest.mark.parametrize("precision,tol", [("f32", 1e-4), ("f64", 1e-9)])
-def test_local_los_tsc_interlaced(precision, tol):
+def test_local_los_tsc_interlaced(precision, tol, unfused):
     req = box_request(n=32, multipoles=[(0, 0, 0), (1, 1, 0), (2, 0, 2), (1, 1, 2), (2, 2, 0)],
-                      precision=precision, n_bins=6)
+                      precision=precision, n_bins=6, unfused=unfused)
     cat = small_cat(seed=2)
     plan, g, o = run_both(req, cat)
     mask = pair_mask(req["multipoles"], req["n_bins"])
     err = normwise_errors(g["B"], o["B"], mask)
-    _say("local", precision, "errors", err)
+    _say("local", precision, "unfused" if unfused else "fused", "errors", err)
     assert np.all(err <= tol)
 
 
