@@ -143,6 +143,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=4)
     ap.add_argument("--mocks", type=int, default=len(SEEDS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--unfused", action="store_true",
+                    help="write the F fields to HBM and reduce in a separate pass (diagnostic)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the path shards by mock "
@@ -161,7 +163,7 @@ def main():
         cats.append(cat)
         devs.append(tsb.catalog_to_device(cat))
         log(f"mock seed {s}: {len(cat['pos'])} particles")
-    plan = tsb.Plan(**WORKLOAD)
+    plan = tsb.Plan(**dict(WORKLOAD, unfused=args.unfused))
     info = plan.info
     log(f"plan: N={info.n} M={info.m} r_f={info.r_f} r_g={info.r_g} outputs={info.n_outputs} "
         f"workspace={info.workspace_bytes / 1e9:.2f} GB")
@@ -198,7 +200,8 @@ def main():
         "config": {"workload": ("256^3 box, L=1000 Mpc/h, TSC+interlacing, local LOS from an observer 1500 Mpc/h "
                                 "below the centre, 20 shells dk=0.01 h/Mpc, B_000 (210 pairs) + B_202 (400 pairs), "
                                 "seeded lognormal+Kaiser mocks, N_p log-uniform in [3e5, 3e6]"),
-                   "seeds": seeds, "n_particles_mean": int(n_mean), "reduction_grid": info.m},
+                   "seeds": seeds, "n_particles_mean": int(n_mean), "reduction_grid": info.m,
+                   "fused_reduction": bool(fused)},
         "roofline": roof,
         "stage_ms": {k: round(v, 4) for k, v in per_launch.items()},
     }

@@ -80,14 +80,13 @@ int plan_alloc(Plan& P, bool dry) {
   ALLOC(P.d_u1, std::max(nf * PF * PF * M, ng * PG * PG * M) * c);
   ALLOC(P.d_u2, std::max(nf * PF * M * M, ng * PG * M * M) * c);
   ALLOC(P.d_fields, ((P.fused ? 0 : nf) + ng) * M * M * M * c);
+  if (P.box_mode && P.los_kind == TSB_LOS_LOCAL) ALLOC(P.d_yspec, ng * PG * PG * PG * c);
   const int64_t ntiles = (int64_t)P.NT * P.NT * P.NT;
-  ALLOC(P.d_tile_count, ntiles * 4);
-  ALLOC(P.d_tile_start, ntiles * 4);
-  ALLOC(P.d_tile_cursor, ntiles * 4);
-  ALLOC(P.d_tile_ndense, ntiles * 4);
-  ALLOC(P.d_dense_off, ntiles * 4);
-  ALLOC(P.d_dense_desc, ntiles * 64 * 16);
-  ALLOC(P.d_dense_bits, ntiles * (8 * (int64_t)P.T * P.T * P.T / 32) * 4);
+  P.nbk = ntiles * 27;
+  ALLOC(P.d_bk_count, 2 * P.nbk * 4);
+  P.d_bk_cursor = dry ? nullptr : P.d_bk_count + P.nbk;
+  ALLOC(P.d_bk_start, (P.nbk + 1) * 4);
+  ALLOC(P.d_scan_part, ((P.nbk + kScanChunk - 1) / kScanChunk + 1) * 4);
   ALLOC(P.d_scal, (int64_t)sizeof(DevScalars));
   ALLOC(P.d_sum_partials, std::max<int64_t>(ntiles, 4 * 512) * 8);
   ALLOC(P.d_partials, (int64_t)P.red_wg * std::max<int64_t>((int64_t)P.outs.size(), 1) * 8);
@@ -115,9 +114,8 @@ void plan_free(Plan& P) {
   void* ptrs[] = {P.d_grid, P.d_t1, P.d_t2, P.d_t3, P.d_spec, P.d_dcube, P.d_u1, P.d_u2, P.d_fields,
                   P.d_tw_n, P.d_tw_m, P.d_bin_lut, P.d_fkinds, P.d_fcomp, P.d_gcomp, P.d_terms,
                   P.d_qgroups, P.d_outs, P.d_out_norm, P.d_partials, P.d_B, P.d_scal, P.d_sum_partials,
-                  P.d_tile_count, P.d_tile_start, P.d_tile_cursor, P.d_keys, P.d_rec_u, P.d_rec_c,
-                  P.d_f2idx, P.d_perm, P.d_tile_ndense, P.d_dense_off, P.d_dense_desc, P.d_dense_bits,
-                  P.d_dense_contrib};
+                  P.d_bk_count, P.d_bk_start, P.d_scan_part, P.d_keys, P.d_rec_u, P.d_rec_c,
+                  P.d_f2idx, P.d_yspec};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
 }
@@ -129,27 +127,37 @@ int ensure_particles(Plan& P, int64_t n) {
   if (n > 2147483647LL) return fail(TSB_E_UNSUPPORTED, "more than 2^31-1 particles");
   const int64_t nchx = (int64_t)P.chans.size() + (P.box_mode ? 0 : 1);
   const int64_t esz = P.precision == TSB_FP64 ? 8 : 4;
-  const int64_t per = 4 + 4 + 24 + nchx * esz;   // key, permutation, u, channel weights
-  const int64_t ntiles = (int64_t)P.NT * P.NT * P.NT;
-  const int64_t np3 = (int64_t)P.p * P.p * P.p;
-  const int64_t per_group = (int64_t)P.copies * np3 * nchx * 8;
-  for (void* p : {(void*)P.d_keys, (void*)P.d_perm, P.d_rec_u, P.d_rec_c, P.d_dense_contrib})
+  const int64_t per = 4 + 24 + nchx * esz;   // key, u, channel weights
+  for (void* p : {(void*)P.d_keys, P.d_rec_u, P.d_rec_c})
     if (p) (void)hipFree(p);
-  P.d_keys = P.d_perm = nullptr;
-  P.d_rec_u = P.d_rec_c = P.d_dense_contrib = nullptr;
-  P.bytes -= per * P.particle_cap + per_group * P.dense_cap;
-  P.particle_cap = P.dense_cap = 0;
+  P.d_keys = nullptr;
+  P.d_rec_u = P.d_rec_c = nullptr;
+  P.bytes -= per * P.particle_cap;
+  P.particle_cap = 0;
   const int64_t cap = std::max<int64_t>(n + n / 8, 1024);
-  // moment groups hold at least 8 particles each and at most 64 per tile
-  const int64_t gcap = std::min<int64_t>(ntiles * 64, cap / 8 + 1);
   int rc;
   if ((rc = dalloc((void**)&P.d_keys, cap * 4, P.bytes, false))) return rc;
-  if ((rc = dalloc((void**)&P.d_perm, cap * 4, P.bytes, false))) return rc;
   if ((rc = dalloc(&P.d_rec_u, cap * 24, P.bytes, false))) return rc;
   if ((rc = dalloc(&P.d_rec_c, cap * nchx * esz, P.bytes, false))) return rc;
-  if ((rc = dalloc(&P.d_dense_contrib, gcap * per_group, P.bytes, false))) return rc;
   P.particle_cap = cap;
-  P.dense_cap = gcap;
+  return TSB_OK;
+}
+
+// Box mode with a local LOS: transform y_L^M*(x^_node) once (same passes and
+// combination as the data) so that each measurement subtracts the mean term
+// in spectrum space.
+int init_yspec(Plan& P) {
+  if (!P.d_yspec) return TSB_OK;
+  int rc;
+  hipStream_t s = nullptr;
+  P.yspec_ready = false;
+  if ((rc = run_ynode_fill(P, s))) return rc;
+  if ((rc = run_forward(P, s))) return rc;
+  const int64_t c = P.precision == TSB_FP64 ? 16 : 8;
+  const int64_t bytes = (int64_t)P.grids.size() * P.PG * P.PG * P.PG * c;
+  TSB_HIP(hipMemcpyAsync(P.d_yspec, P.d_spec, (size_t)bytes, hipMemcpyDeviceToDevice, s));
+  TSB_HIP(hipStreamSynchronize(s));
+  P.yspec_ready = true;
   return TSB_OK;
 }
 
@@ -290,6 +298,7 @@ int tsb_plan_create(const tsb_grid* grid, const tsb_los* los, const tsb_kbins* b
     return fail(TSB_E_DEVICE, "no HIP device");
   }
   rc = plan_alloc(P);
+  if (!rc) rc = init_yspec(P);
   if (rc) {
     plan_free(P);
     delete h;

@@ -234,11 +234,15 @@ __global__ void __launch_bounds__(kBlock) fft_pass_kernel(PassArgs<T> a) {
 
 // Interlace combination and W_mass deconvolution on the stored cube
 // (Sec. 4.2, eq. 39): S = (D1 + e^{i pi (nx+ny+nz)/N} D2)/2 / prod sinc(pi n_i/N)^p;
-// in box mode the DC mode of dn_0^0 (real part of grid 0) is zero.
+// in box mode the DC mode of dn_0^0 (real part of grid 0) is zero, and the
+// mean term (sum w / N^3) y_L^M*(x^_node) of the local-LOS channels is removed
+// here through its precomputed transform (it is linear in the grid).
 template <typename T>
 __global__ void __launch_bounds__(kBlock) combine_kernel(const typename cplx<T>::type* t3,
                                                          typename cplx<T>::type* spec, int ngrid,
-                                                         int copies, int R, int N, int p, int box_mode) {
+                                                         int copies, int R, int N, int p, int box_mode,
+                                                         const typename cplx<T>::type* yspec,
+                                                         const DevScalars* scal) {
   typedef typename cplx<T>::type T2;
   const int P = 2 * R + 1;
   const int64_t P3 = (int64_t)P * P * P;
@@ -268,6 +272,13 @@ __global__ void __launch_bounds__(kBlock) combine_kernel(const typename cplx<T>:
     }
     re /= W;
     im /= W;
+    if (yspec) {
+      // box mode: minus (sum w / N^3) times the same transform of y_L^M*(x^_node)
+      const double mean = scal->mean_cell;
+      const T2 y = yspec[i];
+      re -= mean * (double)y.x;
+      im -= mean * (double)y.y;
+    }
     if (box_mode && g == 0 && nx == 0 && ny == 0 && nz == 0) re = 0.0;
     T2 o;
     o.x = (T)re;
@@ -491,7 +502,8 @@ int forward_impl(Plan& P, hipStream_t s) {
   const int64_t total = (int64_t)P.grids.size() * PG * PG * PG;
   prof_begin(P, kStCombine, s);
   hipLaunchKernelGGL(combine_kernel<T>, dim3(grid_blocks(total)), dim3(kBlock), 0, s, (const T2*)P.d_t3,
-                     (T2*)P.d_spec, (int)P.grids.size(), P.copies, RG, N, P.p, P.box_mode);
+                     (T2*)P.d_spec, (int)P.grids.size(), P.copies, RG, N, P.p, P.box_mode,
+                     P.yspec_ready ? (const T2*)P.d_yspec : (const T2*)nullptr, (const DevScalars*)P.d_scal);
   const int64_t pf3 = (int64_t)P.PF * P.PF * P.PF;
   hipLaunchKernelGGL(dcube_kernel<T>, dim3(grid_blocks(pf3)), dim3(kBlock), 0, s, (const T2*)P.d_spec,
                      (T2*)P.d_dcube, RG, P.RF);

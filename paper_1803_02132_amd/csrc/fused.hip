@@ -35,13 +35,19 @@ struct FusedArgs {
   const T2* gfields;   // G grids [ngrid][M^3]
   const T2* tw;        // e^{-2 pi i k / M}
   int RF, PF, nb, nkinds, ngrid, ngc, nq, nf2, bpg;
+  int ksplit;          // matrix-core contraction: cell-range splits per Q group
   const OutEntry* outs;
   int nout;
   double* partials;    // [nout][gridDim]
   FusedTables tb;
 };
 
-template <typename T, int N1, int N2>
+typedef float floatx16 __attribute__((ext_vector_type(16)));
+
+// MF: the per-line contraction C_q(b1, b2) += sum_x Q_q(x; b1) f2_q(x; b2) runs on
+// the matrix cores (FP32 32x32x2 MFMA; shells padded to 32) with one (q, cell
+// range) unit per wavefront, and the line sums go to FP64 accumulators.
+template <typename T, int N1, int N2, bool MF>
 __global__ void __launch_bounds__(kBlock) fz_reduce_kernel(FusedArgs<T> a) {
   typedef typename cplx<T>::type T2;
   constexpr int M = N1 * N2;
@@ -151,26 +157,80 @@ __global__ void __launch_bounds__(kBlock) fz_reduce_kernel(FusedArgs<T> a) {
       }
       __syncthreads();
     }
-    // sum over the line's cells for every output of this thread
+    if constexpr (MF) {
+      const int wave = tid >> 6, lane = tid & 63;
+      if (wave < a.nq * a.ksplit) {
+        const int q = wave / a.ksplit, sp = wave - q * a.ksplit;
+        const int b = lane & 31, kh = lane >> 5;
+        const bool live = b < a.nb;
+        const T* qr = Q + ((size_t)q * a.nb + (live ? b : 0)) * CP + kh;
+        const T* fr = F2 + ((size_t)a.tb.q_f2row[q] * a.nb + (live ? b : 0)) * CP + kh;
+        const int kl = M / a.ksplit, k0 = sp * kl;
+        floatx16 c = {};
+        for (int kk = k0; kk < k0 + kl; kk += 2) {
+          const float av = live ? (float)qr[kk] : 0.f;
+          const float bv = live ? (float)fr[kk] : 0.f;
+          c = __builtin_amdgcn_mfma_f32_32x32x2f32(av, bv, c, 0, 0, 0);
+        }
 #pragma unroll
-    for (int r = 0; r < kOutPerThread; ++r) {
-      if (tid + r * kBlock >= a.nout) break;
-      double s = 0.0;
-      for (int q = oq0[r]; q < oq1[r]; ++q) {
-        const T* qr = Q + ((size_t)q * a.nb + ob1[r]) * CP;
-        const T* fr = F2 + ((size_t)a.tb.q_f2row[q] * a.nb + ob2[r]) * CP;
-        for (int c = 0; c < M; ++c) s += (double)qr[c] * (double)fr[c];
+        for (int r = 0; r < 16; ++r) acc[r] += (double)c[r];
       }
-      acc[r] += s;
+    } else {
+      // sum over the line's cells for every output of this thread
+#pragma unroll
+      for (int r = 0; r < kOutPerThread; ++r) {
+        if (tid + r * kBlock >= a.nout) break;
+        double s = 0.0;
+        for (int q = oq0[r]; q < oq1[r]; ++q) {
+          const T* qr = Q + ((size_t)q * a.nb + ob1[r]) * CP;
+          const T* fr = F2 + ((size_t)a.tb.q_f2row[q] * a.nb + ob2[r]) * CP;
+          for (int c = 0; c < M; ++c) s += (double)qr[c] * (double)fr[c];
+        }
+        acc[r] += s;
+      }
     }
     __syncthreads();
   }
+  if constexpr (MF) {
+    // unit tiles to LDS (row i = 8 (r / 4) + 4 (lane / 32) + r % 4, column lane % 32),
+    // then each output sums its Q groups and cell ranges in a fixed order
+    double* Ct = (double*)smem;   // [units][32][32]
+    const int wave = tid >> 6, lane = tid & 63;
+    if (wave < a.nq * a.ksplit) {
 #pragma unroll
-  for (int r = 0; r < kOutPerThread; ++r) {
-    const int o = tid + r * kBlock;
-    if (o < a.nout) a.partials[(size_t)o * gridDim.x + blockIdx.x] = acc[r];
+      for (int r = 0; r < 16; ++r) {
+        const int i = 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3), j = lane & 31;
+        Ct[((size_t)wave * 32 + i) * 32 + j] = acc[r];
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < kOutPerThread; ++r) {
+      const int o = tid + r * kBlock;
+      if (o >= a.nout) break;
+      double v = 0.0;
+      for (int q = oq0[r]; q < oq1[r]; ++q)
+        for (int sp = 0; sp < a.ksplit; ++sp) v += Ct[((size_t)(q * a.ksplit + sp) * 32 + ob1[r]) * 32 + ob2[r]];
+      a.partials[(size_t)o * gridDim.x + blockIdx.x] = v;
+    }
+  } else {
+#pragma unroll
+    for (int r = 0; r < kOutPerThread; ++r) {
+      const int o = tid + r * kBlock;
+      if (o < a.nout) a.partials[(size_t)o * gridDim.x + blockIdx.x] = acc[r];
+    }
   }
 }
+
+// Matrix-core contraction (FP32 plans, up to 32 shells and 4 Q groups): cell
+// splits per Q group so that the units fill the four wavefronts.
+int fused_ksplit(const Plan& P) {
+  const int nq = (int)P.qgroups.size();
+  if (P.precision != TSB_FP32 || P.nb > 32 || nq < 1 || nq > 4) return 0;
+  return nq == 1 ? 4 : (nq == 2 ? 2 : 1);
+}
+
+int fused_units(const Plan& P) { return (int)P.qgroups.size() * fused_ksplit(P); }
 
 template <typename T>
 size_t fused_lds_bytes(const Plan& P, int bpg) {
@@ -181,7 +241,9 @@ size_t fused_lds_bytes(const Plan& P, int bpg) {
   const size_t LS = (size_t)N2 * (N1 + 1) + 1;
   size_t off = ((P.qgroups.size() + P.nf2) * P.nb + P.gcomp.size()) * (size_t)(M + 1) * sizeof(T);
   off = (off + 15) / 16 * 16;
-  return off + (size_t)bpg * P.fkinds.size() * (LS + M) * sizeof(T2);
+  const size_t need = off + (size_t)bpg * P.fkinds.size() * (LS + M) * sizeof(T2);
+  const size_t tiles = (size_t)fused_units(P) * 32 * 32 * sizeof(double);
+  return need > tiles ? need : tiles;
 }
 
 template <typename T, int N1, int N2>
@@ -225,7 +287,11 @@ int fused_launch(Plan& P, hipStream_t s) {
   }
   const size_t lds = fused_lds_bytes<T>(P, P.fused_bpg);
   prof_begin(P, kStReduce, s);
-  hipLaunchKernelGGL((fz_reduce_kernel<T, N1, N2>), dim3(P.red_wg), dim3(kBlock), lds, s, a);
+  a.ksplit = fused_ksplit(P);
+  if (a.ksplit > 0)
+    hipLaunchKernelGGL((fz_reduce_kernel<T, N1, N2, true>), dim3(P.red_wg), dim3(kBlock), lds, s, a);
+  else
+    hipLaunchKernelGGL((fz_reduce_kernel<T, N1, N2, false>), dim3(P.red_wg), dim3(kBlock), lds, s, a);
   prof_end(P, kStReduce, s);
   TSB_HIP(hipGetLastError());
   return TSB_OK;

@@ -15,6 +15,8 @@ namespace tsb {
 constexpr int kMaxEll = 8;          // largest l1, l2, L accepted
 constexpr int kMaxBins = 64;
 constexpr int kBlock = 256;          // threads per workgroup of every kernel
+constexpr int kScanPer = 16;         // elements per thread of the bucket scan
+constexpr int kScanChunk = kBlock * kScanPer;
 
 // ---------------------------------------------------------------------------
 // error reporting
@@ -132,17 +134,14 @@ struct Plan {
   double* d_B = nullptr;
   DevScalars* d_scal = nullptr;
   double* d_sum_partials = nullptr;   // per-block partial sums (prep and I)
-  int* d_tile_count = nullptr;
-  int* d_tile_start = nullptr;
-  int* d_tile_cursor = nullptr;
-  int* d_keys = nullptr;
-  int* d_perm = nullptr;      // records in (cell, octant) order within each tile
-  int* d_tile_ndense = nullptr;
-  int* d_dense_off = nullptr;
-  void* d_dense_desc = nullptr;     // [tiles][64] moment-group descriptors
-  void* d_dense_bits = nullptr;     // [tiles][8 T^3 / 32] moment-group keys
-  void* d_dense_contrib = nullptr;  // [groups][copies][p^3][nchx] fixed-point node sums
-  int64_t dense_cap = 0;
+  void* d_yspec = nullptr;      // box mode, local LOS: combined spectra of y_L^M*(x^_node) [ngrid][PG^3]
+  bool yspec_ready = false;     // subtract mean * d_yspec in the combine step
+  int* d_bk_count = nullptr;    // particles per (tile, reach class) bucket [nbk]
+  int* d_bk_cursor = nullptr;   // fill cursors [nbk] (directly after d_bk_count)
+  int* d_bk_start = nullptr;    // bucket starts [nbk + 1]
+  int* d_scan_part = nullptr;   // per-workgroup sums of the bucket scan
+  int64_t nbk = 0;              // tiles * 27
+  int* d_keys = nullptr;        // bucket key per particle
   void* d_rec_u = nullptr;    // particle records in bucket order: u (3 x double)
   void* d_rec_c = nullptr;    //   and channel weights [nchx][cap] (plan precision)
   int64_t particle_cap = 0;
@@ -193,6 +192,7 @@ int run_reduce(Plan& P, hipStream_t s);
 int run_reduce_final(Plan& P, hipStream_t s);
 void plan_fused(Plan& P);                   // fused.hip
 int run_fused(Plan& P, hipStream_t s);
+int run_ynode_fill(Plan& P, hipStream_t s);
 int run_unpack_grids(Plan& P, void* out, hipStream_t s);
 
 // ---------------------------------------------------------------------------

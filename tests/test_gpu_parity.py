@@ -165,3 +165,52 @@ def test_bad_input_is_reported():
     with pytest.raises(tsb.TsbError) as e:
         plan.measure(tsb.catalog_to_device({"pos": pos}))
     assert e.value.code == tsb.abi.TSB_E_INPUT
+
+
+def _assign_vs_oracle(req, cat, tol):
+    plan = tsb.Plan(**req)
+    grids = plan.assign(tsb.catalog_to_device(cat)).cpu().numpy()
+    og, _ = est.assign_channels(oracle_plan(**req), cat)
+    for c, (L, M, part) in enumerate(plan.channels()):
+        for copy in range(grids.shape[0]):
+            ref = og[(L, M)][copy]
+            ref = ref.real if part == 0 else ref.imag
+            scale = max(np.max(np.abs(ref)), 1.0)
+            err = np.max(np.abs(grids[copy, c] - ref))
+            assert err <= tol * scale, (L, M, part, copy, err, scale)
+    return grids
+
+
+def test_assignment_order_independent():
+    # the catalogue in cell order (as generated) and shuffled give identical bits
+    req = box_request(n=32, precision="f32")
+    cat = small_cat(seed=7)
+    plan = tsb.Plan(**req)
+    a = plan.assign(tsb.catalog_to_device(cat)).cpu().numpy()
+    perm = np.random.default_rng(0).permutation(len(cat["pos"]))
+    b = plan.assign(tsb.catalog_to_device({"pos": cat["pos"][perm]})).cpu().numpy()
+    assert np.array_equal(a, b)
+
+
+def test_assignment_crowded_cell():
+    # 30k particles inside one cell on a tile corner plus a uniform background:
+    # worst case for atomics on a single LDS address and for the bucket runs
+    rng = np.random.default_rng(11)
+    h = 1000.0 / 32
+    crowd = (np.array([8.0, 15.0, 31.0]) + 0.9 * rng.random((30000, 3))) * h
+    back = rng.random((5000, 3)) * 1000.0
+    cat = {"pos": np.concatenate([crowd, back]).astype(np.float32)}
+    _say("crowded cell")
+    _assign_vs_oracle(box_request(n=32, precision="f64"), cat, 1e-12)
+
+
+def test_assignment_edges_wrap():
+    # positions on and just outside the box faces wrap periodically (box mode)
+    rng = np.random.default_rng(12)
+    L = 1000.0
+    edge = np.array([0.0, L, -1e-3, L + 1e-3, np.nextafter(np.float32(L), np.float32(0)), 0.5 * L],
+                    np.float32)
+    pos = rng.choice(edge, size=(3000, 3)).astype(np.float32)
+    pos = np.concatenate([pos, (rng.random((3000, 3)) * L).astype(np.float32)])
+    _say("edges")
+    _assign_vs_oracle(box_request(n=32, precision="f64"), {"pos": pos}, 1e-12)
