@@ -66,13 +66,13 @@ __device__ inline typename cplx<T>::type shell_value(const PassArgs<T>& a, int b
   if (n2 == 0 || n2 > a.lut_max) return zero;
   const int bin = a.bin_lut[n2];
   if (bin != batch / a.nkinds) return zero;
-  const FKind k = a.kinds[batch % a.nkinds];
+  const FKind& k = a.kinds[batch % a.nkinds];   // read in place (no private copy)
   const double r = sqrt((double)n2);
-  double u[3];
-  u[a.axA] = fa / r;
-  u[a.axB] = fb / r;
-  u[a.axE] = fe / r;
-  const double ux = u[0], uy = u[1], uz = u[2];
+  // unit vector: a, b, e index the Cartesian axes axA, axB, axE
+  const double ca = fa / r, cb = fb / r, ce = fe / r;
+  const double ux = a.axA == 0 ? ca : (a.axB == 0 ? cb : ce);
+  const double uy = a.axA == 1 ? ca : (a.axB == 1 ? cb : ce);
+  const double uz = a.axA == 2 ? ca : (a.axB == 2 ? cb : ce);
   double fr = 0.0, fi = 0.0;
   for (int p = 0; p < k.nparts; ++p) {
     double yr, yi;

@@ -222,6 +222,233 @@ __global__ void __launch_bounds__(kBlock) fz_reduce_kernel(FusedArgs<T> a) {
   }
 }
 
+// ---------------------------------------------------------------------------
+// FP32 plans, all shells of a line at once: 512 threads, two barriers per line.
+//   phase 1: first-level transforms of every (slot, n1), inputs prefetched into
+//            registers while the previous line finishes;
+//   phase 2: per (shell, k2) the second-level transforms of all slot kinds,
+//            turned straight into the Q and right-factor rows of N1 cells;
+//   then the contraction on the matrix cores (units of (q, cell range) over the
+//   eight wavefronts), which overlaps the next line's loads and phase 1.
+
+constexpr int kWBlock = 512;
+constexpr int kWOut = 8;       // outputs per thread
+constexpr int kWKinds = 4;     // slot kinds per shell held in registers
+constexpr int kWGPre = 2;      // G values per thread and line
+constexpr int kWGroups = 256;  // workgroups of the one-pass kernel
+
+// sq[i] += cf * part(row[i]) * g(c_i) for the N1 cells c_i = k2 + N2 bitrev(i)
+template <int N1, int N2>
+__device__ inline void add_term(float (&sq)[N1], const float2 (&row)[N1], int part, float cf, const float* gr) {
+#pragma unroll
+  for (int i = 0; i < N1; ++i) {
+    const float f = part ? row[i].y : row[i].x;
+    sq[i] += cf * f * gr[N2 * bit_reverse<N1>(i)];
+  }
+}
+
+template <int N1, int N2>
+__device__ inline void put_row(float* frow, const float2 (&row)[N1], int part) {
+#pragma unroll
+  for (int i = 0; i < N1; ++i) frow[N2 * bit_reverse<N1>(i)] = part ? row[i].y : row[i].x;
+}
+
+template <int N1, int N2>
+__global__ void __launch_bounds__(kWBlock) fz_reduce_wide_kernel(FusedArgs<float> a) {
+  typedef float2 T2;
+  constexpr int M = N1 * N2;
+  constexpr int LS = N2 * (N1 + 1) + 1;
+  constexpr int CP = M + 1;
+  const int64_t M3 = (int64_t)M * M * M, lines = (int64_t)M * M;
+  const int nk = a.nkinds, nb = a.nb, nsl = nb * nk;
+  extern __shared__ char smem[];
+  float* Q = (float*)smem;                         // [nq][nb][CP]
+  float* F2 = Q + (size_t)a.nq * nb * CP;          // [nf2][nb][CP]
+  float* Gv = F2 + (size_t)a.nf2 * nb * CP;        // [ngc][CP]
+  size_t off = ((size_t)(a.nq + a.nf2) * nb * CP + (size_t)a.ngc * CP) * sizeof(float);
+  off = (off + 15) / 16 * 16;
+  T2* tw = (T2*)(smem + off);                      // [M] e^{+2 pi i k / M}
+  T2* stage = tw + M;                              // [nsl][LS]
+  const int tid = threadIdx.x;
+  for (int k = tid; k < M; k += kWBlock) {
+    T2 w = a.tw[k];
+    w.y = -w.y;
+    tw[k] = w;
+  }
+  const int wave = tid >> 6, lane = tid & 63;
+  const int nunits = a.nq * a.ksplit;
+  double acc[16];
+#pragma unroll
+  for (int r = 0; r < 16; ++r) acc[r] = 0.0;
+  // phase-1 task of this thread (one per thread) and its prefetched inputs
+  const bool has_task = tid < nsl * N1;
+  const int sl = tid / N1, n1 = tid - (tid / N1) * N1;
+  T2 pv[N2];
+  float gpre[kWGPre];
+  auto prefetch = [&](int64_t line) {
+    if (has_task) {
+      const T2* src = a.u2 + ((int64_t)sl * M * M + line) * a.PF;
+#pragma unroll
+      for (int n2 = 0; n2 < N2; ++n2) {
+        int e = n1 + N1 * n2 + a.RF;
+        if (e >= M) e -= M;
+        T2 x;
+        x.x = 0.f;
+        x.y = 0.f;
+        if (e < a.PF) x = src[e];
+        pv[n2] = x;
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < kWGPre; ++j) {
+      const int idx = tid + j * kWBlock;
+      gpre[j] = 0.f;
+      if (idx < a.ngc * M) {
+        const int f = idx / M, c = idx - f * M;
+        const T2 v = a.gfields[(int64_t)a.tb.g_slot[f] * M3 + line * M + c];
+        gpre[j] = a.tb.g_part[f] ? v.y : v.x;
+      }
+    }
+  };
+  int64_t line = blockIdx.x;
+  if (line < lines) prefetch(line);
+  __syncthreads();   // twiddles
+  for (; line < lines; line += gridDim.x) {
+#pragma unroll
+    for (int j = 0; j < kWGPre; ++j) {
+      const int idx = tid + j * kWBlock;
+      if (idx < a.ngc * M) {
+        const int f = idx / M, c = idx - f * M;
+        Gv[(size_t)f * CP + c] = gpre[j];
+      }
+    }
+    if (has_task) {
+      reg_fft<float, T2, N2>(pv, 1);
+      T2* st = stage + (size_t)sl * LS;
+#pragma unroll
+      for (int i = 0; i < N2; ++i) {
+        const int k2 = bit_reverse<N2>(i);
+        const T2 w = tw[(n1 * k2) % M];
+        T2 o;
+        o.x = pv[i].x * w.x - pv[i].y * w.y;
+        o.y = pv[i].x * w.y + pv[i].y * w.x;
+        st[k2 * (N1 + 1) + n1] = o;
+      }
+    }
+    __syncthreads();
+    if (line + gridDim.x < lines) prefetch(line + gridDim.x);
+    for (int task = tid; task < nb * N2; task += kWBlock) {
+      const int b = task / N2, k2 = task - b * N2;
+      T2 u[kWKinds][N1];
+#pragma unroll
+      for (int k = 0; k < kWKinds; ++k) {
+        if (k < nk) {
+          const T2* st = stage + (size_t)(b * nk + k) * LS + k2 * (N1 + 1);
+#pragma unroll
+          for (int j = 0; j < N1; ++j) u[k][j] = st[j];
+          reg_fft<float, T2, N1>(u[k], 1);
+        } else {
+#pragma unroll
+          for (int j = 0; j < N1; ++j) u[k][j] = make_float2(0.f, 0.f);
+        }
+      }
+      // rows of the N1 cells c_i = k2 + N2 bitrev(i); slot kinds are picked by
+      // uniform branches so that every register index stays static
+      for (int q = 0; q < a.nq; ++q) {
+        float sq[N1];
+#pragma unroll
+        for (int i = 0; i < N1; ++i) sq[i] = 0.f;
+        for (int t = a.tb.q_t0[q]; t < a.tb.q_t1[q]; ++t) {
+          const float cf = (float)a.tb.coef[t];
+          const int part = a.tb.f1part[t];
+          const float* gr = Gv + (size_t)a.tb.g[t] * CP + k2;
+          switch (a.tb.f1kind[t]) {
+            case 0: add_term<N1, N2>(sq, u[0], part, cf, gr); break;
+            case 1: add_term<N1, N2>(sq, u[1], part, cf, gr); break;
+            case 2: add_term<N1, N2>(sq, u[2], part, cf, gr); break;
+            default: add_term<N1, N2>(sq, u[3], part, cf, gr); break;
+          }
+        }
+        float* qrow = Q + ((size_t)q * nb + b) * CP + k2;
+#pragma unroll
+        for (int i = 0; i < N1; ++i) qrow[N2 * bit_reverse<N1>(i)] = sq[i];
+      }
+      for (int r = 0; r < a.nf2; ++r) {
+        float* frow = F2 + ((size_t)r * nb + b) * CP + k2;
+        const int part = a.tb.f2_part[r];
+        switch (a.tb.f2_kind[r]) {
+          case 0: put_row<N1, N2>(frow, u[0], part); break;
+          case 1: put_row<N1, N2>(frow, u[1], part); break;
+          case 2: put_row<N1, N2>(frow, u[2], part); break;
+          default: put_row<N1, N2>(frow, u[3], part); break;
+        }
+      }
+    }
+    __syncthreads();
+    if (wave < nunits) {
+      const int q = wave / a.ksplit, sp = wave - q * a.ksplit;
+      const int b = lane & 31, kh = lane >> 5;
+      const bool live = b < nb;
+      const float* qr = Q + ((size_t)q * nb + (live ? b : 0)) * CP + kh;
+      const float* fr = F2 + ((size_t)a.tb.q_f2row[q] * nb + (live ? b : 0)) * CP + kh;
+      const int kl = M / a.ksplit, k0 = sp * kl;
+      floatx16 c = {};
+      for (int kk = k0; kk < k0 + kl; kk += 2) {
+        const float av = live ? qr[kk] : 0.f;
+        const float bv = live ? fr[kk] : 0.f;
+        c = __builtin_amdgcn_mfma_f32_32x32x2f32(av, bv, c, 0, 0, 0);
+      }
+#pragma unroll
+      for (int r = 0; r < 16; ++r) acc[r] += (double)c[r];
+    }
+  }
+  __syncthreads();
+  double* Ct = (double*)smem;   // [units][32][32]
+  if (wave < nunits) {
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const int i = 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3), j = lane & 31;
+      Ct[((size_t)wave * 32 + i) * 32 + j] = acc[r];
+    }
+  }
+  __syncthreads();
+  for (int o = tid; o < a.nout; o += kWBlock) {
+    const OutEntry e = a.outs[o];
+    double v = 0.0;
+    for (int q = e.q0; q < e.q1; ++q)
+      for (int sp = 0; sp < a.ksplit; ++sp) v += Ct[((size_t)(q * a.ksplit + sp) * 32 + e.b1) * 32 + e.b2];
+    a.partials[(size_t)o * gridDim.x + blockIdx.x] = v;
+  }
+}
+
+size_t wide_lds_bytes(const Plan& P) {
+  const int M = P.M;
+  const int N2 = M >= 128 ? 16 : 8;
+  const int N1 = M / N2;
+  const size_t LS = (size_t)N2 * (N1 + 1) + 1;
+  size_t off = ((P.qgroups.size() + P.nf2) * P.nb + P.gcomp.size()) * (size_t)(M + 1) * sizeof(float);
+  off = (off + 15) / 16 * 16;
+  const size_t need = off + (size_t)M * 8 + (size_t)P.nb * P.fkinds.size() * LS * 8;
+  const size_t units = P.qgroups.size() * (size_t)std::max<size_t>(1, 8 / P.qgroups.size());
+  const size_t tiles = units * 32 * 32 * sizeof(double);
+  return need > tiles ? need : tiles;
+}
+
+// Whether the one-pass FP32 kernel applies (shape limits of its register and
+// LDS layout).
+bool wide_ok(const Plan& P) {
+  if (P.precision != TSB_FP32) return false;
+  if (!(P.M == 64 || P.M == 128)) return false;   // N1 = 8 keeps the slot kinds in registers
+  const int N2 = P.M >= 128 ? 16 : 8, N1 = P.M / N2;
+  const int nq = (int)P.qgroups.size();
+  if (P.nb > 32 || nq < 1 || nq > 8 || (int)P.fkinds.size() > kWKinds) return false;
+  if (P.nb * (int)P.fkinds.size() * N1 > kWBlock) return false;
+  if ((int)P.gcomp.size() * P.M > kWGPre * kWBlock) return false;
+  if ((int)P.outs.size() > kWOut * kWBlock) return false;
+  if ((int)P.terms.size() > kFMaxTerms || P.nf2 > kFMaxComp || (int)P.gcomp.size() > kFMaxComp) return false;
+  return wide_lds_bytes(P) <= 150 * 1024;
+}
+
 // Matrix-core contraction (FP32 plans, up to 32 shells and 4 Q groups): cell
 // splits per Q group so that the units fill the four wavefronts.
 int fused_ksplit(const Plan& P) {
@@ -287,6 +514,17 @@ int fused_launch(Plan& P, hipStream_t s) {
   }
   const size_t lds = fused_lds_bytes<T>(P, P.fused_bpg);
   prof_begin(P, kStReduce, s);
+  if (P.fused_wide) {
+    a.ksplit = std::max(1, 8 / a.nq);
+    if constexpr (std::is_same<T, float>::value && N1 == 8 && N1 * N2 >= 64) {
+      prof_begin(P, kStReduce, s);
+      hipLaunchKernelGGL((fz_reduce_wide_kernel<N1, N2>), dim3(P.red_wg), dim3(kWBlock), wide_lds_bytes(P), s, a);
+      prof_end(P, kStReduce, s);
+      TSB_HIP(hipGetLastError());
+      return TSB_OK;
+    }
+    return fail(TSB_E_UNSUPPORTED, "fused reduction: one-pass kernel does not cover this shape");
+  }
   a.ksplit = fused_ksplit(P);
   if (a.ksplit > 0)
     hipLaunchKernelGGL((fz_reduce_kernel<T, N1, N2, true>), dim3(P.red_wg), dim3(kBlock), lds, s, a);
@@ -321,6 +559,14 @@ void plan_fused(Plan& P) {
   if ((int)P.terms.size() > kFMaxTerms || (int)P.qgroups.size() > kFMaxQ || P.nf2 > kFMaxComp ||
       (int)P.gcomp.size() > kFMaxComp)
     return;
+  P.fused_wide = wide_ok(P);
+  if (P.fused_wide) {
+    // one workgroup of 512 threads per compute unit (its LDS fills one): 256 on MI355X
+    P.fused = true;
+    P.fused_bpg = P.nb;
+    P.red_wg = std::min<int>(kWGroups, M * M);
+    return;
+  }
   const bool f64 = P.precision == TSB_FP64;
   for (int bpg = P.nb; bpg >= 1; --bpg) {
     const size_t b = f64 ? fused_lds_bytes<double>(P, bpg) : fused_lds_bytes<float>(P, bpg);

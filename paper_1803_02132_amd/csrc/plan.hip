@@ -385,7 +385,7 @@ int plan_build(Plan& P) {
   for (auto& q : P.qgroups)
     if (P.f2idx[q.f2] < 0) P.f2idx[q.f2] = P.nf2++;
   plan_fused(P);
-  if (P.fused) P.red_wg = (int)std::min<int64_t>((int64_t)P.M * P.M, 1024);
+  if (P.fused && !P.fused_wide) P.red_wg = (int)std::min<int64_t>((int64_t)P.M * P.M, 1024);
   P.g_offset = P.fused ? 0 : (int64_t)P.nb * (int64_t)P.fkinds.size() * P.M * P.M * P.M;
   return TSB_OK;
 }

@@ -150,6 +150,7 @@ struct Plan {
 
   // fused last F pass + reduction
   bool fused = false;
+  bool fused_wide = false;      // one-pass FP32 kernel (all shells of a line at once)
   int fused_bpg = 1;            // shells per group inside the fused kernel
   int nf2 = 0;                  // F components used as right factors
   std::vector<int> f2idx;       // per F component: its right-factor row or -1
