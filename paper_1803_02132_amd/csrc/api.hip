@@ -83,10 +83,15 @@ int plan_alloc(Plan& P, bool dry) {
   if (P.box_mode && P.los_kind == TSB_LOS_LOCAL) ALLOC(P.d_yspec, ng * PG * PG * PG * c);
   const int64_t ntiles = (int64_t)P.NT * P.NT * P.NT;
   P.nbk = ntiles * 27;
-  ALLOC(P.d_bk_count, 2 * P.nbk * 4);
+  ALLOC(P.d_bk_count, (2 * P.nbk + 1) * 4);   // counts, cursors, heavy-slot counter
   P.d_bk_cursor = dry ? nullptr : P.d_bk_count + P.nbk;
   ALLOC(P.d_bk_start, (P.nbk + 1) * 4);
   ALLOC(P.d_scan_part, ((P.nbk + kScanChunk - 1) / kScanChunk + 1) * 4);
+  ALLOC(P.d_tile_parts, ntiles * 4);
+  ALLOC(P.d_tile_hslot, ntiles * 4);
+  ALLOC(P.d_tile_pstart, (ntiles + 1) * 4);
+  ALLOC(P.d_heavy_tile, (int64_t)assign_max_heavy() * 4);
+  ALLOC(P.d_heavy, assign_heavy_bytes(P));
   ALLOC(P.d_scal, (int64_t)sizeof(DevScalars));
   ALLOC(P.d_sum_partials, std::max<int64_t>(ntiles, 4 * 512) * 8);
   ALLOC(P.d_partials, (int64_t)P.red_wg * std::max<int64_t>((int64_t)P.outs.size(), 1) * 8);
@@ -115,7 +120,8 @@ void plan_free(Plan& P) {
                   P.d_tw_n, P.d_tw_m, P.d_bin_lut, P.d_fkinds, P.d_fcomp, P.d_gcomp, P.d_terms,
                   P.d_qgroups, P.d_outs, P.d_out_norm, P.d_partials, P.d_B, P.d_scal, P.d_sum_partials,
                   P.d_bk_count, P.d_bk_start, P.d_scan_part, P.d_keys, P.d_rec_u, P.d_rec_c,
-                  P.d_f2idx, P.d_yspec};
+                  P.d_f2idx, P.d_yspec, P.d_tile_parts, P.d_tile_hslot, P.d_tile_pstart, P.d_heavy_tile,
+                  P.d_heavy, P.d_work};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
 }
@@ -128,18 +134,21 @@ int ensure_particles(Plan& P, int64_t n) {
   const int64_t nchx = (int64_t)P.chans.size() + (P.box_mode ? 0 : 1);
   const int64_t esz = P.precision == TSB_FP64 ? 8 : 4;
   const int64_t per = 4 + 24 + nchx * esz;   // key, u, channel weights
-  for (void* p : {(void*)P.d_keys, P.d_rec_u, P.d_rec_c})
+  for (void* p : {(void*)P.d_keys, P.d_rec_u, P.d_rec_c, P.d_work})
     if (p) (void)hipFree(p);
   P.d_keys = nullptr;
-  P.d_rec_u = P.d_rec_c = nullptr;
-  P.bytes -= per * P.particle_cap;
-  P.particle_cap = 0;
+  P.d_rec_u = P.d_rec_c = P.d_work = nullptr;
+  P.bytes -= per * P.particle_cap + 8 * P.work_cap;
+  P.particle_cap = P.work_cap = 0;
   const int64_t cap = std::max<int64_t>(n + n / 8, 1024);
+  const int64_t wcap = assign_work_cap(P, cap);
   int rc;
   if ((rc = dalloc((void**)&P.d_keys, cap * 4, P.bytes, false))) return rc;
   if ((rc = dalloc(&P.d_rec_u, cap * 24, P.bytes, false))) return rc;
   if ((rc = dalloc(&P.d_rec_c, cap * nchx * esz, P.bytes, false))) return rc;
+  if ((rc = dalloc(&P.d_work, wcap * 8, P.bytes, false))) return rc;
   P.particle_cap = cap;
+  P.work_cap = wcap;
   return TSB_OK;
 }
 

@@ -431,7 +431,23 @@ struct TileArgs {
   // reads of one tile: neighbour offset (9 (dx+1) + 3 (dy+1) + dz + 1) and class range
   int nr;
   int rd[kMaxRanges], rcl[kMaxRanges], rch[kMaxRanges];
+  // work items: (tile, part); a tile with more than kPartVisits visits is split
+  const int2* work;
+  const int* nwork;            // number of work items (device)
+  const int* hslot;            // per tile: heavy slot or -1
+  unsigned long long* heavy;   // [slot][copies][nchx][T^3] fixed-point sums of split tiles
 };
+
+// Ranges of one tile (wave-parallel): start and length of range r of tile t.
+__device__ inline void tile_range(const TileArgs& a, int tile, int r, int* st, int* len) {
+  const int NT = a.NT;
+  const int tx = tile / (NT * NT), ty = (tile / NT) % NT, tz = tile % NT;
+  const int d = a.rd[r];
+  const int nx = (tx + d / 9 - 1 + NT) % NT, ny = (ty + (d / 3) % 3 - 1 + NT) % NT, nz = (tz + d % 3 - 1 + NT) % NT;
+  const int64_t nt = ((int64_t)nx * NT + ny) * NT + nz;
+  *st = a.start[nt * kClasses + a.rcl[r]];
+  *len = a.start[nt * kClasses + a.rch[r]] - *st;
+}
 
 
 // Node position (relative to the observer) of grid copy g, and y_L^M*(x^) of
@@ -460,6 +476,8 @@ __device__ inline void node_dir(const double* origin, double h, const double* ob
 }
 
 constexpr int kVisitChunk = 128;  // particles staged in LDS at a time (two wavefronts stage them)
+constexpr int kPartVisits = 256;  // visits per work item; busier tiles are split
+constexpr int kMaxHeavy = 2048;   // split tiles with a slot of their own (others run whole)
 
 // A staged particle for one grid copy: on each axis the stencil nodes that
 // fall inside the tile, as weights and offsets into the tile's cell index,
@@ -496,27 +514,26 @@ __global__ void __launch_bounds__(kBlock) assign_tile_kernel(TileArgs a, Records
   __shared__ int r_start[kMaxRanges];
   __shared__ int r_off[kMaxRanges + 1];
   __shared__ Visit<T, NCH> vis[kVisitChunk];
-  __shared__ int it_off[kVisitChunk + 1];
+  __shared__ int it_first[kVisitChunk];      // first work item of each staged particle
+  __shared__ int wtot[2];                     // items of each staging wavefront
+  __shared__ unsigned char it_vis[kVisitChunk * 9];
   const int TS = a.T, T3 = TS * TS * TS;
   const int nch = a.ci.nch;
   const int nchx = nch + (a.box_mode ? 0 : 1);
-  const int tile = blockIdx.x;
+  if ((int)blockIdx.x >= *a.nwork) return;   // the grid is an upper bound of the work items
+  const int2 wk = a.work[blockIdx.x];
+  const int tile = wk.x, part = wk.y;
   const int NT = a.NT;
   const int tx = tile / (NT * NT), ty = (tile / NT) % NT, tz = tile % NT;
   const int o3[3] = {tx * TS, ty * TS, tz * TS};
   const int N = a.N, p = a.p;
   const int lane = threadIdx.x & 63;
+  const int hs = a.hslot[tile];   // >= 0: split tile, sums go to its heavy slot
   if (threadIdx.x < 64) {
     // bucket ranges to read, and their prefix over the first wavefront
     const int r = threadIdx.x;
     int st = 0, len = 0;
-    if (r < a.nr) {
-      const int d = a.rd[r];
-      const int nx = (tx + d / 9 - 1 + NT) % NT, ny = (ty + (d / 3) % 3 - 1 + NT) % NT, nz = (tz + d % 3 - 1 + NT) % NT;
-      const int64_t nt = ((int64_t)nx * NT + ny) * NT + nz;
-      st = a.start[nt * kClasses + a.rcl[r]];
-      len = a.start[nt * kClasses + a.rch[r]] - st;
-    }
+    if (r < a.nr) tile_range(a, tile, r, &st, &len);
     int inc = len;
     for (int off = 1; off < 64; off <<= 1) {
       const int x = __shfl_up(inc, off);
@@ -529,6 +546,8 @@ __global__ void __launch_bounds__(kBlock) assign_tile_kernel(TileArgs a, Records
   const double scale = a.scal->scale, inv_scale = a.scal->inv_scale;
   __syncthreads();
   const int total = r_off[64];
+  const int v0 = hs >= 0 ? part * kPartVisits : 0;
+  const int v1 = hs >= 0 ? min(total, v0 + kPartVisits) : total;
   // staging order scrambled by a multiplier prime to the total, so that
   // spatially sorted input does not put neighbouring lanes on the same cells
   int64_t mult = 7919;
@@ -540,13 +559,13 @@ __global__ void __launch_bounds__(kBlock) assign_tile_kernel(TileArgs a, Records
   for (int g = 0; g < a.copies; ++g) {
     const int nc = g == 0 ? nchx : nch;   // the survey randoms channel lives on copy 0 only
     for (int i = threadIdx.x; i < nchx * T3; i += kBlock) acc[i] = 0ull;
-    for (int c0 = 0; c0 < total; c0 += kVisitChunk) {
-      const int nv = min(kVisitChunk, total - c0);
+    for (int c0 = v0; c0 < v1; c0 += kVisitChunk) {
+      const int nv = min(kVisitChunk, v1 - c0);
       __syncthreads();   // acc cleared / previous chunk consumed
+      int items = 0, inc = 0;
       if (threadIdx.x < kVisitChunk) {
         // two wavefronts: one particle per lane, then per-wavefront item prefixes
         const int v = threadIdx.x;
-        int items = 0;
         if (v < nv) {
           const int idx = (int)(((int64_t)(c0 + v) * mult) % total);
           int lo = 0, hi = a.nr;   // r_off[lo] <= idx < r_off[hi]
@@ -586,27 +605,27 @@ __global__ void __launch_bounds__(kBlock) assign_tile_kernel(TileArgs a, Records
           V.cnt[2] = (unsigned char)cnt[2];
           items = cnt[0] * cnt[1];
         }
-        int inc = items;
+        inc = items;
         for (int off = 1; off < 64; off <<= 1) {
           const int x = __shfl_up(inc, off);
           if (lane >= off) inc += x;
         }
-        it_off[v + 1] = inc;
-        if (v == 0) it_off[0] = 0;
+        if (lane == 63) wtot[v >> 6] = inc;
       }
       __syncthreads();
-      if (threadIdx.x >= 64 && threadIdx.x < kVisitChunk) it_off[threadIdx.x + 1] += it_off[64];
+      if (threadIdx.x < kVisitChunk) {
+        // item -> particle map; the second wavefront follows the first one's items
+        const int v = threadIdx.x;
+        const int first = inc - items + (v >= 64 ? wtot[0] : 0);
+        it_first[v] = first;
+        for (int k = 0; k < items; ++k) it_vis[first + k] = (unsigned char)v;
+      }
+      const int nitems = wtot[0] + wtot[1];
       __syncthreads();
-      const int nitems = it_off[nv];
       for (int it = threadIdx.x; it < nitems; it += kBlock) {
-        int lo = 0, hi = nv;   // it_off[lo] <= it < it_off[hi]
-        while (hi - lo > 1) {
-          const int mid = (lo + hi) >> 1;
-          if (it_off[mid] <= it) lo = mid;
-          else hi = mid;
-        }
-        const Visit<T, NCH>& V = vis[lo];
-        const int loc = it - it_off[lo];
+        const int vi = it_vis[it];
+        const Visit<T, NCH>& V = vis[vi];
+        const int loc = it - it_first[vi];
         const int cy = V.cnt[1];
         const int sx = loc / cy, sy = loc - sx * cy;
         const T wxy = V.w[0][sx] * V.w[1][sy];
@@ -624,6 +643,16 @@ __global__ void __launch_bounds__(kBlock) assign_tile_kernel(TileArgs a, Records
       }
     }
     __syncthreads();
+    if (hs >= 0) {
+      // part of a split tile: add the fixed-point sums into its slot (integer, order-free)
+      unsigned long long* hb = a.heavy + ((size_t)hs * a.copies + g) * nchx * T3;
+      for (int i = threadIdx.x; i < nc * T3; i += kBlock) {
+        const unsigned long long v = acc[i];
+        if (v != 0ull) atomicAdd(hb + i, v);
+      }
+      __syncthreads();
+      continue;
+    }
     // write out this copy
     for (int cell = threadIdx.x; cell < T3; cell += kBlock) {
       const int lx = cell / (TS * TS), ly = (cell / TS) % TS, lz = cell % TS;
@@ -643,6 +672,51 @@ __global__ void __launch_bounds__(kBlock) assign_tile_kernel(TileArgs a, Records
     }
     __syncthreads();
   }
+  if (!a.box_mode && hs < 0) {
+    __shared__ double sh[kBlock];
+    sh[threadIdx.x] = sumI;
+    __syncthreads();
+    for (int st = kBlock / 2; st > 0; st >>= 1) {
+      if (threadIdx.x < st) sh[threadIdx.x] += sh[threadIdx.x + st];
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) a.tile_I[tile] = sh[0];
+  }
+}
+
+// Split tiles: convert the summed fixed-point grids of each heavy slot.
+template <typename T>
+__global__ void __launch_bounds__(kBlock) heavy_final_kernel(TileArgs a, const int* heavy_tile, const int* nheavy) {
+  typedef typename cplx<T>::type T2;
+  const int slot = blockIdx.x;
+  if (slot >= min(*nheavy, kMaxHeavy)) return;
+  const int tile = heavy_tile[slot];
+  const int TS = a.T, T3 = TS * TS * TS, N = a.N, NT = a.NT;
+  const int nch = a.ci.nch;
+  const int nchx = nch + (a.box_mode ? 0 : 1);
+  const int o3[3] = {tile / (NT * NT) * TS, (tile / NT) % NT * TS, tile % NT * TS};
+  const double inv_scale = a.scal->inv_scale;
+  T2* out = (T2*)a.out;
+  const size_t N3 = (size_t)N * N * N;
+  double sumI = 0.0;
+  for (int g = 0; g < a.copies; ++g) {
+    const long long* hb = (const long long*)a.heavy + ((size_t)slot * a.copies + g) * nchx * T3;
+    for (int cell = threadIdx.x; cell < T3; cell += kBlock) {
+      const int lx = cell / (TS * TS), ly = (cell / TS) % TS, lz = cell % TS;
+      const size_t lin = ((size_t)(o3[0] + lx) * N + (o3[1] + ly)) * N + (o3[2] + lz);
+      for (int gr = 0; gr < a.ngrid; ++gr) {
+        const int cre = a.gre[gr], cim = a.gim[gr];
+        T2 o;
+        o.x = (T)((double)hb[(size_t)cre * T3 + cell] * inv_scale);
+        o.y = cim >= 0 ? (T)((double)hb[(size_t)cim * T3 + cell] * inv_scale) : (T)0;
+        out[((size_t)g * a.ngrid + gr) * N3 + lin] = o;
+      }
+      if (!a.box_mode && g == 0) {
+        const double v = a.scal->alpha * (double)hb[(size_t)nch * T3 + cell] * inv_scale;
+        sumI += v * v * v;
+      }
+    }
+  }
   if (!a.box_mode) {
     __shared__ double sh[kBlock];
     sh[threadIdx.x] = sumI;
@@ -653,6 +727,47 @@ __global__ void __launch_bounds__(kBlock) assign_tile_kernel(TileArgs a, Records
     }
     if (threadIdx.x == 0) a.tile_I[tile] = sh[0];
   }
+}
+
+// Work planning, one thread per tile: visits, parts and heavy slots.
+__global__ void __launch_bounds__(kBlock) tile_parts_kernel(TileArgs a, int ntiles, int* parts, int* hslot,
+                                                            int* heavy_tile, int* nheavy) {
+  const int t = blockIdx.x * kBlock + threadIdx.x;
+  if (t >= ntiles) return;
+  int total = 0;
+  for (int r = 0; r < a.nr; ++r) {
+    int st, len;
+    tile_range(a, t, r, &st, &len);
+    total += len;
+  }
+  int np = (total + kPartVisits - 1) / kPartVisits;
+  int hs = -1;
+  if (np > 1) {
+    const int sl = atomicAdd(nheavy, 1);
+    if (sl < kMaxHeavy) {
+      hs = sl;
+      heavy_tile[sl] = t;
+    } else {
+      np = 1;   // out of slots: runs whole
+    }
+  }
+  parts[t] = np < 1 ? 1 : np;
+  hslot[t] = hs;
+}
+
+__global__ void __launch_bounds__(kBlock) tile_work_kernel(int ntiles, const int* parts, const int* pstart,
+                                                           int2* work) {
+  const int t = blockIdx.x * kBlock + threadIdx.x;
+  if (t >= ntiles) return;
+  const int b = pstart[t];
+  for (int p = 0; p < parts[t]; ++p) work[b + p] = make_int2(t, p);
+}
+
+__global__ void __launch_bounds__(kBlock) heavy_zero_kernel(unsigned long long* heavy, const int* nheavy,
+                                                            int64_t per_slot) {
+  const int64_t n = (int64_t)min(*nheavy, kMaxHeavy) * per_slot;
+  for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock)
+    heavy[i] = 0ull;
 }
 
 // y_L^M*(x^_node) on both grid copies in the complex-grid layout of the
@@ -787,6 +902,18 @@ int run_prep(Plan& P, const tsb_catalog* data, const tsb_catalog* rand, hipStrea
   return TSB_OK;
 }
 
+int64_t assign_work_cap(const Plan& P, int64_t particles) {
+  const int64_t ntiles = (int64_t)P.NT * P.NT * P.NT;
+  return ntiles + (8 * particles + kPartVisits - 1) / kPartVisits + 1;
+}
+
+int64_t assign_heavy_bytes(const Plan& P) {
+  const int64_t nchx = (int64_t)P.chans.size() + (P.box_mode ? 0 : 1);
+  return (int64_t)kMaxHeavy * P.copies * nchx * P.T * P.T * P.T * 8;
+}
+
+int assign_max_heavy() { return kMaxHeavy; }
+
 int chan_info(const Plan& P, ChanInfo* ci) {
   *ci = ChanInfo{};
   ci->nch = (int)P.chans.size();
@@ -859,7 +986,6 @@ int assign_impl(Plan& P, const BucketArgs& b, const ChanInfo& ci, hipStream_t s)
     f.scal = P.d_scal;
     hipLaunchKernelGGL((bucket_fill_kernel<T, NCH>), dim3(grid_blocks(ntot)), dim3(kBlock), 0, s, f);
   }
-  prof_end(P, kStBucket, s);
 
   TileArgs a{};
   a.inv_h = (double)P.N / P.L;
@@ -883,9 +1009,37 @@ int assign_impl(Plan& P, const BucketArgs& b, const ChanInfo& ci, hipStream_t s)
   a.tile_I = P.d_sum_partials;
   a.nr = tile_ranges(P.NT, a.rd, a.rcl, a.rch);
   if (a.nr > kMaxRanges) return fail(TSB_E_UNSUPPORTED, "assignment: too many bucket ranges");
+  int* nheavy = P.d_bk_count + 2 * P.nbk;   // cleared with the bucket counters
+  a.work = (const int2*)P.d_work;
+  a.nwork = P.d_tile_pstart + ntiles;
+  a.hslot = P.d_tile_hslot;
+  a.heavy = (unsigned long long*)P.d_heavy;
+  {
+    // work items: tiles with more than kPartVisits visits are split into parts
+    const int tb = (ntiles + kBlock - 1) / kBlock;
+    hipLaunchKernelGGL(tile_parts_kernel, dim3(tb), dim3(kBlock), 0, s, a, ntiles, P.d_tile_parts, P.d_tile_hslot,
+                       P.d_heavy_tile, nheavy);
+    const int nparts = (ntiles + kScanChunk - 1) / kScanChunk;
+    hipLaunchKernelGGL(scan_sums_kernel, dim3(nparts), dim3(kBlock), 0, s, (const int*)P.d_tile_parts,
+                       (int64_t)ntiles, P.d_scan_part);
+    hipLaunchKernelGGL(scan_parts_kernel, dim3(1), dim3(kBlock), 0, s, P.d_scan_part, nparts);
+    hipLaunchKernelGGL(scan_out_kernel, dim3(nparts), dim3(kBlock), 0, s, (const int*)P.d_tile_parts,
+                       (int64_t)ntiles, (const int*)P.d_scan_part, P.d_tile_pstart);
+    hipLaunchKernelGGL(tile_work_kernel, dim3(tb), dim3(kBlock), 0, s, ntiles, (const int*)P.d_tile_parts,
+                       (const int*)P.d_tile_pstart, (int2*)P.d_work);
+    const int64_t per_slot = (int64_t)P.copies * nchx * P.T * P.T * P.T;
+    hipLaunchKernelGGL(heavy_zero_kernel, dim3(1024), dim3(kBlock), 0, s, (unsigned long long*)P.d_heavy,
+                       (const int*)nheavy, per_slot);
+  }
+  prof_end(P, kStBucket, s);
+  // upper bound of the work items: a particle is visited by at most 8 tiles
+  const int64_t work_bound = (int64_t)ntiles + (8 * ntot + kPartVisits - 1) / kPartVisits + 1;
+  if (work_bound > P.work_cap) return fail(TSB_E_UNSUPPORTED, "assignment: work list too small");
   const size_t lds = (size_t)nchx * P.T * P.T * P.T * sizeof(unsigned long long);
   prof_begin(P, kStAssign, s);
-  hipLaunchKernelGGL((assign_tile_kernel<T, NCH>), dim3(ntiles), dim3(kBlock), lds, s, a, rec);
+  hipLaunchKernelGGL((assign_tile_kernel<T, NCH>), dim3((unsigned)work_bound), dim3(kBlock), lds, s, a, rec);
+  hipLaunchKernelGGL(heavy_final_kernel<T>, dim3(kMaxHeavy), dim3(kBlock), 0, s, a, (const int*)P.d_heavy_tile,
+                     (const int*)nheavy);
   if (!P.box_mode) {
     const double vc = P.L * P.L * P.L / ((double)P.N * P.N * P.N);
     hipLaunchKernelGGL(norm_final_kernel, dim3(1), dim3(kBlock), 0, s, (const double*)P.d_sum_partials,
@@ -917,8 +1071,9 @@ int run_assign(Plan& P, const tsb_catalog* data, const tsb_catalog* rand, hipStr
   const int64_t nbk = P.nbk;
   const int nparts = (int)((nbk + kScanChunk - 1) / kScanChunk);
   prof_begin(P, kStBucket, s);
-  // count and cursor are adjacent: one fill clears both
-  hipLaunchKernelGGL(zero_ints_kernel, dim3(grid_blocks(2 * nbk)), dim3(kBlock), 0, s, P.d_bk_count, 2 * nbk);
+  // counts, cursors and the heavy-slot counter are adjacent: one fill clears them
+  hipLaunchKernelGGL(zero_ints_kernel, dim3(grid_blocks(2 * nbk + 1)), dim3(kBlock), 0, s, P.d_bk_count,
+                     2 * nbk + 1);
   if (ntot > 0)
     hipLaunchKernelGGL(bucket_count_kernel, dim3(grid_blocks(ntot)), dim3(kBlock), 0, s, b);
   hipLaunchKernelGGL(scan_sums_kernel, dim3(nparts), dim3(kBlock), 0, s, (const int*)P.d_bk_count, nbk,

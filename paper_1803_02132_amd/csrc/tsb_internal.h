@@ -142,6 +142,13 @@ struct Plan {
   int* d_scan_part = nullptr;   // per-workgroup sums of the bucket scan
   int64_t nbk = 0;              // tiles * 27
   int* d_keys = nullptr;        // bucket key per particle
+  int* d_tile_parts = nullptr;  // work items per tile [ntiles]
+  int* d_tile_hslot = nullptr;  // heavy slot per tile or -1 [ntiles]
+  int* d_tile_pstart = nullptr; // first work item per tile [ntiles + 1]
+  int* d_heavy_tile = nullptr;  // tile of each heavy slot
+  void* d_heavy = nullptr;      // fixed-point sums of split tiles [slot][copies][nchx][T^3]
+  void* d_work = nullptr;       // work items (tile, part) [work_cap]
+  int64_t work_cap = 0;
   void* d_rec_u = nullptr;    // particle records in bucket order: u (3 x double)
   void* d_rec_c = nullptr;    //   and channel weights [nchx][cap] (plan precision)
   int64_t particle_cap = 0;
@@ -194,6 +201,9 @@ int run_reduce_final(Plan& P, hipStream_t s);
 void plan_fused(Plan& P);                   // fused.hip
 int run_fused(Plan& P, hipStream_t s);
 int run_ynode_fill(Plan& P, hipStream_t s);
+int64_t assign_work_cap(const Plan& P, int64_t particles);
+int64_t assign_heavy_bytes(const Plan& P);
+int assign_max_heavy();
 int run_unpack_grids(Plan& P, void* out, hipStream_t s);
 
 // ---------------------------------------------------------------------------
