@@ -477,6 +477,7 @@ __device__ inline void node_dir(const double* origin, double h, const double* ob
 
 constexpr int kVisitChunk = 128;  // particles staged in LDS at a time (two wavefronts stage them)
 constexpr int kPartVisits = 256;  // visits per work item; busier tiles are split
+constexpr int kTileGroups = 1024;  // workgroups of the tile kernel
 constexpr int kMaxHeavy = 2048;   // split tiles with a slot of their own (others run whole)
 
 // A staged particle for one grid copy: on each axis the stencil nodes that
@@ -502,6 +503,20 @@ __device__ inline long long to_fixed(double x) {
   }
 }
 
+// Fixed point back to the plan precision. FP32: the high word (|v| < 2^51, so
+// below 2^19) converts exactly and the low word rounds once more; FP64: exact
+// to one rounding.
+template <typename T>
+__device__ inline T from_fixed(long long v, double inv_scale) {
+  if constexpr (sizeof(T) == 4) {
+    const float s = (float)inv_scale;   // a power of two
+    const float hi = (float)(int)(v >> 32), lo = (float)(unsigned)(v & 0xffffffffLL);
+    return fmaf(hi, 4294967296.0f * s, lo * s);
+  } else {
+    return (double)v * inv_scale;
+  }
+}
+
 // One workgroup per T^3 tile, one grid copy at a time. The particles that
 // reach the tile are staged 64 at a time (stencil weights and in-tile node
 // offsets computed once per particle); then every (particle, in-tile x node,
@@ -516,19 +531,26 @@ __global__ void __launch_bounds__(kBlock) assign_tile_kernel(TileArgs a, Records
   __shared__ Visit<T, NCH> vis[kVisitChunk];
   __shared__ int it_first[kVisitChunk];      // first work item of each staged particle
   __shared__ int wtot[2];                     // items of each staging wavefront
+  __shared__ double wsum[kBlock / 64];
   __shared__ unsigned char it_vis[kVisitChunk * 9];
   const int TS = a.T, T3 = TS * TS * TS;
   const int nch = a.ci.nch;
   const int nchx = nch + (a.box_mode ? 0 : 1);
-  if ((int)blockIdx.x >= *a.nwork) return;   // the grid is an upper bound of the work items
-  const int2 wk = a.work[blockIdx.x];
-  const int tile = wk.x, part = wk.y;
+  const int nwork = *a.nwork;
+  const int N = a.N, p = a.p;
   const int NT = a.NT;
+  const int lane = threadIdx.x & 63;
+  T2* out = (T2*)a.out;
+  const size_t N3 = (size_t)N * N * N;
+  const int stride[3] = {TS * TS, TS, 1};
+  const double scale = a.scal->scale, inv_scale = a.scal->inv_scale;
+  for (int w = blockIdx.x; w < nwork; w += gridDim.x) {
+  const int2 wk = a.work[w];
+  const int tile = wk.x, part = wk.y;
   const int tx = tile / (NT * NT), ty = (tile / NT) % NT, tz = tile % NT;
   const int o3[3] = {tx * TS, ty * TS, tz * TS};
-  const int N = a.N, p = a.p;
-  const int lane = threadIdx.x & 63;
   const int hs = a.hslot[tile];   // >= 0: split tile, sums go to its heavy slot
+  __syncthreads();   // the previous work item is done with the LDS
   if (threadIdx.x < 64) {
     // bucket ranges to read, and their prefix over the first wavefront
     const int r = threadIdx.x;
@@ -543,7 +565,6 @@ __global__ void __launch_bounds__(kBlock) assign_tile_kernel(TileArgs a, Records
     r_off[r + 1] = inc;
     if (r == 0) r_off[0] = 0;
   }
-  const double scale = a.scal->scale, inv_scale = a.scal->inv_scale;
   __syncthreads();
   const int total = r_off[64];
   const int v0 = hs >= 0 ? part * kPartVisits : 0;
@@ -552,9 +573,6 @@ __global__ void __launch_bounds__(kBlock) assign_tile_kernel(TileArgs a, Records
   // spatially sorted input does not put neighbouring lanes on the same cells
   int64_t mult = 7919;
   if (total % 7919 == 0) mult = (total % 7927 == 0) ? 7933 : 7927;
-  T2* out = (T2*)a.out;
-  const size_t N3 = (size_t)N * N * N;
-  const int stride[3] = {TS * TS, TS, 1};
   double sumI = 0.0;
   for (int g = 0; g < a.copies; ++g) {
     const int nc = g == 0 ? nchx : nch;   // the survey randoms channel lives on copy 0 only
@@ -636,8 +654,7 @@ __global__ void __launch_bounds__(kBlock) assign_tile_kernel(TileArgs a, Records
 #pragma unroll
           for (int ch = 0; ch < NCH; ++ch) {
             if (ch >= nc) break;
-            const long long q = to_fixed<T>((double)V.c[ch] * Ws);
-            if (q != 0) atomicAdd(cellp + (size_t)ch * T3, (unsigned long long)q);
+            atomicAdd(cellp + (size_t)ch * T3, (unsigned long long)to_fixed<T>((double)V.c[ch] * Ws));
           }
         }
       }
@@ -660,8 +677,8 @@ __global__ void __launch_bounds__(kBlock) assign_tile_kernel(TileArgs a, Records
       for (int gr = 0; gr < a.ngrid; ++gr) {
         const int cre = a.gre[gr], cim = a.gim[gr];
         T2 o;
-        o.x = (T)((double)(long long)acc[(size_t)cre * T3 + cell] * inv_scale);
-        o.y = cim >= 0 ? (T)((double)(long long)acc[(size_t)cim * T3 + cell] * inv_scale) : (T)0;
+        o.x = from_fixed<T>((long long)acc[(size_t)cre * T3 + cell], inv_scale);
+        o.y = cim >= 0 ? from_fixed<T>((long long)acc[(size_t)cim * T3 + cell], inv_scale) : (T)0;
         out[((size_t)g * a.ngrid + gr) * N3 + lin] = o;
       }
       if (!a.box_mode && g == 0) {
@@ -673,15 +690,13 @@ __global__ void __launch_bounds__(kBlock) assign_tile_kernel(TileArgs a, Records
     __syncthreads();
   }
   if (!a.box_mode && hs < 0) {
-    __shared__ double sh[kBlock];
-    sh[threadIdx.x] = sumI;
+    // fixed-order sum: within each wavefront, then over the four wavefronts
+    for (int off = 32; off > 0; off >>= 1) sumI += __shfl_xor(sumI, off);
+    if (lane == 0) wsum[threadIdx.x >> 6] = sumI;
     __syncthreads();
-    for (int st = kBlock / 2; st > 0; st >>= 1) {
-      if (threadIdx.x < st) sh[threadIdx.x] += sh[threadIdx.x + st];
-      __syncthreads();
-    }
-    if (threadIdx.x == 0) a.tile_I[tile] = sh[0];
+    if (threadIdx.x == 0) a.tile_I[tile] = (wsum[0] + wsum[1]) + (wsum[2] + wsum[3]);
   }
+  }   // work items
 }
 
 // Split tiles: convert the summed fixed-point grids of each heavy slot.
@@ -1037,7 +1052,9 @@ int assign_impl(Plan& P, const BucketArgs& b, const ChanInfo& ci, hipStream_t s)
   if (work_bound > P.work_cap) return fail(TSB_E_UNSUPPORTED, "assignment: work list too small");
   const size_t lds = (size_t)nchx * P.T * P.T * P.T * sizeof(unsigned long long);
   prof_begin(P, kStAssign, s);
-  hipLaunchKernelGGL((assign_tile_kernel<T, NCH>), dim3((unsigned)work_bound), dim3(kBlock), lds, s, a, rec);
+  // persistent workgroups (about four per compute unit) walk the work items
+  const int wgs = (int)std::min<int64_t>(work_bound, kTileGroups);
+  hipLaunchKernelGGL((assign_tile_kernel<T, NCH>), dim3(wgs), dim3(kBlock), lds, s, a, rec);
   hipLaunchKernelGGL(heavy_final_kernel<T>, dim3(kMaxHeavy), dim3(kBlock), 0, s, a, (const int*)P.d_heavy_tile,
                      (const int*)nheavy);
   if (!P.box_mode) {
