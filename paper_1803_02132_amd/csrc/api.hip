@@ -119,7 +119,7 @@ void plan_free(Plan& P) {
   void* ptrs[] = {P.d_grid, P.d_t1, P.d_t2, P.d_t3, P.d_spec, P.d_dcube, P.d_u1, P.d_u2, P.d_fields,
                   P.d_tw_n, P.d_tw_m, P.d_bin_lut, P.d_fkinds, P.d_fcomp, P.d_gcomp, P.d_terms,
                   P.d_qgroups, P.d_outs, P.d_out_norm, P.d_partials, P.d_B, P.d_scal, P.d_sum_partials,
-                  P.d_bk_count, P.d_bk_start, P.d_scan_part, P.d_keys, P.d_rec_u, P.d_rec_c,
+                  P.d_bk_count, P.d_bk_start, P.d_scan_part, P.d_keys, P.d_rec,
                   P.d_f2idx, P.d_yspec, P.d_tile_parts, P.d_tile_hslot, P.d_tile_pstart, P.d_heavy_tile,
                   P.d_heavy, P.d_work};
   for (void* p : ptrs)
@@ -131,21 +131,18 @@ namespace {
 int ensure_particles(Plan& P, int64_t n) {
   if (n <= P.particle_cap) return TSB_OK;
   if (n > 2147483647LL) return fail(TSB_E_UNSUPPORTED, "more than 2^31-1 particles");
-  const int64_t nchx = (int64_t)P.chans.size() + (P.box_mode ? 0 : 1);
-  const int64_t esz = P.precision == TSB_FP64 ? 8 : 4;
-  const int64_t per = 4 + 24 + nchx * esz;   // key, u, channel weights
-  for (void* p : {(void*)P.d_keys, P.d_rec_u, P.d_rec_c, P.d_work})
+  const int64_t per = 4 + record_stride(P);   // key, record
+  for (void* p : {(void*)P.d_keys, P.d_rec, P.d_work})
     if (p) (void)hipFree(p);
   P.d_keys = nullptr;
-  P.d_rec_u = P.d_rec_c = P.d_work = nullptr;
+  P.d_rec = P.d_work = nullptr;
   P.bytes -= per * P.particle_cap + 8 * P.work_cap;
   P.particle_cap = P.work_cap = 0;
   const int64_t cap = std::max<int64_t>(n + n / 8, 1024);
   const int64_t wcap = assign_work_cap(P, cap);
   int rc;
   if ((rc = dalloc((void**)&P.d_keys, cap * 4, P.bytes, false))) return rc;
-  if ((rc = dalloc(&P.d_rec_u, cap * 24, P.bytes, false))) return rc;
-  if ((rc = dalloc(&P.d_rec_c, cap * nchx * esz, P.bytes, false))) return rc;
+  if ((rc = dalloc(&P.d_rec, cap * record_stride(P), P.bytes, false))) return rc;
   if ((rc = dalloc(&P.d_work, wcap * 8, P.bytes, false))) return rc;
   P.particle_cap = cap;
   P.work_cap = wcap;

@@ -360,15 +360,16 @@ __device__ inline void channel_values(const ChanInfo& ci, double x, double y, do
   }
 }
 
-// Particle records in bucket order: grid coordinate u (FP64; NaN marks a
-// particle that takes no part) and its channel weights.
+// Particle records in bucket order, one contiguous record each: the grid
+// coordinate u (3 FP64; NaN in u_x marks a particle that takes no part), then
+// its channel weights in the plan precision; stride a multiple of 16 bytes.
 template <typename T>
 struct Records {
-  double* ux;
-  double* uy;
-  double* uz;
-  T* cv;                       // [nchx][cap]
+  char* base;
+  int stride;
   int64_t cap;
+  __device__ double* u(int64_t slot) const { return (double*)(base + slot * stride); }
+  __device__ T* c(int64_t slot) const { return (T*)(base + slot * stride + 24); }
 };
 
 template <typename T, int NCH>
@@ -402,14 +403,15 @@ __global__ void __launch_bounds__(kBlock) bucket_fill_kernel(FillArgs<T, NCH> a)
     const bool ok = particle_u(a.b, i, u, &w, &ran);
     const CatPtrs& c = ran ? a.b.r : a.b.d;
     const int64_t j = ran ? i - a.b.d.n : i;
-    a.rec.ux[slot] = ok ? u[0] : NAN;
-    a.rec.uy[slot] = u[1];
-    a.rec.uz[slot] = u[2];
+    double* ru = a.rec.u(slot);
+    ru[0] = ok ? u[0] : NAN;
+    ru[1] = u[1];
+    ru[2] = u[2];
     double cv[NCH];
     channel_values<NCH>(a.ci, c.x[j], c.y[j], c.z[j], ok ? w : 0.0, ran, alpha, cv);
 #pragma unroll
     for (int ch = 0; ch < NCH; ++ch)
-      if (ch < a.nchx) a.rec.cv[(int64_t)ch * a.rec.cap + slot] = (T)cv[ch];
+      if (ch < a.nchx) a.rec.c(slot)[ch] = (T)cv[ch];
   }
 }
 
@@ -477,16 +479,18 @@ __device__ inline void node_dir(const double* origin, double h, const double* ob
 
 constexpr int kVisitChunk = 128;  // particles staged in LDS at a time (two wavefronts stage them)
 constexpr int kPartVisits = 256;  // visits per work item; busier tiles are split
-constexpr int kTileGroups = 1024;  // workgroups of the tile kernel
+constexpr int kTileBlock = 256;    // threads per workgroup of the tile kernel
 constexpr int kMaxHeavy = 2048;   // split tiles with a slot of their own (others run whole)
 
 // A staged particle for one grid copy: on each axis the stencil nodes that
 // fall inside the tile, as weights and offsets into the tile's cell index,
-// and its channel weights (plan precision).
+// and its channel weights (plan precision). A work item is one (particle,
+// in-tile x node): it adds the particle's contributions to the in-tile (y, z)
+// nodes of that plane.
 template <typename T, int NCH>
-struct Visit {
-  T w[3][3];
+struct alignas(16) Visit {
   T c[NCH];
+  T w[3][3];
   short off[3][3];
   unsigned char cnt[3];
 };
@@ -517,13 +521,14 @@ __device__ inline T from_fixed(long long v, double inv_scale) {
   }
 }
 
-// One workgroup per T^3 tile, one grid copy at a time. The particles that
-// reach the tile are staged 64 at a time (stencil weights and in-tile node
-// offsets computed once per particle); then every (particle, in-tile x node,
-// in-tile y node) is one work item over all lanes, which adds the particle's
-// fixed-point contribution to each in-tile z node and every channel.
+// Persistent workgroups walk the work items (a tile, or a part of a busy
+// tile), one grid copy at a time. The particles that reach the tile are staged
+// 128 at a time (stencil weights and in-tile node offsets computed once per
+// particle); then every (particle, in-tile x node) is one work item over all
+// lanes, which adds the particle's fixed-point contributions to each in-tile
+// (y, z) node of that plane and every channel.
 template <typename T, int NCH>
-__global__ void __launch_bounds__(kBlock) assign_tile_kernel(TileArgs a, Records<T> rec) {
+__global__ void __launch_bounds__(kTileBlock) assign_tile_kernel(TileArgs a, Records<T> rec) {
   typedef typename cplx<T>::type T2;
   extern __shared__ unsigned long long acc[];   // [nchx][T^3], one grid copy
   __shared__ int r_start[kMaxRanges];
@@ -531,8 +536,9 @@ __global__ void __launch_bounds__(kBlock) assign_tile_kernel(TileArgs a, Records
   __shared__ Visit<T, NCH> vis[kVisitChunk];
   __shared__ int it_first[kVisitChunk];      // first work item of each staged particle
   __shared__ int wtot[2];                     // items of each staging wavefront
-  __shared__ double wsum[kBlock / 64];
-  __shared__ unsigned char it_vis[kVisitChunk * 9];
+  __shared__ double wsum[kTileBlock / 64];
+  __shared__ int item[3];                     // tile, part, heavy slot of the current work item
+  __shared__ unsigned char it_vis[kVisitChunk * 3];
   const int TS = a.T, T3 = TS * TS * TS;
   const int nch = a.ci.nch;
   const int nchx = nch + (a.box_mode ? 0 : 1);
@@ -544,39 +550,50 @@ __global__ void __launch_bounds__(kBlock) assign_tile_kernel(TileArgs a, Records
   const size_t N3 = (size_t)N * N * N;
   const int stride[3] = {TS * TS, TS, 1};
   const double scale = a.scal->scale, inv_scale = a.scal->inv_scale;
+  // ranges of a work item, one per lane of the first wavefront, loaded one
+  // item ahead so that their latency overlaps the current item
+  int pf_tile = 0, pf_hs = -1, pf_part = 0, pf_st = 0, pf_len = 0;
+  auto fetch = [&](int w) {
+    if (threadIdx.x < 64 && w < nwork) {
+      const int2 wk = a.work[w];
+      pf_tile = wk.x;
+      pf_part = wk.y;
+      pf_hs = a.hslot[wk.x];
+      pf_st = 0;
+      pf_len = 0;
+      if (lane < a.nr) tile_range(a, wk.x, lane, &pf_st, &pf_len);
+    }
+  };
+  fetch(blockIdx.x);
   for (int w = blockIdx.x; w < nwork; w += gridDim.x) {
-  const int2 wk = a.work[w];
-  const int tile = wk.x, part = wk.y;
-  const int tx = tile / (NT * NT), ty = (tile / NT) % NT, tz = tile % NT;
-  const int o3[3] = {tx * TS, ty * TS, tz * TS};
-  const int hs = a.hslot[tile];   // >= 0: split tile, sums go to its heavy slot
   __syncthreads();   // the previous work item is done with the LDS
   if (threadIdx.x < 64) {
-    // bucket ranges to read, and their prefix over the first wavefront
-    const int r = threadIdx.x;
-    int st = 0, len = 0;
-    if (r < a.nr) tile_range(a, tile, r, &st, &len);
-    int inc = len;
+    int inc = pf_len;
     for (int off = 1; off < 64; off <<= 1) {
       const int x = __shfl_up(inc, off);
-      if (r >= off) inc += x;
+      if (lane >= off) inc += x;
     }
-    r_start[r] = st;
-    r_off[r + 1] = inc;
-    if (r == 0) r_off[0] = 0;
+    r_start[lane] = pf_st;
+    r_off[lane + 1] = inc;
+    if (lane == 0) {
+      r_off[0] = 0;
+      item[0] = pf_tile;
+      item[1] = pf_part;
+      item[2] = pf_hs;
+    }
   }
+  fetch(w + gridDim.x);
   __syncthreads();
+  const int tile = item[0], part = item[1], hs = item[2];   // hs >= 0: split tile, sums go to its slot
+  const int tx = tile / (NT * NT), ty = (tile / NT) % NT, tz = tile % NT;
+  const int o3[3] = {tx * TS, ty * TS, tz * TS};
   const int total = r_off[64];
   const int v0 = hs >= 0 ? part * kPartVisits : 0;
   const int v1 = hs >= 0 ? min(total, v0 + kPartVisits) : total;
-  // staging order scrambled by a multiplier prime to the total, so that
-  // spatially sorted input does not put neighbouring lanes on the same cells
-  int64_t mult = 7919;
-  if (total % 7919 == 0) mult = (total % 7927 == 0) ? 7933 : 7927;
   double sumI = 0.0;
   for (int g = 0; g < a.copies; ++g) {
     const int nc = g == 0 ? nchx : nch;   // the survey randoms channel lives on copy 0 only
-    for (int i = threadIdx.x; i < nchx * T3; i += kBlock) acc[i] = 0ull;
+    for (int i = threadIdx.x; i < nchx * T3; i += kTileBlock) acc[i] = 0ull;
     for (int c0 = v0; c0 < v1; c0 += kVisitChunk) {
       const int nv = min(kVisitChunk, v1 - c0);
       __syncthreads();   // acc cleared / previous chunk consumed
@@ -585,7 +602,7 @@ __global__ void __launch_bounds__(kBlock) assign_tile_kernel(TileArgs a, Records
         // two wavefronts: one particle per lane, then per-wavefront item prefixes
         const int v = threadIdx.x;
         if (v < nv) {
-          const int idx = (int)(((int64_t)(c0 + v) * mult) % total);
+          const int idx = c0 + v;   // bucket order: neighbouring lanes read neighbouring records
           int lo = 0, hi = a.nr;   // r_off[lo] <= idx < r_off[hi]
           while (hi - lo > 1) {
             const int mid = (lo + hi) >> 1;
@@ -593,10 +610,12 @@ __global__ void __launch_bounds__(kBlock) assign_tile_kernel(TileArgs a, Records
             else hi = mid;
           }
           const int64_t slot = r_start[lo] + (idx - r_off[lo]);
-          const double u[3] = {rec.ux[slot], rec.uy[slot], rec.uz[slot]};
+          const double* ru = rec.u(slot);
+          const double u[3] = {ru[0], ru[1], ru[2]};
+          const T* rc = rec.c(slot);
           T cv[NCH];
 #pragma unroll
-          for (int ch = 0; ch < NCH; ++ch) cv[ch] = ch < nc ? rec.cv[(int64_t)ch * rec.cap + slot] : (T)0;
+          for (int ch = 0; ch < NCH; ++ch) cv[ch] = ch < nc ? rc[ch] : (T)0;
           Visit<T, NCH>& V = vis[v];
           int cnt[3] = {0, 0, 0};
           if (isfinite(u[0])) {
@@ -621,7 +640,7 @@ __global__ void __launch_bounds__(kBlock) assign_tile_kernel(TileArgs a, Records
           V.cnt[0] = (unsigned char)cnt[0];
           V.cnt[1] = (unsigned char)cnt[1];
           V.cnt[2] = (unsigned char)cnt[2];
-          items = cnt[0] * cnt[1];
+          items = cnt[0];
         }
         inc = items;
         for (int off = 1; off < 64; off <<= 1) {
@@ -640,21 +659,45 @@ __global__ void __launch_bounds__(kBlock) assign_tile_kernel(TileArgs a, Records
       }
       const int nitems = wtot[0] + wtot[1];
       __syncthreads();
-      for (int it = threadIdx.x; it < nitems; it += kBlock) {
+      // items in a scrambled order (multiplier prime to their number), so that
+      // the lanes of a wavefront work on particles far apart in the chunk
+      const int imult = nitems % 97 ? 97 : (nitems % 101 ? 101 : 103);
+      for (int i0 = threadIdx.x; i0 < nitems; i0 += kTileBlock) {
+        const int it = (i0 * imult) % nitems;
         const int vi = it_vis[it];
         const Visit<T, NCH>& V = vis[vi];
-        const int loc = it - it_first[vi];
-        const int cy = V.cnt[1];
-        const int sx = loc / cy, sy = loc - sx * cy;
-        const T wxy = V.w[0][sx] * V.w[1][sy];
-        const int base = V.off[0][sx] + V.off[1][sy];
-        for (int sz = 0; sz < V.cnt[2]; ++sz) {
-          const double Ws = (double)(wxy * V.w[2][sz]) * scale;
-          unsigned long long* cellp = acc + base + V.off[2][sz];
+        // the particle's data to registers once (the atomics below may alias it)
+        T c[NCH];
 #pragma unroll
-          for (int ch = 0; ch < NCH; ++ch) {
-            if (ch >= nc) break;
-            atomicAdd(cellp + (size_t)ch * T3, (unsigned long long)to_fixed<T>((double)V.c[ch] * Ws));
+        for (int ch = 0; ch < NCH; ++ch) c[ch] = V.c[ch];
+        const int sx = it - it_first[vi];
+        const int cy = V.cnt[1], cz = V.cnt[2];
+        const T wx = V.w[0][sx];
+        const int ox = V.off[0][sx];
+        T wy[3], wz[3];
+        int oy[3], oz[3];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+          wy[k] = V.w[1][k];
+          oy[k] = V.off[1][k];
+          wz[k] = V.w[2][k];
+          oz[k] = V.off[2][k];
+        }
+#pragma unroll
+        for (int sy = 0; sy < 3; ++sy) {
+          if (sy >= cy) break;
+          const T wxy = wx * wy[sy];
+          const int base = ox + oy[sy];
+#pragma unroll
+          for (int sz = 0; sz < 3; ++sz) {
+            if (sz >= cz) break;
+            const double Ws = (double)(wxy * wz[sz]) * scale;
+            unsigned long long* cellp = acc + base + oz[sz];
+#pragma unroll
+            for (int ch = 0; ch < NCH; ++ch) {
+              if (ch >= nc) break;
+              atomicAdd(cellp + (size_t)ch * T3, (unsigned long long)to_fixed<T>((double)c[ch] * Ws));
+            }
           }
         }
       }
@@ -663,7 +706,7 @@ __global__ void __launch_bounds__(kBlock) assign_tile_kernel(TileArgs a, Records
     if (hs >= 0) {
       // part of a split tile: add the fixed-point sums into its slot (integer, order-free)
       unsigned long long* hb = a.heavy + ((size_t)hs * a.copies + g) * nchx * T3;
-      for (int i = threadIdx.x; i < nc * T3; i += kBlock) {
+      for (int i = threadIdx.x; i < nc * T3; i += kTileBlock) {
         const unsigned long long v = acc[i];
         if (v != 0ull) atomicAdd(hb + i, v);
       }
@@ -671,7 +714,7 @@ __global__ void __launch_bounds__(kBlock) assign_tile_kernel(TileArgs a, Records
       continue;
     }
     // write out this copy
-    for (int cell = threadIdx.x; cell < T3; cell += kBlock) {
+    for (int cell = threadIdx.x; cell < T3; cell += kTileBlock) {
       const int lx = cell / (TS * TS), ly = (cell / TS) % TS, lz = cell % TS;
       const size_t lin = ((size_t)(o3[0] + lx) * N + (o3[1] + ly)) * N + (o3[2] + lz);
       for (int gr = 0; gr < a.ngrid; ++gr) {
@@ -694,7 +737,11 @@ __global__ void __launch_bounds__(kBlock) assign_tile_kernel(TileArgs a, Records
     for (int off = 32; off > 0; off >>= 1) sumI += __shfl_xor(sumI, off);
     if (lane == 0) wsum[threadIdx.x >> 6] = sumI;
     __syncthreads();
-    if (threadIdx.x == 0) a.tile_I[tile] = (wsum[0] + wsum[1]) + (wsum[2] + wsum[3]);
+    if (threadIdx.x == 0) {
+      double t = 0.0;
+      for (int i = 0; i < kTileBlock / 64; ++i) t += wsum[i];
+      a.tile_I[tile] = t;
+    }
   }
   }   // work items
 }
@@ -917,6 +964,12 @@ int run_prep(Plan& P, const tsb_catalog* data, const tsb_catalog* rand, hipStrea
   return TSB_OK;
 }
 
+int record_stride(const Plan& P) {
+  const int nchx = (int)P.chans.size() + (P.box_mode ? 0 : 1);
+  const int esz = P.precision == TSB_FP64 ? 8 : 4;
+  return (24 + nchx * esz + 15) / 16 * 16;
+}
+
 int64_t assign_work_cap(const Plan& P, int64_t particles) {
   const int64_t ntiles = (int64_t)P.NT * P.NT * P.NT;
   return ntiles + (8 * particles + kPartVisits - 1) / kPartVisits + 1;
@@ -988,10 +1041,8 @@ int assign_impl(Plan& P, const BucketArgs& b, const ChanInfo& ci, hipStream_t s)
   const int nchx = ci.nch + (P.box_mode ? 0 : 1);
   Records<T> rec;
   rec.cap = P.particle_cap;
-  rec.ux = (double*)P.d_rec_u;
-  rec.uy = rec.ux + rec.cap;
-  rec.uz = rec.uy + rec.cap;
-  rec.cv = (T*)P.d_rec_c;
+  rec.base = (char*)P.d_rec;
+  rec.stride = record_stride(P);
   if (ntot > 0) {
     FillArgs<T, NCH> f;
     f.b = b;
@@ -1052,9 +1103,17 @@ int assign_impl(Plan& P, const BucketArgs& b, const ChanInfo& ci, hipStream_t s)
   if (work_bound > P.work_cap) return fail(TSB_E_UNSUPPORTED, "assignment: work list too small");
   const size_t lds = (size_t)nchx * P.T * P.T * P.T * sizeof(unsigned long long);
   prof_begin(P, kStAssign, s);
-  // persistent workgroups (about four per compute unit) walk the work items
-  const int wgs = (int)std::min<int64_t>(work_bound, kTileGroups);
-  hipLaunchKernelGGL((assign_tile_kernel<T, NCH>), dim3(wgs), dim3(kBlock), lds, s, a, rec);
+  // persistent workgroups, as many as are resident at once, walk the work items
+  if (P.tile_wgs <= 0) {
+    int per_cu = 0, dev = 0, n_cu = 0;
+    TSB_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)assign_tile_kernel<T, NCH>,
+                                                         kTileBlock, lds));
+    TSB_HIP(hipGetDevice(&dev));
+    TSB_HIP(hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev));
+    P.tile_wgs = std::max(1, per_cu) * std::max(1, n_cu);
+  }
+  const int wgs = (int)std::min<int64_t>(work_bound, P.tile_wgs);
+  hipLaunchKernelGGL((assign_tile_kernel<T, NCH>), dim3(wgs), dim3(kTileBlock), lds, s, a, rec);
   hipLaunchKernelGGL(heavy_final_kernel<T>, dim3(kMaxHeavy), dim3(kBlock), 0, s, a, (const int*)P.d_heavy_tile,
                      (const int*)nheavy);
   if (!P.box_mode) {

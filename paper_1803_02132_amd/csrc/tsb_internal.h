@@ -149,8 +149,8 @@ struct Plan {
   void* d_heavy = nullptr;      // fixed-point sums of split tiles [slot][copies][nchx][T^3]
   void* d_work = nullptr;       // work items (tile, part) [work_cap]
   int64_t work_cap = 0;
-  void* d_rec_u = nullptr;    // particle records in bucket order: u (3 x double)
-  void* d_rec_c = nullptr;    //   and channel weights [nchx][cap] (plan precision)
+  int tile_wgs = 0;             // resident workgroups of the tile kernel (from the occupancy query)
+  void* d_rec = nullptr;      // particle records in bucket order (u, channel weights), [cap][stride]
   int64_t particle_cap = 0;
   int red_chunk = 64, red_wg = 1024;
   int64_t bytes = 0;
@@ -202,6 +202,7 @@ void plan_fused(Plan& P);                   // fused.hip
 int run_fused(Plan& P, hipStream_t s);
 int run_ynode_fill(Plan& P, hipStream_t s);
 int64_t assign_work_cap(const Plan& P, int64_t particles);
+int record_stride(const Plan& P);
 int64_t assign_heavy_bytes(const Plan& P);
 int assign_max_heavy();
 int run_unpack_grids(Plan& P, void* out, hipStream_t s);
