@@ -17,7 +17,7 @@ decomposition formalism for the redshift-space bispectrum" (arXiv:1803.02132):
                    triangle sum that the FFT form rewrites (Sec. 4.2, eq. 35).
 
 Every function states the passage it follows. Readings of passages that are
-silent or ambiguous are listed (R1..R16) in ``estimator``'s header.
+silent or ambiguous are listed (R1..R11) in ``estimator``'s header.
 
 Parity status per function is stated in each module header; every function is
 pinned by a ``-m "not gpu"`` test against closed forms, library routines,
