@@ -87,6 +87,95 @@ def load_traffic(stage, bytes_alg):
     return rec.get("hbm_bytes_per_launch")
 
 
+COPY_PROBE_BYTES = 512 << 20
+# stage -> kernels whose dispatches make up one launch of the stage
+STAGE_KERNELS = {"assign": ("assign_tile_kernel", "heavy_final_kernel"),
+                 "reduce": ("fz_reduce_wide_kernel", "fz_reduce_kernel", "reduce_kernel")}
+# order of the FFT-pass dispatches inside one measurement (fused plan)
+FFT_ORDER = ["fwd_z", "fwd_y", "fwd_x", "invG_x", "invG_y", "invG_z", "invF_x", "invF_y"]
+
+
+def copy_probe(reps=3):
+    """A plain device-to-device copy of COPY_PROBE_BYTES, whose HBM byte counters
+    calibrate those of the path's kernels (read and write once each)."""
+    import torch
+    src = torch.ones(COPY_PROBE_BYTES // 4, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(reps):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    log(f"copy probe: {reps} x {COPY_PROBE_BYTES} B device-to-device")
+
+
+def _read_counters(path):
+    import csv
+    rows = {}
+    with open(path) as fh:
+        for r in csv.DictReader(fh):
+            d = int(r["Dispatch_Id"])
+            rows.setdefault(d, [r["Kernel_Name"], 0.0])
+            rows[d][1] += float(r["Counter_Value"])
+    return [(d, rows[d][0], rows[d][1]) for d in sorted(rows)]
+
+
+def ingest_pmc(fetch_csv, write_csv, command):
+    """Turn two rocprofv3 --pmc runs (FETCH_SIZE, then WRITE_SIZE, KiB per
+    dispatch) of `bench.py --copy-probe` into profiles/traffic_<stage>.json:
+    HBM bytes per launch of each stage, each counter divided by what it reads
+    for the copy probe relative to the probe's true bytes."""
+    out = {}
+    for label, path in (("fetch", fetch_csv), ("write", write_csv)):
+        disp = _read_counters(path)
+        probe = [v for (_, k, v) in disp if "copyBuffer" in k and v * 1024 > 0.5 * COPY_PROBE_BYTES]
+        if not probe:
+            raise SystemExit(f"no copy-probe dispatch in {path}")
+        factor = (sum(probe) / len(probe)) * 1024 / COPY_PROBE_BYTES
+        starts = [i for i, (_, k, _) in enumerate(disp) if "prep_kernel" in k]
+        per = {}
+        n_meas = len(starts)
+        for j, s0 in enumerate(starts):
+            s1 = starts[j + 1] if j + 1 < len(starts) else len(disp)
+            ffts = [v for (_, k, v) in disp[s0:s1] if "fft4_kernel" in k or "fft_pass_kernel" in k]
+            for name, v in zip(FFT_ORDER, ffts):
+                per[name] = per.get(name, 0.0) + v
+            for stage, names in STAGE_KERNELS.items():
+                per[stage] = per.get(stage, 0.0) + sum(v for (_, k, v) in disp[s0:s1] if any(n in k for n in names))
+        out[label] = {st: (v / n_meas) * 1024 / factor for st, v in per.items()}
+        out[label + "_factor"] = factor
+    os.makedirs(os.path.join(ROOT, "profiles"), exist_ok=True)
+    for st in out["fetch"]:
+        src = KERNEL_SOURCES.get(st)
+        rec = {"stage": st, "fetch_bytes_per_launch": round(out["fetch"][st]),
+               "write_bytes_per_launch": round(out["write"].get(st, 0.0)),
+               "hbm_bytes_per_launch": round(out["fetch"][st] + out["write"].get(st, 0.0)),
+               "calibration": {"copy_probe_bytes": COPY_PROBE_BYTES, "fetch_counter_per_true_byte": out["fetch_factor"],
+                               "write_counter_per_true_byte": out["write_factor"]},
+               "source_sha256_16": source_hash(src) if src else None, "command": command}
+        with open(os.path.join(ROOT, "profiles", f"traffic_{st}.json"), "w") as fh:
+            json.dump(rec, fh, indent=1)
+        print(json.dumps(rec))
+
+
+def summarize_trace(stats_csv, command, out_name):
+    """A short text summary of a rocprofv3 --kernel-trace --stats run."""
+    import csv
+    with open(stats_csv) as fh:
+        rows = list(csv.DictReader(fh))
+    lines = [f"# Kernel statistics: {out_name}", "", "Command:", "", "    " + command, "",
+             "| kernel | calls | mean (us) | total (%) |", "|---|---|---|---|"]
+    for r in rows:
+        name = r["Name"]
+        short = name.split("(")[0].replace("tsb::", "").replace("(anonymous namespace)::", "")
+        if "<" in name.split("(")[0]:
+            short = name[:name.index(">") + 1].replace("void ", "").replace("tsb::", "").replace(
+                "(anonymous namespace)::", "")
+        lines.append(f"| `{short}` | {r['Calls']} | {float(r['AverageNs']) / 1e3:.1f} | {float(r['Percentage']):.2f} |")
+    os.makedirs(os.path.join(ROOT, "profiles"), exist_ok=True)
+    with open(os.path.join(ROOT, "profiles", out_name + ".md"), "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+    print("\n".join(lines))
+
+
 def cpu_baseline(cat, threads=1):
     """The FP64 oracle on a bounded sample of one mock, scaled to one mock.
 
@@ -145,7 +234,19 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--unfused", action="store_true",
                     help="write the F fields to HBM and reduce in a separate pass (diagnostic)")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="also run a device copy of known size (calibrates HBM byte counters)")
+    ap.add_argument("--ingest-pmc", nargs=3, metavar=("FETCH_CSV", "WRITE_CSV", "COMMAND"),
+                    help="write profiles/traffic_<stage>.json from two rocprofv3 --pmc runs and exit")
+    ap.add_argument("--summarize-trace", nargs=3, metavar=("STATS_CSV", "COMMAND", "NAME"),
+                    help="write profiles/NAME.md from a rocprofv3 kernel-stats CSV and exit")
     args = ap.parse_args()
+    if args.ingest_pmc:
+        ingest_pmc(*args.ingest_pmc)
+        return
+    if args.summarize_trace:
+        summarize_trace(*args.summarize_trace)
+        return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the path shards by mock "
               "across GPUs without communication, see DESIGN.md", file=sys.stderr)
@@ -167,6 +268,8 @@ def main():
     info = plan.info
     log(f"plan: N={info.n} M={info.m} r_f={info.r_f} r_g={info.r_g} outputs={info.n_outputs} "
         f"workspace={info.workspace_bytes / 1e9:.2f} GB")
+    if args.copy_probe:
+        copy_probe()
     for i in range(args.warmup):
         plan.measure(devs[i % len(devs)])
     tsb.abi.tsb_plan_set_profiling(plan.handle, True)

@@ -10,6 +10,13 @@ LIB_PATH = os.path.join(_HERE, "libtriposh.so")
 if not os.path.exists(LIB_PATH):
     raise ImportError(f"{LIB_PATH} is missing: build it with __graft_entry__.build() "
                       "(or python -m paper_1803_02132_amd.build)")
+# One HIP runtime per process. torch ships its own libamdhip64 whose file name
+# (libamdhip64.so) differs from the soname the library asks for
+# (libamdhip64.so.7): with torch loaded first the library binds to torch's
+# runtime; loaded first itself, it would pull in a second runtime that does not
+# see the device torch initialises. So torch is imported before the library.
+import torch  # noqa: E402,F401
+
 _lib = ctypes.CDLL(LIB_PATH)
 
 TSB_OK, TSB_E_ARG, TSB_E_UNSUPPORTED, TSB_E_NOMEM, TSB_E_INPUT, TSB_E_DEVICE = 0, -1, -2, -3, -4, -5

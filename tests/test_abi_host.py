@@ -122,3 +122,11 @@ def test_every_table1_multipole_accepted():
                 except tsb.TsbError:
                     accepted = False
                 assert accepted == ok, (l1, l2, L)
+
+
+def test_single_hip_runtime_in_process():
+    # the binding must bind the library to torch's HIP runtime: two runtimes in
+    # one process do not share devices
+    maps = open("/proc/self/maps").read()
+    paths = {line.split()[-1] for line in maps.splitlines() if "libamdhip64" in line}
+    assert len(paths) == 1, paths
