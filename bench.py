@@ -154,6 +154,16 @@ def ingest_pmc(fetch_csv, write_csv, command):
         with open(os.path.join(ROOT, "profiles", f"traffic_{st}.json"), "w") as fh:
             json.dump(rec, fh, indent=1)
         print(json.dumps(rec))
+    # human-readable table beside the JSON records
+    lines = ["# HBM traffic per stage launch: 256^3 throughput mocks", "", "Command:", "", "    " + command, "",
+             f"Calibration: a {COPY_PROBE_BYTES} B device copy reads FETCH_SIZE x {out['fetch_factor']:.3f} and "
+             f"WRITE_SIZE x {out['write_factor']:.3f} of its true bytes; counts below are divided by these.", "",
+             "| stage | fetch (MB) | write (MB) | total (MB) |", "|---|---|---|---|"]
+    for st in out["fetch"]:
+        f, w = out["fetch"][st], out["write"].get(st, 0.0)
+        lines.append(f"| {st} | {f / 1e6:.1f} | {w / 1e6:.1f} | {(f + w) / 1e6:.1f} |")
+    with open(os.path.join(ROOT, "profiles", "traffic_box256.md"), "w") as fh:
+        fh.write("\n".join(lines) + "\n")
 
 
 def summarize_trace(stats_csv, command, out_name):
@@ -164,11 +174,8 @@ def summarize_trace(stats_csv, command, out_name):
     lines = [f"# Kernel statistics: {out_name}", "", "Command:", "", "    " + command, "",
              "| kernel | calls | mean (us) | total (%) |", "|---|---|---|---|"]
     for r in rows:
-        name = r["Name"]
-        short = name.split("(")[0].replace("tsb::", "").replace("(anonymous namespace)::", "")
-        if "<" in name.split("(")[0]:
-            short = name[:name.index(">") + 1].replace("void ", "").replace("tsb::", "").replace(
-                "(anonymous namespace)::", "")
+        name = r["Name"].replace("(anonymous namespace)::", "").replace("tsb::", "").replace("void ", "")
+        short = name.split("(")[0]
         lines.append(f"| `{short}` | {r['Calls']} | {float(r['AverageNs']) / 1e3:.1f} | {float(r['Percentage']):.2f} |")
     os.makedirs(os.path.join(ROOT, "profiles"), exist_ok=True)
     with open(os.path.join(ROOT, "profiles", out_name + ".md"), "w") as fh:
