@@ -51,7 +51,9 @@ typedef enum {
   TSB_E_NOMEM = -3,        /* device allocation failed */
   TSB_E_INPUT = -4,        /* bad particle data: NaN/Inf position or weight,
                               survey particle outside the box, particle on the observer */
-  TSB_E_DEVICE = -5        /* a HIP call failed */
+  TSB_E_DEVICE = -5,       /* a HIP call failed */
+  TSB_E_BUSY = -6,         /* server: request not finished yet */
+  TSB_E_CANCELLED = -7     /* server: request dropped when the server was destroyed */
 } tsb_status;
 
 enum { TSB_LOS_GLOBAL = 0, TSB_LOS_LOCAL = 1 };
@@ -197,6 +199,56 @@ int tsb_plan_channel(const tsb_plan* plan, int32_t c, int32_t* L, int32_t* M, in
  * be NULL) and, with reset != 0, clears the accumulators. */
 int tsb_plan_set_profiling(tsb_plan* plan, int32_t enable);
 int tsb_plan_stage_times(tsb_plan* plan, int32_t n, double* ms, int64_t* calls, int32_t reset);
+
+/* Many catalogues in one call (the batched form of eq. 41 over independent
+ * mock catalogues, as in the paper's mock campaigns, Sec. 4.4). Item i measures
+ * data[i] (and randoms[i] in survey mode; randoms may be NULL in box mode)
+ * with plans[i] and writes B_out[i] ([n_mult][n_bins][n_bins], NaN where no
+ * pair is computed), I_out[i] and alpha_out[i] (either array may be NULL).
+ * Items that share a plan run one after another on that plan's own stream;
+ * different plans run concurrently on their own streams, so mocks of
+ * different grid sizes overlap on the device. The batch starts after the work
+ * already enqueued on `stream`, later work on `stream` waits for it, and the
+ * call returns when every result is on the host. Each item's result equals
+ * tsb_measure on the same inputs (bitwise). Errors: as tsb_measure (first error
+ * wins; results of other items are then unspecified). */
+int tsb_measure_batch(tsb_plan* const* plans, const tsb_catalog* const* data,
+                      const tsb_catalog* const* randoms, int32_t n, void* stream,
+                      double* const* B_out, double* I_out, double* alpha_out);
+
+/* Replay the fixed-shape part of a measurement (assignment tiles, transforms,
+ * reduction) as a HIP graph captured once per plan and particle capacity
+ * (default on; stage profiling always launches kernels directly). */
+int tsb_plan_set_graphs(tsb_plan* plan, int32_t enable);
+
+/* Serving: a request loop that admits measurements as they arrive.
+ * tsb_server_create starts a worker thread bound to the current device that
+ * runs up to max_slots measurements at once, each on its own stream and its
+ * own plan workspace, and keeps the plans of recently served geometries
+ * resident. A request is admitted when a slot is free and the HBM footprint of
+ * its workspace and particle buffers fits in hbm_budget_bytes together with
+ * every resident workspace (idle workspaces of other geometries are released
+ * to make room); requests are admitted in arrival order, except that a later
+ * request whose geometry already has an idle workspace may start while an
+ * earlier one waits for memory. Results are bitwise those of tsb_measure on
+ * the same inputs, alone or in any mix.
+ *   tsb_server_submit: `plan` is a template (only its request is used; it is
+ *     not touched by the server and may be destroyed after the call); data /
+ *     randoms point to caller-owned device arrays that must stay valid, and
+ *     B_out to caller-owned host memory that must not be read, until the
+ *     request is done. Returns a ticket (> 0).
+ *   tsb_server_poll: done = 1 when finished; latency_s = submit-to-finish
+ *     wall time; returns the request's status (TSB_OK, or its error) once done,
+ *     TSB_OK while running, TSB_E_ARG for an unknown ticket.
+ *   tsb_server_wait: blocks until the ticket is done, then as poll.
+ *   tsb_server_destroy: finishes running requests, cancels queued ones
+ *     (their status becomes TSB_E_CANCELLED) and frees every workspace. */
+int tsb_server_create(int64_t hbm_budget_bytes, int32_t max_slots, void** server);
+int tsb_server_submit(void* server, const tsb_plan* plan, const tsb_catalog* data,
+                      const tsb_catalog* randoms, double* B_out, int64_t* ticket);
+int tsb_server_poll(void* server, int64_t ticket, int32_t* done, double* latency_s);
+int tsb_server_wait(void* server, int64_t ticket, double* latency_s);
+int tsb_server_destroy(void* server);
 
 const char* tsb_last_error(void);
 

@@ -11,7 +11,7 @@ import numpy as np
 from . import abi
 from .abi import TsbError
 
-__all__ = ["Plan", "TsbError", "abi", "catalog_to_device"]
+__all__ = ["Plan", "Server", "TsbError", "abi", "catalog_to_device", "measure_batch"]
 
 _PAIR = {"paper": abi.TSB_PAIRS_PAPER, "upper": abi.TSB_PAIRS_UPPER, "diagonal": abi.TSB_PAIRS_DIAGONAL,
          "all": abi.TSB_PAIRS_ALL}
@@ -98,10 +98,63 @@ class Plan:
                        out.data_ptr())
         return out
 
+    def set_graphs(self, enable):
+        abi.tsb_plan_set_graphs(self.handle, enable)
+
     def close(self):
         if getattr(self, "handle", None) is not None:
             abi.tsb_plan_destroy(self.handle)
             self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def measure_batch(plans, datas, randoms=None, stream=None):
+    """tsb_measure_batch: item i measures datas[i] (randoms[i]) with plans[i].
+    Returns a list of dict(B, I, alpha)."""
+    import torch
+    s = torch.cuda.current_stream() if stream is None else stream
+    Bs = [np.empty((len(p.multipoles), p.n_bins, p.n_bins), dtype=np.float64) for p in plans]
+    rs = None if randoms is None else [_cat_struct(r) for r in randoms]
+    I, alpha = abi.tsb_measure_batch([p.handle for p in plans], [_cat_struct(d) for d in datas], rs,
+                                     s.cuda_stream, [B.ctypes.data for B in Bs])
+    return [{"B": B, "I": i, "alpha": a} for B, i, a in zip(Bs, I, alpha)]
+
+
+class Server:
+    """tsb_server_*: a request loop on the current device. Keeps each request's
+    catalogue tensors and output array alive until the request is done."""
+
+    def __init__(self, hbm_budget_bytes, max_slots):
+        self.handle = abi.tsb_server_create(hbm_budget_bytes, max_slots)
+        self._live = {}
+
+    def submit(self, plan, data_dev, randoms_dev=None):
+        B = np.empty((len(plan.multipoles), plan.n_bins, plan.n_bins), dtype=np.float64)
+        t = abi.tsb_server_submit(self.handle, plan.handle, _cat_struct(data_dev), _cat_struct(randoms_dev),
+                                  B.ctypes.data)
+        self._live[t] = (B, data_dev, randoms_dev)
+        return t
+
+    def poll(self, ticket):
+        """(done, latency_s, B or None)."""
+        done, lat = abi.tsb_server_poll(self.handle, ticket)
+        return done, lat, (self._live.pop(ticket)[0] if done else None)
+
+    def wait(self, ticket):
+        """Block until done: (latency_s, B)."""
+        lat = abi.tsb_server_wait(self.handle, ticket)
+        return lat, self._live.pop(ticket)[0]
+
+    def close(self):
+        if getattr(self, "handle", None) is not None:
+            abi.tsb_server_destroy(self.handle)
+            self.handle = None
+            self._live.clear()
 
     def __del__(self):
         try:

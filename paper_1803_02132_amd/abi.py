@@ -20,13 +20,15 @@ import torch  # noqa: E402,F401
 _lib = ctypes.CDLL(LIB_PATH)
 
 TSB_OK, TSB_E_ARG, TSB_E_UNSUPPORTED, TSB_E_NOMEM, TSB_E_INPUT, TSB_E_DEVICE = 0, -1, -2, -3, -4, -5
+TSB_E_BUSY, TSB_E_CANCELLED = -6, -7
 TSB_LOS_GLOBAL, TSB_LOS_LOCAL = 0, 1
 TSB_NGP, TSB_CIC, TSB_TSC = 1, 2, 3
 TSB_FP32, TSB_FP64 = 0, 1
 TSB_PAIRS_PAPER, TSB_PAIRS_UPPER, TSB_PAIRS_DIAGONAL, TSB_PAIRS_ALL = 0, 1, 2, 3
 
 _STATUS = {TSB_E_ARG: "TSB_E_ARG", TSB_E_UNSUPPORTED: "TSB_E_UNSUPPORTED", TSB_E_NOMEM: "TSB_E_NOMEM",
-           TSB_E_INPUT: "TSB_E_INPUT", TSB_E_DEVICE: "TSB_E_DEVICE"}
+           TSB_E_INPUT: "TSB_E_INPUT", TSB_E_DEVICE: "TSB_E_DEVICE", TSB_E_BUSY: "TSB_E_BUSY",
+           TSB_E_CANCELLED: "TSB_E_CANCELLED"}
 
 
 class TsbError(RuntimeError):
@@ -99,11 +101,32 @@ _lib.tsb_plan_stage_times.restype = ctypes.c_int
 _lib.tsb_plan_stage_times.argtypes = [ctypes.c_void_p, ctypes.c_int32, _P(ctypes.c_double), _P(ctypes.c_int64),
                                       ctypes.c_int32]
 
+_lib.tsb_measure_batch.restype = ctypes.c_int
+_lib.tsb_measure_batch.argtypes = [_P(ctypes.c_void_p), _P(_P(tsb_catalog)), _P(_P(tsb_catalog)), ctypes.c_int32,
+                                   ctypes.c_void_p, _P(_P(ctypes.c_double)), _P(ctypes.c_double),
+                                   _P(ctypes.c_double)]
+_lib.tsb_plan_set_graphs.restype = ctypes.c_int
+_lib.tsb_plan_set_graphs.argtypes = [ctypes.c_void_p, ctypes.c_int32]
+_lib.tsb_server_create.restype = ctypes.c_int
+_lib.tsb_server_create.argtypes = [ctypes.c_int64, ctypes.c_int32, _P(ctypes.c_void_p)]
+_lib.tsb_server_submit.restype = ctypes.c_int
+_lib.tsb_server_submit.argtypes = [ctypes.c_void_p, ctypes.c_void_p, _P(tsb_catalog), _P(tsb_catalog),
+                                   _P(ctypes.c_double), _P(ctypes.c_int64)]
+_lib.tsb_server_poll.restype = ctypes.c_int
+_lib.tsb_server_poll.argtypes = [ctypes.c_void_p, ctypes.c_int64, _P(ctypes.c_int32), _P(ctypes.c_double)]
+_lib.tsb_server_wait.restype = ctypes.c_int
+_lib.tsb_server_wait.argtypes = [ctypes.c_void_p, ctypes.c_int64, _P(ctypes.c_double)]
+_lib.tsb_server_destroy.restype = ctypes.c_int
+_lib.tsb_server_destroy.argtypes = [ctypes.c_void_p]
+
 STAGES = ["weights", "bucket", "assign", "fwd_z", "fwd_y", "fwd_x", "combine", "invF_x", "invF_y", "invF_z",
           "invG_x", "invG_y", "invG_z", "reduce", "reduce_final"]
 
-EXPORTED = ["tsb_plan_set_profiling", "tsb_plan_stage_times", "tsb_plan_create", "tsb_plan_destroy", "tsb_plan_query", "tsb_plan_get_info", "tsb_plan_nmode",
-            "tsb_measure", "tsb_assign", "tsb_plan_channel", "tsb_last_error"]
+EXPORTED = ["tsb_plan_set_profiling", "tsb_plan_stage_times", "tsb_plan_create", "tsb_plan_destroy",
+            "tsb_plan_query", "tsb_plan_get_info", "tsb_plan_nmode", "tsb_measure", "tsb_assign",
+            "tsb_plan_channel", "tsb_last_error", "tsb_measure_batch", "tsb_plan_set_graphs",
+            "tsb_server_create", "tsb_server_submit", "tsb_server_poll", "tsb_server_wait",
+            "tsb_server_destroy"]
 
 
 def tsb_last_error():
@@ -183,3 +206,56 @@ def tsb_plan_stage_times(h, reset=False):
     calls = (ctypes.c_int64 * n)()
     _check(_lib.tsb_plan_stage_times(h, n, ms, calls, int(bool(reset))))
     return {STAGES[i]: (ms[i], calls[i]) for i in range(n)}
+
+
+def tsb_measure_batch(handles, datas, randoms, stream, B_ptrs):
+    """handles: plan handles; datas / randoms: tsb_catalog structs (randoms None
+    or a list with None in box mode); B_ptrs: host double-buffer pointers.
+    Returns (I list, alpha list)."""
+    n = len(handles)
+    hs = (ctypes.c_void_p * n)(*[h.value if isinstance(h, ctypes.c_void_p) else h for h in handles])
+    ds = (_P(tsb_catalog) * n)(*[ctypes.pointer(d) for d in datas])
+    rs = None
+    if randoms is not None:
+        rs = (_P(tsb_catalog) * n)(*[ctypes.pointer(r) if r is not None else None for r in randoms])
+    bs = (_P(ctypes.c_double) * n)(*[ctypes.cast(p, _P(ctypes.c_double)) for p in B_ptrs])
+    I = (ctypes.c_double * n)()
+    alpha = (ctypes.c_double * n)()
+    _check(_lib.tsb_measure_batch(hs, ds, rs, n, stream, bs, I, alpha))
+    return list(I), list(alpha)
+
+
+def tsb_plan_set_graphs(h, enable):
+    return _check(_lib.tsb_plan_set_graphs(h, int(bool(enable))))
+
+
+def tsb_server_create(budget_bytes, max_slots):
+    h = ctypes.c_void_p()
+    _check(_lib.tsb_server_create(int(budget_bytes), int(max_slots), ctypes.byref(h)))
+    return h
+
+
+def tsb_server_submit(srv, plan, data, randoms, B_ptr):
+    t = ctypes.c_int64()
+    _check(_lib.tsb_server_submit(srv, plan, ctypes.byref(data),
+                                  ctypes.byref(randoms) if randoms is not None else None,
+                                  ctypes.cast(B_ptr, _P(ctypes.c_double)), ctypes.byref(t)))
+    return t.value
+
+
+def tsb_server_poll(srv, ticket):
+    """(done, latency_s); raises the request's error once it is done and failed."""
+    done = ctypes.c_int32()
+    lat = ctypes.c_double()
+    _check(_lib.tsb_server_poll(srv, ticket, ctypes.byref(done), ctypes.byref(lat)))
+    return bool(done.value), lat.value
+
+
+def tsb_server_wait(srv, ticket):
+    lat = ctypes.c_double()
+    _check(_lib.tsb_server_wait(srv, ticket, ctypes.byref(lat)))
+    return lat.value
+
+
+def tsb_server_destroy(srv):
+    return _check(_lib.tsb_server_destroy(srv))

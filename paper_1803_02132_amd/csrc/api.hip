@@ -1,8 +1,17 @@
 // C ABI (include/triposh.h): plan lifetime, buffers and the measurement sequence.
+#include <algorithm>
+#include <chrono>
 #include <cmath>
+#include <condition_variable>
 #include <cstring>
+#include <deque>
 #include <limits>
+#include <mutex>
 #include <new>
+#include <string>
+#include <thread>
+#include <unordered_map>
+#include <vector>
 
 #include "tsb_internal.h"
 
@@ -116,6 +125,13 @@ void plan_free(Plan& P) {
   for (int st = 0; st < kNumStages; ++st)
     for (int k = 0; k < 2; ++k)
       if (P.ev[st][k]) (void)hipEventDestroy(P.ev[st][k]);
+  if (P.graph_exec) (void)hipGraphExecDestroy(P.graph_exec);
+  if (P.cap_stream) (void)hipStreamDestroy(P.cap_stream);
+  if (P.own_stream) (void)hipStreamDestroy(P.own_stream);
+  if (P.h_res) (void)hipHostFree(P.h_res);
+  P.graph_exec = nullptr;
+  P.cap_stream = P.own_stream = nullptr;
+  P.h_res = nullptr;
   void* ptrs[] = {P.d_grid, P.d_t1, P.d_t2, P.d_t3, P.d_spec, P.d_dcube, P.d_u1, P.d_u2, P.d_fields,
                   P.d_tw_n, P.d_tw_m, P.d_bin_lut, P.d_fkinds, P.d_fcomp, P.d_gcomp, P.d_terms,
                   P.d_qgroups, P.d_outs, P.d_out_norm, P.d_partials, P.d_B, P.d_scal, P.d_sum_partials,
@@ -146,6 +162,7 @@ int ensure_particles(Plan& P, int64_t n) {
   if ((rc = dalloc(&P.d_work, wcap * 8, P.bytes, false))) return rc;
   P.particle_cap = cap;
   P.work_cap = wcap;
+  ++P.particle_gen;   // buffers moved: a captured graph is stale
   return TSB_OK;
 }
 
@@ -221,6 +238,105 @@ int check_input_flags(Plan& P, const DevScalars& h) {
   return TSB_OK;
 }
 
+// Everything after the bucketing: the assignment's tile stages, the forward
+// and inverse transforms and the reduction. Launch shapes depend only on the
+// plan and its particle capacity.
+int run_back(Plan& P, hipStream_t s) {
+  int rc;
+  if ((rc = run_assign_back(P, s))) return rc;
+  if ((rc = run_forward(P, s))) return rc;
+  if ((rc = run_inverse(P, s))) return rc;
+  if (P.fused) {
+    if (!P.outs.empty()) {
+      if ((rc = run_fused(P, s))) return rc;
+      if ((rc = run_reduce_final(P, s))) return rc;
+    }
+  } else if ((rc = run_reduce(P, s))) {
+    return rc;
+  }
+  return TSB_OK;
+}
+
+// run_back through a graph captured once per plan and particle capacity
+// (direct launches while stage profiling is on).
+int launch_back(Plan& P, hipStream_t s) {
+  if (P.prof || !P.use_graph) return run_back(P, s);
+  if (!P.graph_exec || P.graph_gen != P.particle_gen) {
+    if (P.graph_exec) {
+      TSB_HIP(hipGraphExecDestroy(P.graph_exec));
+      P.graph_exec = nullptr;
+    }
+    if (!P.cap_stream) TSB_HIP(hipStreamCreateWithFlags(&P.cap_stream, hipStreamNonBlocking));
+    TSB_HIP(hipStreamBeginCapture(P.cap_stream, hipStreamCaptureModeThreadLocal));
+    const int rc = run_back(P, P.cap_stream);
+    hipGraph_t g = nullptr;
+    const hipError_t e = hipStreamEndCapture(P.cap_stream, &g);
+    if (rc) {
+      if (g) (void)hipGraphDestroy(g);
+      return rc;
+    }
+    if (e != hipSuccess || !g) return fail(TSB_E_DEVICE, std::string("graph capture: ") + hipGetErrorString(e));
+    hipGraphExec_t ex = nullptr;
+    const hipError_t ei = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (ei != hipSuccess) return fail(TSB_E_DEVICE, std::string("graph instantiate: ") + hipGetErrorString(ei));
+    P.graph_exec = ex;
+    P.graph_gen = P.particle_gen;
+  }
+  TSB_HIP(hipGraphLaunch(P.graph_exec, s));
+  return TSB_OK;
+}
+
+size_t result_stride(const Plan& P) {
+  return ((P.outs.size() * 8 + sizeof(DevScalars)) + 255) / 256 * 256;
+}
+
+// Pinned result slots; growing them waits for the plan's work to drain.
+int ensure_result_slots(Plan& P, int n) {
+  if (n <= P.res_slots) return TSB_OK;
+  TSB_HIP(hipDeviceSynchronize());
+  if (P.h_res) TSB_HIP(hipHostFree(P.h_res));
+  P.h_res = nullptr;
+  P.res_slots = 0;
+  TSB_HIP(hipHostMalloc(&P.h_res, result_stride(P) * (size_t)n, hipHostMallocDefault));
+  P.res_slots = n;
+  return TSB_OK;
+}
+
+// One measurement enqueued on s; its outputs and scalars land in pinned slot
+// `slot` when s reaches that point.
+int enqueue_measure(Plan& P, const tsb_catalog* data, const tsb_catalog* rand, hipStream_t s, int slot) {
+  int rc;
+  if (slot < 0 || slot >= P.res_slots) return fail(TSB_E_ARG, "result slot out of range");
+  if ((rc = run_front(P, data, rand, s))) return rc;
+  if ((rc = launch_back(P, s))) return rc;
+  char* base = (char*)P.h_res + result_stride(P) * (size_t)slot;
+  if (!P.outs.empty())
+    TSB_HIP(hipMemcpyAsync(base, P.d_B, P.outs.size() * 8, hipMemcpyDeviceToHost, s));
+  TSB_HIP(hipMemcpyAsync(base + P.outs.size() * 8, P.d_scal, sizeof(DevScalars), hipMemcpyDeviceToHost, s));
+  return TSB_OK;
+}
+
+// After the slot's copies completed: input checks and the scatter into the
+// caller's [n_mult][nb][nb] array (NaN where no pair was computed).
+int finish_measure(Plan& P, int slot, double* B_out, double* I_out, double* alpha_out) {
+  const char* base = (const char*)P.h_res + result_stride(P) * (size_t)slot;
+  const double* hb = (const double*)base;
+  DevScalars h;
+  std::memcpy(&h, base + P.outs.size() * 8, sizeof(h));
+  int rc;
+  if ((rc = check_input_flags(P, h))) return rc;
+  const size_t nbb = (size_t)P.nb * P.nb;
+  for (size_t i = 0; i < P.mult.size() * nbb; ++i) B_out[i] = std::numeric_limits<double>::quiet_NaN();
+  for (size_t o = 0; o < P.outs.size(); ++o) {
+    const OutEntry& e = P.outs[o];
+    B_out[(size_t)e.mu * nbb + (size_t)e.b1 * P.nb + e.b2] = hb[o];
+  }
+  if (I_out) *I_out = h.I;
+  if (alpha_out) *alpha_out = h.alpha;
+  return TSB_OK;
+}
+
 }  // namespace
 
 }  // namespace tsb
@@ -229,6 +345,12 @@ using namespace tsb;
 
 struct tsb_plan {
   Plan p;
+  // the request the plan was created from (a server clones it)
+  tsb_grid grid{};
+  tsb_los los{};
+  tsb_kbins bins{};
+  std::vector<tsb_multipole> mult;
+  tsb_options opts{};
 };
 
 extern "C" {
@@ -310,6 +432,11 @@ int tsb_plan_create(const tsb_grid* grid, const tsb_los* los, const tsb_kbins* b
     delete h;
     return rc;
   }
+  h->grid = *grid;
+  h->los = *los;
+  h->bins = *bins;
+  h->mult.assign(multipoles, multipoles + n_multipoles);
+  h->opts = *options;
   *out = h;
   return TSB_OK;
 }
@@ -365,6 +492,7 @@ int tsb_assign(tsb_plan* plan, const tsb_catalog* data, const tsb_catalog* rando
   hipStream_t s = (hipStream_t)stream;
   int rc;
   if ((rc = run_front(P, data, randoms, s))) return rc;
+  if ((rc = run_assign_back(P, s))) return rc;
   if ((rc = run_unpack_grids(P, grids_out, s))) return rc;
   DevScalars h{};
   TSB_HIP(hipMemcpyAsync(&h, P.d_scal, sizeof(h), hipMemcpyDeviceToHost, s));
@@ -378,32 +506,87 @@ int tsb_measure(tsb_plan* plan, const tsb_catalog* data, const tsb_catalog* rand
   Plan& P = plan->p;
   hipStream_t s = (hipStream_t)stream;
   int rc;
-  if ((rc = run_front(P, data, randoms, s))) return rc;
-  if ((rc = run_forward(P, s))) return rc;
-  if ((rc = run_inverse(P, s))) return rc;
-  if (P.fused) {
-    if (!P.outs.empty()) {
-      if ((rc = run_fused(P, s))) return rc;
-      if ((rc = run_reduce_final(P, s))) return rc;
-    }
-  } else if ((rc = run_reduce(P, s))) {
-    return rc;
-  }
-  std::vector<double> hb(P.outs.size());
-  DevScalars h{};
-  if (!hb.empty()) TSB_HIP(hipMemcpyAsync(hb.data(), P.d_B, hb.size() * 8, hipMemcpyDeviceToHost, s));
-  TSB_HIP(hipMemcpyAsync(&h, P.d_scal, sizeof(h), hipMemcpyDeviceToHost, s));
+  if ((rc = set_device(P))) return rc;
+  if ((rc = ensure_result_slots(P, 1))) return rc;
+  if ((rc = enqueue_measure(P, data, randoms, s, 0))) return rc;
   TSB_HIP(hipStreamSynchronize(s));
   collect_stage_times(P);
-  if ((rc = check_input_flags(P, h))) return rc;
-  const size_t nbb = (size_t)P.nb * P.nb;
-  for (size_t i = 0; i < P.mult.size() * nbb; ++i) B_out[i] = std::numeric_limits<double>::quiet_NaN();
-  for (size_t o = 0; o < P.outs.size(); ++o) {
-    const OutEntry& e = P.outs[o];
-    B_out[(size_t)e.mu * nbb + (size_t)e.b1 * P.nb + e.b2] = hb[o];
+  return finish_measure(P, 0, B_out, I_out, alpha_out);
+}
+
+int tsb_measure_batch(tsb_plan* const* plans, const tsb_catalog* const* data, const tsb_catalog* const* randoms,
+                      int32_t n, void* stream, double* const* B_out, double* I_out, double* alpha_out) {
+  if (n < 0 || (n > 0 && (!plans || !data || !B_out))) return fail(TSB_E_ARG, "NULL argument");
+  if (n == 0) return TSB_OK;
+  hipStream_t s = (hipStream_t)stream;
+  // distinct plans, the slot of every item on its plan, and each plan's stream
+  std::vector<Plan*> uniq;
+  std::vector<int> slot(n);
+  std::vector<int> count;
+  for (int i = 0; i < n; ++i) {
+    if (!plans[i] || !B_out[i]) return fail(TSB_E_ARG, "NULL plan or output in the batch");
+    Plan* P = &plans[i]->p;
+    size_t u = 0;
+    while (u < uniq.size() && uniq[u] != P) ++u;
+    if (u == uniq.size()) {
+      uniq.push_back(P);
+      count.push_back(0);
+    }
+    slot[i] = count[u]++;
   }
-  if (I_out) *I_out = h.I;
-  if (alpha_out) *alpha_out = h.alpha;
+  int rc;
+  for (size_t u = 0; u < uniq.size(); ++u) {
+    Plan& P = *uniq[u];
+    if ((rc = set_device(P))) return rc;
+    if ((rc = ensure_result_slots(P, count[u]))) return rc;
+    if (!P.own_stream) TSB_HIP(hipStreamCreateWithFlags(&P.own_stream, hipStreamNonBlocking));
+    // particle buffers sized for the plan's largest catalogue before anything is enqueued
+    int64_t most = 0;
+    for (int i = 0; i < n; ++i) {
+      if (&plans[i]->p != &P) continue;
+      if ((rc = check_catalog(data[i], "data"))) return rc;
+      int64_t nt = data[i]->n;
+      if (!P.box_mode) {
+        if (!randoms || (rc = check_catalog(randoms[i], "randoms"))) return rc ? rc : fail(TSB_E_ARG, "randoms missing");
+        nt += randoms[i]->n;
+      }
+      most = std::max(most, nt);
+    }
+    if ((rc = ensure_particles(P, most))) return rc;
+  }
+  // the batch starts after the work already on the caller's stream
+  hipEvent_t start;
+  TSB_HIP(hipEventCreateWithFlags(&start, hipEventDisableTiming));
+  TSB_HIP(hipEventRecord(start, s));
+  for (Plan* P : uniq) TSB_HIP(hipStreamWaitEvent(P->own_stream, start, 0));
+  int first_err = TSB_OK;
+  for (int i = 0; i < n && !first_err; ++i) {
+    Plan& P = plans[i]->p;
+    first_err = enqueue_measure(P, data[i], randoms ? randoms[i] : nullptr, P.own_stream, slot[i]);
+  }
+  // the caller's stream continues after the whole batch
+  for (Plan* P : uniq) {
+    hipEvent_t e;
+    TSB_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    TSB_HIP(hipEventRecord(e, P->own_stream));
+    TSB_HIP(hipStreamWaitEvent(s, e, 0));
+    TSB_HIP(hipEventDestroy(e));
+  }
+  for (Plan* P : uniq) TSB_HIP(hipStreamSynchronize(P->own_stream));
+  TSB_HIP(hipEventDestroy(start));
+  if (first_err) return first_err;
+  for (Plan* P : uniq) collect_stage_times(*P);
+  for (int i = 0; i < n; ++i) {
+    rc = finish_measure(plans[i]->p, slot[i], B_out[i], I_out ? I_out + i : nullptr,
+                        alpha_out ? alpha_out + i : nullptr);
+    if (rc && !first_err) first_err = rc;
+  }
+  return first_err;
+}
+
+int tsb_plan_set_graphs(tsb_plan* plan, int32_t enable) {
+  if (!plan) return fail(TSB_E_ARG, "NULL argument");
+  plan->p.use_graph = enable != 0;
   return TSB_OK;
 }
 
@@ -430,6 +613,360 @@ int tsb_plan_stage_times(tsb_plan* plan, int32_t n, double* ms, int64_t* calls, 
       P.stage_ms[st] = 0.0;
       P.stage_calls[st] = 0;
     }
+  return TSB_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Serving: a worker thread admits requests into slots (each slot a plan
+// workspace and a stream) by HBM footprint and runs them concurrently.
+
+namespace {
+
+double now_s() {
+  return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+// Request identity for workspace reuse: every field of the plan request.
+std::string request_key(const tsb_plan& t) {
+  std::string k;
+  auto add = [&k](const void* p, size_t n) { k.append((const char*)p, n); };
+  add(&t.grid, sizeof(t.grid));
+  add(&t.los, sizeof(t.los));
+  add(&t.bins, sizeof(t.bins));
+  add(&t.opts, sizeof(t.opts));
+  for (const tsb_multipole& m : t.mult) add(&m, sizeof(m));
+  return k;
+}
+
+struct Engine {
+  tsb_plan* plan = nullptr;
+  std::string key;
+  hipStream_t stream = nullptr;
+  hipEvent_t done = nullptr;
+  int64_t ticket = 0;     // running request (0: idle)
+  double last_used = 0.0;
+};
+
+struct Request {
+  int64_t ticket = 0;
+  std::string key;
+  tsb_plan tmpl;          // request copy (its Plan stays empty)
+  tsb_catalog data{}, rand{};
+  bool has_rand = false;
+  double* B_out = nullptr;
+  double t_submit = 0.0, latency = 0.0;
+  int status = TSB_OK;
+  std::string message;
+  bool done = false;
+};
+
+struct Server {
+  int device = 0;
+  int64_t budget = 0;
+  int max_slots = 1;
+  std::mutex mu;
+  std::condition_variable cv_work, cv_done;
+  std::deque<int64_t> queue;
+  std::unordered_map<int64_t, Request> reqs;
+  std::vector<Engine> engines;   // worker thread only
+  bool stop = false;
+  int64_t next_ticket = 1;
+  std::thread worker;
+};
+
+int64_t engine_bytes(const Engine& e) { return e.plan ? e.plan->p.bytes : 0; }
+
+// Bytes a measurement of n particles adds on top of a workspace.
+int64_t particle_bytes(const tsb_plan& t, int64_t n) {
+  const int64_t cap = std::max<int64_t>(n + n / 8, 1024);
+  return cap * (4 + record_stride(t.p)) + 8 * assign_work_cap(t.p, cap);
+}
+
+void destroy_engine(Engine& e) {
+  if (e.plan) (void)tsb_plan_destroy(e.plan);
+  if (e.done) (void)hipEventDestroy(e.done);
+  if (e.stream) (void)hipStreamDestroy(e.stream);
+  e = Engine{};
+}
+
+// Worker side: finish requests whose events have fired.
+bool reap(Server& S) {
+  bool any = false;
+  for (Engine& e : S.engines) {
+    if (!e.ticket) continue;
+    const hipError_t q = hipEventQuery(e.done);
+    if (q == hipErrorNotReady) continue;
+    int rc;
+    std::string msg;
+    double* B_out;
+    {
+      std::lock_guard<std::mutex> lk(S.mu);
+      B_out = S.reqs[e.ticket].B_out;
+    }
+    if (q != hipSuccess) {
+      rc = fail(TSB_E_DEVICE, std::string("request failed on the device: ") + hipGetErrorString(q));
+    } else {
+      rc = finish_measure(e.plan->p, 0, B_out, nullptr, nullptr);
+    }
+    if (rc) msg = g_err;
+    {
+      std::lock_guard<std::mutex> lk(S.mu);
+      Request& r = S.reqs[e.ticket];
+      r.status = rc;
+      r.message = msg;
+      r.latency = now_s() - r.t_submit;
+      r.done = true;
+    }
+    e.ticket = 0;
+    e.last_used = now_s();
+    any = true;
+  }
+  if (any) S.cv_done.notify_all();
+  return any;
+}
+
+void finish_with_error(Server& S, int64_t ticket, int rc) {
+  std::lock_guard<std::mutex> lk(S.mu);
+  Request& r = S.reqs[ticket];
+  r.status = rc;
+  r.message = g_err;
+  r.latency = now_s() - r.t_submit;
+  r.done = true;
+  S.cv_done.notify_all();
+}
+
+// Worker side: pick an engine for a queued request, creating one when slots
+// and the budget allow (releasing idle workspaces of other geometries first).
+// Returns the engine index, -1 to wait, or -2 with rc set if it can never fit.
+int place(Server& S, const Request& r, int* rc) {
+  const int64_t nt = r.data.n + (r.has_rand ? r.rand.n : 0);
+  int64_t used = 0;
+  for (const Engine& e : S.engines) used += engine_bytes(e);
+  for (size_t i = 0; i < S.engines.size(); ++i) {
+    Engine& e = S.engines[i];
+    if (e.ticket || e.key != r.key) continue;
+    const int64_t cap = e.plan->p.particle_cap;
+    if (cap >= nt) return (int)i;   // fits its buffers as they are
+    const int64_t have = cap > 0 ? particle_bytes(r.tmpl, cap - cap / 9) : 0;
+    if (used + particle_bytes(r.tmpl, nt) - have <= S.budget) return (int)i;
+  }
+  tsb_plan_info info{};
+  if (int q = tsb_plan_query(&r.tmpl.grid, &r.tmpl.los, &r.tmpl.bins, r.tmpl.mult.data(),
+                             (int32_t)r.tmpl.mult.size(), &r.tmpl.opts, &info, nullptr)) {
+    *rc = q;
+    return -2;
+  }
+  const int64_t need = info.workspace_bytes + particle_bytes(r.tmpl, nt);
+  if (need > S.budget) {
+    *rc = fail(TSB_E_NOMEM, "request does not fit the server's HBM budget");
+    return -2;
+  }
+  // release idle workspaces (least recently used first) until slots and bytes allow
+  while ((int)S.engines.size() >= S.max_slots || used + need > S.budget) {
+    int victim = -1;
+    for (size_t i = 0; i < S.engines.size(); ++i)
+      if (!S.engines[i].ticket && (victim < 0 || S.engines[i].last_used < S.engines[victim].last_used))
+        victim = (int)i;
+    if (victim < 0) return -1;   // everything busy: wait
+    used -= engine_bytes(S.engines[victim]);
+    destroy_engine(S.engines[victim]);
+    S.engines.erase(S.engines.begin() + victim);
+  }
+  Engine e;
+  e.key = r.key;
+  int q = tsb_plan_create(&r.tmpl.grid, &r.tmpl.los, &r.tmpl.bins, r.tmpl.mult.data(),
+                          (int32_t)r.tmpl.mult.size(), &r.tmpl.opts, &e.plan);
+  if (!q && hipStreamCreateWithFlags(&e.stream, hipStreamNonBlocking) != hipSuccess)
+    q = fail(TSB_E_DEVICE, "stream creation failed");
+  if (!q && hipEventCreateWithFlags(&e.done, hipEventDisableTiming) != hipSuccess)
+    q = fail(TSB_E_DEVICE, "event creation failed");
+  if (q) {
+    destroy_engine(e);
+    *rc = q;
+    return -2;
+  }
+  S.engines.push_back(e);
+  return (int)S.engines.size() - 1;
+}
+
+// Worker side: admit queued requests in arrival order; a request that has to
+// wait for memory or a slot blocks later requests that would need a new
+// workspace, but not those with an idle workspace of their own geometry.
+bool admit(Server& S) {
+  std::vector<int64_t> order;
+  {
+    std::lock_guard<std::mutex> lk(S.mu);
+    order.assign(S.queue.begin(), S.queue.end());
+  }
+  bool any = false, blocked = false;
+  for (int64_t t : order) {
+    Request r;
+    {
+      std::lock_guard<std::mutex> lk(S.mu);
+      r = S.reqs[t];
+    }
+    bool has_idle = false;
+    for (const Engine& e : S.engines) has_idle = has_idle || (!e.ticket && e.key == r.key);
+    if (blocked && !has_idle) continue;
+    int rc = TSB_OK;
+    const int i = place(S, r, &rc);
+    if (i == -1) {
+      blocked = true;
+      continue;
+    }
+    {
+      std::lock_guard<std::mutex> lk(S.mu);
+      S.queue.erase(std::find(S.queue.begin(), S.queue.end(), t));
+    }
+    any = true;
+    if (i == -2) {
+      finish_with_error(S, t, rc);
+      continue;
+    }
+    Engine& e = S.engines[i];
+    Plan& P = e.plan->p;
+    rc = ensure_result_slots(P, 1);
+    if (!rc) rc = enqueue_measure(P, &r.data, r.has_rand ? &r.rand : nullptr, e.stream, 0);
+    if (!rc && hipEventRecord(e.done, e.stream) != hipSuccess) rc = fail(TSB_E_DEVICE, "event record failed");
+    if (rc) {
+      (void)hipStreamSynchronize(e.stream);
+      finish_with_error(S, t, rc);
+      continue;
+    }
+    e.ticket = t;
+  }
+  return any;
+}
+
+void serve(Server* S) {
+  (void)hipSetDevice(S->device);
+  for (;;) {
+    bool progress = reap(*S);
+    progress = admit(*S) || progress;
+    bool running = false;
+    for (const Engine& e : S->engines) running = running || e.ticket != 0;
+    std::unique_lock<std::mutex> lk(S->mu);
+    if (S->stop) {
+      // cancel what is still queued, then leave once nothing runs
+      for (int64_t t : S->queue) {
+        Request& r = S->reqs[t];
+        r.status = TSB_E_CANCELLED;
+        r.message = "cancelled: the server was destroyed";
+        r.done = true;
+      }
+      S->queue.clear();
+      S->cv_done.notify_all();
+      if (!running) break;
+    }
+    if (!progress) {
+      if (running) S->cv_work.wait_for(lk, std::chrono::microseconds(100));
+      else S->cv_work.wait_for(lk, std::chrono::milliseconds(5), [S] { return S->stop || !S->queue.empty(); });
+    }
+  }
+  for (Engine& e : S->engines) destroy_engine(e);
+  S->engines.clear();
+}
+
+}  // namespace
+
+extern "C" {
+
+int tsb_server_create(int64_t hbm_budget_bytes, int32_t max_slots, void** server) {
+  if (!server || hbm_budget_bytes <= 0 || max_slots < 1) return fail(TSB_E_ARG, "bad argument");
+  *server = nullptr;
+  Server* S = new (std::nothrow) Server();
+  if (!S) return fail(TSB_E_NOMEM, "host allocation failed");
+  if (hipGetDevice(&S->device) != hipSuccess) {
+    delete S;
+    return fail(TSB_E_DEVICE, "no HIP device");
+  }
+  S->budget = hbm_budget_bytes;
+  S->max_slots = max_slots;
+  S->worker = std::thread(serve, S);
+  *server = S;
+  return TSB_OK;
+}
+
+int tsb_server_submit(void* server, const tsb_plan* plan, const tsb_catalog* data, const tsb_catalog* randoms,
+                      double* B_out, int64_t* ticket) {
+  if (!server || !plan || !data || !B_out || !ticket) return fail(TSB_E_ARG, "NULL argument");
+  Server* S = (Server*)server;
+  int rc;
+  if ((rc = check_catalog(data, "data"))) return rc;
+  const bool box = plan->p.box_mode != 0;
+  if (!box && (rc = check_catalog(randoms, "randoms"))) return rc;
+  Request r;
+  r.tmpl.grid = plan->grid;
+  r.tmpl.los = plan->los;
+  r.tmpl.bins = plan->bins;
+  r.tmpl.mult = plan->mult;
+  r.tmpl.opts = plan->opts;
+  r.tmpl.p.box_mode = plan->p.box_mode;
+  r.tmpl.p.chans = plan->p.chans;
+  r.tmpl.p.precision = plan->p.precision;
+  r.tmpl.p.NT = plan->p.NT;
+  r.key = request_key(r.tmpl);
+  r.data = *data;
+  if (!box) {
+    r.rand = *randoms;
+    r.has_rand = true;
+  }
+  r.B_out = B_out;
+  r.t_submit = now_s();
+  {
+    std::lock_guard<std::mutex> lk(S->mu);
+    if (S->stop) return fail(TSB_E_CANCELLED, "the server is shutting down");
+    r.ticket = S->next_ticket++;
+    *ticket = r.ticket;
+    S->reqs.emplace(r.ticket, std::move(r));
+    S->queue.push_back(*ticket);
+  }
+  S->cv_work.notify_one();
+  return TSB_OK;
+}
+
+int tsb_server_poll(void* server, int64_t ticket, int32_t* done, double* latency_s) {
+  if (!server || !done) return fail(TSB_E_ARG, "NULL argument");
+  Server* S = (Server*)server;
+  std::lock_guard<std::mutex> lk(S->mu);
+  auto it = S->reqs.find(ticket);
+  if (it == S->reqs.end()) return fail(TSB_E_ARG, "unknown ticket");
+  *done = it->second.done ? 1 : 0;
+  if (latency_s) *latency_s = it->second.latency;
+  if (it->second.done && it->second.status) {
+    set_error(it->second.message);
+    return it->second.status;
+  }
+  return TSB_OK;
+}
+
+int tsb_server_wait(void* server, int64_t ticket, double* latency_s) {
+  if (!server) return fail(TSB_E_ARG, "NULL argument");
+  Server* S = (Server*)server;
+  std::unique_lock<std::mutex> lk(S->mu);
+  auto it = S->reqs.find(ticket);
+  if (it == S->reqs.end()) return fail(TSB_E_ARG, "unknown ticket");
+  S->cv_done.wait(lk, [&] { return it->second.done; });
+  if (latency_s) *latency_s = it->second.latency;
+  if (it->second.status) {
+    set_error(it->second.message);
+    return it->second.status;
+  }
+  return TSB_OK;
+}
+
+int tsb_server_destroy(void* server) {
+  if (!server) return TSB_OK;
+  Server* S = (Server*)server;
+  {
+    std::lock_guard<std::mutex> lk(S->mu);
+    S->stop = true;
+  }
+  S->cv_work.notify_all();
+  if (S->worker.joinable()) S->worker.join();
+  delete S;
   return TSB_OK;
 }
 

@@ -1035,24 +1035,50 @@ int tile_ranges(int NT, int* rd, int* rcl, int* rch) {
 }
 
 template <typename T, int NCH>
-int assign_impl(Plan& P, const BucketArgs& b, const ChanInfo& ci, hipStream_t s) {
+int assign_front_impl(Plan& P, const BucketArgs& b, const ChanInfo& ci, hipStream_t s) {
   const int ntiles = P.NT * P.NT * P.NT;
   const int64_t ntot = b.d.n + b.r.n;
+  const int nchx = ci.nch + (P.box_mode ? 0 : 1);
+  // upper bound of the work items: a particle is visited by at most 8 tiles
+  const int64_t work_bound = (int64_t)ntiles + (8 * ntot + kPartVisits - 1) / kPartVisits + 1;
+  if (work_bound > P.work_cap) return fail(TSB_E_UNSUPPORTED, "assignment: work list too small");
+  if (P.tile_wgs <= 0) {
+    // persistent workgroups of the tile kernel: as many as are resident at once
+    const size_t lds = (size_t)nchx * P.T * P.T * P.T * sizeof(unsigned long long);
+    int per_cu = 0, dev = 0, n_cu = 0;
+    TSB_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)assign_tile_kernel<T, NCH>,
+                                                         kTileBlock, lds));
+    TSB_HIP(hipGetDevice(&dev));
+    TSB_HIP(hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev));
+    P.tile_wgs = std::max(1, per_cu) * std::max(1, n_cu);
+  }
+  if (ntot > 0) {
+    FillArgs<T, NCH> f;
+    f.b = b;
+    f.ci = ci;
+    f.rec.cap = P.particle_cap;
+    f.rec.base = (char*)P.d_rec;
+    f.rec.stride = record_stride(P);
+    f.nchx = nchx;
+    f.scal = P.d_scal;
+    hipLaunchKernelGGL((bucket_fill_kernel<T, NCH>), dim3(grid_blocks(ntot)), dim3(kBlock), 0, s, f);
+  }
+  prof_end(P, kStBucket, s);
+  TSB_HIP(hipGetLastError());
+  return TSB_OK;
+}
+
+// Everything after the bucketing: fixed launch shapes for a given plan and
+// particle capacity (the work list lives in device memory), so the sequence
+// can be captured into a graph.
+template <typename T, int NCH>
+int assign_back_impl(Plan& P, const ChanInfo& ci, hipStream_t s) {
+  const int ntiles = P.NT * P.NT * P.NT;
   const int nchx = ci.nch + (P.box_mode ? 0 : 1);
   Records<T> rec;
   rec.cap = P.particle_cap;
   rec.base = (char*)P.d_rec;
   rec.stride = record_stride(P);
-  if (ntot > 0) {
-    FillArgs<T, NCH> f;
-    f.b = b;
-    f.ci = ci;
-    f.rec = rec;
-    f.nchx = nchx;
-    f.scal = P.d_scal;
-    hipLaunchKernelGGL((bucket_fill_kernel<T, NCH>), dim3(grid_blocks(ntot)), dim3(kBlock), 0, s, f);
-  }
-
   TileArgs a{};
   a.inv_h = (double)P.N / P.L;
   a.h = P.L / (double)P.N;
@@ -1080,6 +1106,7 @@ int assign_impl(Plan& P, const BucketArgs& b, const ChanInfo& ci, hipStream_t s)
   a.nwork = P.d_tile_pstart + ntiles;
   a.hslot = P.d_tile_hslot;
   a.heavy = (unsigned long long*)P.d_heavy;
+  prof_begin(P, kStAssign, s);
   {
     // work items: tiles with more than kPartVisits visits are split into parts
     const int tb = (ntiles + kBlock - 1) / kBlock;
@@ -1097,23 +1124,9 @@ int assign_impl(Plan& P, const BucketArgs& b, const ChanInfo& ci, hipStream_t s)
     hipLaunchKernelGGL(heavy_zero_kernel, dim3(1024), dim3(kBlock), 0, s, (unsigned long long*)P.d_heavy,
                        (const int*)nheavy, per_slot);
   }
-  prof_end(P, kStBucket, s);
-  // upper bound of the work items: a particle is visited by at most 8 tiles
-  const int64_t work_bound = (int64_t)ntiles + (8 * ntot + kPartVisits - 1) / kPartVisits + 1;
-  if (work_bound > P.work_cap) return fail(TSB_E_UNSUPPORTED, "assignment: work list too small");
   const size_t lds = (size_t)nchx * P.T * P.T * P.T * sizeof(unsigned long long);
-  prof_begin(P, kStAssign, s);
-  // persistent workgroups, as many as are resident at once, walk the work items
-  if (P.tile_wgs <= 0) {
-    int per_cu = 0, dev = 0, n_cu = 0;
-    TSB_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)assign_tile_kernel<T, NCH>,
-                                                         kTileBlock, lds));
-    TSB_HIP(hipGetDevice(&dev));
-    TSB_HIP(hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev));
-    P.tile_wgs = std::max(1, per_cu) * std::max(1, n_cu);
-  }
-  const int wgs = (int)std::min<int64_t>(work_bound, P.tile_wgs);
-  hipLaunchKernelGGL((assign_tile_kernel<T, NCH>), dim3(wgs), dim3(kTileBlock), lds, s, a, rec);
+  hipLaunchKernelGGL((assign_tile_kernel<T, NCH>), dim3(std::max(1, P.tile_wgs)), dim3(kTileBlock), lds, s, a,
+                     rec);
   hipLaunchKernelGGL(heavy_final_kernel<T>, dim3(kMaxHeavy), dim3(kBlock), 0, s, a, (const int*)P.d_heavy_tile,
                      (const int*)nheavy);
   if (!P.box_mode) {
@@ -1162,9 +1175,20 @@ int run_assign(Plan& P, const tsb_catalog* data, const tsb_catalog* rand, hipStr
   if (int rc = chan_info(P, &ci)) return rc;
   const int nchx = ci.nch + (P.box_mode ? 0 : 1);
   const bool f64 = P.precision == TSB_FP64;
-  if (nchx <= 8) return f64 ? assign_impl<double, 8>(P, b, ci, s) : assign_impl<float, 8>(P, b, ci, s);
-  if (nchx <= 16) return f64 ? assign_impl<double, 16>(P, b, ci, s) : assign_impl<float, 16>(P, b, ci, s);
-  return f64 ? assign_impl<double, kMaxCh>(P, b, ci, s) : assign_impl<float, kMaxCh>(P, b, ci, s);
+  if (nchx <= 8) return f64 ? assign_front_impl<double, 8>(P, b, ci, s) : assign_front_impl<float, 8>(P, b, ci, s);
+  if (nchx <= 16)
+    return f64 ? assign_front_impl<double, 16>(P, b, ci, s) : assign_front_impl<float, 16>(P, b, ci, s);
+  return f64 ? assign_front_impl<double, kMaxCh>(P, b, ci, s) : assign_front_impl<float, kMaxCh>(P, b, ci, s);
+}
+
+int run_assign_back(Plan& P, hipStream_t s) {
+  ChanInfo ci;
+  if (int rc = chan_info(P, &ci)) return rc;
+  const int nchx = ci.nch + (P.box_mode ? 0 : 1);
+  const bool f64 = P.precision == TSB_FP64;
+  if (nchx <= 8) return f64 ? assign_back_impl<double, 8>(P, ci, s) : assign_back_impl<float, 8>(P, ci, s);
+  if (nchx <= 16) return f64 ? assign_back_impl<double, 16>(P, ci, s) : assign_back_impl<float, 16>(P, ci, s);
+  return f64 ? assign_back_impl<double, kMaxCh>(P, ci, s) : assign_back_impl<float, kMaxCh>(P, ci, s);
 }
 
 int run_unpack_grids(Plan& P, void* out, hipStream_t s) {

@@ -150,6 +150,16 @@ struct Plan {
   void* d_work = nullptr;       // work items (tile, part) [work_cap]
   int64_t work_cap = 0;
   int tile_wgs = 0;             // resident workgroups of the tile kernel (from the occupancy query)
+  int64_t particle_gen = 0;     // bumped when particle buffers are reallocated
+
+  // launch machinery
+  bool use_graph = true;        // replay the fixed-shape part of a measurement as a graph
+  hipGraphExec_t graph_exec = nullptr;
+  int64_t graph_gen = -1;       // particle_gen the graph was captured with
+  hipStream_t cap_stream = nullptr;   // capture stream (never executes)
+  hipStream_t own_stream = nullptr;   // the plan's stream for batched measurements
+  void* h_res = nullptr;        // pinned result slots: [slot][outputs doubles + DevScalars]
+  int res_slots = 0;
   void* d_rec = nullptr;      // particle records in bucket order (u, channel weights), [cap][stride]
   int64_t particle_cap = 0;
   int red_chunk = 64, red_wg = 1024;
@@ -201,6 +211,7 @@ int run_reduce_final(Plan& P, hipStream_t s);
 void plan_fused(Plan& P);                   // fused.hip
 int run_fused(Plan& P, hipStream_t s);
 int run_ynode_fill(Plan& P, hipStream_t s);
+int run_assign_back(Plan& P, hipStream_t s);
 int64_t assign_work_cap(const Plan& P, int64_t particles);
 int record_stride(const Plan& P);
 int64_t assign_heavy_bytes(const Plan& P);

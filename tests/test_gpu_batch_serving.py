@@ -1,0 +1,110 @@
+"""Batched and served measurements through the C ABI.
+
+Every result must equal the plain single-catalogue measurement on the same
+inputs bitwise (the kernels are order-independent and each workspace is
+private), whether it ran through the captured graph, in a batch of mixed grid
+sizes, or on the server alone or in a mix of concurrent requests; one of them
+is also checked against the FP64 oracle.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from mocks import lognormal_box
+from oracle import estimator as est
+from tests.gpu_util import oracle_plan, pair_mask, normwise_errors, box_request
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+import paper_1803_02132_amd as tsb  # noqa: E402
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def _same(a, b):
+    return np.array_equal(np.nan_to_num(a, nan=7.0), np.nan_to_num(b, nan=7.0))
+
+
+def _cat(n, seed, n_target):
+    return lognormal_box(n, 1000.0, n_target, seed, rsd="local", observer=(500.0, 500.0, -1500.0))
+
+
+def _requests():
+    # three geometries: 32^3, 48^3 (radix 3), 64^3, TSC + interlacing, local LOS, FP32
+    return [box_request(n=32, n_bins=6), box_request(n=48, n_bins=6), box_request(n=64, n_bins=6)]
+
+
+def test_graph_equals_direct_launches():
+    req = box_request(n=32, n_bins=6)
+    plan_g, plan_d = tsb.Plan(**req), tsb.Plan(**req)
+    plan_d.set_graphs(False)
+    for k, (seed, n_target) in enumerate([(21, 8000), (22, 30000), (23, 12000)]):
+        _say("graph vs direct", seed, n_target)   # the second catalogue regrows the particle buffers
+        dev = tsb.catalog_to_device(_cat(32, seed, n_target))
+        a = plan_g.measure(dev)["B"]
+        b = plan_d.measure(dev)["B"]
+        assert _same(a, b), k
+
+
+def test_batch_of_mixed_grids_matches_single_measurements():
+    reqs = _requests()
+    plans = [tsb.Plan(**r) for r in reqs]
+    items = [(0, 31, 10000), (1, 32, 20000), (2, 33, 40000), (1, 34, 15000), (0, 35, 5000), (2, 36, 25000)]
+    devs, single = [], []
+    for gi, seed, n_target in items:
+        cat = _cat(reqs[gi]["n"], seed, n_target)
+        devs.append(tsb.catalog_to_device(cat))
+        single.append(plans[gi].measure(devs[-1])["B"])
+    _say("batch of", len(items))
+    out = tsb.measure_batch([plans[gi] for gi, _, _ in items], devs)
+    for k, o in enumerate(out):
+        assert _same(o["B"], single[k]), k
+    # the radix-3 grid against the oracle
+    gi, seed, n_target = items[1]
+    o = est.measure(oracle_plan(**reqs[gi]), _cat(reqs[gi]["n"], seed, n_target))
+    err = normwise_errors(out[1]["B"], o["B"], pair_mask(reqs[gi]["multipoles"], reqs[gi]["n_bins"]))
+    _say("48^3 batch item vs oracle", err)
+    assert np.all(err <= 1e-4)
+
+
+def test_server_alone_and_in_a_mix():
+    reqs = _requests()
+    tmpl = [tsb.Plan(**r) for r in reqs]
+    cats = {k: tsb.catalog_to_device(_cat(reqs[g]["n"], 40 + k, 12000 + 3000 * k)) for k, g in
+            enumerate([0, 1, 2, 0, 1])}
+    geo = [0, 1, 2, 0, 1]
+    srv = tsb.Server(8 << 30, 3)
+    try:
+        _say("server: alone")
+        lat_alone, alone = srv.wait(srv.submit(tmpl[0], cats[0]))
+        assert lat_alone > 0
+        _say("server: mix")
+        tickets = [(k, srv.submit(tmpl[geo[k]], cats[k])) for k in [1, 0, 2, 3, 0, 4, 2]]
+        res = [(k, srv.wait(t)) for k, t in tickets]
+        for k, (lat, B) in res:
+            ref = alone if k == 0 else tmpl[geo[k]].measure(cats[k])["B"]
+            assert _same(B, ref), k
+            assert lat > 0
+    finally:
+        srv.close()
+
+
+def test_server_rejects_what_cannot_fit():
+    req = box_request(n=32, n_bins=6)
+    plan = tsb.Plan(**req)
+    srv = tsb.Server(1 << 20, 2)   # 1 MiB: no workspace fits
+    try:
+        t = srv.submit(plan, tsb.catalog_to_device(_cat(32, 50, 5000)))
+        with pytest.raises(tsb.TsbError) as e:
+            srv.wait(t)
+        assert e.value.code == tsb.abi.TSB_E_NOMEM
+    finally:
+        srv.close()

@@ -214,3 +214,14 @@ def test_assignment_edges_wrap():
     pos = np.concatenate([pos, (rng.random((3000, 3)) * L).astype(np.float32)])
     _say("edges")
     _assign_vs_oracle(box_request(n=32, precision="f64"), {"pos": pos}, 1e-12)
+
+
+@pytest.mark.parametrize("precision,tol", [("f32", 1e-4), ("f64", 1e-9)])
+def test_radix3_grid(precision, tol):
+    # 48^3 = 2^4 3: the transforms take the radix-4/2/3 passes
+    req = box_request(n=48, n_bins=6, precision=precision)
+    cat = small_cat(n=48, n_target=30000, seed=13)
+    plan, g, o = run_both(req, cat)
+    err = normwise_errors(g["B"], o["B"], pair_mask(req["multipoles"], req["n_bins"]))
+    _say("48^3", precision, "errors", err, "M", plan.info.m)
+    assert np.all(err <= tol)
