@@ -232,6 +232,106 @@ def cpu_baseline(cat, threads=1):
                        f"sample took {sample_s:.0f} s")}
 
 
+# Batched mix (64 mocks of uneven grids): seed s < 24 at 128^3, s < 48 at 192^3,
+# else 256^3; particle counts log-uniform in [3e5, 3e6] from the seed.
+BATCH_CLASSES = [(128, range(0, 24)), (192, range(24, 48)), (256, range(48, 64))]
+
+
+def _pool(tsb, sizes, per_size):
+    """A pool of distinct seeded catalogues per grid size (device-resident):
+    {n: [(seed, n_particles, device catalogue), ...]}."""
+    from mocks.lognormal import workload
+    pool = {}
+    for n, seeds in sizes:
+        pool[n] = []
+        for s in list(seeds)[:per_size]:
+            _, cat = workload("box256", seed=s, n=n)
+            pool[n].append((s, len(cat["pos"]), tsb.catalog_to_device(cat)))
+            log(f"pool {n}^3 seed {s}: {len(cat['pos'])} particles")
+    return pool
+
+
+def batch_leg(tsb, torch, pool, per_size):
+    """64 mocks of mixed grids through tsb_measure_batch, against the same
+    measurements made one by one with tsb_measure."""
+    plans = {n: tsb.Plan(**dict(WORKLOAD, n=n)) for n, _ in BATCH_CLASSES}
+    items = []
+    for n, seeds in BATCH_CLASSES:
+        for s in seeds:
+            items.append((n, pool[n][s % per_size][2]))
+    ps = [plans[n] for n, _ in items]
+    ds = [d for _, d in items]
+    tsb.measure_batch(ps, ds)                    # warm-up: workspaces, graphs
+    for p, d in zip(ps, ds):
+        p.measure(d)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    tsb.measure_batch(ps, ds)
+    t_batch = time.perf_counter() - t0
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for p, d in zip(ps, ds):
+        p.measure(d)
+    t_plain = time.perf_counter() - t0
+    for p in plans.values():
+        p.close()
+    return {"mocks": len(items), "mix": "24 x 128^3, 24 x 192^3, 16 x 256^3",
+            "distinct_catalogues": sum(len(v) for v in pool.values()),
+            "batched_mocks_per_s": round(len(items) / t_batch, 2),
+            "plain_mocks_per_s": round(len(items) / t_plain, 2),
+            "batched_over_plain": round(t_plain / t_batch, 3)}
+
+
+def serve_leg(tsb, torch, pool, n_req, rate, slots, budget_gb):
+    """Poisson request stream (mean `rate` per second) over the pool's grid
+    sizes through the server; then the same requests submitted at once."""
+    rng = np.random.default_rng(2024)
+    sizes = sorted(pool)
+    tmpl = {n: tsb.Plan(**dict(WORKLOAD, n=n)) for n in sizes}
+    reqs = []
+    for _ in range(n_req):
+        n = sizes[rng.integers(len(sizes))]
+        reqs.append((n, pool[n][rng.integers(len(pool[n]))][2]))
+    srv = tsb.Server(int(budget_gb * (1 << 30)), slots)
+    try:
+        for n in sizes:                          # warm-up: one workspace per size
+            srv.wait(srv.submit(tmpl[n], pool[n][0][2]))
+        gaps = rng.exponential(1.0 / rate, size=n_req)
+        lat, pending = [], {}
+        t0 = time.perf_counter()
+        t_next = t0
+        for (n, d), gap in zip(reqs, gaps):
+            t_next += gap
+            while time.perf_counter() < t_next:
+                for t in list(pending):
+                    done, l, _ = srv.poll(t)
+                    if done:
+                        lat.append(l)
+                        pending.pop(t)
+                time.sleep(0.0005)
+            pending[srv.submit(tmpl[n], d)] = True
+        for t in list(pending):
+            lat.append(srv.wait(t)[0])
+        t_stream = time.perf_counter() - t0
+        # the same requests at once: continuous batching under load
+        t0 = time.perf_counter()
+        tickets = [srv.submit(tmpl[n], d) for n, d in reqs]
+        lat_burst = [srv.wait(t)[0] for t in tickets]
+        t_burst = time.perf_counter() - t0
+    finally:
+        srv.close()
+        for p in tmpl.values():
+            p.close()
+    ms = np.array(lat) * 1e3
+    mb = np.array(lat_burst) * 1e3
+    return {"requests": n_req, "rate_per_s": rate, "grids": [f"{n}^3" for n in sizes], "slots": slots,
+            "hbm_budget_gb": budget_gb,
+            "poisson": {"mocks_per_s": round(n_req / t_stream, 3), "p50_ms": round(float(np.percentile(ms, 50)), 3),
+                        "p99_ms": round(float(np.percentile(ms, 99)), 3)},
+            "burst": {"mocks_per_s": round(n_req / t_burst, 2), "p50_ms": round(float(np.percentile(mb, 50)), 3),
+                      "p99_ms": round(float(np.percentile(mb, 99)), 3)}}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -241,6 +341,12 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--unfused", action="store_true",
                     help="write the F fields to HBM and reduce in a separate pass (diagnostic)")
+    ap.add_argument("--no-batch", action="store_true", help="skip the batched 64-mock leg")
+    ap.add_argument("--no-serve", action="store_true", help="skip the serving leg")
+    ap.add_argument("--pool", type=int, default=2, help="distinct catalogues per grid size in those legs")
+    ap.add_argument("--serve-requests", type=int, default=64)
+    ap.add_argument("--serve-rate", type=float, default=4.0)
+    ap.add_argument("--serve-slots", type=int, default=4)
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a device copy of known size (calibrates HBM byte counters)")
     ap.add_argument("--ingest-pmc", nargs=3, metavar=("FETCH_CSV", "WRITE_CSV", "COMMAND"),
@@ -277,9 +383,11 @@ def main():
         f"workspace={info.workspace_bytes / 1e9:.2f} GB")
     if args.copy_probe:
         copy_probe()
+    # stage events ride inside the captured graph: turn them on before the
+    # warm-up so that the timed steps replay the same graph
+    tsb.abi.tsb_plan_set_profiling(plan.handle, True)
     for i in range(args.warmup):
         plan.measure(devs[i % len(devs)])
-    tsb.abi.tsb_plan_set_profiling(plan.handle, True)
     tsb.abi.tsb_plan_stage_times(plan.handle, reset=True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -315,6 +423,18 @@ def main():
         "roofline": roof,
         "stage_ms": {k: round(v, 4) for k, v in per_launch.items()},
     }
+    plan.close()
+    if not (args.no_batch and args.no_serve):
+        pool = _pool(tsb, [(n, seeds) for n, seeds in BATCH_CLASSES], args.pool)
+        if not args.no_batch:
+            log("batched leg ...")
+            out["batched"] = batch_leg(tsb, torch, pool, args.pool)
+            log(f"batched: {out['batched']}")
+        if not args.no_serve:
+            log("serving leg ...")
+            out["serving"] = serve_leg(tsb, torch, pool, args.serve_requests, args.serve_rate, args.serve_slots, 64)
+            log(f"serving: {out['serving']}")
+        del pool
     if not args.no_cpu_baseline:
         log("timing the oracle on the host ...")
         out["cpu_baseline"] = cpu_baseline(cats[0])

@@ -257,20 +257,36 @@ int run_back(Plan& P, hipStream_t s) {
   return TSB_OK;
 }
 
-// run_back through a graph captured once per plan and particle capacity
-// (direct launches while stage profiling is on).
+// run_back through a graph captured once per plan, particle capacity and
+// profiling state (with profiling on, the stage events are event-record nodes
+// of the graph, so stage times cover the replayed launches).
 int launch_back(Plan& P, hipStream_t s) {
-  if (P.prof || !P.use_graph) return run_back(P, s);
-  if (!P.graph_exec || P.graph_gen != P.particle_gen) {
+  if (!P.use_graph || (P.prof && P.prof_graph_failed)) return run_back(P, s);
+  if (!P.graph_exec || P.graph_gen != P.particle_gen || P.graph_prof != P.prof) {
     if (P.graph_exec) {
       TSB_HIP(hipGraphExecDestroy(P.graph_exec));
       P.graph_exec = nullptr;
     }
     if (!P.cap_stream) TSB_HIP(hipStreamCreateWithFlags(&P.cap_stream, hipStreamNonBlocking));
+    bool pending[kNumStages];
+    for (int st = 0; st < kNumStages; ++st) pending[st] = P.ev_pending[st];
     TSB_HIP(hipStreamBeginCapture(P.cap_stream, hipStreamCaptureModeThreadLocal));
     const int rc = run_back(P, P.cap_stream);
+    P.graph_stages = 0;
+    for (int st = 0; st < kNumStages; ++st) {
+      if (P.ev_pending[st] && !pending[st]) P.graph_stages |= 1u << st;
+      P.ev_pending[st] = pending[st];
+    }
     hipGraph_t g = nullptr;
     const hipError_t e = hipStreamEndCapture(P.cap_stream, &g);
+    if ((rc || e != hipSuccess || !g) && P.prof) {
+      // stage events could not ride in the graph: profile with direct launches
+      if (g) (void)hipGraphDestroy(g);
+      (void)hipGetLastError();
+      P.prof_graph_failed = true;
+      for (int st = 0; st < kNumStages; ++st) P.ev_pending[st] = pending[st];
+      return run_back(P, s);
+    }
     if (rc) {
       if (g) (void)hipGraphDestroy(g);
       return rc;
@@ -282,8 +298,11 @@ int launch_back(Plan& P, hipStream_t s) {
     if (ei != hipSuccess) return fail(TSB_E_DEVICE, std::string("graph instantiate: ") + hipGetErrorString(ei));
     P.graph_exec = ex;
     P.graph_gen = P.particle_gen;
+    P.graph_prof = P.prof;
   }
   TSB_HIP(hipGraphLaunch(P.graph_exec, s));
+  for (int st = 0; st < kNumStages; ++st)
+    if (P.graph_stages >> st & 1u) P.ev_pending[st] = true;
   return TSB_OK;
 }
 

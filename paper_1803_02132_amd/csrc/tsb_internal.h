@@ -156,6 +156,9 @@ struct Plan {
   bool use_graph = true;        // replay the fixed-shape part of a measurement as a graph
   hipGraphExec_t graph_exec = nullptr;
   int64_t graph_gen = -1;       // particle_gen the graph was captured with
+  bool graph_prof = false;      // the graph holds the stage-timing event records
+  uint32_t graph_stages = 0;    // stages whose events the graph records
+  bool prof_graph_failed = false;   // profiling falls back to direct launches
   hipStream_t cap_stream = nullptr;   // capture stream (never executes)
   hipStream_t own_stream = nullptr;   // the plan's stream for batched measurements
   void* h_res = nullptr;        // pinned result slots: [slot][outputs doubles + DevScalars]
@@ -182,13 +185,21 @@ struct Plan {
   int64_t stage_calls[kNumStages] = {};
 };
 
-// Bracket a stage with events when profiling is on (errors ignored: timing only).
+// Bracket a stage with events when profiling is on (errors ignored: timing
+// only). Inside a stream capture the record becomes an external event node of
+// the graph, so that replays record the event too.
+inline void prof_record(hipEvent_t e, hipStream_t s) {
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  (void)hipStreamIsCapturing(s, &cs);
+  if (cs == hipStreamCaptureStatusActive) (void)hipEventRecordWithFlags(e, s, hipEventRecordExternal);
+  else (void)hipEventRecord(e, s);
+}
 inline void prof_begin(Plan& P, int st, hipStream_t s) {
-  if (P.prof && P.ev[st][0]) (void)hipEventRecord(P.ev[st][0], s);
+  if (P.prof && P.ev[st][0]) prof_record(P.ev[st][0], s);
 }
 inline void prof_end(Plan& P, int st, hipStream_t s) {
   if (P.prof && P.ev[st][1]) {
-    (void)hipEventRecord(P.ev[st][1], s);
+    prof_record(P.ev[st][1], s);
     P.ev_pending[st] = true;
   }
 }
