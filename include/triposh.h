@@ -225,13 +225,15 @@ int tsb_plan_set_graphs(tsb_plan* plan, int32_t enable);
  * tsb_server_create starts a worker thread bound to the current device that
  * runs up to max_slots measurements at once, each on its own stream and its
  * own plan workspace, and keeps the plans of recently served geometries
- * resident. A request is admitted when a slot is free and the HBM footprint of
- * its workspace and particle buffers fits in hbm_budget_bytes together with
- * every resident workspace (idle workspaces of other geometries are released
- * to make room); requests are admitted in arrival order, except that a later
- * request whose geometry already has an idle workspace may start while an
- * earlier one waits for memory. Results are bitwise those of tsb_measure on
- * the same inputs, alone or in any mix.
+ * resident. A request runs on an idle workspace of its geometry, or on a new
+ * one when a slot is free and the HBM footprint of the workspace and its
+ * particle buffers fits in hbm_budget_bytes together with every resident
+ * workspace. Idle workspaces of other geometries are released (least recently
+ * used first) only for a geometry that has no workspace at all; otherwise the
+ * request waits for its geometry's workspace to free up. Requests are admitted
+ * in arrival order, except that a later request whose geometry has an idle
+ * workspace may start while an earlier one waits. Results are bitwise those of
+ * tsb_measure on the same inputs, alone or in any mix.
  *   tsb_server_submit: `plan` is a template (only its request is used; it is
  *     not touched by the server and may be destroyed after the call); data /
  *     randoms point to caller-owned device arrays that must stay valid, and

@@ -110,6 +110,22 @@ int plan_alloc(Plan& P, bool dry) {
   if ((rc = twiddles(&P.d_tw_n, P.N, f64, B, dry))) return rc;
   if ((rc = twiddles(&P.d_tw_m, P.M, f64, B, dry))) return rc;
   if ((rc = upload(&P.d_bin_lut, P.bin_lut, B, dry))) return rc;
+  {
+    // combine-step tables (eq. 39 and the interlace phase, per axis)
+    std::vector<double> tab(3 * (size_t)PG);
+    for (int64_t j = 0; j < PG; ++j) {
+      const long double n = (long double)(j - P.RG), x = n / (long double)N;
+      long double w = 1.0L;
+      if (j != P.RG) {
+        const long double sc = std::sin((long double)M_PI * x) / ((long double)M_PI * x);
+        for (int k = 0; k < P.p; ++k) w *= sc;
+      }
+      tab[j] = (double)(1.0L / w);
+      tab[PG + j] = (double)std::cos((long double)M_PI * x);
+      tab[2 * PG + j] = (double)std::sin((long double)M_PI * x);
+    }
+    if ((rc = upload(&P.d_axis_tab, tab, B, dry))) return rc;
+  }
   if ((rc = upload(&P.d_fkinds, P.fkinds, B, dry))) return rc;
   if ((rc = upload(&P.d_fcomp, P.fcomp, B, dry))) return rc;
   if ((rc = upload(&P.d_gcomp, P.gcomp, B, dry))) return rc;
@@ -136,7 +152,7 @@ void plan_free(Plan& P) {
                   P.d_tw_n, P.d_tw_m, P.d_bin_lut, P.d_fkinds, P.d_fcomp, P.d_gcomp, P.d_terms,
                   P.d_qgroups, P.d_outs, P.d_out_norm, P.d_partials, P.d_B, P.d_scal, P.d_sum_partials,
                   P.d_bk_count, P.d_bk_start, P.d_scan_part, P.d_keys, P.d_rec,
-                  P.d_f2idx, P.d_yspec, P.d_tile_parts, P.d_tile_hslot, P.d_tile_pstart, P.d_heavy_tile,
+                  P.d_f2idx, P.d_yspec, P.d_axis_tab, P.d_tile_parts, P.d_tile_hslot, P.d_tile_pstart, P.d_heavy_tile,
                   P.d_heavy, P.d_work};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
@@ -782,6 +798,12 @@ int place(Server& S, const Request& r, int* rc) {
     *rc = fail(TSB_E_NOMEM, "request does not fit the server's HBM budget");
     return -2;
   }
+  // a busy workspace of the same geometry will free up: wait for it rather
+  // than evict another geometry's workspace (no create/destroy churn)
+  bool same_geometry = false;
+  for (const Engine& e : S.engines) same_geometry = same_geometry || e.key == r.key;
+  const bool fits = (int)S.engines.size() < S.max_slots && used + need <= S.budget;
+  if (same_geometry && !fits) return -1;
   // release idle workspaces (least recently used first) until slots and bytes allow
   while ((int)S.engines.size() >= S.max_slots || used + need > S.budget) {
     int victim = -1;

@@ -531,13 +531,13 @@ template <typename T, int NCH>
 __global__ void __launch_bounds__(kTileBlock) assign_tile_kernel(TileArgs a, Records<T> rec) {
   typedef typename cplx<T>::type T2;
   extern __shared__ unsigned long long acc[];   // [nchx][T^3], one grid copy
-  __shared__ int r_start[kMaxRanges];
-  __shared__ int r_off[kMaxRanges + 1];
+  __shared__ int r_start[2][kMaxRanges];        // range tables of the current and the next work item
+  __shared__ int r_off[2][kMaxRanges + 1];
+  __shared__ int item[2][3];                    // tile, part, heavy slot
   __shared__ Visit<T, NCH> vis[kVisitChunk];
   __shared__ int it_first[kVisitChunk];      // first work item of each staged particle
   __shared__ int wtot[2];                     // items of each staging wavefront
   __shared__ double wsum[kTileBlock / 64];
-  __shared__ int item[3];                     // tile, part, heavy slot of the current work item
   __shared__ unsigned char it_vis[kVisitChunk * 3];
   const int TS = a.T, T3 = TS * TS * TS;
   const int nch = a.ci.nch;
@@ -550,8 +550,11 @@ __global__ void __launch_bounds__(kTileBlock) assign_tile_kernel(TileArgs a, Rec
   const size_t N3 = (size_t)N * N * N;
   const int stride[3] = {TS * TS, TS, 1};
   const double scale = a.scal->scale, inv_scale = a.scal->inv_scale;
-  // ranges of a work item, one per lane of the first wavefront, loaded one
-  // item ahead so that their latency overlaps the current item
+
+  // Work-item pipeline: the ranges of the next-but-one item are fetched into
+  // the first wavefront's registers, and the first chunk of particle records
+  // of the next item into the staging lanes' registers, while the current
+  // item is processed; the current item's first chunk serves both grid copies.
   int pf_tile = 0, pf_hs = -1, pf_part = 0, pf_st = 0, pf_len = 0;
   auto fetch = [&](int w) {
     if (threadIdx.x < 64 && w < nwork) {
@@ -564,32 +567,68 @@ __global__ void __launch_bounds__(kTileBlock) assign_tile_kernel(TileArgs a, Rec
       if (lane < a.nr) tile_range(a, wk.x, lane, &pf_st, &pf_len);
     }
   };
-  fetch(blockIdx.x);
+  auto publish = [&](int b) {   // the fetched item -> range table b (first wavefront)
+    if (threadIdx.x < 64) {
+      int inc = pf_len;
+      for (int off = 1; off < 64; off <<= 1) {
+        const int x = __shfl_up(inc, off);
+        if (lane >= off) inc += x;
+      }
+      r_start[b][lane] = pf_st;
+      r_off[b][lane + 1] = inc;
+      if (lane == 0) {
+        r_off[b][0] = 0;
+        item[b][0] = pf_tile;
+        item[b][1] = pf_part;
+        item[b][2] = pf_hs;
+      }
+    }
+  };
+  auto window = [&](int b, int* v0, int* v1) {   // visits of the item in table b
+    const int total = r_off[b][64], hs = item[b][2];
+    *v0 = hs >= 0 ? item[b][1] * kPartVisits : 0;
+    *v1 = hs >= 0 ? min(total, *v0 + kPartVisits) : total;
+  };
+  auto load_rec = [&](int b, int idx, double* u, T* cv) {   // visit idx of table b
+    int lo = 0, hi = a.nr;   // r_off[lo] <= idx < r_off[hi]
+    while (hi - lo > 1) {
+      const int mid = (lo + hi) >> 1;
+      if (r_off[b][mid] <= idx) lo = mid;
+      else hi = mid;
+    }
+    const int64_t slot = r_start[b][lo] + (idx - r_off[b][lo]);
+    const double* ru = rec.u(slot);
+    u[0] = ru[0];
+    u[1] = ru[1];
+    u[2] = ru[2];
+    const T* rc = rec.c(slot);
+#pragma unroll
+    for (int ch = 0; ch < NCH; ++ch) cv[ch] = ch < nchx ? rc[ch] : (T)0;
+  };
+  double cu[3] = {0.0, 0.0, 0.0}, nu[3] = {0.0, 0.0, 0.0};
+  T cc[NCH], ncv[NCH];
+#pragma unroll
+  for (int ch = 0; ch < NCH; ++ch) cc[ch] = ncv[ch] = (T)0;
+  int cb = 0;
+  if ((int)blockIdx.x < nwork) {
+    fetch(blockIdx.x);
+    publish(0);
+    __syncthreads();
+    if (threadIdx.x < kVisitChunk) {
+      int v0, v1;
+      window(0, &v0, &v1);
+      if (v0 + (int)threadIdx.x < v1) load_rec(0, v0 + threadIdx.x, cu, cc);
+    }
+    fetch(blockIdx.x + gridDim.x);
+  }
   for (int w = blockIdx.x; w < nwork; w += gridDim.x) {
   __syncthreads();   // the previous work item is done with the LDS
-  if (threadIdx.x < 64) {
-    int inc = pf_len;
-    for (int off = 1; off < 64; off <<= 1) {
-      const int x = __shfl_up(inc, off);
-      if (lane >= off) inc += x;
-    }
-    r_start[lane] = pf_st;
-    r_off[lane + 1] = inc;
-    if (lane == 0) {
-      r_off[0] = 0;
-      item[0] = pf_tile;
-      item[1] = pf_part;
-      item[2] = pf_hs;
-    }
-  }
-  fetch(w + gridDim.x);
-  __syncthreads();
-  const int tile = item[0], part = item[1], hs = item[2];   // hs >= 0: split tile, sums go to its slot
+  const int tile = item[cb][0], hs = item[cb][2];   // hs >= 0: split tile, sums go to its slot
   const int tx = tile / (NT * NT), ty = (tile / NT) % NT, tz = tile % NT;
   const int o3[3] = {tx * TS, ty * TS, tz * TS};
-  const int total = r_off[64];
-  const int v0 = hs >= 0 ? part * kPartVisits : 0;
-  const int v1 = hs >= 0 ? min(total, v0 + kPartVisits) : total;
+  int v0, v1;
+  window(cb, &v0, &v1);
+  const bool has_next = w + (int)gridDim.x < nwork;
   double sumI = 0.0;
   for (int g = 0; g < a.copies; ++g) {
     const int nc = g == 0 ? nchx : nch;   // the survey randoms channel lives on copy 0 only
@@ -602,20 +641,17 @@ __global__ void __launch_bounds__(kTileBlock) assign_tile_kernel(TileArgs a, Rec
         // two wavefronts: one particle per lane, then per-wavefront item prefixes
         const int v = threadIdx.x;
         if (v < nv) {
-          const int idx = c0 + v;   // bucket order: neighbouring lanes read neighbouring records
-          int lo = 0, hi = a.nr;   // r_off[lo] <= idx < r_off[hi]
-          while (hi - lo > 1) {
-            const int mid = (lo + hi) >> 1;
-            if (r_off[mid] <= idx) lo = mid;
-            else hi = mid;
-          }
-          const int64_t slot = r_start[lo] + (idx - r_off[lo]);
-          const double* ru = rec.u(slot);
-          const double u[3] = {ru[0], ru[1], ru[2]};
-          const T* rc = rec.c(slot);
+          double u[3];
           T cv[NCH];
+          if (c0 == v0) {   // the item's first chunk: already in registers
+            u[0] = cu[0];
+            u[1] = cu[1];
+            u[2] = cu[2];
 #pragma unroll
-          for (int ch = 0; ch < NCH; ++ch) cv[ch] = ch < nc ? rc[ch] : (T)0;
+            for (int ch = 0; ch < NCH; ++ch) cv[ch] = cc[ch];
+          } else {
+            load_rec(cb, c0 + v, u, cv);
+          }
           Visit<T, NCH>& V = vis[v];
           int cnt[3] = {0, 0, 0};
           if (isfinite(u[0])) {
@@ -702,7 +738,17 @@ __global__ void __launch_bounds__(kTileBlock) assign_tile_kernel(TileArgs a, Rec
         }
       }
     }
+    if (g == 0 && has_next) publish(cb ^ 1);
     __syncthreads();
+    if (g == 0 && has_next) {
+      // the next item's first chunk of records, loaded while this one finishes
+      if (threadIdx.x < kVisitChunk) {
+        int n0, n1;
+        window(cb ^ 1, &n0, &n1);
+        if (n0 + (int)threadIdx.x < n1) load_rec(cb ^ 1, n0 + threadIdx.x, nu, ncv);
+      }
+      fetch(w + 2 * gridDim.x);
+    }
     if (hs >= 0) {
       // part of a split tile: add the fixed-point sums into its slot (integer, order-free)
       unsigned long long* hb = a.heavy + ((size_t)hs * a.copies + g) * nchx * T3;
@@ -733,7 +779,7 @@ __global__ void __launch_bounds__(kTileBlock) assign_tile_kernel(TileArgs a, Rec
     __syncthreads();
   }
   if (!a.box_mode && hs < 0) {
-    // fixed-order sum: within each wavefront, then over the four wavefronts
+    // fixed-order sum: within each wavefront, then over the wavefronts
     for (int off = 32; off > 0; off >>= 1) sumI += __shfl_xor(sumI, off);
     if (lane == 0) wsum[threadIdx.x >> 6] = sumI;
     __syncthreads();
@@ -743,6 +789,13 @@ __global__ void __launch_bounds__(kTileBlock) assign_tile_kernel(TileArgs a, Rec
       a.tile_I[tile] = t;
     }
   }
+  // advance the pipeline
+  cb ^= 1;
+  cu[0] = nu[0];
+  cu[1] = nu[1];
+  cu[2] = nu[2];
+#pragma unroll
+  for (int ch = 0; ch < NCH; ++ch) cc[ch] = ncv[ch];
   }   // work items
 }
 

@@ -240,46 +240,44 @@ __global__ void __launch_bounds__(kBlock) fft_pass_kernel(PassArgs<T> a) {
 template <typename T>
 __global__ void __launch_bounds__(kBlock) combine_kernel(const typename cplx<T>::type* t3,
                                                          typename cplx<T>::type* spec, int ngrid,
-                                                         int copies, int R, int N, int p, int box_mode,
+                                                         int copies, int R, int box_mode,
+                                                         const double* axis_tab,
                                                          const typename cplx<T>::type* yspec,
                                                          const DevScalars* scal) {
+  // axis_tab: [P] 1/W_axis(n), then [P] cos(pi n/N), then [P] sin(pi n/N), n = index - R;
+  // W and the interlace phase factor over the three axes
   typedef typename cplx<T>::type T2;
   const int P = 2 * R + 1;
+  const double* iw = axis_tab;
+  const double* pc = axis_tab + P;
+  const double* ps = axis_tab + 2 * P;
   const int64_t P3 = (int64_t)P * P * P;
   const int64_t total = (int64_t)ngrid * P3;
+  const double mean = yspec ? scal->mean_cell : 0.0;
   for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < total; i += (int64_t)gridDim.x * kBlock) {
     const int g = (int)(i / P3);
-    const int64_t m = i % P3;
-    const int nx = (int)(m / ((int64_t)P * P)) - R, ny = (int)((m / P) % P) - R, nz = (int)(m % P) - R;
+    const int64_t m = i - g * P3;
+    const int ix = (int)(m / ((int64_t)P * P)), iy = (int)((m / P) % P), iz = (int)(m % P);
     const T2 v1 = t3[i];
     double re = v1.x, im = v1.y;
     if (copies == 2) {
       const T2 v2 = t3[(int64_t)ngrid * P3 + i];
-      double s, c;
-      sincospi((double)(nx + ny + nz) / (double)N, &s, &c);
-      re = 0.5 * (re + c * (double)v2.x - s * (double)v2.y);
-      im = 0.5 * (im + c * (double)v2.y + s * (double)v2.x);
+      // e^{i pi (nx+ny+nz)/N} as the product of the three axis phases
+      const double cxy = pc[ix] * pc[iy] - ps[ix] * ps[iy], sxy = pc[ix] * ps[iy] + ps[ix] * pc[iy];
+      const double c = cxy * pc[iz] - sxy * ps[iz], sn = cxy * ps[iz] + sxy * pc[iz];
+      re = 0.5 * (re + c * (double)v2.x - sn * (double)v2.y);
+      im = 0.5 * (im + c * (double)v2.y + sn * (double)v2.x);
     }
-    double W = 1.0;
-    const int n3[3] = {nx, ny, nz};
-    for (int ax = 0; ax < 3; ++ax) {
-      if (n3[ax] == 0) continue;
-      const double x = (double)n3[ax] / (double)N;
-      const double sc = sinpi(x) / (M_PI * x);
-      double wp = sc;
-      for (int k = 1; k < p; ++k) wp *= sc;
-      W *= wp;
-    }
-    re /= W;
-    im /= W;
+    const double inv_w = iw[ix] * iw[iy] * iw[iz];
+    re *= inv_w;
+    im *= inv_w;
     if (yspec) {
       // box mode: minus (sum w / N^3) times the same transform of y_L^M*(x^_node)
-      const double mean = scal->mean_cell;
       const T2 y = yspec[i];
       re -= mean * (double)y.x;
       im -= mean * (double)y.y;
     }
-    if (box_mode && g == 0 && nx == 0 && ny == 0 && nz == 0) re = 0.0;
+    if (box_mode && g == 0 && ix == R && iy == R && iz == R) re = 0.0;
     T2 o;
     o.x = (T)re;
     o.y = (T)im;
@@ -502,7 +500,7 @@ int forward_impl(Plan& P, hipStream_t s) {
   const int64_t total = (int64_t)P.grids.size() * PG * PG * PG;
   prof_begin(P, kStCombine, s);
   hipLaunchKernelGGL(combine_kernel<T>, dim3(grid_blocks(total)), dim3(kBlock), 0, s, (const T2*)P.d_t3,
-                     (T2*)P.d_spec, (int)P.grids.size(), P.copies, RG, N, P.p, P.box_mode,
+                     (T2*)P.d_spec, (int)P.grids.size(), P.copies, RG, P.box_mode, (const double*)P.d_axis_tab,
                      P.yspec_ready ? (const T2*)P.d_yspec : (const T2*)nullptr, (const DevScalars*)P.d_scal);
   const int64_t pf3 = (int64_t)P.PF * P.PF * P.PF;
   hipLaunchKernelGGL(dcube_kernel<T>, dim3(grid_blocks(pf3)), dim3(kBlock), 0, s, (const T2*)P.d_spec,

@@ -134,6 +134,7 @@ struct Plan {
   double* d_B = nullptr;
   DevScalars* d_scal = nullptr;
   double* d_sum_partials = nullptr;   // per-block partial sums (prep and I)
+  double* d_axis_tab = nullptr;   // per stored axis mode: 1/W_axis, cos and sin of pi n/N
   void* d_yspec = nullptr;      // box mode, local LOS: combined spectra of y_L^M*(x^_node) [ngrid][PG^3]
   bool yspec_ready = false;     // subtract mean * d_yspec in the combine step
   int* d_bk_count = nullptr;    // particles per (tile, reach class) bucket [nbk]
