@@ -81,13 +81,14 @@ int plan_alloc(Plan& P, bool dry) {
 #define ALLOC(ptr, n) \
   if ((rc = dalloc((void**)&(ptr), (n), B, dry))) return rc
   ALLOC(P.d_grid, nbc * N * N * N * c);
-  ALLOC(P.d_t1, nbc * N * N * PG * c);
-  ALLOC(P.d_t2, nbc * N * PG * PG * c);
+  const int64_t PGs = pad_line(PG), PFs = pad_line(PF);
+  ALLOC(P.d_t1, nbc * N * N * PGs * c);
+  ALLOC(P.d_t2, nbc * N * PG * PGs * c);
   ALLOC(P.d_t3, nbc * PG * PG * PG * c);
   ALLOC(P.d_spec, ng * PG * PG * PG * c);
   ALLOC(P.d_dcube, PF * PF * PF * c);
-  ALLOC(P.d_u1, std::max(nf * PF * PF * M, ng * PG * PG * M) * c);
-  ALLOC(P.d_u2, std::max(nf * PF * M * M, ng * PG * M * M) * c);
+  ALLOC(P.d_u1, std::max(nf * PF * PFs * M, ng * PG * PGs * M) * c);
+  ALLOC(P.d_u2, std::max(nf * PFs * M * M, ng * PGs * M * M) * c);
   ALLOC(P.d_fields, ((P.fused ? 0 : nf) + ng) * M * M * M * c);
   if (P.box_mode && P.los_kind == TSB_LOS_LOCAL) ALLOC(P.d_yspec, ng * PG * PG * PG * c);
   const int64_t ntiles = (int64_t)P.NT * P.NT * P.NT;

@@ -455,6 +455,7 @@ template <typename T>
 int forward_impl(Plan& P, hipStream_t s) {
   typedef typename cplx<T>::type T2;
   const int N = P.N, PG = P.PG, RG = P.RG;
+  const int64_t PGs = pad_line(PG);   // stored innermost extent of the pass buffers
   const int nbc = P.copies * (int)P.grids.size();
   const int64_t N2 = (int64_t)N * N, N3 = N2 * N;
   int rc;
@@ -466,7 +467,7 @@ int forward_impl(Plan& P, hipStream_t s) {
     a.tw = (const T2*)P.d_tw_n;
     a.nbatch = nbc; a.dA = N; a.dB = N;
     a.in_bs = N3; a.in_sa = N2; a.in_sb = N; a.in_se = 1;
-    a.out_bs = N2 * PG; a.out_sa = (int64_t)N * PG; a.out_sb = PG; a.out_se = 1;
+    a.out_bs = N2 * PGs; a.out_sa = (int64_t)N * PGs; a.out_sb = PGs; a.out_se = 1;
     a.in_cnt = N; a.in_off = 0; a.out_cnt = PG; a.out_off = RG;
     a.N = N; a.dir = -1; a.contiguous = 1;
     if ((rc = launch_pass<T>(P, kStFwdZ, a, s))) return rc;
@@ -478,8 +479,8 @@ int forward_impl(Plan& P, hipStream_t s) {
     a.out = (T2*)P.d_t2;
     a.tw = (const T2*)P.d_tw_n;
     a.nbatch = nbc; a.dA = N; a.dB = PG;
-    a.in_bs = N2 * PG; a.in_sa = (int64_t)N * PG; a.in_sb = 1; a.in_se = PG;
-    a.out_bs = (int64_t)N * PG * PG; a.out_sa = (int64_t)PG * PG; a.out_sb = 1; a.out_se = PG;
+    a.in_bs = N2 * PGs; a.in_sa = (int64_t)N * PGs; a.in_sb = 1; a.in_se = PGs;
+    a.out_bs = (int64_t)N * PG * PGs; a.out_sa = (int64_t)PG * PGs; a.out_sb = 1; a.out_se = PGs;
     a.in_cnt = N; a.in_off = 0; a.out_cnt = PG; a.out_off = RG;
     a.N = N; a.dir = -1; a.contiguous = 0;
     if ((rc = launch_pass<T>(P, kStFwdY, a, s))) return rc;
@@ -491,7 +492,7 @@ int forward_impl(Plan& P, hipStream_t s) {
     a.out = (T2*)P.d_t3;
     a.tw = (const T2*)P.d_tw_n;
     a.nbatch = nbc; a.dA = PG; a.dB = PG;
-    a.in_bs = (int64_t)N * PG * PG; a.in_sa = PG; a.in_sb = 1; a.in_se = (int64_t)PG * PG;
+    a.in_bs = (int64_t)N * PG * PGs; a.in_sa = PGs; a.in_sb = 1; a.in_se = (int64_t)PG * PGs;
     a.out_bs = (int64_t)PG * PG * PG; a.out_sa = PG; a.out_sb = 1; a.out_se = (int64_t)PG * PG;
     a.in_cnt = N; a.in_off = 0; a.out_cnt = PG; a.out_off = RG;
     a.N = N; a.dir = -1; a.contiguous = 0;
@@ -519,7 +520,7 @@ int inverse_chain(Plan& P, int stage0, const typename cplx<T>::type* cube, int64
                   int R, PassArgs<T> pre, typename cplx<T>::type* fields, bool last_pass, hipStream_t s) {
   typedef typename cplx<T>::type T2;
   const int M = P.M, PR = 2 * R + 1;
-  const int64_t M2 = (int64_t)M * M, PR2 = (int64_t)PR * PR;
+  const int64_t M2 = (int64_t)M * M, PR2 = (int64_t)PR * PR, PRs = pad_line(PR);
   int rc;
   // x with the pre-operation: [b][qx][qy][qz] -> [b][x][qy][qz]
   {
@@ -529,7 +530,7 @@ int inverse_chain(Plan& P, int stage0, const typename cplx<T>::type* cube, int64
     a.tw = (const T2*)P.d_tw_m;
     a.nbatch = nbatch; a.dA = PR; a.dB = PR;
     a.in_bs = cube_bs; a.in_sa = PR; a.in_sb = 1; a.in_se = PR2;
-    a.out_bs = (int64_t)M * PR2; a.out_sa = PR; a.out_sb = 1; a.out_se = PR2;
+    a.out_bs = (int64_t)M * PR * PRs; a.out_sa = PRs; a.out_sb = 1; a.out_se = PR * PRs;
     a.in_cnt = PR; a.in_off = R; a.out_cnt = M; a.out_off = 0;
     a.offA = R; a.offB = R; a.offE = R;
     a.axA = 1; a.axB = 2; a.axE = 0;
@@ -543,8 +544,8 @@ int inverse_chain(Plan& P, int stage0, const typename cplx<T>::type* cube, int64
     a.out = (T2*)P.d_u2;
     a.tw = (const T2*)P.d_tw_m;
     a.nbatch = nbatch; a.dA = M; a.dB = PR;
-    a.in_bs = (int64_t)M * PR2; a.in_sa = PR2; a.in_sb = 1; a.in_se = PR;
-    a.out_bs = M2 * PR; a.out_sa = (int64_t)M * PR; a.out_sb = 1; a.out_se = PR;
+    a.in_bs = (int64_t)M * PR * PRs; a.in_sa = PR * PRs; a.in_sb = 1; a.in_se = PRs;
+    a.out_bs = M2 * PRs; a.out_sa = (int64_t)M * PRs; a.out_sb = 1; a.out_se = PRs;
     a.in_cnt = PR; a.in_off = R; a.out_cnt = M; a.out_off = 0;
     a.N = M; a.dir = 1; a.contiguous = 0;
     if ((rc = launch_pass<T>(P, stage0 + 1, a, s))) return rc;
@@ -556,7 +557,7 @@ int inverse_chain(Plan& P, int stage0, const typename cplx<T>::type* cube, int64
     a.out = fields;
     a.tw = (const T2*)P.d_tw_m;
     a.nbatch = nbatch; a.dA = M; a.dB = M;
-    a.in_bs = M2 * PR; a.in_sa = (int64_t)M * PR; a.in_sb = PR; a.in_se = 1;
+    a.in_bs = M2 * PRs; a.in_sa = (int64_t)M * PRs; a.in_sb = PRs; a.in_se = 1;
     a.out_bs = M2 * M; a.out_sa = M2; a.out_sb = M; a.out_se = 1;
     a.in_cnt = PR; a.in_off = R; a.out_cnt = M; a.out_off = 0;
     a.N = M; a.dir = 1; a.contiguous = 1;

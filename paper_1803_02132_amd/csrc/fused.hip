@@ -34,7 +34,7 @@ struct FusedArgs {
   const T2* u2;        // F slots after the x and y passes: [nf][M][M][PF]
   const T2* gfields;   // G grids [ngrid][M^3]
   const T2* tw;        // e^{-2 pi i k / M}
-  int RF, PF, nb, nkinds, ngrid, ngc, nq, nf2, bpg;
+  int RF, PF, PFs, nb, nkinds, ngrid, ngc, nq, nf2, bpg;   // PFs: stored line stride of u2
   int ksplit;          // matrix-core contraction: cell-range splits per Q group
   const OutEntry* outs;
   int nout;
@@ -97,7 +97,7 @@ __global__ void __launch_bounds__(kBlock) fz_reduce_kernel(FusedArgs<T> a) {
       for (int task = tid; task < nsl * N1; task += kBlock) {
         const int sl = task / N1, n1 = task - sl * N1;
         const int64_t slot = (int64_t)b0 * nk + sl;
-        const T2* src = a.u2 + (slot * M * M + line) * a.PF;
+        const T2* src = a.u2 + (slot * M * M + line) * a.PFs;
         T2 v[N2];
 #pragma unroll
         for (int n2 = 0; n2 < N2; ++n2) {
@@ -287,7 +287,7 @@ __global__ void __launch_bounds__(kWBlock) fz_reduce_wide_kernel(FusedArgs<float
   float gpre[kWGPre];
   auto prefetch = [&](int64_t line) {
     if (has_task) {
-      const T2* src = a.u2 + ((int64_t)sl * M * M + line) * a.PF;
+      const T2* src = a.u2 + ((int64_t)sl * M * M + line) * a.PFs;
 #pragma unroll
       for (int n2 = 0; n2 < N2; ++n2) {
         int e = n1 + N1 * n2 + a.RF;
@@ -482,6 +482,7 @@ int fused_launch(Plan& P, hipStream_t s) {
   a.tw = (const T2*)P.d_tw_m;
   a.RF = P.RF;
   a.PF = P.PF;
+  a.PFs = (int)pad_line(P.PF);
   a.nb = P.nb;
   a.nkinds = (int)P.fkinds.size();
   a.ngrid = (int)P.grids.size();

@@ -205,6 +205,10 @@ inline void prof_end(Plan& P, int st, hipStream_t s) {
   }
 }
 
+// Stored innermost extent of the pruned pass buffers: rows padded to 16
+// elements so that groups of 16 consecutive entries start on 128-byte lines.
+inline int64_t pad_line(int64_t n) { return (n + 15) / 16 * 16; }
+
 int plan_build(Plan& P);   // host planning (plan.hip)
 // (-1)^m sqrt((l-m)!/(l+m)!) at index l(l+1)/2 + m, l <= kMaxEll (45 entries)
 void ylm_norm_table(double* norm);
