@@ -103,7 +103,7 @@ int plan_alloc(Plan& P, bool dry) {
   ALLOC(P.d_heavy_tile, (int64_t)assign_max_heavy() * 4);
   ALLOC(P.d_heavy, assign_heavy_bytes(P));
   ALLOC(P.d_scal, (int64_t)sizeof(DevScalars));
-  ALLOC(P.d_sum_partials, std::max<int64_t>(ntiles, 4 * 512) * 8);
+  ALLOC(P.d_sum_partials, std::max<int64_t>(ntiles, 8 * 512) * 8);
   ALLOC(P.d_partials, (int64_t)P.red_wg * std::max<int64_t>((int64_t)P.outs.size(), 1) * 8);
   ALLOC(P.d_B, std::max<int64_t>((int64_t)P.outs.size(), 1) * 8);
 #undef ALLOC

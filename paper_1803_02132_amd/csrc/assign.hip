@@ -4,11 +4,15 @@
 // Assignment is a gather over tiles: particles are bucketed by the T^3 tile of
 // their cell and by which neighbouring tiles their stencils reach, and one
 // workgroup per output tile scatters into LDS the particles of its own tile
-// and those of its 26 neighbours that reach it. Contributions are rounded to 64-bit fixed
-// point (scale 2^e with sum|w| 2^e < 2^61 in FP64 plans, 2^51 in FP32 plans)
-// and added with integer LDS atomics,
-// so every grid value is independent of thread and bucket order: the result is
-// bitwise reproducible.
+// and those of its 26 neighbours that reach it. Contributions are rounded to
+// fixed point and added with integer LDS atomics, so every grid value is
+// independent of thread and bucket order: the result is bitwise reproducible.
+// One 64-bit word per channel at a plan-wide scale 2^e, with sum|w| 2^e below
+// 2^61 (FP64 plans) or 2^51 (FP32 plans); in FP32 plans, tiles that run as a
+// single work item instead add the two channels of a complex grid into one
+// word as two 32-bit sums at a per-tile scale (half the atomics). The survey
+// randoms channel, which feeds the normalisation, always keeps its own word
+// at the plan-wide scale.
 #include <cmath>
 
 #include "tsb_internal.h"
@@ -48,25 +52,31 @@ struct PrepArgs {
   double P0, inv_h, origin[3], obs[3];
   int N, box_mode, local;
   DevScalars* scal;
-  double* partials;   // [gridDim][4]
+  double* partials;   // [gridDim][kPrepVals]
 };
 
-__device__ inline void block_sum4(double* v, double* sh) {
+// Per-block reduction of the weights: sum w and sum |w| of data and randoms,
+// then max |w| of data and randoms.
+constexpr int kPrepVals = 6;
+
+__device__ inline void block_reduce_prep(double* v, double* sh) {
   // fixed-order tree over the block
   const int t = threadIdx.x;
-  for (int k = 0; k < 4; ++k) sh[k * kBlock + t] = v[k];
+  for (int k = 0; k < kPrepVals; ++k) sh[k * kBlock + t] = v[k];
   __syncthreads();
   for (int s = kBlock / 2; s > 0; s >>= 1) {
-    if (t < s)
+    if (t < s) {
       for (int k = 0; k < 4; ++k) sh[k * kBlock + t] += sh[k * kBlock + t + s];
+      for (int k = 4; k < kPrepVals; ++k) sh[k * kBlock + t] = fmax(sh[k * kBlock + t], sh[k * kBlock + t + s]);
+    }
     __syncthreads();
   }
-  for (int k = 0; k < 4; ++k) v[k] = sh[k * kBlock];
+  for (int k = 0; k < kPrepVals; ++k) v[k] = sh[k * kBlock];
 }
 
 __global__ void __launch_bounds__(kBlock) prep_kernel(PrepArgs a) {
-  __shared__ double sh[4 * kBlock];
-  double v[4] = {0.0, 0.0, 0.0, 0.0};
+  __shared__ double sh[kPrepVals * kBlock];
+  double v[kPrepVals] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
   int err = 0;
   const int64_t ntot = a.d.n + a.r.n;
   for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < ntot;
@@ -89,25 +99,29 @@ __global__ void __launch_bounds__(kBlock) prep_kernel(PrepArgs a) {
     if (ran) {
       v[1] += w;
       v[3] += fabs(w);
+      v[5] = fmax(v[5], fabs(w));
     } else {
       v[0] += w;
       v[2] += fabs(w);
+      v[4] = fmax(v[4], fabs(w));
     }
   }
   if (err) atomicOr(&a.scal->err, err);
-  block_sum4(v, sh);
+  block_reduce_prep(v, sh);
   if (threadIdx.x == 0)
-    for (int k = 0; k < 4; ++k) a.partials[blockIdx.x * 4 + k] = v[k];
+    for (int k = 0; k < kPrepVals; ++k) a.partials[blockIdx.x * kPrepVals + k] = v[k];
 }
 
 __global__ void __launch_bounds__(kBlock) prep_final_kernel(const double* partials, int nblocks,
                                                             DevScalars* scal, int box_mode,
                                                             double n3, double volume, int fixed_bits) {
-  __shared__ double sh[4 * kBlock];
-  double v[4] = {0.0, 0.0, 0.0, 0.0};
-  for (int b = threadIdx.x; b < nblocks; b += kBlock)
-    for (int k = 0; k < 4; ++k) v[k] += partials[b * 4 + k];
-  block_sum4(v, sh);
+  __shared__ double sh[kPrepVals * kBlock];
+  double v[kPrepVals] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  for (int b = threadIdx.x; b < nblocks; b += kBlock) {
+    for (int k = 0; k < 4; ++k) v[k] += partials[b * kPrepVals + k];
+    for (int k = 4; k < kPrepVals; ++k) v[k] = fmax(v[k], partials[b * kPrepVals + k]);
+  }
+  block_reduce_prep(v, sh);
   if (threadIdx.x == 0) {
     scal->sum_w = v[0];
     scal->sum_w_ran = v[1];
@@ -115,6 +129,9 @@ __global__ void __launch_bounds__(kBlock) prep_final_kernel(const double* partia
     scal->sum_abs_ran = v[3];
     const double alpha = box_mode ? 0.0 : (v[1] != 0.0 ? v[0] / v[1] : 0.0);   // Sec. 4.1
     scal->alpha = alpha;
+    // |y_L^M| <= 1 (Racah normalisation), so |c| <= max |w| (data) and
+    // |alpha| max |w| (randoms)
+    scal->cmax = fmax(v[4], fabs(alpha) * v[5]);
     const double wtot = v[2] + fabs(alpha) * v[3];
     int e = 40;
     if (wtot > 0.0 && isfinite(wtot)) {
@@ -362,7 +379,10 @@ __device__ inline void channel_values(const ChanInfo& ci, double x, double y, do
 
 // Particle records in bucket order, one contiguous record each: the grid
 // coordinate u (3 FP64; NaN in u_x marks a particle that takes no part), then
-// its channel weights in the plan precision; stride a multiple of 16 bytes.
+// its channel weights in the plan precision in slot order: slots 2g and 2g+1
+// hold the real and imaginary channel of complex grid g (0 where grid g has no
+// imaginary channel), and in survey mode slot 2 ngrid the randoms channel;
+// stride a multiple of 16 bytes.
 template <typename T>
 struct Records {
   char* base;
@@ -378,6 +398,8 @@ struct FillArgs {
   ChanInfo ci;
   Records<T> rec;
   int nchx;
+  int slot_of[kMaxCh];   // channel -> record slot
+  int zslot;             // slot that stays 0 (a grid without imaginary channel), or -1
   const DevScalars* scal;
 };
 
@@ -409,9 +431,11 @@ __global__ void __launch_bounds__(kBlock) bucket_fill_kernel(FillArgs<T, NCH> a)
     ru[2] = u[2];
     double cv[NCH];
     channel_values<NCH>(a.ci, c.x[j], c.y[j], c.z[j], ok ? w : 0.0, ran, alpha, cv);
+    T* rc = a.rec.c(slot);
 #pragma unroll
     for (int ch = 0; ch < NCH; ++ch)
-      if (ch < a.nchx) a.rec.c(slot)[ch] = (T)cv[ch];
+      if (ch < a.nchx) rc[a.slot_of[ch]] = (T)cv[ch];
+    if (a.zslot >= 0) rc[a.zslot] = (T)0;
   }
 }
 
@@ -424,8 +448,10 @@ struct TileArgs {
   double inv_h, h, origin[3];
   int N, T, NT, p, copies, box_mode;
   ChanInfo ci;
-  int ngrid;
-  int gre[kMaxGrids], gim[kMaxGrids];
+  int ngrid;                   // complex output grids (record slots 2g, 2g+1)
+  int nw;                      // 64-bit fixed-point words per node
+  double wmax;                 // largest node weight of the kernel (p = 3: 0.75^3)
+  int wr;                      // word of the survey randoms channel, or -1
   const int* start;            // bucket starts [ntiles * 27 + 1]
   const DevScalars* scal;
   void* out;                   // [copies][ngrid][N^3] complex
@@ -437,7 +463,7 @@ struct TileArgs {
   const int2* work;
   const int* nwork;            // number of work items (device)
   const int* hslot;            // per tile: heavy slot or -1
-  unsigned long long* heavy;   // [slot][copies][nchx][T^3] fixed-point sums of split tiles
+  unsigned long long* heavy;   // [slot][copies][nw][T^3] fixed-point sums of split tiles
 };
 
 // Ranges of one tile (wave-parallel): start and length of range r of tile t.
@@ -495,9 +521,9 @@ struct alignas(16) Visit {
   unsigned char cnt[3];
 };
 
-// Fixed-point rounding. FP64 plans: 2^61 / sum|w| resolution, llrint. FP32
-// plans: 2^51 / sum|w|, so |x| < 2^51 and adding 1.5 * 2^52 leaves
-// round-to-nearest(x) in the low mantissa bits (exact).
+// Fixed-point rounding to the nearest integer. FP64 plans: llrint. FP32 plans:
+// |x| < 2^51, so adding 1.5 * 2^52 leaves round-to-nearest(x) in the low
+// mantissa bits (exact).
 template <typename T>
 __device__ inline long long to_fixed(double x) {
   if constexpr (sizeof(T) == 4) {
@@ -507,17 +533,53 @@ __device__ inline long long to_fixed(double x) {
   }
 }
 
-// Fixed point back to the plan precision. FP32: the high word (|v| < 2^51, so
-// below 2^19) converts exactly and the low word rounds once more; FP64: exact
-// to one rounding.
+// Packed FP32 tiles add the two channels of a complex grid in one 64-bit
+// word: word = hi 2^32 + lo (two's complement, modulo 2^64), with both sums
+// below 2^31 in magnitude, so each is recovered exactly from the total. The
+// low dword is lo, the high dword hi - 1 when lo < 0.
+__device__ inline unsigned long long pack2(int lo, int hi) {
+  return ((unsigned long long)(unsigned)(hi + (lo >> 31)) << 32) | (unsigned)lo;
+}
+
+__device__ inline void unpack2(unsigned long long v, int* lo, int* hi) {
+  *lo = (int)(unsigned)v;
+  *hi = (int)(unsigned)(v >> 32) - (*lo >> 31);
+}
+
+// Exponent of the per-tile fixed-point scale of packed FP32 tiles: each
+// half-word sum is bounded by (visits of the tile) * max |c| * (largest node
+// weight of the kernel), and the scale maps that bound below 2^30. A
+// contribution is the FP32 product c W 2^e rounded to the nearest integer
+// (ties to even), so the rounding errors carry no bias. Packing is used for
+// tiles of at most kPartVisits visits (those that run as one work item), so
+// the fixed-point step is at most 2^-22 max |c| W_max.
+__device__ inline int tile_exponent(int visits, double cw) {
+  const double bound = (double)visits * cw;
+  if (!(bound > 0.0) || !isfinite(bound)) return 0;
+  int ex;
+  frexp(bound, &ex);   // bound < 2^ex
+  return min(100, max(-100, 30 - ex));
+}
+
+// One grid copy's fixed-point words of a node -> the complex output grids:
+// packed (word g holds grid g, tile scale) or one word per channel slot
+// (words 2g and 2g+1, plan-wide scale).
 template <typename T>
-__device__ inline T from_fixed(long long v, double inv_scale) {
-  if constexpr (sizeof(T) == 4) {
-    const float s = (float)inv_scale;   // a power of two
-    const float hi = (float)(int)(v >> 32), lo = (float)(unsigned)(v & 0xffffffffLL);
-    return fmaf(hi, 4294967296.0f * s, lo * s);
-  } else {
-    return (double)v * inv_scale;
+__device__ inline void put_node(const unsigned long long* w, size_t wstride, int ngrid, bool packed, int et_neg,
+                                double inv_scale, typename cplx<T>::type* out, size_t gstride) {
+  typedef typename cplx<T>::type T2;
+  for (int gr = 0; gr < ngrid; ++gr) {
+    T2 o;
+    if (packed) {
+      int lo, hi;
+      unpack2(w[(size_t)gr * wstride], &lo, &hi);
+      o.x = (T)ldexpf((float)lo, et_neg);
+      o.y = (T)ldexpf((float)hi, et_neg);
+    } else {
+      o.x = (T)((double)(long long)w[(size_t)(2 * gr) * wstride] * inv_scale);
+      o.y = (T)((double)(long long)w[(size_t)(2 * gr + 1) * wstride] * inv_scale);
+    }
+    out[(size_t)gr * gstride] = o;
   }
 }
 
@@ -530,7 +592,7 @@ __device__ inline T from_fixed(long long v, double inv_scale) {
 template <typename T, int NCH>
 __global__ void __launch_bounds__(kTileBlock) assign_tile_kernel(TileArgs a, Records<T> rec) {
   typedef typename cplx<T>::type T2;
-  extern __shared__ unsigned long long acc[];   // [nchx][T^3], one grid copy
+  extern __shared__ unsigned long long acc[];   // [nw][T^3], one grid copy
   __shared__ int r_start[2][kMaxRanges];        // range tables of the current and the next work item
   __shared__ int r_off[2][kMaxRanges + 1];
   __shared__ int item[2][3];                    // tile, part, heavy slot
@@ -540,8 +602,8 @@ __global__ void __launch_bounds__(kTileBlock) assign_tile_kernel(TileArgs a, Rec
   __shared__ double wsum[kTileBlock / 64];
   __shared__ unsigned char it_vis[kVisitChunk * 3];
   const int TS = a.T, T3 = TS * TS * TS;
-  const int nch = a.ci.nch;
-  const int nchx = nch + (a.box_mode ? 0 : 1);
+  const int npair = a.ngrid, nw = a.nw, wr = a.wr;
+  const int nslot = 2 * npair;   // grid slots; the randoms slot sits in register NCH - 1
   const int nwork = *a.nwork;
   const int N = a.N, p = a.p;
   const int NT = a.NT;
@@ -549,7 +611,7 @@ __global__ void __launch_bounds__(kTileBlock) assign_tile_kernel(TileArgs a, Rec
   T2* out = (T2*)a.out;
   const size_t N3 = (size_t)N * N * N;
   const int stride[3] = {TS * TS, TS, 1};
-  const double scale = a.scal->scale, inv_scale = a.scal->inv_scale;
+  const double scale = a.scal->scale, inv_scale = a.scal->inv_scale, cmax = a.scal->cmax;
 
   // Work-item pipeline: the ranges of the next-but-one item are fetched into
   // the first wavefront's registers, and the first chunk of particle records
@@ -603,7 +665,8 @@ __global__ void __launch_bounds__(kTileBlock) assign_tile_kernel(TileArgs a, Rec
     u[2] = ru[2];
     const T* rc = rec.c(slot);
 #pragma unroll
-    for (int ch = 0; ch < NCH; ++ch) cv[ch] = ch < nchx ? rc[ch] : (T)0;
+    for (int ch = 0; ch < NCH; ++ch) cv[ch] = ch < nslot ? rc[ch] : (T)0;
+    if (wr >= 0) cv[NCH - 1] = rc[nslot];
   };
   double cu[3] = {0.0, 0.0, 0.0}, nu[3] = {0.0, 0.0, 0.0};
   T cc[NCH], ncv[NCH];
@@ -628,11 +691,15 @@ __global__ void __launch_bounds__(kTileBlock) assign_tile_kernel(TileArgs a, Rec
   const int o3[3] = {tx * TS, ty * TS, tz * TS};
   int v0, v1;
   window(cb, &v0, &v1);
+  // FP32 tiles that run whole: two channels per word at the tile's own scale
+  const bool packed = sizeof(T) == 4 && r_off[cb][64] <= kPartVisits;
+  const int et = packed ? tile_exponent(r_off[cb][64], cmax * a.wmax) : 0;
+  const float tscale = ldexpf(1.0f, et);
   const bool has_next = w + (int)gridDim.x < nwork;
   double sumI = 0.0;
   for (int g = 0; g < a.copies; ++g) {
-    const int nc = g == 0 ? nchx : nch;   // the survey randoms channel lives on copy 0 only
-    for (int i = threadIdx.x; i < nchx * T3; i += kTileBlock) acc[i] = 0ull;
+    const int nwg = (g == 0 || wr < 0) ? nw : nw - 1;   // the randoms word is the last one, copy 0 only
+    for (int i = threadIdx.x; i < nw * T3; i += kTileBlock) acc[i] = 0ull;
     for (int c0 = v0; c0 < v1; c0 += kVisitChunk) {
       const int nv = min(kVisitChunk, v1 - c0);
       __syncthreads();   // acc cleared / previous chunk consumed
@@ -719,20 +786,35 @@ __global__ void __launch_bounds__(kTileBlock) assign_tile_kernel(TileArgs a, Rec
           wz[k] = V.w[2][k];
           oz[k] = V.off[2][k];
         }
+        const T wxs = packed ? wx * (T)tscale : wx;   // packed: the tile scale folded into the x weight
 #pragma unroll
         for (int sy = 0; sy < 3; ++sy) {
           if (sy >= cy) break;
-          const T wxy = wx * wy[sy];
+          const T wxy = wxs * wy[sy];
           const int base = ox + oy[sy];
 #pragma unroll
           for (int sz = 0; sz < 3; ++sz) {
             if (sz >= cz) break;
-            const double Ws = (double)(wxy * wz[sz]) * scale;
+            const T Wt = wxy * wz[sz];
             unsigned long long* cellp = acc + base + oz[sz];
+            if (sizeof(T) == 4 && packed) {
 #pragma unroll
-            for (int ch = 0; ch < NCH; ++ch) {
-              if (ch >= nc) break;
-              atomicAdd(cellp + (size_t)ch * T3, (unsigned long long)to_fixed<T>((double)c[ch] * Ws));
+              for (int k = 0; k < NCH / 2; ++k) {
+                if (k >= npair) break;
+                atomicAdd(cellp + (size_t)k * T3, pack2(__float2int_rn((float)c[2 * k] * (float)Wt),
+                                                        __float2int_rn((float)c[2 * k + 1] * (float)Wt)));
+              }
+            } else {
+              const double Ws = (double)Wt * scale;
+#pragma unroll
+              for (int k = 0; k < NCH; ++k) {
+                if (k >= nslot) break;
+                atomicAdd(cellp + (size_t)k * T3, (unsigned long long)to_fixed<T>((double)c[k] * Ws));
+              }
+            }
+            if (wr >= 0 && g == 0) {   // randoms channel: full 64-bit word, plan-wide scale
+              const double Wr = (double)(wx * wy[sy] * wz[sz]) * scale;
+              atomicAdd(cellp + (size_t)wr * T3, (unsigned long long)to_fixed<T>((double)c[NCH - 1] * Wr));
             }
           }
         }
@@ -751,8 +833,8 @@ __global__ void __launch_bounds__(kTileBlock) assign_tile_kernel(TileArgs a, Rec
     }
     if (hs >= 0) {
       // part of a split tile: add the fixed-point sums into its slot (integer, order-free)
-      unsigned long long* hb = a.heavy + ((size_t)hs * a.copies + g) * nchx * T3;
-      for (int i = threadIdx.x; i < nc * T3; i += kTileBlock) {
+      unsigned long long* hb = a.heavy + ((size_t)hs * a.copies + g) * nw * T3;
+      for (int i = threadIdx.x; i < nwg * T3; i += kTileBlock) {
         const unsigned long long v = acc[i];
         if (v != 0ull) atomicAdd(hb + i, v);
       }
@@ -763,22 +845,16 @@ __global__ void __launch_bounds__(kTileBlock) assign_tile_kernel(TileArgs a, Rec
     for (int cell = threadIdx.x; cell < T3; cell += kTileBlock) {
       const int lx = cell / (TS * TS), ly = (cell / TS) % TS, lz = cell % TS;
       const size_t lin = ((size_t)(o3[0] + lx) * N + (o3[1] + ly)) * N + (o3[2] + lz);
-      for (int gr = 0; gr < a.ngrid; ++gr) {
-        const int cre = a.gre[gr], cim = a.gim[gr];
-        T2 o;
-        o.x = from_fixed<T>((long long)acc[(size_t)cre * T3 + cell], inv_scale);
-        o.y = cim >= 0 ? from_fixed<T>((long long)acc[(size_t)cim * T3 + cell], inv_scale) : (T)0;
-        out[((size_t)g * a.ngrid + gr) * N3 + lin] = o;
-      }
-      if (!a.box_mode && g == 0) {
+      put_node<T>(acc + cell, T3, npair, packed, -et, inv_scale, out + (size_t)g * npair * N3 + lin, N3);
+      if (wr >= 0 && g == 0) {
         // Sec. 4.2, eq. 37: sum_j (alpha R_j)^3 over this tile
-        const double v = a.scal->alpha * (double)(long long)acc[(size_t)nch * T3 + cell] * inv_scale;
+        const double v = a.scal->alpha * (double)(long long)acc[(size_t)wr * T3 + cell] * inv_scale;
         sumI += v * v * v;
       }
     }
     __syncthreads();
   }
-  if (!a.box_mode && hs < 0) {
+  if (wr >= 0 && hs < 0) {
     // fixed-order sum: within each wavefront, then over the wavefronts
     for (int off = 32; off > 0; off >>= 1) sumI += __shfl_xor(sumI, off);
     if (lane == 0) wsum[threadIdx.x >> 6] = sumI;
@@ -799,41 +875,35 @@ __global__ void __launch_bounds__(kTileBlock) assign_tile_kernel(TileArgs a, Rec
   }   // work items
 }
 
-// Split tiles: convert the summed fixed-point grids of each heavy slot.
+// Split tiles (one word per channel slot, plan-wide scale): convert the
+// summed fixed-point grids of each heavy slot.
 template <typename T>
 __global__ void __launch_bounds__(kBlock) heavy_final_kernel(TileArgs a, const int* heavy_tile, const int* nheavy) {
   typedef typename cplx<T>::type T2;
+  __shared__ double sh[kBlock];
   const int slot = blockIdx.x;
   if (slot >= min(*nheavy, kMaxHeavy)) return;
   const int tile = heavy_tile[slot];
   const int TS = a.T, T3 = TS * TS * TS, N = a.N, NT = a.NT;
-  const int nch = a.ci.nch;
-  const int nchx = nch + (a.box_mode ? 0 : 1);
+  const int nw = a.nw, wr = a.wr;
   const int o3[3] = {tile / (NT * NT) * TS, (tile / NT) % NT * TS, tile % NT * TS};
   const double inv_scale = a.scal->inv_scale;
   T2* out = (T2*)a.out;
   const size_t N3 = (size_t)N * N * N;
   double sumI = 0.0;
   for (int g = 0; g < a.copies; ++g) {
-    const long long* hb = (const long long*)a.heavy + ((size_t)slot * a.copies + g) * nchx * T3;
+    const unsigned long long* hb = a.heavy + ((size_t)slot * a.copies + g) * nw * T3;
     for (int cell = threadIdx.x; cell < T3; cell += kBlock) {
       const int lx = cell / (TS * TS), ly = (cell / TS) % TS, lz = cell % TS;
       const size_t lin = ((size_t)(o3[0] + lx) * N + (o3[1] + ly)) * N + (o3[2] + lz);
-      for (int gr = 0; gr < a.ngrid; ++gr) {
-        const int cre = a.gre[gr], cim = a.gim[gr];
-        T2 o;
-        o.x = (T)((double)hb[(size_t)cre * T3 + cell] * inv_scale);
-        o.y = cim >= 0 ? (T)((double)hb[(size_t)cim * T3 + cell] * inv_scale) : (T)0;
-        out[((size_t)g * a.ngrid + gr) * N3 + lin] = o;
-      }
-      if (!a.box_mode && g == 0) {
-        const double v = a.scal->alpha * (double)hb[(size_t)nch * T3 + cell] * inv_scale;
+      put_node<T>(hb + cell, T3, a.ngrid, false, 0, inv_scale, out + (size_t)g * a.ngrid * N3 + lin, N3);
+      if (wr >= 0 && g == 0) {
+        const double v = a.scal->alpha * (double)(long long)hb[(size_t)wr * T3 + cell] * inv_scale;
         sumI += v * v * v;
       }
     }
   }
-  if (!a.box_mode) {
-    __shared__ double sh[kBlock];
+  if (wr >= 0) {
     sh[threadIdx.x] = sumI;
     __syncthreads();
     for (int st = kBlock / 2; st > 0; st >>= 1) {
@@ -939,7 +1009,7 @@ __global__ void zero_ints_kernel(int* p, int64_t n) {
 __global__ void zero_scal_kernel(DevScalars* s) {
   if (threadIdx.x == 0) {
     s->sum_w = s->sum_w_ran = s->sum_abs = s->sum_abs_ran = 0.0;
-    s->alpha = s->scale = s->inv_scale = s->mean_cell = s->I = 0.0;
+    s->alpha = s->scale = s->inv_scale = s->mean_cell = s->I = s->cmax = 0.0;
     s->err = 0;
     s->pad = 0;
   }
@@ -1017,11 +1087,17 @@ int run_prep(Plan& P, const tsb_catalog* data, const tsb_catalog* rand, hipStrea
   return TSB_OK;
 }
 
+// Record slots: two per complex grid, plus the randoms channel in survey mode.
+static int record_slots(const Plan& P) { return 2 * (int)P.grids.size() + (P.box_mode ? 0 : 1); }
+
 int record_stride(const Plan& P) {
-  const int nchx = (int)P.chans.size() + (P.box_mode ? 0 : 1);
   const int esz = P.precision == TSB_FP64 ? 8 : 4;
-  return (24 + nchx * esz + 15) / 16 * 16;
+  return (24 + record_slots(P) * esz + 15) / 16 * 16;
 }
+
+// 64-bit fixed-point words per node held for one grid copy: one per record
+// slot (packed FP32 tiles use the first ngrid of them).
+int assign_words(const Plan& P) { return record_slots(P); }
 
 int64_t assign_work_cap(const Plan& P, int64_t particles) {
   const int64_t ntiles = (int64_t)P.NT * P.NT * P.NT;
@@ -1029,8 +1105,7 @@ int64_t assign_work_cap(const Plan& P, int64_t particles) {
 }
 
 int64_t assign_heavy_bytes(const Plan& P) {
-  const int64_t nchx = (int64_t)P.chans.size() + (P.box_mode ? 0 : 1);
-  return (int64_t)kMaxHeavy * P.copies * nchx * P.T * P.T * P.T * 8;
+  return (int64_t)kMaxHeavy * P.copies * assign_words(P) * P.T * P.T * P.T * 8;
 }
 
 int assign_max_heavy() { return kMaxHeavy; }
@@ -1038,7 +1113,8 @@ int assign_max_heavy() { return kMaxHeavy; }
 int chan_info(const Plan& P, ChanInfo* ci) {
   *ci = ChanInfo{};
   ci->nch = (int)P.chans.size();
-  if (ci->nch + 1 > kMaxCh || (int)P.grids.size() > kMaxGrids) return fail(TSB_E_UNSUPPORTED, "too many channels");
+  if (ci->nch + 1 > kMaxCh || (int)P.grids.size() > kMaxGrids || record_slots(P) > kMaxCh)
+    return fail(TSB_E_UNSUPPORTED, "too many channels");
   ci->local = P.los_kind == TSB_LOS_LOCAL;
   for (int i = 0; i < 3; ++i) ci->obs[i] = P.observer[i];
   for (int c = 0; c < ci->nch; ++c) {
@@ -1092,12 +1168,12 @@ int assign_front_impl(Plan& P, const BucketArgs& b, const ChanInfo& ci, hipStrea
   const int ntiles = P.NT * P.NT * P.NT;
   const int64_t ntot = b.d.n + b.r.n;
   const int nchx = ci.nch + (P.box_mode ? 0 : 1);
+  const size_t lds = (size_t)assign_words(P) * P.T * P.T * P.T * sizeof(unsigned long long);
   // upper bound of the work items: a particle is visited by at most 8 tiles
   const int64_t work_bound = (int64_t)ntiles + (8 * ntot + kPartVisits - 1) / kPartVisits + 1;
   if (work_bound > P.work_cap) return fail(TSB_E_UNSUPPORTED, "assignment: work list too small");
   if (P.tile_wgs <= 0) {
     // persistent workgroups of the tile kernel: as many as are resident at once
-    const size_t lds = (size_t)nchx * P.T * P.T * P.T * sizeof(unsigned long long);
     int per_cu = 0, dev = 0, n_cu = 0;
     TSB_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)assign_tile_kernel<T, NCH>,
                                                          kTileBlock, lds));
@@ -1113,6 +1189,15 @@ int assign_front_impl(Plan& P, const BucketArgs& b, const ChanInfo& ci, hipStrea
     f.rec.base = (char*)P.d_rec;
     f.rec.stride = record_stride(P);
     f.nchx = nchx;
+    f.zslot = -1;
+    for (int gr = 0; gr < (int)P.grids.size(); ++gr) {
+      f.slot_of[P.grids[gr].re] = 2 * gr;
+      if (P.grids[gr].im >= 0)
+        f.slot_of[P.grids[gr].im] = 2 * gr + 1;
+      else
+        f.zslot = 2 * gr + 1;
+    }
+    if (!P.box_mode) f.slot_of[ci.nch] = 2 * (int)P.grids.size();
     f.scal = P.d_scal;
     hipLaunchKernelGGL((bucket_fill_kernel<T, NCH>), dim3(grid_blocks(ntot)), dim3(kBlock), 0, s, f);
   }
@@ -1127,7 +1212,7 @@ int assign_front_impl(Plan& P, const BucketArgs& b, const ChanInfo& ci, hipStrea
 template <typename T, int NCH>
 int assign_back_impl(Plan& P, const ChanInfo& ci, hipStream_t s) {
   const int ntiles = P.NT * P.NT * P.NT;
-  const int nchx = ci.nch + (P.box_mode ? 0 : 1);
+  const int nw = assign_words(P);
   Records<T> rec;
   rec.cap = P.particle_cap;
   rec.base = (char*)P.d_rec;
@@ -1144,10 +1229,9 @@ int assign_back_impl(Plan& P, const ChanInfo& ci, hipStream_t s) {
   a.box_mode = P.box_mode;
   a.ci = ci;
   a.ngrid = (int)P.grids.size();
-  for (int g = 0; g < a.ngrid; ++g) {
-    a.gre[g] = P.grids[g].re;
-    a.gim[g] = P.grids[g].im;
-  }
+  a.nw = nw;
+  a.wr = P.box_mode ? -1 : nw - 1;
+  a.wmax = P.p == 3 ? 0.421875 : 1.0;
   a.start = P.d_bk_start;
   a.scal = P.d_scal;
   a.out = P.d_grid;
@@ -1173,11 +1257,11 @@ int assign_back_impl(Plan& P, const ChanInfo& ci, hipStream_t s) {
                        (int64_t)ntiles, (const int*)P.d_scan_part, P.d_tile_pstart);
     hipLaunchKernelGGL(tile_work_kernel, dim3(tb), dim3(kBlock), 0, s, ntiles, (const int*)P.d_tile_parts,
                        (const int*)P.d_tile_pstart, (int2*)P.d_work);
-    const int64_t per_slot = (int64_t)P.copies * nchx * P.T * P.T * P.T;
+    const int64_t per_slot = (int64_t)P.copies * nw * P.T * P.T * P.T;
     hipLaunchKernelGGL(heavy_zero_kernel, dim3(1024), dim3(kBlock), 0, s, (unsigned long long*)P.d_heavy,
                        (const int*)nheavy, per_slot);
   }
-  const size_t lds = (size_t)nchx * P.T * P.T * P.T * sizeof(unsigned long long);
+  const size_t lds = (size_t)nw * P.T * P.T * P.T * sizeof(unsigned long long);
   hipLaunchKernelGGL((assign_tile_kernel<T, NCH>), dim3(std::max(1, P.tile_wgs)), dim3(kTileBlock), lds, s, a,
                      rec);
   hipLaunchKernelGGL(heavy_final_kernel<T>, dim3(kMaxHeavy), dim3(kBlock), 0, s, a, (const int*)P.d_heavy_tile,
@@ -1226,10 +1310,10 @@ int run_assign(Plan& P, const tsb_catalog* data, const tsb_catalog* rand, hipStr
 
   ChanInfo ci;
   if (int rc = chan_info(P, &ci)) return rc;
-  const int nchx = ci.nch + (P.box_mode ? 0 : 1);
+  const int nreg = record_slots(P);
   const bool f64 = P.precision == TSB_FP64;
-  if (nchx <= 8) return f64 ? assign_front_impl<double, 8>(P, b, ci, s) : assign_front_impl<float, 8>(P, b, ci, s);
-  if (nchx <= 16)
+  if (nreg <= 8) return f64 ? assign_front_impl<double, 8>(P, b, ci, s) : assign_front_impl<float, 8>(P, b, ci, s);
+  if (nreg <= 16)
     return f64 ? assign_front_impl<double, 16>(P, b, ci, s) : assign_front_impl<float, 16>(P, b, ci, s);
   return f64 ? assign_front_impl<double, kMaxCh>(P, b, ci, s) : assign_front_impl<float, kMaxCh>(P, b, ci, s);
 }
@@ -1237,10 +1321,10 @@ int run_assign(Plan& P, const tsb_catalog* data, const tsb_catalog* rand, hipStr
 int run_assign_back(Plan& P, hipStream_t s) {
   ChanInfo ci;
   if (int rc = chan_info(P, &ci)) return rc;
-  const int nchx = ci.nch + (P.box_mode ? 0 : 1);
+  const int nreg = record_slots(P);
   const bool f64 = P.precision == TSB_FP64;
-  if (nchx <= 8) return f64 ? assign_back_impl<double, 8>(P, ci, s) : assign_back_impl<float, 8>(P, ci, s);
-  if (nchx <= 16) return f64 ? assign_back_impl<double, 16>(P, ci, s) : assign_back_impl<float, 16>(P, ci, s);
+  if (nreg <= 8) return f64 ? assign_back_impl<double, 8>(P, ci, s) : assign_back_impl<float, 8>(P, ci, s);
+  if (nreg <= 16) return f64 ? assign_back_impl<double, 16>(P, ci, s) : assign_back_impl<float, 16>(P, ci, s);
   return f64 ? assign_back_impl<double, kMaxCh>(P, ci, s) : assign_back_impl<float, kMaxCh>(P, ci, s);
 }
 

@@ -360,13 +360,14 @@ int plan_build(Plan& P) {
   }
 
   // ---- assignment tile and reduction chunk ---------------------------------------
-  const int nchx = (int)P.chans.size() + (P.box_mode ? 0 : 1);
-  if (N % 8 == 0 && N / 8 >= 3 && (int64_t)P.copies * nchx * 512 * 8 <= 65536)
+  // one grid copy's fixed-point words per node sit in LDS at a time
+  const int words = assign_words(P);
+  if (N % 8 == 0 && N / 8 >= 3 && (int64_t)words * 512 * 8 <= 65536)
     P.T = 8;
   else
     P.T = 4;
   P.NT = N / P.T;
-  if ((int64_t)P.copies * nchx * P.T * P.T * P.T * 8 > 160 * 1024)
+  if ((int64_t)words * P.T * P.T * P.T * 8 > 64 * 1024)
     return fail(TSB_E_UNSUPPORTED, "too many channels for the assignment tile");
   const int esz = P.precision == TSB_FP64 ? 8 : 4;
   const int64_t per_cell = (int64_t)P.nb * (int64_t)P.fcomp.size() + (int64_t)P.gcomp.size() +

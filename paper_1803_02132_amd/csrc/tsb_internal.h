@@ -63,6 +63,7 @@ struct OutEntry { int mu, b1, b2, q0, q1; };  // B(mu,b1,b2) = sum_{q0<=q<q1} su
 struct DevScalars {
   double sum_w, sum_w_ran, sum_abs, sum_abs_ran;
   double alpha, scale, inv_scale, mean_cell, I;
+  double cmax;    // bound on |channel weight| of any particle (FP32 per-tile fixed point)
   int err;        // bit 0: non-finite input, bit 1: outside the box (survey),
                   // bit 2: particle on the observer
   int pad;
@@ -147,7 +148,7 @@ struct Plan {
   int* d_tile_hslot = nullptr;  // heavy slot per tile or -1 [ntiles]
   int* d_tile_pstart = nullptr; // first work item per tile [ntiles + 1]
   int* d_heavy_tile = nullptr;  // tile of each heavy slot
-  void* d_heavy = nullptr;      // fixed-point sums of split tiles [slot][copies][nchx][T^3]
+  void* d_heavy = nullptr;      // fixed-point sums of split tiles [slot][copies][words][T^3]
   void* d_work = nullptr;       // work items (tile, part) [work_cap]
   int64_t work_cap = 0;
   int tile_wgs = 0;             // resident workgroups of the tile kernel (from the occupancy query)
@@ -230,6 +231,7 @@ int run_ynode_fill(Plan& P, hipStream_t s);
 int run_assign_back(Plan& P, hipStream_t s);
 int64_t assign_work_cap(const Plan& P, int64_t particles);
 int record_stride(const Plan& P);
+int assign_words(const Plan& P);
 int64_t assign_heavy_bytes(const Plan& P);
 int assign_max_heavy();
 int run_unpack_grids(Plan& P, void* out, hipStream_t s);

@@ -79,6 +79,39 @@ def test_assignment_grids(p, precision):
             assert err <= tol * scale, (L, M, part, copy, err, scale)
 
 
+@pytest.mark.parametrize("p", [1, 2, 3])
+def test_assignment_grids_sparse_fp32(p):
+    # Few particles per tile: FP32 tiles that run as one work item add the two
+    # channels of a complex grid into one 64-bit word at a per-tile scale.
+    # Error model: FP32 rounding of the summed grid and of the grid after the
+    # box-mode mean term, plus, per contribution to a node, the FP32 product
+    # c W 2^e (three roundings) rounded to a fixed-point step of at most
+    # 2^-22 max|c| (here max|c| = 1): below 2^-21 per contribution.
+    req = box_request(n=32, multipoles=[(0, 0, 0), (2, 0, 2)], assign_p=p, precision="f32")
+    _say("assign sparse", p)
+    cat = small_cat(n_target=1500, seed=5)
+    plan = tsb.Plan(**req)
+    grids = plan.assign(tsb.catalog_to_device(cat)).cpu().numpy()
+    op = oracle_plan(**req)
+    og, _ = est.assign_channels(op, cat)
+    n = req["n"]
+    for copy in range(2):
+        u = est.grid_coordinate(np.asarray(cat["pos"], np.float64), op) + 0.5 * copy
+        idx = [est.axis_stencil(u[:, a], p)[0] % n for a in range(3)]
+        contrib = np.zeros((n, n, n))
+        for a in range(p):
+            for b in range(p):
+                for c in range(p):
+                    np.add.at(contrib, (idx[0][:, a], idx[1][:, b], idx[2][:, c]), 1.0)
+        for ch, (L, M, part) in enumerate(plan.channels()):
+            ref = og[(L, M)][copy]
+            ref = ref.real if part == 0 else ref.imag
+            mean = len(cat["pos"]) / n ** 3
+            bound = 2.0 ** -22 * (np.abs(ref) + mean) + contrib * 2.0 ** -21
+            err = np.abs(grids[copy, ch] - ref)
+            assert np.all(err <= bound), (L, M, part, copy, float(np.max(err / bound)))
+
+
 def test_assignment_survey_and_nmode():
     req = box_request(n=32, box_mode=False, P0=1e4, interlace=False, observer=(500.0, 500.0, 500.0),
                       multipoles=[(0, 0, 0), (2, 0, 2)], precision="f64")
