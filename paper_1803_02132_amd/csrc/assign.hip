@@ -447,6 +447,7 @@ constexpr int kMaxRanges = 64;
 struct TileArgs {
   double inv_h, h, origin[3];
   int N, T, NT, p, copies, box_mode;
+  int lt;                      // log2 T (T is 4 or 8)
   ChanInfo ci;
   int ngrid;                   // complex output grids (record slots 2g, 2g+1)
   int nw;                      // 64-bit fixed-point words per node
@@ -611,7 +612,7 @@ __global__ void __launch_bounds__(kTileBlock) assign_tile_kernel(TileArgs a, Rec
   T2* out = (T2*)a.out;
   const size_t N3 = (size_t)N * N * N;
   const int stride[3] = {TS * TS, TS, 1};
-  const double scale = a.scal->scale, inv_scale = a.scal->inv_scale, cmax = a.scal->cmax;
+  const double scale = a.scal->scale, inv_scale = a.scal->inv_scale, cmax = a.scal->cmax, alpha = a.scal->alpha;
 
   // Work-item pipeline: the ranges of the next-but-one item are fetched into
   // the first wavefront's registers, and the first chunk of particle records
@@ -842,14 +843,17 @@ __global__ void __launch_bounds__(kTileBlock) assign_tile_kernel(TileArgs a, Rec
       continue;
     }
     // write out this copy
-    for (int cell = threadIdx.x; cell < T3; cell += kTileBlock) {
-      const int lx = cell / (TS * TS), ly = (cell / TS) % TS, lz = cell % TS;
-      const size_t lin = ((size_t)(o3[0] + lx) * N + (o3[1] + ly)) * N + (o3[2] + lz);
-      put_node<T>(acc + cell, T3, npair, packed, -et, inv_scale, out + (size_t)g * npair * N3 + lin, N3);
-      if (wr >= 0 && g == 0) {
-        // Sec. 4.2, eq. 37: sum_j (alpha R_j)^3 over this tile
-        const double v = a.scal->alpha * (double)(long long)acc[(size_t)wr * T3 + cell] * inv_scale;
-        sumI += v * v * v;
+    {
+      T2* tout = out + (size_t)g * npair * N3 + ((size_t)o3[0] * N + o3[1]) * N + o3[2];
+      const int lt = a.lt, tm = TS - 1;
+      for (int cell = threadIdx.x; cell < T3; cell += kTileBlock) {
+        const int lx = cell >> (2 * lt), ly = (cell >> lt) & tm, lz = cell & tm;
+        put_node<T>(acc + cell, T3, npair, packed, -et, inv_scale, tout + ((lx * N + ly) * N + lz), N3);
+        if (wr >= 0 && g == 0) {
+          // Sec. 4.2, eq. 37: sum_j (alpha R_j)^3 over this tile
+          const double v = alpha * (double)(long long)acc[(size_t)wr * T3 + cell] * inv_scale;
+          sumI += v * v * v;
+        }
       }
     }
     __syncthreads();
@@ -1223,6 +1227,7 @@ int assign_back_impl(Plan& P, const ChanInfo& ci, hipStream_t s) {
   for (int i = 0; i < 3; ++i) a.origin[i] = P.origin[i];
   a.N = P.N;
   a.T = P.T;
+  a.lt = P.T == 8 ? 3 : 2;
   a.NT = P.NT;
   a.p = P.p;
   a.copies = P.copies;
