@@ -282,25 +282,50 @@ def batch_leg(tsb, torch, pool, per_size):
             "batched_over_plain": round(t_plain / t_batch, 3)}
 
 
-def serve_leg(tsb, torch, pool, n_req, rate, slots, budget_gb):
-    """Poisson request stream (mean `rate` per second) over the pool's grid
-    sizes through the server; then the same requests submitted at once."""
-    rng = np.random.default_rng(2024)
-    sizes = sorted(pool)
-    tmpl = {n: tsb.Plan(**dict(WORKLOAD, n=n)) for n in sizes}
+# serving requests: grids, multipoles and particle counts of the request stream
+SERVE_SIZES = (128, 192, 256, 384, 512)
+SERVE_MULTIPOLES = [(0, 0, 0), (1, 1, 0), (2, 0, 2)]
+SERVE_NP = (500_000, 20_000_000)
+
+
+def serve_catalogue(tsb, seed=7000):
+    """One seeded mock of SERVE_NP[1] particles (the headline recipe, field on a
+    256^3 grid), shuffled once and resident on the device. A request of N_p
+    particles takes the first N_p: a Poisson subsample of the same field."""
+    from mocks.lognormal import workload
+    _, cat = workload("box256", seed=seed, n_target=SERVE_NP[1])
+    perm = np.random.Generator(np.random.PCG64(seed)).permutation(len(cat["pos"]))
+    log(f"serving catalogue: {len(perm)} particles")
+    return tsb.catalog_to_device({"pos": cat["pos"][perm], "w": None, "nbar": None})
+
+
+def _prefix(dev, n):
+    return {k: (None if v is None else v[:n]) for k, v in dev.items()}
+
+
+def serve_leg(tsb, torch, big, n_req, rate, slots, budget_gb):
+    """Poisson request stream (mean `rate` per second): each request a grid
+    drawn uniformly from SERVE_SIZES and N_p log-uniform in SERVE_NP, measuring
+    SERVE_MULTIPOLES through the server; then the same requests submitted at
+    once (continuous batching under load)."""
+    rng = np.random.Generator(np.random.PCG64(2024))
+    n_big = int(big["x"].numel())
+    tmpl = {n: tsb.Plan(**dict(WORKLOAD, n=n, multipoles=SERVE_MULTIPOLES)) for n in SERVE_SIZES}
+    lo, hi = SERVE_NP
     reqs = []
     for _ in range(n_req):
-        n = sizes[rng.integers(len(sizes))]
-        reqs.append((n, pool[n][rng.integers(len(pool[n]))][2]))
+        n = SERVE_SIZES[rng.integers(len(SERVE_SIZES))]
+        npart = min(n_big, int(lo * (hi / lo) ** rng.random()))
+        reqs.append((n, npart))
+    gaps = rng.exponential(1.0 / rate, size=n_req)
     srv = tsb.Server(int(budget_gb * (1 << 30)), slots)
     try:
-        for n in sizes:                          # warm-up: one workspace per size
-            srv.wait(srv.submit(tmpl[n], pool[n][0][2]))
-        gaps = rng.exponential(1.0 / rate, size=n_req)
+        for n in SERVE_SIZES:                    # warm-up: a workspace per grid with full particle buffers
+            srv.wait(srv.submit(tmpl[n], _prefix(big, n_big)))
         lat, pending = [], {}
         t0 = time.perf_counter()
         t_next = t0
-        for (n, d), gap in zip(reqs, gaps):
+        for k, ((n, npart), gap) in enumerate(zip(reqs, gaps)):
             t_next += gap
             while time.perf_counter() < t_next:
                 for t in list(pending):
@@ -309,13 +334,14 @@ def serve_leg(tsb, torch, pool, n_req, rate, slots, budget_gb):
                         lat.append(l)
                         pending.pop(t)
                 time.sleep(0.0005)
-            pending[srv.submit(tmpl[n], d)] = True
+            pending[srv.submit(tmpl[n], _prefix(big, npart))] = True
+            if (k + 1) % 64 == 0:
+                log(f"serving: {k + 1} of {n_req} requests submitted")
         for t in list(pending):
             lat.append(srv.wait(t)[0])
         t_stream = time.perf_counter() - t0
-        # the same requests at once: continuous batching under load
         t0 = time.perf_counter()
-        tickets = [srv.submit(tmpl[n], d) for n, d in reqs]
+        tickets = [srv.submit(tmpl[n], _prefix(big, npart)) for n, npart in reqs]
         lat_burst = [srv.wait(t)[0] for t in tickets]
         t_burst = time.perf_counter() - t0
     finally:
@@ -324,8 +350,11 @@ def serve_leg(tsb, torch, pool, n_req, rate, slots, budget_gb):
             p.close()
     ms = np.array(lat) * 1e3
     mb = np.array(lat_burst) * 1e3
-    return {"requests": n_req, "rate_per_s": rate, "grids": [f"{n}^3" for n in sizes], "slots": slots,
-            "hbm_budget_gb": budget_gb,
+    nps = np.array([npart for _, npart in reqs])
+    return {"requests": n_req, "rate_per_s": rate, "grids": [f"{n}^3" for n in SERVE_SIZES],
+            "multipoles": ["".join(map(str, m)) for m in SERVE_MULTIPOLES],
+            "particles": {"min": int(nps.min()), "median": int(np.median(nps)), "max": int(nps.max())},
+            "slots": slots, "hbm_budget_gb": budget_gb,
             "poisson": {"mocks_per_s": round(n_req / t_stream, 3), "p50_ms": round(float(np.percentile(ms, 50)), 3),
                         "p99_ms": round(float(np.percentile(ms, 99)), 3)},
             "burst": {"mocks_per_s": round(n_req / t_burst, 2), "p50_ms": round(float(np.percentile(mb, 50)), 3),
@@ -344,9 +373,10 @@ def main():
     ap.add_argument("--no-batch", action="store_true", help="skip the batched 64-mock leg")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving leg")
     ap.add_argument("--pool", type=int, default=2, help="distinct catalogues per grid size in those legs")
-    ap.add_argument("--serve-requests", type=int, default=64)
+    ap.add_argument("--serve-requests", type=int, default=256)
     ap.add_argument("--serve-rate", type=float, default=4.0)
-    ap.add_argument("--serve-slots", type=int, default=4)
+    ap.add_argument("--serve-slots", type=int, default=8)
+    ap.add_argument("--serve-budget-gb", type=float, default=160.0)
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a device copy of known size (calibrates HBM byte counters)")
     ap.add_argument("--ingest-pmc", nargs=3, metavar=("FETCH_CSV", "WRITE_CSV", "COMMAND"),
@@ -424,17 +454,19 @@ def main():
         "stage_ms": {k: round(v, 4) for k, v in per_launch.items()},
     }
     plan.close()
-    if not (args.no_batch and args.no_serve):
+    if not args.no_batch:
         pool = _pool(tsb, [(n, seeds) for n, seeds in BATCH_CLASSES], args.pool)
-        if not args.no_batch:
-            log("batched leg ...")
-            out["batched"] = batch_leg(tsb, torch, pool, args.pool)
-            log(f"batched: {out['batched']}")
-        if not args.no_serve:
-            log("serving leg ...")
-            out["serving"] = serve_leg(tsb, torch, pool, args.serve_requests, args.serve_rate, args.serve_slots, 64)
-            log(f"serving: {out['serving']}")
+        log("batched leg ...")
+        out["batched"] = batch_leg(tsb, torch, pool, args.pool)
+        log(f"batched: {out['batched']}")
         del pool
+    if not args.no_serve:
+        log("serving leg ...")
+        big = serve_catalogue(tsb)
+        out["serving"] = serve_leg(tsb, torch, big, args.serve_requests, args.serve_rate, args.serve_slots,
+                                   args.serve_budget_gb)
+        log(f"serving: {out['serving']}")
+        del big
     if not args.no_cpu_baseline:
         log("timing the oracle on the host ...")
         out["cpu_baseline"] = cpu_baseline(cats[0])

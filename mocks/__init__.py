@@ -6,7 +6,7 @@ workloads. It holds none of the estimator's arithmetic and is the only code the
 oracle's callers and the HIP path's callers share.
 """
 from .lognormal import (power_law_pk, gaussian_field, lognormal_box, survey_catalogue,
-                        workload, WORKLOADS, to_soa)
+                        workload, survey_workload, WORKLOADS, to_soa)
 
 __all__ = ["power_law_pk", "gaussian_field", "lognormal_box", "survey_catalogue",
-           "workload", "WORKLOADS", "to_soa"]
+           "workload", "survey_workload", "WORKLOADS", "to_soa"]

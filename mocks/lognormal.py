@@ -165,6 +165,15 @@ WORKLOADS = {
                    los="local", observer=(500.0, 500.0, -1000.0),
                    multipoles=[(0, 0, 0), (2, 0, 2)], n_bins=20, dk=0.01, k_min=0.0,
                    rsd="local", precision="f32"),
+    # survey window: 256^3 grid, L = 2000, 2M galaxies in the half shell
+    # 500 <= r <= 1000 about the box centre (the observer), 10x randoms, FKP
+    # weights with P0 = 1e4, {000, 202, 112, 404}, 25 bins of dk = 0.008
+    # (up to about half the Nyquist frequency), TSC + interlacing
+    "survey256": dict(n=256, box_len=2000.0, n_data=2_000_000, r_min=500.0, r_max=1000.0,
+                      random_factor=10, P0=1.0e4, assign_p=3, interlace=True, los="local",
+                      observer=(1000.0, 1000.0, 1000.0),
+                      multipoles=[(0, 0, 0), (2, 0, 2), (1, 1, 2), (4, 0, 4)], n_bins=25,
+                      dk=0.008, k_min=0.0, precision="f32"),
 }
 
 
@@ -172,6 +181,16 @@ def headline_particle_count(seed):
     """N_p = floor(3e5 * 10^U), U ~ U(0,1) drawn from the seed."""
     rng = np.random.Generator(np.random.PCG64(10_000 + seed))
     return int(np.floor(3.0e5 * 10.0 ** rng.random()))
+
+
+def survey_workload(name, seed=0, n_data=None):
+    """Build (spec, data, randoms) for a named survey workload (step 5)."""
+    spec = dict(WORKLOADS[name])
+    if n_data is not None:
+        spec["n_data"] = n_data
+    data, rand = survey_catalogue(spec["n"], spec["box_len"], spec["n_data"], seed, spec["r_min"],
+                                  spec["r_max"], random_factor=spec["random_factor"])
+    return spec, data, rand
 
 
 def workload(name, seed=0, n_target=None, n=None):
