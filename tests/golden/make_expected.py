@@ -7,6 +7,10 @@ Outputs (small .npz files next to this script):
   box128_seed0.npz   every pair of the 128^3 box workload (500k particles,
                      Kaiser along a local LOS, TSC + interlacing, 000 110 202 112)
   box256_seed48.npz  sampled shell pairs of one 256^3 throughput mock (000, 202)
+  survey256_seed3.npz sampled shell pairs of the 256^3 survey-window workload
+                     (2M galaxies in a half shell, 20M randoms, FKP weights,
+                     000 202 112 404, 25 shells)
+Pass workload names (box128 box256 survey256) to write only those files.
 Each file also stores a checksum of the generated catalogue so the tests can
 confirm they regenerated the same input.
 """
@@ -20,10 +24,12 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(os.path.dirname(HERE))
 sys.path.insert(0, ROOT)
 
-from mocks.lognormal import WORKLOADS, workload  # noqa: E402
+from mocks.lognormal import WORKLOADS, survey_workload, workload  # noqa: E402
 from oracle import estimator as est  # noqa: E402
 
 SAMPLED_PAIRS_256 = [(0, 0), (0, 19), (3, 7), (7, 3), (9, 9), (12, 18), (18, 12), (19, 19)]
+# few distinct shells, so that the oracle's cached shell fields fit in memory
+SAMPLED_PAIRS_SURVEY = [(3, 3), (3, 24), (24, 3), (9, 16), (16, 9), (9, 9), (24, 24)]
 
 
 def catalogue_checksum(cat):
@@ -31,13 +37,24 @@ def catalogue_checksum(cat):
     return np.array([len(p), p.sum(), (p * p).sum()])
 
 
-def oracle_plan(spec):
+def oracle_plan(spec, box_mode=True):
     return est.Plan(n=spec["n"], box_len=spec["box_len"], multipoles=spec["multipoles"], n_bins=spec["n_bins"],
                     dk=spec["dk"], k_min=spec["k_min"], assign_p=spec["assign_p"], interlace=spec["interlace"],
-                    los=spec["los"], observer=spec.get("observer", (0.0, 0.0, 0.0)), box_mode=True)
+                    los=spec["los"], observer=spec.get("observer", (0.0, 0.0, 0.0)), box_mode=box_mode,
+                    P0=spec.get("P0", 0.0))
 
 
-def main():
+def survey256():
+    t0 = time.time()
+    spec, data, rand = survey_workload("survey256", seed=3)
+    res = est.measure(oracle_plan(spec, box_mode=False), data, rand, pairs=SAMPLED_PAIRS_SURVEY)
+    np.savez(os.path.join(HERE, "survey256_seed3.npz"), B=res["B"], B_imag=res["B_imag"], I=res["I"],
+             alpha=res["alpha"], nmode=res["nmode"], pairs=np.array(SAMPLED_PAIRS_SURVEY),
+             checksum=catalogue_checksum(data), checksum_randoms=catalogue_checksum(rand))
+    print(f"survey256 done in {time.time() - t0:.0f} s", flush=True)
+
+
+def box128():
     t0 = time.time()
     spec, cat = workload("box128", seed=0)
     res = est.measure(oracle_plan(spec), cat)
@@ -45,6 +62,8 @@ def main():
              nmode=res["nmode"], checksum=catalogue_checksum(cat))
     print(f"box128 done in {time.time() - t0:.0f} s", flush=True)
 
+
+def box256():
     t0 = time.time()
     spec, cat = workload("box256", seed=48)
     res = est.measure(oracle_plan(spec), cat, pairs=SAMPLED_PAIRS_256)
@@ -53,5 +72,9 @@ def main():
     print(f"box256 done in {time.time() - t0:.0f} s", flush=True)
 
 
+TARGETS = {"box128": box128, "box256": box256, "survey256": survey256}
+
+
 if __name__ == "__main__":
-    main()
+    for name in sys.argv[1:] or list(TARGETS):
+        TARGETS[name]()

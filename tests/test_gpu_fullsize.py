@@ -5,6 +5,8 @@ from its seed and checked against the stored checksum).
 * 128^3 box, 500k particles, Kaiser along a local LOS, TSC + interlacing,
   {000, 110, 202, 112}, 20 shells: every computed pair.
 * 256^3 throughput mock (the configuration bench.py times): sampled pairs.
+* 256^3 survey window (L = 2000, 2M galaxies in a half shell, 20M randoms,
+  FKP weights, {000, 202, 112, 404}, 25 shells): sampled pairs, alpha and I.
 
 Tolerance: 1e-4 normwise per multipole (max |dB| / max |B| over the compared
 pairs), FP32 fields with FP64 accumulation.
@@ -15,7 +17,7 @@ import sys
 import numpy as np
 import pytest
 
-from mocks.lognormal import WORKLOADS, workload
+from mocks.lognormal import WORKLOADS, survey_workload, workload
 
 pytestmark = pytest.mark.gpu
 
@@ -89,4 +91,26 @@ def test_box256_sampled_pairs():
     pairs = [tuple(p) for p in exp["pairs"]]
     err = _compare(res["B"], exp["B"], pairs)
     _say("box256 normwise errors per multipole (sampled pairs)", err)
+    assert np.all(err <= 1e-4)
+
+
+def test_survey256_sampled_pairs():
+    exp = np.load(os.path.join(GOLDEN, "survey256_seed3.npz"))
+    spec, data, rand = survey_workload("survey256", seed=3)
+    assert np.allclose(_checksum(data), exp["checksum"], rtol=1e-12, atol=0)
+    assert np.allclose(_checksum(rand), exp["checksum_randoms"], rtol=1e-12, atol=0)
+    req = _request("survey256", box_mode=False, P0=spec["P0"])
+    _say("survey256", len(data["pos"]), "galaxies", len(rand["pos"]), "randoms")
+    plan = tsb.Plan(**req)
+    assert np.array_equal(np.array(plan.nmode), exp["nmode"])
+    res = plan.measure(tsb.catalog_to_device(data), tsb.catalog_to_device(rand))
+    pairs = [tuple(p) for p in exp["pairs"]]
+    err = _compare(res["B"], exp["B"], pairs)
+    _say("survey256 normwise errors per multipole (sampled pairs)", err, "alpha", res["alpha"],
+         float(exp["alpha"]), "I", res["I"], float(exp["I"]))
+    assert res["alpha"] == pytest.approx(float(exp["alpha"]), rel=1e-12)
+    # I = v_c sum (alpha R / v_c)^3 is cubic in the randoms' weights, which an
+    # FP32 plan stores rounded to FP32; n-bar here takes 50 radial values, so
+    # those roundings need not average out: |dI / I| <= 3 * 2^-24
+    assert res["I"] == pytest.approx(float(exp["I"]), rel=3 * 2.0 ** -24)
     assert np.all(err <= 1e-4)
