@@ -10,7 +10,9 @@ Outputs (small .npz files next to this script):
   survey256_seed3.npz sampled shell pairs of the 256^3 survey-window workload
                      (2M galaxies in a half shell, 20M randoms, FKP weights,
                      000 202 112 404, 25 shells)
-Pass workload names (box128 box256 survey256) to write only those files.
+  serve384_seed7001.npz sampled shell pairs of a 384^3 serving request
+                     (2M particles, 000 110 202)
+Pass workload names (box128 box256 survey256 serve384) to write only those files.
 Each file also stores a checksum of the generated catalogue so the tests can
 confirm they regenerated the same input.
 """
@@ -30,6 +32,7 @@ from oracle import estimator as est  # noqa: E402
 SAMPLED_PAIRS_256 = [(0, 0), (0, 19), (3, 7), (7, 3), (9, 9), (12, 18), (18, 12), (19, 19)]
 # few distinct shells, so that the oracle's cached shell fields fit in memory
 SAMPLED_PAIRS_SURVEY = [(3, 3), (3, 24), (24, 3), (9, 16), (16, 9), (9, 9), (24, 24)]
+SAMPLED_PAIRS_384 = [(4, 4), (4, 15), (15, 4), (15, 15)]
 
 
 def catalogue_checksum(cat):
@@ -72,7 +75,19 @@ def box256():
     print(f"box256 done in {time.time() - t0:.0f} s", flush=True)
 
 
-TARGETS = {"box128": box128, "box256": box256, "survey256": survey256}
+def serve384():
+    # a serving request on a radix-3 grid: 2M particles of a mock whose field
+    # lives on a 256^3 grid, measured on 384^3 with {000, 110, 202}
+    t0 = time.time()
+    spec, cat = workload("box256", seed=7001, n_target=2_000_000)
+    spec = dict(spec, n=384, multipoles=[(0, 0, 0), (1, 1, 0), (2, 0, 2)])
+    res = est.measure(oracle_plan(spec), cat, pairs=SAMPLED_PAIRS_384)
+    np.savez(os.path.join(HERE, "serve384_seed7001.npz"), B=res["B"], B_imag=res["B_imag"], I=res["I"],
+             nmode=res["nmode"], pairs=np.array(SAMPLED_PAIRS_384), checksum=catalogue_checksum(cat))
+    print(f"serve384 done in {time.time() - t0:.0f} s", flush=True)
+
+
+TARGETS = {"box128": box128, "box256": box256, "survey256": survey256, "serve384": serve384}
 
 
 if __name__ == "__main__":

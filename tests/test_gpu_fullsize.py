@@ -7,6 +7,8 @@ from its seed and checked against the stored checksum).
 * 256^3 throughput mock (the configuration bench.py times): sampled pairs.
 * 256^3 survey window (L = 2000, 2M galaxies in a half shell, 20M randoms,
   FKP weights, {000, 202, 112, 404}, 25 shells): sampled pairs, alpha and I.
+* 384^3 serving request (radix-3 grid, 2M particles, {000, 110, 202}):
+  sampled pairs.
 
 Tolerance: 1e-4 normwise per multipole (max |dB| / max |B| over the compared
 pairs), FP32 fields with FP64 accumulation.
@@ -113,4 +115,20 @@ def test_survey256_sampled_pairs():
     # FP32 plan stores rounded to FP32; n-bar here takes 50 radial values, so
     # those roundings need not average out: |dI / I| <= 3 * 2^-24
     assert res["I"] == pytest.approx(float(exp["I"]), rel=3 * 2.0 ** -24)
+    assert np.all(err <= 1e-4)
+
+
+def test_serve384_sampled_pairs():
+    exp = np.load(os.path.join(GOLDEN, "serve384_seed7001.npz"))
+    spec, cat = workload("box256", seed=7001, n_target=2_000_000)
+    assert np.allclose(_checksum(cat), exp["checksum"], rtol=1e-12, atol=0)
+    req = _request("box256", n=384, multipoles=[(0, 0, 0), (1, 1, 0), (2, 0, 2)])
+    _say("serve384", len(cat["pos"]), "particles")
+    plan = tsb.Plan(**req)
+    assert np.array_equal(np.array(plan.nmode), exp["nmode"])
+    res = plan.measure(tsb.catalog_to_device(cat))
+    pairs = [tuple(p) for p in exp["pairs"]]
+    err = _compare(res["B"], exp["B"], pairs)
+    _say("serve384 normwise errors per multipole (sampled pairs)", err, "I", res["I"], float(exp["I"]))
+    assert res["I"] == pytest.approx(float(exp["I"]), rel=1e-12)
     assert np.all(err <= 1e-4)
