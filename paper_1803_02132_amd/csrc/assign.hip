@@ -504,23 +504,50 @@ __device__ inline void node_dir(const double* origin, double h, const double* ob
   }
 }
 
-constexpr int kVisitChunk = 128;  // particles staged in LDS at a time (two wavefronts stage them)
+constexpr int kVisitChunk = 128;  // particles staged in LDS at a time (a power of two)
 constexpr int kPartVisits = 256;  // visits per work item; busier tiles are split
 constexpr int kTileBlock = 256;    // threads per workgroup of the tile kernel
 constexpr int kMaxHeavy = 2048;   // split tiles with a slot of their own (others run whole)
 
-// A staged particle for one grid copy: on each axis the stencil nodes that
-// fall inside the tile, as weights and offsets into the tile's cell index,
-// and its channel weights (plan precision). A work item is one (particle,
-// in-tile x node): it adds the particle's contributions to the in-tile (y, z)
-// nodes of that plane.
-template <typename T, int NCH>
-struct alignas(16) Visit {
-  T c[NCH];
-  T w[3][3];
-  short off[3][3];
-  unsigned char cnt[3];
+// A staged (particle, grid copy) visit: per axis the stencil parameter d (the
+// kernel weights are functions of d and the stencil index) and which stencil
+// nodes fall inside the tile: the first in-tile stencil index s0, their count
+// and the in-tile node of each stencil index (consecutive stencil indices;
+// with one tile per axis the nodes may wrap inside the tile). The channel
+// weights live per particle beside it. A work item is one (visit, in-tile x
+// node): it adds the particle's contributions to the in-tile (y, z) nodes of
+// that plane.
+template <typename T>
+struct Visit {
+  T d[3];
+  unsigned char s0[3], cnt[3], l[3][3];
 };
+
+// Weight of stencil node s (0 .. p-1) of the order-p kernel at parameter d
+// (the same expressions as axis_stencil).
+template <typename T>
+__device__ inline T stencil_weight(int p, T d, int s) {
+  if (p == 3) {
+    const T h = (T)0.5;
+    return s == 0 ? h * (h - d) * (h - d) : (s == 1 ? (T)0.75 - d * d : h * (h + d) * (h + d));
+  }
+  if (p == 2) return s == 0 ? (T)1 - d : d;
+  return (T)1;
+}
+
+// Parameter d of axis_stencil for grid coordinate u (the weights follow from
+// stencil_weight): TSC and NGP measure from the nearest node, CIC from the
+// node below.
+__device__ inline double stencil_param(double u, int p, int* j0) {
+  if (p == 2) {
+    const double j = floor(u);
+    *j0 = (int)j;
+    return u - j;
+  }
+  const double j = floor(u + 0.5);
+  *j0 = (int)j - (p == 3 ? 1 : 0);
+  return u - j;
+}
 
 // Fixed-point rounding to the nearest integer. FP64 plans: llrint. FP32 plans:
 // |x| < 2^51, so adding 1.5 * 2^52 leaves round-to-nearest(x) in the low
@@ -585,39 +612,46 @@ __device__ inline void put_node(const unsigned long long* w, size_t wstride, int
 }
 
 // Persistent workgroups walk the work items (a tile, or a part of a busy
-// tile), one grid copy at a time. The particles that reach the tile are staged
-// 128 at a time (stencil weights and in-tile node offsets computed once per
-// particle); then every (particle, in-tile x node) is one work item over all
+// tile). The particles that reach the tile are staged 128 at a time as visits
+// (stencil parameters and in-tile node ranges computed once per particle and
+// grid copy); then every (visit, in-tile x node) is one work item over all
 // lanes, which adds the particle's fixed-point contributions to each in-tile
-// (y, z) node of that plane and every channel.
+// (y, z) node of that plane and every channel. Packed FP32 tiles stage both
+// grid copies in one pass (their two-channel words of both copies fit the
+// LDS of one unpacked copy); other tiles run one copy per pass. FP32 plans
+// with up to 8 channel slots keep four workgroups per CU.
 template <typename T, int NCH>
-__global__ void __launch_bounds__(kTileBlock) assign_tile_kernel(TileArgs a, Records<T> rec) {
+__global__ void __launch_bounds__(kTileBlock, (sizeof(T) == 4 && NCH <= 8) ? 4 : 1)
+    assign_tile_kernel(TileArgs a, Records<T> rec) {
   typedef typename cplx<T>::type T2;
-  extern __shared__ unsigned long long acc[];   // [nw][T^3], one grid copy
+  constexpr int kPC = sizeof(T) == 4 ? 2 : 1;   // grid copies staged per pass at most
+  constexpr int kV = kVisitChunk * kPC;         // visits per chunk
+  extern __shared__ unsigned long long acc[];   // [nw][T^3]
   __shared__ int r_start[2][kMaxRanges];        // range tables of the current and the next work item
   __shared__ int r_off[2][kMaxRanges + 1];
   __shared__ int item[2][3];                    // tile, part, heavy slot
-  __shared__ Visit<T, NCH> vis[kVisitChunk];
-  __shared__ int it_first[kVisitChunk];      // first work item of each staged particle
-  __shared__ int wtot[2];                     // items of each staging wavefront
+  __shared__ Visit<T> vis[kV];                  // [copy in pass][particle]
+  __shared__ T pch[kVisitChunk][NCH];           // channel weights per staged particle
+  __shared__ int it_first[kV];                  // first work item of each visit
+  __shared__ int wtot[kTileBlock / 64];         // items of each staging wavefront
   __shared__ double wsum[kTileBlock / 64];
-  __shared__ unsigned char it_vis[kVisitChunk * 3];
+  __shared__ unsigned char it_vis[kV * 3];
   const int TS = a.T, T3 = TS * TS * TS;
   const int npair = a.ngrid, nw = a.nw, wr = a.wr;
   const int nslot = 2 * npair;   // grid slots; the randoms slot sits in register NCH - 1
   const int nwork = *a.nwork;
   const int N = a.N, p = a.p;
   const int NT = a.NT;
-  const int lane = threadIdx.x & 63;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int vt = threadIdx.x & (kVisitChunk - 1);   // the particle this thread stages and prefetches
   T2* out = (T2*)a.out;
   const size_t N3 = (size_t)N * N * N;
-  const int stride[3] = {TS * TS, TS, 1};
   const double scale = a.scal->scale, inv_scale = a.scal->inv_scale, cmax = a.scal->cmax, alpha = a.scal->alpha;
 
   // Work-item pipeline: the ranges of the next-but-one item are fetched into
   // the first wavefront's registers, and the first chunk of particle records
-  // of the next item into the staging lanes' registers, while the current
-  // item is processed; the current item's first chunk serves both grid copies.
+  // of the next item into registers (each particle in every thread that
+  // stages it), while the current item is processed.
   int pf_tile = 0, pf_hs = -1, pf_part = 0, pf_st = 0, pf_len = 0;
   auto fetch = [&](int w) {
     if (threadIdx.x < 64 && w < nwork) {
@@ -678,10 +712,10 @@ __global__ void __launch_bounds__(kTileBlock) assign_tile_kernel(TileArgs a, Rec
     fetch(blockIdx.x);
     publish(0);
     __syncthreads();
-    if (threadIdx.x < kVisitChunk) {
+    {
       int v0, v1;
       window(0, &v0, &v1);
-      if (v0 + (int)threadIdx.x < v1) load_rec(0, v0 + threadIdx.x, cu, cc);
+      if (v0 + vt < v1) load_rec(0, v0 + vt, cu, cc);
     }
     fetch(blockIdx.x + gridDim.x);
   }
@@ -692,23 +726,25 @@ __global__ void __launch_bounds__(kTileBlock) assign_tile_kernel(TileArgs a, Rec
   const int o3[3] = {tx * TS, ty * TS, tz * TS};
   int v0, v1;
   window(cb, &v0, &v1);
-  // FP32 tiles that run whole: two channels per word at the tile's own scale
+  // FP32 tiles that run whole: two channels per word at the tile's own scale,
+  // both grid copies in one pass (word of copy c, grid k: c * npair + k)
   const bool packed = sizeof(T) == 4 && r_off[cb][64] <= kPartVisits;
   const int et = packed ? tile_exponent(r_off[cb][64], cmax * a.wmax) : 0;
   const float tscale = ldexpf(1.0f, et);
+  const int ncp = packed ? a.copies : 1;                 // grid copies per pass
+  const int wrw = wr < 0 ? -1 : (packed ? a.copies * npair : wr);   // randoms word
   const bool has_next = w + (int)gridDim.x < nwork;
   double sumI = 0.0;
-  for (int g = 0; g < a.copies; ++g) {
-    const int nwg = (g == 0 || wr < 0) ? nw : nw - 1;   // the randoms word is the last one, copy 0 only
+  for (int g0 = 0; g0 < a.copies; g0 += ncp) {
     for (int i = threadIdx.x; i < nw * T3; i += kTileBlock) acc[i] = 0ull;
     for (int c0 = v0; c0 < v1; c0 += kVisitChunk) {
       const int nv = min(kVisitChunk, v1 - c0);
       __syncthreads();   // acc cleared / previous chunk consumed
-      int items = 0, inc = 0;
-      if (threadIdx.x < kVisitChunk) {
-        // two wavefronts: one particle per lane, then per-wavefront item prefixes
-        const int v = threadIdx.x;
-        if (v < nv) {
+      int items = 0;
+      {
+        // staging: thread t stages copy g0 + (t >> 7) of particle t & 127
+        const int cp = threadIdx.x / kVisitChunk;
+        if (cp < ncp && vt < nv) {
           double u[3];
           T cv[NCH];
           if (c0 == v0) {   // the item's first chunk: already in registers
@@ -718,50 +754,59 @@ __global__ void __launch_bounds__(kTileBlock) assign_tile_kernel(TileArgs a, Rec
 #pragma unroll
             for (int ch = 0; ch < NCH; ++ch) cv[ch] = cc[ch];
           } else {
-            load_rec(cb, c0 + v, u, cv);
+            load_rec(cb, c0 + vt, u, cv);
           }
-          Visit<T, NCH>& V = vis[v];
+          Visit<T>& V = vis[threadIdx.x];
           int cnt[3] = {0, 0, 0};
           if (isfinite(u[0])) {
             for (int ax = 0; ax < 3; ++ax) {
-              double wt[3];
-              const int j0 = axis_stencil(u[ax] + 0.5 * g, p, wt);
+              int j0;
+              V.d[ax] = (T)stencil_param(u[ax] + 0.5 * (g0 + cp), p, &j0);
+              int s0 = -1;
               for (int sidx = 0; sidx < p; ++sidx) {
                 int jj = j0 + sidx;
                 jj += jj < 0 ? N : (jj >= N ? -N : 0);
                 const int l = jj - o3[ax];
-                if (l >= 0 && l < TS) {
-                  V.w[ax][cnt[ax]] = (T)wt[sidx];
-                  V.off[ax][cnt[ax]] = (short)(l * stride[ax]);
+                const bool in = l >= 0 && l < TS;
+                V.l[ax][sidx] = (unsigned char)(in ? l : 0);
+                if (in) {
+                  if (s0 < 0) s0 = sidx;
                   ++cnt[ax];
                 }
               }
+              V.s0[ax] = (unsigned char)max(s0, 0);
             }
           }
+          if (cp == 0) {
 #pragma unroll
-          for (int ch = 0; ch < NCH; ++ch) V.c[ch] = cv[ch];
+            for (int ch = 0; ch < NCH; ++ch) pch[vt][ch] = cv[ch];
+          }
           if (cnt[0] == 0 || cnt[1] == 0 || cnt[2] == 0) cnt[0] = cnt[1] = cnt[2] = 0;
           V.cnt[0] = (unsigned char)cnt[0];
           V.cnt[1] = (unsigned char)cnt[1];
           V.cnt[2] = (unsigned char)cnt[2];
           items = cnt[0];
         }
-        inc = items;
-        for (int off = 1; off < 64; off <<= 1) {
-          const int x = __shfl_up(inc, off);
-          if (lane >= off) inc += x;
-        }
-        if (lane == 63) wtot[v >> 6] = inc;
       }
+      int inc = items;
+      for (int off = 1; off < 64; off <<= 1) {
+        const int x = __shfl_up(inc, off);
+        if (lane >= off) inc += x;
+      }
+      if (lane == 63) wtot[wave] = inc;
       __syncthreads();
-      if (threadIdx.x < kVisitChunk) {
-        // item -> particle map; the second wavefront follows the first one's items
-        const int v = threadIdx.x;
-        const int first = inc - items + (v >= 64 ? wtot[0] : 0);
-        it_first[v] = first;
-        for (int k = 0; k < items; ++k) it_vis[first + k] = (unsigned char)v;
+      int nitems = 0, wbase = 0;
+#pragma unroll
+      for (int k = 0; k < kTileBlock / 64; ++k) {
+        wbase += k < wave ? wtot[k] : 0;
+        nitems += wtot[k];
       }
-      const int nitems = wtot[0] + wtot[1];
+      {
+        // item -> visit map (visits of a pass are numbered by staging thread)
+        const int first = wbase + inc - items;
+        if (threadIdx.x < kV) it_first[threadIdx.x] = first;
+        for (int k = 0; k < items; ++k) it_vis[first + k] = (unsigned char)threadIdx.x;
+      }
       __syncthreads();
       // items in a scrambled order (multiplier prime to their number), so that
       // the lanes of a wavefront work on particles far apart in the chunk
@@ -769,25 +814,30 @@ __global__ void __launch_bounds__(kTileBlock) assign_tile_kernel(TileArgs a, Rec
       for (int i0 = threadIdx.x; i0 < nitems; i0 += kTileBlock) {
         const int it = (i0 * imult) % nitems;
         const int vi = it_vis[it];
-        const Visit<T, NCH>& V = vis[vi];
+        const Visit<T>& V = vis[vi];
+        const int cp = vi / kVisitChunk, pv = vi & (kVisitChunk - 1);
         // the particle's data to registers once (the atomics below may alias it)
         T c[NCH];
 #pragma unroll
-        for (int ch = 0; ch < NCH; ++ch) c[ch] = V.c[ch];
+        for (int ch = 0; ch < NCH; ++ch) c[ch] = pch[pv][ch];
         const int sx = it - it_first[vi];
         const int cy = V.cnt[1], cz = V.cnt[2];
-        const T wx = V.w[0][sx];
-        const int ox = V.off[0][sx];
+        const int sx0 = V.s0[0] + sx, sy0 = V.s0[1], sz0 = V.s0[2];
+        const T wx = stencil_weight<T>(p, V.d[0], sx0);
+        const int ox = V.l[0][sx0] * TS * TS;
         T wy[3], wz[3];
         int oy[3], oz[3];
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
-          wy[k] = V.w[1][k];
-          oy[k] = V.off[1][k];
-          wz[k] = V.w[2][k];
-          oz[k] = V.off[2][k];
+          const int ky = min(sy0 + k, 2), kz = min(sz0 + k, 2);   // indices past the count are not used
+          wy[k] = stencil_weight<T>(p, V.d[1], sy0 + k);
+          oy[k] = V.l[1][ky] * TS;
+          wz[k] = stencil_weight<T>(p, V.d[2], sz0 + k);
+          oz[k] = V.l[2][kz];
         }
         const T wxs = packed ? wx * (T)tscale : wx;   // packed: the tile scale folded into the x weight
+        unsigned long long* cbase = acc + (packed ? (size_t)cp * npair * T3 : 0);
+        const bool randoms = wrw >= 0 && g0 + cp == 0;
 #pragma unroll
         for (int sy = 0; sy < 3; ++sy) {
           if (sy >= cy) break;
@@ -797,7 +847,7 @@ __global__ void __launch_bounds__(kTileBlock) assign_tile_kernel(TileArgs a, Rec
           for (int sz = 0; sz < 3; ++sz) {
             if (sz >= cz) break;
             const T Wt = wxy * wz[sz];
-            unsigned long long* cellp = acc + base + oz[sz];
+            unsigned long long* cellp = cbase + base + oz[sz];
             if (sizeof(T) == 4 && packed) {
 #pragma unroll
               for (int k = 0; k < NCH / 2; ++k) {
@@ -813,28 +863,29 @@ __global__ void __launch_bounds__(kTileBlock) assign_tile_kernel(TileArgs a, Rec
                 atomicAdd(cellp + (size_t)k * T3, (unsigned long long)to_fixed<T>((double)c[k] * Ws));
               }
             }
-            if (wr >= 0 && g == 0) {   // randoms channel: full 64-bit word, plan-wide scale
+            if (randoms) {   // randoms channel: full 64-bit word, plan-wide scale
               const double Wr = (double)(wx * wy[sy] * wz[sz]) * scale;
-              atomicAdd(cellp + (size_t)wr * T3, (unsigned long long)to_fixed<T>((double)c[NCH - 1] * Wr));
+              atomicAdd(acc + (size_t)wrw * T3 + base + oz[sz],
+                        (unsigned long long)to_fixed<T>((double)c[NCH - 1] * Wr));
             }
           }
         }
       }
     }
-    if (g == 0 && has_next) publish(cb ^ 1);
+    if (g0 == 0 && has_next) publish(cb ^ 1);
     __syncthreads();
-    if (g == 0 && has_next) {
+    if (g0 == 0 && has_next) {
       // the next item's first chunk of records, loaded while this one finishes
-      if (threadIdx.x < kVisitChunk) {
-        int n0, n1;
-        window(cb ^ 1, &n0, &n1);
-        if (n0 + (int)threadIdx.x < n1) load_rec(cb ^ 1, n0 + threadIdx.x, nu, ncv);
-      }
+      int n0, n1;
+      window(cb ^ 1, &n0, &n1);
+      if (n0 + vt < n1) load_rec(cb ^ 1, n0 + vt, nu, ncv);
       fetch(w + 2 * gridDim.x);
     }
     if (hs >= 0) {
-      // part of a split tile: add the fixed-point sums into its slot (integer, order-free)
-      unsigned long long* hb = a.heavy + ((size_t)hs * a.copies + g) * nw * T3;
+      // part of a split tile (one copy per pass): add the fixed-point sums
+      // into its slot (integer, order-free)
+      const int nwg = (g0 == 0 || wr < 0) ? nw : nw - 1;   // the randoms word is the last one, copy 0 only
+      unsigned long long* hb = a.heavy + ((size_t)hs * a.copies + g0) * nw * T3;
       for (int i = threadIdx.x; i < nwg * T3; i += kTileBlock) {
         const unsigned long long v = acc[i];
         if (v != 0ull) atomicAdd(hb + i, v);
@@ -842,16 +893,21 @@ __global__ void __launch_bounds__(kTileBlock) assign_tile_kernel(TileArgs a, Rec
       __syncthreads();
       continue;
     }
-    // write out this copy
+    // write out the copies of this pass
     {
-      T2* tout = out + (size_t)g * npair * N3 + ((size_t)o3[0] * N + o3[1]) * N + o3[2];
       const int lt = a.lt, tm = TS - 1;
-      for (int cell = threadIdx.x; cell < T3; cell += kTileBlock) {
-        const int lx = cell >> (2 * lt), ly = (cell >> lt) & tm, lz = cell & tm;
-        put_node<T>(acc + cell, T3, npair, packed, -et, inv_scale, tout + ((lx * N + ly) * N + lz), N3);
-        if (wr >= 0 && g == 0) {
-          // Sec. 4.2, eq. 37: sum_j (alpha R_j)^3 over this tile
-          const double v = alpha * (double)(long long)acc[(size_t)wr * T3 + cell] * inv_scale;
+      for (int cp = 0; cp < ncp; ++cp) {
+        T2* tout = out + (size_t)(g0 + cp) * npair * N3 + ((size_t)o3[0] * N + o3[1]) * N + o3[2];
+        const unsigned long long* cw = acc + (packed ? (size_t)cp * npair * T3 : 0);
+        for (int cell = threadIdx.x; cell < T3; cell += kTileBlock) {
+          const int lx = cell >> (2 * lt), ly = (cell >> lt) & tm, lz = cell & tm;
+          put_node<T>(cw + cell, T3, npair, packed, -et, inv_scale, tout + ((lx * N + ly) * N + lz), N3);
+        }
+      }
+      if (wrw >= 0 && g0 == 0) {
+        // Sec. 4.2, eq. 37: sum_j (alpha R_j)^3 over this tile
+        for (int cell = threadIdx.x; cell < T3; cell += kTileBlock) {
+          const double v = alpha * (double)(long long)acc[(size_t)wrw * T3 + cell] * inv_scale;
           sumI += v * v * v;
         }
       }
@@ -861,7 +917,7 @@ __global__ void __launch_bounds__(kTileBlock) assign_tile_kernel(TileArgs a, Rec
   if (wr >= 0 && hs < 0) {
     // fixed-order sum: within each wavefront, then over the wavefronts
     for (int off = 32; off > 0; off >>= 1) sumI += __shfl_xor(sumI, off);
-    if (lane == 0) wsum[threadIdx.x >> 6] = sumI;
+    if (lane == 0) wsum[wave] = sumI;
     __syncthreads();
     if (threadIdx.x == 0) {
       double t = 0.0;
