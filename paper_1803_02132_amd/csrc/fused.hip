@@ -391,12 +391,18 @@ __global__ void __launch_bounds__(kWBlock) fz_reduce_wide_kernel(FusedArgs<float
       const bool live = b < nb;
       const float* qr = Q + ((size_t)q * nb + (live ? b : 0)) * CP + kh;
       const float* fr = F2 + ((size_t)a.tb.q_f2row[q] * nb + (live ? b : 0)) * CP + kh;
-      const int kl = M / a.ksplit, k0 = sp * kl;
+      const int kl = M / a.ksplit, k0 = sp * kl;   // kl is a multiple of 8
       floatx16 c = {};
-      for (int kk = k0; kk < k0 + kl; kk += 2) {
-        const float av = live ? qr[kk] : 0.f;
-        const float bv = live ? fr[kk] : 0.f;
-        c = __builtin_amdgcn_mfma_f32_32x32x2f32(av, bv, c, 0, 0, 0);
+      for (int kk = k0; kk < k0 + kl; kk += 8) {
+        // four steps' operands first, so that one LDS wait covers four MFMAs
+        float av[4], bv[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          av[j] = live ? qr[kk + 2 * j] : 0.f;
+          bv[j] = live ? fr[kk + 2 * j] : 0.f;
+        }
+#pragma unroll
+        for (int j = 0; j < 4; ++j) c = __builtin_amdgcn_mfma_f32_32x32x2f32(av[j], bv[j], c, 0, 0, 0);
       }
 #pragma unroll
       for (int r = 0; r < 16; ++r) acc[r] += (double)c[r];
