@@ -93,15 +93,15 @@ int plan_alloc(Plan& P, bool dry) {
   if (P.box_mode && P.los_kind == TSB_LOS_LOCAL) ALLOC(P.d_yspec, ng * PG * PG * PG * c);
   const int64_t ntiles = (int64_t)P.NT * P.NT * P.NT;
   P.nbk = ntiles * 27;
-  ALLOC(P.d_bk_count, (2 * P.nbk + 1) * 4);   // counts, cursors, heavy-slot counter
+  ALLOC(P.d_bk_count, (2 * P.nbk + 2) * 4);   // counts, cursors, heavy-slot and extra-part counters
   P.d_bk_cursor = dry ? nullptr : P.d_bk_count + P.nbk;
   ALLOC(P.d_bk_start, (P.nbk + 1) * 4);
   ALLOC(P.d_scan_part, ((P.nbk + kScanChunk - 1) / kScanChunk + 1) * 4);
-  ALLOC(P.d_tile_parts, ntiles * 4);
   ALLOC(P.d_tile_hslot, ntiles * 4);
-  ALLOC(P.d_tile_pstart, (ntiles + 1) * 4);
   ALLOC(P.d_heavy_tile, (int64_t)assign_max_heavy() * 4);
   ALLOC(P.d_heavy, assign_heavy_bytes(P));
+  // split-tile slots start at zero; the conversion kernel clears each slot it reads
+  if (!dry) TSB_HIP(hipMemset(P.d_heavy, 0, (size_t)assign_heavy_bytes(P)));
   ALLOC(P.d_scal, (int64_t)sizeof(DevScalars));
   ALLOC(P.d_sum_partials, std::max<int64_t>(ntiles, 8 * 512) * 8);
   ALLOC(P.d_partials, (int64_t)P.red_wg * std::max<int64_t>((int64_t)P.outs.size(), 1) * 8);
@@ -153,7 +153,7 @@ void plan_free(Plan& P) {
                   P.d_tw_n, P.d_tw_m, P.d_bin_lut, P.d_fkinds, P.d_fcomp, P.d_gcomp, P.d_terms,
                   P.d_qgroups, P.d_outs, P.d_out_norm, P.d_partials, P.d_B, P.d_scal, P.d_sum_partials,
                   P.d_bk_count, P.d_bk_start, P.d_scan_part, P.d_keys, P.d_rec,
-                  P.d_f2idx, P.d_yspec, P.d_axis_tab, P.d_tile_parts, P.d_tile_hslot, P.d_tile_pstart, P.d_heavy_tile,
+                  P.d_f2idx, P.d_yspec, P.d_axis_tab, P.d_tile_hslot, P.d_heavy_tile,
                   P.d_heavy, P.d_work};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);

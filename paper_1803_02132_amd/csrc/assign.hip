@@ -460,9 +460,11 @@ struct TileArgs {
   // reads of one tile: neighbour offset (9 (dx+1) + 3 (dy+1) + dz + 1) and class range
   int nr;
   int rd[kMaxRanges], rcl[kMaxRanges], rch[kMaxRanges];
-  // work items: (tile, part); a tile with more than kPartVisits visits is split
-  const int2* work;
-  const int* nwork;            // number of work items (device)
+  // work items: the extra parts of split tiles (a tile with more than
+  // kPartVisits visits), then part 0 of every tile
+  const int2* work;            // extra parts (tile, part >= 1)
+  const int* nextra;           // number of extra parts (device)
+  int ntiles;
   const int* hslot;            // per tile: heavy slot or -1
   unsigned long long* heavy;   // [slot][copies][nw][T^3] fixed-point sums of split tiles
 };
@@ -523,16 +525,30 @@ struct Visit {
   unsigned char s0[3], cnt[3], l[3][3];
 };
 
-// Weight of stencil node s (0 .. p-1) of the order-p kernel at parameter d
-// (the same expressions as axis_stencil).
+// Weights of the p stencil nodes of the order-p kernel at parameter d (the
+// same expressions as axis_stencil; unused entries 0).
 template <typename T>
-__device__ inline T stencil_weight(int p, T d, int s) {
+__device__ inline void stencil_weights(int p, T d, T* w) {
+  const T h = (T)0.5;
   if (p == 3) {
-    const T h = (T)0.5;
-    return s == 0 ? h * (h - d) * (h - d) : (s == 1 ? (T)0.75 - d * d : h * (h + d) * (h + d));
+    w[0] = h * (h - d) * (h - d);
+    w[1] = (T)0.75 - d * d;
+    w[2] = h * (h + d) * (h + d);
+  } else if (p == 2) {
+    w[0] = (T)1 - d;
+    w[1] = d;
+    w[2] = (T)0;
+  } else {
+    w[0] = (T)1;
+    w[1] = (T)0;
+    w[2] = (T)0;
   }
-  if (p == 2) return s == 0 ? (T)1 - d : d;
-  return (T)1;
+}
+
+// w[s] for a stencil index s in 0..2 held in a register (static indexing)
+template <typename T>
+__device__ inline T pick3(const T* w, int s) {
+  return s == 0 ? w[0] : (s == 1 ? w[1] : w[2]);
 }
 
 // Parameter d of axis_stencil for grid coordinate u (the weights follow from
@@ -639,7 +655,7 @@ __global__ void __launch_bounds__(kTileBlock, (sizeof(T) == 4 && NCH <= 8) ? 4 :
   const int TS = a.T, T3 = TS * TS * TS;
   const int npair = a.ngrid, nw = a.nw, wr = a.wr;
   const int nslot = 2 * npair;   // grid slots; the randoms slot sits in register NCH - 1
-  const int nwork = *a.nwork;
+  const int nextra = *a.nextra, nwork = a.ntiles + nextra;
   const int N = a.N, p = a.p;
   const int NT = a.NT;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -655,7 +671,7 @@ __global__ void __launch_bounds__(kTileBlock, (sizeof(T) == 4 && NCH <= 8) ? 4 :
   int pf_tile = 0, pf_hs = -1, pf_part = 0, pf_st = 0, pf_len = 0;
   auto fetch = [&](int w) {
     if (threadIdx.x < 64 && w < nwork) {
-      const int2 wk = a.work[w];
+      const int2 wk = w < nextra ? a.work[w] : make_int2(w - nextra, 0);
       pf_tile = wk.x;
       pf_part = wk.y;
       pf_hs = a.hslot[wk.x];
@@ -823,16 +839,20 @@ __global__ void __launch_bounds__(kTileBlock, (sizeof(T) == 4 && NCH <= 8) ? 4 :
         const int sx = it - it_first[vi];
         const int cy = V.cnt[1], cz = V.cnt[2];
         const int sx0 = V.s0[0] + sx, sy0 = V.s0[1], sz0 = V.s0[2];
-        const T wx = stencil_weight<T>(p, V.d[0], sx0);
+        T wa[3], wb[3], wc[3];
+        stencil_weights<T>(p, V.d[0], wa);
+        stencil_weights<T>(p, V.d[1], wb);
+        stencil_weights<T>(p, V.d[2], wc);
+        const T wx = pick3(wa, sx0);
         const int ox = V.l[0][sx0] * TS * TS;
         T wy[3], wz[3];
         int oy[3], oz[3];
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
           const int ky = min(sy0 + k, 2), kz = min(sz0 + k, 2);   // indices past the count are not used
-          wy[k] = stencil_weight<T>(p, V.d[1], sy0 + k);
+          wy[k] = pick3(wb, ky);
           oy[k] = V.l[1][ky] * TS;
-          wz[k] = stencil_weight<T>(p, V.d[2], sz0 + k);
+          wz[k] = pick3(wc, kz);
           oz[k] = V.l[2][kz];
         }
         const T wxs = packed ? wx * (T)tscale : wx;   // packed: the tile scale folded into the x weight
@@ -936,7 +956,7 @@ __global__ void __launch_bounds__(kTileBlock, (sizeof(T) == 4 && NCH <= 8) ? 4 :
 }
 
 // Split tiles (one word per channel slot, plan-wide scale): convert the
-// summed fixed-point grids of each heavy slot.
+// summed fixed-point grids of each heavy slot, then clear the slot.
 template <typename T>
 __global__ void __launch_bounds__(kBlock) heavy_final_kernel(TileArgs a, const int* heavy_tile, const int* nheavy) {
   typedef typename cplx<T>::type T2;
@@ -952,7 +972,7 @@ __global__ void __launch_bounds__(kBlock) heavy_final_kernel(TileArgs a, const i
   const size_t N3 = (size_t)N * N * N;
   double sumI = 0.0;
   for (int g = 0; g < a.copies; ++g) {
-    const unsigned long long* hb = a.heavy + ((size_t)slot * a.copies + g) * nw * T3;
+    unsigned long long* hb = a.heavy + ((size_t)slot * a.copies + g) * nw * T3;
     for (int cell = threadIdx.x; cell < T3; cell += kBlock) {
       const int lx = cell / (TS * TS), ly = (cell / TS) % TS, lz = cell % TS;
       const size_t lin = ((size_t)(o3[0] + lx) * N + (o3[1] + ly)) * N + (o3[2] + lz);
@@ -961,6 +981,8 @@ __global__ void __launch_bounds__(kBlock) heavy_final_kernel(TileArgs a, const i
         const double v = a.scal->alpha * (double)(long long)hb[(size_t)wr * T3 + cell] * inv_scale;
         sumI += v * v * v;
       }
+      // the slot starts the next measurement at zero (each word read by this thread only)
+      for (int k = 0; k < nw; ++k) hb[(size_t)k * T3 + cell] = 0ull;
     }
   }
   if (wr >= 0) {
@@ -974,45 +996,34 @@ __global__ void __launch_bounds__(kBlock) heavy_final_kernel(TileArgs a, const i
   }
 }
 
-// Work planning, one thread per tile: visits, parts and heavy slots.
-__global__ void __launch_bounds__(kBlock) tile_parts_kernel(TileArgs a, int ntiles, int* parts, int* hslot,
-                                                            int* heavy_tile, int* nheavy) {
-  const int t = blockIdx.x * kBlock + threadIdx.x;
-  if (t >= ntiles) return;
-  int total = 0;
-  for (int r = 0; r < a.nr; ++r) {
-    int st, len;
-    tile_range(a, t, r, &st, &len);
-    total += len;
+// Work planning, one wavefront per tile: the tile's visits (its ranges summed
+// across the lanes), its heavy slot, and for a split tile its parts after the
+// first, appended to the extra work list. Work items are order-free (integer
+// sums), so the append order does not matter.
+__global__ void __launch_bounds__(kBlock) tile_parts_kernel(TileArgs a, int ntiles, int* hslot, int* heavy_tile,
+                                                            int* nheavy, int* nextra, int2* extra) {
+  const int lane = threadIdx.x & 63;
+  const int t = blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
+  if (t >= ntiles) return;   // the whole wavefront leaves together
+  int len = 0;
+  if (lane < a.nr) {
+    int st;
+    tile_range(a, t, lane, &st, &len);
   }
-  int np = (total + kPartVisits - 1) / kPartVisits;
+  for (int off = 32; off > 0; off >>= 1) len += __shfl_xor(len, off);
+  if (lane != 0) return;
+  const int np = (len + kPartVisits - 1) / kPartVisits;
   int hs = -1;
   if (np > 1) {
     const int sl = atomicAdd(nheavy, 1);
-    if (sl < kMaxHeavy) {
+    if (sl < kMaxHeavy) {   // out of slots: the tile runs whole
       hs = sl;
       heavy_tile[sl] = t;
-    } else {
-      np = 1;   // out of slots: runs whole
+      const int e = atomicAdd(nextra, np - 1);
+      for (int q = 1; q < np; ++q) extra[e + q - 1] = make_int2(t, q);
     }
   }
-  parts[t] = np < 1 ? 1 : np;
   hslot[t] = hs;
-}
-
-__global__ void __launch_bounds__(kBlock) tile_work_kernel(int ntiles, const int* parts, const int* pstart,
-                                                           int2* work) {
-  const int t = blockIdx.x * kBlock + threadIdx.x;
-  if (t >= ntiles) return;
-  const int b = pstart[t];
-  for (int p = 0; p < parts[t]; ++p) work[b + p] = make_int2(t, p);
-}
-
-__global__ void __launch_bounds__(kBlock) heavy_zero_kernel(unsigned long long* heavy, const int* nheavy,
-                                                            int64_t per_slot) {
-  const int64_t n = (int64_t)min(*nheavy, kMaxHeavy) * per_slot;
-  for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock)
-    heavy[i] = 0ull;
 }
 
 // y_L^M*(x^_node) on both grid copies in the complex-grid layout of the
@@ -1299,29 +1310,17 @@ int assign_back_impl(Plan& P, const ChanInfo& ci, hipStream_t s) {
   a.tile_I = P.d_sum_partials;
   a.nr = tile_ranges(P.NT, a.rd, a.rcl, a.rch);
   if (a.nr > kMaxRanges) return fail(TSB_E_UNSUPPORTED, "assignment: too many bucket ranges");
-  int* nheavy = P.d_bk_count + 2 * P.nbk;   // cleared with the bucket counters
+  int* nheavy = P.d_bk_count + 2 * P.nbk;   // heavy slots and extra parts: cleared with the bucket counters
+  int* nextra = nheavy + 1;
   a.work = (const int2*)P.d_work;
-  a.nwork = P.d_tile_pstart + ntiles;
+  a.nextra = nextra;
+  a.ntiles = ntiles;
   a.hslot = P.d_tile_hslot;
   a.heavy = (unsigned long long*)P.d_heavy;
   prof_begin(P, kStAssign, s);
-  {
-    // work items: tiles with more than kPartVisits visits are split into parts
-    const int tb = (ntiles + kBlock - 1) / kBlock;
-    hipLaunchKernelGGL(tile_parts_kernel, dim3(tb), dim3(kBlock), 0, s, a, ntiles, P.d_tile_parts, P.d_tile_hslot,
-                       P.d_heavy_tile, nheavy);
-    const int nparts = (ntiles + kScanChunk - 1) / kScanChunk;
-    hipLaunchKernelGGL(scan_sums_kernel, dim3(nparts), dim3(kBlock), 0, s, (const int*)P.d_tile_parts,
-                       (int64_t)ntiles, P.d_scan_part);
-    hipLaunchKernelGGL(scan_parts_kernel, dim3(1), dim3(kBlock), 0, s, P.d_scan_part, nparts);
-    hipLaunchKernelGGL(scan_out_kernel, dim3(nparts), dim3(kBlock), 0, s, (const int*)P.d_tile_parts,
-                       (int64_t)ntiles, (const int*)P.d_scan_part, P.d_tile_pstart);
-    hipLaunchKernelGGL(tile_work_kernel, dim3(tb), dim3(kBlock), 0, s, ntiles, (const int*)P.d_tile_parts,
-                       (const int*)P.d_tile_pstart, (int2*)P.d_work);
-    const int64_t per_slot = (int64_t)P.copies * nw * P.T * P.T * P.T;
-    hipLaunchKernelGGL(heavy_zero_kernel, dim3(1024), dim3(kBlock), 0, s, (unsigned long long*)P.d_heavy,
-                       (const int*)nheavy, per_slot);
-  }
+  // work items: tiles with more than kPartVisits visits are split into parts
+  hipLaunchKernelGGL(tile_parts_kernel, dim3((ntiles + kBlock / 64 - 1) / (kBlock / 64)), dim3(kBlock), 0, s, a,
+                     ntiles, P.d_tile_hslot, P.d_heavy_tile, nheavy, nextra, (int2*)P.d_work);
   const size_t lds = (size_t)nw * P.T * P.T * P.T * sizeof(unsigned long long);
   hipLaunchKernelGGL((assign_tile_kernel<T, NCH>), dim3(std::max(1, P.tile_wgs)), dim3(kTileBlock), lds, s, a,
                      rec);
@@ -1359,8 +1358,8 @@ int run_assign(Plan& P, const tsb_catalog* data, const tsb_catalog* rand, hipStr
   const int nparts = (int)((nbk + kScanChunk - 1) / kScanChunk);
   prof_begin(P, kStBucket, s);
   // counts, cursors and the heavy-slot counter are adjacent: one fill clears them
-  hipLaunchKernelGGL(zero_ints_kernel, dim3(grid_blocks(2 * nbk + 1)), dim3(kBlock), 0, s, P.d_bk_count,
-                     2 * nbk + 1);
+  hipLaunchKernelGGL(zero_ints_kernel, dim3(grid_blocks(2 * nbk + 2)), dim3(kBlock), 0, s, P.d_bk_count,
+                     2 * nbk + 2);
   if (ntot > 0)
     hipLaunchKernelGGL(bucket_count_kernel, dim3(grid_blocks(ntot)), dim3(kBlock), 0, s, b);
   hipLaunchKernelGGL(scan_sums_kernel, dim3(nparts), dim3(kBlock), 0, s, (const int*)P.d_bk_count, nbk,

@@ -144,9 +144,7 @@ struct Plan {
   int* d_scan_part = nullptr;   // per-workgroup sums of the bucket scan
   int64_t nbk = 0;              // tiles * 27
   int* d_keys = nullptr;        // bucket key per particle
-  int* d_tile_parts = nullptr;  // work items per tile [ntiles]
   int* d_tile_hslot = nullptr;  // heavy slot per tile or -1 [ntiles]
-  int* d_tile_pstart = nullptr; // first work item per tile [ntiles + 1]
   int* d_heavy_tile = nullptr;  // tile of each heavy slot
   void* d_heavy = nullptr;      // fixed-point sums of split tiles [slot][copies][words][T^3]
   void* d_work = nullptr;       // work items (tile, part) [work_cap]
