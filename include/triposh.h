@@ -188,16 +188,19 @@ int tsb_assign(tsb_plan* plan, const tsb_catalog* data, const tsb_catalog* rando
  * part (0: Re of w y_L^M*, 1: Im of w y_L^M*). */
 int tsb_plan_channel(const tsb_plan* plan, int32_t c, int32_t* L, int32_t* M, int32_t* part);
 
-/* Stage timing. With profiling enabled, every later tsb_measure records HIP
- * events around each stage on the caller's stream and accumulates the elapsed
- * times. Stages (index: name): 0 weights, 1 bucket, 2 assign, 3 fwd_z, 4 fwd_y,
+/* Stage timing. `stages` is a bit mask of stage indices (0: off, -1: every
+ * stage). Every later tsb_measure records HIP events around each selected
+ * stage on the caller's stream (inside the replayed graph for the graph-held
+ * stages) and accumulates the elapsed times; each event pair adds a little
+ * time of its own, so timing one stage perturbs a measurement less than
+ * timing all. Stages (index: name): 0 weights, 1 bucket, 2 assign, 3 fwd_z, 4 fwd_y,
  * 5 fwd_x, 6 combine, 7 invF_x, 8 invF_y, 9 invF_z, 10 invG_x, 11 invG_y,
  * 12 invG_z, 13 reduce, 14 reduce_final. Each of 3..13 is one kernel launch per
  * measurement (13: one per block of 4096 outputs; when the last F transform
  * runs inside the reduction, stage 9 is empty and 13 covers both). tsb_plan_stage_times writes
  * up to n entries of accumulated milliseconds and call counts (either array may
  * be NULL) and, with reset != 0, clears the accumulators. */
-int tsb_plan_set_profiling(tsb_plan* plan, int32_t enable);
+int tsb_plan_set_profiling(tsb_plan* plan, int32_t stages);
 int tsb_plan_stage_times(tsb_plan* plan, int32_t n, double* ms, int64_t* calls, int32_t reset);
 
 /* Many catalogues in one call (the batched form of eq. 41 over independent

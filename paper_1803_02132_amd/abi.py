@@ -195,8 +195,17 @@ def tsb_assign(h, data, randoms, stream, grids_out_ptr):
                                   stream, grids_out_ptr))
 
 
-def tsb_plan_set_profiling(h, enable):
-    return _check(_lib.tsb_plan_set_profiling(h, int(bool(enable))))
+def tsb_plan_set_profiling(h, stages=True):
+    """stages: True (every stage), False/None (off) or an iterable of stage names."""
+    if stages is True:
+        mask = -1
+    elif not stages:
+        mask = 0
+    else:
+        mask = 0
+        for name in stages:
+            mask |= 1 << STAGES.index(name)
+    return _check(_lib.tsb_plan_set_profiling(h, mask))
 
 
 def tsb_plan_stage_times(h, reset=False):

@@ -626,14 +626,14 @@ int tsb_plan_set_graphs(tsb_plan* plan, int32_t enable) {
   return TSB_OK;
 }
 
-int tsb_plan_set_profiling(tsb_plan* plan, int32_t enable) {
+int tsb_plan_set_profiling(tsb_plan* plan, int32_t stages) {
   if (!plan) return fail(TSB_E_ARG, "NULL argument");
   Plan& P = plan->p;
-  if (enable && !P.ev[0][0]) {
+  if (stages && !P.ev[0][0]) {
     for (int st = 0; st < kNumStages; ++st)
       for (int k = 0; k < 2; ++k) TSB_HIP(hipEventCreate(&P.ev[st][k]));
   }
-  P.prof = enable != 0;
+  P.prof = (unsigned)stages & ((1u << kNumStages) - 1u);
   return TSB_OK;
 }
 

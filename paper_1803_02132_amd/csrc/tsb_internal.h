@@ -156,7 +156,7 @@ struct Plan {
   bool use_graph = true;        // replay the fixed-shape part of a measurement as a graph
   hipGraphExec_t graph_exec = nullptr;
   int64_t graph_gen = -1;       // particle_gen the graph was captured with
-  bool graph_prof = false;      // the graph holds the stage-timing event records
+  unsigned graph_prof = 0;      // stage mask of the event records the graph holds
   uint32_t graph_stages = 0;    // stages whose events the graph records
   bool prof_graph_failed = false;   // profiling falls back to direct launches
   hipStream_t cap_stream = nullptr;   // capture stream (never executes)
@@ -178,7 +178,7 @@ struct Plan {
   int64_t g_offset = 0;         // element offset of the G grids in d_fields
 
   // stage timing (HIP events on the measurement stream)
-  bool prof = false;
+  unsigned prof = 0;            // stages bracketed by timing events (bit per stage)
   hipEvent_t ev[kNumStages][2] = {};
   bool ev_pending[kNumStages] = {};
   double stage_ms[kNumStages] = {};
@@ -195,10 +195,10 @@ inline void prof_record(hipEvent_t e, hipStream_t s) {
   else (void)hipEventRecord(e, s);
 }
 inline void prof_begin(Plan& P, int st, hipStream_t s) {
-  if (P.prof && P.ev[st][0]) prof_record(P.ev[st][0], s);
+  if (((P.prof >> st) & 1u) && P.ev[st][0]) prof_record(P.ev[st][0], s);
 }
 inline void prof_end(Plan& P, int st, hipStream_t s) {
-  if (P.prof && P.ev[st][1]) {
+  if (((P.prof >> st) & 1u) && P.ev[st][1]) {
     prof_record(P.ev[st][1], s);
     P.ev_pending[st] = true;
   }
