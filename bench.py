@@ -43,7 +43,7 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def stage_bytes(info, copies, n_particles, fused=True, esz=4):
+def stage_bytes(info, copies, n_particles, fused=True, esz=4, n_bins=None):
     """Algorithmic HBM bytes per launch of each single-kernel stage: every input
     read once and every output written once in the stated layout (particle
     records: 12 B of position plus 4 B per channel)."""
@@ -52,7 +52,7 @@ def stage_bytes(info, copies, n_particles, fused=True, esz=4):
     PG, PF = 2 * info.r_g + 1, 2 * info.r_f + 1
     ng = info.n_grids
     nbc = copies * ng
-    nf = info.n_fslots * WORKLOAD["n_bins"]
+    nf = info.n_fslots * (WORKLOAD["n_bins"] if n_bins is None else n_bins)
     out = {
         "assign": nbc * N ** 3 * c + (24 + 4 * info.n_channels) * n_particles,
         "fwd_z": nbc * N ** 3 * c + nbc * N * N * PG * c,
@@ -254,15 +254,17 @@ def _pool(tsb, sizes, per_size):
     return pool
 
 
-def batch_leg(tsb, torch, pool, per_size):
+def batch_leg(tsb, torch, pool, per_size, replicas=1):
     """64 mocks of mixed grids through tsb_measure_batch, against the same
-    measurements made one by one with tsb_measure."""
-    plans = {n: tsb.Plan(**dict(WORKLOAD, n=n)) for n, _ in BATCH_CLASSES}
+    measurements made one by one with tsb_measure. Each grid size has
+    `replicas` plans (workspaces) that take its items in turn, so that mocks
+    of one size also run concurrently."""
+    plans = {n: [tsb.Plan(**dict(WORKLOAD, n=n)) for _ in range(replicas)] for n, _ in BATCH_CLASSES}
     items = []
     for n, seeds in BATCH_CLASSES:
-        for s in seeds:
-            items.append((n, pool[n][s % per_size][2]))
-    ps = [plans[n] for n, _ in items]
+        for k, s in enumerate(seeds):
+            items.append((plans[n][k % replicas], pool[n][s % per_size][2]))
+    ps = [p for p, _ in items]
     ds = [d for _, d in items]
     tsb.measure_batch(ps, ds)                    # warm-up: workspaces, graphs
     for p, d in zip(ps, ds):
@@ -276,9 +278,10 @@ def batch_leg(tsb, torch, pool, per_size):
     for p, d in zip(ps, ds):
         p.measure(d)
     t_plain = time.perf_counter() - t0
-    for p in plans.values():
-        p.close()
-    return {"mocks": len(items), "mix": "24 x 128^3, 24 x 192^3, 16 x 256^3",
+    for reps in plans.values():
+        for p in reps:
+            p.close()
+    return {"mocks": len(items), "mix": "24 x 128^3, 24 x 192^3, 16 x 256^3", "plans_per_size": replicas,
             "distinct_catalogues": sum(len(v) for v in pool.values()),
             "batched_mocks_per_s": round(len(items) / t_batch, 2),
             "plain_mocks_per_s": round(len(items) / t_plain, 2),
@@ -375,11 +378,15 @@ def main():
                     help="write the F fields to HBM and reduce in a separate pass (diagnostic)")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched 64-mock leg")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving leg")
-    ap.add_argument("--pool", type=int, default=2, help="distinct catalogues per grid size in those legs")
+    ap.add_argument("--pool", type=int, default=2, help="distinct catalogues per grid size in the batched leg")
+    ap.add_argument("--batch-replicas", type=int, default=1, help="plans per grid size in the batched leg")
     ap.add_argument("--serve-requests", type=int, default=256)
     ap.add_argument("--serve-rate", type=float, default=4.0)
     ap.add_argument("--serve-slots", type=int, default=8)
     ap.add_argument("--serve-budget-gb", type=float, default=160.0)
+    ap.add_argument("--workload", choices=["box256", "box128", "survey256"], default="box256",
+                    help="box256: the throughput mock (default, the reported metric); box128 and survey256: "
+                         "the 128^3 box and the 256^3 survey-window configurations, for their own timings")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a device copy of known size (calibrates HBM byte counters)")
     ap.add_argument("--ingest-pmc", nargs=3, metavar=("FETCH_CSV", "WRITE_CSV", "COMMAND"),
@@ -405,12 +412,34 @@ def main():
     torch.cuda.set_device(0)
     seeds = SEEDS[:max(1, args.mocks)]
     cats, devs = [], []
-    for s in seeds:
-        spec, cat = workload("box256", seed=s)
+    req, rands = dict(WORKLOAD), None
+    if args.workload == "box256":
+        for s in seeds:
+            spec, cat = workload("box256", seed=s)
+            cats.append(cat)
+            devs.append(tsb.catalog_to_device(cat))
+            log(f"mock seed {s}: {len(cat['pos'])} particles")
+    else:
+        from mocks.lognormal import WORKLOADS, survey_workload
+        w = WORKLOADS[args.workload]
+        req = dict(n=w["n"], box_len=w["box_len"], n_bins=w["n_bins"], dk=w["dk"], k_min=w["k_min"],
+                   multipoles=w["multipoles"], assign_p=w["assign_p"], interlace=w["interlace"], los=w["los"],
+                   observer=w["observer"], box_mode=True, precision=w["precision"], pair_mode="paper")
+        seeds = seeds[:1]
+        if args.workload == "survey256":
+            spec, cat, rcat = survey_workload("survey256", seed=3)
+            req.update(box_mode=False, P0=w["P0"])
+            rands = [tsb.catalog_to_device(rcat)]
+            log(f"survey: {len(cat['pos'])} galaxies, {len(rcat['pos'])} randoms")
+        else:
+            spec, cat = workload(args.workload, seed=seeds[0])
         cats.append(cat)
         devs.append(tsb.catalog_to_device(cat))
-        log(f"mock seed {s}: {len(cat['pos'])} particles")
-    plan = tsb.Plan(**dict(WORKLOAD, unfused=args.unfused))
+    plan = tsb.Plan(**dict(req, unfused=args.unfused))
+
+    def step(i):
+        k = i % len(devs)
+        plan.measure(devs[k], None if rands is None else rands[k])
     info = plan.info
     log(f"plan: N={info.n} M={info.m} r_f={info.r_f} r_g={info.r_g} outputs={info.n_outputs} "
         f"workspace={info.workspace_bytes / 1e9:.2f} GB")
@@ -421,26 +450,28 @@ def main():
     # region: the stage table, and which single-kernel stage dominates.
     tsb.abi.tsb_plan_set_profiling(plan.handle, True)
     for i in range(args.warmup):
-        plan.measure(devs[i % len(devs)])
+        step(i)
     tsb.abi.tsb_plan_stage_times(plan.handle, reset=True)
     for i in range(max(len(devs), 4)):
-        plan.measure(devs[i % len(devs)])
+        step(i)
     times = tsb.abi.tsb_plan_stage_times(plan.handle, reset=True)
     n_mean = float(np.mean([len(c["pos"]) for c in cats]))
+    if rands is not None:
+        n_mean += float(rands[0]["x"].numel())
     fused = times["invF_z"][1] == 0
-    bytes_alg = stage_bytes(info, 2, n_mean, fused=fused)
+    bytes_alg = stage_bytes(info, 1 + int(bool(req["interlace"])), n_mean, fused=fused, n_bins=req["n_bins"])
     per_launch = {k: (ms / calls if calls else 0.0) for k, (ms, calls) in times.items()}
     log("stage mean ms per launch: " + ", ".join(f"{k}={v:.3f}" for k, v in per_launch.items()))
     dom = max((k for k in bytes_alg), key=lambda k: times[k][0])
     # the timed region keeps events around the dominant stage only (each
     # event pair adds a little time to a measurement)
     tsb.abi.tsb_plan_set_profiling(plan.handle, [dom])
-    plan.measure(devs[0])                        # the graph with the new event set
+    step(0)                                      # the graph with the new event set
     tsb.abi.tsb_plan_stage_times(plan.handle, reset=True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for i in range(args.steps):
-        plan.measure(devs[i % len(devs)])
+        step(i)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     elapsed = t1 - t0
@@ -454,14 +485,26 @@ def main():
     roof = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
             "bytes_per_launch": int(bytes_alg[dom]), "mean_launch_ms": round(dom_launch_ms, 4)}
+    mult = "+".join("B_" + "".join(map(str, m)) for m in req["multipoles"])
+    if args.workload == "box256":
+        metric = "mocks/sec for B_000+B_202 all k-bin pairs at 256^3"
+        desc = ("256^3 box, L=1000 Mpc/h, TSC+interlacing, local LOS from an observer 1500 Mpc/h "
+                "below the centre, 20 shells dk=0.01 h/Mpc, B_000 (210 pairs) + B_202 (400 pairs), "
+                "seeded lognormal+Kaiser mocks, N_p log-uniform in [3e5, 3e6]")
+    elif args.workload == "box128":
+        metric = f"mocks/sec for {mult} all k-bin pairs at 128^3"
+        desc = ("128^3 box, L=1000 Mpc/h, 500k particles, TSC+interlacing, local LOS from an observer 1500 Mpc/h "
+                "below the centre, 20 shells dk=0.01 h/Mpc, seeded lognormal+Kaiser mock")
+    else:
+        metric = f"mocks/sec for {mult} all k-bin pairs, 256^3 survey window"
+        desc = ("256^3 grid, L=2000 Mpc/h, 2M galaxies in the half shell 500-1000 Mpc/h about the observer, "
+                "20M randoms, FKP P0=1e4, TSC+interlacing, 25 shells dk=0.008 h/Mpc, seeded lognormal+Kaiser mock")
     out = {
-        "metric": "mocks/sec for B_000+B_202 all k-bin pairs at 256^3",
+        "metric": metric,
         "value": round(value, 3), "unit": "mocks/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": round(1e3 * elapsed / args.steps, 3), "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f32", "data": "synthetic",
-        "config": {"workload": ("256^3 box, L=1000 Mpc/h, TSC+interlacing, local LOS from an observer 1500 Mpc/h "
-                                "below the centre, 20 shells dk=0.01 h/Mpc, B_000 (210 pairs) + B_202 (400 pairs), "
-                                "seeded lognormal+Kaiser mocks, N_p log-uniform in [3e5, 3e6]"),
+        "config": {"workload": desc,
                    "seeds": seeds, "n_particles_mean": int(n_mean), "reduction_grid": info.m,
                    "fused_reduction": bool(fused)},
         "roofline": roof,
@@ -471,7 +514,7 @@ def main():
     if not args.no_batch:
         pool = _pool(tsb, [(n, seeds) for n, seeds in BATCH_CLASSES], args.pool)
         log("batched leg ...")
-        out["batched"] = batch_leg(tsb, torch, pool, args.pool)
+        out["batched"] = batch_leg(tsb, torch, pool, args.pool, args.batch_replicas)
         log(f"batched: {out['batched']}")
         del pool
     if not args.no_serve:
@@ -481,7 +524,7 @@ def main():
                                    args.serve_budget_gb)
         log(f"serving: {out['serving']}")
         del big
-    if not args.no_cpu_baseline:
+    if not args.no_cpu_baseline and args.workload == "box256":
         log("timing the oracle on the host ...")
         out["cpu_baseline"] = cpu_baseline(cats[0])
     else:

@@ -347,3 +347,34 @@ def test_box_normalisation():
     _, info = est.assign_channels(plan, cat)
     n = len(cat["pos"])
     assert info["I"] == pytest.approx(n ** 3 / plan.box_len ** 6, rel=1e-14)
+
+
+def _node_lattice(n, box, origin=(0.0, 0.0, 0.0)):
+    """One unit-weight particle on every grid node (float32 positions that are
+    exactly the nodes: box / n is a dyadic fraction here)."""
+    j = np.arange(n, dtype=np.float64) * (box / n)
+    X, Y, Z = np.meshgrid(j + origin[0], j + origin[1], j + origin[2], indexing="ij")
+    pos = np.stack([X.ravel(), Y.ravel(), Z.ravel()], axis=1).astype(np.float32)
+    assert np.array_equal(pos.astype(np.float64), np.stack([X.ravel(), Y.ravel(), Z.ravel()], axis=1))
+    return {"pos": pos, "w": None, "nbar": None}
+
+
+def test_box_mean_term_cancels_a_node_lattice():
+    # Reading R7 (box mode subtracts (sum w / N^3) y_L^M*(x^_node) at every
+    # node): NGP particles sitting on the nodes give D_L^M(node) = y_L^M*(x^_node)
+    # exactly, and the mean is one particle per cell, so every channel, the
+    # y-weighted ones of the local LOS included, vanishes before any transform,
+    # and with it every multipole. A wrong node position, sign or conjugation
+    # in the term leaves the L > 0 channels nonzero.
+    plan = small_plan(assign_p=1, interlace=False)
+    cat = _node_lattice(plan.n, plan.box_len)
+    grids, _ = est.assign_channels(plan, cat)
+    for (L, M), per in grids.items():
+        assert np.max(np.abs(per[0])) == 0.0, (L, M)
+    res = est.measure(plan, cat)
+    assert np.all(res["B"] == 0.0)
+    # the same lattice one quarter cell off the nodes no longer cancels
+    off = {"pos": (cat["pos"] + np.float32(0.25 * plan.box_len / plan.n)).astype(np.float32), "w": None,
+           "nbar": None}
+    grids_off, _ = est.assign_channels(plan, off)
+    assert max(np.max(np.abs(per[0])) for (L, M), per in grids_off.items() if L > 0) > 1e-3
