@@ -47,7 +47,8 @@ typedef float floatx16 __attribute__((ext_vector_type(16)));
 // MF: the per-line contraction C_q(b1, b2) += sum_x Q_q(x; b1) f2_q(x; b2) runs on
 // the matrix cores (FP32 32x32x2 MFMA; shells padded to 32) with one (q, cell
 // range) unit per wavefront, and the line sums go to FP64 accumulators.
-template <typename T, int N1, int N2, bool MF>
+// UPW: matrix-core units per wavefront (two when a plan needs more than four).
+template <typename T, int N1, int N2, bool MF, int UPW>
 __global__ void __launch_bounds__(kBlock) fz_reduce_kernel(FusedArgs<T> a) {
   typedef typename cplx<T>::type T2;
   constexpr int M = N1 * N2;
@@ -67,6 +68,9 @@ __global__ void __launch_bounds__(kBlock) fz_reduce_kernel(FusedArgs<T> a) {
   // this thread's outputs (the same for every line)
   int ob1[kOutPerThread], ob2[kOutPerThread], oq0[kOutPerThread], oq1[kOutPerThread];
   double acc[kOutPerThread];
+  double acc2[UPW > 1 ? 16 : 1];   // the second unit of a wavefront
+#pragma unroll
+  for (int r = 0; r < (UPW > 1 ? 16 : 1); ++r) acc2[r] = 0.0;
 #pragma unroll
   for (int r = 0; r < kOutPerThread; ++r) {
     acc[r] = 0.0;
@@ -159,21 +163,30 @@ __global__ void __launch_bounds__(kBlock) fz_reduce_kernel(FusedArgs<T> a) {
     }
     if constexpr (MF) {
       const int wave = tid >> 6, lane = tid & 63;
-      if (wave < a.nq * a.ksplit) {
-        const int q = wave / a.ksplit, sp = wave - q * a.ksplit;
-        const int b = lane & 31, kh = lane >> 5;
-        const bool live = b < a.nb;
-        const T* qr = Q + ((size_t)q * a.nb + (live ? b : 0)) * CP + kh;
-        const T* fr = F2 + ((size_t)a.tb.q_f2row[q] * a.nb + (live ? b : 0)) * CP + kh;
-        const int kl = M / a.ksplit, k0 = sp * kl;
-        floatx16 c = {};
-        for (int kk = k0; kk < k0 + kl; kk += 2) {
-          const float av = live ? (float)qr[kk] : 0.f;
-          const float bv = live ? (float)fr[kk] : 0.f;
-          c = __builtin_amdgcn_mfma_f32_32x32x2f32(av, bv, c, 0, 0, 0);
-        }
 #pragma unroll
-        for (int r = 0; r < 16; ++r) acc[r] += (double)c[r];
+      for (int uu = 0; uu < UPW; ++uu) {
+        const int unit = wave + uu * (kBlock / 64);
+        if (unit < a.nq * a.ksplit) {
+          const int q = unit / a.ksplit, sp = unit - q * a.ksplit;
+          const int b = lane & 31, kh = lane >> 5;
+          const bool live = b < a.nb;
+          const T* qr = Q + ((size_t)q * a.nb + (live ? b : 0)) * CP + kh;
+          const T* fr = F2 + ((size_t)a.tb.q_f2row[q] * a.nb + (live ? b : 0)) * CP + kh;
+          const int kl = M / a.ksplit, k0 = sp * kl;   // kl is even
+          floatx16 c = {};
+          for (int kk = k0; kk < k0 + kl; kk += 2) {
+            const float av = live ? (float)qr[kk] : 0.f;
+            const float bv = live ? (float)fr[kk] : 0.f;
+            c = __builtin_amdgcn_mfma_f32_32x32x2f32(av, bv, c, 0, 0, 0);
+          }
+          if (uu == 0) {
+#pragma unroll
+            for (int r = 0; r < 16; ++r) acc[r] += (double)c[r];
+          } else {
+#pragma unroll
+            for (int r = 0; r < (UPW > 1 ? 16 : 1); ++r) acc2[r] += (double)c[r];
+          }
+        }
       }
     } else {
       // sum over the line's cells for every output of this thread
@@ -196,11 +209,15 @@ __global__ void __launch_bounds__(kBlock) fz_reduce_kernel(FusedArgs<T> a) {
     // then each output sums its Q groups and cell ranges in a fixed order
     double* Ct = (double*)smem;   // [units][32][32]
     const int wave = tid >> 6, lane = tid & 63;
-    if (wave < a.nq * a.ksplit) {
 #pragma unroll
-      for (int r = 0; r < 16; ++r) {
-        const int i = 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3), j = lane & 31;
-        Ct[((size_t)wave * 32 + i) * 32 + j] = acc[r];
+    for (int uu = 0; uu < UPW; ++uu) {
+      const int unit = wave + uu * (kBlock / 64);
+      if (unit < a.nq * a.ksplit) {
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+          const int i = 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3), j = lane & 31;
+          Ct[((size_t)unit * 32 + i) * 32 + j] = uu == 0 ? acc[r] : acc2[UPW > 1 ? r : 0];
+        }
       }
     }
     __syncthreads();
@@ -223,19 +240,23 @@ __global__ void __launch_bounds__(kBlock) fz_reduce_kernel(FusedArgs<T> a) {
 }
 
 // ---------------------------------------------------------------------------
-// FP32 plans, all shells of a line at once: 512 threads, two barriers per line.
-//   phase 1: first-level transforms of every (slot, n1), inputs prefetched into
-//            registers while the previous line finishes;
-//   phase 2: per (shell, k2) the second-level transforms of all slot kinds,
-//            turned straight into the Q and right-factor rows of N1 cells;
-//   then the contraction on the matrix cores (units of (q, cell range) over the
-//   eight wavefronts), which overlaps the next line's loads and phase 1.
+// FP32 plans, the shells of a line in one or two groups: 512 threads, two
+// barriers per group.
+//   phase 1: first-level transforms of every (slot, n1) of the group, inputs
+//            prefetched into registers while the previous group finishes;
+//   phase 2: per (shell, k2) the second-level transforms of the slot kinds
+//            (all together when a shell has at most four, else one at a time),
+//            turned straight into the Q rows and right-factor rows of N1
+//            cells;
+//   then, once every shell of the line is done, the contraction on the matrix
+//   cores (units of (q, cell range) over the eight wavefronts), which overlaps
+//   the next line's loads and first phase.
 
 constexpr int kWBlock = 512;
 constexpr int kWOut = 8;       // outputs per thread
-constexpr int kWKinds = 4;     // slot kinds per shell held in registers
 constexpr int kWGPre = 2;      // G values per thread and line
 constexpr int kWGroups = 256;  // workgroups of the one-pass kernel
+constexpr int kWMaxQ = 8;      // Q groups
 
 // sq[i] += cf * part(row[i]) * g(c_i) for the N1 cells c_i = k2 + N2 bitrev(i)
 template <int N1, int N2>
@@ -254,21 +275,35 @@ __device__ inline void put_row(float* frow, const float2 (&row)[N1], int part) {
 }
 
 template <int N1, int N2>
+__device__ inline void put_row(float* frow, const float (&row)[N1]) {
+#pragma unroll
+  for (int i = 0; i < N1; ++i) frow[N2 * bit_reverse<N1>(i)] = row[i];
+}
+
+constexpr int kWKinds = 4;     // slot kinds per shell held in registers at once (KR mode)
+
+// KR: the slot kinds of a shell (at most kWKinds) are transformed together and
+// held in registers while the Q rows are formed one group at a time;
+// otherwise the kinds are transformed one at a time and the Q rows of up to
+// NQ groups (2, 4 or 8) are held in registers. GR: the shells of a line come
+// in more than one group.
+template <int N1, int N2, int NQ, bool KR, bool GR>
 __global__ void __launch_bounds__(kWBlock) fz_reduce_wide_kernel(FusedArgs<float> a) {
   typedef float2 T2;
   constexpr int M = N1 * N2;
   constexpr int LS = N2 * (N1 + 1) + 1;
   constexpr int CP = M + 1;
   const int64_t M3 = (int64_t)M * M * M, lines = (int64_t)M * M;
-  const int nk = a.nkinds, nb = a.nb, nsl = nb * nk;
+  const int nk = a.nkinds, nb = a.nb, nq = a.nq, bpg = GR ? a.bpg : nb;
+  const int ngrp = GR ? (nb + bpg - 1) / bpg : 1;
   extern __shared__ char smem[];
   float* Q = (float*)smem;                         // [nq][nb][CP]
-  float* F2 = Q + (size_t)a.nq * nb * CP;          // [nf2][nb][CP]
+  float* F2 = Q + (size_t)nq * nb * CP;            // [nf2][nb][CP]
   float* Gv = F2 + (size_t)a.nf2 * nb * CP;        // [ngc][CP]
-  size_t off = ((size_t)(a.nq + a.nf2) * nb * CP + (size_t)a.ngc * CP) * sizeof(float);
+  size_t off = ((size_t)(nq + a.nf2) * nb * CP + (size_t)a.ngc * CP) * sizeof(float);
   off = (off + 15) / 16 * 16;
   T2* tw = (T2*)(smem + off);                      // [M] e^{+2 pi i k / M}
-  T2* stage = tw + M;                              // [nsl][LS]
+  T2* stage = tw + M;                              // [bpg * nk][LS]
   const int tid = threadIdx.x;
   for (int k = tid; k < M; k += kWBlock) {
     T2 w = a.tw[k];
@@ -276,18 +311,19 @@ __global__ void __launch_bounds__(kWBlock) fz_reduce_wide_kernel(FusedArgs<float
     tw[k] = w;
   }
   const int wave = tid >> 6, lane = tid & 63;
-  const int nunits = a.nq * a.ksplit;
+  const int nunits = nq * a.ksplit;
   double acc[16];
 #pragma unroll
   for (int r = 0; r < 16; ++r) acc[r] = 0.0;
-  // phase-1 task of this thread (one per thread) and its prefetched inputs
-  const bool has_task = tid < nsl * N1;
+  // phase-1 task of this thread in a group (slot sl of the group, n1) and its
+  // prefetched inputs
   const int sl = tid / N1, n1 = tid - (tid / N1) * N1;
   T2 pv[N2];
   float gpre[kWGPre];
-  auto prefetch = [&](int64_t line) {
-    if (has_task) {
-      const T2* src = a.u2 + ((int64_t)sl * M * M + line) * a.PFs;
+  auto group_slots = [&](int g) { return min(bpg, nb - g * bpg) * nk; };
+  auto prefetch = [&](int64_t line, int g) {
+    if (sl < group_slots(g)) {
+      const T2* src = a.u2 + ((int64_t)(g * bpg * nk + sl) * M * M + line) * a.PFs;
 #pragma unroll
       for (int n2 = 0; n2 < N2; ++n2) {
         int e = n1 + N1 * n2 + a.RF;
@@ -299,19 +335,21 @@ __global__ void __launch_bounds__(kWBlock) fz_reduce_wide_kernel(FusedArgs<float
         pv[n2] = x;
       }
     }
+    if (g == 0) {
 #pragma unroll
-    for (int j = 0; j < kWGPre; ++j) {
-      const int idx = tid + j * kWBlock;
-      gpre[j] = 0.f;
-      if (idx < a.ngc * M) {
-        const int f = idx / M, c = idx - f * M;
-        const T2 v = a.gfields[(int64_t)a.tb.g_slot[f] * M3 + line * M + c];
-        gpre[j] = a.tb.g_part[f] ? v.y : v.x;
+      for (int j = 0; j < kWGPre; ++j) {
+        const int idx = tid + j * kWBlock;
+        gpre[j] = 0.f;
+        if (idx < a.ngc * M) {
+          const int f = idx / M, c = idx - f * M;
+          const T2 v = a.gfields[(int64_t)a.tb.g_slot[f] * M3 + line * M + c];
+          gpre[j] = a.tb.g_part[f] ? v.y : v.x;
+        }
       }
     }
   };
   int64_t line = blockIdx.x;
-  if (line < lines) prefetch(line);
+  if (line < lines) prefetch(line, 0);
   __syncthreads();   // twiddles
   for (; line < lines; line += gridDim.x) {
 #pragma unroll
@@ -322,69 +360,106 @@ __global__ void __launch_bounds__(kWBlock) fz_reduce_wide_kernel(FusedArgs<float
         Gv[(size_t)f * CP + c] = gpre[j];
       }
     }
-    if (has_task) {
-      reg_fft<float, T2, N2>(pv, 1);
-      T2* st = stage + (size_t)sl * LS;
+    for (int g = 0; g < ngrp; ++g) {
+      const int b0 = g * bpg, nbg = min(bpg, nb - b0);
+      if (sl < nbg * nk) {
+        reg_fft<float, T2, N2>(pv, 1);
+        T2* st = stage + (size_t)sl * LS;
 #pragma unroll
-      for (int i = 0; i < N2; ++i) {
-        const int k2 = bit_reverse<N2>(i);
-        const T2 w = tw[(n1 * k2) % M];
-        T2 o;
-        o.x = pv[i].x * w.x - pv[i].y * w.y;
-        o.y = pv[i].x * w.y + pv[i].y * w.x;
-        st[k2 * (N1 + 1) + n1] = o;
-      }
-    }
-    __syncthreads();
-    if (line + gridDim.x < lines) prefetch(line + gridDim.x);
-    for (int task = tid; task < nb * N2; task += kWBlock) {
-      const int b = task / N2, k2 = task - b * N2;
-      T2 u[kWKinds][N1];
-#pragma unroll
-      for (int k = 0; k < kWKinds; ++k) {
-        if (k < nk) {
-          const T2* st = stage + (size_t)(b * nk + k) * LS + k2 * (N1 + 1);
-#pragma unroll
-          for (int j = 0; j < N1; ++j) u[k][j] = st[j];
-          reg_fft<float, T2, N1>(u[k], 1);
-        } else {
-#pragma unroll
-          for (int j = 0; j < N1; ++j) u[k][j] = make_float2(0.f, 0.f);
+        for (int i = 0; i < N2; ++i) {
+          const int k2 = bit_reverse<N2>(i);
+          const T2 w = tw[(n1 * k2) % M];
+          T2 o;
+          o.x = pv[i].x * w.x - pv[i].y * w.y;
+          o.y = pv[i].x * w.y + pv[i].y * w.x;
+          st[k2 * (N1 + 1) + n1] = o;
         }
       }
-      // rows of the N1 cells c_i = k2 + N2 bitrev(i); slot kinds are picked by
-      // uniform branches so that every register index stays static
-      for (int q = 0; q < a.nq; ++q) {
-        float sq[N1];
+      __syncthreads();
+      if (g + 1 < ngrp) prefetch(line, g + 1);
+      else if (line + gridDim.x < lines) prefetch(line + gridDim.x, 0);
+      if constexpr (KR) {
+      for (int task = tid; task < nbg * N2; task += kWBlock) {
+        const int bl = task / N2, k2 = task - bl * N2, b = b0 + bl;
+        T2 u[kWKinds][N1];
 #pragma unroll
-        for (int i = 0; i < N1; ++i) sq[i] = 0.f;
-        for (int t = a.tb.q_t0[q]; t < a.tb.q_t1[q]; ++t) {
-          const float cf = (float)a.tb.coef[t];
-          const int part = a.tb.f1part[t];
-          const float* gr = Gv + (size_t)a.tb.g[t] * CP + k2;
-          switch (a.tb.f1kind[t]) {
-            case 0: add_term<N1, N2>(sq, u[0], part, cf, gr); break;
-            case 1: add_term<N1, N2>(sq, u[1], part, cf, gr); break;
-            case 2: add_term<N1, N2>(sq, u[2], part, cf, gr); break;
-            default: add_term<N1, N2>(sq, u[3], part, cf, gr); break;
+        for (int k = 0; k < kWKinds; ++k) {
+          if (k < nk) {
+            const T2* st = stage + (size_t)(bl * nk + k) * LS + k2 * (N1 + 1);
+#pragma unroll
+            for (int j = 0; j < N1; ++j) u[k][j] = st[j];
+            reg_fft<float, T2, N1>(u[k], 1);
+          } else {
+#pragma unroll
+            for (int j = 0; j < N1; ++j) u[k][j] = make_float2(0.f, 0.f);
           }
         }
-        float* qrow = Q + ((size_t)q * nb + b) * CP + k2;
+        // rows of the N1 cells c_i = k2 + N2 bitrev(i); slot kinds are picked by
+        // uniform branches so that every register index stays static
+        for (int q = 0; q < nq; ++q) {
+          float sq[N1];
 #pragma unroll
-        for (int i = 0; i < N1; ++i) qrow[N2 * bit_reverse<N1>(i)] = sq[i];
-      }
-      for (int r = 0; r < a.nf2; ++r) {
-        float* frow = F2 + ((size_t)r * nb + b) * CP + k2;
-        const int part = a.tb.f2_part[r];
-        switch (a.tb.f2_kind[r]) {
-          case 0: put_row<N1, N2>(frow, u[0], part); break;
-          case 1: put_row<N1, N2>(frow, u[1], part); break;
-          case 2: put_row<N1, N2>(frow, u[2], part); break;
-          default: put_row<N1, N2>(frow, u[3], part); break;
+          for (int i = 0; i < N1; ++i) sq[i] = 0.f;
+          for (int t = a.tb.q_t0[q]; t < a.tb.q_t1[q]; ++t) {
+            const float cf = (float)a.tb.coef[t];
+            const int part = a.tb.f1part[t];
+            const float* gr = Gv + (size_t)a.tb.g[t] * CP + k2;
+            switch (a.tb.f1kind[t]) {
+              case 0: add_term<N1, N2>(sq, u[0], part, cf, gr); break;
+              case 1: add_term<N1, N2>(sq, u[1], part, cf, gr); break;
+              case 2: add_term<N1, N2>(sq, u[2], part, cf, gr); break;
+              default: add_term<N1, N2>(sq, u[3], part, cf, gr); break;
+            }
+          }
+          put_row<N1, N2>(Q + ((size_t)q * nb + b) * CP + k2, sq);
+        }
+        for (int r = 0; r < a.nf2; ++r) {
+          float* frow = F2 + ((size_t)r * nb + b) * CP + k2;
+          const int part = a.tb.f2_part[r];
+          switch (a.tb.f2_kind[r]) {
+            case 0: put_row<N1, N2>(frow, u[0], part); break;
+            case 1: put_row<N1, N2>(frow, u[1], part); break;
+            case 2: put_row<N1, N2>(frow, u[2], part); break;
+            default: put_row<N1, N2>(frow, u[3], part); break;
+          }
         }
       }
+      } else {
+      for (int task = tid; task < nbg * N2; task += kWBlock) {
+        const int bl = task / N2, k2 = task - bl * N2, b = b0 + bl;
+        float sq[NQ][N1];
+#pragma unroll
+        for (int q = 0; q < NQ; ++q)
+#pragma unroll
+          for (int i = 0; i < N1; ++i) sq[q][i] = 0.f;
+        for (int k = 0; k < nk; ++k) {
+          // kind k of shell b: second-level transform of cells c_i = k2 + N2 bitrev(i)
+          T2 u[N1];
+          const T2* st = stage + (size_t)(bl * nk + k) * LS + k2 * (N1 + 1);
+#pragma unroll
+          for (int j = 0; j < N1; ++j) u[j] = st[j];
+          reg_fft<float, T2, N1>(u, 1);
+          // its terms of each Q row (uniform branches keep register indices static)
+#pragma unroll
+          for (int q = 0; q < NQ; ++q) {
+            if (q >= nq) break;
+            for (int t = a.tb.q_t0[q]; t < a.tb.q_t1[q]; ++t) {
+              if (a.tb.f1kind[t] != k) continue;
+              add_term<N1, N2>(sq[q], u, a.tb.f1part[t], (float)a.tb.coef[t], Gv + (size_t)a.tb.g[t] * CP + k2);
+            }
+          }
+          for (int r = 0; r < a.nf2; ++r)
+            if (a.tb.f2_kind[r] == k) put_row<N1, N2>(F2 + ((size_t)r * nb + b) * CP + k2, u, a.tb.f2_part[r]);
+        }
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) {
+          if (q >= nq) break;
+          put_row<N1, N2>(Q + ((size_t)q * nb + b) * CP + k2, sq[q]);
+        }
+      }
+      }
+      __syncthreads();
     }
-    __syncthreads();
     if (wave < nunits) {
       const int q = wave / a.ksplit, sp = wave - q * a.ksplit;
       const int b = lane & 31, kh = lane >> 5;
@@ -427,40 +502,50 @@ __global__ void __launch_bounds__(kWBlock) fz_reduce_wide_kernel(FusedArgs<float
   }
 }
 
-size_t wide_lds_bytes(const Plan& P) {
+// Shells per group of the one-pass kernel at the given group size.
+size_t wide_lds_bytes(const Plan& P, int bpg) {
   const int M = P.M;
   const int N2 = M >= 128 ? 16 : 8;
   const int N1 = M / N2;
   const size_t LS = (size_t)N2 * (N1 + 1) + 1;
   size_t off = ((P.qgroups.size() + P.nf2) * P.nb + P.gcomp.size()) * (size_t)(M + 1) * sizeof(float);
   off = (off + 15) / 16 * 16;
-  const size_t need = off + (size_t)M * 8 + (size_t)P.nb * P.fkinds.size() * LS * 8;
+  const size_t need = off + (size_t)M * 8 + (size_t)bpg * P.fkinds.size() * LS * 8;
   const size_t units = P.qgroups.size() * (size_t)std::max<size_t>(1, 8 / P.qgroups.size());
   const size_t tiles = units * 32 * 32 * sizeof(double);
   return need > tiles ? need : tiles;
 }
 
-// Whether the one-pass FP32 kernel applies (shape limits of its register and
-// LDS layout).
-bool wide_ok(const Plan& P) {
-  if (P.precision != TSB_FP32) return false;
-  if (!(P.M == 64 || P.M == 128)) return false;   // N1 = 8 keeps the slot kinds in registers
+// Shells per group for the one-pass FP32 kernel (the fewest groups whose
+// first-phase tasks fit the workgroup and whose LDS fits), or 0 when the
+// kernel does not apply (shape limits of its register and LDS layout).
+int wide_group(const Plan& P) {
+  if (P.precision != TSB_FP32) return 0;
+  if (!(P.M == 64 || P.M == 128)) return 0;   // N1 = 8
   const int N2 = P.M >= 128 ? 16 : 8, N1 = P.M / N2;
-  const int nq = (int)P.qgroups.size();
-  if (P.nb > 32 || nq < 1 || nq > 8 || (int)P.fkinds.size() > kWKinds) return false;
-  if (P.nb * (int)P.fkinds.size() * N1 > kWBlock) return false;
-  if ((int)P.gcomp.size() * P.M > kWGPre * kWBlock) return false;
-  if ((int)P.outs.size() > kWOut * kWBlock) return false;
-  if ((int)P.terms.size() > kFMaxTerms || P.nf2 > kFMaxComp || (int)P.gcomp.size() > kFMaxComp) return false;
-  return wide_lds_bytes(P) <= 150 * 1024;
+  const int nq = (int)P.qgroups.size(), nk = (int)P.fkinds.size();
+  if (P.nb > 32 || nq < 1 || nq > kWMaxQ || nk < 1) return 0;
+  if ((int)P.gcomp.size() * P.M > kWGPre * kWBlock) return 0;
+  if ((int)P.outs.size() > kWOut * kWBlock) return 0;
+  if ((int)P.terms.size() > kFMaxTerms || P.nf2 > kFMaxComp || (int)P.gcomp.size() > kFMaxComp) return 0;
+  for (int ng = 1; ng <= 4; ++ng) {
+    const int bpg = (P.nb + ng - 1) / ng;
+    if (bpg * nk * N1 > kWBlock) continue;
+    if (wide_lds_bytes(P, bpg) <= 150 * 1024) return bpg;
+  }
+  return 0;
 }
 
 // Matrix-core contraction (FP32 plans, up to 32 shells and 4 Q groups): cell
 // splits per Q group so that the units fill the four wavefronts.
 int fused_ksplit(const Plan& P) {
   const int nq = (int)P.qgroups.size();
-  if (P.precision != TSB_FP32 || P.nb > 32 || nq < 1 || nq > 4) return 0;
-  return nq == 1 ? 4 : (nq == 2 ? 2 : 1);
+  if (P.precision != TSB_FP32 || P.nb > 32 || nq < 1 || nq > 8 || P.M % 2 != 0) return 0;
+  // up to eight (Q group, cell range) units, two per wavefront of the
+  // 256-thread kernel; every cell range an even number of cells
+  int ks = std::max(1, 8 / nq);
+  while (ks > 1 && P.M % (2 * ks) != 0) ks /= 2;
+  return ks;
 }
 
 int fused_units(const Plan& P) { return (int)P.qgroups.size() * fused_ksplit(P); }
@@ -524,8 +609,18 @@ int fused_launch(Plan& P, hipStream_t s) {
   if (P.fused_wide) {
     a.ksplit = std::max(1, 8 / a.nq);
     if constexpr (std::is_same<T, float>::value && N1 == 8 && N1 * N2 >= 64) {
-      prof_begin(P, kStReduce, s);
-      hipLaunchKernelGGL((fz_reduce_wide_kernel<N1, N2>), dim3(P.red_wg), dim3(kWBlock), wide_lds_bytes(P), s, a);
+      const size_t wl = wide_lds_bytes(P, P.fused_bpg);
+      const bool grouped = P.fused_bpg < P.nb;
+      if (a.nkinds <= kWKinds && !grouped)
+        hipLaunchKernelGGL((fz_reduce_wide_kernel<N1, N2, 1, true, false>), dim3(P.red_wg), dim3(kWBlock), wl, s, a);
+      else if (a.nkinds <= kWKinds)
+        hipLaunchKernelGGL((fz_reduce_wide_kernel<N1, N2, 1, true, true>), dim3(P.red_wg), dim3(kWBlock), wl, s, a);
+      else if (a.nq <= 2)
+        hipLaunchKernelGGL((fz_reduce_wide_kernel<N1, N2, 2, false, true>), dim3(P.red_wg), dim3(kWBlock), wl, s, a);
+      else if (a.nq <= 4)
+        hipLaunchKernelGGL((fz_reduce_wide_kernel<N1, N2, 4, false, true>), dim3(P.red_wg), dim3(kWBlock), wl, s, a);
+      else
+        hipLaunchKernelGGL((fz_reduce_wide_kernel<N1, N2, 8, false, true>), dim3(P.red_wg), dim3(kWBlock), wl, s, a);
       prof_end(P, kStReduce, s);
       TSB_HIP(hipGetLastError());
       return TSB_OK;
@@ -533,10 +628,12 @@ int fused_launch(Plan& P, hipStream_t s) {
     return fail(TSB_E_UNSUPPORTED, "fused reduction: one-pass kernel does not cover this shape");
   }
   a.ksplit = fused_ksplit(P);
-  if (a.ksplit > 0)
-    hipLaunchKernelGGL((fz_reduce_kernel<T, N1, N2, true>), dim3(P.red_wg), dim3(kBlock), lds, s, a);
+  if (a.ksplit > 0 && a.nq * a.ksplit > kBlock / 64)
+    hipLaunchKernelGGL((fz_reduce_kernel<T, N1, N2, true, 2>), dim3(P.red_wg), dim3(kBlock), lds, s, a);
+  else if (a.ksplit > 0)
+    hipLaunchKernelGGL((fz_reduce_kernel<T, N1, N2, true, 1>), dim3(P.red_wg), dim3(kBlock), lds, s, a);
   else
-    hipLaunchKernelGGL((fz_reduce_kernel<T, N1, N2, false>), dim3(P.red_wg), dim3(kBlock), lds, s, a);
+    hipLaunchKernelGGL((fz_reduce_kernel<T, N1, N2, false, 1>), dim3(P.red_wg), dim3(kBlock), lds, s, a);
   prof_end(P, kStReduce, s);
   TSB_HIP(hipGetLastError());
   return TSB_OK;
@@ -566,11 +663,12 @@ void plan_fused(Plan& P) {
   if ((int)P.terms.size() > kFMaxTerms || (int)P.qgroups.size() > kFMaxQ || P.nf2 > kFMaxComp ||
       (int)P.gcomp.size() > kFMaxComp)
     return;
-  P.fused_wide = wide_ok(P);
+  const int wide_bpg = wide_group(P);
+  P.fused_wide = wide_bpg > 0;
   if (P.fused_wide) {
     // one workgroup of 512 threads per compute unit (its LDS fills one): 256 on MI355X
     P.fused = true;
-    P.fused_bpg = P.nb;
+    P.fused_bpg = wide_bpg;
     P.red_wg = std::min<int>(kWGroups, M * M);
     return;
   }

@@ -286,3 +286,20 @@ def test_box_mean_term_cancels_a_node_lattice(precision):
         res = np.max(np.abs(b_lat[mu][mask[mu]]))
         _say("lattice", precision, req["multipoles"][mu], res, scale)
         assert res <= 1e-6 * scale
+
+
+def test_one_pass_reduction_in_shell_groups():
+    # {000, 110, 202} carries five slot kinds per shell: the one-pass reduction
+    # transforms them one at a time, and with 14 shells on M = 64 it processes
+    # each line's shells in two groups.
+    n, box = 64, 1000.0
+    kf = 2.0 * math.pi / box
+    req = box_request(n=n, box_len=box, n_bins=14, dk=15.0 / 14.0 * kf,
+                      multipoles=[(0, 0, 0), (1, 1, 0), (2, 0, 2)], precision="f32")
+    cat = small_cat(n=n, box_len=box, n_target=60000, seed=12)
+    plan, g, o = run_both(req, cat)
+    assert plan.info.m == 64 and plan.info.n_fslots == 5
+    mask = pair_mask(req["multipoles"], req["n_bins"])
+    err = normwise_errors(g["B"], o["B"], mask)
+    _say("grouped one-pass errors", err)
+    assert np.all(err <= 1e-4)
