@@ -1375,6 +1375,8 @@ int run_assign(Plan& P, const tsb_catalog* data, const tsb_catalog* rand, hipStr
   if (nreg <= 8) return f64 ? assign_front_impl<double, 8>(P, b, ci, s) : assign_front_impl<float, 8>(P, b, ci, s);
   if (nreg <= 16)
     return f64 ? assign_front_impl<double, 16>(P, b, ci, s) : assign_front_impl<float, 16>(P, b, ci, s);
+  if (nreg <= 24)
+    return f64 ? assign_front_impl<double, 24>(P, b, ci, s) : assign_front_impl<float, 24>(P, b, ci, s);
   return f64 ? assign_front_impl<double, kMaxCh>(P, b, ci, s) : assign_front_impl<float, kMaxCh>(P, b, ci, s);
 }
 
@@ -1385,6 +1387,7 @@ int run_assign_back(Plan& P, hipStream_t s) {
   const bool f64 = P.precision == TSB_FP64;
   if (nreg <= 8) return f64 ? assign_back_impl<double, 8>(P, ci, s) : assign_back_impl<float, 8>(P, ci, s);
   if (nreg <= 16) return f64 ? assign_back_impl<double, 16>(P, ci, s) : assign_back_impl<float, 16>(P, ci, s);
+  if (nreg <= 24) return f64 ? assign_back_impl<double, 24>(P, ci, s) : assign_back_impl<float, 24>(P, ci, s);
   return f64 ? assign_back_impl<double, kMaxCh>(P, ci, s) : assign_back_impl<float, kMaxCh>(P, ci, s);
 }
 

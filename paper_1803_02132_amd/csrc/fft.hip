@@ -245,30 +245,33 @@ __global__ void __launch_bounds__(kBlock) combine_kernel(const typename cplx<T>:
                                                          const typename cplx<T>::type* yspec,
                                                          const DevScalars* scal) {
   // axis_tab: [P] 1/W_axis(n), then [P] cos(pi n/N), then [P] sin(pi n/N), n = index - R;
-  // W and the interlace phase factor over the three axes
+  // W and the interlace phase factor over the three axes. One row (grid, x, y)
+  // per half workgroup, z across its lanes; the row's x and y factors are
+  // formed once per row.
   typedef typename cplx<T>::type T2;
   const int P = 2 * R + 1;
   const double* iw = axis_tab;
   const double* pc = axis_tab + P;
   const double* ps = axis_tab + 2 * P;
   const int64_t P3 = (int64_t)P * P * P;
-  const int64_t total = (int64_t)ngrid * P3;
+  const int rows = ngrid * P * P;
   const double mean = yspec ? scal->mean_cell : 0.0;
-  for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < total; i += (int64_t)gridDim.x * kBlock) {
-    const int g = (int)(i / P3);
-    const int64_t m = i - g * P3;
-    const int ix = (int)(m / ((int64_t)P * P)), iy = (int)((m / P) % P), iz = (int)(m % P);
+  for (int row = blockIdx.x * (kBlock / 128) + (threadIdx.x >> 7); row < rows; row += gridDim.x * (kBlock / 128))
+  for (int iz = threadIdx.x & 127; iz < P; iz += 128) {
+    const int g = row / (P * P), rxy = row - g * P * P, ix = rxy / P, iy = rxy - ix * P;
+    const double czz = pc[iz], szz = ps[iz], wz = iw[iz];
+    const int64_t i = (int64_t)row * P + iz;
     const T2 v1 = t3[i];
     double re = v1.x, im = v1.y;
     if (copies == 2) {
       const T2 v2 = t3[(int64_t)ngrid * P3 + i];
       // e^{i pi (nx+ny+nz)/N} as the product of the three axis phases
       const double cxy = pc[ix] * pc[iy] - ps[ix] * ps[iy], sxy = pc[ix] * ps[iy] + ps[ix] * pc[iy];
-      const double c = cxy * pc[iz] - sxy * ps[iz], sn = cxy * ps[iz] + sxy * pc[iz];
+      const double c = cxy * czz - sxy * szz, sn = cxy * szz + sxy * czz;
       re = 0.5 * (re + c * (double)v2.x - sn * (double)v2.y);
       im = 0.5 * (im + c * (double)v2.y + sn * (double)v2.x);
     }
-    const double inv_w = iw[ix] * iw[iy] * iw[iz];
+    const double inv_w = iw[ix] * iw[iy] * wz;
     re *= inv_w;
     im *= inv_w;
     if (yspec) {
@@ -498,10 +501,10 @@ int forward_impl(Plan& P, hipStream_t s) {
     a.N = N; a.dir = -1; a.contiguous = 0;
     if ((rc = launch_pass<T>(P, kStFwdX, a, s))) return rc;
   }
-  const int64_t total = (int64_t)P.grids.size() * PG * PG * PG;
   prof_begin(P, kStCombine, s);
-  hipLaunchKernelGGL(combine_kernel<T>, dim3(grid_blocks(total)), dim3(kBlock), 0, s, (const T2*)P.d_t3,
-                     (T2*)P.d_spec, (int)P.grids.size(), P.copies, RG, P.box_mode, (const double*)P.d_axis_tab,
+  const int64_t row_pairs = ((int64_t)P.grids.size() * PG * PG + 1) / 2;   // two rows per workgroup
+  hipLaunchKernelGGL(combine_kernel<T>, dim3((int)std::min<int64_t>(row_pairs, 8192)), dim3(kBlock), 0, s,
+                     (const T2*)P.d_t3, (T2*)P.d_spec, (int)P.grids.size(), P.copies, RG, P.box_mode, (const double*)P.d_axis_tab,
                      P.yspec_ready ? (const T2*)P.d_yspec : (const T2*)nullptr, (const DevScalars*)P.d_scal);
   const int64_t pf3 = (int64_t)P.PF * P.PF * P.PF;
   hipLaunchKernelGGL(dcube_kernel<T>, dim3(grid_blocks(pf3)), dim3(kBlock), 0, s, (const T2*)P.d_spec,
