@@ -254,7 +254,7 @@ def _pool(tsb, sizes, per_size):
     return pool
 
 
-def batch_leg(tsb, torch, pool, per_size, replicas=1):
+def batch_leg(tsb, torch, pool, per_size, replicas=1, autotune=True):
     """64 mocks of mixed grids through tsb_measure_batch, against the same
     measurements made one by one with tsb_measure. Each grid size has
     `replicas` plans (workspaces) that take its items in turn, so that mocks
@@ -266,6 +266,11 @@ def batch_leg(tsb, torch, pool, per_size, replicas=1):
             items.append((plans[n][k % replicas], pool[n][s % per_size][2]))
     ps = [p for p, _ in items]
     ds = [d for _, d in items]
+    tuned = {}
+    if autotune:                                  # each plan's schedule, on one of its catalogues
+        for n, reps in plans.items():
+            for p in reps:
+                tuned[f"{n}^3"] = p.autotune(pool[n][0][2])
     tsb.measure_batch(ps, ds)                    # warm-up: workspaces, graphs
     for p, d in zip(ps, ds):
         p.measure(d)
@@ -282,6 +287,7 @@ def batch_leg(tsb, torch, pool, per_size, replicas=1):
         for p in reps:
             p.close()
     return {"mocks": len(items), "mix": "24 x 128^3, 24 x 192^3, 16 x 256^3", "plans_per_size": replicas,
+            "autotune": tuned or None,
             "distinct_catalogues": sum(len(v) for v in pool.values()),
             "batched_mocks_per_s": round(len(items) / t_batch, 2),
             "plain_mocks_per_s": round(len(items) / t_plain, 2),
@@ -380,6 +386,8 @@ def main():
     ap.add_argument("--no-serve", action="store_true", help="skip the serving leg")
     ap.add_argument("--pool", type=int, default=2, help="distinct catalogues per grid size in the batched leg")
     ap.add_argument("--batch-replicas", type=int, default=1, help="plans per grid size in the batched leg")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="keep the default launch schedules (no tsb_plan_autotune before timing)")
     ap.add_argument("--serve-requests", type=int, default=256)
     ap.add_argument("--serve-rate", type=float, default=4.0)
     ap.add_argument("--serve-slots", type=int, default=8)
@@ -445,6 +453,11 @@ def main():
         f"workspace={info.workspace_bytes / 1e9:.2f} GB")
     if args.copy_probe:
         copy_probe()
+    tune = None
+    if not args.no_autotune:
+        t0 = time.perf_counter()
+        tune = plan.autotune(devs[0], None if rands is None else rands[0])
+        log(f"autotune ({time.perf_counter() - t0:.2f} s): {tune}")
     # Every stage timed with HIP events (they ride inside the captured graph)
     # over the warm-up steps plus one pass over the mocks, outside the timed
     # region: the stage table, and which single-kernel stage dominates.
@@ -506,7 +519,7 @@ def main():
         "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": desc,
                    "seeds": seeds, "n_particles_mean": int(n_mean), "reduction_grid": info.m,
-                   "fused_reduction": bool(fused)},
+                   "fused_reduction": bool(fused), "autotune": tune},
         "roofline": roof,
         "stage_ms": {k: round(v, 4) for k, v in per_launch.items()},
     }
@@ -514,7 +527,7 @@ def main():
     if not args.no_batch:
         pool = _pool(tsb, [(n, seeds) for n, seeds in BATCH_CLASSES], args.pool)
         log("batched leg ...")
-        out["batched"] = batch_leg(tsb, torch, pool, args.pool, args.batch_replicas)
+        out["batched"] = batch_leg(tsb, torch, pool, args.pool, args.batch_replicas, not args.no_autotune)
         log(f"batched: {out['batched']}")
         del pool
     if not args.no_serve:

@@ -201,6 +201,24 @@ int tsb_plan_channel(const tsb_plan* plan, int32_t c, int32_t* L, int32_t* M, in
  * up to n entries of accumulated milliseconds and call counts (either array may
  * be NULL) and, with reset != 0, clears the accumulators. */
 int tsb_plan_set_profiling(tsb_plan* plan, int32_t stages);
+
+/* Empirical tuning of the plan's launch schedule for the batched and
+ * repeated measurements of the paper's mock campaigns (Sec. 4.4): measures
+ * `data` (and `randoms` in survey mode) repeatedly on `stream`, timing each
+ * candidate with HIP events over `reps` runs, and keeps the fastest (a
+ * candidate replaces the default only when it is at least 2% faster)
+ *   - lines per workgroup of every power-of-two FFT pass (the LDS rule, or 8,
+ *     16, 32, 64 lines, at most 64 KiB of LDS);
+ *   - the persistent grid of the assignment tile kernel (0.5 to 2 times its
+ *     occupancy-sized default).
+ * These change how work is split, not the arithmetic: results stay bitwise
+ * the same. The choices stay with the plan (the captured graph is rebuilt).
+ * choice (may be NULL) receives 16 values: lines per workgroup per stage
+ * (index as in tsb_plan_stage_times; 0 = the LDS rule), then the tile-kernel
+ * workgroups. Clears the stage-time accumulators and keeps the profiling
+ * setting. Errors as tsb_measure. */
+int tsb_plan_autotune(tsb_plan* plan, const tsb_catalog* data, const tsb_catalog* randoms, void* stream,
+                      int32_t reps, int32_t* choice);
 int tsb_plan_stage_times(tsb_plan* plan, int32_t n, double* ms, int64_t* calls, int32_t reset);
 
 /* Many catalogues in one call (the batched form of eq. 41 over independent

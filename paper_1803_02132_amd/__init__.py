@@ -98,6 +98,13 @@ class Plan:
                        out.data_ptr())
         return out
 
+    def autotune(self, data_dev, randoms_dev=None, stream=None, reps=3):
+        """tsb_plan_autotune on these catalogues; returns the chosen schedule."""
+        import torch
+        s = torch.cuda.current_stream() if stream is None else stream
+        return abi.tsb_plan_autotune(self.handle, _cat_struct(data_dev), _cat_struct(randoms_dev), s.cuda_stream,
+                                     reps)
+
     def set_graphs(self, enable):
         abi.tsb_plan_set_graphs(self.handle, enable)
 

@@ -97,6 +97,9 @@ _lib.tsb_assign.argtypes = [ctypes.c_void_p, _P(tsb_catalog), _P(tsb_catalog), c
 
 _lib.tsb_plan_set_profiling.restype = ctypes.c_int
 _lib.tsb_plan_set_profiling.argtypes = [ctypes.c_void_p, ctypes.c_int32]
+_lib.tsb_plan_autotune.restype = ctypes.c_int
+_lib.tsb_plan_autotune.argtypes = [ctypes.c_void_p, _P(tsb_catalog), _P(tsb_catalog), ctypes.c_void_p, ctypes.c_int32,
+                                   _P(ctypes.c_int32)]
 _lib.tsb_plan_stage_times.restype = ctypes.c_int
 _lib.tsb_plan_stage_times.argtypes = [ctypes.c_void_p, ctypes.c_int32, _P(ctypes.c_double), _P(ctypes.c_int64),
                                       ctypes.c_int32]
@@ -122,7 +125,7 @@ _lib.tsb_server_destroy.argtypes = [ctypes.c_void_p]
 STAGES = ["weights", "bucket", "assign", "fwd_z", "fwd_y", "fwd_x", "combine", "invF_x", "invF_y", "invF_z",
           "invG_x", "invG_y", "invG_z", "reduce", "reduce_final"]
 
-EXPORTED = ["tsb_plan_set_profiling", "tsb_plan_stage_times", "tsb_plan_create", "tsb_plan_destroy",
+EXPORTED = ["tsb_plan_set_profiling", "tsb_plan_stage_times", "tsb_plan_autotune", "tsb_plan_create", "tsb_plan_destroy",
             "tsb_plan_query", "tsb_plan_get_info", "tsb_plan_nmode", "tsb_measure", "tsb_assign",
             "tsb_plan_channel", "tsb_last_error", "tsb_measure_batch", "tsb_plan_set_graphs",
             "tsb_server_create", "tsb_server_submit", "tsb_server_poll", "tsb_server_wait",
@@ -206,6 +209,16 @@ def tsb_plan_set_profiling(h, stages=True):
         for name in stages:
             mask |= 1 << STAGES.index(name)
     return _check(_lib.tsb_plan_set_profiling(h, mask))
+
+
+def tsb_plan_autotune(h, data, randoms, stream, reps=3):
+    """Tune the plan's launch schedule; returns {stage: lines per workgroup
+    (0 = LDS rule)} for the tuned FFT stages and 'tile_wgs'."""
+    choice = (ctypes.c_int32 * 16)()
+    _check(_lib.tsb_plan_autotune(h, data, randoms, ctypes.c_void_p(stream), int(reps), choice))
+    out = {name: int(choice[i]) for i, name in enumerate(STAGES) if choice[i]}
+    out["tile_wgs"] = int(choice[len(STAGES)])
+    return out
 
 
 def tsb_plan_stage_times(h, reset=False):

@@ -279,7 +279,7 @@ int run_back(Plan& P, hipStream_t s) {
 // of the graph, so stage times cover the replayed launches).
 int launch_back(Plan& P, hipStream_t s) {
   if (!P.use_graph || (P.prof && P.prof_graph_failed)) return run_back(P, s);
-  if (!P.graph_exec || P.graph_gen != P.particle_gen || P.graph_prof != P.prof) {
+  if (!P.graph_exec || P.graph_gen != P.particle_gen || P.graph_prof != P.prof || P.graph_tune != P.tune_gen) {
     if (P.graph_exec) {
       TSB_HIP(hipGraphExecDestroy(P.graph_exec));
       P.graph_exec = nullptr;
@@ -316,6 +316,7 @@ int launch_back(Plan& P, hipStream_t s) {
     P.graph_exec = ex;
     P.graph_gen = P.particle_gen;
     P.graph_prof = P.prof;
+    P.graph_tune = P.tune_gen;
   }
   TSB_HIP(hipGraphLaunch(P.graph_exec, s));
   for (int st = 0; st < kNumStages; ++st)
@@ -634,6 +635,107 @@ int tsb_plan_set_profiling(tsb_plan* plan, int32_t stages) {
       for (int k = 0; k < 2; ++k) TSB_HIP(hipEventCreate(&P.ev[st][k]));
   }
   P.prof = (unsigned)stages & ((1u << kNumStages) - 1u);
+  return TSB_OK;
+}
+
+// A tuned setting replaces the current best only when it is at least 2% faster
+// (timing noise otherwise flips choices between equivalent schedules).
+static constexpr double kTuneGain = 0.98;
+
+int tsb_plan_autotune(tsb_plan* plan, const tsb_catalog* data, const tsb_catalog* randoms, void* stream,
+                      int32_t reps, int32_t* choice) {
+  if (!plan || !data || reps < 1) return fail(TSB_E_ARG, "bad argument");
+  Plan& P = plan->p;
+  hipStream_t s = (hipStream_t)stream;
+  int rc;
+  if ((rc = set_device(P))) return rc;
+  if ((rc = ensure_result_slots(P, 1))) return rc;
+  if (!P.ev[0][0]) {
+    for (int st = 0; st < kNumStages; ++st)
+      for (int k = 0; k < 2; ++k) TSB_HIP(hipEventCreate(&P.ev[st][k]));
+  }
+  std::vector<double> B((size_t)P.mult.size() * P.nb * P.nb);
+  const unsigned prof_saved = P.prof;
+  auto clear_times = [&]() {
+    for (int st = 0; st < kNumStages; ++st) {
+      P.stage_ms[st] = 0.0;
+      P.stage_calls[st] = 0;
+    }
+  };
+  auto run = [&](unsigned mask) -> int {   // one measurement with events on the stages of mask
+    P.prof = mask;
+    int r = enqueue_measure(P, data, randoms, s, 0);
+    if (r) return r;
+    TSB_HIP(hipStreamSynchronize(s));
+    collect_stage_times(P);
+    return finish_measure(P, 0, B.data(), nullptr, nullptr);
+  };
+  auto stage_time = [&](int st, double* ms) -> int {   // mean over reps (after one untimed run)
+    int r = run(1u << st);
+    if (r) return r;
+    clear_times();
+    for (int i = 0; i < reps; ++i)
+      if ((r = run(1u << st))) return r;
+    *ms = P.stage_calls[st] ? P.stage_ms[st] / (double)P.stage_calls[st] : 0.0;
+    return TSB_OK;
+  };
+  // which stages launch anything, and the tile kernel's default grid
+  clear_times();
+  if ((rc = run((1u << kNumStages) - 1u))) {
+    P.prof = prof_saved;
+    return rc;
+  }
+  int64_t calls[kNumStages];
+  for (int st = 0; st < kNumStages; ++st) calls[st] = P.stage_calls[st];
+  // FFT passes of power-of-two length: lines per workgroup
+  static const int kFftStages[] = {kStFwdZ, kStFwdY, kStFwdX, kStInvFX, kStInvFY, kStInvFZ,
+                                   kStInvGX, kStInvGY, kStInvGZ};
+  static const int kLpw[] = {0, 8, 16, 32, 64};
+  for (int st : kFftStages) {
+    const int len = st <= kStFwdX ? P.N : P.M;
+    if (!calls[st] || (len & (len - 1)) != 0) continue;
+    double best = 0.0;
+    int best_lpw = 0;
+    for (int c : kLpw) {
+      P.lpw_tune[st] = c;
+      ++P.tune_gen;
+      double ms = 0.0;
+      if ((rc = stage_time(st, &ms))) break;
+      if (c == 0 || ms < kTuneGain * best) {   // a candidate must beat the default clearly
+        best = ms;
+        best_lpw = c;
+      }
+    }
+    P.lpw_tune[st] = best_lpw;
+    ++P.tune_gen;
+    if (rc) break;
+  }
+  // persistent grid of the assignment tile kernel, around its occupancy-sized default
+  if (!rc && P.tile_wgs > 0) {
+    const int base = P.tile_wgs;
+    static const double kScale[] = {1.0, 0.5, 0.75, 1.5, 2.0};
+    double best = 0.0;
+    int best_wgs = base;
+    for (double f : kScale) {
+      P.tile_wgs = std::max(1, (int)(base * f));
+      ++P.tune_gen;
+      double ms = 0.0;
+      if ((rc = stage_time(kStAssign, &ms))) break;
+      if (f == 1.0 || ms < kTuneGain * best) {
+        best = ms;
+        best_wgs = P.tile_wgs;
+      }
+    }
+    P.tile_wgs = best_wgs;
+    ++P.tune_gen;
+  }
+  P.prof = prof_saved;
+  clear_times();
+  if (rc) return rc;
+  if (choice) {
+    for (int st = 0; st < kNumStages; ++st) choice[st] = P.lpw_tune[st];
+    choice[kNumStages] = P.tile_wgs;
+  }
   return TSB_OK;
 }
 

@@ -404,11 +404,17 @@ int pick_lpw(int N, int esz) {
 }
 
 template <typename T, int N1, int N2>
-int launch_fft4(PassArgs<T>& a, hipStream_t s) {
+int launch_fft4(PassArgs<T>& a, hipStream_t s, int lpw_req) {
   typedef typename cplx<T>::type T2;
   constexpr int LS = N2 * (N1 + 1) + 1;
+  // lines per workgroup: the largest power of two up to 64 whose LDS stays
+  // within 40 KiB, or a tuned value (at most 64 KiB of LDS)
   int lpw = 64;
   while (lpw > 1 && (int64_t)lpw * LS * (int64_t)sizeof(T2) > 40 * 1024) lpw /= 2;
+  if (lpw_req > 0) {
+    lpw = lpw_req;
+    while (lpw > 1 && (int64_t)lpw * LS * (int64_t)sizeof(T2) > 64 * 1024) lpw /= 2;
+  }
   a.lpw = lpw;
   const int64_t nbb = (a.dB + a.lpw - 1) / a.lpw;
   const int64_t blocks = (int64_t)a.nbatch * a.dA * nbb;
@@ -424,14 +430,15 @@ int launch_pass(Plan& P, int stage, PassArgs<T>& a, hipStream_t s) {
   if (a.nbatch <= 0 || a.dA <= 0 || a.dB <= 0) return TSB_OK;
   prof_begin(P, stage, s);
   int rc = TSB_OK;
+  const int req = P.lpw_tune[stage];
   switch (a.N) {
-    case 16: rc = launch_fft4<T, 4, 4>(a, s); break;
-    case 32: rc = launch_fft4<T, 4, 8>(a, s); break;
-    case 64: rc = launch_fft4<T, 8, 8>(a, s); break;
-    case 128: rc = launch_fft4<T, 8, 16>(a, s); break;
-    case 256: rc = launch_fft4<T, 16, 16>(a, s); break;
-    case 512: rc = launch_fft4<T, 16, 32>(a, s); break;
-    case 1024: rc = launch_fft4<T, 32, 32>(a, s); break;
+    case 16: rc = launch_fft4<T, 4, 4>(a, s, req); break;
+    case 32: rc = launch_fft4<T, 4, 8>(a, s, req); break;
+    case 64: rc = launch_fft4<T, 8, 8>(a, s, req); break;
+    case 128: rc = launch_fft4<T, 8, 16>(a, s, req); break;
+    case 256: rc = launch_fft4<T, 16, 16>(a, s, req); break;
+    case 512: rc = launch_fft4<T, 16, 32>(a, s, req); break;
+    case 1024: rc = launch_fft4<T, 32, 32>(a, s, req); break;
     default: {
       // lengths with a factor 3: LDS Stockham radix 4/2/3
       a.lpw = pick_lpw(a.N, sizeof(T));

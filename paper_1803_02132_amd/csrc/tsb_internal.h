@@ -157,6 +157,9 @@ struct Plan {
   hipGraphExec_t graph_exec = nullptr;
   int64_t graph_gen = -1;       // particle_gen the graph was captured with
   unsigned graph_prof = 0;      // stage mask of the event records the graph holds
+  int tune_gen = 0;             // bumped whenever a launch parameter changes
+  int graph_tune = 0;           // the tune_gen the graph was captured with
+  int lpw_tune[kNumStages] = {};   // FFT lines per workgroup per stage (0: the LDS rule)
   uint32_t graph_stages = 0;    // stages whose events the graph records
   bool prof_graph_failed = false;   // profiling falls back to direct launches
   hipStream_t cap_stream = nullptr;   // capture stream (never executes)

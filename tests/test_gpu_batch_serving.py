@@ -108,3 +108,18 @@ def test_server_rejects_what_cannot_fit():
         assert e.value.code == tsb.abi.TSB_E_NOMEM
     finally:
         srv.close()
+
+
+def test_autotune_keeps_results_bitwise():
+    # the tuned launch schedule changes how work is split, not the arithmetic
+    req = box_request(n=64, n_bins=6)
+    dev = tsb.catalog_to_device(_cat(64, 41, 40000))
+    plan_a, plan_b = tsb.Plan(**req), tsb.Plan(**req)
+    ref = plan_a.measure(dev)["B"]
+    choice = plan_b.autotune(dev, reps=2)
+    _say("autotune choice", choice)
+    assert choice["tile_wgs"] >= 1
+    assert all(v in (8, 16, 32, 64) for k, v in choice.items() if k != "tile_wgs")   # 0 (the rule) is not listed
+    assert _same(plan_b.measure(dev)["B"], ref)
+    plan_b.set_graphs(False)
+    assert _same(plan_b.measure(dev)["B"], ref)
