@@ -21,6 +21,6 @@ silent or ambiguous are listed (R1..R11) in ``estimator``'s header.
 
 Parity status per function is stated in each module header; every function is
 pinned by a ``-m "not gpu"`` test against closed forms, library routines,
-brute force or values printed in the paper, except the conventions listed
-there as "parity unpinned".
+brute force or values printed in the paper; the conventions listed there are
+pinned by exact properties they imply.
 """

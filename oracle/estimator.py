@@ -61,9 +61,11 @@ Readings where the paper is silent or ambiguous (listed again in the design doc):
   R11 The multipole is the real part of eq. 41; its imaginary part vanishes for
       l1 + l2 + L even and is returned for checking.
 
-Parity unpinned beyond oracle-vs-HIP agreement: the conventions R5 (interlace
-phase), R7 (box-mode node term) and R8 (value of I) -- each is a definition,
-not a derivable number.
+The conventions R5 (interlace phase), R7 (box-mode node term) and R8 (value
+of I) are definitions, each pinned by a property it implies: R5 by the exact
+covariance of the interlaced field under a half-cell shift of the particles
+along (1,1,1), R7 by the exact cancellation of every channel for particles on
+the nodes, R8 by the closed form n-bar^3 V for a uniform density.
 """
 from dataclasses import dataclass, field
 from typing import Optional, Sequence

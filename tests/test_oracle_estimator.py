@@ -378,3 +378,45 @@ def test_box_mean_term_cancels_a_node_lattice():
            "nbar": None}
     grids_off, _ = est.assign_channels(plan, off)
     assert max(np.max(np.abs(per[0])) for (L, M), per in grids_off.items() if L > 0) > 1e-3
+
+
+def test_interlacing_phase_covariance_under_half_cell_shift():
+    # Reading R5 (grid 2 takes the particles shifted by +H/2 per axis; the
+    # combination is (D1 + e^{i pi (nx+ny+nz)/N} D2)/2): shifting every particle
+    # by H/2 along (1,1,1) turns grid 1 into grid 2 and grid 2 into grid 1
+    # shifted by a whole cell, so the combined field picks up exactly
+    # e^{-i pi (nx+ny+nz)/N}. A wrong sign or direction of the phase breaks it.
+    plan = small_plan(los="global", multipoles=[(0, 0, 0)], assign_p=3, interlace=True)
+    n, box = plan.n, plan.box_len
+    h = box / n
+    rng = np.random.default_rng(21)
+    ticks = rng.integers(0, 1024 * n, size=(2000, 3))          # positions on a 1/1024-cell lattice
+    pos = (ticks * (h / 1024)).astype(np.float32)
+    shifted = (((ticks + 512) % (1024 * n)) * (h / 1024)).astype(np.float32)
+    w = (0.5 + rng.random(2000)).astype(np.float32)
+    s1 = est.spectra(plan, est.assign_channels(plan, {"pos": pos, "w": w, "nbar": None})[0])[(0, 0)]
+    s2 = est.spectra(plan, est.assign_channels(plan, {"pos": shifted, "w": w, "nbar": None})[0])[(0, 0)]
+    nx, ny, nz = est.mode_vectors(n)
+    keep = (np.abs(nx) != n // 2) & (np.abs(ny) != n // 2) & (np.abs(nz) != n // 2)
+    keep[0, 0, 0] = False
+    expect = np.exp(-1j * np.pi * (nx + ny + nz) / n) * s1
+    assert np.max(np.abs(s2 - expect)[keep]) <= 1e-12 * np.max(np.abs(s1))
+    # the opposite phase convention does not satisfy it
+    wrong = np.exp(1j * np.pi * (nx + ny + nz) / n) * s1
+    assert np.max(np.abs(s2 - wrong)[keep]) > 1e-3 * np.max(np.abs(s1))
+
+
+def test_survey_normalisation_of_a_uniform_density():
+    # Reading R8 (survey I = v_c sum_j (alpha R_j / v_c)^3, R the gridded
+    # randoms): for randoms that fill every node once with weight w (NGP), the
+    # mean density n-bar = alpha w / v_c is uniform and eq. 37 gives
+    # I = integral of n-bar^3 over the box = n-bar^3 V.
+    plan = small_plan(assign_p=1, interlace=False, box_mode=False, multipoles=[(0, 0, 0)], los="global")
+    rand = _node_lattice(plan.n, plan.box_len)
+    rand["w"] = np.full(len(rand["pos"]), 0.75, dtype=np.float32)
+    cat = small_cat(seed=23)
+    _, info = est.assign_channels(plan, cat, rand)
+    vc = plan.box_len ** 3 / plan.n ** 3
+    nbar = info["alpha"] * 0.75 / vc
+    assert info["alpha"] == pytest.approx(len(cat["pos"]) / (0.75 * len(rand["pos"])), rel=1e-13)
+    assert info["I"] == pytest.approx(nbar ** 3 * plan.box_len ** 3, rel=1e-12)
