@@ -646,6 +646,7 @@ __global__ void __launch_bounds__(kTileBlock, (sizeof(T) == 4 && NCH <= 8) ? 4 :
   __shared__ int r_start[2][kMaxRanges];        // range tables of the current and the next work item
   __shared__ int r_off[2][kMaxRanges + 1];
   __shared__ int item[2][3];                    // tile, part, heavy slot
+  __shared__ int r_code[kMaxRanges];            // neighbour offset | low class << 8 | high class << 16
   __shared__ Visit<T> vis[kV];                  // [copy in pass][particle]
   __shared__ T pch[kVisitChunk][NCH];           // channel weights per staged particle
   __shared__ int it_first[kV];                  // first work item of each visit
@@ -668,21 +669,41 @@ __global__ void __launch_bounds__(kTileBlock, (sizeof(T) == 4 && NCH <= 8) ? 4 :
   // the first wavefront's registers, and the first chunk of particle records
   // of the next item into registers (each particle in every thread that
   // stages it), while the current item is processed.
-  int pf_tile = 0, pf_hs = -1, pf_part = 0, pf_st = 0, pf_len = 0;
+  // The loads of a fetch stay in flight until the item is published one work
+  // item later: the neighbour ranges sit in LDS for the whole kernel,
+  // ordinary items need no load to name their tile, and a range's length is
+  // formed only at publication.
+  if (threadIdx.x < kMaxRanges) {
+    const int r = (int)threadIdx.x < a.nr ? (int)threadIdx.x : 0;
+    r_code[threadIdx.x] = a.rd[r] | a.rcl[r] << 8 | a.rch[r] << 16;
+  }
+  __syncthreads();
+  int pf_tile = 0, pf_hs = -1, pf_part = 0, pf_st = 0, pf_en = 0;
   auto fetch = [&](int w) {
     if (threadIdx.x < 64 && w < nwork) {
-      const int2 wk = w < nextra ? a.work[w] : make_int2(w - nextra, 0);
-      pf_tile = wk.x;
-      pf_part = wk.y;
-      pf_hs = a.hslot[wk.x];
-      pf_st = 0;
-      pf_len = 0;
-      if (lane < a.nr) tile_range(a, wk.x, lane, &pf_st, &pf_len);
+      int t = w - nextra, part = 0;
+      if (w < nextra) {
+        const int2 wk = a.work[w];
+        t = wk.x;
+        part = wk.y;
+      }
+      pf_tile = t;
+      pf_part = part;
+      pf_hs = a.hslot[t];
+      // every lane loads (lanes past the ranges repeat range 0 and are
+      // masked at publication), so no register is cleared under a load
+      const int code = r_code[lane], my_d = code & 255, my_lo = (code >> 8) & 255, my_hi = code >> 16;
+      const int tx = t / (NT * NT), ty = (t / NT) % NT, tz = t % NT;
+      const int nx = (tx + my_d / 9 - 1 + NT) % NT, ny = (ty + (my_d / 3) % 3 - 1 + NT) % NT,
+                nz = (tz + my_d % 3 - 1 + NT) % NT;
+      const int64_t nt = ((int64_t)nx * NT + ny) * NT + nz;
+      pf_st = a.start[nt * kClasses + my_lo];
+      pf_en = a.start[nt * kClasses + my_hi];
     }
   };
   auto publish = [&](int b) {   // the fetched item -> range table b (first wavefront)
     if (threadIdx.x < 64) {
-      int inc = pf_len;
+      int inc = lane < a.nr ? pf_en - pf_st : 0;
       for (int off = 1; off < 64; off <<= 1) {
         const int x = __shfl_up(inc, off);
         if (lane >= off) inc += x;
@@ -895,7 +916,8 @@ __global__ void __launch_bounds__(kTileBlock, (sizeof(T) == 4 && NCH <= 8) ? 4 :
     if (g0 == 0 && has_next) publish(cb ^ 1);
     __syncthreads();
     if (g0 == 0 && has_next) {
-      // the next item's first chunk of records, loaded while this one finishes
+      // the next item's first chunk of records, then the ranges of the
+      // next-but-one item, loaded while this one finishes
       int n0, n1;
       window(cb ^ 1, &n0, &n1);
       if (n0 + vt < n1) load_rec(cb ^ 1, n0 + vt, nu, ncv);
