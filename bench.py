@@ -169,7 +169,7 @@ def ingest_pmc(fetch_csv, write_csv, command):
         fh.write("\n".join(lines) + "\n")
 
 
-def summarize_trace(stats_csv, command, out_name):
+def summarize_trace(stats_csv, command, out_name, trace_csv=None, timed=0, bench_log=None):
     """A short text summary of a rocprofv3 --kernel-trace --stats run."""
     import csv
     with open(stats_csv) as fh:
@@ -180,6 +180,33 @@ def summarize_trace(stats_csv, command, out_name):
         name = r["Name"].replace("(anonymous namespace)::", "").replace("tsb::", "").replace("void ", "")
         short = name.split("(")[0]
         lines.append(f"| `{short}` | {r['Calls']} | {float(r['AverageNs']) / 1e3:.1f} | {float(r['Percentage']):.2f} |")
+    if trace_csv and timed:
+        # the timed region is the run's last `timed` measurements: per stage,
+        # the mean duration of each of its kernels over its last dispatches
+        with open(trace_csv) as fh:
+            disp = sorted((int(r["Start_Timestamp"]), int(r["End_Timestamp"]), r["Kernel_Name"])
+                          for r in csv.DictReader(fh))
+        lines += ["", f"Timed region (the last {timed} dispatches of each kernel of a stage, from the kernel trace "
+                  "of the same run; compare the stage mean that the run's bench line reports):", "",
+                  "| stage | kernel | mean (us) |", "|---|---|---|"]
+        for stage, names in STAGE_KERNELS.items():
+            total = 0.0
+            for nm in names:
+                d = [(e - s) / 1e3 for s, e, k in disp if nm in k][-timed:]
+                if d:
+                    lines.append(f"| {stage} | `{nm}` | {sum(d) / len(d):.1f} |")
+                    total += sum(d) / len(d)
+            if total:
+                lines.append(f"| {stage} | sum | {total:.1f} |")
+    if bench_log:
+        # the bench line that the profiled run printed (its event-timed stage means)
+        with open(bench_log) as fh:
+            js = [ln for ln in fh if ln.startswith("{")]
+        if js:
+            rec = json.loads(js[-1])
+            lines += ["", "Bench line of the same run: " + json.dumps({"value": rec.get("value"),
+                                                                      "roofline": rec.get("roofline"),
+                                                                      "stage_ms": rec.get("stage_ms")})]
     os.makedirs(os.path.join(ROOT, "profiles"), exist_ok=True)
     with open(os.path.join(ROOT, "profiles", out_name + ".md"), "w") as fh:
         fh.write("\n".join(lines) + "\n")
@@ -401,12 +428,19 @@ def main():
                     help="write profiles/traffic_<stage>.json from two rocprofv3 --pmc runs and exit")
     ap.add_argument("--summarize-trace", nargs=3, metavar=("STATS_CSV", "COMMAND", "NAME"),
                     help="write profiles/NAME.md from a rocprofv3 kernel-stats CSV and exit")
+    ap.add_argument("--trace-csv", default=None,
+                    help="with --summarize-trace: the run's kernel-trace CSV, for the timed-region table")
+    ap.add_argument("--timed-launches", type=int, default=0,
+                    help="with --trace-csv: measurements in the run's timed region")
+    ap.add_argument("--bench-log", default=None,
+                    help="with --summarize-trace: the profiled run's output, whose bench line is quoted")
     args = ap.parse_args()
     if args.ingest_pmc:
         ingest_pmc(*args.ingest_pmc)
         return
     if args.summarize_trace:
-        summarize_trace(*args.summarize_trace)
+        summarize_trace(*args.summarize_trace, trace_csv=args.trace_csv, timed=args.timed_launches,
+                        bench_log=args.bench_log)
         return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the path shards by mock "

@@ -1,5 +1,7 @@
 """Shared helpers of the GPU parity tests (input plumbing and comparisons only)."""
 import math
+import os
+import sys
 
 import numpy as np
 
@@ -49,3 +51,23 @@ def box_request(n=32, box_len=1000.0, n_bins=8, dk=None, **kw):
                box_mode=True, precision="f32")
     req.update(kw)
     return req
+
+
+# Lines printed by the GPU tests (errors against the oracle per multipole and
+# the like), repeated in the run's terminal summary by conftest.py.
+REPORT = []
+
+
+def report(*a):
+    """Print a result line and keep it, with the test's id, for the summary."""
+    def fmt(x):
+        if isinstance(x, np.ndarray) and x.dtype.kind == "f":
+            return np.array2string(x, formatter={"float_kind": lambda v: f"{v:.2e}"})
+        if isinstance(x, float):
+            return f"{x:.6g}"
+        return str(x)
+    line = " ".join(fmt(x) for x in a)
+    print(line, flush=True)
+    sys.stdout.flush()
+    test = os.environ.get("PYTEST_CURRENT_TEST", "").split(" ")[0].split("::")[-1]
+    REPORT.append(f"{test}: {line}" if test else line)

@@ -6,14 +6,13 @@ private), whether it ran through the captured graph, in a batch of mixed grid
 sizes, or on the server alone or in a mix of concurrent requests; one of them
 is also checked against the FP64 oracle.
 """
-import sys
 
 import numpy as np
 import pytest
 
 from mocks import lognormal_box
 from oracle import estimator as est
-from tests.gpu_util import oracle_plan, pair_mask, normwise_errors, box_request
+from tests.gpu_util import oracle_plan, pair_mask, normwise_errors, box_request, report
 
 pytestmark = pytest.mark.gpu
 
@@ -25,8 +24,7 @@ import paper_1803_02132_amd as tsb  # noqa: E402
 
 
 def _say(*a):
-    print(*a, flush=True)
-    sys.stdout.flush()
+    report(*a)
 
 
 def _same(a, b):

@@ -14,12 +14,12 @@ Tolerance: 1e-4 normwise per multipole (max |dB| / max |B| over the compared
 pairs), FP32 fields with FP64 accumulation.
 """
 import os
-import sys
 
 import numpy as np
 import pytest
 
 from mocks.lognormal import WORKLOADS, survey_workload, workload
+from tests.gpu_util import report
 
 pytestmark = pytest.mark.gpu
 
@@ -33,8 +33,7 @@ GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
 
 
 def _say(*a):
-    print(*a, flush=True)
-    sys.stdout.flush()
+    report(*a)
 
 
 def _checksum(cat):

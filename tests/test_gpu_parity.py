@@ -9,14 +9,13 @@ Assignment grids: FP64 to 1e-12 and FP32 to 2e-6 of the largest value;
 N_mode bit-exact.
 """
 import math
-import sys
 
 import numpy as np
 import pytest
 
 from mocks import lognormal_box
 from oracle import estimator as est
-from tests.gpu_util import oracle_plan, pair_mask, normwise_errors, box_request
+from tests.gpu_util import oracle_plan, pair_mask, normwise_errors, box_request, report
 
 pytestmark = pytest.mark.gpu
 
@@ -28,8 +27,7 @@ import paper_1803_02132_amd as tsb  # noqa: E402
 
 
 def _say(*a):
-    print(*a, flush=True)
-    sys.stdout.flush()
+    report(*a)
 
 
 def small_cat(n=32, box_len=1000.0, n_target=20000, seed=1, rsd="local", observer=(500.0, 500.0, -1500.0)):
