@@ -607,9 +607,10 @@ __device__ inline int tile_exponent(int visits, double cw) {
 
 // One grid copy's fixed-point words of a node -> the complex output grids:
 // packed (word g holds grid g, tile scale) or one word per channel slot
-// (words 2g and 2g+1, plan-wide scale).
-template <typename T>
-__device__ inline void put_node(const unsigned long long* w, size_t wstride, int ngrid, bool packed, int et_neg,
+// (words 2g and 2g+1, plan-wide scale). With clear, the words read are set
+// to zero (the accumulators then start the next work item cleared).
+template <typename T, bool clear>
+__device__ inline void put_node(unsigned long long* w, size_t wstride, int ngrid, bool packed, int et_neg,
                                 double inv_scale, typename cplx<T>::type* out, size_t gstride) {
   typedef typename cplx<T>::type T2;
   for (int gr = 0; gr < ngrid; ++gr) {
@@ -619,9 +620,11 @@ __device__ inline void put_node(const unsigned long long* w, size_t wstride, int
       unpack2(w[(size_t)gr * wstride], &lo, &hi);
       o.x = (T)ldexpf((float)lo, et_neg);
       o.y = (T)ldexpf((float)hi, et_neg);
+      if (clear) w[(size_t)gr * wstride] = 0ull;
     } else {
       o.x = (T)((double)(long long)w[(size_t)(2 * gr) * wstride] * inv_scale);
       o.y = (T)((double)(long long)w[(size_t)(2 * gr + 1) * wstride] * inv_scale);
+      if (clear) w[(size_t)(2 * gr) * wstride] = w[(size_t)(2 * gr + 1) * wstride] = 0ull;
     }
     out[(size_t)gr * gstride] = o;
   }
@@ -677,6 +680,9 @@ __global__ void __launch_bounds__(kTileBlock, (sizeof(T) == 4 && NCH <= 8) ? 4 :
     const int r = (int)threadIdx.x < a.nr ? (int)threadIdx.x : 0;
     r_code[threadIdx.x] = a.rd[r] | a.rcl[r] << 8 | a.rch[r] << 16;
   }
+  // the accumulators start cleared; afterwards every pass's write-out clears
+  // the words it reads
+  for (int i = threadIdx.x; i < nw * T3; i += kTileBlock) acc[i] = 0ull;
   __syncthreads();
   int pf_tile = 0, pf_hs = -1, pf_part = 0, pf_st = 0, pf_en = 0;
   auto fetch = [&](int w) {
@@ -756,8 +762,9 @@ __global__ void __launch_bounds__(kTileBlock, (sizeof(T) == 4 && NCH <= 8) ? 4 :
     }
     fetch(blockIdx.x + gridDim.x);
   }
+  // the previous work item ended with a barrier after its last LDS use (and
+  // published this item's table before one)
   for (int w = blockIdx.x; w < nwork; w += gridDim.x) {
-  __syncthreads();   // the previous work item is done with the LDS
   const int tile = item[cb][0], hs = item[cb][2];   // hs >= 0: split tile, sums go to its slot
   const int tx = tile / (NT * NT), ty = (tile / NT) % NT, tz = tile % NT;
   const int o3[3] = {tx * TS, ty * TS, tz * TS};
@@ -773,10 +780,9 @@ __global__ void __launch_bounds__(kTileBlock, (sizeof(T) == 4 && NCH <= 8) ? 4 :
   const bool has_next = w + (int)gridDim.x < nwork;
   double sumI = 0.0;
   for (int g0 = 0; g0 < a.copies; g0 += ncp) {
-    for (int i = threadIdx.x; i < nw * T3; i += kTileBlock) acc[i] = 0ull;
     for (int c0 = v0; c0 < v1; c0 += kVisitChunk) {
       const int nv = min(kVisitChunk, v1 - c0);
-      __syncthreads();   // acc cleared / previous chunk consumed
+      if (c0 != v0) __syncthreads();   // the previous chunk is consumed
       int items = 0;
       {
         // staging: thread t stages copy g0 + (t >> 7) of particle t & 127
@@ -930,7 +936,10 @@ __global__ void __launch_bounds__(kTileBlock, (sizeof(T) == 4 && NCH <= 8) ? 4 :
       unsigned long long* hb = a.heavy + ((size_t)hs * a.copies + g0) * nw * T3;
       for (int i = threadIdx.x; i < nwg * T3; i += kTileBlock) {
         const unsigned long long v = acc[i];
-        if (v != 0ull) atomicAdd(hb + i, v);
+        if (v != 0ull) {
+          atomicAdd(hb + i, v);
+          acc[i] = 0ull;
+        }
       }
       __syncthreads();
       continue;
@@ -940,16 +949,17 @@ __global__ void __launch_bounds__(kTileBlock, (sizeof(T) == 4 && NCH <= 8) ? 4 :
       const int lt = a.lt, tm = TS - 1;
       for (int cp = 0; cp < ncp; ++cp) {
         T2* tout = out + (size_t)(g0 + cp) * npair * N3 + ((size_t)o3[0] * N + o3[1]) * N + o3[2];
-        const unsigned long long* cw = acc + (packed ? (size_t)cp * npair * T3 : 0);
+        unsigned long long* cw = acc + (packed ? (size_t)cp * npair * T3 : 0);
         for (int cell = threadIdx.x; cell < T3; cell += kTileBlock) {
           const int lx = cell >> (2 * lt), ly = (cell >> lt) & tm, lz = cell & tm;
-          put_node<T>(cw + cell, T3, npair, packed, -et, inv_scale, tout + ((lx * N + ly) * N + lz), N3);
+          put_node<T, true>(cw + cell, T3, npair, packed, -et, inv_scale, tout + ((lx * N + ly) * N + lz), N3);
         }
       }
       if (wrw >= 0 && g0 == 0) {
         // Sec. 4.2, eq. 37: sum_j (alpha R_j)^3 over this tile
         for (int cell = threadIdx.x; cell < T3; cell += kTileBlock) {
           const double v = alpha * (double)(long long)acc[(size_t)wrw * T3 + cell] * inv_scale;
+          acc[(size_t)wrw * T3 + cell] = 0ull;
           sumI += v * v * v;
         }
       }
@@ -998,7 +1008,7 @@ __global__ void __launch_bounds__(kBlock) heavy_final_kernel(TileArgs a, const i
     for (int cell = threadIdx.x; cell < T3; cell += kBlock) {
       const int lx = cell / (TS * TS), ly = (cell / TS) % TS, lz = cell % TS;
       const size_t lin = ((size_t)(o3[0] + lx) * N + (o3[1] + ly)) * N + (o3[2] + lz);
-      put_node<T>(hb + cell, T3, a.ngrid, false, 0, inv_scale, out + (size_t)g * a.ngrid * N3 + lin, N3);
+      put_node<T, false>(hb + cell, T3, a.ngrid, false, 0, inv_scale, out + (size_t)g * a.ngrid * N3 + lin, N3);
       if (wr >= 0 && g == 0) {
         const double v = a.scal->alpha * (double)(long long)hb[(size_t)wr * T3 + cell] * inv_scale;
         sumI += v * v * v;
