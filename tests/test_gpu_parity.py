@@ -152,6 +152,22 @@ def test_local_los_tsc_interlaced(precision, tol, unfused):
     assert np.all(err <= tol)
 
 
+@pytest.mark.parametrize("pair_mode", ["diagonal", "all"])
+def test_pair_modes(pair_mode):
+    # the diagonal measurement (k1 = k2 only, the cheaper one of Sec. 4.4) and
+    # every ordered pair: the computed pairs match the oracle, the others are NaN
+    req = box_request(n=32, multipoles=[(0, 0, 0), (1, 1, 0), (2, 0, 2), (1, 1, 2)], precision="f32", n_bins=6,
+                      pair_mode=pair_mode)
+    cat = small_cat(seed=4)
+    plan, g, o = run_both(req, cat)
+    mask = pair_mask(req["multipoles"], req["n_bins"], pair_mode)
+    err = normwise_errors(g["B"], o["B"], mask)
+    _say(pair_mode, "errors", err)
+    assert np.all(np.isnan(g["B"][~mask]))
+    assert np.all(np.isfinite(g["B"][mask]))
+    assert np.all(err <= 1e-4)
+
+
 def test_survey_fkp():
     req = box_request(n=32, box_mode=False, P0=1e4, interlace=True, observer=(500.0, 500.0, 500.0),
                       multipoles=[(0, 0, 0), (2, 0, 2), (4, 0, 4)], precision="f32", n_bins=6)
