@@ -171,7 +171,10 @@ int tsb_plan_nmode(const tsb_plan* plan, int64_t* nmode, double* k_eff);
  *            outside the plan's pair set are NaN; real part of eq. 41;
  *   I_out    host scalar, the normalisation I (may be NULL);
  *   alpha_out host scalar, alpha (0 in box mode) (may be NULL).
- * Synchronises the stream. Errors: TSB_E_ARG, TSB_E_INPUT, TSB_E_DEVICE. */
+ * Synchronises the stream. Errors: TSB_E_ARG, TSB_E_INPUT (a non-finite
+ * position or weight, a survey particle outside the box or at the observer,
+ * or a normalisation I that is not positive, e.g. an empty catalogue, for
+ * which eq. 41 is undefined), TSB_E_DEVICE. */
 int tsb_measure(tsb_plan* plan, const tsb_catalog* data, const tsb_catalog* randoms,
                 void* stream, double* B_out, double* I_out, double* alpha_out);
 

@@ -162,7 +162,7 @@ void plan_free(Plan& P) {
 namespace {
 
 int ensure_particles(Plan& P, int64_t n) {
-  if (n <= P.particle_cap) return TSB_OK;
+  if (n <= P.particle_cap && P.d_rec) return TSB_OK;   // (buffers exist even for an empty catalogue)
   if (n > 2147483647LL) return fail(TSB_E_UNSUPPORTED, "more than 2^31-1 particles");
   const int64_t per = 4 + record_stride(P);   // key, record
   for (void* p : {(void*)P.d_keys, P.d_rec, P.d_work})
@@ -363,6 +363,8 @@ int finish_measure(Plan& P, int slot, double* B_out, double* I_out, double* alph
   std::memcpy(&h, base + P.outs.size() * 8, sizeof(h));
   int rc;
   if ((rc = check_input_flags(P, h))) return rc;
+  if (!(h.I > 0.0) || !std::isfinite(h.I))
+    return fail(TSB_E_INPUT, "the normalisation I is not positive (no weighted particles or randoms): B is undefined");
   const size_t nbb = (size_t)P.nb * P.nb;
   for (size_t i = 0; i < P.mult.size() * nbb; ++i) B_out[i] = std::numeric_limits<double>::quiet_NaN();
   for (size_t o = 0; o < P.outs.size(); ++o) {

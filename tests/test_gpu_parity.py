@@ -216,6 +216,38 @@ def test_bad_input_is_reported():
     assert e.value.code == tsb.abi.TSB_E_INPUT
 
 
+def test_empty_catalogue_is_reported():
+    # no particles: the normalisation I vanishes and eq. 41 is undefined; the
+    # grids of the assignment are all zero
+    req = box_request(n=32, precision="f32")
+    plan = tsb.Plan(**req)
+    empty = tsb.catalog_to_device({"pos": np.zeros((0, 3), np.float32)})
+    with pytest.raises(tsb.TsbError) as e:
+        plan.measure(empty)
+    assert e.value.code == tsb.abi.TSB_E_INPUT
+    assert not np.any(plan.assign(empty).cpu().numpy())
+    # the plan still measures a catalogue afterwards
+    cat = small_cat(seed=8)
+    g = plan.measure(tsb.catalog_to_device(cat))
+    o = est.measure(oracle_plan(**req), cat)
+    mask = pair_mask(req["multipoles"], req["n_bins"])
+    assert np.all(normwise_errors(g["B"], o["B"], mask) <= 1e-4)
+
+
+def test_single_particle():
+    # the smallest catalogue: one particle off the nodes. Only the monopole is
+    # compared: with one particle the l > 0 shell sums nearly cancel (the
+    # grid's cubic symmetry), leaving values at the rounding level
+    req = box_request(n=32, precision="f32", multipoles=[(0, 0, 0)])
+    cat = {"pos": np.array([[123.4, 567.8, 901.2]], np.float32)}
+    plan, g, o = run_both(req, cat)
+    mask = pair_mask(req["multipoles"], req["n_bins"])
+    err = normwise_errors(g["B"], o["B"], mask)
+    _say("single particle errors", err, "I", g["I"], o["I"])
+    assert g["I"] == pytest.approx(o["I"], rel=1e-12)
+    assert np.all(err <= 1e-4)
+
+
 def _assign_vs_oracle(req, cat, tol):
     plan = tsb.Plan(**req)
     grids = plan.assign(tsb.catalog_to_device(cat)).cpu().numpy()
