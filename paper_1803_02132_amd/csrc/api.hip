@@ -98,7 +98,8 @@ int plan_alloc(Plan& P, bool dry) {
   ALLOC(P.d_bk_start, (P.nbk + 1) * 4);
   ALLOC(P.d_scan_part, ((P.nbk + kScanChunk - 1) / kScanChunk + 1) * 4);
   ALLOC(P.d_tile_hslot, ntiles * 4);
-  ALLOC(P.d_heavy_tile, (int64_t)assign_max_heavy() * 4);
+  P.heavy_slots = assign_max_heavy(P);
+  ALLOC(P.d_heavy_tile, (int64_t)P.heavy_slots * 4);
   ALLOC(P.d_heavy, assign_heavy_bytes(P));
   // split-tile slots start at zero; the conversion kernel clears each slot it reads
   if (!dry) TSB_HIP(hipMemset(P.d_heavy, 0, (size_t)assign_heavy_bytes(P)));

@@ -467,6 +467,7 @@ struct TileArgs {
   int ntiles;
   const int* hslot;            // per tile: heavy slot or -1
   unsigned long long* heavy;   // [slot][copies][nw][T^3] fixed-point sums of split tiles
+  int max_heavy;               // slots of split tiles
 };
 
 // Ranges of one tile (wave-parallel): start and length of range r of tile t.
@@ -509,7 +510,7 @@ __device__ inline void node_dir(const double* origin, double h, const double* ob
 constexpr int kVisitChunk = 128;  // particles staged in LDS at a time (a power of two)
 constexpr int kPartVisits = 256;  // visits per work item; busier tiles are split
 constexpr int kTileBlock = 256;    // threads per workgroup of the tile kernel
-constexpr int kMaxHeavy = 2048;   // split tiles with a slot of their own (others run whole)
+constexpr int kMinHeavy = 2048;   // split-tile slots at least (or one per tile); others run whole
 
 // A staged (particle, grid copy) visit: per axis the stencil parameter d (the
 // kernel weights are functions of d and the stencil index) and which stencil
@@ -595,8 +596,8 @@ __device__ inline void unpack2(unsigned long long v, int* lo, int* hi) {
 // weight of the kernel), and the scale maps that bound below 2^30. A
 // contribution is the FP32 product c W 2^e rounded to the nearest integer
 // (ties to even), so the rounding errors carry no bias. Packing is used for
-// tiles of at most kPartVisits visits (those that run as one work item), so
-// the fixed-point step is at most 2^-22 max |c| W_max.
+// work items of at most kPartVisits visits (a whole tile, or a part of a
+// split one), so the fixed-point step is at most 2^-21 max |c| W_max.
 __device__ inline int tile_exponent(int visits, double cw) {
   const double bound = (double)visits * cw;
   if (!(bound > 0.0) || !isfinite(bound)) return 0;
@@ -772,8 +773,16 @@ __global__ void __launch_bounds__(kTileBlock, (sizeof(T) == 4 && NCH <= 8) ? 4 :
   window(cb, &v0, &v1);
   // FP32 tiles that run whole: two channels per word at the tile's own scale,
   // both grid copies in one pass (word of copy c, grid k: c * npair + k)
-  const bool packed = sizeof(T) == 4 && r_off[cb][64] <= kPartVisits;
-  const int et = packed ? tile_exponent(r_off[cb][64], cmax * a.wmax) : 0;
+  // FP32 work items of at most kPartVisits visits pack two channels per word
+  // at a scale of their own: a whole tile (from its visits), or a part of a
+  // split tile (from kPartVisits, the same for every part: which part a
+  // particle falls in depends on the bucket order, its rounding must not).
+  // A part converts its sums to the plan's scale, exactly, when it adds them
+  // into the slot (the shift plan_e - et is never negative then).
+  const int plan_e = ilogb(scale);
+  const int et_item = tile_exponent(hs >= 0 ? kPartVisits : v1 - v0, cmax * a.wmax);
+  const bool packed = sizeof(T) == 4 && (r_off[cb][64] <= kPartVisits || (hs >= 0 && plan_e >= et_item));
+  const int et = packed ? et_item : 0;
   const float tscale = ldexpf(1.0f, et);
   const int ncp = packed ? a.copies : 1;                 // grid copies per pass
   const int wrw = wr < 0 ? -1 : (packed ? a.copies * npair : wr);   // randoms word
@@ -930,15 +939,41 @@ __global__ void __launch_bounds__(kTileBlock, (sizeof(T) == 4 && NCH <= 8) ? 4 :
       fetch(w + 2 * gridDim.x);
     }
     if (hs >= 0) {
-      // part of a split tile (one copy per pass): add the fixed-point sums
-      // into its slot (integer, order-free)
-      const int nwg = (g0 == 0 || wr < 0) ? nw : nw - 1;   // the randoms word is the last one, copy 0 only
-      unsigned long long* hb = a.heavy + ((size_t)hs * a.copies + g0) * nw * T3;
-      for (int i = threadIdx.x; i < nwg * T3; i += kTileBlock) {
-        const unsigned long long v = acc[i];
-        if (v != 0ull) {
-          atomicAdd(hb + i, v);
+      // part of a split tile: add the fixed-point sums into its slot
+      // (integer, order-free; the randoms word is the last one, copy 0 only)
+      if (packed) {
+        // both copies in this pass: each two-channel word unpacks into the
+        // slot's channel words, shifted to the plan's scale (exact)
+        const int sh = plan_e - et;
+        for (int i = threadIdx.x; i < ncp * npair * T3; i += kTileBlock) {
+          const unsigned long long v = acc[i];
+          if (v == 0ull) continue;
+          const int cell = i & (T3 - 1), ck = i / T3, q = ck / npair, k = ck - q * npair;
+          unsigned long long* hb = a.heavy + ((size_t)hs * a.copies + g0 + q) * nw * T3 + cell;
+          int lo, hi;
+          unpack2(v, &lo, &hi);
+          atomicAdd(hb + (size_t)(2 * k) * T3, (unsigned long long)lo << sh);
+          atomicAdd(hb + (size_t)(2 * k + 1) * T3, (unsigned long long)hi << sh);
           acc[i] = 0ull;
+        }
+        if (wrw >= 0) {
+          unsigned long long* hb = a.heavy + (size_t)hs * a.copies * nw * T3 + (size_t)wr * T3;
+          for (int cell = threadIdx.x; cell < T3; cell += kTileBlock) {
+            const unsigned long long v = acc[(size_t)wrw * T3 + cell];
+            if (v == 0ull) continue;
+            atomicAdd(hb + cell, v);
+            acc[(size_t)wrw * T3 + cell] = 0ull;
+          }
+        }
+      } else {
+        const int nwg = (g0 == 0 || wr < 0) ? nw : nw - 1;
+        unsigned long long* hb = a.heavy + ((size_t)hs * a.copies + g0) * nw * T3;
+        for (int i = threadIdx.x; i < nwg * T3; i += kTileBlock) {
+          const unsigned long long v = acc[i];
+          if (v != 0ull) {
+            atomicAdd(hb + i, v);
+            acc[i] = 0ull;
+          }
         }
       }
       __syncthreads();
@@ -994,7 +1029,7 @@ __global__ void __launch_bounds__(kBlock) heavy_final_kernel(TileArgs a, const i
   typedef typename cplx<T>::type T2;
   __shared__ double sh[kBlock];
   const int slot = blockIdx.x;
-  if (slot >= min(*nheavy, kMaxHeavy)) return;
+  if (slot >= min(*nheavy, a.max_heavy)) return;
   const int tile = heavy_tile[slot];
   const int TS = a.T, T3 = TS * TS * TS, N = a.N, NT = a.NT;
   const int nw = a.nw, wr = a.wr;
@@ -1048,7 +1083,7 @@ __global__ void __launch_bounds__(kBlock) tile_parts_kernel(TileArgs a, int ntil
   int hs = -1;
   if (np > 1) {
     const int sl = atomicAdd(nheavy, 1);
-    if (sl < kMaxHeavy) {   // out of slots: the tile runs whole
+    if (sl < a.max_heavy) {   // out of slots: the tile runs whole
       hs = sl;
       heavy_tile[sl] = t;
       const int e = atomicAdd(nextra, np - 1);
@@ -1208,10 +1243,19 @@ int64_t assign_work_cap(const Plan& P, int64_t particles) {
 }
 
 int64_t assign_heavy_bytes(const Plan& P) {
-  return (int64_t)kMaxHeavy * P.copies * assign_words(P) * P.T * P.T * P.T * 8;
+  return (int64_t)P.heavy_slots * P.copies * assign_words(P) * P.T * P.T * P.T * 8;
 }
 
-int assign_max_heavy() { return kMaxHeavy; }
+// Slots for split tiles: a quarter of the tiles (dense catalogues split many),
+// at least kMinHeavy, at most one per tile, and at most 1 GiB of sums.
+int assign_max_heavy(const Plan& P) {
+  const int64_t ntiles = (int64_t)P.NT * P.NT * P.NT;
+  const int64_t per = (int64_t)P.copies * assign_words(P) * P.T * P.T * P.T * 8;
+  int64_t n = std::max<int64_t>(kMinHeavy, ntiles / 4);
+  n = std::min<int64_t>(n, (1LL << 30) / per);
+  n = std::max<int64_t>(n, kMinHeavy);
+  return (int)std::min<int64_t>(n, ntiles);
+}
 
 int chan_info(const Plan& P, ChanInfo* ci) {
   *ci = ChanInfo{};
@@ -1349,6 +1393,7 @@ int assign_back_impl(Plan& P, const ChanInfo& ci, hipStream_t s) {
   a.ntiles = ntiles;
   a.hslot = P.d_tile_hslot;
   a.heavy = (unsigned long long*)P.d_heavy;
+  a.max_heavy = P.heavy_slots;
   prof_begin(P, kStAssign, s);
   // work items: tiles with more than kPartVisits visits are split into parts
   hipLaunchKernelGGL(tile_parts_kernel, dim3((ntiles + kBlock / 64 - 1) / (kBlock / 64)), dim3(kBlock), 0, s, a,
@@ -1356,7 +1401,7 @@ int assign_back_impl(Plan& P, const ChanInfo& ci, hipStream_t s) {
   const size_t lds = (size_t)nw * P.T * P.T * P.T * sizeof(unsigned long long);
   hipLaunchKernelGGL((assign_tile_kernel<T, NCH>), dim3(std::max(1, P.tile_wgs)), dim3(kTileBlock), lds, s, a,
                      rec);
-  hipLaunchKernelGGL(heavy_final_kernel<T>, dim3(kMaxHeavy), dim3(kBlock), 0, s, a, (const int*)P.d_heavy_tile,
+  hipLaunchKernelGGL(heavy_final_kernel<T>, dim3(P.heavy_slots), dim3(kBlock), 0, s, a, (const int*)P.d_heavy_tile,
                      (const int*)nheavy);
   if (!P.box_mode) {
     const double vc = P.L * P.L * P.L / ((double)P.N * P.N * P.N);

@@ -146,6 +146,7 @@ struct Plan {
   int* d_keys = nullptr;        // bucket key per particle
   int* d_tile_hslot = nullptr;  // heavy slot per tile or -1 [ntiles]
   int* d_heavy_tile = nullptr;  // tile of each heavy slot
+  int heavy_slots = 0;          // slots of split tiles (d_heavy_tile, d_heavy)
   void* d_heavy = nullptr;      // fixed-point sums of split tiles [slot][copies][words][T^3]
   void* d_work = nullptr;       // work items (tile, part) [work_cap]
   int64_t work_cap = 0;
@@ -234,7 +235,7 @@ int64_t assign_work_cap(const Plan& P, int64_t particles);
 int record_stride(const Plan& P);
 int assign_words(const Plan& P);
 int64_t assign_heavy_bytes(const Plan& P);
-int assign_max_heavy();
+int assign_max_heavy(const Plan& P);
 int run_unpack_grids(Plan& P, void* out, hipStream_t s);
 
 // ---------------------------------------------------------------------------
