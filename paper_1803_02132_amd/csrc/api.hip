@@ -98,7 +98,7 @@ int plan_alloc(Plan& P, bool dry) {
   ALLOC(P.d_bk_start, (P.nbk + 1) * 4);
   ALLOC(P.d_scan_part, ((P.nbk + kScanChunk - 1) / kScanChunk + 1) * 4);
   ALLOC(P.d_tile_hslot, ntiles * 4);
-  P.heavy_slots = assign_max_heavy(P);
+  P.heavy_slots = assign_max_heavy(P, B);
   ALLOC(P.d_heavy_tile, (int64_t)P.heavy_slots * 4);
   ALLOC(P.d_heavy, assign_heavy_bytes(P));
   // split-tile slots start at zero; the conversion kernel clears each slot it reads

@@ -1247,12 +1247,13 @@ int64_t assign_heavy_bytes(const Plan& P) {
 }
 
 // Slots for split tiles: a quarter of the tiles (dense catalogues split many),
-// at least kMinHeavy, at most one per tile, and at most 1 GiB of sums.
-int assign_max_heavy(const Plan& P) {
+// at least kMinHeavy, at most one per tile, and at most 1 GiB of sums or an
+// eighth of the rest of the workspace (other_bytes), whichever is larger.
+int assign_max_heavy(const Plan& P, int64_t other_bytes) {
   const int64_t ntiles = (int64_t)P.NT * P.NT * P.NT;
   const int64_t per = (int64_t)P.copies * assign_words(P) * P.T * P.T * P.T * 8;
   int64_t n = std::max<int64_t>(kMinHeavy, ntiles / 4);
-  n = std::min<int64_t>(n, (1LL << 30) / per);
+  n = std::min<int64_t>(n, std::max<int64_t>(1LL << 30, other_bytes / 8) / per);
   n = std::max<int64_t>(n, kMinHeavy);
   return (int)std::min<int64_t>(n, ntiles);
 }

@@ -235,7 +235,7 @@ int64_t assign_work_cap(const Plan& P, int64_t particles);
 int record_stride(const Plan& P);
 int assign_words(const Plan& P);
 int64_t assign_heavy_bytes(const Plan& P);
-int assign_max_heavy(const Plan& P);
+int assign_max_heavy(const Plan& P, int64_t other_bytes);
 int run_unpack_grids(Plan& P, void* out, hipStream_t s);
 
 // ---------------------------------------------------------------------------
