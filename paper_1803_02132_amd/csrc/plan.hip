@@ -387,6 +387,13 @@ int plan_build(Plan& P) {
     if (P.f2idx[q.f2] < 0) P.f2idx[q.f2] = P.nf2++;
   plan_fused(P);
   if (P.fused && !P.fused_wide) P.red_wg = (int)std::min<int64_t>((int64_t)P.M * P.M, 1024);
+  // unfused FP32 plans with at most 32 shells: the sum over a chunk's cells on
+  // the matrix cores (32 x 32 tiles, k steps of 8 cells), up to 16 Q groups
+  P.red_mfma = 0;
+  if (!P.fused && P.precision == TSB_FP32 && P.nb <= 32 && P.red_chunk % 8 == 0) {
+    const int upw = ((int)P.qgroups.size() + 3) / 4;
+    if (upw >= 1 && upw <= 4) P.red_mfma = upw == 1 ? 1 : (upw == 2 ? 2 : 4);
+  }
   P.g_offset = P.fused ? 0 : (int64_t)P.nb * (int64_t)P.fkinds.size() * P.M * P.M * P.M;
   return TSB_OK;
 }

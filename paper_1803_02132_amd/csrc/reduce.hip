@@ -106,6 +106,105 @@ __global__ void __launch_bounds__(kBlock) reduce_kernel(RedArgs<T> a) {
   }
 }
 
+// FP32 plans with at most 32 shells: the same staging and Q rows, but the sum
+// over a chunk's cells of Q_q(x; b1) f2_q(x; b2) runs on the matrix cores as
+// one 32 x 32 tile of (b1, b2) per Q group (FP32 32x32x2 MFMA; shells padded
+// to 32, lanes past the shells feed zeros), FP32 within a chunk and FP64
+// across chunks. Wavefront w holds the tiles of Q groups w, w + 4, ... (UPW
+// of them); the workgroup's partial of every output is then formed from the
+// tiles in a fixed order.
+typedef float floatx16 __attribute__((ext_vector_type(16)));
+
+template <int UPW>
+__global__ void __launch_bounds__(kBlock) reduce_mfma_kernel(RedArgs<float> a) {
+  extern __shared__ char smem[];
+  const int C = a.chunk;
+  const int CP = C + 1;
+  float* Fv = (float*)smem;                      // [nb][nfc][CP]
+  float* Gv = Fv + (size_t)a.nb * a.nfc * CP;    // [ngc][CP]
+  float* Qv = Gv + (size_t)a.ngc * CP;           // [nq][nb][CP]
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  constexpr int kWaves = kBlock / 64;
+  double acc[UPW][16];
+#pragma unroll
+  for (int u = 0; u < UPW; ++u)
+#pragma unroll
+    for (int r = 0; r < 16; ++r) acc[u][r] = 0.0;
+
+  for (int64_t ch = blockIdx.x; ch < a.nchunks; ch += gridDim.x) {
+    const int64_t c0 = ch * C;
+    const int nslot = a.nb * a.nkinds;
+    for (int idx = tid; idx < nslot * C; idx += kBlock) {
+      const int slot = idx / C, c = idx - slot * C;
+      const float2 v = a.fields[(int64_t)slot * a.M3 + c0 + c];
+      const int b = slot / a.nkinds, k = slot - b * a.nkinds;
+      for (int f = 0; f < a.nfc; ++f)
+        if (a.fcomp[f].slot == k) Fv[((size_t)b * a.nfc + f) * CP + c] = a.fcomp[f].part ? v.y : v.x;
+    }
+    for (int idx = tid; idx < a.ngrid * C; idx += kBlock) {
+      const int g = idx / C, c = idx - g * C;
+      const float2 v = a.fields[((int64_t)nslot + g) * a.M3 + c0 + c];
+      for (int f = 0; f < a.ngc; ++f)
+        if (a.gcomp[f].slot == g) Gv[(size_t)f * CP + c] = a.gcomp[f].part ? v.y : v.x;
+    }
+    __syncthreads();
+    for (int idx = tid; idx < a.nq * a.nb * C; idx += kBlock) {
+      const int c = idx % C;
+      const int qb = idx / C;
+      const int b1 = qb % a.nb, q = qb / a.nb;
+      const QGroup g = a.qg[q];
+      double s = 0.0;
+      for (int t = g.t0; t < g.t1; ++t) {
+        const Term tm = a.terms[t];
+        s += tm.coef * (double)Fv[((size_t)b1 * a.nfc + tm.f1) * CP + c] * (double)Gv[(size_t)tm.g * CP + c];
+      }
+      Qv[((size_t)q * a.nb + b1) * CP + c] = (float)s;
+    }
+    __syncthreads();
+    const int b = lane & 31, kh = lane >> 5;
+    const bool live = b < a.nb;
+#pragma unroll
+    for (int u = 0; u < UPW; ++u) {
+      const int q = wave + kWaves * u;
+      if (q >= a.nq) break;   // uniform in the wavefront
+      const float* qr = Qv + ((size_t)q * a.nb + (live ? b : 0)) * CP + kh;
+      const float* fr = Fv + ((size_t)(live ? b : 0) * a.nfc + a.qg[q].f2) * CP + kh;
+      floatx16 c = {};
+      for (int kk = 0; kk < C; kk += 8) {
+        float av[4], bv[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          av[j] = live ? qr[kk + 2 * j] : 0.f;
+          bv[j] = live ? fr[kk + 2 * j] : 0.f;
+        }
+#pragma unroll
+        for (int j = 0; j < 4; ++j) c = __builtin_amdgcn_mfma_f32_32x32x2f32(av[j], bv[j], c, 0, 0, 0);
+      }
+#pragma unroll
+      for (int r = 0; r < 16; ++r) acc[u][r] += (double)c[r];
+    }
+    __syncthreads();   // the next chunk overwrites the staged rows
+  }
+  double* Ct = (double*)smem;   // [nq][32][32]
+#pragma unroll
+  for (int u = 0; u < UPW; ++u) {
+    const int q = wave + kWaves * u;
+    if (q >= a.nq) break;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const int i = 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3), j = lane & 31;
+      Ct[((size_t)q * 32 + i) * 32 + j] = acc[u][r];
+    }
+  }
+  __syncthreads();
+  for (int o = tid; o < a.nout_all; o += kBlock) {
+    const OutEntry e = a.outs[o];
+    double v = 0.0;
+    for (int q = e.q0; q < e.q1; ++q) v += Ct[((size_t)q * 32 + e.b1) * 32 + e.b2];
+    a.partials[(size_t)o * gridDim.x + blockIdx.x] = v;
+  }
+}
+
 // One block per output: each thread sums a fixed subset of the workgroup
 // partials, then a fixed-shape tree; the order never depends on scheduling.
 __global__ void __launch_bounds__(kBlock) reduce_final_kernel(const double* partials, int nwg,
@@ -151,6 +250,22 @@ int reduce_impl(Plan& P, hipStream_t s) {
   const int per_launch = kOutPerThread * kBlock;
   a.nout_all = nout_all;
   prof_begin(P, kStReduce, s);
+  if constexpr (std::is_same<T, float>::value) {
+    if (P.red_mfma > 0) {
+      const size_t lds_m = std::max(lds, (size_t)a.nq * 32 * 32 * sizeof(double));
+      a.out0 = 0;
+      a.nout = nout_all;
+      if (P.red_mfma == 1)
+        hipLaunchKernelGGL(reduce_mfma_kernel<1>, dim3(P.red_wg), dim3(kBlock), lds_m, s, a);
+      else if (P.red_mfma == 2)
+        hipLaunchKernelGGL(reduce_mfma_kernel<2>, dim3(P.red_wg), dim3(kBlock), lds_m, s, a);
+      else
+        hipLaunchKernelGGL(reduce_mfma_kernel<4>, dim3(P.red_wg), dim3(kBlock), lds_m, s, a);
+      prof_end(P, kStReduce, s);
+      TSB_HIP(hipGetLastError());
+      return run_reduce_final(P, s);
+    }
+  }
   for (int o0 = 0; o0 < nout_all; o0 += per_launch) {
     a.out0 = o0;
     a.nout = std::min(per_launch, nout_all - o0);

@@ -170,6 +170,7 @@ struct Plan {
   void* d_rec = nullptr;      // particle records in bucket order (u, channel weights), [cap][stride]
   int64_t particle_cap = 0;
   int red_chunk = 64, red_wg = 1024;
+  int red_mfma = 0;             // unfused FP32 reduction on the matrix cores: Q-group tiles per wavefront (0: off)
   int64_t bytes = 0;
 
   // fused last F pass + reduction
