@@ -390,7 +390,8 @@ int plan_build(Plan& P) {
   // unfused FP32 plans with at most 32 shells: the sum over a chunk's cells on
   // the matrix cores (32 x 32 tiles, k steps of 8 cells), up to 16 Q groups
   P.red_mfma = 0;
-  if (!P.fused && P.precision == TSB_FP32 && P.nb <= 32 && P.red_chunk % 8 == 0) {
+  if (!P.fused && P.precision == TSB_FP32 && P.nb <= 32 && P.red_chunk % 8 == 0 && P.fkinds.size() <= 32 &&
+      P.grids.size() <= 32) {
     const int upw = ((int)P.qgroups.size() + 3) / 4;
     if (upw >= 1 && upw <= 4) P.red_mfma = upw == 1 ? 1 : (upw == 2 ? 2 : 4);
   }

@@ -17,6 +17,7 @@ namespace tsb {
 namespace {
 
 constexpr int kOutPerThread = 16;   // outputs per thread per launch
+constexpr int kRedMaxKinds = 32;    // F slot kinds and G grids of the matrix-core kernel
 
 template <typename T>
 struct RedArgs {
@@ -35,6 +36,9 @@ struct RedArgs {
   int chunk;               // cells per chunk
   int64_t nchunks;
   double* partials;        // [nout_all][gridDim]
+  // matrix-core kernel: per F slot kind and per G grid, the component taking
+  // the real and the imaginary part (-1: none)
+  int kre[kRedMaxKinds], kim[kRedMaxKinds], gre[kRedMaxKinds], gim[kRedMaxKinds];
 };
 
 template <typename T>
@@ -134,18 +138,21 @@ __global__ void __launch_bounds__(kBlock) reduce_mfma_kernel(RedArgs<float> a) {
   for (int64_t ch = blockIdx.x; ch < a.nchunks; ch += gridDim.x) {
     const int64_t c0 = ch * C;
     const int nslot = a.nb * a.nkinds;
+    // one load per slot element, its parts straight to their component rows
     for (int idx = tid; idx < nslot * C; idx += kBlock) {
       const int slot = idx / C, c = idx - slot * C;
       const float2 v = a.fields[(int64_t)slot * a.M3 + c0 + c];
       const int b = slot / a.nkinds, k = slot - b * a.nkinds;
-      for (int f = 0; f < a.nfc; ++f)
-        if (a.fcomp[f].slot == k) Fv[((size_t)b * a.nfc + f) * CP + c] = a.fcomp[f].part ? v.y : v.x;
+      const int fr = a.kre[k], fi = a.kim[k];
+      if (fr >= 0) Fv[((size_t)b * a.nfc + fr) * CP + c] = v.x;
+      if (fi >= 0) Fv[((size_t)b * a.nfc + fi) * CP + c] = v.y;
     }
     for (int idx = tid; idx < a.ngrid * C; idx += kBlock) {
       const int g = idx / C, c = idx - g * C;
       const float2 v = a.fields[((int64_t)nslot + g) * a.M3 + c0 + c];
-      for (int f = 0; f < a.ngc; ++f)
-        if (a.gcomp[f].slot == g) Gv[(size_t)f * CP + c] = a.gcomp[f].part ? v.y : v.x;
+      const int fr = a.gre[g], fi = a.gim[g];
+      if (fr >= 0) Gv[(size_t)fr * CP + c] = v.x;
+      if (fi >= 0) Gv[(size_t)fi * CP + c] = v.y;
     }
     __syncthreads();
     for (int idx = tid; idx < a.nq * a.nb * C; idx += kBlock) {
@@ -253,6 +260,9 @@ int reduce_impl(Plan& P, hipStream_t s) {
   if constexpr (std::is_same<T, float>::value) {
     if (P.red_mfma > 0) {
       const size_t lds_m = std::max(lds, (size_t)a.nq * 32 * 32 * sizeof(double));
+      for (int k = 0; k < kRedMaxKinds; ++k) a.kre[k] = a.kim[k] = a.gre[k] = a.gim[k] = -1;
+      for (size_t f = 0; f < P.fcomp.size(); ++f) (P.fcomp[f].part ? a.kim : a.kre)[P.fcomp[f].slot] = (int)f;
+      for (size_t f = 0; f < P.gcomp.size(); ++f) (P.gcomp[f].part ? a.gim : a.gre)[P.gcomp[f].slot] = (int)f;
       a.out0 = 0;
       a.nout = nout_all;
       if (P.red_mfma == 1)
