@@ -394,6 +394,16 @@ int plan_build(Plan& P) {
       P.grids.size() <= 32) {
     const int upw = ((int)P.qgroups.size() + 3) / 4;
     if (upw >= 1 && upw <= 4) P.red_mfma = upw == 1 ? 1 : (upw == 2 ? 2 : 4);
+    // fewer, longer chunks: up to 96 KiB of staged rows (one workgroup per CU
+    // then; a chunk's fixed costs dominate short ones)
+    if (P.red_mfma) {
+      int Cm = 64;
+      while (Cm > 8 && per_cell * (Cm + 1) * esz > 96 * 1024) Cm /= 2;
+      if (Cm > P.red_chunk) {
+        P.red_chunk = Cm;
+        P.red_wg = (int)std::min<int64_t>((int64_t)P.M * P.M * P.M / Cm, 1024);
+      }
+    }
   }
   P.g_offset = P.fused ? 0 : (int64_t)P.nb * (int64_t)P.fkinds.size() * P.M * P.M * P.M;
   return TSB_OK;
