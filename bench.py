@@ -447,7 +447,7 @@ def main():
         return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the path shards by mock "
-              "across GPUs without communication, see DESIGN.md", file=sys.stderr)
+              "across GPUs without communication (one plan and request queue per GPU)", file=sys.stderr)
         sys.exit(2)
 
     import torch

@@ -30,7 +30,7 @@ dn(k) = sum_j e^{-ik.x_j} D_j = numpy.fft.fftn(D). Then
   int d3x -> (V/N^3) sum_x,
 so that all factors of V and N cancel in eq. 35.
 
-Readings where the paper is silent or ambiguous (listed again in the design doc):
+Readings where the paper is silent or ambiguous:
 
   R1  Bins: [k_min + b dk, k_min + (b+1) dk), membership decided once per integer
       |n|^2 as floor((k_f sqrt(n^2) - k_min)/dk) in FP64; DC (n = 0) is in no shell.
