@@ -636,10 +636,12 @@ __device__ inline void put_node(unsigned long long* w, size_t wstride, int ngrid
 // (stencil parameters and in-tile node ranges computed once per particle and
 // grid copy); then every (visit, in-tile x node) is one work item over all
 // lanes, which adds the particle's fixed-point contributions to each in-tile
-// (y, z) node of that plane and every channel. Packed FP32 tiles stage both
-// grid copies in one pass (their two-channel words of both copies fit the
-// LDS of one unpacked copy); other tiles run one copy per pass. FP32 plans
-// with up to 8 channel slots keep four workgroups per CU.
+// (y, z) node of that plane and every channel. Packed FP32 items (a whole
+// tile or a part of a split one) stage both grid copies in one pass (their
+// two-channel words of both copies fit the LDS of one unpacked copy); other
+// items run one copy per pass. Parts of split tiles add their sums into the
+// tile's slot; whole tiles write their nodes out. FP32 plans with up to 8
+// channel slots keep four workgroups per CU.
 template <typename T, int NCH>
 __global__ void __launch_bounds__(kTileBlock, (sizeof(T) == 4 && NCH <= 8) ? 4 : 1)
     assign_tile_kernel(TileArgs a, Records<T> rec) {
