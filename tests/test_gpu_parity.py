@@ -297,6 +297,24 @@ def test_assignment_edges_wrap():
     _assign_vs_oracle(box_request(n=32, precision="f64"), {"pos": pos}, 1e-12)
 
 
+def test_small_tiles_dense_fp32():
+    # 16^3: 4^3 tiles, packed whole and as the parts of split tiles; 20k
+    # particles make most tiles split
+    req = box_request(n=16, precision="f32", n_bins=3, multipoles=[(0, 0, 0), (1, 1, 0), (2, 0, 2)])
+    cat = small_cat(n=16, n_target=20000, seed=9)
+    _say("small tiles dense", len(cat["pos"]))
+    _assign_vs_oracle(req, cat, 2e-6)
+    plan, g, o = run_both(req, cat)
+    mask = pair_mask(req["multipoles"], req["n_bins"])
+    err = normwise_errors(g["B"], o["B"], mask)
+    _say("small tiles errors", err)
+    assert np.all(err <= 1e-4)
+    # order-free fixed-point sums: a shuffled catalogue gives the same bits
+    perm = np.random.default_rng(1).permutation(len(cat["pos"]))
+    b = plan.measure(tsb.catalog_to_device({"pos": cat["pos"][perm]}))["B"]
+    assert np.array_equal(np.nan_to_num(g["B"], nan=7.0), np.nan_to_num(b, nan=7.0))
+
+
 @pytest.mark.parametrize("precision,tol", [("f32", 1e-4), ("f64", 1e-9)])
 def test_radix3_grid(precision, tol):
     # 48^3 = 2^4 3: the transforms take the radix-4/2/3 passes
