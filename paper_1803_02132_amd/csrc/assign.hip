@@ -773,10 +773,9 @@ __global__ void __launch_bounds__(kTileBlock, (sizeof(T) == 4 && NCH <= 8) ? 4 :
   const int o3[3] = {tx * TS, ty * TS, tz * TS};
   int v0, v1;
   window(cb, &v0, &v1);
-  // FP32 tiles that run whole: two channels per word at the tile's own scale,
-  // both grid copies in one pass (word of copy c, grid k: c * npair + k)
-  // FP32 work items of at most kPartVisits visits pack two channels per word
-  // at a scale of their own: a whole tile (from its visits), or a part of a
+  // FP32 work items of at most kPartVisits visits pack two channels per word,
+  // both grid copies in one pass (word of copy c, grid k: c * npair + k), at
+  // a scale of their own: a whole tile (from its visits), or a part of a
   // split tile (from kPartVisits, the same for every part: which part a
   // particle falls in depends on the bucket order, its rounding must not).
   // A part converts its sums to the plan's scale, exactly, when it adds them
