@@ -321,6 +321,32 @@ def batch_leg(tsb, torch, pool, per_size, replicas=1, autotune=True):
             "batched_over_plain": round(t_plain / t_batch, 3)}
 
 
+def concurrent_leg(tsb, torch, devs, n_plans=3, n_items=48, autotune=True):
+    """The headline mocks through tsb_measure_batch with several plans of the
+    same geometry, so that consecutive mocks overlap on the device, against the
+    same measurements one by one."""
+    plans = [tsb.Plan(**WORKLOAD) for _ in range(n_plans)]
+    if autotune:
+        for p in plans:
+            p.autotune(devs[0])
+    ps = [plans[i % n_plans] for i in range(n_items)]
+    ds = [devs[i % len(devs)] for i in range(n_items)]
+    tsb.measure_batch(ps, ds)                    # warm-up: workspaces, graphs
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    tsb.measure_batch(ps, ds)
+    t_batch = time.perf_counter() - t0
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for p, d in zip(ps, ds):
+        p.measure(d)
+    t_plain = time.perf_counter() - t0
+    for p in plans:
+        p.close()
+    return {"plans": n_plans, "mocks": n_items, "batched_mocks_per_s": round(n_items / t_batch, 2),
+            "plain_mocks_per_s": round(n_items / t_plain, 2)}
+
+
 # serving requests: grids, multipoles and particle counts of the request stream
 SERVE_SIZES = (128, 192, 256, 384, 512)
 SERVE_MULTIPOLES = [(0, 0, 0), (1, 1, 0), (2, 0, 2)]
@@ -568,6 +594,10 @@ def main():
         "stage_ms": {k: round(v, 4) for k, v in per_launch.items()},
     }
     plan.close()
+    if not args.no_batch and args.workload == "box256" and args.pairs == "paper":
+        log("concurrent leg ...")
+        out["concurrent"] = concurrent_leg(tsb, torch, devs, autotune=not args.no_autotune)
+        log(f"concurrent: {out['concurrent']}")
     if not args.no_batch:
         pool = _pool(tsb, [(n, seeds) for n, seeds in BATCH_CLASSES], args.pool)
         log("batched leg ...")
