@@ -384,7 +384,15 @@ def reduce_fft(plan, spec, I, pairs=None):
     """O10 (eq. 41 / eq. 51): B[mu][b1][b2] and its imaginary part.
 
     ``pairs``: optional iterable of (b1, b2) to evaluate (others stay NaN).
-    B = Re[(N H / I) sum_{m1 m2 M} 3j(l1 l2 L; m1 m2 M) (V/N^3) sum_x F F G]."""
+    B = Re[(N H / I) sum_{m1 m2 M} 3j(l1 l2 L; m1 m2 M) (V/N^3) sum_x F F G].
+
+    Pairs are evaluated row by row (one b1 at a time): the F fields of shell
+    b1 and the products F(b1) G stay in memory while the row runs, the F
+    fields of each b2 only while that pair runs, so a full-size grid needs a
+    few dozen fields at a time. The terms of every pair are added in the
+    order of ``angular.reduction_terms``. Under a global LOS a term whose
+    weight y_L^M*(d) is exactly zero (every M != 0 for d = z) contributes
+    exactly zero and is skipped."""
     n = plan.n
     nb = plan.n_bins
     bg = bin_grid(plan)
@@ -393,16 +401,25 @@ def reduce_fft(plan, spec, I, pairs=None):
     if pairs is None:
         pairs = [(b1, b2) for b1 in range(nb) for b2 in range(nb)]
     pairs = list(pairs)
-    need_b = sorted({b for p in pairs for b in p})
-    los = "global" if plan.los == "global" else "local"
-    fcache = {}
+    dv = plan.volume / n ** 3
+    nmult = len(plan.multipoles)
+    Bre = np.full((nmult, nb, nb), np.nan)
+    Bim = np.full((nmult, nb, nb), np.nan)
 
-    def F(l, m, b):
-        key = (l, m, b)
-        if key not in fcache:
-            fcache[key] = f_field(plan, spec, l, m, b, bg, units, nm)
-        return fcache[key]
+    def los_weight(L, M):
+        if plan.los != "global":
+            return 1.0
+        d = np.asarray(plan.los_dir, np.float64)
+        d = d / np.linalg.norm(d)
+        return complex(np.conj(ang.ylm(L, M, d[0], d[1], d[2])))
 
+    # every (m1, m2, M) with m1+m2+M = 0 per multipole; under a global LOS the
+    # weight y_L^M*(d) sits inside G_L^M (R10)
+    mterms = []
+    for (l1, l2, L) in plan.multipoles:
+        terms = [t for t in ang.reduction_terms(l1, l2, L, los="local") if los_weight(L, t[2]) != 0]
+        pref = ang.n_factor(l1, l2, L) * ang.h_factor(l1, l2, L) / I
+        mterms.append((l1, l2, L, terms, pref))
     gcache = {}
 
     def G(L, M):
@@ -410,25 +427,28 @@ def reduce_fft(plan, spec, I, pairs=None):
             gcache[(L, M)] = g_field(plan, spec, L, M)
         return gcache[(L, M)]
 
-    nmult = len(plan.multipoles)
-    Bre = np.full((nmult, nb, nb), np.nan)
-    Bim = np.full((nmult, nb, nb), np.nan)
-    dv = plan.volume / n ** 3
-    for mu, (l1, l2, L) in enumerate(plan.multipoles):
-        # every (m1, m2, M) with m1+m2+M = 0; under a global LOS the weight
-        # y_L^M*(d) sits inside G_L^M (R10) and removes M != 0 for d = z
-        terms = ang.reduction_terms(l1, l2, L, los="local")
-        pref = ang.n_factor(l1, l2, L) * ang.h_factor(l1, l2, L) / I
-        acc = {p: 0j for p in pairs}
-        for (m1, m2, M, w3j) in terms:
-            g = G(L, M)
-            for b1 in sorted({p[0] for p in pairs}):
-                P = (F(l1, m1, b1) * g).ravel()
-                for b2 in sorted({p[1] for p in pairs if p[0] == b1}):
-                    acc[(b1, b2)] += w3j * dv * np.dot(P, F(l2, m2, b2).ravel())
-        for (b1, b2), v in acc.items():
-            Bre[mu, b1, b2] = (pref * v).real
-            Bim[mu, b1, b2] = (pref * v).imag
+    def shell_fields(b, cache):
+        def F(l, m):
+            if (l, m) not in cache:
+                cache[(l, m)] = f_field(plan, spec, l, m, b, bg, units, nm)
+            return cache[(l, m)]
+        return F
+
+    for b1 in sorted({p[0] for p in pairs}):
+        f1 = {}
+        F1 = shell_fields(b1, f1)
+        prod = {}   # (mu, term index) -> F_l1^m1(x; b1) G_L^M(x)
+        for b2 in sorted({p[1] for p in pairs if p[0] == b1}):
+            F2 = F1 if b2 == b1 else shell_fields(b2, {})
+            for mu, (l1, l2, L, terms, pref) in enumerate(mterms):
+                acc = 0j
+                for t, (m1, m2, M, w3j) in enumerate(terms):
+                    if (mu, t) not in prod:
+                        prod[(mu, t)] = (F1(l1, m1) * G(L, M)).ravel()
+                    acc += w3j * dv * np.dot(prod[(mu, t)], F2(l2, m2).ravel())
+                Bre[mu, b1, b2] = (pref * acc).real
+                Bim[mu, b1, b2] = (pref * acc).imag
+        del f1, prod
     return Bre, Bim
 
 

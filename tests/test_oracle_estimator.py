@@ -420,3 +420,73 @@ def test_survey_normalisation_of_a_uniform_density():
     nbar = info["alpha"] * 0.75 / vc
     assert info["alpha"] == pytest.approx(len(cat["pos"]) / (0.75 * len(rand["pos"])), rel=1e-13)
     assert info["I"] == pytest.approx(nbar ** 3 * plan.box_len ** 3, rel=1e-12)
+
+
+# ----------------------------------------------------------------------------
+# FKP weights (O1), alpha (O2) and the mean |k| of a shell
+
+
+def test_fkp_weight_hand_values():
+    # Sec. 5.2, eq. 53: w = w_c / (1 + nbar P0). With nbar P0 = 1 a weight halves,
+    # with nbar P0 = 3 it falls to a quarter, with nbar P0 = 0 it is unchanged.
+    P0 = 1024.0   # powers of two keep nbar P0 exact
+    w_c = np.array([1.0, 2.0, 0.5, 3.0])
+    nbar = np.array([1.0, 3.0, 0.0, 1.0]) / 1024.0
+    w = est.fkp_weights(w_c, nbar, P0)
+    assert np.array_equal(w, np.array([0.5, 0.5, 0.5, 1.5]))
+    # no FKP factor without nbar or with P0 <= 0 (R9)
+    assert np.array_equal(est.fkp_weights(w_c, None, P0), w_c)
+    assert np.array_equal(est.fkp_weights(w_c, nbar, 0.0), w_c)
+
+
+def test_alpha_with_fkp_weights():
+    # Sec. 4.1 with eq. 53: alpha = sum_gal w_c/(1+nbar P0) / sum_ran w_c/(1+nbar P0).
+    # Galaxies: 2 at nbar P0 = 1 (w = 1/2), 1 at nbar P0 = 3 (w = 1/4): sum 5/4.
+    # Randoms: 8 at nbar P0 = 1 (w = 1/2), 4 at nbar P0 = 0 (w = 1): sum 8.
+    P0 = 64.0
+    plan = est.Plan(n=16, box_len=100.0, multipoles=[(0, 0, 0)], n_bins=2, dk=0.1, box_mode=False,
+                    los="global", P0=P0, assign_p=1)
+    gal = {"pos": np.full((3, 3), 30.0), "w": None, "nbar": np.array([1.0, 1.0, 3.0]) / 64.0}
+    ran = {"pos": np.full((12, 3), 60.0), "w": None, "nbar": np.array([1.0] * 8 + [0.0] * 4) / 64.0}
+    _, info = est.assign_channels(plan, gal, ran)
+    assert info["sum_w"] == 1.25
+    assert info["sum_w_ran"] == 8.0
+    assert info["alpha"] == 1.25 / 8.0
+
+
+def test_k_eff_against_sum_of_three_squares():
+    # mean |k| over a shell's modes, counted by the number r3(s) of integer
+    # vectors with |n|^2 = s (an enumeration independent of the mode grid)
+    N, box = 32, 1000.0
+    kf = 2 * math.pi / box
+    plan = est.Plan(n=N, box_len=box, multipoles=[(0, 0, 0)], n_bins=6, dk=2.5 * kf, k_min=0.7 * kf)
+    r3 = _r3_counts(3 * (N // 2) ** 2)
+    got = est.k_eff(plan)
+    for b in range(6):
+        lo, hi = plan.k_min + b * plan.dk, plan.k_min + (b + 1) * plan.dk
+        num = den = 0.0
+        for s in range(1, len(r3)):
+            k = kf * math.sqrt(s)
+            if lo <= k < hi and r3[s]:
+                num += r3[s] * k
+                den += r3[s]
+        assert den == est.nmode(plan)[b]
+        assert abs(got[b] - num / den) <= 1e-13 * (num / den)
+
+
+@pytest.mark.slow
+def test_fft_route_equals_triangle_sum_c1():
+    # the 32^3 box of the smallest configuration: CIC, global z LOS, 8 shells of
+    # 2 k_f, {000, 202}, every pair of both multipoles by both routes (eq. 35 vs eq. 41)
+    plan = est.Plan(n=32, box_len=1000.0, multipoles=[(0, 0, 0), (2, 0, 2)], n_bins=8,
+                    dk=2 * 2 * math.pi / 1000.0, assign_p=2, los="global", box_mode=True)
+    cat = lognormal_box(32, 1000.0, 20000, 1, rsd="global")
+    grids, info = est.assign_channels(plan, cat)
+    spec = est.spectra(plan, grids)
+    Bf, If = est.reduce_fft(plan, spec, info["I"])
+    Bb, Ib = est.brute_force(plan, spec, info["I"])
+    for mu in range(2):
+        scale = np.nanmax(np.abs(Bb[mu]))
+        assert scale > 0
+        assert np.nanmax(np.abs(Bf[mu] - Bb[mu])) <= 1e-12 * scale
+        assert np.nanmax(np.abs(If[mu])) <= 1e-12 * scale
