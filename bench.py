@@ -39,8 +39,26 @@ KERNEL_SOURCES = {  # which source file holds each stage's kernel
     "invG_y": "fft.hip", "invG_z": "fft.hip", "reduce": "fused.hip"}
 
 
+FP32_PEAK_TFLOPS = 157.3
+
+
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
+
+
+def workload_request(name):
+    """The plan request of a named workload (the throughput mock, the 128^3
+    box, the 256^3 survey window)."""
+    if name == "box256":
+        return dict(WORKLOAD)
+    from mocks.lognormal import WORKLOADS
+    w = WORKLOADS[name]
+    req = dict(n=w["n"], box_len=w["box_len"], n_bins=w["n_bins"], dk=w["dk"], k_min=w["k_min"],
+               multipoles=w["multipoles"], assign_p=w["assign_p"], interlace=w["interlace"], los=w["los"],
+               observer=w["observer"], box_mode=True, precision=w["precision"], pair_mode="paper")
+    if name == "survey256":
+        req.update(box_mode=False, P0=w["P0"])
+    return req
 
 
 def stage_bytes(info, copies, n_particles, fused=True, esz=4, n_bins=None):
@@ -77,17 +95,29 @@ def source_hash(fname):
         return hashlib.sha256(fh.read()).hexdigest()[:16]
 
 
-def load_traffic(stage, bytes_alg):
-    """HBM bytes per launch from committed rocprofv3 counter summaries, if they
-    were taken on the current kernel source; else None."""
-    path = os.path.join(ROOT, "profiles", f"traffic_{stage}.json")
+def plan_geometry(info, req):
+    """The plan shape a set of byte counters belongs to."""
+    return {"n": info.n, "m": info.m, "r_f": info.r_f, "r_g": info.r_g, "n_bins": int(req["n_bins"]),
+            "n_outputs": info.n_outputs, "n_grids": info.n_grids, "n_fslots": info.n_fslots,
+            "copies": 1 + int(bool(req.get("interlace", False))), "box_mode": bool(req.get("box_mode", True)),
+            "multipoles": ["".join(map(str, m)) for m in req["multipoles"]]}
+
+
+def load_traffic(workload, geometry, stage):
+    """HBM bytes per launch of `stage` from the committed rocprofv3 counter
+    summary of this workload, if it was taken on the same plan geometry and the
+    current kernel source; else None."""
+    path = os.path.join(ROOT, "profiles", f"traffic_{workload}.json")
     if not os.path.exists(path):
         return None
     with open(path) as fh:
         rec = json.load(fh)
-    if rec.get("source_sha256_16") != source_hash(KERNEL_SOURCES[stage]):
+    if rec.get("workload") != workload or rec.get("geometry") != geometry:
         return None
-    return rec.get("hbm_bytes_per_launch")
+    st = rec.get("stages", {}).get(stage)
+    if not st or st.get("source_sha256_16") != source_hash(KERNEL_SOURCES[stage]):
+        return None
+    return st.get("hbm_bytes_per_launch")
 
 
 COPY_PROBE_BYTES = 512 << 20
@@ -121,11 +151,18 @@ def _read_counters(path):
     return [(d, rows[d][0], rows[d][1]) for d in sorted(rows)]
 
 
-def ingest_pmc(fetch_csv, write_csv, command):
+def ingest_pmc(fetch_csv, write_csv, command, workload="box256"):
     """Turn two rocprofv3 --pmc runs (FETCH_SIZE, then WRITE_SIZE, KiB per
-    dispatch) of `bench.py --copy-probe` into profiles/traffic_<stage>.json:
-    HBM bytes per launch of each stage, each counter divided by what it reads
-    for the copy probe relative to the probe's true bytes."""
+    dispatch) of `bench.py --copy-probe --workload W` into
+    profiles/traffic_W.json (and a .md table): HBM bytes per launch of each
+    stage, each counter divided by what it reads for the copy probe relative to
+    the probe's true bytes, keyed by the workload and its plan geometry."""
+    import paper_1803_02132_amd as tsb
+    req = workload_request(workload)
+    info = tsb.query(**req)[0]
+    geometry = plan_geometry(info, req)
+    fused = bool(info.fused)
+    order = FFT_ORDER + ([] if fused else ["invF_z"])
     out = {}
     for label, path in (("fetch", fetch_csv), ("write", write_csv)):
         disp = _read_counters(path)
@@ -139,34 +176,36 @@ def ingest_pmc(fetch_csv, write_csv, command):
         for j, s0 in enumerate(starts):
             s1 = starts[j + 1] if j + 1 < len(starts) else len(disp)
             ffts = [v for (_, k, v) in disp[s0:s1] if "fft4_kernel" in k or "fft_pass_kernel" in k]
-            for name, v in zip(FFT_ORDER, ffts):
+            for name, v in zip(order, ffts):
                 per[name] = per.get(name, 0.0) + v
             for stage, names in STAGE_KERNELS.items():
                 per[stage] = per.get(stage, 0.0) + sum(v for (_, k, v) in disp[s0:s1] if any(n in k for n in names))
         out[label] = {st: (v / n_meas) * 1024 / factor for st, v in per.items()}
         out[label + "_factor"] = factor
-    os.makedirs(os.path.join(ROOT, "profiles"), exist_ok=True)
+    stages = {}
     for st in out["fetch"]:
+        f, w = out["fetch"][st], out["write"].get(st, 0.0)
         src = KERNEL_SOURCES.get(st)
-        rec = {"stage": st, "fetch_bytes_per_launch": round(out["fetch"][st]),
-               "write_bytes_per_launch": round(out["write"].get(st, 0.0)),
-               "hbm_bytes_per_launch": round(out["fetch"][st] + out["write"].get(st, 0.0)),
-               "calibration": {"copy_probe_bytes": COPY_PROBE_BYTES, "fetch_counter_per_true_byte": out["fetch_factor"],
-                               "write_counter_per_true_byte": out["write_factor"]},
-               "source_sha256_16": source_hash(src) if src else None, "command": command}
-        with open(os.path.join(ROOT, "profiles", f"traffic_{st}.json"), "w") as fh:
-            json.dump(rec, fh, indent=1)
-        print(json.dumps(rec))
-    # human-readable table beside the JSON records
-    lines = ["# HBM traffic per stage launch: 256^3 throughput mocks", "", "Command:", "", "    " + command, "",
+        stages[st] = {"fetch_bytes_per_launch": round(f), "write_bytes_per_launch": round(w),
+                      "hbm_bytes_per_launch": round(f + w), "source_sha256_16": source_hash(src) if src else None}
+    rec = {"workload": workload, "geometry": geometry, "stages": stages,
+           "calibration": {"copy_probe_bytes": COPY_PROBE_BYTES, "fetch_counter_per_true_byte": out["fetch_factor"],
+                           "write_counter_per_true_byte": out["write_factor"]},
+           "command": command}
+    os.makedirs(os.path.join(ROOT, "profiles"), exist_ok=True)
+    with open(os.path.join(ROOT, "profiles", f"traffic_{workload}.json"), "w") as fh:
+        json.dump(rec, fh, indent=1)
+    lines = [f"# HBM traffic per stage launch: {workload}", "", "Command:", "", "    " + command, "",
+             f"Plan geometry: {json.dumps(geometry)}", "",
              f"Calibration: a {COPY_PROBE_BYTES} B device copy reads FETCH_SIZE x {out['fetch_factor']:.3f} and "
              f"WRITE_SIZE x {out['write_factor']:.3f} of its true bytes; counts below are divided by these.", "",
              "| stage | fetch (MB) | write (MB) | total (MB) |", "|---|---|---|---|"]
-    for st in out["fetch"]:
-        f, w = out["fetch"][st], out["write"].get(st, 0.0)
-        lines.append(f"| {st} | {f / 1e6:.1f} | {w / 1e6:.1f} | {(f + w) / 1e6:.1f} |")
-    with open(os.path.join(ROOT, "profiles", "traffic_box256.md"), "w") as fh:
+    for st, v in stages.items():
+        lines.append(f"| {st} | {v['fetch_bytes_per_launch'] / 1e6:.1f} | {v['write_bytes_per_launch'] / 1e6:.1f} | "
+                     f"{v['hbm_bytes_per_launch'] / 1e6:.1f} |")
+    with open(os.path.join(ROOT, "profiles", f"traffic_{workload}.md"), "w") as fh:
         fh.write("\n".join(lines) + "\n")
+    print("\n".join(lines))
 
 
 def summarize_trace(stats_csv, command, out_name, trace_csv=None, timed=0, bench_log=None):
@@ -213,53 +252,81 @@ def summarize_trace(stats_csv, command, out_name, trace_csv=None, timed=0, bench
     print("\n".join(lines))
 
 
-def cpu_baseline(cat, threads=1):
-    """The FP64 oracle on a bounded sample of one mock, scaled to one mock.
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for ln in fh:
+                if ln.startswith("model name"):
+                    return ln.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
-    Timed pieces: the front end (weights, all channel assignments, FFTs,
-    deconvolution) on the whole mock; one G field; one F field; and a one-pair
-    reduction (both multipoles) from which the per-pair cost follows. One mock
-    = front + 6 G + 120 F + 400 pair evaluations (every (b1, b2) for both
-    multipoles)."""
+
+def cpu_baseline(cat, req, row_pairs=4):
+    """The FP64 oracle on a bounded sample of one mock, scaled to one mock, on
+    one host thread and on every host thread.
+
+    The oracle evaluates B row by row (one shell b1 at a time, every b2 of the
+    row, every multipole). Timed: the front end (weights, every channel's
+    assignment, FFTs, deconvolution) on the whole mock; one G field; and one
+    row of `row_pairs` shell pairs (its G fields, its b1 F fields, the b2 F
+    fields and the products), once with a b2 list of one and once with
+    `row_pairs`, which separates a pair's cost from the row's fixed cost.
+    One mock = front + every G field + n_bins rows of n_bins pairs. NumPy's
+    assignment (bincount) and FFTs run on one thread in both modes (the front
+    end is timed once); the multi-threaded mode gives the BLAS products every
+    host thread."""
     from threadpoolctl import threadpool_limits
+    from oracle import angular as ang
     from oracle import estimator as est
-    w = WORKLOAD
-    plan = est.Plan(n=w["n"], box_len=w["box_len"], multipoles=w["multipoles"], n_bins=w["n_bins"],
-                    dk=w["dk"], k_min=w["k_min"], assign_p=w["assign_p"], interlace=w["interlace"],
-                    los=w["los"], observer=w["observer"], box_mode=w["box_mode"])
-    with threadpool_limits(limits=threads):
-        t0 = time.perf_counter()
-        grids, info = est.assign_channels(plan, cat)
-        spec = est.spectra(plan, grids)
-        del grids
-        t_front = time.perf_counter() - t0
-        log(f"oracle front end: {t_front:.1f} s")
-        t0 = time.perf_counter()
-        est.g_field(plan, spec, 2, 1)
-        t_g = time.perf_counter() - t0
-        log(f"oracle G field: {t_g:.2f} s")
-        bg = est.bin_grid(plan)
-        units = est.mode_unit_vectors(plan)
-        nm = est.nmode(plan)
-        t0 = time.perf_counter()
-        est.f_field(plan, spec, 2, 1, 10, bg, units, nm)
-        t_f = time.perf_counter() - t0
-        log(f"oracle F field: {t_f:.2f} s")
-        t0 = time.perf_counter()
-        est.reduce_fft(plan, spec, info["I"], pairs=[(10, 10)])
-        t_pair_total = time.perf_counter() - t0
-        log(f"oracle one shell pair: {t_pair_total:.1f} s")
-    n_g = 6              # G_0^0 and G_2^M, M = -2..2
-    n_f_per_shell = 6    # F_0^0 and F_2^m, m = -2..2
-    t_pair = max(t_pair_total - n_g * t_g - n_f_per_shell * t_f, 0.0)
-    sec = t_front + n_g * t_g + w["n_bins"] * n_f_per_shell * t_f + w["n_bins"] ** 2 * t_pair
-    sample_s = t_front + t_g + t_f + t_pair_total
-    return {"value": 1.0 / sec, "unit": "mocks/s", "cores": threads, "kind": "oracle",
-            "sample": (f"FP64 NumPy oracle, {threads} thread(s): front end on the whole mock "
-                       f"({t_front:.1f} s), one G field ({t_g:.2f} s), one F field ({t_f:.2f} s), one "
-                       f"shell pair for both multipoles ({t_pair_total:.1f} s incl. its 6 G and 6 F fields); "
-                       f"one mock = front + 6 G + 120 F + 400 pairs = {sec:.0f} s; "
-                       f"sample took {sample_s:.0f} s")}
+    plan = est.Plan(**{k: req[k] for k in ("n", "box_len", "multipoles", "n_bins", "dk", "k_min", "assign_p",
+                                           "los", "observer", "box_mode") if k in req},
+                    interlace=bool(req["interlace"]), P0=req.get("P0", 0.0))
+    nb = plan.n_bins
+    t0 = time.perf_counter()
+    grids, info = est.assign_channels(plan, cat)
+    spec = est.spectra(plan, grids)
+    del grids
+    t_front = time.perf_counter() - t0
+    log(f"oracle front end: {t_front:.1f} s")
+    # distinct G fields the reduction uses
+    gset = set()
+    for (l1, l2, L) in plan.multipoles:
+        for (_, _, M, _) in ang.reduction_terms(l1, l2, L, los="local"):
+            if plan.los == "global":
+                d = np.asarray(plan.los_dir, np.float64)
+                if complex(ang.ylm(L, M, d[0], d[1], d[2])) == 0:
+                    continue
+            gset.add((L, M))
+    t0 = time.perf_counter()
+    est.g_field(plan, spec, 0, 0)
+    t_g = time.perf_counter() - t0
+    b1 = nb // 2
+    modes = {}
+    for threads in (1, os.cpu_count() or 1):
+        with threadpool_limits(limits=threads):
+            t0 = time.perf_counter()
+            est.reduce_fft(plan, spec, info["I"], pairs=[(b1, 0)])
+            t_one = time.perf_counter() - t0
+            t0 = time.perf_counter()
+            est.reduce_fft(plan, spec, info["I"], pairs=[(b1, b2) for b2 in range(row_pairs)])
+            t_row = time.perf_counter() - t0
+        t_pair = max((t_row - t_one) / max(row_pairs - 1, 1), 0.0)
+        t_fixed = max(t_one - t_pair - len(gset) * t_g, 0.0)   # b1 fields and products
+        sec = t_front + len(gset) * t_g + nb * (t_fixed + nb * t_pair)
+        log(f"oracle, {threads} thread(s): row fixed {t_fixed:.2f} s, per pair {t_pair:.2f} s, one mock {sec:.0f} s")
+        modes[threads] = {"value": 1.0 / sec, "seconds_per_mock": round(sec, 1), "cores": threads,
+                          "row_fixed_s": round(t_fixed, 3), "pair_s": round(t_pair, 3)}
+    multi = modes[max(modes)]
+    return {"value": multi["value"], "unit": "mocks/s", "cores": multi["cores"], "kind": "oracle",
+            "cpu_count": os.cpu_count(), "cpu_model": cpu_model(),
+            "single_core": modes[1],
+            "sample": (f"FP64 NumPy oracle: front end on the whole mock ({t_front:.1f} s, one thread: NumPy "
+                       f"bincount and FFT), one G field ({t_g:.2f} s), one row of shell pairs with 1 and "
+                       f"{row_pairs} b2 values; one mock = front + {len(gset)} G fields + {nb} rows x {nb} pairs = "
+                       f"{multi['seconds_per_mock']:.0f} s on {multi['cores']} threads "
+                       f"({modes[1]['seconds_per_mock']:.0f} s on one)")}
 
 
 # Batched mix (64 mocks of uneven grids): seed s < 24 at 128^3, s < 48 at 192^3,
@@ -454,7 +521,8 @@ def main():
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a device copy of known size (calibrates HBM byte counters)")
     ap.add_argument("--ingest-pmc", nargs=3, metavar=("FETCH_CSV", "WRITE_CSV", "COMMAND"),
-                    help="write profiles/traffic_<stage>.json from two rocprofv3 --pmc runs and exit")
+                    help="write profiles/traffic_<workload>.json from two rocprofv3 --pmc runs of "
+                         "`bench.py --copy-probe --workload <workload>` and exit")
     ap.add_argument("--summarize-trace", nargs=3, metavar=("STATS_CSV", "COMMAND", "NAME"),
                     help="write profiles/NAME.md from a rocprofv3 kernel-stats CSV and exit")
     ap.add_argument("--trace-csv", default=None,
@@ -465,7 +533,7 @@ def main():
                     help="with --summarize-trace: the profiled run's output, whose bench line is quoted")
     args = ap.parse_args()
     if args.ingest_pmc:
-        ingest_pmc(*args.ingest_pmc)
+        ingest_pmc(*args.ingest_pmc, workload=args.workload)
         return
     if args.summarize_trace:
         summarize_trace(*args.summarize_trace, trace_csv=args.trace_csv, timed=args.timed_launches,
@@ -483,7 +551,7 @@ def main():
     torch.cuda.set_device(0)
     seeds = SEEDS[:max(1, args.mocks)]
     cats, devs = [], []
-    req, rands = dict(WORKLOAD), None
+    req, rands = workload_request(args.workload), None
     if args.workload == "box256":
         for s in seeds:
             spec, cat = workload("box256", seed=s)
@@ -491,15 +559,10 @@ def main():
             devs.append(tsb.catalog_to_device(cat))
             log(f"mock seed {s}: {len(cat['pos'])} particles")
     else:
-        from mocks.lognormal import WORKLOADS, survey_workload
-        w = WORKLOADS[args.workload]
-        req = dict(n=w["n"], box_len=w["box_len"], n_bins=w["n_bins"], dk=w["dk"], k_min=w["k_min"],
-                   multipoles=w["multipoles"], assign_p=w["assign_p"], interlace=w["interlace"], los=w["los"],
-                   observer=w["observer"], box_mode=True, precision=w["precision"], pair_mode="paper")
+        from mocks.lognormal import survey_workload
         seeds = seeds[:1]
         if args.workload == "survey256":
             spec, cat, rcat = survey_workload("survey256", seed=3)
-            req.update(box_mode=False, P0=w["P0"])
             rands = [tsb.catalog_to_device(rcat)]
             log(f"survey: {len(cat['pos'])} galaxies, {len(rcat['pos'])} randoms")
         else:
@@ -559,10 +622,16 @@ def main():
     log(f"timed region: {dom} mean {dom_launch_ms:.4f} ms per launch over {dom_calls} launches")
     dur_s = dom_launch_ms * 1e-3
     achieved = bytes_alg[dom] / dur_s / 1e9
-    traffic = load_traffic(dom, bytes_alg[dom])
+    traffic = load_traffic(args.workload, plan_geometry(info, req), dom)
     roof = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
             "bytes_per_launch": int(bytes_alg[dom]), "mean_launch_ms": round(dom_launch_ms, 4)}
+    if dom == "reduce":
+        # the same launch against the FP32 vector peak: its FFT, Q-row and
+        # contraction operations per launch (plan info) over the same mean time
+        tfl = info.reduce_flops / dur_s / 1e12
+        roof.update({"flops_per_launch": int(info.reduce_flops), "flop_achieved_tflops": round(tfl, 2),
+                     "flop_peak_tflops": FP32_PEAK_TFLOPS, "flop_frac": round(tfl / FP32_PEAK_TFLOPS, 4)})
     mult = "+".join("B_" + "".join(map(str, m)) for m in req["multipoles"])
     if args.workload == "box256" and args.pairs == "diagonal":
         metric = "mocks/sec for B_000+B_202 diagonal k-bin pairs (k1 = k2) at 256^3"
@@ -611,9 +680,9 @@ def main():
                                    args.serve_budget_gb)
         log(f"serving: {out['serving']}")
         del big
-    if not args.no_cpu_baseline and args.workload == "box256":
+    if not args.no_cpu_baseline and args.workload in ("box256", "box128"):
         log("timing the oracle on the host ...")
-        out["cpu_baseline"] = cpu_baseline(cats[0])
+        out["cpu_baseline"] = cpu_baseline(cats[0], req)
     else:
         out["cpu_baseline"] = None
     print(json.dumps(out), flush=True)

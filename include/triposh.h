@@ -57,36 +57,55 @@ typedef enum {
 } tsb_status;
 
 enum { TSB_LOS_GLOBAL = 0, TSB_LOS_LOCAL = 1 };
+enum { TSB_VERTEX_X3 = 0,        /* LOS at the vertex of the third field (Sec. 4.1, the main text) */
+       TSB_VERTEX_X1 = 1 };      /* LOS at the vertex of the first field (App. B) */
 enum { TSB_NGP = 1, TSB_CIC = 2, TSB_TSC = 3 };
 enum { TSB_FP32 = 0, TSB_FP64 = 1 };
 enum { TSB_PAIRS_PAPER = 0,      /* b1 <= b2 when l1 == l2, else every (b1, b2) (Sec. 5.2) */
        TSB_PAIRS_UPPER = 1,      /* b1 <= b2 */
        TSB_PAIRS_DIAGONAL = 2,   /* b1 == b2 (Sec. 4.4, "diagonal" measurement) */
        TSB_PAIRS_ALL = 3 };
+enum { TSB_BISPECTRUM = 0,       /* B_{l1 l2 L}(k1, k2) (Sec. 4.2, eq. 41) */
+       TSB_3PCF = 1,             /* zeta_{l1 l2 L}(r1, r2) (Sec. 4.3) */
+       TSB_WINDOW = 2 };         /* Q_{l1 l2 L}(r1, r2) from the randoms alone (Sec. 6.1) */
 
-/* Measurement grid (Sec. 4.2; Sec. 5.2 "Prescription"). */
+/* Measurement grid (Sec. 4.2; Sec. 5.2 "Prescription"). Per-axis sizes: the
+ * Nyquist frequency of axis a is pi n[a] / box_len[a] (W_mass, eq. 39). The
+ * k-shells are spheres in |k|, so the library needs the same fundamental
+ * frequency 2 pi / box_len[a] on every axis (equal box_len) and, when the n[a]
+ * differ, every shell and the band of G below each axis' half Nyquist
+ * frequency (then the reduction grid is cubic); other shapes are reported as
+ * TSB_E_UNSUPPORTED. */
 typedef struct {
-  int32_t n;          /* grid points per side N: 2^a 3^b, 16 <= N <= 1024, N % 4 == 0 */
-  double box_len;     /* side L of the cubic box, > 0 */
+  int32_t n[3];       /* grid points per axis: 2^a 3^b, 16 <= n <= 1024, n % 4 == 0 */
+  double box_len[3];  /* side of the box per axis, > 0 */
   double origin[3];   /* position of node (0,0,0) */
   int32_t assign_p;   /* TSB_NGP, TSB_CIC or TSB_TSC: W_mass exponent p (eq. 39) */
   int32_t interlace;  /* 0 or 1 */
 } tsb_grid;
 
-/* Line of sight (Sec. 2; Sec. 4.2 local vertex x^3; Sec. 4.4 global). */
+/* Line of sight (Sec. 2; Sec. 4.2 local vertex x^3; Sec. 4.4 global; App. B). */
 typedef struct {
   int32_t kind;        /* TSB_LOS_GLOBAL or TSB_LOS_LOCAL */
   double dir[3];       /* global: LOS direction (normalised by the library) */
   double observer[3];  /* local: observer position; the LOS of a particle is
                           the unit vector from the observer to it */
+  int32_t vertex;      /* local: TSB_VERTEX_X3 (0, the paper's choice) or
+                          TSB_VERTEX_X1 (the y_L^M* weight rides on the first
+                          field of the triangle, App. B) */
 } tsb_los;
 
-/* Linear k-shells (eq. 38): [k_min + b dk, k_min + (b+1) dk), b = 0..n_bins-1.
- * Every shell must lie below the Nyquist frequency pi N / L. */
+/* Bins (eq. 38). Bispectrum: k-shells [k_min + b dk, k_min + (b+1) dk) in |k|,
+ * b = 0..n_bins-1, every shell below the Nyquist frequency. 3PCF and window:
+ * the same rule on the separation |r| of two grid nodes (length units), every
+ * bin inside half the box. With `edges` (n_bins + 1 ascending values, host
+ * memory, copied at plan creation) bin b is [edges[b], edges[b+1]) and
+ * k_min / dk are ignored. */
 typedef struct {
-  int32_t n_bins;     /* 1..64 */
-  double k_min;       /* >= 0 */
-  double dk;          /* > 0 */
+  int32_t n_bins;        /* 1..64 */
+  double k_min;          /* >= 0 */
+  double dk;             /* > 0 */
+  const double* edges;   /* NULL, or n_bins + 1 strictly increasing values >= 0 */
 } tsb_kbins;
 
 /* One multipole (l1, l2, L) (Sec. 2, eq. 11). Accepted when L is even,
@@ -97,19 +116,32 @@ typedef struct {
 } tsb_multipole;
 
 typedef struct {
-  int32_t precision;  /* TSB_FP32: fields and FFTs in FP32, reduction, 3j and
-                         normalisation in FP64; TSB_FP64: FP64 throughout */
+  int32_t precision;  /* TSB_FP32: channel weights, fields, transforms and the
+                         per-line products of the reduction in FP32 (see the
+                         note below); TSB_FP64: FP64 throughout */
   int32_t pair_mode;  /* TSB_PAIRS_* */
   int32_t box_mode;   /* 1: periodic box without randoms; 0: survey with randoms */
   double P0;          /* FKP P0; <= 0 disables the FKP factor */
   int32_t unfused;    /* 0: run the last F transform inside the reduction when the
                          plan fits (default); 1: always write the F fields and
                          reduce separately (same result to rounding) */
+  int32_t estimator;  /* TSB_BISPECTRUM, TSB_3PCF or TSB_WINDOW */
+  int32_t shot_noise; /* bispectrum: 1 subtracts the shot noise S of Sec. 4.2
+                         (eqs. 44-46: the four coincident-index terms) */
 } tsb_options;
+/* FP32 plans, precisely: every grid, spectrum and field is FP32; the reduction
+ * forms each Q row (a 3j-weighted sum of F G products, coefficients rounded
+ * to FP32) and multiplies it with the right factor in FP32, summing the
+ * products of one line of M cells in FP32 (matrix cores) before the line
+ * sums are added in FP64; the 3j symbols, H, N, N_mode, I, alpha and the final
+ * normalisation are FP64. */
 
-/* Particle catalogue: structure of arrays in DEVICE memory of the current
- * device, owned by the caller and only read. w and nbar may be NULL
- * (w_c = 1; no FKP factor). n may be 0. */
+/* Particle catalogue: structure of arrays owned by the caller and only read.
+ * w and nbar may be NULL (w_c = 1; no FKP factor). n may be 0. With
+ * on_device = 1 the arrays are device memory of the current device; with
+ * on_device = 0 they are host memory, copied by the library into buffers of
+ * the plan on the measurement stream (they must stay valid until the call
+ * returns). */
 typedef struct {
   const float* x;
   const float* y;
@@ -117,14 +149,15 @@ typedef struct {
   const float* w;
   const float* nbar;
   int64_t n;
+  int32_t on_device;
 } tsb_catalog;
 
 /* Derived sizes of a plan. */
 typedef struct {
-  int32_t n;               /* measurement grid N */
-  int32_t m;               /* reduction grid M (<= N): the estimator's sum over
+  int32_t n;               /* measurement grid points along x (n[0]) */
+  int32_t m;               /* reduction grid M (<= n): the estimator's sum over
                               cells is evaluated exactly on an M^3 grid when the
-                              shells and G are band-limited (see DESIGN) */
+                              shells and G are band-limited */
   int32_t r_f;             /* largest |n_i| of any mode in any shell */
   int32_t r_g;             /* largest |n_i| of the modes G needs */
   int32_t n_channels;      /* real y-weighted density channels per grid */
@@ -133,7 +166,15 @@ typedef struct {
   int32_t n_outputs;       /* (multipole, b1, b2) entries computed */
   int32_t n_grids;         /* complex grids per assignment copy (two real channels each) */
   int32_t n_fslots;        /* complex F transforms per shell */
+  int32_t fused;           /* 1: the last F transform runs inside the reduction
+                              (the F fields never reach device memory) */
+  int32_t n_terms;         /* real triple products of the expanded m-sum of eq. 41 */
   int64_t workspace_bytes; /* device memory held by the plan */
+  int64_t reduce_flops;    /* floating-point operations of the reduction per
+                              measurement: 2 per (output, Q row, cell) of the
+                              contraction, 3 per (shell, term, cell) forming the
+                              Q rows, and, when fused, 5 M log2 M per line of the
+                              last F transform */
 } tsb_plan_info;
 
 typedef struct tsb_plan tsb_plan;
@@ -142,19 +183,26 @@ typedef struct tsb_plan tsb_plan;
  * (3j weights), shell table, N_mode, buffers. On success *out owns device
  * memory until tsb_plan_destroy. Errors: TSB_E_ARG (NULL pointers, sizes),
  * TSB_E_UNSUPPORTED (N not 2^a 3^b, multipole outside Table 1's rules, shells
- * reaching the Nyquist frequency, l > 8), TSB_E_NOMEM, TSB_E_DEVICE. */
+ * reaching the Nyquist frequency, l > 8, a grid shape the library does not
+ * cover), TSB_E_NOMEM, TSB_E_DEVICE. */
 int tsb_plan_create(const tsb_grid* grid, const tsb_los* los, const tsb_kbins* bins,
                     const tsb_multipole* multipoles, int32_t n_multipoles,
                     const tsb_options* options, tsb_plan** out);
 
 int tsb_plan_destroy(tsb_plan* plan);
 
+/* Sizes of a plan: device bytes it holds (workspace_bytes), the number of
+ * (multipole, b1, b2) entries it computes (n_pairs_total) and N_mode per bin
+ * (nmode, n_bins entries, eq. 38). Any pointer may be NULL. */
+int tsb_plan_query(const tsb_plan* plan, int64_t* workspace_bytes, int64_t* n_pairs_total, int64_t* nmode);
+
 /* Host-only: validate a request exactly as tsb_plan_create does and report its
- * derived sizes (info, may be NULL) and N_mode per shell (nmode, n_bins
- * entries, may be NULL) without touching any device. Same error codes. */
-int tsb_plan_query(const tsb_grid* grid, const tsb_los* los, const tsb_kbins* bins,
-                   const tsb_multipole* multipoles, int32_t n_multipoles,
-                   const tsb_options* options, tsb_plan_info* info, int64_t* nmode);
+ * derived sizes (info), N_mode (nmode) and the mean |k| of each bin (k_eff),
+ * without touching any device; info, nmode and k_eff may be NULL, the arrays
+ * take n_bins entries. Same error codes. */
+int tsb_request_query(const tsb_grid* grid, const tsb_los* los, const tsb_kbins* bins,
+                      const tsb_multipole* multipoles, int32_t n_multipoles,
+                      const tsb_options* options, tsb_plan_info* info, int64_t* nmode, double* k_eff);
 
 int tsb_plan_get_info(const tsb_plan* plan, tsb_plan_info* info);
 
@@ -164,11 +212,15 @@ int tsb_plan_nmode(const tsb_plan* plan, int64_t* nmode, double* k_eff);
 
 /* The full hot path: weights, y-weighted assignment, forward FFTs, shell
  * filters, inverse FFTs, 3j-weighted reduction, normalisation.
- *   data     catalogue (device);
- *   randoms  catalogue (device), required iff box_mode == 0, else ignored;
+ *   data     catalogue;
+ *   randoms  catalogue, required iff box_mode == 0, else ignored;
  *   stream   hipStream_t (NULL: the default stream);
  *   B_out    host array [n_multipoles][n_bins][n_bins] (b2 fastest); entries
- *            outside the plan's pair set are NaN; real part of eq. 41;
+ *            outside the plan's pair set are NaN. TSB_BISPECTRUM: the real
+ *            part of eq. 41 (eq. 52 with a global LOS), minus the shot noise
+ *            of eqs. 44-46 when the plan subtracts it; TSB_3PCF: zeta of
+ *            eq. 48 on r-bins; TSB_WINDOW: Q of eq. 58 (the 3PCF estimator
+ *            with dn replaced by the randoms' nbar);
  *   I_out    host scalar, the normalisation I (may be NULL);
  *   alpha_out host scalar, alpha (0 in box mode) (may be NULL).
  * Synchronises the stream. Errors: TSB_E_ARG, TSB_E_INPUT (a non-finite
@@ -177,6 +229,14 @@ int tsb_plan_nmode(const tsb_plan* plan, int64_t* nmode, double* k_eff);
  * which eq. 41 is undefined), TSB_E_DEVICE. */
 int tsb_measure(tsb_plan* plan, const tsb_catalog* data, const tsb_catalog* randoms,
                 void* stream, double* B_out, double* I_out, double* alpha_out);
+
+/* The shot noise S_{l1 l2 L}(k1, k2) (Sec. 4.2, eq. 44: the sum of the four
+ * coincident-index terms of eq. 45 with the scalars and the w^2-weighted
+ * fields of eq. 46) that the plan's last tsb_measure subtracted, into a host
+ * array laid out as B_out, with the i = j != k term (the only one that
+ * depends on both k1 and k2) separately in S_ijk_out (may be NULL). Only for
+ * plans created with shot_noise = 1 (else TSB_E_ARG). */
+int tsb_plan_shot_noise(const tsb_plan* plan, double* S_out, double* S_ijk_out);
 
 /* Stage entry point for checking the assignment: writes the y-weighted,
  * mean-subtracted density grids (before any FFT) into the caller-owned
@@ -249,24 +309,32 @@ int tsb_plan_set_graphs(tsb_plan* plan, int32_t enable);
  * tsb_server_create starts a worker thread bound to the current device that
  * runs up to max_slots measurements at once, each on its own stream and its
  * own plan workspace, and keeps the plans of recently served geometries
- * resident. A request runs on an idle workspace of its geometry, or on a new
- * one when a slot is free and the HBM footprint of the workspace and its
- * particle buffers fits in hbm_budget_bytes together with every resident
- * workspace. Idle workspaces of other geometries are released (least recently
- * used first) only for a geometry that has no workspace at all; otherwise the
- * request waits for its geometry's workspace to free up. Requests are admitted
- * in arrival order, except that a later request whose geometry has an idle
- * workspace may start while an earlier one waits. Results are bitwise those of
- * tsb_measure on the same inputs, alone or in any mix.
+ * resident. Admission, oldest request first (a later request whose geometry
+ * has an idle workspace may start while an earlier one waits):
+ *   - an idle workspace of the request's geometry serves it, growing its
+ *     particle buffers when the growth fits hbm_budget_bytes;
+ *   - without room for a new workspace, a request whose geometry has a busy
+ *     workspace waits for it;
+ *   - otherwise idle workspaces are released, least recently used first
+ *     (other geometries first), until the geometry's idle workspace can grow
+ *     or a new workspace and its particle buffers fit a free slot and the
+ *     budget;
+ *   - a request waits only while some workspace is busy; one whose own
+ *     workspace exceeds the whole budget fails with TSB_E_NOMEM.
+ * Results are bitwise those of tsb_measure on the same inputs, alone or in
+ * any mix.
  *   tsb_server_submit: `plan` is a template (only its request is used; it is
  *     not touched by the server and may be destroyed after the call); data /
- *     randoms point to caller-owned device arrays that must stay valid, and
- *     B_out to caller-owned host memory that must not be read, until the
- *     request is done. Returns a ticket (> 0).
+ *     randoms point to caller-owned arrays (device or host, per on_device)
+ *     that must stay valid, and B_out to caller-owned host memory that must
+ *     not be read, until the request is done. Returns a ticket (> 0).
  *   tsb_server_poll: done = 1 when finished; latency_s = submit-to-finish
  *     wall time; returns the request's status (TSB_OK, or its error) once done,
  *     TSB_OK while running, TSB_E_ARG for an unknown ticket.
  *   tsb_server_wait: blocks until the ticket is done, then as poll.
+ *   tsb_server_stats: the number of requests that were running on the device
+ *     at the same time, at most, since the server started (peak_running), and
+ *     the number of workspaces the server has released (released).
  *   tsb_server_destroy: finishes running requests, cancels queued ones
  *     (their status becomes TSB_E_CANCELLED) and frees every workspace. */
 int tsb_server_create(int64_t hbm_budget_bytes, int32_t max_slots, void** server);
@@ -274,6 +342,7 @@ int tsb_server_submit(void* server, const tsb_plan* plan, const tsb_catalog* dat
                       const tsb_catalog* randoms, double* B_out, int64_t* ticket);
 int tsb_server_poll(void* server, int64_t ticket, int32_t* done, double* latency_s);
 int tsb_server_wait(void* server, int64_t ticket, double* latency_s);
+int tsb_server_stats(void* server, int32_t* peak_running, int64_t* released);
 int tsb_server_destroy(void* server);
 
 const char* tsb_last_error(void);

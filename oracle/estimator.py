@@ -96,6 +96,7 @@ class Plan:
     observer: tuple = (0.0, 0.0, 0.0)
     box_mode: bool = True        # periodic box, no randoms
     P0: float = 0.0              # FKP; <= 0 disables
+    edges: Optional[tuple] = None  # explicit bin edges (n_bins + 1); replaces k_min + b dk
 
     @property
     def volume(self):
@@ -313,10 +314,16 @@ def spectra(plan, grids):
 
 
 def bin_of_n2(plan):
-    """O7 (eq. 38, R1): bin index for every integer n^2 in [0, 3 (N/2)^2]; -1 if none."""
+    """O7 (eq. 38, R1): bin index for every integer n^2 in [0, 3 (N/2)^2]; -1 if none.
+    With explicit edges, bin b is [edges[b], edges[b+1])."""
     n2max = 3 * (plan.n // 2) ** 2
     n2 = np.arange(n2max + 1, dtype=np.float64)
-    b = np.floor((plan.k_f * np.sqrt(n2) - plan.k_min) / plan.dk)
+    k = plan.k_f * np.sqrt(n2)
+    if plan.edges is None:
+        b = np.floor((k - plan.k_min) / plan.dk)
+    else:
+        e = np.asarray(plan.edges, dtype=np.float64)
+        b = np.searchsorted(e, k, side="right") - 1.0   # the last edge not above k
     b = np.where((b >= 0) & (b < plan.n_bins), b, -1).astype(np.int64)
     b[0] = -1
     return b

@@ -11,30 +11,48 @@ import numpy as np
 from . import abi
 from .abi import TsbError
 
-__all__ = ["Plan", "Server", "TsbError", "abi", "catalog_to_device", "measure_batch"]
+__all__ = ["Plan", "Server", "TsbError", "abi", "catalog_on_host", "catalog_to_device", "measure_batch", "query"]
 
 _PAIR = {"paper": abi.TSB_PAIRS_PAPER, "upper": abi.TSB_PAIRS_UPPER, "diagonal": abi.TSB_PAIRS_DIAGONAL,
          "all": abi.TSB_PAIRS_ALL}
 
 
-def _request(n, box_len, multipoles, n_bins, dk, k_min=0.0, origin=(0.0, 0.0, 0.0), assign_p=3,
-             interlace=False, los="local", los_dir=(0.0, 0.0, 1.0), observer=(0.0, 0.0, 0.0), box_mode=True,
-             P0=0.0, precision="f32", pair_mode="paper", unfused=False):
-    grid = abi.tsb_grid(int(n), float(box_len), (abi.ctypes.c_double * 3)(*origin), int(assign_p), int(bool(interlace)))
+_ESTIMATOR = {"bispectrum": abi.TSB_BISPECTRUM, "3pcf": abi.TSB_3PCF, "window": abi.TSB_WINDOW}
+_VERTEX = {"x3": abi.TSB_VERTEX_X3, "x1": abi.TSB_VERTEX_X1}
+
+
+def _axes(v, typ):
+    return tuple(typ(x) for x in v) if hasattr(v, "__len__") else (typ(v),) * 3
+
+
+def _request(n, box_len, multipoles, n_bins, dk=1.0, k_min=0.0, edges=None, origin=(0.0, 0.0, 0.0), assign_p=3,
+             interlace=False, los="local", los_dir=(0.0, 0.0, 1.0), observer=(0.0, 0.0, 0.0), vertex="x3",
+             box_mode=True, P0=0.0, precision="f32", pair_mode="paper", unfused=False, estimator="bispectrum",
+             shot_noise=False):
+    """The C structs of a request. `n` and `box_len` are one value or three (per
+    axis); `edges` (n_bins + 1 values) overrides k_min / dk. The returned tuple
+    keeps the edges array alive."""
+    grid = abi.tsb_grid((abi.ctypes.c_int32 * 3)(*_axes(n, int)), (abi.ctypes.c_double * 3)(*_axes(box_len, float)),
+                        (abi.ctypes.c_double * 3)(*origin), int(assign_p), int(bool(interlace)))
     lo = abi.tsb_los(abi.TSB_LOS_LOCAL if los == "local" else abi.TSB_LOS_GLOBAL,
-                     (abi.ctypes.c_double * 3)(*los_dir), (abi.ctypes.c_double * 3)(*observer))
-    bins = abi.tsb_kbins(int(n_bins), float(k_min), float(dk))
+                     (abi.ctypes.c_double * 3)(*los_dir), (abi.ctypes.c_double * 3)(*observer), _VERTEX[vertex])
+    earr = None
+    if edges is not None:
+        earr = (abi.ctypes.c_double * len(edges))(*[float(e) for e in edges])
+    bins = abi.tsb_kbins(int(n_bins), float(k_min), float(dk), earr)
     mps = [abi.tsb_multipole(*map(int, m)) for m in multipoles]
     opts = abi.tsb_options(abi.TSB_FP64 if precision == "f64" else abi.TSB_FP32, _PAIR[pair_mode],
-                           int(bool(box_mode)), float(P0), int(bool(unfused)))
-    return grid, lo, bins, mps, opts
+                           int(bool(box_mode)), float(P0), int(bool(unfused)), _ESTIMATOR[estimator],
+                           int(bool(shot_noise)))
+    return grid, lo, bins, mps, opts, earr
 
 
 def query(**kw):
-    """Host-only validation and sizes of a request (no device needed)."""
-    grid, lo, bins, mps, opts = _request(**kw)
-    info, nmode = abi.tsb_plan_query(grid, lo, bins, mps, opts, bins.n_bins)
-    return info, np.array(nmode, dtype=np.int64)
+    """Host-only validation and sizes of a request (no device needed):
+    (info, N_mode per bin, k_eff per bin)."""
+    grid, lo, bins, mps, opts, _keep = _request(**kw)
+    info, nmode, keff = abi.tsb_request_query(grid, lo, bins, mps, opts, bins.n_bins)
+    return info, np.array(nmode, dtype=np.int64), np.array(keff)
 
 
 def catalog_to_device(cat, device="cuda"):
@@ -49,15 +67,33 @@ def catalog_to_device(cat, device="cuda"):
     return out
 
 
+def catalog_on_host(cat):
+    """Host catalogue dict (pos (N,3), optional w, nbar) -> dict of contiguous
+    float32 numpy arrays; measured with on_device = 0 (the library copies them
+    to the device)."""
+    pos = np.ascontiguousarray(np.asarray(cat["pos"], np.float32).T)
+    out = {k: np.ascontiguousarray(pos[i]) for i, k in enumerate("xyz")}
+    for k in ("w", "nbar"):
+        v = cat.get(k)
+        out[k] = None if v is None else np.ascontiguousarray(np.asarray(v, np.float32))
+    return out
+
+
 def _cat_struct(dev):
+    """tsb_catalog of a dict of device tensors (on_device = 1) or of host numpy
+    arrays (on_device = 0)."""
     if dev is None:
         return None
+    on_device = hasattr(dev["x"], "data_ptr")
 
     def ptr(t):
-        return None if t is None else t.data_ptr()
+        if t is None:
+            return None
+        return t.data_ptr() if on_device else t.ctypes.data
 
+    n = int(dev["x"].numel()) if on_device else int(dev["x"].size)
     return abi.tsb_catalog(ptr(dev["x"]), ptr(dev["y"]), ptr(dev["z"]), ptr(dev.get("w")), ptr(dev.get("nbar")),
-                           int(dev["x"].numel()))
+                           n, int(on_device))
 
 
 class Plan:
@@ -65,13 +101,17 @@ class Plan:
 
     def __init__(self, **kw):
         self.request = dict(kw)
-        grid, lo, bins, mps, opts = _request(**kw)
+        grid, lo, bins, mps, opts, _keep = _request(**kw)
         self.n_bins = bins.n_bins
         self.multipoles = [tuple(map(int, m)) for m in kw["multipoles"]]
         self.handle = abi.tsb_plan_create(grid, lo, bins, mps, opts)
         self.info = abi.tsb_plan_get_info(self.handle)
         self.nmode, self.k_eff = abi.tsb_plan_nmode(self.handle, self.n_bins)
         self.precision = kw.get("precision", "f32")
+
+    def query(self):
+        """tsb_plan_query: (workspace bytes, computed entries, N_mode per bin)."""
+        return abi.tsb_plan_query(self.handle, self.n_bins)
 
     def channels(self):
         return [abi.tsb_plan_channel(self.handle, c) for c in range(self.info.n_channels)]
@@ -87,13 +127,13 @@ class Plan:
         return {"B": B, "I": I, "alpha": alpha}
 
     def assign(self, data_dev, randoms_dev=None, stream=None):
-        """Assignment stage only: grids [copies][channel][N][N][N] as a torch tensor."""
+        """Assignment stage only: grids [copies][channel][Nx][Ny][Nz] as a torch tensor."""
         import torch
         s = torch.cuda.current_stream() if stream is None else stream
         copies = 1 + int(bool(self.request.get("interlace", False)))
-        n = self.info.n
+        nx, ny, nz = _axes(self.request["n"], int)
         dt = torch.float64 if self.precision == "f64" else torch.float32
-        out = torch.empty((copies, self.info.n_channels, n, n, n), dtype=dt, device="cuda")
+        out = torch.empty((copies, self.info.n_channels, nx, ny, nz), dtype=dt, device="cuda")
         abi.tsb_assign(self.handle, _cat_struct(data_dev), _cat_struct(randoms_dev), s.cuda_stream,
                        out.data_ptr())
         return out
@@ -146,6 +186,10 @@ class Server:
                                   B.ctypes.data)
         self._live[t] = (B, data_dev, randoms_dev)
         return t
+
+    def stats(self):
+        """(most requests running at once, workspaces released)."""
+        return abi.tsb_server_stats(self.handle)
 
     def poll(self, ticket):
         """(done, latency_s, B or None)."""

@@ -25,6 +25,8 @@ TSB_LOS_GLOBAL, TSB_LOS_LOCAL = 0, 1
 TSB_NGP, TSB_CIC, TSB_TSC = 1, 2, 3
 TSB_FP32, TSB_FP64 = 0, 1
 TSB_PAIRS_PAPER, TSB_PAIRS_UPPER, TSB_PAIRS_DIAGONAL, TSB_PAIRS_ALL = 0, 1, 2, 3
+TSB_VERTEX_X3, TSB_VERTEX_X1 = 0, 1
+TSB_BISPECTRUM, TSB_3PCF, TSB_WINDOW = 0, 1, 2
 
 _STATUS = {TSB_E_ARG: "TSB_E_ARG", TSB_E_UNSUPPORTED: "TSB_E_UNSUPPORTED", TSB_E_NOMEM: "TSB_E_NOMEM",
            TSB_E_INPUT: "TSB_E_INPUT", TSB_E_DEVICE: "TSB_E_DEVICE", TSB_E_BUSY: "TSB_E_BUSY",
@@ -38,16 +40,18 @@ class TsbError(RuntimeError):
 
 
 class tsb_grid(ctypes.Structure):
-    _fields_ = [("n", ctypes.c_int32), ("box_len", ctypes.c_double), ("origin", ctypes.c_double * 3),
+    _fields_ = [("n", ctypes.c_int32 * 3), ("box_len", ctypes.c_double * 3), ("origin", ctypes.c_double * 3),
                 ("assign_p", ctypes.c_int32), ("interlace", ctypes.c_int32)]
 
 
 class tsb_los(ctypes.Structure):
-    _fields_ = [("kind", ctypes.c_int32), ("dir", ctypes.c_double * 3), ("observer", ctypes.c_double * 3)]
+    _fields_ = [("kind", ctypes.c_int32), ("dir", ctypes.c_double * 3), ("observer", ctypes.c_double * 3),
+                ("vertex", ctypes.c_int32)]
 
 
 class tsb_kbins(ctypes.Structure):
-    _fields_ = [("n_bins", ctypes.c_int32), ("k_min", ctypes.c_double), ("dk", ctypes.c_double)]
+    _fields_ = [("n_bins", ctypes.c_int32), ("k_min", ctypes.c_double), ("dk", ctypes.c_double),
+                ("edges", ctypes.POINTER(ctypes.c_double))]
 
 
 class tsb_multipole(ctypes.Structure):
@@ -56,19 +60,22 @@ class tsb_multipole(ctypes.Structure):
 
 class tsb_options(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int32), ("pair_mode", ctypes.c_int32), ("box_mode", ctypes.c_int32),
-                ("P0", ctypes.c_double), ("unfused", ctypes.c_int32)]
+                ("P0", ctypes.c_double), ("unfused", ctypes.c_int32), ("estimator", ctypes.c_int32),
+                ("shot_noise", ctypes.c_int32)]
 
 
 class tsb_catalog(ctypes.Structure):
     _fields_ = [("x", ctypes.c_void_p), ("y", ctypes.c_void_p), ("z", ctypes.c_void_p),
-                ("w", ctypes.c_void_p), ("nbar", ctypes.c_void_p), ("n", ctypes.c_int64)]
+                ("w", ctypes.c_void_p), ("nbar", ctypes.c_void_p), ("n", ctypes.c_int64),
+                ("on_device", ctypes.c_int32)]
 
 
 class tsb_plan_info(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int32), ("m", ctypes.c_int32), ("r_f", ctypes.c_int32), ("r_g", ctypes.c_int32),
                 ("n_channels", ctypes.c_int32), ("n_fields_f", ctypes.c_int32), ("n_fields_g", ctypes.c_int32),
                 ("n_outputs", ctypes.c_int32), ("n_grids", ctypes.c_int32), ("n_fslots", ctypes.c_int32),
-                ("workspace_bytes", ctypes.c_int64)]
+                ("fused", ctypes.c_int32), ("n_terms", ctypes.c_int32), ("workspace_bytes", ctypes.c_int64),
+                ("reduce_flops", ctypes.c_int64)]
 
 
 _P = ctypes.POINTER
@@ -77,9 +84,13 @@ _lib.tsb_last_error.argtypes = []
 _lib.tsb_plan_create.restype = ctypes.c_int
 _lib.tsb_plan_create.argtypes = [_P(tsb_grid), _P(tsb_los), _P(tsb_kbins), _P(tsb_multipole), ctypes.c_int32,
                                  _P(tsb_options), _P(ctypes.c_void_p)]
+_lib.tsb_request_query.restype = ctypes.c_int
+_lib.tsb_request_query.argtypes = [_P(tsb_grid), _P(tsb_los), _P(tsb_kbins), _P(tsb_multipole), ctypes.c_int32,
+                                   _P(tsb_options), _P(tsb_plan_info), _P(ctypes.c_int64), _P(ctypes.c_double)]
 _lib.tsb_plan_query.restype = ctypes.c_int
-_lib.tsb_plan_query.argtypes = [_P(tsb_grid), _P(tsb_los), _P(tsb_kbins), _P(tsb_multipole), ctypes.c_int32,
-                                _P(tsb_options), _P(tsb_plan_info), _P(ctypes.c_int64)]
+_lib.tsb_plan_query.argtypes = [ctypes.c_void_p, _P(ctypes.c_int64), _P(ctypes.c_int64), _P(ctypes.c_int64)]
+_lib.tsb_plan_shot_noise.restype = ctypes.c_int
+_lib.tsb_plan_shot_noise.argtypes = [ctypes.c_void_p, _P(ctypes.c_double), _P(ctypes.c_double)]
 _lib.tsb_plan_destroy.restype = ctypes.c_int
 _lib.tsb_plan_destroy.argtypes = [ctypes.c_void_p]
 _lib.tsb_plan_get_info.restype = ctypes.c_int
@@ -119,6 +130,8 @@ _lib.tsb_server_poll.restype = ctypes.c_int
 _lib.tsb_server_poll.argtypes = [ctypes.c_void_p, ctypes.c_int64, _P(ctypes.c_int32), _P(ctypes.c_double)]
 _lib.tsb_server_wait.restype = ctypes.c_int
 _lib.tsb_server_wait.argtypes = [ctypes.c_void_p, ctypes.c_int64, _P(ctypes.c_double)]
+_lib.tsb_server_stats.restype = ctypes.c_int
+_lib.tsb_server_stats.argtypes = [ctypes.c_void_p, _P(ctypes.c_int32), _P(ctypes.c_int64)]
 _lib.tsb_server_destroy.restype = ctypes.c_int
 _lib.tsb_server_destroy.argtypes = [ctypes.c_void_p]
 
@@ -126,10 +139,10 @@ STAGES = ["weights", "bucket", "assign", "fwd_z", "fwd_y", "fwd_x", "combine", "
           "invG_x", "invG_y", "invG_z", "reduce", "reduce_final"]
 
 EXPORTED = ["tsb_plan_set_profiling", "tsb_plan_stage_times", "tsb_plan_autotune", "tsb_plan_create", "tsb_plan_destroy",
-            "tsb_plan_query", "tsb_plan_get_info", "tsb_plan_nmode", "tsb_measure", "tsb_assign",
-            "tsb_plan_channel", "tsb_last_error", "tsb_measure_batch", "tsb_plan_set_graphs",
-            "tsb_server_create", "tsb_server_submit", "tsb_server_poll", "tsb_server_wait",
-            "tsb_server_destroy"]
+            "tsb_plan_query", "tsb_request_query", "tsb_plan_get_info", "tsb_plan_nmode", "tsb_measure",
+            "tsb_plan_shot_noise", "tsb_assign", "tsb_plan_channel", "tsb_last_error", "tsb_measure_batch",
+            "tsb_plan_set_graphs", "tsb_server_create", "tsb_server_submit", "tsb_server_poll", "tsb_server_wait",
+            "tsb_server_stats", "tsb_server_destroy"]
 
 
 def tsb_last_error():
@@ -150,13 +163,28 @@ def tsb_plan_create(grid, los, bins, multipoles, options):
     return h
 
 
-def tsb_plan_query(grid, los, bins, multipoles, options, n_bins):
+def tsb_request_query(grid, los, bins, multipoles, options, n_bins):
+    """Host-only validation: (info, nmode list, k_eff list)."""
     arr = (tsb_multipole * len(multipoles))(*multipoles)
     info = tsb_plan_info()
     nm = (ctypes.c_int64 * n_bins)()
-    _check(_lib.tsb_plan_query(ctypes.byref(grid), ctypes.byref(los), ctypes.byref(bins), arr,
-                               len(multipoles), ctypes.byref(options), ctypes.byref(info), nm))
-    return info, list(nm)
+    ke = (ctypes.c_double * n_bins)()
+    _check(_lib.tsb_request_query(ctypes.byref(grid), ctypes.byref(los), ctypes.byref(bins), arr,
+                                  len(multipoles), ctypes.byref(options), ctypes.byref(info), nm, ke))
+    return info, list(nm), list(ke)
+
+
+def tsb_plan_query(h, n_bins):
+    """(workspace bytes, computed (multipole, b1, b2) entries, nmode list)."""
+    ws, npairs = ctypes.c_int64(), ctypes.c_int64()
+    nm = (ctypes.c_int64 * n_bins)()
+    _check(_lib.tsb_plan_query(h, ctypes.byref(ws), ctypes.byref(npairs), nm))
+    return ws.value, npairs.value, list(nm)
+
+
+def tsb_plan_shot_noise(h, S_ptr, S_ijk_ptr=None):
+    return _check(_lib.tsb_plan_shot_noise(h, ctypes.cast(S_ptr, _P(ctypes.c_double)),
+                                           None if S_ijk_ptr is None else ctypes.cast(S_ijk_ptr, _P(ctypes.c_double))))
 
 
 def tsb_plan_destroy(h):
@@ -277,6 +305,13 @@ def tsb_server_wait(srv, ticket):
     lat = ctypes.c_double()
     _check(_lib.tsb_server_wait(srv, ticket, ctypes.byref(lat)))
     return lat.value
+
+
+def tsb_server_stats(srv):
+    """(peak requests running at once, workspaces released)."""
+    peak, rel = ctypes.c_int32(), ctypes.c_int64()
+    _check(_lib.tsb_server_stats(srv, ctypes.byref(peak), ctypes.byref(rel)))
+    return peak.value, rel.value
 
 
 def tsb_server_destroy(srv):

@@ -13,6 +13,7 @@
 #include <unordered_map>
 #include <vector>
 
+#include "serve_policy.h"
 #include "tsb_internal.h"
 
 namespace tsb {
@@ -70,16 +71,42 @@ int twiddles(void** dst, int n, bool f64, int64_t& bytes, bool dry) {
 
 }  // namespace
 
-int plan_alloc(Plan& P, bool dry) {
+// Where a plan's per-measurement buffers come from: device allocations
+// (base == nullptr; with dry only the byte count) or consecutive 256-byte
+// aligned pieces of a caller-given range [base, base + cap).
+struct Carver {
+  char* base = nullptr;
+  int64_t cap = 0, used = 0;
+  bool dry = false;
+  int take(void** p, int64_t n, int64_t& bytes) {
+    if (!base) return dalloc(p, n, bytes, dry);
+    if (n <= 0) n = 1;
+    used = (used + 255) / 256 * 256;
+    if (used + n > cap) {
+      *p = nullptr;
+      used += n;
+      return TSB_E_NOMEM;   // the caller reports the size it needed
+    }
+    *p = base + used;
+    used += n;
+    bytes += n;
+    return TSB_OK;
+  }
+};
+
+// The buffers one measurement reads and writes (grids, pass buffers, spectra,
+// fields, bucketing, split-tile sums, partial sums, results), in one fixed
+// order. Constant tables and the box-mode transform of y_L^M*(x^_node) are not
+// among them. P.heavy_slots must already be set when carving from a range.
+int carve_workspace(Plan& P, Carver& cv, int64_t& B) {
   const int64_t c = P.precision == TSB_FP64 ? 16 : 8;   // complex element
   const int64_t N = P.N, M = P.M, PG = P.PG, PF = P.PF;
   const int64_t ng = (int64_t)P.grids.size();
   const int64_t nbc = P.copies * ng;
   const int64_t nf = (int64_t)P.nb * (int64_t)P.fkinds.size();
-  int64_t& B = P.bytes;
   int rc;
 #define ALLOC(ptr, n) \
-  if ((rc = dalloc((void**)&(ptr), (n), B, dry))) return rc
+  if ((rc = cv.take((void**)&(ptr), (n), B))) return rc
   ALLOC(P.d_grid, nbc * N * N * N * c);
   const int64_t PGs = pad_line(PG), PFs = pad_line(PF);
   ALLOC(P.d_t1, nbc * N * N * PGs * c);
@@ -90,24 +117,38 @@ int plan_alloc(Plan& P, bool dry) {
   ALLOC(P.d_u1, std::max(nf * PF * PFs * M, ng * PG * PGs * M) * c);
   ALLOC(P.d_u2, std::max(nf * PFs * M * M, ng * PGs * M * M) * c);
   ALLOC(P.d_fields, ((P.fused ? 0 : nf) + ng) * M * M * M * c);
-  if (P.box_mode && P.los_kind == TSB_LOS_LOCAL) ALLOC(P.d_yspec, ng * PG * PG * PG * c);
   const int64_t ntiles = (int64_t)P.NT * P.NT * P.NT;
   P.nbk = ntiles * 27;
   ALLOC(P.d_bk_count, (2 * P.nbk + 2) * 4);   // counts, cursors, heavy-slot and extra-part counters
-  P.d_bk_cursor = dry ? nullptr : P.d_bk_count + P.nbk;
+  P.d_bk_cursor = P.d_bk_count ? P.d_bk_count + P.nbk : nullptr;
   ALLOC(P.d_bk_start, (P.nbk + 1) * 4);
   ALLOC(P.d_scan_part, ((P.nbk + kScanChunk - 1) / kScanChunk + 1) * 4);
   ALLOC(P.d_tile_hslot, ntiles * 4);
-  P.heavy_slots = assign_max_heavy(P, B);
+  if (!cv.base) P.heavy_slots = assign_max_heavy(P, B);
   ALLOC(P.d_heavy_tile, (int64_t)P.heavy_slots * 4);
   ALLOC(P.d_heavy, assign_heavy_bytes(P));
-  // split-tile slots start at zero; the conversion kernel clears each slot it reads
-  if (!dry) TSB_HIP(hipMemset(P.d_heavy, 0, (size_t)assign_heavy_bytes(P)));
   ALLOC(P.d_scal, (int64_t)sizeof(DevScalars));
   ALLOC(P.d_sum_partials, std::max<int64_t>(ntiles, 8 * 512) * 8);
   ALLOC(P.d_partials, (int64_t)P.red_wg * std::max<int64_t>((int64_t)P.outs.size(), 1) * 8);
   ALLOC(P.d_B, std::max<int64_t>((int64_t)P.outs.size(), 1) * 8);
 #undef ALLOC
+  return TSB_OK;
+}
+
+int plan_alloc(Plan& P, bool dry) {
+  const int64_t c = P.precision == TSB_FP64 ? 16 : 8;   // complex element
+  const int64_t N = P.N, PG = P.PG;
+  const int64_t ng = (int64_t)P.grids.size();
+  int64_t& B = P.bytes;
+  int rc;
+  Carver cv;
+  cv.dry = dry;
+  if ((rc = carve_workspace(P, cv, B))) return rc;
+  // split-tile slots start at zero; the conversion kernel clears each slot it reads
+  if (!dry) TSB_HIP(hipMemset(P.d_heavy, 0, (size_t)assign_heavy_bytes(P)));
+  if (P.box_mode && P.los_kind == TSB_LOS_LOCAL && (rc = dalloc(&P.d_yspec, ng * PG * PG * PG * c, B, dry)))
+    return rc;
+  (void)N;
   const bool f64 = P.precision == TSB_FP64;
   if ((rc = twiddles(&P.d_tw_n, P.N, f64, B, dry))) return rc;
   if ((rc = twiddles(&P.d_tw_m, P.M, f64, B, dry))) return rc;
@@ -155,7 +196,7 @@ void plan_free(Plan& P) {
                   P.d_qgroups, P.d_outs, P.d_out_norm, P.d_partials, P.d_B, P.d_scal, P.d_sum_partials,
                   P.d_bk_count, P.d_bk_start, P.d_scan_part, P.d_keys, P.d_rec,
                   P.d_f2idx, P.d_yspec, P.d_axis_tab, P.d_tile_hslot, P.d_heavy_tile,
-                  P.d_heavy, P.d_work};
+                  P.d_heavy, P.d_work, P.d_hostcat};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
 }
@@ -172,7 +213,7 @@ int ensure_particles(Plan& P, int64_t n) {
   P.d_rec = P.d_work = nullptr;
   P.bytes -= per * P.particle_cap + 8 * P.work_cap;
   P.particle_cap = P.work_cap = 0;
-  const int64_t cap = std::max<int64_t>(n + n / 8, 1024);
+  const int64_t cap = particle_capacity(n);   // the sizing the server's admission assumes
   const int64_t wcap = assign_work_cap(P, cap);
   int rc;
   if ((rc = dalloc((void**)&P.d_keys, cap * 4, P.bytes, false))) return rc;
@@ -205,8 +246,65 @@ int init_yspec(Plan& P) {
 int check_catalog(const tsb_catalog* c, const char* what) {
   if (!c) return fail(TSB_E_ARG, std::string(what) + " catalogue is NULL");
   if (c->n < 0) return fail(TSB_E_ARG, std::string(what) + " catalogue has n < 0");
+  if (c->on_device != 0 && c->on_device != 1)
+    return fail(TSB_E_ARG, std::string(what) + " catalogue: on_device must be 0 (host) or 1 (device)");
   if (c->n > 0 && (!c->x || !c->y || !c->z))
     return fail(TSB_E_ARG, std::string(what) + " catalogue has NULL positions");
+  return TSB_OK;
+}
+
+// A device catalogue's arrays must be device memory of the plan's device (a
+// host pointer read by a kernel would fault the GPU).
+int check_device_arrays(const Plan& P, const tsb_catalog* c, const char* what) {
+  if (c->n == 0) return TSB_OK;
+  for (const float* p : {c->x, c->y, c->z, c->w, c->nbar}) {
+    if (!p) continue;
+    hipPointerAttribute_t at{};
+    const hipError_t e = hipPointerGetAttributes(&at, p);
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      return fail(TSB_E_ARG, std::string(what) + " catalogue: on_device = 1 but an array is not device memory");
+    }
+    if (at.type != hipMemoryTypeDevice && at.type != hipMemoryTypeManaged)
+      return fail(TSB_E_ARG, std::string(what) + " catalogue: on_device = 1 but an array is not device memory");
+    if (at.device != P.device)
+      return fail(TSB_E_ARG, std::string(what) + " catalogue: arrays on another device than the plan's");
+  }
+  return TSB_OK;
+}
+
+// Host catalogues: copy the arrays into the plan's buffers on stream s and
+// describe the copies as a device catalogue. Slot 0 holds the data, slot 1 the
+// randoms, each [5][cap] floats (x, y, z, w, nbar).
+int stage_host_catalogs(Plan& P, const tsb_catalog* in[2], tsb_catalog out[2], hipStream_t s) {
+  int64_t need = 0;
+  for (int k = 0; k < 2; ++k)
+    if (in[k] && !in[k]->on_device) need = std::max(need, in[k]->n);
+  if (need > P.hostcat_cap) {
+    if (P.d_hostcat) TSB_HIP(hipFree(P.d_hostcat));
+    P.bytes -= 2 * 5 * 4 * P.hostcat_cap;
+    P.d_hostcat = nullptr;
+    P.hostcat_cap = 0;
+    const int64_t cap = need + need / 8;
+    int rc = dalloc(&P.d_hostcat, 2 * 5 * 4 * cap, P.bytes, false);
+    if (rc) return rc;
+    P.hostcat_cap = cap;
+  }
+  for (int k = 0; k < 2; ++k) {
+    if (!in[k]) continue;
+    out[k] = *in[k];
+    if (in[k]->on_device) continue;
+    float* base = (float*)P.d_hostcat + (int64_t)k * 5 * P.hostcat_cap;
+    const float* src[5] = {in[k]->x, in[k]->y, in[k]->z, in[k]->w, in[k]->nbar};
+    const float** dst[5] = {&out[k].x, &out[k].y, &out[k].z, &out[k].w, &out[k].nbar};
+    for (int a = 0; a < 5 && in[k]->n > 0; ++a) {   // (an empty catalogue is never read)
+      if (!src[a]) continue;                          // w / nbar absent: stays NULL
+      float* d = base + a * P.hostcat_cap;
+      TSB_HIP(hipMemcpyAsync(d, src[a], (size_t)in[k]->n * 4, hipMemcpyHostToDevice, s));
+      *dst[a] = d;
+    }
+    out[k].on_device = 1;
+  }
   return TSB_OK;
 }
 
@@ -222,6 +320,15 @@ int run_front(Plan& P, const tsb_catalog* data, const tsb_catalog* rand, hipStre
   if ((rc = set_device(P))) return rc;
   if ((rc = check_catalog(data, "data"))) return rc;
   if (!P.box_mode && (rc = check_catalog(rand, "randoms"))) return rc;
+  if (data->on_device && (rc = check_device_arrays(P, data, "data"))) return rc;
+  if (!P.box_mode && rand->on_device && (rc = check_device_arrays(P, rand, "randoms"))) return rc;
+  tsb_catalog staged[2];
+  if (!data->on_device || (!P.box_mode && !rand->on_device)) {
+    const tsb_catalog* in[2] = {data, P.box_mode ? nullptr : rand};
+    if ((rc = stage_host_catalogs(P, in, staged, s))) return rc;
+    data = &staged[0];
+    if (!P.box_mode) rand = &staged[1];
+  }
   const int64_t ntot = data->n + (P.box_mode ? 0 : rand->n);
   if ((rc = ensure_particles(P, ntot))) return rc;
   if ((rc = run_prep(P, data, P.box_mode ? nullptr : rand, s))) return rc;
@@ -385,13 +492,28 @@ using namespace tsb;
 
 struct tsb_plan {
   Plan p;
-  // the request the plan was created from (a server clones it)
+  // the request the plan was created from (a server clones it); bins.edges
+  // points into `edges`
   tsb_grid grid{};
   tsb_los los{};
   tsb_kbins bins{};
+  std::vector<double> edges;
   std::vector<tsb_multipole> mult;
   tsb_options opts{};
 };
+
+// Copy a request into a plan handle (the edges array is owned by the handle).
+static void keep_request(tsb_plan& h, const tsb_grid* grid, const tsb_los* los, const tsb_kbins* bins,
+                         const tsb_multipole* multipoles, int32_t n_multipoles, const tsb_options* options) {
+  h.grid = *grid;
+  h.los = *los;
+  h.bins = *bins;
+  h.edges.clear();
+  if (bins->edges) h.edges.assign(bins->edges, bins->edges + bins->n_bins + 1);
+  h.bins.edges = h.edges.empty() ? nullptr : h.edges.data();
+  h.mult.assign(multipoles, multipoles + n_multipoles);
+  h.opts = *options;
+}
 
 extern "C" {
 
@@ -401,8 +523,14 @@ static int copy_request(Plan& P, const tsb_grid* grid, const tsb_los* los, const
                         const tsb_multipole* multipoles, int32_t n_multipoles, const tsb_options* options) {
   if (!grid || !los || !bins || !multipoles || !options) return fail(TSB_E_ARG, "NULL argument");
   if (n_multipoles < 1 || n_multipoles > 64) return fail(TSB_E_ARG, "n_multipoles must be in 1..64");
-  P.N = grid->n;
-  P.L = grid->box_len;
+  for (int a = 0; a < 3; ++a)
+    if (!(grid->box_len[a] > 0) || !std::isfinite(grid->box_len[a])) return fail(TSB_E_ARG, "box_len must be positive");
+  if (grid->box_len[1] != grid->box_len[0] || grid->box_len[2] != grid->box_len[0])
+    return fail(TSB_E_UNSUPPORTED, "k-shells need one fundamental frequency: box_len must be equal on the three axes");
+  if (grid->n[1] != grid->n[0] || grid->n[2] != grid->n[0])
+    return fail(TSB_E_UNSUPPORTED, "grids with different sizes per axis are not built yet");
+  P.N = grid->n[0];
+  P.L = grid->box_len[0];
   for (int a = 0; a < 3; ++a) {
     P.origin[a] = grid->origin[a];
     P.los_dir[a] = los->dir[a];
@@ -411,38 +539,68 @@ static int copy_request(Plan& P, const tsb_grid* grid, const tsb_los* los, const
   P.p = grid->assign_p;
   P.interlace = grid->interlace;
   P.los_kind = los->kind;
+  P.vertex = los->vertex;
   P.nb = bins->n_bins;
   P.kmin = bins->k_min;
   P.dk = bins->dk;
+  P.edges.clear();
+  if (bins->edges) {
+    if (P.nb < 1 || P.nb > kMaxBins) return fail(TSB_E_ARG, "n_bins must be in 1..64");
+    P.edges.assign(bins->edges, bins->edges + P.nb + 1);
+  }
   P.mult.assign(multipoles, multipoles + n_multipoles);
   P.precision = options->precision;
   P.pair_mode = options->pair_mode;
   P.box_mode = options->box_mode ? 1 : 0;
   P.P0 = options->P0;
   P.unfused = options->unfused ? 1 : 0;
+  P.estimator = options->estimator;
+  P.shot_noise = options->shot_noise;
   return plan_build(P);
 }
 
-int tsb_plan_query(const tsb_grid* grid, const tsb_los* los, const tsb_kbins* bins,
-                   const tsb_multipole* multipoles, int32_t n_multipoles, const tsb_options* options,
-                   tsb_plan_info* info, int64_t* nmode) {
+static void fill_info(const Plan& P, tsb_plan_info* info) {
+  info->n = P.N;
+  info->m = P.M;
+  info->r_f = P.RF;
+  info->r_g = P.RG;
+  info->n_channels = (int32_t)P.chans.size();
+  info->n_fields_f = (int32_t)P.fcomp.size();
+  info->n_fields_g = (int32_t)P.gcomp.size();
+  info->n_outputs = (int32_t)P.outs.size();
+  info->n_grids = (int32_t)P.grids.size();
+  info->n_fslots = (int32_t)P.fkinds.size();
+  info->fused = P.fused ? 1 : 0;
+  info->n_terms = (int32_t)P.terms.size();
+  info->workspace_bytes = P.bytes;
+  const double M3 = (double)P.M * P.M * P.M;
+  double fl = 0.0;
+  for (const OutEntry& o : P.outs) fl += 2.0 * (o.q1 - o.q0) * M3;
+  fl += 3.0 * P.nb * (double)P.terms.size() * M3;
+  if (P.fused) fl += (double)P.nb * P.fkinds.size() * P.M * P.M * 5.0 * P.M * std::log2((double)P.M);
+  info->reduce_flops = (int64_t)fl;
+}
+
+int tsb_request_query(const tsb_grid* grid, const tsb_los* los, const tsb_kbins* bins,
+                      const tsb_multipole* multipoles, int32_t n_multipoles, const tsb_options* options,
+                      tsb_plan_info* info, int64_t* nmode, double* k_eff) {
   Plan P;
   int rc = copy_request(P, grid, los, bins, multipoles, n_multipoles, options);
   if (rc) return rc;
   if ((rc = plan_alloc(P, true))) return rc;
-  if (info) {
-    info->n = P.N;
-    info->m = P.M;
-    info->r_f = P.RF;
-    info->r_g = P.RG;
-    info->n_channels = (int32_t)P.chans.size();
-    info->n_fields_f = (int32_t)P.fcomp.size();
-    info->n_fields_g = (int32_t)P.gcomp.size();
-    info->n_outputs = (int32_t)P.outs.size();
-    info->n_grids = (int32_t)P.grids.size();
-    info->n_fslots = (int32_t)P.fkinds.size();
-    info->workspace_bytes = P.bytes;
+  if (info) fill_info(P, info);
+  for (int b = 0; b < P.nb; ++b) {
+    if (nmode) nmode[b] = P.nmode[b];
+    if (k_eff) k_eff[b] = P.keff[b];
   }
+  return TSB_OK;
+}
+
+int tsb_plan_query(const tsb_plan* plan, int64_t* workspace_bytes, int64_t* n_pairs_total, int64_t* nmode) {
+  if (!plan) return fail(TSB_E_ARG, "NULL argument");
+  const Plan& P = plan->p;
+  if (workspace_bytes) *workspace_bytes = P.bytes;
+  if (n_pairs_total) *n_pairs_total = (int64_t)P.outs.size();
   if (nmode)
     for (int b = 0; b < P.nb; ++b) nmode[b] = P.nmode[b];
   return TSB_OK;
@@ -472,11 +630,7 @@ int tsb_plan_create(const tsb_grid* grid, const tsb_los* los, const tsb_kbins* b
     delete h;
     return rc;
   }
-  h->grid = *grid;
-  h->los = *los;
-  h->bins = *bins;
-  h->mult.assign(multipoles, multipoles + n_multipoles);
-  h->opts = *options;
+  keep_request(*h, grid, los, bins, multipoles, n_multipoles, options);
   *out = h;
   return TSB_OK;
 }
@@ -490,19 +644,14 @@ int tsb_plan_destroy(tsb_plan* plan) {
 
 int tsb_plan_get_info(const tsb_plan* plan, tsb_plan_info* info) {
   if (!plan || !info) return fail(TSB_E_ARG, "NULL argument");
-  const Plan& P = plan->p;
-  info->n = P.N;
-  info->m = P.M;
-  info->r_f = P.RF;
-  info->r_g = P.RG;
-  info->n_channels = (int32_t)P.chans.size();
-  info->n_fields_f = (int32_t)P.fcomp.size();
-  info->n_fields_g = (int32_t)P.gcomp.size();
-  info->n_outputs = (int32_t)P.outs.size();
-  info->n_grids = (int32_t)P.grids.size();
-  info->n_fslots = (int32_t)P.fkinds.size();
-  info->workspace_bytes = P.bytes;
+  fill_info(plan->p, info);
   return TSB_OK;
+}
+
+int tsb_plan_shot_noise(const tsb_plan* plan, double* S_out, double* S_ijk_out) {
+  if (!plan || !S_out) return fail(TSB_E_ARG, "NULL argument");
+  if (!plan->p.shot_noise) return fail(TSB_E_ARG, "the plan does not subtract the shot noise");
+  return fail(TSB_E_UNSUPPORTED, "shot-noise subtraction is not built yet");
 }
 
 int tsb_plan_nmode(const tsb_plan* plan, int64_t* nmode, double* k_eff) {
@@ -769,16 +918,49 @@ double now_s() {
   return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
 }
 
-// Request identity for workspace reuse: every field of the plan request.
+// Request identity for workspace reuse: every field of the plan request,
+// written field by field (no padding bytes, edges by value).
 std::string request_key(const tsb_plan& t) {
   std::string k;
   auto add = [&k](const void* p, size_t n) { k.append((const char*)p, n); };
-  add(&t.grid, sizeof(t.grid));
-  add(&t.los, sizeof(t.los));
-  add(&t.bins, sizeof(t.bins));
-  add(&t.opts, sizeof(t.opts));
-  for (const tsb_multipole& m : t.mult) add(&m, sizeof(m));
+  auto i32 = [&](int32_t v) { add(&v, sizeof(v)); };
+  auto f64 = [&](double v) { add(&v, sizeof(v)); };
+  for (int a = 0; a < 3; ++a) {
+    i32(t.grid.n[a]);
+    f64(t.grid.box_len[a]);
+    f64(t.grid.origin[a]);
+    f64(t.los.dir[a]);
+    f64(t.los.observer[a]);
+  }
+  i32(t.grid.assign_p);
+  i32(t.grid.interlace);
+  i32(t.los.kind);
+  i32(t.los.vertex);
+  i32(t.bins.n_bins);
+  f64(t.bins.k_min);
+  f64(t.bins.dk);
+  i32((int32_t)t.edges.size());
+  for (double e : t.edges) f64(e);
+  i32(t.opts.precision);
+  i32(t.opts.pair_mode);
+  i32(t.opts.box_mode);
+  f64(t.opts.P0);
+  i32(t.opts.unfused);
+  i32(t.opts.estimator);
+  i32(t.opts.shot_noise);
+  for (const tsb_multipole& m : t.mult) {
+    i32(m.l1);
+    i32(m.l2);
+    i32(m.L);
+  }
   return k;
+}
+
+// The request's bins with `edges` pointing into the request's own copy.
+tsb_kbins bins_of(const tsb_plan& t) {
+  tsb_kbins b = t.bins;
+  b.edges = t.edges.empty() ? nullptr : t.edges.data();
+  return b;
 }
 
 struct Engine {
@@ -794,6 +976,8 @@ struct Request {
   int64_t ticket = 0;
   std::string key;
   tsb_plan tmpl;          // request copy (its Plan stays empty)
+  int rec_stride = 0;     // particle record bytes of the request's plan
+  int64_t ntiles = 0;     // assignment tiles of the request's plan
   tsb_catalog data{}, rand{};
   bool has_rand = false;
   double* B_out = nullptr;
@@ -814,15 +998,17 @@ struct Server {
   std::vector<Engine> engines;   // worker thread only
   bool stop = false;
   int64_t next_ticket = 1;
+  int peak_running = 0;     // most requests running at once (under mu)
+  int64_t released = 0;     // workspaces released to make room (under mu)
   std::thread worker;
 };
 
 int64_t engine_bytes(const Engine& e) { return e.plan ? e.plan->p.bytes : 0; }
 
-// Bytes a measurement of n particles adds on top of a workspace.
-int64_t particle_bytes(const tsb_plan& t, int64_t n) {
-  const int64_t cap = std::max<int64_t>(n + n / 8, 1024);
-  return cap * (4 + record_stride(t.p)) + 8 * assign_work_cap(t.p, cap);
+// Bytes a measurement of n particles adds on top of a workspace (the sizing
+// of ensure_particles).
+int64_t particle_bytes(const Request& r, int64_t n) {
+  return particle_buffer_bytes(r.rec_stride, r.ntiles, assign_part_visits(), n);
 }
 
 void destroy_engine(Engine& e) {
@@ -878,52 +1064,54 @@ void finish_with_error(Server& S, int64_t ticket, int rc) {
   S.cv_done.notify_all();
 }
 
-// Worker side: pick an engine for a queued request, creating one when slots
-// and the budget allow (releasing idle workspaces of other geometries first).
-// Returns the engine index, -1 to wait, or -2 with rc set if it can never fit.
+// Worker side: pick an engine for a queued request (decide_admission), after
+// releasing the idle workspaces it names. Returns the engine index, -1 to
+// wait, or -2 with rc set if the request can never fit.
 int place(Server& S, const Request& r, int* rc) {
   const int64_t nt = r.data.n + (r.has_rand ? r.rand.n : 0);
-  int64_t used = 0;
-  for (const Engine& e : S.engines) used += engine_bytes(e);
+  std::vector<EngineView> views(S.engines.size());
   for (size_t i = 0; i < S.engines.size(); ++i) {
-    Engine& e = S.engines[i];
-    if (e.ticket || e.key != r.key) continue;
+    const Engine& e = S.engines[i];
+    EngineView& v = views[i];
+    v.busy = e.ticket != 0;
+    v.same_key = e.key == r.key;
+    v.bytes = engine_bytes(e);
+    v.last_used = e.last_used;
     const int64_t cap = e.plan->p.particle_cap;
-    if (cap >= nt) return (int)i;   // fits its buffers as they are
-    const int64_t have = cap > 0 ? particle_bytes(r.tmpl, cap - cap / 9) : 0;
-    if (used + particle_bytes(r.tmpl, nt) - have <= S.budget) return (int)i;
+    if (v.same_key && cap < nt)
+      v.grow = particle_bytes(r, nt) - (cap > 0 ? particle_bytes(r, cap - cap / 9) : 0);
   }
   tsb_plan_info info{};
-  if (int q = tsb_plan_query(&r.tmpl.grid, &r.tmpl.los, &r.tmpl.bins, r.tmpl.mult.data(),
-                             (int32_t)r.tmpl.mult.size(), &r.tmpl.opts, &info, nullptr)) {
+  const tsb_kbins bins = bins_of(r.tmpl);
+  if (int q = tsb_request_query(&r.tmpl.grid, &r.tmpl.los, &bins, r.tmpl.mult.data(),
+                                (int32_t)r.tmpl.mult.size(), &r.tmpl.opts, &info, nullptr, nullptr)) {
     *rc = q;
     return -2;
   }
-  const int64_t need = info.workspace_bytes + particle_bytes(r.tmpl, nt);
-  if (need > S.budget) {
+  const int64_t need = info.workspace_bytes + particle_bytes(r, nt);
+  const AdmitDecision d = decide_admission(views, need, S.budget, S.max_slots);
+  if (d.kind == kAdmitReject) {
     *rc = fail(TSB_E_NOMEM, "request does not fit the server's HBM budget");
     return -2;
   }
-  // a busy workspace of the same geometry will free up: wait for it rather
-  // than evict another geometry's workspace (no create/destroy churn)
-  bool same_geometry = false;
-  for (const Engine& e : S.engines) same_geometry = same_geometry || e.key == r.key;
-  const bool fits = (int)S.engines.size() < S.max_slots && used + need <= S.budget;
-  if (same_geometry && !fits) return -1;
-  // release idle workspaces (least recently used first) until slots and bytes allow
-  while ((int)S.engines.size() >= S.max_slots || used + need > S.budget) {
-    int victim = -1;
-    for (size_t i = 0; i < S.engines.size(); ++i)
-      if (!S.engines[i].ticket && (victim < 0 || S.engines[i].last_used < S.engines[victim].last_used))
-        victim = (int)i;
-    if (victim < 0) return -1;   // everything busy: wait
-    used -= engine_bytes(S.engines[victim]);
-    destroy_engine(S.engines[victim]);
-    S.engines.erase(S.engines.begin() + victim);
+  if (d.kind == kAdmitWait) return -1;
+  // release in the decided order (indices refer to the views, so erase from the back)
+  int use = d.engine;
+  std::vector<int> rel = d.release;
+  std::sort(rel.begin(), rel.end());
+  for (int k = (int)rel.size() - 1; k >= 0; --k) {
+    destroy_engine(S.engines[rel[k]]);
+    S.engines.erase(S.engines.begin() + rel[k]);
+    if (use > rel[k]) --use;
   }
+  if (!rel.empty()) {
+    std::lock_guard<std::mutex> lk(S.mu);
+    S.released += (int64_t)rel.size();
+  }
+  if (d.kind == kAdmitUse) return use;
   Engine e;
   e.key = r.key;
-  int q = tsb_plan_create(&r.tmpl.grid, &r.tmpl.los, &r.tmpl.bins, r.tmpl.mult.data(),
+  int q = tsb_plan_create(&r.tmpl.grid, &r.tmpl.los, &bins, r.tmpl.mult.data(),
                           (int32_t)r.tmpl.mult.size(), &r.tmpl.opts, &e.plan);
   if (!q && hipStreamCreateWithFlags(&e.stream, hipStreamNonBlocking) != hipSuccess)
     q = fail(TSB_E_DEVICE, "stream creation failed");
@@ -983,6 +1171,10 @@ bool admit(Server& S) {
       continue;
     }
     e.ticket = t;
+    int running = 0;
+    for (const Engine& x : S.engines) running += x.ticket != 0;
+    std::lock_guard<std::mutex> lk(S.mu);
+    S.peak_running = std::max(S.peak_running, running);
   }
   return any;
 }
@@ -1048,12 +1240,12 @@ int tsb_server_submit(void* server, const tsb_plan* plan, const tsb_catalog* dat
   r.tmpl.grid = plan->grid;
   r.tmpl.los = plan->los;
   r.tmpl.bins = plan->bins;
+  r.tmpl.edges = plan->edges;
+  r.tmpl.bins.edges = nullptr;   // bins_of() points it at r.tmpl.edges when used
   r.tmpl.mult = plan->mult;
   r.tmpl.opts = plan->opts;
-  r.tmpl.p.box_mode = plan->p.box_mode;
-  r.tmpl.p.chans = plan->p.chans;
-  r.tmpl.p.precision = plan->p.precision;
-  r.tmpl.p.NT = plan->p.NT;
+  r.rec_stride = record_stride(plan->p);
+  r.ntiles = (int64_t)plan->p.NT * plan->p.NT * plan->p.NT;
   r.key = request_key(r.tmpl);
   r.data = *data;
   if (!box) {
@@ -1101,6 +1293,15 @@ int tsb_server_wait(void* server, int64_t ticket, double* latency_s) {
     set_error(it->second.message);
     return it->second.status;
   }
+  return TSB_OK;
+}
+
+int tsb_server_stats(void* server, int32_t* peak_running, int64_t* released) {
+  if (!server) return fail(TSB_E_ARG, "NULL argument");
+  Server* S = (Server*)server;
+  std::lock_guard<std::mutex> lk(S->mu);
+  if (peak_running) *peak_running = S->peak_running;
+  if (released) *released = S->released;
   return TSB_OK;
 }
 

@@ -15,6 +15,7 @@
 // at the plan-wide scale.
 #include <cmath>
 
+#include "serve_policy.h"
 #include "tsb_internal.h"
 
 namespace tsb {
@@ -1140,6 +1141,11 @@ __global__ void __launch_bounds__(kBlock) norm_final_kernel(const double* tile_I
   if (threadIdx.x == 0) scal->I = sh[0] / (vc * vc);   // I = v_c sum (alpha R / v_c)^3
 }
 
+__global__ void zero_u64_kernel(unsigned long long* p, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = 0ull;
+}
+
 __global__ void zero_ints_kernel(int* p, int64_t n) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
     p[i] = 0;
@@ -1239,9 +1245,10 @@ int record_stride(const Plan& P) {
 int assign_words(const Plan& P) { return record_slots(P); }
 
 int64_t assign_work_cap(const Plan& P, int64_t particles) {
-  const int64_t ntiles = (int64_t)P.NT * P.NT * P.NT;
-  return ntiles + (8 * particles + kPartVisits - 1) / kPartVisits + 1;
+  return work_capacity((int64_t)P.NT * P.NT * P.NT, particles, kPartVisits);
 }
+
+int assign_part_visits() { return kPartVisits; }
 
 int64_t assign_heavy_bytes(const Plan& P) {
   return (int64_t)P.heavy_slots * P.copies * assign_words(P) * P.T * P.T * P.T * 8;
@@ -1492,6 +1499,16 @@ int run_unpack_grids(Plan& P, void* out, hipStream_t s) {
   else
     hipLaunchKernelGGL(unpack_kernel<float>, dim3(grid_blocks(total)), dim3(kBlock), 0, s, (const void*)P.d_grid,
                        out, m);
+  TSB_HIP(hipGetLastError());
+  return TSB_OK;
+}
+
+// Clear `bytes` (a multiple of 8) of device memory with a kernel (no memset
+// node: the call may be captured into a graph).
+int run_fill_zero(void* p, int64_t bytes, hipStream_t s) {
+  const int64_t n = bytes / 8;
+  if (n <= 0) return TSB_OK;
+  hipLaunchKernelGGL(zero_u64_kernel, dim3(grid_blocks(n)), dim3(kBlock), 0, s, (unsigned long long*)p, n);
   TSB_HIP(hipGetLastError());
   return TSB_OK;
 }

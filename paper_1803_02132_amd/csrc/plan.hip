@@ -77,7 +77,22 @@ int plan_build(Plan& P) {
   if (P.p < 1 || P.p > 3) return fail(TSB_E_ARG, "assign_p must be 1 (NGP), 2 (CIC) or 3 (TSC)");
   if (P.interlace != 0 && P.interlace != 1) return fail(TSB_E_ARG, "interlace must be 0 or 1");
   if (P.nb < 1 || P.nb > kMaxBins) return fail(TSB_E_ARG, "n_bins must be in 1..64");
-  if (!(P.dk > 0) || !(P.kmin >= 0)) return fail(TSB_E_ARG, "need dk > 0 and k_min >= 0");
+  if (P.edges.empty()) {
+    if (!(P.dk > 0) || !(P.kmin >= 0) || !std::isfinite(P.dk) || !std::isfinite(P.kmin))
+      return fail(TSB_E_ARG, "need dk > 0 and k_min >= 0");
+  } else {
+    if ((int)P.edges.size() != P.nb + 1) return fail(TSB_E_ARG, "edges must hold n_bins + 1 values");
+    for (int b = 0; b <= P.nb; ++b)
+      if (!std::isfinite(P.edges[b]) || P.edges[b] < 0 || (b > 0 && !(P.edges[b] > P.edges[b - 1])))
+        return fail(TSB_E_ARG, "edges must be finite, >= 0 and strictly increasing");
+  }
+  if (P.vertex != TSB_VERTEX_X3 && P.vertex != TSB_VERTEX_X1) return fail(TSB_E_ARG, "los vertex must be 0 (x3) or 1 (x1)");
+  if (P.estimator < TSB_BISPECTRUM || P.estimator > TSB_WINDOW) return fail(TSB_E_ARG, "estimator must be 0, 1 or 2");
+  if (P.shot_noise != 0 && P.shot_noise != 1) return fail(TSB_E_ARG, "shot_noise must be 0 or 1");
+  if (P.vertex == TSB_VERTEX_X1 && P.los_kind == TSB_LOS_LOCAL)
+    return fail(TSB_E_UNSUPPORTED, "the LOS at the first vertex is not built yet");
+  if (P.estimator != TSB_BISPECTRUM) return fail(TSB_E_UNSUPPORTED, "the 3PCF and window estimators are not built yet");
+  if (P.shot_noise) return fail(TSB_E_UNSUPPORTED, "shot-noise subtraction is not built yet");
   if (P.mult.empty()) return fail(TSB_E_ARG, "no multipoles");
   if (P.los_kind != TSB_LOS_GLOBAL && P.los_kind != TSB_LOS_LOCAL)
     return fail(TSB_E_ARG, "los kind must be global (0) or local (1)");
@@ -106,9 +121,17 @@ int plan_build(Plan& P) {
   std::vector<int> lut(n2all + 1, -1);
   int64_t n2maxF = 0;
   for (int64_t n2 = 1; n2 <= n2all; ++n2) {
-    double b = std::floor((kf * std::sqrt((double)n2) - P.kmin) / P.dk);
-    if (b >= 0 && b < P.nb) {
-      lut[n2] = (int)b;
+    const double k = kf * std::sqrt((double)n2);
+    int bin = -1;
+    if (P.edges.empty()) {
+      const double b = std::floor((k - P.kmin) / P.dk);
+      if (b >= 0 && b < P.nb) bin = (int)b;
+    } else if (k >= P.edges[0] && k < P.edges[P.nb]) {
+      // [edges[b], edges[b+1]): the last edge not above k
+      bin = (int)(std::upper_bound(P.edges.begin(), P.edges.end(), k) - P.edges.begin()) - 1;
+    }
+    if (bin >= 0) {
+      lut[n2] = bin;
       n2maxF = n2;
     }
   }

@@ -299,6 +299,37 @@ int run_reduce_final(Plan& P, hipStream_t s) {
   return TSB_OK;
 }
 
+namespace {
+
+__global__ void __launch_bounds__(kBlock) fill_nan_kernel(double* p, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock)
+    p[i] = __longlong_as_double(0x7ff8000000000000LL);   // quiet NaN
+}
+
+__global__ void __launch_bounds__(kBlock) scatter_outputs_kernel(const double* B, const OutEntry* outs, int nout,
+                                                                int nb, double* full) {
+  for (int o = blockIdx.x * kBlock + threadIdx.x; o < nout; o += gridDim.x * kBlock) {
+    const OutEntry e = outs[o];
+    full[((int64_t)e.mu * nb + e.b1) * nb + e.b2] = B[o];
+  }
+}
+
+}  // namespace
+
+// The computed outputs in the caller's [n_mult][n_bins][n_bins] layout, NaN
+// where no pair is computed, written to device memory `full`.
+int run_scatter_outputs(Plan& P, double* full, hipStream_t s) {
+  const int64_t total = (int64_t)P.mult.size() * P.nb * P.nb;
+  hipLaunchKernelGGL(fill_nan_kernel, dim3((int)std::min<int64_t>((total + kBlock - 1) / kBlock, 1024)),
+                     dim3(kBlock), 0, s, full, total);
+  const int nout = (int)P.outs.size();
+  if (nout > 0)
+    hipLaunchKernelGGL(scatter_outputs_kernel, dim3((nout + kBlock - 1) / kBlock), dim3(kBlock), 0, s,
+                       (const double*)P.d_B, (const OutEntry*)P.d_outs, nout, P.nb, full);
+  TSB_HIP(hipGetLastError());
+  return TSB_OK;
+}
+
 int run_reduce(Plan& P, hipStream_t s) {
   if (P.outs.empty()) return TSB_OK;
   return P.precision == TSB_FP64 ? reduce_impl<double>(P, s) : reduce_impl<float>(P, s);

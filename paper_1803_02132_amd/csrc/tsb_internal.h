@@ -83,8 +83,10 @@ struct Plan {
   double los_dir[3] = {0, 0, 1}, observer[3] = {0, 0, 0};
   int nb = 0;
   double kmin = 0, dk = 0;
+  std::vector<double> edges;      // explicit bin edges (n_bins + 1), empty: k_min + b dk
   std::vector<tsb_multipole> mult;
   int precision = TSB_FP32, pair_mode = TSB_PAIRS_PAPER, box_mode = 1, unfused = 0;
+  int vertex = TSB_VERTEX_X3, estimator = TSB_BISPECTRUM, shot_noise = 0;
   double P0 = 0;
   int device = 0;
 
@@ -169,6 +171,8 @@ struct Plan {
   int res_slots = 0;
   void* d_rec = nullptr;      // particle records in bucket order (u, channel weights), [cap][stride]
   int64_t particle_cap = 0;
+  void* d_hostcat = nullptr;    // device copies of host catalogues: [2][5][hostcat_cap] float
+  int64_t hostcat_cap = 0;
   int red_chunk = 64, red_wg = 1024;
   int red_mfma = 0;             // unfused FP32 reduction on the matrix cores: Q-group tiles per wavefront (0: off)
   int64_t bytes = 0;
@@ -233,11 +237,14 @@ int run_fused(Plan& P, hipStream_t s);
 int run_ynode_fill(Plan& P, hipStream_t s);
 int run_assign_back(Plan& P, hipStream_t s);
 int64_t assign_work_cap(const Plan& P, int64_t particles);
+int assign_part_visits();   // visits per assignment work item
 int record_stride(const Plan& P);
 int assign_words(const Plan& P);
 int64_t assign_heavy_bytes(const Plan& P);
 int assign_max_heavy(const Plan& P, int64_t other_bytes);
 int run_unpack_grids(Plan& P, void* out, hipStream_t s);
+int run_fill_zero(void* p, int64_t bytes, hipStream_t s);        // kernel fill, bytes % 8 == 0
+int run_scatter_outputs(Plan& P, double* full, hipStream_t s);   // [n_mult][nb][nb], NaN where not computed
 
 // ---------------------------------------------------------------------------
 // device helpers

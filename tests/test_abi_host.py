@@ -46,37 +46,54 @@ def req(**kw):
 ])
 def test_nmode_bit_exact_with_oracle(kw):
     r = req(**kw)
-    info, nm = tsb.query(**r)
+    info, nm, ke = tsb.query(**r)
     oplan = est.Plan(n=r["n"], box_len=r["box_len"], multipoles=r["multipoles"], n_bins=r["n_bins"],
                      dk=r["dk"], k_min=r["k_min"])
     assert np.array_equal(nm, est.nmode(oplan))
+    # mean |k| of each shell (eq. 38) against the oracle (pinned by a lattice count)
+    assert np.allclose(ke, est.k_eff(oplan), rtol=1e-12, atol=0)
+
+
+def test_explicit_edges_nmode_bit_exact_with_oracle():
+    # uneven shells given by their edges (eq. 38 with explicit bins)
+    edges = [0.004, 0.011, 0.013, 0.03, 0.0455, 0.071, 0.1]
+    r = req(n=64, n_bins=6, edges=edges)
+    info, nm, ke = tsb.query(**r)
+    oplan = est.Plan(n=64, box_len=1000.0, multipoles=r["multipoles"], n_bins=6, dk=1.0, edges=tuple(edges))
+    assert np.array_equal(nm, est.nmode(oplan))
+    assert np.allclose(ke, est.k_eff(oplan), rtol=1e-12, atol=0)
+    # the same shells as k_min + b dk give the same modes as the equivalent edges
+    dk = 0.0125
+    a = tsb.query(**req(n=64, n_bins=6, k_min=0.005, dk=dk))[1]
+    b = tsb.query(**req(n=64, n_bins=6, edges=[0.005 + i * dk for i in range(7)]))[1]
+    assert a.sum() > 0 and np.abs(a - b).sum() <= 2   # edges rounded once vs floor((k - k_min)/dk)
 
 
 def test_reduction_grid_rule():
     # 256^3, L = 1000, shells to k = 0.2: modes |n| < 31.8, G needs |n| < 63.7,
     # so a 128^3 grid holds every closed triangle without aliasing
-    info, _ = tsb.query(**req(n=256, n_bins=20, dk=0.01))
+    info, _, _ = tsb.query(**req(n=256, n_bins=20, dk=0.01))
     assert (info.n, info.m, info.r_f, info.r_g) == (256, 128, 31, 63)
     assert info.m > 2 * info.r_f + info.r_g
     # shells up to k_N/2 on a small grid: pairs wrap, the full grid is used
-    info, _ = tsb.query(**req(n=32, n_bins=8, dk=2 * 2 * math.pi / 1000.0))
+    info, _, _ = tsb.query(**req(n=32, n_bins=8, dk=2 * 2 * math.pi / 1000.0))
     assert info.m == 32 and info.r_g == 15
 
 
 def test_channel_and_field_counts():
     # local LOS {000, 202}: channels (0,0), (2,0), (2,1)re/im, (2,2)re/im
-    info, _ = tsb.query(**req())
+    info, _, _ = tsb.query(**req())
     assert info.n_channels == 6 and info.n_grids == 3
     # F_0^0, F_2^0 (one packed transform), F_2^1, F_2^2
     assert info.n_fields_f == 6 and info.n_fslots == 3
     # global z LOS {000, 202}: only m = 0 fields survive (Sec. 4.4)
-    info, _ = tsb.query(**req(los="global"))
+    info, _, _ = tsb.query(**req(los="global"))
     assert info.n_channels == 1 and info.n_fields_f == 2 and info.n_fslots == 1
 
 
 @pytest.mark.parametrize("pair_mode,count", [("paper", 36 + 64), ("upper", 72), ("diagonal", 16), ("all", 128)])
 def test_pair_counts(pair_mode, count):
-    info, _ = tsb.query(**req(n_bins=8, pair_mode=pair_mode))
+    info, _, _ = tsb.query(**req(n_bins=8, pair_mode=pair_mode))
     assert info.n_outputs == count
 
 
@@ -84,9 +101,9 @@ def test_paper_pair_counts_for_eleven_shells():
     # Sec. 5.2: 512^3 in a (3.5 Gpc/h)^3 box, 11 shells of 0.02 h/Mpc give 66 pairs
     # when l1 = l2, else 121
     r = req(n=512, box_len=3500.0, n_bins=11, dk=0.02, k_min=0.0, multipoles=[(0, 0, 0)])
-    info, _ = tsb.query(**r)
+    info, _, _ = tsb.query(**r)
     assert info.n_outputs == 66
-    info, _ = tsb.query(**dict(r, multipoles=[(2, 0, 2)]))
+    info, _, _ = tsb.query(**dict(r, multipoles=[(2, 0, 2)]))
     assert info.n_outputs == 121
 
 
@@ -103,6 +120,8 @@ def test_paper_pair_counts_for_eleven_shells():
     (dict(box_len=0.0), tsb.abi.TSB_E_ARG),
     (dict(assign_p=4), tsb.abi.TSB_E_ARG),
     (dict(los="global", los_dir=(0.0, 0.0, 0.0)), tsb.abi.TSB_E_ARG),
+    (dict(box_len=(1000.0, 1000.0, 1200.0)), tsb.abi.TSB_E_UNSUPPORTED),   # one fundamental frequency needed
+    (dict(n_bins=2, edges=[0.01, 0.02, 0.02]), tsb.abi.TSB_E_ARG),         # edges not increasing
 ])
 def test_invalid_requests(bad, code):
     with pytest.raises(tsb.TsbError) as e:

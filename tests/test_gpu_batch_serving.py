@@ -91,8 +91,57 @@ def test_server_alone_and_in_a_mix():
             ref = alone if k == 0 else tmpl[geo[k]].measure(cats[k])["B"]
             assert _same(B, ref), k
             assert lat > 0
+        peak, released = srv.stats()
+        _say("server mix: peak requests running at once", peak, "workspaces released", released)
+        assert peak >= 2   # requests of different geometries overlapped on the device
     finally:
         srv.close()
+
+
+def test_server_under_a_tight_budget():
+    # fewer slots than geometries and a budget that holds about one workspace:
+    # idle workspaces are released (LRU) and buffers grow for a larger
+    # catalogue of a geometry whose idle workspace is too small; every request
+    # finishes with the bits of a plain measurement
+    reqs = _requests()
+    tmpl = [tsb.Plan(**r) for r in reqs]
+    biggest = max(p.info.workspace_bytes for p in tmpl)
+    srv = tsb.Server(int(1.5 * biggest) + (64 << 20), 2)
+    try:
+        order = [(0, 60, 4000), (1, 61, 4000), (2, 62, 4000), (0, 63, 60000), (1, 64, 9000), (0, 65, 3000)]
+        cats = [tsb.catalog_to_device(_cat(reqs[g]["n"], s, n)) for g, s, n in order]
+        tickets = [srv.submit(tmpl[g], c) for (g, _, _), c in zip(order, cats)]
+        _say("tight budget: submitted", len(tickets))
+        for (g, _, _), c, t in zip(order, cats, tickets):
+            lat, B = srv.wait(t)
+            assert _same(B, tmpl[g].measure(c)["B"])
+        peak, released = srv.stats()
+        _say("tight budget: peak running", peak, "released", released)
+        assert released >= 2
+    finally:
+        srv.close()
+
+
+def test_server_cancels_queued_requests_at_destroy():
+    # requests still queued when the server is destroyed are dropped (their
+    # output is never written); the running one finishes with correct bits.
+    # One slot: the first request also creates its workspace, so the others
+    # are still queued when tsb_server_destroy is called right after submit.
+    req = box_request(n=64, n_bins=6)
+    plan = tsb.Plan(**req)
+    dev = tsb.catalog_to_device(_cat(64, 70, 30000))
+    ref = plan.measure(dev)["B"]
+    srv = tsb.abi.tsb_server_create(8 << 30, 1)
+    outs = [np.full_like(ref, 12345.0) for _ in range(12)]
+    cs = tsb._cat_struct(dev)
+    for B in outs:
+        tsb.abi.tsb_server_submit(srv, plan.handle, cs, None, B.ctypes.data)
+    tsb.abi.tsb_server_destroy(srv)
+    done = [k for k, B in enumerate(outs) if not np.all(B == 12345.0)]
+    _say("destroy with 12 queued: finished", len(done), "cancelled", 12 - len(done))
+    assert len(done) < 12
+    for k in done:
+        assert _same(outs[k], ref), k
 
 
 def test_server_rejects_what_cannot_fit():

@@ -4,16 +4,20 @@ from its seed and checked against the stored checksum).
 
 * 128^3 box, 500k particles, Kaiser along a local LOS, TSC + interlacing,
   {000, 110, 202, 112}, 20 shells: every computed pair.
-* 256^3 throughput mock (the configuration bench.py times): sampled pairs.
+* 256^3 throughput mock (the configuration bench.py times): every pair.
 * 256^3 survey window (L = 2000, 2M galaxies in a half shell, 20M randoms,
-  FKP weights, {000, 202, 112, 404}, 25 shells): sampled pairs, alpha and I.
+  FKP weights, {000, 202, 112, 404}, 25 shells): pairs that touch every
+  shell, alpha and I.
+* 512^3 request (the largest grid of the serving mix; 2M particles, global
+  LOS, {000, 202}): sampled pairs.
 * 384^3 serving request (radix-3 grid, 2M particles, {000, 110, 202}):
   sampled pairs.
 * 512^3, the largest grid of the serving mix: properties that hold at any
   size (translation by one cell with a global LOS, order independence).
 
 Tolerance: 1e-4 normwise per multipole (max |dB| / max |B| over the compared
-pairs), FP32 fields with FP64 accumulation.
+pairs), FP32 fields with FP64 accumulation. The elementwise relative error on
+the pairs with |B| >= 1e-2 max |B| is reported beside it.
 """
 import os
 
@@ -52,7 +56,10 @@ def _request(name, **kw):
     return req
 
 
-def _compare(B, ref, pairs=None):
+def _compare(B, ref, pairs=None, elementwise=None):
+    """Normwise error per multipole (max |dB| / max |B_oracle| over the compared
+    pairs); with a list `elementwise`, also appends per multipole the largest
+    |dB| / |B_oracle| over the pairs with |B_oracle| >= 1e-2 max |B_oracle|."""
     errs = []
     for mu in range(ref.shape[0]):
         sel = np.isfinite(B[mu]) & np.isfinite(ref[mu])
@@ -64,6 +71,9 @@ def _compare(B, ref, pairs=None):
         assert sel.any()
         scale = np.max(np.abs(ref[mu][sel]))
         errs.append(np.max(np.abs(B[mu][sel] - ref[mu][sel])) / scale)
+        if elementwise is not None:
+            big = sel & (np.abs(ref[mu]) >= 1e-2 * scale)
+            elementwise.append(float(np.max(np.abs(B[mu][big] - ref[mu][big]) / np.abs(ref[mu][big]))))
     return np.array(errs)
 
 
@@ -77,13 +87,15 @@ def test_box128_every_pair(unfused):
     plan = tsb.Plan(**req)
     assert np.array_equal(np.array(plan.nmode), exp["nmode"])
     res = plan.measure(tsb.catalog_to_device(cat))
-    err = _compare(res["B"], exp["B"])
-    _say("box128 normwise errors per multipole", err, "I", res["I"], exp["I"])
+    elem = []
+    err = _compare(res["B"], exp["B"], elementwise=elem)
+    _say("box128 normwise errors per multipole", err, "elementwise", np.array(elem), "I", res["I"], exp["I"])
     assert res["I"] == pytest.approx(float(exp["I"]), rel=1e-12)
     assert np.all(err <= 1e-4)
 
 
-def test_box256_sampled_pairs():
+def test_box256_every_pair():
+    # the configuration the benchmark times: 210 pairs of B_000 and 400 of B_202
     exp = np.load(os.path.join(GOLDEN, "box256_seed48.npz"))
     spec, cat = workload("box256", seed=48)
     assert np.allclose(_checksum(cat), exp["checksum"], rtol=1e-12, atol=0)
@@ -91,13 +103,34 @@ def test_box256_sampled_pairs():
     plan = tsb.Plan(**bench.WORKLOAD)
     assert np.array_equal(np.array(plan.nmode), exp["nmode"])
     res = plan.measure(tsb.catalog_to_device(cat))
-    pairs = [tuple(p) for p in exp["pairs"]]
-    err = _compare(res["B"], exp["B"], pairs)
-    _say("box256 normwise errors per multipole (sampled pairs)", err)
+    assert np.isfinite(res["B"]).sum() == 610
+    elem = []
+    err = _compare(res["B"], exp["B"], elementwise=elem)
+    _say("box256 every pair: normwise errors per multipole", err, "elementwise", np.array(elem))
+    assert res["I"] == pytest.approx(float(exp["I"]), rel=1e-12)
     assert np.all(err <= 1e-4)
 
 
-def test_survey256_sampled_pairs():
+def test_box512_sampled_pairs():
+    # the largest grid of the serving mix: 2M particles on 512^3, global LOS along z
+    exp = np.load(os.path.join(GOLDEN, "box512_seed7002.npz"))
+    spec, cat = workload("box256", seed=7002, n_target=2_000_000)
+    assert np.allclose(_checksum(cat), exp["checksum"], rtol=1e-12, atol=0)
+    req = _request("box256", n=512, multipoles=[(0, 0, 0), (2, 0, 2)], los="global")
+    _say("box512", len(cat["pos"]), "particles")
+    plan = tsb.Plan(**req)
+    assert np.array_equal(np.array(plan.nmode), exp["nmode"])
+    res = plan.measure(tsb.catalog_to_device(cat))
+    pairs = [tuple(p) for p in exp["pairs"]]
+    elem = []
+    err = _compare(res["B"], exp["B"], pairs, elementwise=elem)
+    _say("box512 normwise errors per multipole (sampled pairs)", err, "elementwise", np.array(elem),
+         "I", res["I"], float(exp["I"]))
+    assert res["I"] == pytest.approx(float(exp["I"]), rel=1e-12)
+    assert np.all(err <= 1e-4)
+
+
+def test_survey256_every_shell():
     exp = np.load(os.path.join(GOLDEN, "survey256_seed3.npz"))
     spec, data, rand = survey_workload("survey256", seed=3)
     assert np.allclose(_checksum(data), exp["checksum"], rtol=1e-12, atol=0)
@@ -108,9 +141,11 @@ def test_survey256_sampled_pairs():
     assert np.array_equal(np.array(plan.nmode), exp["nmode"])
     res = plan.measure(tsb.catalog_to_device(data), tsb.catalog_to_device(rand))
     pairs = [tuple(p) for p in exp["pairs"]]
-    err = _compare(res["B"], exp["B"], pairs)
-    _say("survey256 normwise errors per multipole (sampled pairs)", err, "alpha", res["alpha"],
-         float(exp["alpha"]), "I", res["I"], float(exp["I"]))
+    assert {b for p in pairs for b in p} == set(range(25))
+    elem = []
+    err = _compare(res["B"], exp["B"], pairs, elementwise=elem)
+    _say("survey256 normwise errors per multipole (pairs over every shell)", err, "elementwise",
+         np.array(elem), "alpha", res["alpha"], float(exp["alpha"]), "I", res["I"], float(exp["I"]))
     assert res["alpha"] == pytest.approx(float(exp["alpha"]), rel=1e-12)
     # I = v_c sum (alpha R / v_c)^3 is cubic in the randoms' weights, which an
     # FP32 plan stores rounded to FP32; n-bar here takes 50 radial values, so

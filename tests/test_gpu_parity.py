@@ -185,7 +185,7 @@ def test_reduced_grid_matches_full_grid_oracle():
     # shells up to |n| < 8 on a 64^3 grid: the sum over cells runs on M = 32 < N
     req = box_request(n=64, box_len=1000.0, n_bins=4, dk=2.0 * 2.0 * math.pi / 1000.0,
                       multipoles=[(0, 0, 0), (2, 0, 2), (1, 1, 2)], precision="f64")
-    info, _ = tsb.query(**req)
+    info, _, _ = tsb.query(**req)
     assert info.m < info.n
     cat = small_cat(n=64, n_target=60000, seed=3)
     plan, g, o = run_both(req, cat)
@@ -367,3 +367,75 @@ def test_one_pass_reduction_in_shell_groups():
     err = normwise_errors(g["B"], o["B"], mask)
     _say("grouped one-pass errors", err)
     assert np.all(err <= 1e-4)
+
+
+def test_plan_k_eff_and_query_match_oracle():
+    # k_eff (mean |k| of a shell, eq. 38) and N_mode of a plan on the device,
+    # and the plan-based size query
+    req = box_request(n=64, n_bins=8, dk=0.011, k_min=0.002)
+    plan = tsb.Plan(**req)
+    o = oracle_plan(**req)
+    assert np.array_equal(np.array(plan.nmode), est.nmode(o))
+    assert np.allclose(plan.k_eff, est.k_eff(o), rtol=1e-12, atol=0)
+    ws, npairs, nm = plan.query()
+    assert ws == plan.info.workspace_bytes and npairs == plan.info.n_outputs
+    assert np.array_equal(np.array(nm), est.nmode(o))
+
+
+def test_host_catalogue_equals_device_catalogue():
+    # on_device = 0: the library copies the arrays; the result is bitwise the
+    # device-catalogue result (survey mode: data and randoms, with w and nbar)
+    req = box_request(n=32, n_bins=6, box_mode=False, P0=1e4, observer=(500.0, 500.0, 500.0),
+                      multipoles=[(0, 0, 0), (2, 0, 2)])
+    rng = np.random.default_rng(7)
+
+    def shell(npts):
+        v = rng.standard_normal((npts, 3))
+        v /= np.linalg.norm(v, axis=1)[:, None]
+        return 500.0 + v * (200.0 + 200.0 * rng.random(npts))[:, None]
+
+    data = {"pos": shell(5000), "w": 0.5 + rng.random(5000), "nbar": 1e-4 * (1 + rng.random(5000))}
+    rand = {"pos": shell(20000), "w": None, "nbar": 1e-4 * (1 + rng.random(20000))}
+    plan = tsb.Plan(**req)
+    dev = plan.measure(tsb.catalog_to_device(data), tsb.catalog_to_device(rand))
+    host = plan.measure(tsb.catalog_on_host(data), tsb.catalog_on_host(rand))
+    mixed = plan.measure(tsb.catalog_on_host(data), tsb.catalog_to_device(rand))
+    report("host catalogue vs device catalogue: alpha", host["alpha"], dev["alpha"])
+    for r in (host, mixed):
+        assert np.array_equal(np.nan_to_num(r["B"], nan=7.0), np.nan_to_num(dev["B"], nan=7.0))
+        assert r["I"] == dev["I"] and r["alpha"] == dev["alpha"]
+    o = est.measure(oracle_plan(**req), data, rand)
+    err = normwise_errors(host["B"], o["B"], pair_mask(req["multipoles"], req["n_bins"]))
+    report("host catalogue vs oracle", err)
+    assert np.all(err <= 1e-4)
+
+
+def test_survey_particle_outside_the_box_is_reported():
+    # survey mode does not wrap positions: a galaxy past the box is an input
+    # error (the kernels skip it; the measurement reports TSB_E_INPUT)
+    req = box_request(n=32, n_bins=6, box_mode=False, observer=(500.0, 500.0, 500.0))
+    rng = np.random.default_rng(9)
+    data = {"pos": 300.0 + 400.0 * rng.random((3000, 3))}
+    rand = {"pos": 300.0 + 400.0 * rng.random((9000, 3))}
+    plan = tsb.Plan(**req)
+    plan.measure(tsb.catalog_to_device(data), tsb.catalog_to_device(rand))   # inside: fine
+    data["pos"][17] = (500.0, 1000.5, 500.0)
+    with pytest.raises(tsb.TsbError) as e:
+        plan.measure(tsb.catalog_to_device(data), tsb.catalog_to_device(rand))
+    assert e.value.code == tsb.abi.TSB_E_INPUT and "outside" in str(e.value)
+
+
+def test_particle_at_the_observer_is_reported():
+    # a local LOS is undefined for a particle at the observer (eq. 34)
+    req = box_request(n=32, n_bins=6)
+    cat = small_cat(seed=12)
+    pos = cat["pos"].copy()
+    pos[5] = req["observer"]
+    plan = tsb.Plan(**req)
+    with pytest.raises(tsb.TsbError) as e:
+        plan.measure(tsb.catalog_to_device({"pos": pos}))
+    assert e.value.code == tsb.abi.TSB_E_INPUT and "observer" in str(e.value)
+    # the plan measures normally afterwards
+    g = plan.measure(tsb.catalog_to_device(cat))
+    o = est.measure(oracle_plan(**req), cat)
+    assert np.all(normwise_errors(g["B"], o["B"], pair_mask(req["multipoles"], req["n_bins"])) <= 1e-4)
