@@ -230,6 +230,24 @@ int tsb_plan_nmode(const tsb_plan* plan, int64_t* nmode, double* k_eff);
 int tsb_measure(tsb_plan* plan, const tsb_catalog* data, const tsb_catalog* randoms,
                 void* stream, double* B_out, double* I_out, double* alpha_out);
 
+/* tsb_measure for callers that cannot allocate device memory: code under HIP
+ * graph capture, tight serving loops, harnesses that forbid allocation. Same
+ * arguments, results and errors as tsb_measure (bitwise the same B, I and
+ * alpha for the same plan and catalogues), but the call allocates nothing:
+ * every buffer the measurement reads and writes (grids, pass buffers, fields,
+ * bucketing, partial sums, particle records, results) lives in one static
+ * device array of the library, 256 MiB per device, held from the library's
+ * load to the end of the process; the plan's constant tables stay with the
+ * plan. The catalogues must be device memory (on_device = 1). A plan and
+ * catalogue that need more than the 256 MiB fail with TSB_E_NOMEM and a
+ * message giving the size they need (grids up to 64^3 with the multipoles of
+ * Sec. 5.2 fit). Every call on a device shares that device's array, which
+ * keeps the last call's contents (the call clears what must start at zero):
+ * calls that overlap on one device race and must not be made. Synchronises
+ * the stream. */
+int tsb_measure_noalloc(tsb_plan* plan, const tsb_catalog* data, const tsb_catalog* randoms,
+                        void* stream, double* B_out, double* I_out, double* alpha_out);
+
 /* The shot noise S_{l1 l2 L}(k1, k2) (Sec. 4.2, eq. 44: the sum of the four
  * coincident-index terms of eq. 45 with the scalars and the w^2-weighted
  * fields of eq. 46) that the plan's last tsb_measure subtracted, into a host

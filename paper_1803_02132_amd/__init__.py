@@ -126,6 +126,16 @@ class Plan:
                                    s.cuda_stream, B.ctypes.data)
         return {"B": B, "I": I, "alpha": alpha}
 
+    def measure_noalloc(self, data_dev, randoms_dev=None, stream=None):
+        """tsb_measure_noalloc: the same measurement with no device allocation
+        (buffers in the library's static scratch). Device catalogues only."""
+        import torch
+        s = torch.cuda.current_stream() if stream is None else stream
+        B = np.empty((len(self.multipoles), self.n_bins, self.n_bins), dtype=np.float64)
+        I, alpha = abi.tsb_measure_noalloc(self.handle, _cat_struct(data_dev), _cat_struct(randoms_dev),
+                                           s.cuda_stream, B.ctypes.data)
+        return {"B": B, "I": I, "alpha": alpha}
+
     def assign(self, data_dev, randoms_dev=None, stream=None):
         """Assignment stage only: grids [copies][channel][Nx][Ny][Nz] as a torch tensor."""
         import torch

@@ -103,6 +103,9 @@ _lib.tsb_plan_channel.argtypes = [ctypes.c_void_p, ctypes.c_int32, _P(ctypes.c_i
 _lib.tsb_measure.restype = ctypes.c_int
 _lib.tsb_measure.argtypes = [ctypes.c_void_p, _P(tsb_catalog), _P(tsb_catalog), ctypes.c_void_p,
                              _P(ctypes.c_double), _P(ctypes.c_double), _P(ctypes.c_double)]
+_lib.tsb_measure_noalloc.restype = ctypes.c_int
+_lib.tsb_measure_noalloc.argtypes = [ctypes.c_void_p, _P(tsb_catalog), _P(tsb_catalog), ctypes.c_void_p,
+                                     _P(ctypes.c_double), _P(ctypes.c_double), _P(ctypes.c_double)]
 _lib.tsb_assign.restype = ctypes.c_int
 _lib.tsb_assign.argtypes = [ctypes.c_void_p, _P(tsb_catalog), _P(tsb_catalog), ctypes.c_void_p, ctypes.c_void_p]
 
@@ -140,6 +143,7 @@ STAGES = ["weights", "bucket", "assign", "fwd_z", "fwd_y", "fwd_x", "combine", "
 
 EXPORTED = ["tsb_plan_set_profiling", "tsb_plan_stage_times", "tsb_plan_autotune", "tsb_plan_create", "tsb_plan_destroy",
             "tsb_plan_query", "tsb_request_query", "tsb_plan_get_info", "tsb_plan_nmode", "tsb_measure",
+            "tsb_measure_noalloc",
             "tsb_plan_shot_noise", "tsb_assign", "tsb_plan_channel", "tsb_last_error", "tsb_measure_batch",
             "tsb_plan_set_graphs", "tsb_server_create", "tsb_server_submit", "tsb_server_poll", "tsb_server_wait",
             "tsb_server_stats", "tsb_server_destroy"]
@@ -218,6 +222,16 @@ def tsb_measure(h, data, randoms, stream, B_out_ptr):
     _check(_lib.tsb_measure(h, ctypes.byref(data), ctypes.byref(randoms) if randoms is not None else None,
                             stream, ctypes.cast(B_out_ptr, _P(ctypes.c_double)), ctypes.byref(I),
                             ctypes.byref(alpha)))
+    return I.value, alpha.value
+
+
+def tsb_measure_noalloc(h, data, randoms, stream, B_out_ptr):
+    """As tsb_measure, in the library's static scratch. Returns (I, alpha)."""
+    I = ctypes.c_double()
+    alpha = ctypes.c_double()
+    _check(_lib.tsb_measure_noalloc(h, ctypes.byref(data), ctypes.byref(randoms) if randoms is not None else None,
+                                    stream, ctypes.cast(B_out_ptr, _P(ctypes.c_double)), ctypes.byref(I),
+                                    ctypes.byref(alpha)))
     return I.value, alpha.value
 
 

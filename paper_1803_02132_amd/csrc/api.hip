@@ -1319,3 +1319,151 @@ int tsb_server_destroy(void* server) {
 }
 
 }  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Measurement without device allocation (tsb_measure_noalloc): the plan's
+// constant tables stay where they are; every buffer a measurement reads and
+// writes, including the particle records and the result array, is laid out in
+// `scratch`, a file-scope device array of kScratchBytes that each device holds
+// from the library's load to the end of the process. Host code never uses the
+// array's name as an address: hipGetSymbolAddress gives each device's copy
+// once, with that device current, and only that pointer reaches kernels and
+// copies.
+
+namespace tsb {
+
+namespace {
+
+constexpr int64_t kScratchBytes = 256LL << 20;
+constexpr int kMaxDevices = 64;
+
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+std::mutex g_scratch_mu;
+char* g_scratch_ptr[kMaxDevices] = {};
+
+// This device's copy of `scratch` (looked up once per device; the device must
+// be current).
+int scratch_base(int dev, char** out) {
+  if (dev < 0 || dev >= kMaxDevices) return fail(TSB_E_DEVICE, "device index beyond the scratch table");
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p) {
+      (void)hipGetLastError();
+      return fail(TSB_E_DEVICE, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+    }
+    g_scratch_ptr[dev] = (char*)p;
+  }
+  *out = g_scratch_ptr[dev];
+  return TSB_OK;
+}
+
+// The plan fields a measurement's buffers hang on; saved before they are
+// pointed into the scratch and put back afterwards.
+struct WorkspaceState {
+  void *grid, *t1, *t2, *t3, *spec, *dcube, *u1, *u2, *fields, *heavy, *rec, *work;
+  int *bk_count, *bk_cursor, *bk_start, *scan_part, *tile_hslot, *heavy_tile, *keys;
+  double *partials, *B, *sum_partials;
+  DevScalars* scal;
+  int64_t nbk, particle_cap, work_cap;
+  unsigned prof;
+
+  explicit WorkspaceState(const Plan& P)
+      : grid(P.d_grid), t1(P.d_t1), t2(P.d_t2), t3(P.d_t3), spec(P.d_spec), dcube(P.d_dcube), u1(P.d_u1),
+        u2(P.d_u2), fields(P.d_fields), heavy(P.d_heavy), rec(P.d_rec), work(P.d_work), bk_count(P.d_bk_count),
+        bk_cursor(P.d_bk_cursor), bk_start(P.d_bk_start), scan_part(P.d_scan_part), tile_hslot(P.d_tile_hslot),
+        heavy_tile(P.d_heavy_tile), keys(P.d_keys), partials(P.d_partials), B(P.d_B),
+        sum_partials(P.d_sum_partials), scal(P.d_scal), nbk(P.nbk), particle_cap(P.particle_cap),
+        work_cap(P.work_cap), prof(P.prof) {}
+
+  void restore(Plan& P) const {
+    P.d_grid = grid; P.d_t1 = t1; P.d_t2 = t2; P.d_t3 = t3; P.d_spec = spec; P.d_dcube = dcube;
+    P.d_u1 = u1; P.d_u2 = u2; P.d_fields = fields; P.d_heavy = heavy; P.d_rec = rec; P.d_work = work;
+    P.d_bk_count = bk_count; P.d_bk_cursor = bk_cursor; P.d_bk_start = bk_start; P.d_scan_part = scan_part;
+    P.d_tile_hslot = tile_hslot; P.d_heavy_tile = heavy_tile; P.d_keys = keys; P.d_partials = partials;
+    P.d_B = B; P.d_sum_partials = sum_partials; P.d_scal = scal; P.nbk = nbk; P.particle_cap = particle_cap;
+    P.work_cap = work_cap; P.prof = prof;
+  }
+};
+
+int measure_in_scratch(Plan& P, const tsb_catalog* data, const tsb_catalog* rand, hipStream_t s, double* B_out,
+                       DevScalars* h) {
+  int rc;
+  char* base = nullptr;
+  if ((rc = scratch_base(P.device, &base))) return rc;
+  const int64_t ntot = data->n + (P.box_mode ? 0 : rand->n);
+  if (ntot > 2147483647LL) return fail(TSB_E_UNSUPPORTED, "more than 2^31-1 particles");
+  Carver cv;
+  cv.base = base;
+  cv.cap = kScratchBytes;
+  int64_t bytes = 0;
+  rc = carve_workspace(P, cv, bytes);
+  const int64_t cap = std::max<int64_t>(ntot, 1);
+  const int64_t wcap = assign_work_cap(P, cap);
+  double* full = nullptr;
+  if (!rc) rc = cv.take((void**)&P.d_keys, cap * 4, bytes);
+  if (!rc) rc = cv.take(&P.d_rec, cap * record_stride(P), bytes);
+  if (!rc) rc = cv.take(&P.d_work, wcap * 8, bytes);
+  if (!rc) rc = cv.take((void**)&full, (int64_t)P.mult.size() * P.nb * P.nb * 8, bytes);
+  if (rc) {
+    // carve once more without a cap for the figure the message reports
+    Carver need;
+    need.base = base;
+    need.cap = INT64_MAX;
+    int64_t b2 = 0;
+    (void)carve_workspace(P, need, b2);
+    need.used += cap * 4 + 255 + cap * record_stride(P) + 255 + wcap * 8 + 255 +
+                 (int64_t)P.mult.size() * P.nb * P.nb * 8;
+    return fail(TSB_E_NOMEM, "tsb_measure_noalloc: this plan and catalogue need about " +
+                                 std::to_string(need.used >> 20) + " MiB of the library's static scratch, which holds " +
+                                 std::to_string(kScratchBytes >> 20) + " MiB");
+  }
+  P.particle_cap = cap;
+  P.work_cap = wcap;
+  P.prof = 0;
+  // the split-tile slots start at zero (the scratch keeps whatever the last call left)
+  if ((rc = run_fill_zero(P.d_heavy, assign_heavy_bytes(P), s))) return rc;
+  if ((rc = run_prep(P, data, P.box_mode ? nullptr : rand, s))) return rc;
+  if ((rc = run_assign(P, data, P.box_mode ? nullptr : rand, s))) return rc;
+  if ((rc = run_back(P, s))) return rc;
+  if ((rc = run_scatter_outputs(P, full, s))) return rc;
+  TSB_HIP(hipMemcpyAsync(B_out, full, P.mult.size() * P.nb * P.nb * sizeof(double), hipMemcpyDeviceToHost, s));
+  TSB_HIP(hipMemcpyAsync(h, P.d_scal, sizeof(DevScalars), hipMemcpyDeviceToHost, s));
+  TSB_HIP(hipStreamSynchronize(s));
+  return TSB_OK;
+}
+
+}  // namespace
+
+}  // namespace tsb
+
+extern "C" int tsb_measure_noalloc(tsb_plan* plan, const tsb_catalog* data, const tsb_catalog* randoms, void* stream,
+                                   double* B_out, double* I_out, double* alpha_out) {
+  if (!plan || !B_out) return fail(TSB_E_ARG, "NULL argument");
+  Plan& P = plan->p;
+  hipStream_t s = (hipStream_t)stream;
+  int rc;
+  if ((rc = set_device(P))) return rc;
+  if ((rc = check_catalog(data, "data"))) return rc;
+  if (!P.box_mode && (rc = check_catalog(randoms, "randoms"))) return rc;
+  if (!data->on_device || (!P.box_mode && !randoms->on_device))
+    return fail(TSB_E_ARG, "tsb_measure_noalloc takes device catalogues only (on_device = 1)");
+  if ((rc = check_device_arrays(P, data, "data"))) return rc;
+  if (!P.box_mode && (rc = check_device_arrays(P, randoms, "randoms"))) return rc;
+  const WorkspaceState saved(P);
+  DevScalars h{};
+  rc = measure_in_scratch(P, data, randoms, s, B_out, &h);
+  saved.restore(P);
+  if (rc) {
+    (void)hipStreamSynchronize(s);   // nothing of this call stays in flight
+    return rc;
+  }
+  if ((rc = check_input_flags(P, h))) return rc;
+  if (!(h.I > 0.0) || !std::isfinite(h.I))
+    return fail(TSB_E_INPUT, "the normalisation I is not positive (no weighted particles or randoms): B is undefined");
+  if (I_out) *I_out = h.I;
+  if (alpha_out) *alpha_out = h.alpha;
+  return TSB_OK;
+}
