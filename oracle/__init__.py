@@ -15,6 +15,8 @@ decomposition formalism for the redshift-space bispectrum" (arXiv:1803.02132):
                    shell filters, the 3j-weighted triple-product reduction and
                    the normalisation (Sec. 4.1, 4.2, 4.4, 5.2), plus the direct
                    triangle sum that the FFT form rewrites (Sec. 4.2, eq. 35).
+* ``shotnoise`` -- the shot noise of the estimator: the coincident-index terms
+                   of its particle description (Sec. 4.2, eqs. 43-46).
 
 Every function states the passage it follows. Readings of passages that are
 silent or ambiguous are listed (R1..R11) in ``estimator``'s header.
