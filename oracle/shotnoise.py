@@ -50,7 +50,9 @@ Readings (the paper's printed forms are the continuum limits of these):
       scale dependence of this term is left for future work).
   S5  N_L^M is a pure particle sum: in a periodic box it has no mean term and
       no randoms, and its DC mode is kept; it is gridded, interlaced,
-      deconvolved and Nyquist-zeroed like dn.
+      deconvolved and Nyquist-zeroed like dn. H_L^M is zero on the Nyquist
+      planes too (R6 for every field: dn and N vanish there, and so does the
+      self-pair part of their product that the subtraction stands for).
 
 Pins (tests/test_oracle_shotnoise.py): the terms against a direct triple sum
 over particle indices split by coincidence class, with exact particle Fourier
@@ -238,16 +240,22 @@ def shot_noise(plan, dn, nk, sb, cw2, I, pairs=None):
         return acache[key]
 
     hcache = {}
+    nx, ny, nz = est.mode_vectors(n)
+    nyq = (np.abs(nx) == n // 2) | (np.abs(ny) == n // 2) | (np.abs(nz) == n // 2)
 
     def H(L, M):
-        """H_L^M(x) = (N^3/V) ifftn(dn_L^M N_0^0* - Sbar_L^M C/W^2)."""
+        """H_L^M(x) = (N^3/V) ifftn(dn_L^M N_0^0* - Sbar_L^M C/W^2), zero on the
+        Nyquist planes like every field (R6; dn and N vanish there, and so does
+        the self-pair part of their product)."""
         if (L, M) not in hcache:
             src = dn[(L, M)] if (L, M) in dn else None
             if src is None:   # global LOS: dn_L^M = y_L^M*(d) dn (R10)
                 d = np.asarray(plan.los_dir, np.float64)
                 d = d / np.linalg.norm(d)
                 src = complex(np.conj(ang.ylm(L, M, d[0], d[1], d[2]))) * dn[(0, 0)]
-            hcache[(L, M)] = (n ** 3 / plan.volume) * np.fft.ifftn(src * np.conj(nk[(0, 0)]) - sb[(L, M)] * cw2)
+            spec = src * np.conj(nk[(0, 0)]) - sb[(L, M)] * cw2
+            spec[nyq] = 0.0
+            hcache[(L, M)] = (n ** 3 / plan.volume) * np.fft.ifftn(spec)
         return hcache[(L, M)]
 
     for mu, (l1, l2, L) in enumerate(plan.multipoles):
