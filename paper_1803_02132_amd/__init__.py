@@ -109,6 +109,14 @@ class Plan:
         self.nmode, self.k_eff = abi.tsb_plan_nmode(self.handle, self.n_bins)
         self.precision = kw.get("precision", "f32")
 
+    def shot_noise(self):
+        """The shot noise S that the last measure() subtracted (plans created with
+        shot_noise=True) and its i = j != k term, each (n_mult, n_bins, n_bins)."""
+        S = np.empty((len(self.multipoles), self.n_bins, self.n_bins), dtype=np.float64)
+        Sij = np.empty_like(S)
+        abi.tsb_plan_shot_noise(self.handle, S.ctypes.data, Sij.ctypes.data)
+        return S, Sij
+
     def query(self):
         """tsb_plan_query: (workspace bytes, computed entries, N_mode per bin)."""
         return abi.tsb_plan_query(self.handle, self.n_bins)

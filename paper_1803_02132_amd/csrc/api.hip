@@ -128,7 +128,7 @@ int carve_workspace(Plan& P, Carver& cv, int64_t& B) {
   ALLOC(P.d_heavy_tile, (int64_t)P.heavy_slots * 4);
   ALLOC(P.d_heavy, assign_heavy_bytes(P));
   ALLOC(P.d_scal, (int64_t)sizeof(DevScalars));
-  ALLOC(P.d_sum_partials, std::max<int64_t>(ntiles, 8 * 512) * 8);
+  ALLOC(P.d_sum_partials, std::max<int64_t>(std::max<int64_t>(ntiles, 8 * 512), 512 * (int64_t)P.chans.size()) * 8);
   ALLOC(P.d_partials, (int64_t)P.red_wg * std::max<int64_t>((int64_t)P.outs.size(), 1) * 8);
   ALLOC(P.d_B, std::max<int64_t>((int64_t)P.outs.size(), 1) * 8);
 #undef ALLOC
@@ -177,6 +177,32 @@ int plan_alloc(Plan& P, bool dry) {
   if ((rc = upload(&P.d_outs, P.outs, B, dry))) return rc;
   if ((rc = upload(&P.d_out_norm, P.out_norm, B, dry))) return rc;
   if ((rc = upload(&P.d_f2idx, P.f2idx, B, dry))) return rc;
+  if (P.shot_noise) {
+    // shot noise (Sec. 4.2, eqs. 44-46): second spectra, H spectra, the cube of
+    // ones, scalars, the shell mode list, alias sums and term combos
+    const int64_t g3 = ng * PG * PG * PG * c;
+    if ((rc = dalloc((void**)&P.d_scal_n, (int64_t)sizeof(DevScalars), B, dry))) return rc;
+    if ((rc = dalloc(&P.d_nspec, g3, B, dry))) return rc;
+    if ((rc = dalloc(&P.d_hspec, g3, B, dry))) return rc;
+    if ((rc = dalloc((void**)&P.d_sbar, std::max<int64_t>((int64_t)P.chans.size(), 1) * 8, B, dry))) return rc;
+    if ((rc = dalloc((void**)&P.d_Braw, std::max<int64_t>((int64_t)P.outs.size(), 1) * 8, B, dry))) return rc;
+    if ((rc = dalloc((void**)&P.d_ssums, std::max<int64_t>((int64_t)P.sn_combos.size() * P.nb * 2, 1) * 8, B, dry)))
+      return rc;
+    const int64_t pf3 = (int64_t)P.PF * P.PF * P.PF;
+    if (P.precision == TSB_FP64) {
+      std::vector<double> ones(2 * pf3, 0.0);
+      for (int64_t i = 0; i < pf3; ++i) ones[2 * i] = 1.0;
+      if ((rc = upload((double**)&P.d_ucube, ones, B, dry))) return rc;
+    } else {
+      std::vector<float> ones(2 * pf3, 0.0f);
+      for (int64_t i = 0; i < pf3; ++i) ones[2 * i] = 1.0f;
+      if ((rc = upload((float**)&P.d_ucube, ones, B, dry))) return rc;
+    }
+    if ((rc = upload(&P.d_shell_modes, P.sn_mode_list, B, dry))) return rc;
+    if ((rc = upload(&P.d_shell_start, P.sn_mode_start, B, dry))) return rc;
+    if ((rc = upload(&P.d_cw2_tab, P.sn_alias, B, dry))) return rc;
+    if ((rc = upload(&P.d_sn_combos, P.sn_combos, B, dry))) return rc;
+  }
   return TSB_OK;
 }
 
@@ -196,7 +222,9 @@ void plan_free(Plan& P) {
                   P.d_qgroups, P.d_outs, P.d_out_norm, P.d_partials, P.d_B, P.d_scal, P.d_sum_partials,
                   P.d_bk_count, P.d_bk_start, P.d_scan_part, P.d_keys, P.d_rec,
                   P.d_f2idx, P.d_yspec, P.d_axis_tab, P.d_tile_hslot, P.d_heavy_tile,
-                  P.d_heavy, P.d_work, P.d_hostcat};
+                  P.d_heavy, P.d_work, P.d_hostcat, P.d_scal_n, P.d_nspec, P.d_hspec, P.d_ucube,
+                  P.d_sbar, P.d_Braw, P.d_ssums, P.d_shell_modes, P.d_shell_start, P.d_cw2_tab,
+                  P.d_sn_combos};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
 }
@@ -315,14 +343,17 @@ int set_device(const Plan& P) {
   return TSB_OK;
 }
 
-int run_front(Plan& P, const tsb_catalog* data, const tsb_catalog* rand, hipStream_t s) {
+// Weights and bucketing of a measurement. Host catalogues are copied into the
+// plan's buffers first (described in `staged`); *data_out / *rand_out (if
+// given) receive the device catalogues the kernels read.
+int run_front(Plan& P, const tsb_catalog* data, const tsb_catalog* rand, hipStream_t s, tsb_catalog* staged,
+              const tsb_catalog** data_out, const tsb_catalog** rand_out) {
   int rc;
   if ((rc = set_device(P))) return rc;
   if ((rc = check_catalog(data, "data"))) return rc;
   if (!P.box_mode && (rc = check_catalog(rand, "randoms"))) return rc;
   if (data->on_device && (rc = check_device_arrays(P, data, "data"))) return rc;
   if (!P.box_mode && rand->on_device && (rc = check_device_arrays(P, rand, "randoms"))) return rc;
-  tsb_catalog staged[2];
   if (!data->on_device || (!P.box_mode && !rand->on_device)) {
     const tsb_catalog* in[2] = {data, P.box_mode ? nullptr : rand};
     if ((rc = stage_host_catalogs(P, in, staged, s))) return rc;
@@ -333,7 +364,14 @@ int run_front(Plan& P, const tsb_catalog* data, const tsb_catalog* rand, hipStre
   if ((rc = ensure_particles(P, ntot))) return rc;
   if ((rc = run_prep(P, data, P.box_mode ? nullptr : rand, s))) return rc;
   if ((rc = run_assign(P, data, P.box_mode ? nullptr : rand, s))) return rc;
+  if (data_out) *data_out = data;
+  if (rand_out) *rand_out = rand;
   return TSB_OK;
+}
+
+int run_front(Plan& P, const tsb_catalog* data, const tsb_catalog* rand, hipStream_t s) {
+  tsb_catalog staged[2];
+  return run_front(P, data, rand, s, staged, nullptr, nullptr);
 }
 
 // Launches per stage in one measurement (for per-launch averages).
@@ -432,8 +470,16 @@ int launch_back(Plan& P, hipStream_t s) {
   return TSB_OK;
 }
 
+// Bytes per pinned result slot: the outputs and the device scalars; a
+// shot-noise plan adds the raw estimator, the i = j != k term, Sbar per channel
+// and the shell sums.
+size_t shot_extra(const Plan& P) {
+  if (!P.shot_noise) return 0;
+  return (P.outs.size() * 2 + P.chans.size() + P.sn_combos.size() * P.nb * 2) * 8;
+}
+
 size_t result_stride(const Plan& P) {
-  return ((P.outs.size() * 8 + sizeof(DevScalars)) + 255) / 256 * 256;
+  return ((P.outs.size() * 8 + sizeof(DevScalars) + shot_extra(P)) + 255) / 256 * 256;
 }
 
 // Pinned result slots; growing them waits for the plan's work to drain.
@@ -450,15 +496,70 @@ int ensure_result_slots(Plan& P, int n) {
 
 // One measurement enqueued on s; its outputs and scalars land in pinned slot
 // `slot` when s reaches that point.
+// The inverse transforms and the reduction of the raw estimator (eq. 41).
+int run_reduction_part(Plan& P, hipStream_t s) {
+  int rc;
+  if ((rc = run_inverse(P, s))) return rc;
+  if (P.fused) {
+    if (!P.outs.empty()) {
+      if ((rc = run_fused(P, s))) return rc;
+      if ((rc = run_reduce_final(P, s))) return rc;
+    }
+  } else if ((rc = run_reduce(P, s))) {
+    return rc;
+  }
+  return TSB_OK;
+}
+
+// A shot-noise plan's measurement, launched directly (its passes interleave
+// particle-count-dependent and fixed-shape launches): the estimator's pass,
+// Sbar, the w^2-weighted pass of the N fields, the k-space terms, the raw
+// estimator's reduction (kept in d_Braw) and the i = j != k term's reduction.
+int run_shot_measure(Plan& P, const tsb_catalog* data, const tsb_catalog* rand, hipStream_t s) {
+  int rc;
+  tsb_catalog staged[2];
+  if ((rc = run_front(P, data, rand, s, staged, &data, &rand))) return rc;
+  if ((rc = run_assign_back(P, s))) return rc;
+  if ((rc = run_forward(P, s))) return rc;
+  if ((rc = run_sbar(P, data, P.box_mode ? nullptr : rand, s))) return rc;
+  P.wpass = 1;
+  rc = run_prep(P, data, P.box_mode ? nullptr : rand, s);
+  if (!rc) rc = run_assign(P, data, P.box_mode ? nullptr : rand, s);
+  if (!rc) rc = run_assign_back(P, s);
+  if (!rc) rc = run_forward(P, s);
+  P.wpass = 0;
+  if (rc) return rc;
+  if ((rc = run_shot_kspace(P, s))) return rc;
+  if ((rc = run_reduction_part(P, s))) return rc;
+  if (!P.outs.empty())
+    TSB_HIP(hipMemcpyAsync(P.d_Braw, P.d_B, P.outs.size() * 8, hipMemcpyDeviceToDevice, s));
+  P.spass = 1;
+  rc = run_reduction_part(P, s);
+  P.spass = 0;
+  return rc;
+}
+
 int enqueue_measure(Plan& P, const tsb_catalog* data, const tsb_catalog* rand, hipStream_t s, int slot) {
   int rc;
   if (slot < 0 || slot >= P.res_slots) return fail(TSB_E_ARG, "result slot out of range");
-  if ((rc = run_front(P, data, rand, s))) return rc;
-  if ((rc = launch_back(P, s))) return rc;
+  if (P.shot_noise) {
+    if ((rc = run_shot_measure(P, data, rand, s))) return rc;
+  } else {
+    if ((rc = run_front(P, data, rand, s))) return rc;
+    if ((rc = launch_back(P, s))) return rc;
+  }
   char* base = (char*)P.h_res + result_stride(P) * (size_t)slot;
-  if (!P.outs.empty())
-    TSB_HIP(hipMemcpyAsync(base, P.d_B, P.outs.size() * 8, hipMemcpyDeviceToHost, s));
-  TSB_HIP(hipMemcpyAsync(base + P.outs.size() * 8, P.d_scal, sizeof(DevScalars), hipMemcpyDeviceToHost, s));
+  const size_t no = P.outs.size() * 8;
+  if (!P.outs.empty()) TSB_HIP(hipMemcpyAsync(base, P.d_B, no, hipMemcpyDeviceToHost, s));
+  TSB_HIP(hipMemcpyAsync(base + no, P.d_scal, sizeof(DevScalars), hipMemcpyDeviceToHost, s));
+  if (P.shot_noise) {
+    char* x = base + no + sizeof(DevScalars);
+    if (!P.outs.empty()) TSB_HIP(hipMemcpyAsync(x, P.d_Braw, no, hipMemcpyDeviceToHost, s));
+    TSB_HIP(hipMemcpyAsync(x + no, P.d_sbar, P.chans.size() * 8, hipMemcpyDeviceToHost, s));
+    if (!P.sn_combos.empty())
+      TSB_HIP(hipMemcpyAsync(x + no + P.chans.size() * 8, P.d_ssums, P.sn_combos.size() * P.nb * 16,
+                             hipMemcpyDeviceToHost, s));
+  }
   return TSB_OK;
 }
 
@@ -474,10 +575,19 @@ int finish_measure(Plan& P, int slot, double* B_out, double* I_out, double* alph
   if (!(h.I > 0.0) || !std::isfinite(h.I))
     return fail(TSB_E_INPUT, "the normalisation I is not positive (no weighted particles or randoms): B is undefined");
   const size_t nbb = (size_t)P.nb * P.nb;
-  for (size_t i = 0; i < P.mult.size() * nbb; ++i) B_out[i] = std::numeric_limits<double>::quiet_NaN();
-  for (size_t o = 0; o < P.outs.size(); ++o) {
-    const OutEntry& e = P.outs[o];
-    B_out[(size_t)e.mu * nbb + (size_t)e.b1 * P.nb + e.b2] = hb[o];
+  if (P.shot_noise) {
+    // slot layout: S_ij (the last reduction), scalars, raw B, Sbar, shell sums
+    const char* x = base + P.outs.size() * 8 + sizeof(DevScalars);
+    const double* braw = (const double*)x;
+    const double* sbar = braw + P.outs.size();
+    const double* sums = sbar + P.chans.size();
+    shot_finish(P, sbar, sums, braw, hb, h.I, B_out);
+  } else {
+    for (size_t i = 0; i < P.mult.size() * nbb; ++i) B_out[i] = std::numeric_limits<double>::quiet_NaN();
+    for (size_t o = 0; o < P.outs.size(); ++o) {
+      const OutEntry& e = P.outs[o];
+      B_out[(size_t)e.mu * nbb + (size_t)e.b1 * P.nb + e.b2] = hb[o];
+    }
   }
   if (I_out) *I_out = h.I;
   if (alpha_out) *alpha_out = h.alpha;
@@ -650,8 +760,13 @@ int tsb_plan_get_info(const tsb_plan* plan, tsb_plan_info* info) {
 
 int tsb_plan_shot_noise(const tsb_plan* plan, double* S_out, double* S_ijk_out) {
   if (!plan || !S_out) return fail(TSB_E_ARG, "NULL argument");
-  if (!plan->p.shot_noise) return fail(TSB_E_ARG, "the plan does not subtract the shot noise");
-  return fail(TSB_E_UNSUPPORTED, "shot-noise subtraction is not built yet");
+  const Plan& P = plan->p;
+  if (!P.shot_noise) return fail(TSB_E_ARG, "the plan does not subtract the shot noise");
+  const size_t n = P.mult.size() * (size_t)P.nb * P.nb;
+  if (P.last_S.size() != n) return fail(TSB_E_ARG, "no measurement yet");
+  std::copy(P.last_S.begin(), P.last_S.end(), S_out);
+  if (S_ijk_out) std::copy(P.last_Sij.begin(), P.last_Sij.end(), S_ijk_out);
+  return TSB_OK;
 }
 
 int tsb_plan_nmode(const tsb_plan* plan, int64_t* nmode, double* k_eff) {
@@ -1450,6 +1565,7 @@ extern "C" int tsb_measure_noalloc(tsb_plan* plan, const tsb_catalog* data, cons
   if (!P.box_mode && (rc = check_catalog(randoms, "randoms"))) return rc;
   if (!data->on_device || (!P.box_mode && !randoms->on_device))
     return fail(TSB_E_ARG, "tsb_measure_noalloc takes device catalogues only (on_device = 1)");
+  if (P.shot_noise) return fail(TSB_E_UNSUPPORTED, "tsb_measure_noalloc does not run shot-noise plans");
   if ((rc = check_device_arrays(P, data, "data"))) return rc;
   if (!P.box_mode && (rc = check_device_arrays(P, randoms, "randoms"))) return rc;
   const WorkspaceState saved(P);

@@ -29,20 +29,28 @@ constexpr int kPrepBlocks = 512;
 struct CatPtrs {
   const float *x, *y, *z, *w, *nbar;
   int64_t n;
+  int wpow;   // 1: the weight w; 2: w^2 (the w^2-weighted fields N_L^M of the shot noise)
 };
 
-CatPtrs cat_ptrs(const tsb_catalog* c) {
+// The catalogue as the kernels read it; the plan's pass decides the weight power.
+CatPtrs cat_ptrs(const Plan& P, const tsb_catalog* c) {
   CatPtrs p{};
   if (c) {
     p.x = c->x; p.y = c->y; p.z = c->z; p.w = c->w; p.nbar = c->nbar; p.n = c->n;
   }
+  p.wpow = P.wpass ? 2 : 1;
   return p;
 }
 
+// The scalars of the plan's current pass: the measurement's own, or those of
+// the w^2-weighted pass (its fixed-point scale; its alpha is -alpha^2, so that
+// randoms enter the N fields with +alpha^2 w^2, eq. 46).
+DevScalars* pass_scalars(const Plan& P) { return P.wpass ? P.d_scal_n : P.d_scal; }
+
 __device__ inline double particle_weight(const CatPtrs& c, int64_t i, double P0) {
   double w = c.w ? (double)c.w[i] : 1.0;
-  if (c.nbar && P0 > 0.0) w = w / (1.0 + (double)c.nbar[i] * P0);
-  return w;
+  if (c.nbar && P0 > 0.0) w = w / (1.0 + (double)c.nbar[i] * P0);   // Sec. 5.2, eq. 54
+  return c.wpow == 2 ? w * w : w;
 }
 
 // ----------------------------------------------------------------------------
@@ -115,7 +123,8 @@ __global__ void __launch_bounds__(kBlock) prep_kernel(PrepArgs a) {
 
 __global__ void __launch_bounds__(kBlock) prep_final_kernel(const double* partials, int nblocks,
                                                             DevScalars* scal, int box_mode,
-                                                            double n3, double volume, int fixed_bits) {
+                                                            double n3, double volume, int fixed_bits,
+                                                            const DevScalars* main) {
   __shared__ double sh[kPrepVals * kBlock];
   double v[kPrepVals] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
   for (int b = threadIdx.x; b < nblocks; b += kBlock) {
@@ -128,7 +137,8 @@ __global__ void __launch_bounds__(kBlock) prep_final_kernel(const double* partia
     scal->sum_w_ran = v[1];
     scal->sum_abs = v[2];
     scal->sum_abs_ran = v[3];
-    const double alpha = box_mode ? 0.0 : (v[1] != 0.0 ? v[0] / v[1] : 0.0);   // Sec. 4.1
+    double alpha = box_mode ? 0.0 : (v[1] != 0.0 ? v[0] / v[1] : 0.0);   // Sec. 4.1
+    if (main) alpha = -main->alpha * main->alpha;   // w^2 pass: randoms carry +alpha^2 (eq. 46)
     scal->alpha = alpha;
     // |y_L^M| <= 1 (Racah normalisation), so |c| <= max |w| (data) and
     // |alpha| max |w| (randoms)
@@ -144,7 +154,7 @@ __global__ void __launch_bounds__(kBlock) prep_final_kernel(const double* partia
     }
     scal->scale = ldexp(1.0, e);
     scal->inv_scale = ldexp(1.0, -e);
-    scal->mean_cell = box_mode ? v[0] / n3 : 0.0;
+    scal->mean_cell = box_mode && !main ? v[0] / n3 : 0.0;   // the N fields have no mean term
     scal->I = box_mode ? v[0] * v[0] * v[0] / (volume * volume) : 0.0;   // Sec. 4.4
   }
 }
@@ -432,6 +442,8 @@ __global__ void __launch_bounds__(kBlock) bucket_fill_kernel(FillArgs<T, NCH> a)
     ru[2] = u[2];
     double cv[NCH];
     channel_values<NCH>(a.ci, c.x[j], c.y[j], c.z[j], ok ? w : 0.0, ran, alpha, cv);
+    // the w^2 pass builds no normalisation: its randoms channel stays empty
+    if (a.b.d.wpow == 2 && a.ci.nch < NCH) cv[a.ci.nch] = 0.0;
     T* rc = a.rec.c(slot);
 #pragma unroll
     for (int ch = 0; ch < NCH; ++ch)
@@ -1207,8 +1219,8 @@ int grid_blocks(int64_t n) {
 
 int run_prep(Plan& P, const tsb_catalog* data, const tsb_catalog* rand, hipStream_t s) {
   PrepArgs a{};
-  a.d = cat_ptrs(data);
-  a.r = P.box_mode ? CatPtrs{} : cat_ptrs(rand);
+  a.d = cat_ptrs(P, data);
+  a.r = P.box_mode ? CatPtrs{} : cat_ptrs(P, rand);
   a.P0 = P.P0;
   a.inv_h = (double)P.N / P.L;
   for (int i = 0; i < 3; ++i) {
@@ -1218,15 +1230,16 @@ int run_prep(Plan& P, const tsb_catalog* data, const tsb_catalog* rand, hipStrea
   a.N = P.N;
   a.box_mode = P.box_mode;
   a.local = P.los_kind == TSB_LOS_LOCAL;
-  a.scal = P.d_scal;
+  DevScalars* scal = pass_scalars(P);
+  a.scal = scal;
   a.partials = P.d_sum_partials;
   prof_begin(P, kStWeights, s);
-  hipLaunchKernelGGL(zero_scal_kernel, dim3(1), dim3(64), 0, s, P.d_scal);
+  hipLaunchKernelGGL(zero_scal_kernel, dim3(1), dim3(64), 0, s, scal);
   hipLaunchKernelGGL(prep_kernel, dim3(kPrepBlocks), dim3(kBlock), 0, s, a);
   const double n3 = (double)P.N * P.N * P.N;
   hipLaunchKernelGGL(prep_final_kernel, dim3(1), dim3(kBlock), 0, s, (const double*)P.d_sum_partials,
-                     kPrepBlocks, P.d_scal, P.box_mode, n3, P.L * P.L * P.L,
-                     P.precision == TSB_FP64 ? 61 : 51);
+                     kPrepBlocks, scal, P.box_mode, n3, P.L * P.L * P.L,
+                     P.precision == TSB_FP64 ? 61 : 51, P.wpass ? (const DevScalars*)P.d_scal : nullptr);
   prof_end(P, kStWeights, s);
   TSB_HIP(hipGetLastError());
   return TSB_OK;
@@ -1354,7 +1367,7 @@ int assign_front_impl(Plan& P, const BucketArgs& b, const ChanInfo& ci, hipStrea
         f.zslot = 2 * gr + 1;
     }
     if (!P.box_mode) f.slot_of[ci.nch] = 2 * (int)P.grids.size();
-    f.scal = P.d_scal;
+    f.scal = pass_scalars(P);
     hipLaunchKernelGGL((bucket_fill_kernel<T, NCH>), dim3(grid_blocks(ntot)), dim3(kBlock), 0, s, f);
   }
   prof_end(P, kStBucket, s);
@@ -1390,7 +1403,7 @@ int assign_back_impl(Plan& P, const ChanInfo& ci, hipStream_t s) {
   a.wr = P.box_mode ? -1 : nw - 1;
   a.wmax = P.p == 3 ? 0.421875 : 1.0;
   a.start = P.d_bk_start;
-  a.scal = P.d_scal;
+  a.scal = pass_scalars(P);
   a.out = P.d_grid;
   a.tile_I = P.d_sum_partials;
   a.nr = tile_ranges(P.NT, a.rd, a.rcl, a.rch);
@@ -1415,7 +1428,7 @@ int assign_back_impl(Plan& P, const ChanInfo& ci, hipStream_t s) {
   if (!P.box_mode) {
     const double vc = P.L * P.L * P.L / ((double)P.N * P.N * P.N);
     hipLaunchKernelGGL(norm_final_kernel, dim3(1), dim3(kBlock), 0, s, (const double*)P.d_sum_partials,
-                       ntiles, P.d_scal, vc);
+                       ntiles, pass_scalars(P), vc);
   }
   prof_end(P, kStAssign, s);
   TSB_HIP(hipGetLastError());
@@ -1424,8 +1437,8 @@ int assign_back_impl(Plan& P, const ChanInfo& ci, hipStream_t s) {
 
 int run_assign(Plan& P, const tsb_catalog* data, const tsb_catalog* rand, hipStream_t s) {
   BucketArgs b{};
-  b.d = cat_ptrs(data);
-  b.r = P.box_mode ? CatPtrs{} : cat_ptrs(rand);
+  b.d = cat_ptrs(P, data);
+  b.r = P.box_mode ? CatPtrs{} : cat_ptrs(P, rand);
   b.inv_h = (double)P.N / P.L;
   for (int i = 0; i < 3; ++i) b.origin[i] = P.origin[i];
   b.P0 = P.P0;
@@ -1503,6 +1516,90 @@ int run_unpack_grids(Plan& P, void* out, hipStream_t s) {
   return TSB_OK;
 }
 
+// Sbar_L^M of the shot noise (Sec. 4.2, eq. 46): per real channel c (part of
+// w y_L^M*), sum_gal w^3 ch_c(x^) - alpha^3 sum_ran w^3 ch_c(x^), as FP64 sums per
+// block added in a fixed order.
+template <int NCH>
+struct SbarArgs {
+  CatPtrs d, r;
+  double P0;
+  ChanInfo ci;
+  const DevScalars* scal;
+  double* partials;   // [gridDim][nch]
+};
+
+template <int NCH>
+__global__ void __launch_bounds__(kBlock) sbar_kernel(SbarArgs<NCH> a) {
+  __shared__ double sh[kBlock];
+  const double alpha = a.scal->alpha;
+  double acc[NCH];
+#pragma unroll
+  for (int c = 0; c < NCH; ++c) acc[c] = 0.0;
+  const int64_t ntot = a.d.n + a.r.n;
+  for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < ntot; i += (int64_t)gridDim.x * kBlock) {
+    const bool ran = i >= a.d.n;
+    const CatPtrs& c = ran ? a.r : a.d;
+    const int64_t j = ran ? i - a.d.n : i;
+    const double w = particle_weight(c, j, a.P0);
+    if (!isfinite(w) || !isfinite((double)c.x[j]) || !isfinite((double)c.y[j]) || !isfinite((double)c.z[j]))
+      continue;   // reported by the weight pass
+    double cv[NCH];
+    // w^3 and alpha^3: galaxies w^3 y*, randoms -alpha^3 w^3 y*
+    channel_values<NCH>(a.ci, c.x[j], c.y[j], c.z[j], w * w * w, ran, alpha * alpha * alpha, cv);
+#pragma unroll
+    for (int ch = 0; ch < NCH; ++ch) acc[ch] += ch < a.ci.nch ? cv[ch] : 0.0;
+  }
+  for (int ch = 0; ch < a.ci.nch; ++ch) {
+    double v = 0.0;
+#pragma unroll
+    for (int k = 0; k < NCH; ++k) v = k == ch ? acc[k] : v;
+    sh[threadIdx.x] = v;
+    __syncthreads();
+    for (int st = kBlock / 2; st > 0; st >>= 1) {
+      if (threadIdx.x < st) sh[threadIdx.x] += sh[threadIdx.x + st];
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) a.partials[(size_t)blockIdx.x * a.ci.nch + ch] = sh[0];
+    __syncthreads();
+  }
+}
+
+__global__ void __launch_bounds__(kBlock) sbar_final_kernel(const double* partials, int nblocks, int nch,
+                                                            double* out) {
+  __shared__ double sh[kBlock];
+  for (int ch = 0; ch < nch; ++ch) {
+    double v = 0.0;
+    for (int b = threadIdx.x; b < nblocks; b += kBlock) v += partials[(size_t)b * nch + ch];
+    sh[threadIdx.x] = v;
+    __syncthreads();
+    for (int st = kBlock / 2; st > 0; st >>= 1) {
+      if (threadIdx.x < st) sh[threadIdx.x] += sh[threadIdx.x + st];
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) out[ch] = sh[0];
+    __syncthreads();
+  }
+}
+
+template <int NCH>
+int sbar_impl(Plan& P, const tsb_catalog* data, const tsb_catalog* rand, hipStream_t s) {
+  SbarArgs<NCH> a{};
+  const int saved = P.wpass;
+  P.wpass = 0;
+  a.d = cat_ptrs(P, data);
+  a.r = P.box_mode ? CatPtrs{} : cat_ptrs(P, rand);
+  P.wpass = saved;
+  a.P0 = P.P0;
+  if (int rc = chan_info(P, &a.ci)) return rc;
+  a.scal = P.d_scal;
+  a.partials = P.d_sum_partials;   // (free between the weight pass and the tiles)
+  hipLaunchKernelGGL((sbar_kernel<NCH>), dim3(kPrepBlocks), dim3(kBlock), 0, s, a);
+  hipLaunchKernelGGL(sbar_final_kernel, dim3(1), dim3(kBlock), 0, s, (const double*)P.d_sum_partials, kPrepBlocks,
+                     a.ci.nch, P.d_sbar);
+  TSB_HIP(hipGetLastError());
+  return TSB_OK;
+}
+
 // Clear `bytes` (a multiple of 8) of device memory with a kernel (no memset
 // node: the call may be captured into a graph).
 int run_fill_zero(void* p, int64_t bytes, hipStream_t s) {
@@ -1511,6 +1608,14 @@ int run_fill_zero(void* p, int64_t bytes, hipStream_t s) {
   hipLaunchKernelGGL(zero_u64_kernel, dim3(grid_blocks(n)), dim3(kBlock), 0, s, (unsigned long long*)p, n);
   TSB_HIP(hipGetLastError());
   return TSB_OK;
+}
+
+int run_sbar(Plan& P, const tsb_catalog* data, const tsb_catalog* rand, hipStream_t s) {
+  const int nch = (int)P.chans.size();
+  if (nch <= 8) return sbar_impl<8>(P, data, rand, s);
+  if (nch <= 16) return sbar_impl<16>(P, data, rand, s);
+  if (nch <= 24) return sbar_impl<24>(P, data, rand, s);
+  return sbar_impl<kMaxCh>(P, data, rand, s);
 }
 
 int run_ynode_fill(Plan& P, hipStream_t s) {

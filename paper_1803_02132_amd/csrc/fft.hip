@@ -510,6 +510,16 @@ int forward_impl(Plan& P, hipStream_t s) {
   }
   prof_begin(P, kStCombine, s);
   const int64_t row_pairs = ((int64_t)P.grids.size() * PG * PG + 1) / 2;   // two rows per workgroup
+  if (P.wpass) {
+    // the w^2-weighted N fields of the shot noise: a pure particle sum (no mean
+    // term, DC kept), into their own spectra
+    hipLaunchKernelGGL(combine_kernel<T>, dim3((int)std::min<int64_t>(row_pairs, 8192)), dim3(kBlock), 0, s,
+                       (const T2*)P.d_t3, (T2*)P.d_nspec, (int)P.grids.size(), P.copies, RG, 0,
+                       (const double*)P.d_axis_tab, (const T2*)nullptr, (const DevScalars*)P.d_scal_n);
+    prof_end(P, kStCombine, s);
+    TSB_HIP(hipGetLastError());
+    return TSB_OK;
+  }
   hipLaunchKernelGGL(combine_kernel<T>, dim3((int)std::min<int64_t>(row_pairs, 8192)), dim3(kBlock), 0, s,
                      (const T2*)P.d_t3, (T2*)P.d_spec, (int)P.grids.size(), P.copies, RG, P.box_mode, (const double*)P.d_axis_tab,
                      P.yspec_ready ? (const T2*)P.d_yspec : (const T2*)nullptr, (const DevScalars*)P.d_scal);
@@ -590,7 +600,9 @@ int inverse_impl(Plan& P, hipStream_t s) {
     pre.pre = P.n2maxG >= 0 ? 1 : 0;
     pre.n2max = P.n2maxG;
     const int64_t pg3 = (int64_t)P.PG * P.PG * P.PG;
-    if ((rc = inverse_chain<T>(P, kStInvGX, (const T2*)P.d_spec, pg3, (int)P.grids.size(), P.RG, pre,
+    // the shot noise's i = j != k term takes the H spectra in place of dn_L^M
+    const void* gsrc = P.spass ? P.d_hspec : P.d_spec;
+    if ((rc = inverse_chain<T>(P, kStInvGX, (const T2*)gsrc, pg3, (int)P.grids.size(), P.RG, pre,
                                fields + P.g_offset, true, s)))
       return rc;
   }
@@ -604,7 +616,9 @@ int inverse_impl(Plan& P, hipStream_t s) {
     pre.nkinds = (int)P.fkinds.size();
     ylm_norm_table(pre.ynorm);
     // with the fused reduction the z pass of F happens inside the reduction
-    if ((rc = inverse_chain<T>(P, kStInvFX, (const T2*)P.d_dcube, 0, nf, P.RF, pre, fields, !P.fused, s)))
+    // (the shot noise's unit shell fields f_l^m filter a cube of ones)
+    const void* fsrc = P.spass ? P.d_ucube : P.d_dcube;
+    if ((rc = inverse_chain<T>(P, kStInvFX, (const T2*)fsrc, 0, nf, P.RF, pre, fields, !P.fused, s)))
       return rc;
   }
   return TSB_OK;

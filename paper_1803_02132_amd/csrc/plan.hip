@@ -20,6 +20,8 @@ long double lfact(int n) {
   return r;
 }
 
+}  // namespace
+
 // Wigner 3j symbol by Racah's formula in extended precision (Sec. 2, eq. 11).
 double three_j(int j1, int j2, int j3, int m1, int m2, int m3) {
   if (m1 + m2 + m3 != 0) return 0.0;
@@ -43,6 +45,8 @@ double three_j(int j1, int j2, int j3, int m1, int m2, int m3) {
   return (double)v;
 }
 
+namespace {
+
 bool is_2a3b(int n) {
   if (n <= 0) return false;
   while (n % 2 == 0) n /= 2;
@@ -50,16 +54,16 @@ bool is_2a3b(int n) {
   return n == 1;
 }
 
+}  // namespace
+
 // y_L^M(d) for any M via y^{-M} = (-1)^M conj(y^M), with the device routine.
-cd ylm_any(int l, int m, const double* d, const double* norm) {
+std::complex<double> ylm_any(int l, int m, const double* d, const double* norm) {
   double re, im;
   ylm_pos_m(l, std::abs(m), d[0], d[1], d[2], norm, &re, &im);
   cd v(re, im);
   if (m < 0) v = ((std::abs(m) % 2) ? -1.0 : 1.0) * std::conj(v);
   return v;
 }
-
-}  // namespace
 
 void ylm_norm_table(double* norm) {
   for (int l = 0; l <= kMaxEll; ++l)
@@ -92,7 +96,6 @@ int plan_build(Plan& P) {
   if (P.vertex == TSB_VERTEX_X1 && P.los_kind == TSB_LOS_LOCAL)
     return fail(TSB_E_UNSUPPORTED, "the LOS at the first vertex is not built yet");
   if (P.estimator != TSB_BISPECTRUM) return fail(TSB_E_UNSUPPORTED, "the 3PCF and window estimators are not built yet");
-  if (P.shot_noise) return fail(TSB_E_UNSUPPORTED, "shot-noise subtraction is not built yet");
   if (P.mult.empty()) return fail(TSB_E_ARG, "no multipoles");
   if (P.los_kind != TSB_LOS_GLOBAL && P.los_kind != TSB_LOS_LOCAL)
     return fail(TSB_E_ARG, "los kind must be global (0) or local (1)");
@@ -429,6 +432,11 @@ int plan_build(Plan& P) {
     }
   }
   P.g_offset = P.fused ? 0 : (int64_t)P.nb * (int64_t)P.fkinds.size() * P.M * P.M * P.M;
+  if (P.shot_noise) {
+    if (P.estimator != TSB_BISPECTRUM) return fail(TSB_E_UNSUPPORTED, "shot-noise subtraction is for the bispectrum");
+    if (int rc = shot_plan(P)) return rc;
+    P.use_graph = false;   // its passes are launched directly
+  }
   return TSB_OK;
 }
 

@@ -4,6 +4,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <complex>
 #include <cstdint>
 #include <string>
 #include <vector>
@@ -136,6 +137,31 @@ struct Plan {
   double* d_partials = nullptr;
   double* d_B = nullptr;
   DevScalars* d_scal = nullptr;
+  // shot noise (Sec. 4.2, eqs. 44-46)
+  int wpass = 0;                // 1 while the w^2-weighted fields N are assigned and transformed
+  int spass = 0;                // 1 while the i = j != k term runs the inverse transforms and reduction
+  DevScalars* d_scal_n = nullptr;   // scalars of the w^2 pass
+  void* d_nspec = nullptr;      // combined spectra of the N channels [ngrid][PG^3]
+  void* d_hspec = nullptr;      // H spectra: dn_L^M N_0^0* - Sbar C/W^2 [ngrid][PG^3]
+  void* d_ucube = nullptr;      // 1 on the F cube (the unit shell fields f_l^m) [PF^3]
+  double* d_sbar = nullptr;     // Sbar per real channel [nch]
+  double* d_Braw = nullptr;     // the raw estimator while the shot-noise term runs [outputs]
+  double* d_ssums = nullptr;    // shell sums of y_l^m* (dn N_L^M* - Sbar C/W^2): [combo][bin] complex
+  double* d_ssum_part = nullptr;   // their per-block partials
+  int* d_shell_modes = nullptr;     // F-cube indices of the shell modes, bin by bin
+  int* d_shell_start = nullptr;     // [n_bins + 1] offsets into d_shell_modes
+  double* d_cw2_tab = nullptr;      // per stored axis mode: A_p, B_p (alias sums, eq. 45 reading)
+  struct SnCombo { int l, m, L, M; };   // sum_{k in b} y_l^m*(k^) P_L^M(k)
+  std::vector<SnCombo> sn_combos;
+  SnCombo* d_sn_combos = nullptr;
+  std::vector<double> sn_ybar;          // ybar_l^m*(b): [(l, m) index][bin] complex (re, im)
+  std::vector<int> sn_ybar_index;       // (l, m) -> index into sn_ybar, l(l+1) + m
+  struct SnTerm { int mu, m1, m2, M; double w3j; int cjk, cik; };   // complex terms of eq. 45 and their combos
+  std::vector<SnTerm> sn_terms;
+  std::vector<double> h_sn;             // host copies after a measurement: Sbar, sums, raw B, S_ij
+  std::vector<double> last_S, last_Sij; // the last measurement's S and S_ij ([n_mult][nb][nb])
+  std::vector<int> sn_mode_list, sn_mode_start;   // host copies of the shell mode list
+  std::vector<double> sn_alias;                   // host copy of the alias-sum table
   double* d_sum_partials = nullptr;   // per-block partial sums (prep and I)
   double* d_axis_tab = nullptr;   // per stored axis mode: 1/W_axis, cos and sin of pi n/N
   void* d_yspec = nullptr;      // box mode, local LOS: combined spectra of y_L^M*(x^_node) [ngrid][PG^3]
@@ -218,6 +244,8 @@ inline void prof_end(Plan& P, int st, hipStream_t s) {
 inline int64_t pad_line(int64_t n) { return (n + 15) / 16 * 16; }
 
 int plan_build(Plan& P);   // host planning (plan.hip)
+double three_j(int j1, int j2, int j3, int m1, int m2, int m3);   // Wigner 3j (Racah), plan.hip
+std::complex<double> ylm_any(int l, int m, const double* d, const double* norm);   // y_l^m(d), any m
 // (-1)^m sqrt((l-m)!/(l+m)!) at index l(l+1)/2 + m, l <= kMaxEll (45 entries)
 void ylm_norm_table(double* norm);
 int plan_alloc(Plan& P, bool dry = false);   // device buffers (api.hip); dry: sizes only
@@ -244,6 +272,11 @@ int64_t assign_heavy_bytes(const Plan& P);
 int assign_max_heavy(const Plan& P, int64_t other_bytes);
 int run_unpack_grids(Plan& P, void* out, hipStream_t s);
 int run_fill_zero(void* p, int64_t bytes, hipStream_t s);        // kernel fill, bytes % 8 == 0
+int run_sbar(Plan& P, const tsb_catalog* data, const tsb_catalog* rand, hipStream_t s);   // Sbar per channel
+int run_shot_kspace(Plan& P, hipStream_t s);   // H spectra and the shell sums (shot.hip)
+int shot_plan(Plan& P);                        // host tables of the shot noise (shot.hip)
+void shot_finish(Plan& P, const double* sbar, const double* sums, const double* Braw, const double* Sij,
+                 double I, double* B_out);      // host: S and B - S (shot.hip)
 int run_scatter_outputs(Plan& P, double* full, hipStream_t s);   // [n_mult][nb][nb], NaN where not computed
 
 // ---------------------------------------------------------------------------

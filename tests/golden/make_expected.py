@@ -6,6 +6,8 @@ from the HIP path. Run from the repository root:
 Outputs (small .npz files next to this script):
   box128_seed0.npz   every pair of the 128^3 box workload (500k particles,
                      Kaiser along a local LOS, TSC + interlacing, 000 110 202 112)
+  box128_shot_seed0.npz the shot noise of the same measurement (Sec. 4.2,
+                     eqs. 44-46): its four terms, S and B - S, every pair
   box256_seed48.npz  every shell pair of one 256^3 throughput mock (000, 202):
                      the configuration the benchmark times
   box512_seed7002.npz sampled shell pairs of a 512^3 request (the largest grid
@@ -16,7 +18,7 @@ Outputs (small .npz files next to this script):
                      shell, 20M randoms, FKP weights, 000 202 112 404)
   serve384_seed7001.npz sampled shell pairs of a 384^3 serving request
                      (2M particles, 000 110 202)
-Pass workload names (box128 box256 box512 survey256 serve384) to write only those files.
+Pass workload names (box128 box128_shot box256 box512 survey256 serve384) to write only those files.
 Each file also stores a checksum of the generated catalogue so the tests can
 confirm they regenerated the same input.
 """
@@ -32,6 +34,7 @@ sys.path.insert(0, ROOT)
 
 from mocks.lognormal import WORKLOADS, survey_workload, workload  # noqa: E402
 from oracle import estimator as est  # noqa: E402
+from oracle import shotnoise as sn  # noqa: E402
 
 # every shell once as b1 and once as b2: (b, b + 6 mod 25); the upper pairs
 # (b1 < b2) alone cover every shell, so the b1 <= b2 multipoles see all of them
@@ -80,6 +83,15 @@ def box128():
     print(f"box128 done in {time.time() - t0:.0f} s", flush=True)
 
 
+def box128_shot():
+    t0 = time.time()
+    spec, cat = workload("box128", seed=0)
+    res = sn.measure_shot_noise(oracle_plan(spec), cat)
+    np.savez(os.path.join(HERE, "box128_shot_seed0.npz"), B=res["B"], S=res["S"], S_iii=res["iii"],
+             S_ij=res["ij"], S_jk=res["jk"], S_ik=res["ik"], I=res["I"], checksum=catalogue_checksum(cat))
+    print(f"box128_shot done in {time.time() - t0:.0f} s", flush=True)
+
+
 def box256():
     t0 = time.time()
     spec, cat = workload("box256", seed=48)
@@ -114,7 +126,7 @@ def serve384():
     print(f"serve384 done in {time.time() - t0:.0f} s", flush=True)
 
 
-TARGETS = {"box128": box128, "box256": box256, "box512": box512, "survey256": survey256, "serve384": serve384}
+TARGETS = {"box128": box128, "box128_shot": box128_shot, "box256": box256, "box512": box512, "survey256": survey256, "serve384": serve384}
 
 
 if __name__ == "__main__":
