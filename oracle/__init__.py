@@ -17,6 +17,8 @@ decomposition formalism for the redshift-space bispectrum" (arXiv:1803.02132):
                    triangle sum that the FFT form rewrites (Sec. 4.2, eq. 35).
 * ``shotnoise`` -- the shot noise of the estimator: the coincident-index terms
                    of its particle description (Sec. 4.2, eqs. 43-46).
+* ``threepoint`` -- the three-point-function multipoles (Sec. 4.3, eqs. 47-48)
+                   and the window multipoles of the randoms (Sec. 6.1, eq. 58).
 
 Every function states the passage it follows. Readings of passages that are
 silent or ambiguous are listed (R1..R11) in ``estimator``'s header.
