@@ -65,9 +65,20 @@ enum { TSB_PAIRS_PAPER = 0,      /* b1 <= b2 when l1 == l2, else every (b1, b2) 
        TSB_PAIRS_UPPER = 1,      /* b1 <= b2 */
        TSB_PAIRS_DIAGONAL = 2,   /* b1 == b2 (Sec. 4.4, "diagonal" measurement) */
        TSB_PAIRS_ALL = 3 };
+/* Estimators. The 3PCF and the window multipoles average over the grid
+ * separation vectors r = H n (H = box_len / n) whose length falls in each
+ * r-bin (the configuration-space counterpart of the k-shells; the zero
+ * separation, if a bin holds r = 0, enters with y_l^m = delta_l0), so that
+ * zeta(b1, b2) is eq. 47 with those averages, computed in the FFT form of
+ * eq. 48 with F_l^m(x; b) = (1/V) sum_k e^{ik.x} dn(k) K_l^m(k; b) and
+ * K_l^m(k; b) = (1/N_r) sum_{n in b} y_l^m*(n^) e^{ik.Hn} (eq. 49 on the grid).
+ * N_r and the mean |r| per bin are what tsb_plan_nmode reports for them. The
+ * window multipoles need survey mode; the 3PCF shot noise (eq. 51) is not
+ * subtracted. */
 enum { TSB_BISPECTRUM = 0,       /* B_{l1 l2 L}(k1, k2) (Sec. 4.2, eq. 41) */
-       TSB_3PCF = 1,             /* zeta_{l1 l2 L}(r1, r2) (Sec. 4.3) */
-       TSB_WINDOW = 2 };         /* Q_{l1 l2 L}(r1, r2) from the randoms alone (Sec. 6.1) */
+       TSB_3PCF = 1,             /* zeta_{l1 l2 L}(r1, r2) (Sec. 4.3, eqs. 47-48) */
+       TSB_WINDOW = 2 };         /* Q_{l1 l2 L}(r1, r2) from the randoms alone (Sec. 6.1, eq. 58):
+                                    randoms weighted +alpha w, galaxies only fix alpha */
 
 /* Measurement grid (Sec. 4.2; Sec. 5.2 "Prescription"). Per-axis sizes: the
  * Nyquist frequency of axis a is pi n[a] / box_len[a] (W_mass, eq. 39). The
@@ -183,8 +194,10 @@ typedef struct tsb_plan tsb_plan;
  * (3j weights), shell table, N_mode, buffers. On success *out owns device
  * memory until tsb_plan_destroy. Errors: TSB_E_ARG (NULL pointers, sizes),
  * TSB_E_UNSUPPORTED (N not 2^a 3^b, multipole outside Table 1's rules, shells
- * reaching the Nyquist frequency, l > 8, a grid shape the library does not
- * cover), TSB_E_NOMEM, TSB_E_DEVICE. */
+ * reaching the Nyquist frequency or r-bins reaching half the box, l > 8, a
+ * grid shape the library does not cover, window multipoles in box mode, the
+ * 3PCF with shot_noise), TSB_E_NOMEM, TSB_E_DEVICE. 3PCF and window plans
+ * build their separation kernels K here (one inverse transform per F slot). */
 int tsb_plan_create(const tsb_grid* grid, const tsb_los* los, const tsb_kbins* bins,
                     const tsb_multipole* multipoles, int32_t n_multipoles,
                     const tsb_options* options, tsb_plan** out);

@@ -148,6 +148,9 @@ int plan_alloc(Plan& P, bool dry) {
   if (!dry) TSB_HIP(hipMemset(P.d_heavy, 0, (size_t)assign_heavy_bytes(P)));
   if (P.box_mode && P.los_kind == TSB_LOS_LOCAL && (rc = dalloc(&P.d_yspec, ng * PG * PG * PG * c, B, dry)))
     return rc;
+  if (P.estimator != TSB_BISPECTRUM &&
+      (rc = dalloc(&P.d_kslot, (int64_t)P.nb * (int64_t)P.fkinds.size() * P.PF * P.PF * P.PF * c, B, dry)))
+    return rc;
   (void)N;
   const bool f64 = P.precision == TSB_FP64;
   if ((rc = twiddles(&P.d_tw_n, P.N, f64, B, dry))) return rc;
@@ -224,7 +227,7 @@ void plan_free(Plan& P) {
                   P.d_f2idx, P.d_yspec, P.d_axis_tab, P.d_tile_hslot, P.d_heavy_tile,
                   P.d_heavy, P.d_work, P.d_hostcat, P.d_scal_n, P.d_nspec, P.d_hspec, P.d_ucube,
                   P.d_sbar, P.d_Braw, P.d_ssums, P.d_shell_modes, P.d_shell_start, P.d_cw2_tab,
-                  P.d_sn_combos};
+                  P.d_sn_combos, P.d_kslot};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
 }
@@ -735,6 +738,7 @@ int tsb_plan_create(const tsb_grid* grid, const tsb_los* los, const tsb_kbins* b
   }
   rc = plan_alloc(P);
   if (!rc) rc = init_yspec(P);
+  if (!rc) rc = run_separation_kernels(P, nullptr);
   if (rc) {
     plan_free(P);
     delete h;

@@ -354,6 +354,7 @@ __global__ void __launch_bounds__(kBlock) scan_out_kernel(const int* in, int64_t
 struct ChanInfo {
   int nch;                     // real channels (the survey randoms channel is nch)
   int local;
+  int window;                  // window multipoles: randoms +alpha, galaxies 0 (Sec. 6.1, eq. 58)
   double obs[3];
   int chL[kMaxCh], chM[kMaxCh], chPart[kMaxCh];
   double ynorm[45];
@@ -362,7 +363,8 @@ struct ChanInfo {
 template <int NCH>
 __device__ inline void channel_values(const ChanInfo& ci, double x, double y, double z, double w, bool ran,
                                       double alpha, double* cv) {
-  // c = w y_L^M*(x^) (eq. 34); randoms carry -alpha (eq. 34); survey mode adds
+  // c = w y_L^M*(x^) (eq. 34); randoms carry -alpha (eq. 34), or for the window
+  // multipoles +alpha with the galaxies left out; survey mode adds
   // the randoms channel (weight w, randoms only) used by the normalisation
   double ux = 0.0, uy = 0.0, uz = 1.0;
   if (ci.local) {
@@ -374,7 +376,7 @@ __device__ inline void channel_values(const ChanInfo& ci, double x, double y, do
       uz = dz / r;
     }
   }
-  const double s = ran ? -alpha * w : w;
+  const double s = ci.window ? (ran ? alpha * w : 0.0) : (ran ? -alpha * w : w);
 #pragma unroll
   for (int c = 0; c < NCH; ++c) {
     if (c >= ci.nch) {
@@ -1285,6 +1287,7 @@ int chan_info(const Plan& P, ChanInfo* ci) {
   if (ci->nch + 1 > kMaxCh || (int)P.grids.size() > kMaxGrids || record_slots(P) > kMaxCh)
     return fail(TSB_E_UNSUPPORTED, "too many channels");
   ci->local = P.los_kind == TSB_LOS_LOCAL;
+  ci->window = P.estimator == TSB_WINDOW;
   for (int i = 0; i < 3; ++i) ci->obs[i] = P.observer[i];
   for (int c = 0; c < ci->nch; ++c) {
     ci->chL[c] = P.chans[c].L;

@@ -35,7 +35,8 @@ struct PassArgs {
   int lpw;                 // lines per workgroup (consecutive b)
   int contiguous;          // element stride 1 (else b stride 1)
   // pre-operation on loaded values
-  int pre;                 // 0 none, 1 band mask |n|^2 <= n2max, 2 shell filter
+  int pre;                 // 0 none, 1 band mask |n|^2 <= n2max, 2 shell filter,
+                           // 3 times the slot's separation kernel (3PCF)
   int offA, offB, offE;    // frequency = index - off for a, b, e
   int axA, axB, axE;       // which Cartesian axis (0 x, 1 y, 2 z) a, b and e index
   int64_t n2max;
@@ -43,6 +44,8 @@ struct PassArgs {
   int64_t lut_max;
   const FKind* kinds;
   int nkinds;
+  const void* kslot;       // pre 3: [batch][in cube layout] separation kernels
+  int64_t kslot_bs;
   double ynorm[45];
 };
 
@@ -92,6 +95,11 @@ __device__ inline typename cplx<T>::type apply_pre(const PassArgs<T>& a, int bat
                                                    typename cplx<T>::type v) {
   typedef typename cplx<T>::type T2;
   const int fa = ia - a.offA, fb = ib - a.offB, fe = e - a.offE;
+  if (a.pre == 3) {
+    const T2 k = ((const T2*)a.kslot)[(int64_t)batch * a.kslot_bs + (int64_t)ia * a.in_sa +
+                                      (int64_t)ib * a.in_sb + (int64_t)e * a.in_se];
+    return cmul<T2, T>(v, k);
+  }
   if (a.pre == 1) {
     const int64_t n2 = (int64_t)fa * fa + (int64_t)fb * fb + (int64_t)fe * fe;
     if (n2 > a.n2max) {
@@ -606,10 +614,13 @@ int inverse_impl(Plan& P, hipStream_t s) {
                                fields + P.g_offset, true, s)))
       return rc;
   }
-  // F slots: shell filter of dn_0^0 times y_l^m*(k^) (eq. 42)
+  // F slots: shell filter of dn_0^0 times y_l^m*(k^) (eq. 42), or for the 3PCF
+  // dn_0^0 times the slot's separation kernel (eq. 48)
   {
     PassArgs<T> pre{};
-    pre.pre = 2;
+    pre.pre = P.d_kslot ? 3 : 2;
+    pre.kslot = P.d_kslot;
+    pre.kslot_bs = (int64_t)P.PF * P.PF * P.PF;
     pre.bin_lut = P.d_bin_lut;
     pre.lut_max = (int64_t)P.bin_lut.size() - 1;
     pre.kinds = P.d_fkinds;
@@ -624,7 +635,106 @@ int inverse_impl(Plan& P, hipStream_t s) {
   return TSB_OK;
 }
 
+// Separation kernels of the 3PCF (Sec. 4.3): for F slot (bin b, kind k) with
+// parts (l_p, m_p, c_p),
+//   Kslot(k) = sum_p c_p i^-l_p sum_{n in b} y_lp^mp*(n^) e^{2 pi i k.n / N},
+// i.e. N_r(b) i^-l K_l^m(k; b) of eq. 49 on the grid. The sum over separation
+// vectors is the inverse transform of the shell-filtered cube of ones with n in
+// the role of the mode (the r-bin table maps n^2 to bins); the zero
+// separation, which the shell filter skips, adds c_p for l_p = 0 to every mode
+// when a bin holds r = 0.
+template <typename T>
+__global__ void __launch_bounds__(kBlock) kslot_gather_kernel(const typename cplx<T>::type* fields,
+                                                             typename cplx<T>::type* kslot, int nbatch, int nkinds,
+                                                             int N, int R, int zero_bin, const FKind* kinds) {
+  typedef typename cplx<T>::type T2;
+  const int PR = 2 * R + 1;
+  const int64_t pr3 = (int64_t)PR * PR * PR, total = (int64_t)nbatch * pr3, N3 = (int64_t)N * N * N;
+  for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < total; i += (int64_t)gridDim.x * kBlock) {
+    const int batch = (int)(i / pr3);
+    const int64_t q = i - (int64_t)batch * pr3;
+    const int qx = (int)(q / ((int64_t)PR * PR)), qy = (int)((q / PR) % PR), qz = (int)(q % PR);
+    int x = qx - R, y = qy - R, z = qz - R;
+    x += x < 0 ? N : 0;
+    y += y < 0 ? N : 0;
+    z += z < 0 ? N : 0;
+    T2 v = fields[(int64_t)batch * N3 + ((int64_t)x * N + y) * N + z];
+    if (batch / nkinds == zero_bin) {
+      const FKind& k = kinds[batch % nkinds];
+      for (int p = 0; p < k.nparts; ++p)
+        if (k.part[p].l == 0) {
+          v.x += (T)k.part[p].fr;
+          v.y += (T)k.part[p].fi;
+        }
+    }
+    kslot[i] = v;
+  }
+}
+
+template <typename T>
+int separation_impl(Plan& P, hipStream_t s) {
+  typedef typename cplx<T>::type T2;
+  if (P.M != P.N) return fail(TSB_E_UNSUPPORTED, "separation kernels need the reduction grid M = N");
+  const int nk = (int)P.fkinds.size(), nf = P.nb * nk, PF = P.PF;
+  const int64_t pf3 = (int64_t)PF * PF * PF, N3 = (int64_t)P.N * P.N * P.N;
+  // slot kinds with the factors i^-l_p
+  std::vector<FKind> kinds = P.fkinds;
+  for (auto& k : kinds)
+    for (int p = 0; p < k.nparts; ++p) {
+      static const double ire[4] = {1, 0, -1, 0}, iim[4] = {0, -1, 0, 1};   // i^-l
+      const int l4 = k.part[p].l % 4;
+      const double fr = k.part[p].fr, fi = k.part[p].fi;
+      k.part[p].fr = fr * ire[l4] - fi * iim[l4];
+      k.part[p].fi = fr * iim[l4] + fi * ire[l4];
+    }
+  std::vector<T> ones(2 * pf3, (T)0);
+  for (int64_t i = 0; i < pf3; ++i) ones[2 * i] = (T)1;
+  void *d_kinds = nullptr, *d_ones = nullptr, *d_fields = nullptr;
+  auto release = [&]() {
+    if (d_kinds) (void)hipFree(d_kinds);
+    if (d_ones) (void)hipFree(d_ones);
+    if (d_fields) (void)hipFree(d_fields);
+  };
+  int rc = TSB_OK;
+  if (hipMalloc(&d_kinds, kinds.size() * sizeof(FKind)) != hipSuccess ||
+      hipMalloc(&d_ones, ones.size() * sizeof(T)) != hipSuccess ||
+      hipMalloc(&d_fields, (size_t)nf * N3 * sizeof(T2)) != hipSuccess) {
+    (void)hipGetLastError();
+    release();
+    return fail(TSB_E_NOMEM, "device allocation for the separation kernels failed");
+  }
+  if (hipMemcpy(d_kinds, kinds.data(), kinds.size() * sizeof(FKind), hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(d_ones, ones.data(), ones.size() * sizeof(T), hipMemcpyHostToDevice) != hipSuccess) {
+    release();
+    return fail(TSB_E_DEVICE, "upload of the separation-kernel tables failed");
+  }
+  PassArgs<T> pre{};
+  pre.pre = 2;
+  pre.bin_lut = P.d_bin_lut;
+  pre.lut_max = (int64_t)P.bin_lut.size() - 1;
+  pre.kinds = (const FKind*)d_kinds;
+  pre.nkinds = nk;
+  ylm_norm_table(pre.ynorm);
+  const unsigned saved = P.prof;
+  P.prof = 0;
+  rc = inverse_chain<T>(P, kStInvFX, (const T2*)d_ones, 0, nf, P.RF, pre, (T2*)d_fields, true, s);
+  P.prof = saved;
+  if (!rc) {
+    hipLaunchKernelGGL(kslot_gather_kernel<T>, dim3(grid_blocks((int64_t)nf * pf3)), dim3(kBlock), 0, s,
+                       (const T2*)d_fields, (T2*)P.d_kslot, nf, nk, P.N, P.RF, P.bin_lut[0], (const FKind*)d_kinds);
+    if (hipGetLastError() != hipSuccess || hipStreamSynchronize(s) != hipSuccess)
+      rc = fail(TSB_E_DEVICE, "separation-kernel construction failed");
+  }
+  release();
+  return rc;
+}
+
 }  // namespace
+
+int run_separation_kernels(Plan& P, hipStream_t s) {
+  if (!P.d_kslot) return TSB_OK;
+  return P.precision == TSB_FP64 ? separation_impl<double>(P, s) : separation_impl<float>(P, s);
+}
 
 int run_forward(Plan& P, hipStream_t s) {
   return P.precision == TSB_FP64 ? forward_impl<double>(P, s) : forward_impl<float>(P, s);

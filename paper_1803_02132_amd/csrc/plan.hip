@@ -95,7 +95,10 @@ int plan_build(Plan& P) {
   if (P.shot_noise != 0 && P.shot_noise != 1) return fail(TSB_E_ARG, "shot_noise must be 0 or 1");
   if (P.vertex == TSB_VERTEX_X1 && P.los_kind == TSB_LOS_LOCAL)
     return fail(TSB_E_UNSUPPORTED, "the LOS at the first vertex is not built yet");
-  if (P.estimator != TSB_BISPECTRUM) return fail(TSB_E_UNSUPPORTED, "the 3PCF and window estimators are not built yet");
+  const bool xi = P.estimator != TSB_BISPECTRUM;   // separation bins (Sec. 4.3, 6.1)
+  if (xi && P.shot_noise) return fail(TSB_E_UNSUPPORTED, "the 3PCF shot noise (eq. 51) is not subtracted");
+  if (P.estimator == TSB_WINDOW && P.box_mode)
+    return fail(TSB_E_UNSUPPORTED, "window multipoles need a random catalogue (survey mode)");
   if (P.mult.empty()) return fail(TSB_E_ARG, "no multipoles");
   if (P.los_kind != TSB_LOS_GLOBAL && P.los_kind != TSB_LOS_LOCAL)
     return fail(TSB_E_ARG, "los kind must be global (0) or local (1)");
@@ -117,14 +120,16 @@ int plan_build(Plan& P) {
   }
   P.copies = 1 + P.interlace;
 
-  // ---- k-shells (eq. 38): bin of every integer n^2 ---------------------------
+  // ---- k-shells (eq. 38), or separation bins of the 3PCF: bin of every
+  // integer n^2 (|k| = k_f sqrt(n^2); |r| = H sqrt(n^2), n = 0 included) ------
   const double kf = 2.0 * M_PI / P.L;
+  const double unit = xi ? P.L / N : kf;
   const int64_t h = N / 2;
   const int64_t n2all = 3 * h * h;
   std::vector<int> lut(n2all + 1, -1);
   int64_t n2maxF = 0;
-  for (int64_t n2 = 1; n2 <= n2all; ++n2) {
-    const double k = kf * std::sqrt((double)n2);
+  for (int64_t n2 = xi ? 0 : 1; n2 <= n2all; ++n2) {
+    const double k = unit * std::sqrt((double)n2);
     int bin = -1;
     if (P.edges.empty()) {
       const double b = std::floor((k - P.kmin) / P.dk);
@@ -138,14 +143,26 @@ int plan_build(Plan& P) {
       n2maxF = n2;
     }
   }
-  if (n2maxF == 0) return fail(TSB_E_UNSUPPORTED, "no grid mode falls in any k-shell");
-  // no shell may hold a mode with an index component of N/2 (those are zeroed)
+  bool any_bin = false;
+  for (int64_t n2 = 0; n2 <= n2all; ++n2) any_bin = any_bin || lut[n2] >= 0;
+  if (!any_bin) return fail(TSB_E_UNSUPPORTED, xi ? "no grid separation falls in any r-bin"
+                                                  : "no grid mode falls in any k-shell");
+  // no shell may hold a mode with an index component of N/2 (those are zeroed);
+  // r-bins stay inside half the box (r and -r distinct)
   for (int64_t n2 = h * h; n2 <= n2all; ++n2)
-    if (lut[n2] >= 0) return fail(TSB_E_UNSUPPORTED, "k-shells reach the Nyquist frequency");
-  P.n2maxF = n2maxF;
-  int RF = (int)std::floor(std::sqrt((double)n2maxF));
-  while ((int64_t)(RF + 1) * (RF + 1) <= n2maxF) ++RF;
-  while ((int64_t)RF * RF > n2maxF) --RF;
+    if (lut[n2] >= 0)
+      return fail(TSB_E_UNSUPPORTED, xi ? "r-bins reach half the box" : "k-shells reach the Nyquist frequency");
+  int RF;
+  if (xi) {
+    // the 3PCF filters every mode: F and G cover the whole (non-Nyquist) cube
+    RF = (int)h - 1;
+    P.n2maxF = 3 * (int64_t)RF * RF;
+  } else {
+    P.n2maxF = n2maxF;
+    RF = (int)std::floor(std::sqrt((double)n2maxF));
+    while ((int64_t)(RF + 1) * (RF + 1) <= n2maxF) ++RF;
+    while ((int64_t)RF * RF > n2maxF) --RF;
+  }
   P.RF = RF;
   P.bin_lut.assign(lut.begin(), lut.begin() + (3 * (int64_t)RF * RF + 1));
 
@@ -154,7 +171,7 @@ int plan_build(Plan& P) {
   // |n3| <= 2 sqrt(n2maxF). If 2 RF < N/2 no F pair wraps on the N grid, and the
   // sum over cells of F F G equals (N/M)^3 times the same sum on any M grid with
   // M > 2 RF + RG: then no closed triangle aliases onto another.
-  if (4 * RF < N) {
+  if (!xi && 4 * RF < N) {
     P.n2maxG = 4 * n2maxF;
     int RG = (int)std::floor(2.0 * std::sqrt((double)n2maxF));
     while ((int64_t)(RG + 1) * (RG + 1) <= P.n2maxG) ++RG;
@@ -178,15 +195,16 @@ int plan_build(Plan& P) {
   // N_mode and mean |k| per shell (all modes of a shell are in the F cube)
   P.nmode.assign(P.nb, 0);
   P.keff.assign(P.nb, 0.0);
+  // (3PCF: N_r and the mean |r| of the separation vectors of each bin)
   for (int x = -RF; x <= RF; ++x)
     for (int y = -RF; y <= RF; ++y)
       for (int z = -RF; z <= RF; ++z) {
         int64_t n2 = (int64_t)x * x + (int64_t)y * y + (int64_t)z * z;
-        if (n2 > n2maxF) continue;
+        if (n2 > P.n2maxF) continue;
         int b = P.bin_lut[n2];
         if (b < 0) continue;
         P.nmode[b] += 1;
-        P.keff[b] += kf * std::sqrt((double)n2);
+        P.keff[b] += unit * std::sqrt((double)n2);
       }
   for (int b = 0; b < P.nb; ++b) P.keff[b] = P.nmode[b] ? P.keff[b] / P.nmode[b] : NAN;
 
@@ -269,9 +287,15 @@ int plan_build(Plan& P) {
     }
     return out;
   };
+  // 3PCF: the F fields are built from the separation kernels K'_l^m = i^-l K_l^m
+  // (K of eq. 49 on the grid), which have the parity of y_l^m*(k^) and so keep
+  // the symmetries used below; F = i^l F', and the phase i^(l1+l2) moves into
+  // the coefficients (the fields of every term are real)
   P.mu_pref.assign(P.mult.size(), 0.0);
   for (int mu = 0; mu < (int)P.mult.size(); ++mu) {
     int l1 = P.mult[mu].l1, l2 = P.mult[mu].l2, L = P.mult[mu].L;
+    static const cd ipow[4] = {cd(1, 0), cd(0, 1), cd(-1, 0), cd(0, -1)};
+    const cd phase = xi ? ipow[(l1 + l2) % 4] : cd(1, 0);
     P.mu_pref[mu] = (double)((2 * l1 + 1) * (2 * l2 + 1) * (2 * L + 1)) * three_j(l1, l2, L, 0, 0, 0);
     for (int m1 = -l1; m1 <= l1; ++m1)
       for (int m2 = -l2; m2 <= l2; ++m2) {
@@ -282,7 +306,7 @@ int plan_build(Plan& P) {
         for (auto& a : ffactor(l1, m1))
           for (auto& b : ffactor(l2, m2))
             for (auto& c : gfactor(L, M)) {
-              double re = (w * a.second * b.second * c.second).real();
+              double re = (phase * w * a.second * b.second * c.second).real();
               acc[std::make_tuple(mu, a.first, b.first, c.first)] += re;
             }
       }
@@ -381,7 +405,11 @@ int plan_build(Plan& P) {
         }
         if (!want || P.nmode[b1] == 0 || P.nmode[b2] == 0) continue;
         P.outs.push_back({mu, b1, b2, q0, q1});
-        P.out_norm.push_back(P.mu_pref[mu] / ((double)P.nmode[b1] * (double)P.nmode[b2] * M3));
+        double nrm = P.mu_pref[mu] / ((double)P.nmode[b1] * (double)P.nmode[b2] * M3);
+        // 3PCF: the three fields of eq. 48 carry 1/V each (eqs. 42, 49), of
+        // which the estimator's cell volume takes one back
+        if (xi) nrm /= P.L * P.L * P.L * P.L * P.L * P.L;
+        P.out_norm.push_back(nrm);
       }
   }
 

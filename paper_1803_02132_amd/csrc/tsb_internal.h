@@ -164,6 +164,7 @@ struct Plan {
   std::vector<double> sn_alias;                   // host copy of the alias-sum table
   double* d_sum_partials = nullptr;   // per-block partial sums (prep and I)
   double* d_axis_tab = nullptr;   // per stored axis mode: 1/W_axis, cos and sin of pi n/N
+  void* d_kslot = nullptr;      // 3PCF: separation kernel of every F slot [nb * nkinds][PF^3]
   void* d_yspec = nullptr;      // box mode, local LOS: combined spectra of y_L^M*(x^_node) [ngrid][PG^3]
   bool yspec_ready = false;     // subtract mean * d_yspec in the combine step
   int* d_bk_count = nullptr;    // particles per (tile, reach class) bucket [nbk]
@@ -258,6 +259,7 @@ int run_prep(Plan& P, const tsb_catalog* data, const tsb_catalog* rand, hipStrea
 int run_assign(Plan& P, const tsb_catalog* data, const tsb_catalog* rand, hipStream_t s);
 int run_forward(Plan& P, hipStream_t s);
 int run_inverse(Plan& P, hipStream_t s);
+int run_separation_kernels(Plan& P, hipStream_t s);   // 3PCF: fills d_kslot
 int run_reduce(Plan& P, hipStream_t s);
 int run_reduce_final(Plan& P, hipStream_t s);
 void plan_fused(Plan& P);                   // fused.hip

@@ -130,6 +130,38 @@ def test_invalid_requests(bad, code):
     assert tsb.abi.tsb_last_error()
 
 
+def test_separation_bins_of_the_3pcf_match_the_oracle():
+    # r-bins of the 3PCF and the window multipoles (Sec. 4.3): N_r and the mean
+    # |r| of the grid separation vectors per bin, the zero separation included
+    from oracle import threepoint as tp
+    r = dict(n=16, box_len=160.0, multipoles=[(0, 0, 0), (2, 0, 2)], n_bins=3, dk=11.0, k_min=0.0,
+             assign_p=3, interlace=True, box_mode=True)
+    for estimator in ("3pcf", "window"):
+        info, nr, reff = tsb.query(estimator=estimator, **dict(r, box_mode=estimator == "3pcf"))
+        op = est.Plan(**r)
+        assert np.array_equal(nr, tp.n_r(op))
+        nx, ny, nz, rb = tp.separation_vectors(op)
+        dist = 10.0 * np.sqrt(nx * nx + ny * ny + nz * nz)
+        for b in range(3):
+            assert reff[b] == pytest.approx(np.mean(dist[rb == b]), rel=1e-12)
+        assert info.m == 16   # every mode takes part: the reduction grid is the full grid
+    assert nr[0] == 7         # r = 0 and the six vectors at r = 10
+
+
+@pytest.mark.parametrize("bad,code", [
+    (dict(estimator="window"), tsb.abi.TSB_E_UNSUPPORTED),                  # window needs randoms
+    (dict(estimator="3pcf", shot_noise=True), tsb.abi.TSB_E_UNSUPPORTED),  # eq. 51 not subtracted
+    (dict(estimator="3pcf", dk=30.0), tsb.abi.TSB_E_UNSUPPORTED),          # r-bins reach half the box
+    (dict(estimator="3pcf", k_min=500.0), tsb.abi.TSB_E_UNSUPPORTED),      # no separation in any bin
+])
+def test_invalid_3pcf_requests(bad, code):
+    r = dict(n=16, box_len=160.0, multipoles=[(0, 0, 0)], n_bins=3, dk=11.0, k_min=0.0, box_mode=True)
+    r.update(bad)
+    with pytest.raises(tsb.TsbError) as e:
+        tsb.query(**r)
+    assert e.value.code == code
+
+
 def test_every_table1_multipole_accepted():
     for l1 in range(5):
         for l2 in range(5):
