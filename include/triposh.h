@@ -8,7 +8,7 @@
  *   - mass assignment and W_mass deconvolution                      (Sec. 4.2, eq. 39)
  *   - F_l^m(x;k) and G_L^M(x) by inverse FFTs                       (Sec. 4.2, eq. 42)
  *   - B = H sum_{m1 m2 M} 3j (N/I) int d3x F F G                    (Sec. 4.2, eq. 41;
- *                                                                     Sec. 4.4, eq. 51)
+ *                                                                     Sec. 4.4, eq. 52)
  *   - normalisation I                                               (Sec. 4.2, eq. 37; Sec. 4.4)
  *
  * Conventions fixed by the library where the paper is silent:
@@ -26,7 +26,7 @@
  *   - survey (box_mode = 0): dn = data - alpha randoms with
  *     alpha = sum_data w / sum_rand w (Sec. 4.1), I = v_c sum_j (alpha R_j/v_c)^3
  *     with R the randoms assigned on the first grid;
- *   - FKP weight (Sec. 5.2, eq. 53): w = w_c / (1 + nbar P0) when P0 > 0 and
+ *   - FKP weight (Sec. 5.2, eq. 54): w = w_c / (1 + nbar P0) when P0 > 0 and
  *     the catalogue carries nbar; otherwise w = w_c.
  *
  * Every call returns 0 (TSB_OK) or a negative tsb_status; nothing throws across

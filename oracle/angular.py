@@ -21,7 +21,7 @@ Contents and the passage each follows (arXiv:1803.02132):
                          and H_{l1 l2 L} (Sec. 2, after eq. 11).
 * ``reduction_terms`` -- the (m1, m2, M) terms with non-zero 3j weight, for the
                          local-LOS estimator (Sec. 4.2, eq. 41) and the global
-                         plane-parallel one (Sec. 4.4, eq. 51).
+                         plane-parallel one (Sec. 4.4, eq. 52).
 
 Pins (tests/test_oracle_angular.py): closed-form 3j values, the column
 permutation / sign-flip symmetries and orthogonality of 3j, sympy's
@@ -167,7 +167,7 @@ def reduction_terms(l1, l2, L, los="local"):
     """Non-zero terms (m1, m2, M, 3j) of the m-sum.
 
     local LOS (Sec. 4.2, eq. 41): every (m1, m2, M) with m1 + m2 + M = 0.
-    global LOS along z (Sec. 4.4, eq. 51): y_L^M*(z) = delta_M0, so M = 0, m2 = -m1.
+    global LOS along z (Sec. 4.4, eq. 52): y_L^M*(z) = delta_M0, so M = 0, m2 = -m1.
     """
     out = []
     for m1 in range(-l1, l1 + 1):

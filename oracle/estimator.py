@@ -4,7 +4,7 @@ TEST INFRASTRUCTURE ONLY (see the package header).
 
 What it computes (arXiv:1803.02132):
 
-  O1  weights w = w_c / (1 + nbar P0)                      Sec. 5.2, eq. 53 (FKP factor)
+  O1  weights w = w_c / (1 + nbar P0)                      Sec. 5.2, eq. 54 (FKP factor)
   O2  alpha = sum_gal w / sum_ran w                        Sec. 4.1, after eq. 32
   O3  per-particle channel weights w_i y_L^M*(x_i^)         Sec. 4.1, eq. 34 (randoms x -alpha)
   O4  mass assignment (NGP/CIC/TSC) on a periodic grid      Sec. 4.2 (W_mass, eq. 39); App. C
@@ -13,7 +13,7 @@ What it computes (arXiv:1803.02132):
   O7  k-shells and N_mode                                   Sec. 4.2, eq. 38; Sec. 5.2
   O8  G_L^M(x) = int d3k/(2pi)^3 e^{ik.x} dn_L^M(k)/W        Sec. 4.2, eq. 42
   O9  F_l^m(x;k) = shell average of e^{ik.x} y_l^m*(k^) dn(k)/W   Sec. 4.2, eq. 42 with eq. 38
-  O10 B = H sum_m 3j (N/I) int d3x F F G                    Sec. 4.2, eq. 41; Sec. 4.4, eq. 51
+  O10 B = H sum_m 3j (N/I) int d3x F F G                    Sec. 4.2, eq. 41; Sec. 4.4, eq. 52
   O11 I = int d3x nbar^3 (survey) or (sum w)^3/V^2 (box)    Sec. 4.2, eq. 37; Sec. 4.4
   O12 the direct shell-averaged triangle sum of eq. 35     Sec. 4.2, eq. 35
 
@@ -112,7 +112,7 @@ class Plan:
 
 
 def fkp_weights(w_c, nbar, P0):
-    """O1 (Sec. 5.2, eq. 53; R9): w = w_c * 1/(1 + nbar P0)."""
+    """O1 (Sec. 5.2, eq. 54; R9): w = w_c * 1/(1 + nbar P0)."""
     w_c = np.asarray(w_c, dtype=np.float64)
     if nbar is None or P0 <= 0.0:
         return w_c.copy()
@@ -388,7 +388,7 @@ def f_field(plan, spec, l, m, b, bg=None, units=None, nm=None):
 
 
 def reduce_fft(plan, spec, I, pairs=None):
-    """O10 (eq. 41 / eq. 51): B[mu][b1][b2] and its imaginary part.
+    """O10 (eq. 41 / eq. 52): B[mu][b1][b2] and its imaginary part.
 
     ``pairs``: optional iterable of (b1, b2) to evaluate (others stay NaN).
     B = Re[(N H / I) sum_{m1 m2 M} 3j(l1 l2 L; m1 m2 M) (V/N^3) sum_x F F G].

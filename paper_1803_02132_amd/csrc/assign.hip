@@ -1,5 +1,5 @@
 // Weights, y-weighted density channels and mass assignment (Sec. 4.1, eq. 34;
-// Sec. 4.2, eq. 39; Sec. 5.2, eq. 53).
+// Sec. 4.2, eq. 39; Sec. 5.2, eq. 54).
 //
 // Assignment is a gather over tiles: particles are bucketed by the T^3 tile of
 // their cell and by which neighbouring tiles their stencils reach, and one

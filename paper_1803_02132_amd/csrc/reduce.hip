@@ -1,4 +1,4 @@
-// The 3j-weighted triple-product reduction (Sec. 4.2, eq. 41; Sec. 4.4, eq. 51):
+// The 3j-weighted triple-product reduction (Sec. 4.2, eq. 41; Sec. 4.4, eq. 52):
 //   B_mu(b1, b2) = N H / (I N_mode(b1) N_mode(b2) M^3)
 //                  * sum_q sum_x Q_q(x; b1) f2_q(x; b2),
 //   Q_q(x; b1)  = sum_t coef_t f1_t(x; b1) g_t(x),

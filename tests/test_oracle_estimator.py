@@ -427,7 +427,7 @@ def test_survey_normalisation_of_a_uniform_density():
 
 
 def test_fkp_weight_hand_values():
-    # Sec. 5.2, eq. 53: w = w_c / (1 + nbar P0). With nbar P0 = 1 a weight halves,
+    # Sec. 5.2, eq. 54: w = w_c / (1 + nbar P0). With nbar P0 = 1 a weight halves,
     # with nbar P0 = 3 it falls to a quarter, with nbar P0 = 0 it is unchanged.
     P0 = 1024.0   # powers of two keep nbar P0 exact
     w_c = np.array([1.0, 2.0, 0.5, 3.0])
@@ -440,7 +440,7 @@ def test_fkp_weight_hand_values():
 
 
 def test_alpha_with_fkp_weights():
-    # Sec. 4.1 with eq. 53: alpha = sum_gal w_c/(1+nbar P0) / sum_ran w_c/(1+nbar P0).
+    # Sec. 4.1 with eq. 54: alpha = sum_gal w_c/(1+nbar P0) / sum_ran w_c/(1+nbar P0).
     # Galaxies: 2 at nbar P0 = 1 (w = 1/2), 1 at nbar P0 = 3 (w = 1/4): sum 5/4.
     # Randoms: 8 at nbar P0 = 1 (w = 1/2), 4 at nbar P0 = 0 (w = 1): sum 8.
     P0 = 64.0
