@@ -8,11 +8,16 @@
 // fixed point and added with integer LDS atomics, so every grid value is
 // independent of thread and bucket order: the result is bitwise reproducible.
 // One 64-bit word per channel at a plan-wide scale 2^e, with sum|w| 2^e below
-// 2^61 (FP64 plans) or 2^51 (FP32 plans); in FP32 plans, tiles that run as a
-// single work item instead add the two channels of a complex grid into one
-// word as two 32-bit sums at a per-tile scale (half the atomics). The survey
-// randoms channel, which feeds the normalisation, always keeps its own word
-// at the plan-wide scale.
+// 2^61 (FP64 plans) or 2^51 (FP32 plans); in FP32 box plans, tiles that run
+// as a single work item instead add the two channels of a complex grid into
+// one word as two 32-bit sums at a per-tile scale (half the atomics). Survey
+// plans keep the plan-wide scale: their dn is the small difference of two
+// window-shaped fields (galaxies and alpha randoms), so a relative bias
+// between the two of 1e-7 already shows at the lowest k, and rounding at the
+// coarse per-tile step is biased at that level (many contributions are a
+// fraction of the step, and their fractional parts are not uniform). The
+// survey randoms channel, which feeds the normalisation, always keeps its own
+// word at the plan-wide scale.
 #include <cmath>
 
 #include "serve_policy.h"
@@ -797,7 +802,8 @@ __global__ void __launch_bounds__(kTileBlock, (sizeof(T) == 4 && NCH <= 8) ? 4 :
   // into the slot (the shift plan_e - et is never negative then).
   const int plan_e = ilogb(scale);
   const int et_item = tile_exponent(hs >= 0 ? kPartVisits : v1 - v0, cmax * a.wmax);
-  const bool packed = sizeof(T) == 4 && (r_off[cb][64] <= kPartVisits || (hs >= 0 && plan_e >= et_item));
+  const bool packed =
+      sizeof(T) == 4 && a.box_mode && (r_off[cb][64] <= kPartVisits || (hs >= 0 && plan_e >= et_item));
   const int et = packed ? et_item : 0;
   const float tscale = ldexpf(1.0f, et);
   const int ncp = packed ? a.copies : 1;                 // grid copies per pass
