@@ -178,7 +178,9 @@ typedef struct {
   int32_t n_grids;         /* complex grids per assignment copy (two real channels each) */
   int32_t n_fslots;        /* complex F transforms per shell */
   int32_t fused;           /* 1: the last F transform runs inside the reduction
-                              (the F fields never reach device memory) */
+                              (the F fields never reach device memory); 2: the
+                              same in the one-pass FP32 kernel (all shells of a
+                              line in one workgroup); 0: F fields in memory */
   int32_t n_terms;         /* real triple products of the expanded m-sum of eq. 41 */
   int64_t workspace_bytes; /* device memory held by the plan */
   int64_t reduce_flops;    /* floating-point operations of the reduction per
@@ -304,15 +306,28 @@ int tsb_plan_set_profiling(tsb_plan* plan, int32_t stages);
  *   - lines per workgroup of every power-of-two FFT pass (the LDS rule, or 8,
  *     16, 32, 64 lines, at most 64 KiB of LDS);
  *   - the persistent grid of the assignment tile kernel (0.5 to 2 times its
- *     occupancy-sized default).
+ *     occupancy-sized default);
+ *   - for the one-pass FP32 reduction, how its second phase is split: one task
+ *     per (row, shell, k2), a row being one Q group or one right factor, or
+ *     one task per (shell, k2) covering every row.
  * These change how work is split, not the arithmetic: results stay bitwise
  * the same. The choices stay with the plan (the captured graph is rebuilt).
- * choice (may be NULL) receives 16 values: lines per workgroup per stage
+ * choice (may be NULL) receives 17 values: lines per workgroup per stage
  * (index as in tsb_plan_stage_times; 0 = the LDS rule), then the tile-kernel
- * workgroups. Clears the stage-time accumulators and keeps the profiling
- * setting. Errors as tsb_measure. */
+ * workgroups, then the reduction split (1 row tasks, 0 shell tasks, -1 when
+ * the plan does not use the one-pass kernel). Clears the stage-time
+ * accumulators and keeps the profiling setting. Errors as tsb_measure. */
 int tsb_plan_autotune(tsb_plan* plan, const tsb_catalog* data, const tsb_catalog* randoms, void* stream,
                       int32_t reps, int32_t* choice);
+
+/* Apply a launch schedule, e.g. one that tsb_plan_autotune returned for a
+ * plan of the same request, so that a tuned schedule can be reused without
+ * tuning again (serving loops, repeated campaigns). `choice` holds the 17
+ * values in tsb_plan_autotune's layout: lines per workgroup per stage (0, 8,
+ * 16, 32 or 64; ignored by passes whose length is not a power of two), the
+ * tile-kernel workgroups (0: the occupancy default), the reduction split (1,
+ * 0, or -1 to leave it). Results stay bitwise the same. Errors: TSB_E_ARG. */
+int tsb_plan_set_schedule(tsb_plan* plan, const int32_t* choice);
 int tsb_plan_stage_times(tsb_plan* plan, int32_t n, double* ms, int64_t* calls, int32_t reset);
 
 /* Many catalogues in one call (the batched form of eq. 41 over independent

@@ -163,6 +163,10 @@ class Plan:
         return abi.tsb_plan_autotune(self.handle, _cat_struct(data_dev), _cat_struct(randoms_dev), s.cuda_stream,
                                      reps)
 
+    def set_schedule(self, choice):
+        """tsb_plan_set_schedule with a dict in the layout autotune() returns."""
+        abi.tsb_plan_set_schedule(self.handle, choice)
+
     def set_graphs(self, enable):
         abi.tsb_plan_set_graphs(self.handle, enable)
 

@@ -122,6 +122,8 @@ _lib.tsb_measure_batch.restype = ctypes.c_int
 _lib.tsb_measure_batch.argtypes = [_P(ctypes.c_void_p), _P(_P(tsb_catalog)), _P(_P(tsb_catalog)), ctypes.c_int32,
                                    ctypes.c_void_p, _P(_P(ctypes.c_double)), _P(ctypes.c_double),
                                    _P(ctypes.c_double)]
+_lib.tsb_plan_set_schedule.restype = ctypes.c_int
+_lib.tsb_plan_set_schedule.argtypes = [ctypes.c_void_p, _P(ctypes.c_int32)]
 _lib.tsb_plan_set_graphs.restype = ctypes.c_int
 _lib.tsb_plan_set_graphs.argtypes = [ctypes.c_void_p, ctypes.c_int32]
 _lib.tsb_server_create.restype = ctypes.c_int
@@ -145,7 +147,7 @@ EXPORTED = ["tsb_plan_set_profiling", "tsb_plan_stage_times", "tsb_plan_autotune
             "tsb_plan_query", "tsb_request_query", "tsb_plan_get_info", "tsb_plan_nmode", "tsb_measure",
             "tsb_measure_noalloc",
             "tsb_plan_shot_noise", "tsb_assign", "tsb_plan_channel", "tsb_last_error", "tsb_measure_batch",
-            "tsb_plan_set_graphs", "tsb_server_create", "tsb_server_submit", "tsb_server_poll", "tsb_server_wait",
+            "tsb_plan_set_graphs", "tsb_plan_set_schedule", "tsb_server_create", "tsb_server_submit", "tsb_server_poll", "tsb_server_wait",
             "tsb_server_stats", "tsb_server_destroy"]
 
 
@@ -255,12 +257,24 @@ def tsb_plan_set_profiling(h, stages=True):
 
 def tsb_plan_autotune(h, data, randoms, stream, reps=3):
     """Tune the plan's launch schedule; returns {stage: lines per workgroup
-    (0 = LDS rule)} for the tuned FFT stages and 'tile_wgs'."""
-    choice = (ctypes.c_int32 * 16)()
+    (0 = LDS rule)} for the tuned FFT stages, 'tile_wgs' and 'reduce_row_tasks'
+    (1, 0, or -1 when the one-pass reduction is not used)."""
+    choice = (ctypes.c_int32 * 17)()
     _check(_lib.tsb_plan_autotune(h, data, randoms, ctypes.c_void_p(stream), int(reps), choice))
     out = {name: int(choice[i]) for i, name in enumerate(STAGES) if choice[i]}
     out["tile_wgs"] = int(choice[len(STAGES)])
+    out["reduce_row_tasks"] = int(choice[len(STAGES) + 1])
     return out
+
+
+def tsb_plan_set_schedule(h, choice):
+    """Apply a schedule in the layout tsb_plan_autotune returns (a dict)."""
+    arr = (ctypes.c_int32 * 17)()
+    for i, name in enumerate(STAGES):
+        arr[i] = int(choice.get(name, 0))
+    arr[len(STAGES)] = int(choice.get("tile_wgs", 0))
+    arr[len(STAGES) + 1] = int(choice.get("reduce_row_tasks", -1))
+    _check(_lib.tsb_plan_set_schedule(h, arr))
 
 
 def tsb_plan_stage_times(h, reset=False):

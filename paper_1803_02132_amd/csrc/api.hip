@@ -683,7 +683,7 @@ static void fill_info(const Plan& P, tsb_plan_info* info) {
   info->n_outputs = (int32_t)P.outs.size();
   info->n_grids = (int32_t)P.grids.size();
   info->n_fslots = (int32_t)P.fkinds.size();
-  info->fused = P.fused ? 1 : 0;
+  info->fused = P.fused ? (P.fused_wide ? 2 : 1) : 0;
   info->n_terms = (int32_t)P.terms.size();
   info->workspace_bytes = P.bytes;
   const double M3 = (double)P.M * P.M * P.M;
@@ -892,6 +892,24 @@ int tsb_measure_batch(tsb_plan* const* plans, const tsb_catalog* const* data, co
   return first_err;
 }
 
+int tsb_plan_set_schedule(tsb_plan* plan, const int32_t* choice) {
+  if (!plan || !choice) return fail(TSB_E_ARG, "NULL argument");
+  Plan& P = plan->p;
+  for (int st = 0; st < kNumStages; ++st) {
+    const int c = choice[st];
+    if (c != 0 && c != 8 && c != 16 && c != 32 && c != 64)
+      return fail(TSB_E_ARG, "lines per workgroup must be 0 (the LDS rule), 8, 16, 32 or 64");
+  }
+  if (choice[kNumStages] < 0) return fail(TSB_E_ARG, "tile-kernel workgroups must be >= 0 (0: the occupancy default)");
+  const int rt = choice[kNumStages + 1];
+  if (rt < -1 || rt > 1) return fail(TSB_E_ARG, "reduction split must be -1, 0 or 1");
+  for (int st = 0; st < kNumStages; ++st) P.lpw_tune[st] = choice[st];
+  P.tile_wgs = choice[kNumStages];
+  if (rt >= 0) P.fused_rt = rt;
+  ++P.tune_gen;
+  return TSB_OK;
+}
+
 int tsb_plan_set_graphs(tsb_plan* plan, int32_t enable) {
   if (!plan) return fail(TSB_E_ARG, "NULL argument");
   plan->p.use_graph = enable != 0;
@@ -1000,12 +1018,30 @@ int tsb_plan_autotune(tsb_plan* plan, const tsb_catalog* data, const tsb_catalog
     P.tile_wgs = best_wgs;
     ++P.tune_gen;
   }
+  // second phase of the one-pass reduction: (row, shell, k2) tasks or (shell, k2) tasks
+  if (!rc && P.fused && P.fused_wide) {
+    double best = 0.0;
+    int best_rt = 1;
+    for (int c : {1, 0}) {
+      P.fused_rt = c;
+      ++P.tune_gen;
+      double ms = 0.0;
+      if ((rc = stage_time(kStReduce, &ms))) break;
+      if (c == 1 || ms < kTuneGain * best) {
+        best = ms;
+        best_rt = c;
+      }
+    }
+    P.fused_rt = best_rt;
+    ++P.tune_gen;
+  }
   P.prof = prof_saved;
   clear_times();
   if (rc) return rc;
   if (choice) {
     for (int st = 0; st < kNumStages; ++st) choice[st] = P.lpw_tune[st];
     choice[kNumStages] = P.tile_wgs;
+    choice[kNumStages + 1] = P.fused && P.fused_wide ? P.fused_rt : -1;
   }
   return TSB_OK;
 }

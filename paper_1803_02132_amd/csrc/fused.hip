@@ -26,6 +26,7 @@ struct FusedTables {
   int q_t0[kFMaxQ], q_t1[kFMaxQ], q_f2row[kFMaxQ];
   int f2_kind[kFMaxComp], f2_part[kFMaxComp];   // per right-factor row
   int g_slot[kFMaxComp], g_part[kFMaxComp];     // per G component
+  unsigned q_kmask[kFMaxQ];                     // slot kinds among the left factors of Q group q
 };
 
 template <typename T>
@@ -257,6 +258,7 @@ constexpr int kWOut = 8;       // outputs per thread
 constexpr int kWGPre = 2;      // G values per thread and line
 constexpr int kWGroups = 256;  // workgroups of the one-pass kernel
 constexpr int kWMaxQ = 8;      // Q groups
+constexpr size_t kLdsPerCU = 160 * 1024;   // gfx950: the whole LDS of a CU for one workgroup
 
 // sq[i] += cf * part(row[i]) * g(c_i) for the N1 cells c_i = k2 + N2 bitrev(i)
 template <int N1, int N2>
@@ -286,8 +288,12 @@ constexpr int kWKinds = 4;     // slot kinds per shell held in registers at once
 // held in registers while the Q rows are formed one group at a time;
 // otherwise the kinds are transformed one at a time and the Q rows of up to
 // NQ groups (2, 4 or 8) are held in registers. GR: the shells of a line come
-// in more than one group.
-template <int N1, int N2, int NQ, bool KR, bool GR>
+// in more than one group. RT: the second phase runs one task per (row, shell,
+// k2), a row being a Q group or a right factor, so that small shell groups
+// still fill the workgroup; each task transforms the kinds its row needs.
+// The terms of a row are added in the same order as without RT (term order
+// with KR, kind by kind without), so RT changes only the split of the work.
+template <int N1, int N2, int NQ, bool KR, bool GR, bool RT>
 __global__ void __launch_bounds__(kWBlock) fz_reduce_wide_kernel(FusedArgs<float> a) {
   typedef float2 T2;
   constexpr int M = N1 * N2;
@@ -378,7 +384,65 @@ __global__ void __launch_bounds__(kWBlock) fz_reduce_wide_kernel(FusedArgs<float
       __syncthreads();
       if (g + 1 < ngrp) prefetch(line, g + 1);
       else if (line + gridDim.x < lines) prefetch(line + gridDim.x, 0);
-      if constexpr (KR) {
+      if constexpr (RT) {
+      const int per_row = nbg * N2, nrow = nq + a.nf2;
+      for (int task = tid; task < nrow * per_row; task += kWBlock) {
+        const int r = task / per_row, rest = task - r * per_row;
+        const int bl = rest / N2, k2 = rest - bl * N2, b = b0 + bl;
+        auto load_kind = [&](int k, T2 (&u)[N1]) {
+          const T2* st = stage + (size_t)(bl * nk + k) * LS + k2 * (N1 + 1);
+#pragma unroll
+          for (int j = 0; j < N1; ++j) u[j] = st[j];
+          reg_fft<float, T2, N1>(u, 1);
+        };
+        if (r < nq) {
+          float sq[N1];
+#pragma unroll
+          for (int i = 0; i < N1; ++i) sq[i] = 0.f;
+          const unsigned kmask = a.tb.q_kmask[r];
+          if constexpr (KR) {
+            // every kind the row needs in registers, then the terms in order
+            T2 u[kWKinds][N1];
+#pragma unroll
+            for (int k = 0; k < kWKinds; ++k) {
+              if (k < nk && ((kmask >> k) & 1u)) {
+                load_kind(k, u[k]);
+              } else {
+#pragma unroll
+                for (int j = 0; j < N1; ++j) u[k][j] = make_float2(0.f, 0.f);
+              }
+            }
+            for (int t = a.tb.q_t0[r]; t < a.tb.q_t1[r]; ++t) {
+              const float cf = (float)a.tb.coef[t];
+              const int part = a.tb.f1part[t];
+              const float* gr = Gv + (size_t)a.tb.g[t] * CP + k2;
+              switch (a.tb.f1kind[t]) {
+                case 0: add_term<N1, N2>(sq, u[0], part, cf, gr); break;
+                case 1: add_term<N1, N2>(sq, u[1], part, cf, gr); break;
+                case 2: add_term<N1, N2>(sq, u[2], part, cf, gr); break;
+                default: add_term<N1, N2>(sq, u[3], part, cf, gr); break;
+              }
+            }
+          } else {
+            for (int k = 0; k < nk; ++k) {
+              if (!((kmask >> k) & 1u)) continue;
+              T2 u[N1];
+              load_kind(k, u);
+              for (int t = a.tb.q_t0[r]; t < a.tb.q_t1[r]; ++t) {
+                if (a.tb.f1kind[t] != k) continue;
+                add_term<N1, N2>(sq, u, a.tb.f1part[t], (float)a.tb.coef[t], Gv + (size_t)a.tb.g[t] * CP + k2);
+              }
+            }
+          }
+          put_row<N1, N2>(Q + ((size_t)r * nb + b) * CP + k2, sq);
+        } else {
+          const int rr = r - nq;
+          T2 u[N1];
+          load_kind(a.tb.f2_kind[rr], u);
+          put_row<N1, N2>(F2 + ((size_t)rr * nb + b) * CP + k2, u, a.tb.f2_part[rr]);
+        }
+      }
+      } else if constexpr (KR) {
       for (int task = tid; task < nbg * N2; task += kWBlock) {
         const int bl = task / N2, k2 = task - bl * N2, b = b0 + bl;
         T2 u[kWKinds][N1];
@@ -531,7 +595,7 @@ int wide_group(const Plan& P) {
   for (int ng = 1; ng <= 4; ++ng) {
     const int bpg = (P.nb + ng - 1) / ng;
     if (bpg * nk * N1 > kWBlock) continue;
-    if (wide_lds_bytes(P, bpg) <= 150 * 1024) return bpg;
+    if (wide_lds_bytes(P, bpg) <= kLdsPerCU) return bpg;
   }
   return 0;
 }
@@ -604,6 +668,10 @@ int fused_launch(Plan& P, hipStream_t s) {
     a.tb.g_slot[f] = P.gcomp[f].slot;
     a.tb.g_part[f] = P.gcomp[f].part;
   }
+  for (size_t q = 0; q < P.qgroups.size(); ++q) {
+    a.tb.q_kmask[q] = 0u;
+    for (int t = P.qgroups[q].t0; t < P.qgroups[q].t1; ++t) a.tb.q_kmask[q] |= 1u << a.tb.f1kind[t];
+  }
   const size_t lds = fused_lds_bytes<T>(P, P.fused_bpg);
   prof_begin(P, kStReduce, s);
   if (P.fused_wide) {
@@ -611,16 +679,23 @@ int fused_launch(Plan& P, hipStream_t s) {
     if constexpr (std::is_same<T, float>::value && N1 == 8 && N1 * N2 >= 64) {
       const size_t wl = wide_lds_bytes(P, P.fused_bpg);
       const bool grouped = P.fused_bpg < P.nb;
-      if (a.nkinds <= kWKinds && !grouped)
-        hipLaunchKernelGGL((fz_reduce_wide_kernel<N1, N2, 1, true, false>), dim3(P.red_wg), dim3(kWBlock), wl, s, a);
+      const dim3 grid(P.red_wg), block(kWBlock);
+      if (P.fused_rt && a.nkinds <= kWKinds && !grouped)
+        hipLaunchKernelGGL((fz_reduce_wide_kernel<N1, N2, 1, true, false, true>), grid, block, wl, s, a);
+      else if (P.fused_rt && a.nkinds <= kWKinds)
+        hipLaunchKernelGGL((fz_reduce_wide_kernel<N1, N2, 1, true, true, true>), grid, block, wl, s, a);
+      else if (P.fused_rt)
+        hipLaunchKernelGGL((fz_reduce_wide_kernel<N1, N2, 1, false, true, true>), grid, block, wl, s, a);
+      else if (a.nkinds <= kWKinds && !grouped)
+        hipLaunchKernelGGL((fz_reduce_wide_kernel<N1, N2, 1, true, false, false>), grid, block, wl, s, a);
       else if (a.nkinds <= kWKinds)
-        hipLaunchKernelGGL((fz_reduce_wide_kernel<N1, N2, 1, true, true>), dim3(P.red_wg), dim3(kWBlock), wl, s, a);
+        hipLaunchKernelGGL((fz_reduce_wide_kernel<N1, N2, 1, true, true, false>), grid, block, wl, s, a);
       else if (a.nq <= 2)
-        hipLaunchKernelGGL((fz_reduce_wide_kernel<N1, N2, 2, false, true>), dim3(P.red_wg), dim3(kWBlock), wl, s, a);
+        hipLaunchKernelGGL((fz_reduce_wide_kernel<N1, N2, 2, false, true, false>), grid, block, wl, s, a);
       else if (a.nq <= 4)
-        hipLaunchKernelGGL((fz_reduce_wide_kernel<N1, N2, 4, false, true>), dim3(P.red_wg), dim3(kWBlock), wl, s, a);
+        hipLaunchKernelGGL((fz_reduce_wide_kernel<N1, N2, 4, false, true, false>), grid, block, wl, s, a);
       else
-        hipLaunchKernelGGL((fz_reduce_wide_kernel<N1, N2, 8, false, true>), dim3(P.red_wg), dim3(kWBlock), wl, s, a);
+        hipLaunchKernelGGL((fz_reduce_wide_kernel<N1, N2, 8, false, true, false>), grid, block, wl, s, a);
       prof_end(P, kStReduce, s);
       TSB_HIP(hipGetLastError());
       return TSB_OK;

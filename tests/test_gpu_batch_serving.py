@@ -166,7 +166,35 @@ def test_autotune_keeps_results_bitwise():
     choice = plan_b.autotune(dev, reps=2)
     _say("autotune choice", choice)
     assert choice["tile_wgs"] >= 1
-    assert all(v in (8, 16, 32, 64) for k, v in choice.items() if k != "tile_wgs")   # 0 (the rule) is not listed
+    assert choice["reduce_row_tasks"] == -1   # this plan (M = 48) does not run the one-pass reduction
+    assert all(v in (8, 16, 32, 64) for k, v in choice.items()
+               if k not in ("tile_wgs", "reduce_row_tasks"))   # 0 (the rule) is not listed
     assert _same(plan_b.measure(dev)["B"], ref)
     plan_b.set_graphs(False)
     assert _same(plan_b.measure(dev)["B"], ref)
+
+
+@pytest.mark.parametrize("mults,n_bins,dk_kf", [
+    ([(0, 0, 0), (2, 0, 2)], 7, 2.0),                                 # kinds in registers, one shell group
+    ([(0, 0, 0), (2, 0, 2)], 24, 0.6),                                # kinds in registers, shell groups
+    ([(0, 0, 0), (1, 1, 0), (2, 0, 2), (1, 1, 2)], 16, 0.9),          # kind by kind, shell groups
+])
+def test_reduction_split_and_schedule_reuse_are_bitwise(mults, n_bins, dk_kf):
+    # the one-pass reduction's second phase as row tasks or shell tasks, and a
+    # schedule applied from another plan: the same arithmetic, bitwise
+    import math
+    req = box_request(n=64, n_bins=n_bins, dk=dk_kf * 2.0 * math.pi / 1000.0, multipoles=mults)
+    dev = tsb.catalog_to_device(_cat(64, 43, 40000))
+    plan = tsb.Plan(**req)
+    assert plan.info.fused == 2
+    out = {}
+    for rt in (0, 1):
+        plan.set_schedule({"reduce_row_tasks": rt})
+        out[rt] = plan.measure(dev)["B"]
+    _say("split", mults, n_bins, "row tasks vs shell tasks bitwise", _same(out[0], out[1]))
+    assert _same(out[0], out[1])
+    tuned = tsb.Plan(**req)
+    choice = tuned.autotune(dev, reps=1)
+    other = tsb.Plan(**req)
+    other.set_schedule(choice)
+    assert _same(other.measure(dev)["B"], out[1])
