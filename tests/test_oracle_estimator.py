@@ -490,3 +490,47 @@ def test_fft_route_equals_triangle_sum_c1():
         assert scale > 0
         assert np.nanmax(np.abs(Bf[mu] - Bb[mu])) <= 1e-12 * scale
         assert np.nanmax(np.abs(If[mu])) <= 1e-12 * scale
+
+
+# ----------------------------------------------------------------------------
+# first-vertex LOS (App. B; reading R12)
+
+X1_MULTIPOLES = [(0, 0, 0), (2, 0, 2), (0, 2, 2), (1, 1, 2), (2, 2, 2), (1, 1, 0)]
+
+
+def test_first_vertex_fft_route_equals_triangle_sum():
+    # eq. 35 with y_L^M*(x^) on the first field's density, summed directly over
+    # the shell pairs, against the FFT route with the weighted shell fields
+    plan = small_plan(vertex="x1", multipoles=X1_MULTIPOLES)
+    cat = small_cat(seed=21)
+    Bf, If, Bb, Ib, _, _ = _both_routes(plan, cat)
+    for mu in range(len(X1_MULTIPOLES)):
+        scale = np.nanmax(np.abs(Bb[mu]))
+        assert scale > 0
+        assert np.nanmax(np.abs(Bf[mu] - Bb[mu])) <= 1e-11 * scale
+        assert np.nanmax(np.abs(If[mu])) <= 1e-11 * scale
+
+
+def test_first_vertex_equals_third_vertex_at_L0_and_differs_at_L2():
+    # y_0^0 = 1 carries no LOS, so L = 0 does not depend on the vertex (App. B);
+    # at L = 2 the two vertices give different numbers near the observer
+    cat = small_cat(seed=22, observer=(50.0, 50.0, -30.0))
+    kw = dict(multipoles=X1_MULTIPOLES, observer=(50.0, 50.0, -30.0))
+    B1 = _measure_B(small_plan(vertex="x1", **kw), cat)
+    B3 = _measure_B(small_plan(vertex="x3", **kw), cat)
+    for mu, (l1, l2, L) in enumerate(X1_MULTIPOLES):
+        scale = np.max(np.abs(B3[mu]))
+        d = np.max(np.abs(B1[mu] - B3[mu]))
+        if L == 0:
+            assert d <= 1e-12 * scale
+        else:
+            assert d >= 1e-3 * scale
+
+
+def test_first_vertex_far_observer_matches_global_los():
+    mps = [(0, 0, 0), (2, 0, 2), (0, 2, 2), (1, 1, 2)]
+    cat = small_cat(seed=16, rsd="global")
+    Bg = _measure_B(small_plan(los="global", multipoles=mps), cat)
+    B1 = _measure_B(small_plan(los="local", vertex="x1", observer=(50.0, 50.0, -1e9), multipoles=mps), cat)
+    for mu in range(len(mps)):
+        assert np.max(np.abs(B1[mu] - Bg[mu])) <= 1e-6 * np.max(np.abs(Bg[mu]))
