@@ -36,7 +36,8 @@ struct PassArgs {
   int contiguous;          // element stride 1 (else b stride 1)
   // pre-operation on loaded values
   int pre;                 // 0 none, 1 band mask |n|^2 <= n2max, 2 shell filter,
-                           // 3 times the slot's separation kernel (3PCF)
+                           // 3 times the slot's separation kernel (3PCF),
+                           // 4 shell filter of each part's own source spectrum
   int offA, offB, offE;    // frequency = index - off for a, b, e
   int axA, axB, axE;       // which Cartesian axis (0 x, 1 y, 2 z) a, b and e index
   int64_t n2max;
@@ -46,6 +47,8 @@ struct PassArgs {
   int nkinds;
   const void* kslot;       // pre 3: [batch][in cube layout] separation kernels
   int64_t kslot_bs;
+  const void* spec;        // pre 4: spectra [grid][PG^3], frequency n at n + RG per axis
+  int RG;
   double ynorm[45];
 };
 
@@ -91,10 +94,76 @@ __device__ inline typename cplx<T>::type shell_value(const PassArgs<T>& a, int b
 }
 
 template <typename T>
+__device__ inline typename cplx<T>::type shell_value_src(const PassArgs<T>& a, int batch, int fa, int fb,
+                                                         int fe, typename cplx<T>::type v) {
+  // F slot input of the first-vertex LOS: sum_parts factor * y_l^m*(k^) * S_part(k)
+  // on shell b, S_part = dn_0^0 (the loaded value) or dn_L^M from a grid spectrum
+  typedef typename cplx<T>::type T2;
+  T2 zero;
+  zero.x = 0;
+  zero.y = 0;
+  const int64_t n2 = (int64_t)fa * fa + (int64_t)fb * fb + (int64_t)fe * fe;
+  if (n2 == 0 || n2 > a.lut_max) return zero;
+  const int bin = a.bin_lut[n2];
+  if (bin != batch / a.nkinds) return zero;
+  const FKind& k = a.kinds[batch % a.nkinds];
+  const double r = sqrt((double)n2);
+  const double ca = fa / r, cb = fb / r, ce = fe / r;
+  const double ux = a.axA == 0 ? ca : (a.axB == 0 ? cb : ce);
+  const double uy = a.axA == 1 ? ca : (a.axB == 1 ? cb : ce);
+  const double uz = a.axA == 2 ? ca : (a.axB == 2 ? cb : ce);
+  const int nx = a.axA == 0 ? fa : (a.axB == 0 ? fb : fe);
+  const int ny = a.axA == 1 ? fa : (a.axB == 1 ? fb : fe);
+  const int nz = a.axA == 2 ? fa : (a.axB == 2 ? fb : fe);
+  const int PG = 2 * a.RG + 1;
+  const int64_t pg3 = (int64_t)PG * PG * PG;
+  const int64_t ip = ((int64_t)(nx + a.RG) * PG + (ny + a.RG)) * PG + (nz + a.RG);
+  const int64_t im = ((int64_t)(a.RG - nx) * PG + (a.RG - ny)) * PG + (a.RG - nz);
+  double fr = 0.0, fi = 0.0;
+  for (int p = 0; p < k.nparts; ++p) {
+    const FPart& fp = k.part[p];
+    const int am = fp.m < 0 ? -fp.m : fp.m;
+    double yr, yi;
+    ylm_pos_m(fp.l, am, ux, uy, uz, a.ynorm, &yr, &yi);
+    if (fp.m < 0) {   // y_l^-m = (-1)^m conj(y_l^m)
+      const double sg = (am & 1) ? -1.0 : 1.0;
+      yr *= sg;
+      yi *= -sg;
+    }
+    double sr = (double)v.x, si = (double)v.y;
+    if (fp.src >= 0) {
+      const T2* S = (const T2*)a.spec + (int64_t)fp.src * pg3;
+      const T2 s0 = S[ip];
+      sr = (double)s0.x;
+      si = (double)s0.y;
+      if (fp.smode != 0) {
+        const T2 s1 = S[im];
+        if (fp.smode == 1) {   // (S(k) + conj S(-k)) / 2
+          sr = 0.5 * ((double)s0.x + (double)s1.x);
+          si = 0.5 * ((double)s0.y - (double)s1.y);
+        } else {               // (S(k) - conj S(-k)) / (2i)
+          sr = 0.5 * ((double)s0.y + (double)s1.y);
+          si = -0.5 * ((double)s0.x - (double)s1.x);
+        }
+      }
+    }
+    // factor * conj(y) * S
+    const double cr = fp.fr * yr + fp.fi * yi, ci = fp.fi * yr - fp.fr * yi;
+    fr += cr * sr - ci * si;
+    fi += cr * si + ci * sr;
+  }
+  T2 o;
+  o.x = (T)fr;
+  o.y = (T)fi;
+  return o;
+}
+
+template <typename T>
 __device__ inline typename cplx<T>::type apply_pre(const PassArgs<T>& a, int batch, int ia, int ib, int e,
                                                    typename cplx<T>::type v) {
   typedef typename cplx<T>::type T2;
   const int fa = ia - a.offA, fb = ib - a.offB, fe = e - a.offE;
+  if (a.pre == 4) return shell_value_src<T>(a, batch, fa, fb, fe, v);
   if (a.pre == 3) {
     const T2 k = ((const T2*)a.kslot)[(int64_t)batch * a.kslot_bs + (int64_t)ia * a.in_sa +
                                       (int64_t)ib * a.in_sb + (int64_t)e * a.in_se];
@@ -603,6 +672,7 @@ int inverse_impl(Plan& P, hipStream_t s) {
   int rc;
   // G grids first: band-limited spectra (eq. 42). The F chain runs last so that,
   // with the fused reduction, its y-pass output is still in d_u2 afterwards.
+  // (The first-vertex LOS needs G_0^0 only: grid 0.)
   {
     PassArgs<T> pre{};
     pre.pre = P.n2maxG >= 0 ? 1 : 0;
@@ -610,17 +680,19 @@ int inverse_impl(Plan& P, hipStream_t s) {
     const int64_t pg3 = (int64_t)P.PG * P.PG * P.PG;
     // the shot noise's i = j != k term takes the H spectra in place of dn_L^M
     const void* gsrc = P.spass ? P.d_hspec : P.d_spec;
-    if ((rc = inverse_chain<T>(P, kStInvGX, (const T2*)gsrc, pg3, (int)P.grids.size(), P.RG, pre,
-                               fields + P.g_offset, true, s)))
+    const int ngi = P.first_vertex ? 1 : (int)P.grids.size();
+    if ((rc = inverse_chain<T>(P, kStInvGX, (const T2*)gsrc, pg3, ngi, P.RG, pre, fields + P.g_offset, true, s)))
       return rc;
   }
   // F slots: shell filter of dn_0^0 times y_l^m*(k^) (eq. 42), or for the 3PCF
   // dn_0^0 times the slot's separation kernel (eq. 48)
   {
     PassArgs<T> pre{};
-    pre.pre = P.d_kslot ? 3 : 2;
+    pre.pre = P.d_kslot ? 3 : (P.fsources ? 4 : 2);
     pre.kslot = P.d_kslot;
     pre.kslot_bs = (int64_t)P.PF * P.PF * P.PF;
+    pre.spec = P.d_spec;
+    pre.RG = P.RG;
     pre.bin_lut = P.d_bin_lut;
     pre.lut_max = (int64_t)P.bin_lut.size() - 1;
     pre.kinds = P.d_fkinds;

@@ -93,8 +93,13 @@ int plan_build(Plan& P) {
   if (P.vertex != TSB_VERTEX_X3 && P.vertex != TSB_VERTEX_X1) return fail(TSB_E_ARG, "los vertex must be 0 (x3) or 1 (x1)");
   if (P.estimator < TSB_BISPECTRUM || P.estimator > TSB_WINDOW) return fail(TSB_E_ARG, "estimator must be 0, 1 or 2");
   if (P.shot_noise != 0 && P.shot_noise != 1) return fail(TSB_E_ARG, "shot_noise must be 0 or 1");
-  if (P.vertex == TSB_VERTEX_X1 && P.los_kind == TSB_LOS_LOCAL)
-    return fail(TSB_E_UNSUPPORTED, "the LOS at the first vertex is not built yet");
+  // LOS at the first vertex (App. B): the y_L^M* weight moves from G onto the
+  // first shell field; under a global LOS both vertices are the same estimator
+  const bool x1 = P.vertex == TSB_VERTEX_X1 && P.los_kind == TSB_LOS_LOCAL;
+  P.first_vertex = x1;
+  if (x1 && P.estimator != TSB_BISPECTRUM)
+    return fail(TSB_E_UNSUPPORTED, "the first-vertex LOS is built for the bispectrum");
+  if (x1 && P.shot_noise) return fail(TSB_E_UNSUPPORTED, "the shot noise is built for the third-vertex LOS");
   const bool xi = P.estimator != TSB_BISPECTRUM;   // separation bins (Sec. 4.3, 6.1)
   if (xi && P.shot_noise) return fail(TSB_E_UNSUPPORTED, "the 3PCF shot noise (eq. 51) is not subtracted");
   if (P.estimator == TSB_WINDOW && P.box_mode)
@@ -230,7 +235,8 @@ int plan_build(Plan& P) {
       P.chans.push_back({L, M, 1});
       P.grids.push_back({c, c + 1});
     }
-  // (L, M, part) -> G component (grid, part)
+  // (L, M, part) -> G component (grid, part); the first-vertex LOS needs G_0^0
+  // only (grid 0, real part), the other grids feed its first shell fields
   std::map<std::tuple<int, int, int>, int> gkey;
   P.gcomp.clear();
   for (int g = 0; g < (int)P.grids.size(); ++g) {
@@ -238,6 +244,7 @@ int plan_build(Plan& P) {
       int c = part ? P.grids[g].im : P.grids[g].re;
       if (c < 0) continue;
       const RealChannel& ch = P.chans[c];
+      if (x1 && (ch.L != 0 || ch.M != 0)) continue;
       gkey[std::make_tuple(ch.L, ch.M, ch.part)] = (int)P.gcomp.size();
       P.gcomp.push_back({g, part});
     }
@@ -246,28 +253,38 @@ int plan_build(Plan& P) {
   // ---- expansion of Re sum_{m1 m2 M} 3j F F G into real triple products --------
   double norm[64];
   ylm_norm_table(norm);
-  // logical F components: (l, |m|, part); part 0/1 = Re/Im of F_l^m (m > 0),
-  // part 0 = the real field f_l = c_l F_l^0 (m = 0, c_l = 1 for even l, -i for odd l)
-  typedef std::tuple<int, int, int> LKey;
+  // logical F components: (l, m, part, L, M) for the shell field of
+  // y_l^m*(k^) dn_L^M(k); dn_0^0 (L = M = 0) for every field of the
+  // third-vertex LOS and for the second field of the first-vertex one. Of
+  // each conjugate pair, F_{l L}^{-m -M} = (-1)^{l+m+M} conj(F_{l L}^{m M})
+  // (real catalogue weights), the member with M > 0, or M = 0 and m >= 0, is
+  // kept: part 0/1 = its Re/Im, or for m = M = 0 part 0 = the real field
+  // c_l F (c_l = 1 for even l, -i for odd l).
+  typedef std::tuple<int, int, int, int, int> LKey;
   std::map<std::tuple<int, LKey, LKey, int>, double> acc;   // (mu, f1, f2, g) -> coef
-  auto ffactor = [](int l, int m) {
+  auto ffactor = [](int l, int m, int L = 0, int M = 0) {
     std::vector<std::pair<LKey, cd>> out;
-    int am = std::abs(m);
-    if (m == 0) {
+    const bool keep = M > 0 || (M == 0 && m >= 0);
+    const int mc = keep ? m : -m, Mc = keep ? M : -M;
+    if (mc == 0 && Mc == 0) {
       cd inv_c = (l % 2) ? cd(0, 1) : cd(1, 0);   // 1/c_l
-      out.push_back({LKey(l, 0, 0), inv_c});
-    } else if (m > 0) {
-      out.push_back({LKey(l, am, 0), cd(1, 0)});
-      out.push_back({LKey(l, am, 1), cd(0, 1)});
+      out.push_back({LKey(l, 0, 0, L, 0), inv_c});
+    } else if (keep) {
+      out.push_back({LKey(l, mc, 0, L, Mc), cd(1, 0)});
+      out.push_back({LKey(l, mc, 1, L, Mc), cd(0, 1)});
     } else {
-      double s = ((l + am) % 2) ? -1.0 : 1.0;    // F^{-m} = (-1)^{l+m} conj(F^m)
-      out.push_back({LKey(l, am, 0), cd(s, 0)});
-      out.push_back({LKey(l, am, 1), cd(0, -s)});
+      double s = ((l + std::abs(m) + std::abs(M)) % 2) ? -1.0 : 1.0;
+      out.push_back({LKey(l, mc, 0, L, Mc), cd(s, 0)});
+      out.push_back({LKey(l, mc, 1, L, Mc), cd(0, -s)});
     }
     return out;
   };
   auto gfactor = [&](int L, int M) {
     std::vector<std::pair<int, cd>> out;
+    if (x1) {   // the weight sits in the first field
+      out.push_back({gkey.at(std::make_tuple(0, 0, 0)), cd(1, 0)});
+      return out;
+    }
     if (P.los_kind == TSB_LOS_GLOBAL) {
       // Sec. 4.4 with a general direction: G_L^M = y_L^M*(d) G_0^0
       cd y = std::conj(ylm_any(L, M, P.los_dir, norm));
@@ -303,7 +320,7 @@ int plan_build(Plan& P) {
         if (std::abs(M) > L) continue;
         double w = three_j(l1, l2, L, m1, m2, M);
         if (w == 0.0) continue;
-        for (auto& a : ffactor(l1, m1))
+        for (auto& a : (x1 ? ffactor(l1, m1, L, M) : ffactor(l1, m1)))
           for (auto& b : ffactor(l2, m2))
             for (auto& c : gfactor(L, M)) {
               double re = (phase * w * a.second * b.second * c.second).real();
@@ -321,51 +338,74 @@ int plan_build(Plan& P) {
     used[std::get<1>(kv.first)] = 1;
     used[std::get<2>(kv.first)] = 1;
   }
-  // F slot kinds: one complex slot per (l, m > 0); real m = 0 fields packed in pairs
+  // source of the shell filter of dn_L^M (M >= 0): dn_0^0 is the prepared F
+  // cube; otherwise the spectrum of the complex grid that holds the channel,
+  // itself for M > 0 (its grid is Re + i Im of dn_L^M), or the Hermitian part
+  // of a packed pair of real M = 0 channels
+  auto source = [&](FPart& fp, int L, int M) {
+    fp.src = -1;
+    fp.smode = 0;
+    if (L == 0 && M == 0) return;
+    for (int g = 0; g < (int)P.grids.size(); ++g)
+      for (int part = 0; part < 2; ++part) {
+        const int c = part ? P.grids[g].im : P.grids[g].re;
+        if (c < 0 || P.chans[c].L != L || P.chans[c].M != M || P.chans[c].part != 0) continue;
+        fp.src = g;
+        fp.smode = M > 0 ? 0 : 1 + part;
+      }
+  };
+  // F slot kinds: one complex slot per (l, m, L, M) kept with M > 0 or m > 0;
+  // the real m = M = 0 fields packed in pairs
   P.fkinds.clear();
   P.fcomp.clear();
   std::map<LKey, int> fidx;
-  std::vector<int> m0l;
-  std::vector<std::pair<int, int>> mpos;
+  std::vector<LKey> m0l, mpos;
   for (auto& kv : used) {
-    int l = std::get<0>(kv.first), m = std::get<1>(kv.first);
-    if (m == 0) {
-      m0l.push_back(l);
-    } else if (std::find(mpos.begin(), mpos.end(), std::make_pair(l, m)) == mpos.end()) {
-      mpos.push_back({l, m});
+    const LKey& key = kv.first;
+    const LKey base(std::get<0>(key), std::get<1>(key), 0, std::get<3>(key), std::get<4>(key));
+    if (std::get<1>(key) == 0 && std::get<4>(key) == 0) {
+      m0l.push_back(base);
+    } else if (std::find(mpos.begin(), mpos.end(), base) == mpos.end()) {
+      mpos.push_back(base);
     }
   }
   for (size_t i = 0; i < m0l.size(); i += 2) {
     FKind k{};
-    int la = m0l[i];
+    int la = std::get<0>(m0l[i]);
     cd ca = (la % 2) ? cd(0, -1) : cd(1, 0);
-    k.part[0] = {la, 0, ca.real(), ca.imag()};
+    k.part[0] = FPart{la, 0, ca.real(), ca.imag(), -1, 0};
+    source(k.part[0], std::get<3>(m0l[i]), 0);
     k.nparts = 1;
     int kind = (int)P.fkinds.size();
-    fidx[LKey(la, 0, 0)] = (int)P.fcomp.size();
+    fidx[m0l[i]] = (int)P.fcomp.size();
     P.fcomp.push_back({kind, 0});
     if (i + 1 < m0l.size()) {
-      int lb = m0l[i + 1];
+      int lb = std::get<0>(m0l[i + 1]);
       cd cb = ((lb % 2) ? cd(0, -1) : cd(1, 0)) * cd(0, 1);   // i c_lb
-      k.part[1] = {lb, 0, cb.real(), cb.imag()};
+      k.part[1] = FPart{lb, 0, cb.real(), cb.imag(), -1, 0};
+      source(k.part[1], std::get<3>(m0l[i + 1]), 0);
       k.nparts = 2;
-      fidx[LKey(lb, 0, 0)] = (int)P.fcomp.size();
+      fidx[m0l[i + 1]] = (int)P.fcomp.size();
       P.fcomp.push_back({kind, 1});
     }
     P.fkinds.push_back(k);
   }
-  for (auto& lm : mpos) {
+  for (auto& key : mpos) {
     FKind k{};
-    k.part[0] = {lm.first, lm.second, 1.0, 0.0};
+    k.part[0] = FPart{std::get<0>(key), std::get<1>(key), 1.0, 0.0, -1, 0};
+    source(k.part[0], std::get<3>(key), std::get<4>(key));
     k.nparts = 1;
     int kind = (int)P.fkinds.size();
     for (int part = 0; part < 2; ++part) {
-      LKey key(lm.first, lm.second, part);
-      fidx[key] = (int)P.fcomp.size();
+      LKey pk(std::get<0>(key), std::get<1>(key), part, std::get<3>(key), std::get<4>(key));
+      fidx[pk] = (int)P.fcomp.size();
       P.fcomp.push_back({kind, part});
     }
     P.fkinds.push_back(k);
   }
+  P.fsources = false;
+  for (auto& k : P.fkinds)
+    for (int p = 0; p < k.nparts; ++p) P.fsources = P.fsources || k.part[p].src >= 0;
   // terms sorted by (mu, f2): one Q group per (mu, f2)
   P.terms.clear();
   for (auto& t : kept)

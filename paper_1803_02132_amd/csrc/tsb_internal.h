@@ -44,8 +44,12 @@ struct RealChannel { int L, M, part; };
 struct ComplexGrid { int re, im; };  // indices into channels; im = -1: none
 
 // Input of one F slot (Sec. 4.2, eq. 42): sum over parts of
-//   (fr + i fi) * y_l^m*(k^) * dn(k) restricted to one shell.
-struct FPart { int l, m; double fr, fi; };
+//   (fr + i fi) * y_l^m*(k^) * S(k) restricted to one shell,
+// S = dn_0^0 (src < 0: the prepared F cube) or, for the first-vertex LOS,
+// dn_L^M from the spectrum of complex grid src: the grid itself (smode 0),
+// or the Hermitian part of its real (1) or imaginary (2) channel. m < 0 is
+// allowed (y_l^-m = (-1)^m conj(y_l^m)).
+struct FPart { int l, m; double fr, fi; int src, smode; };
 struct FKind { int nparts; FPart part[2]; };
 
 // A real field used by the reduction: part (0 re, 1 im) of F slot kind
@@ -88,6 +92,8 @@ struct Plan {
   std::vector<tsb_multipole> mult;
   int precision = TSB_FP32, pair_mode = TSB_PAIRS_PAPER, box_mode = 1, unfused = 0;
   int vertex = TSB_VERTEX_X3, estimator = TSB_BISPECTRUM, shot_noise = 0;
+  bool first_vertex = false;    // local LOS at the first vertex (App. B)
+  bool fsources = false;        // some F slot part filters a channel other than dn_0^0
   double P0 = 0;
   int device = 0;
 

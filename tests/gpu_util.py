@@ -11,7 +11,7 @@ from oracle import estimator as est
 def oracle_plan(**kw):
     """Oracle Plan from the keyword request used by paper_1803_02132_amd.Plan."""
     keep = {k: kw[k] for k in ("n", "box_len", "multipoles", "n_bins", "dk", "k_min", "origin", "assign_p",
-                               "interlace", "los", "los_dir", "observer", "box_mode", "P0", "edges") if k in kw}
+                               "interlace", "los", "los_dir", "observer", "box_mode", "P0", "edges", "vertex") if k in kw}
     if keep.get("edges") is not None:
         keep["edges"] = tuple(float(e) for e in keep["edges"])
     keep["interlace"] = bool(keep.get("interlace", False))
