@@ -123,7 +123,7 @@ def load_traffic(workload, geometry, stage):
 COPY_PROBE_BYTES = 512 << 20
 # stage -> kernels whose dispatches make up one launch of the stage
 STAGE_KERNELS = {"assign": ("tile_parts_kernel", "assign_tile_kernel", "heavy_final_kernel"),
-                 "reduce": ("fz_reduce_wide_kernel", "fz_reduce_kernel", "reduce_kernel")}
+                 "reduce": ("fz_reduce_wide_kernel", "fz_reduce_kernel", "reduce_kernel", "reduce_mfma_kernel")}
 # order of the FFT-pass dispatches inside one measurement (fused plan)
 FFT_ORDER = ["fwd_z", "fwd_y", "fwd_x", "invG_x", "invG_y", "invG_z", "invF_x", "invF_y"]
 
