@@ -19,9 +19,13 @@ decomposition formalism for the redshift-space bispectrum" (arXiv:1803.02132):
                    of its particle description (Sec. 4.2, eqs. 43-46).
 * ``threepoint`` -- the three-point-function multipoles (Sec. 4.3, eqs. 47-48)
                    and the window multipoles of the randoms (Sec. 6.1, eq. 58).
+* ``masked``    -- the masked model (Sec. 6.2): the 9j coupling of window and
+                   model multipoles (eq. 63, App. A), the integral constraint
+                   (eq. 64) and the Hankel transform to the bispectrum (eq. 68).
 
 Every function states the passage it follows. Readings of passages that are
-silent or ambiguous are listed (R1..R11) in ``estimator``'s header.
+silent or ambiguous are listed in each module's header (R1..R12, S1..S5,
+T1..T4, M1..M4).
 
 Parity status per function is stated in each module header; every function is
 pinned by a ``-m "not gpu"`` test against closed forms, library routines,
