@@ -140,12 +140,16 @@ typedef struct {
   int32_t shot_noise; /* bispectrum: 1 subtracts the shot noise S of Sec. 4.2
                          (eqs. 44-46: the four coincident-index terms) */
 } tsb_options;
-/* FP32 plans, precisely: every grid, spectrum and field is FP32; the reduction
- * forms each Q row (a 3j-weighted sum of F G products, coefficients rounded
- * to FP32) and multiplies it with the right factor in FP32, summing the
- * products of one line of M cells in FP32 (matrix cores) before the line
- * sums are added in FP64; the 3j symbols, H, N, N_mode, I, alpha and the final
- * normalisation are FP64. */
+/* FP32 plans, precisely: channel weights are computed in FP64 and stored in
+ * FP32; assignment contributions are rounded to 64-bit fixed point (exact
+ * integer sums); every grid, spectrum and field is FP32 (the interlace
+ * combination and the W_mass division compute in FP64). The fused reduction
+ * forms each Q row (a 3j-weighted sum of F G products, coefficients rounded to
+ * FP32) and multiplies it with the right factor in FP32, summing the products
+ * of one z-line of M cells in FP32 (matrix cores) before the line sums are
+ * added in FP64; the unfused reduction forms Q in FP64, stores it in FP32 and
+ * sums chunks of at most 64 cells in FP32 before FP64. The 3j symbols, H, N, N_mode,
+ * k_eff, I, alpha and the final normalisation are FP64. */
 
 /* Particle catalogue: structure of arrays owned by the caller and only read.
  * w and nbar may be NULL (w_c = 1; no FKP factor). n may be 0. With
@@ -390,6 +394,41 @@ int tsb_server_poll(void* server, int64_t ticket, int32_t* done, double* latency
 int tsb_server_wait(void* server, int64_t ticket, double* latency_s);
 int tsb_server_stats(void* server, int32_t* peak_running, int64_t* released);
 int tsb_server_destroy(void* server);
+
+/* ---- Masked model (Sec. 6.2), host code --------------------------------------
+ * The window multipoles Q (TSB_WINDOW plans) and model three-point-function
+ * multipoles zeta on the same r-bins give the masked model that the measured
+ * zeta and B are compared with. Arrays are host memory, caller-owned, FP64,
+ * [multipole][r1][r2] with r2 fastest. The r integrals are quadrature sums
+ * sum_i w_i f(r_i) with the caller's nodes r (>= 0) and weights w. Multipoles
+ * with l1, l2, L in 0..16; those with l1 + l2 + L odd contribute nothing.
+ *
+ * tsb_wigner_9j: the 9j symbol {l[0] l[1] l[2]; l[3] l[4] l[5]; l[6] l[7] l[8]}
+ *   of App. A (eq. A5) that the coupling uses.
+ * tsb_masked_zeta: eq. 63 for each output multipole (zeta_out [n_out][n_r][n_r]):
+ *   sum over model (l1' l2' L') and window (l1'' l2'' L'') multipoles of
+ *   N_{l1l2L} {l1'' l2'' L''; l1' l2' L'; l1 l2 L} H_{l1l2L} H_{l1 l1' l1''}
+ *   H_{l2 l2' l2''} H_{L L' L''} / (H_{l1'l2'L'} H_{l1''l2''L''}) Q'' zeta',
+ *   with H = 3j(. . .; 0 0 0) and N = (2l1+1)(2l2+1)(2L+1); multipoles absent from
+ *   a set count as zero. With integral_constraint != 0 it also subtracts
+ *   Q_{l1l2L} zeta_bar, zeta_bar of eq. 64 (the sum over multipoles in both sets
+ *   of int r1^2 r2^2 Q zeta / (H^2 N), over int r1^2 r2^2 Q_000; Q_000 must be
+ *   among the window multipoles), and writes zeta_bar (may be NULL; 0 without
+ *   the constraint). r and w may be NULL without the constraint.
+ * tsb_masked_bispectrum: eq. 68, B(k1, k2) = (-i)^{l1+l2} (4 pi)^2
+ *   sum_ij w_i r_i^2 w_j r_j^2 j_l1(k1 r_i) j_l2(k2 r_j) zeta(r_i, r_j), for
+ *   even l1 + l2 (real), B_out [n_k][n_k] (k2 fastest).
+ * Errors: TSB_E_ARG (NULL pointers, empty sets, missing Q_000, negative r or k),
+ * TSB_E_UNSUPPORTED (l outside 0..16, odd l1 + l2 in the transform), TSB_E_INPUT
+ * (a vanishing integral of Q_000). */
+int tsb_wigner_9j(const int32_t* l, double* out);
+int tsb_masked_zeta(const tsb_multipole* model, int32_t n_model, const double* zeta,
+                    const tsb_multipole* window, int32_t n_window, const double* Q,
+                    const double* r, const double* w, int32_t n_r,
+                    const tsb_multipole* out, int32_t n_out, int32_t integral_constraint,
+                    double* zeta_out, double* zeta_bar);
+int tsb_masked_bispectrum(int32_t l1, int32_t l2, const double* zeta, const double* r, const double* w,
+                          int32_t n_r, const double* k, int32_t n_k, double* B_out);
 
 const char* tsb_last_error(void);
 

@@ -234,3 +234,37 @@ class Server:
             self.close()
         except Exception:
             pass
+
+
+def wigner_9j(*l):
+    """tsb_wigner_9j: {l0 l1 l2; l3 l4 l5; l6 l7 l8} (App. A)."""
+    return abi.tsb_wigner_9j(*l)
+
+
+def masked_zeta(out, model, zeta, window, Q, r=None, w=None, integral_constraint=True):
+    """tsb_masked_zeta (Sec. 6.2, eqs. 63-64). zeta, Q: dicts multipole ->
+    (n_r, n_r) arrays (r2 fastest). Returns ({out multipole: array}, zeta_bar)."""
+    model, window, out = [tuple(map(int, m)) for m in model], [tuple(map(int, m)) for m in window], \
+        [tuple(map(int, m)) for m in out]
+    z = np.ascontiguousarray(np.stack([np.asarray(zeta[m], np.float64) for m in model]))
+    q = np.ascontiguousarray(np.stack([np.asarray(Q[m], np.float64) for m in window]))
+    n_r = z.shape[1]
+    rr = None if r is None else np.ascontiguousarray(np.asarray(r, np.float64))
+    ww = None if w is None else np.ascontiguousarray(np.asarray(w, np.float64))
+    res = np.empty((len(out), n_r, n_r), np.float64)
+    zbar = abi.tsb_masked_zeta(model, z.ctypes.data, window, q.ctypes.data,
+                               None if rr is None else rr.ctypes.data, None if ww is None else ww.ctypes.data,
+                               n_r, out, res.ctypes.data, integral_constraint)
+    return {m: res[i] for i, m in enumerate(out)}, zbar
+
+
+def masked_bispectrum(l1, l2, zeta, r, w, k):
+    """tsb_masked_bispectrum (Sec. 6.2, eq. 68): B(k1, k2) on the k grid."""
+    z = np.ascontiguousarray(np.asarray(zeta, np.float64))
+    rr = np.ascontiguousarray(np.asarray(r, np.float64))
+    ww = np.ascontiguousarray(np.asarray(w, np.float64))
+    kk = np.ascontiguousarray(np.asarray(k, np.float64))
+    B = np.empty((kk.size, kk.size), np.float64)
+    abi.tsb_masked_bispectrum(l1, l2, z.ctypes.data, rr.ctypes.data, ww.ctypes.data, rr.size, kk.ctypes.data,
+                              kk.size, B.ctypes.data)
+    return B

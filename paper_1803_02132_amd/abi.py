@@ -122,6 +122,17 @@ _lib.tsb_measure_batch.restype = ctypes.c_int
 _lib.tsb_measure_batch.argtypes = [_P(ctypes.c_void_p), _P(_P(tsb_catalog)), _P(_P(tsb_catalog)), ctypes.c_int32,
                                    ctypes.c_void_p, _P(_P(ctypes.c_double)), _P(ctypes.c_double),
                                    _P(ctypes.c_double)]
+_lib.tsb_wigner_9j.restype = ctypes.c_int
+_lib.tsb_wigner_9j.argtypes = [_P(ctypes.c_int32), _P(ctypes.c_double)]
+_lib.tsb_masked_zeta.restype = ctypes.c_int
+_lib.tsb_masked_zeta.argtypes = [_P(tsb_multipole), ctypes.c_int32, ctypes.c_void_p, _P(tsb_multipole), ctypes.c_int32,
+                                 ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32,
+                                 _P(tsb_multipole), ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p,
+                                 _P(ctypes.c_double)]
+_lib.tsb_masked_bispectrum.restype = ctypes.c_int
+_lib.tsb_masked_bispectrum.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p,
+                                       ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.c_int32,
+                                       ctypes.c_void_p]
 _lib.tsb_plan_set_schedule.restype = ctypes.c_int
 _lib.tsb_plan_set_schedule.argtypes = [ctypes.c_void_p, _P(ctypes.c_int32)]
 _lib.tsb_plan_set_graphs.restype = ctypes.c_int
@@ -148,7 +159,7 @@ EXPORTED = ["tsb_plan_set_profiling", "tsb_plan_stage_times", "tsb_plan_autotune
             "tsb_measure_noalloc",
             "tsb_plan_shot_noise", "tsb_assign", "tsb_plan_channel", "tsb_last_error", "tsb_measure_batch",
             "tsb_plan_set_graphs", "tsb_plan_set_schedule", "tsb_server_create", "tsb_server_submit", "tsb_server_poll", "tsb_server_wait",
-            "tsb_server_stats", "tsb_server_destroy"]
+            "tsb_server_stats", "tsb_server_destroy", "tsb_wigner_9j", "tsb_masked_zeta", "tsb_masked_bispectrum"]
 
 
 def tsb_last_error():
@@ -265,6 +276,29 @@ def tsb_plan_autotune(h, data, randoms, stream, reps=3):
     out["tile_wgs"] = int(choice[len(STAGES)])
     out["reduce_row_tasks"] = int(choice[len(STAGES) + 1])
     return out
+
+
+def tsb_wigner_9j(*l):
+    arr = (ctypes.c_int32 * 9)(*[int(v) for v in l])
+    out = ctypes.c_double()
+    _check(_lib.tsb_wigner_9j(arr, ctypes.byref(out)))
+    return out.value
+
+
+def _mults(ms):
+    return (tsb_multipole * len(ms))(*[tsb_multipole(*map(int, m)) for m in ms])
+
+
+def tsb_masked_zeta(model, zeta_ptr, window, Q_ptr, r_ptr, w_ptr, n_r, out, zeta_out_ptr, integral):
+    zbar = ctypes.c_double()
+    _check(_lib.tsb_masked_zeta(_mults(model), len(model), zeta_ptr, _mults(window), len(window), Q_ptr, r_ptr,
+                                w_ptr, int(n_r), _mults(out), len(out), int(bool(integral)), zeta_out_ptr,
+                                ctypes.byref(zbar)))
+    return zbar.value
+
+
+def tsb_masked_bispectrum(l1, l2, zeta_ptr, r_ptr, w_ptr, n_r, k_ptr, n_k, B_ptr):
+    _check(_lib.tsb_masked_bispectrum(int(l1), int(l2), zeta_ptr, r_ptr, w_ptr, int(n_r), k_ptr, int(n_k), B_ptr))
 
 
 def tsb_plan_set_schedule(h, choice):

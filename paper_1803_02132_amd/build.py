@@ -6,7 +6,7 @@ import sys
 from concurrent.futures import ThreadPoolExecutor
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-SOURCES = ["plan.hip", "assign.hip", "fft.hip", "fused.hip", "reduce.hip", "shot.hip", "api.hip"]
+SOURCES = ["plan.hip", "assign.hip", "fft.hip", "fused.hip", "reduce.hip", "shot.hip", "masked.hip", "api.hip"]
 LIB = os.path.join(HERE, "libtriposh.so")
 OBJ_DIR = os.path.join(HERE, "_build")
 
