@@ -489,10 +489,14 @@ int plan_build(Plan& P) {
     const int upw = ((int)P.qgroups.size() + 3) / 4;
     if (upw >= 1 && upw <= 4) P.red_mfma = upw == 1 ? 1 : (upw == 2 ? 2 : 4);
     // fewer, longer chunks: up to 96 KiB of staged rows (one workgroup per CU
-    // then; a chunk's fixed costs dominate short ones)
+    // then; a chunk's fixed costs dominate short ones). Plans whose terms fit
+    // the kernel arguments take the 1024-thread kernel with up to 150 KiB.
     if (P.red_mfma) {
+      const bool wide = P.qgroups.size() <= 16 && P.terms.size() <= 64;
+      if (wide) P.red_mfma = 8;
+      const int64_t cap = wide ? 150 * 1024 : 96 * 1024;
       int Cm = 64;
-      while (Cm > 8 && per_cell * (Cm + 1) * esz > 96 * 1024) Cm /= 2;
+      while (Cm > 8 && per_cell * (Cm + 1) * esz > cap) Cm /= 2;
       if (Cm > P.red_chunk) {
         P.red_chunk = Cm;
         P.red_wg = (int)std::min<int64_t>((int64_t)P.M * P.M * P.M / Cm, 1024);

@@ -212,6 +212,121 @@ __global__ void __launch_bounds__(kBlock) reduce_mfma_kernel(RedArgs<float> a) {
   }
 }
 
+// The same reduction for FP32 plans with at most 32 shells, 16 Q groups and 64
+// terms, in 1024-thread workgroups (four wavefronts per SIMD with one
+// workgroup per CU): each thread issues its share of a chunk's field loads
+// before it stores any of them, the Q rows are formed one group at a time with
+// the group's terms in the kernel arguments (uniform loops, scalar loads), and
+// one wavefront per Q group runs its 32 x 32 (b1, b2) tile on the matrix cores.
+// The arithmetic is that of reduce_mfma_kernel: Q in FP64 rounded to FP32, the
+// products of a chunk summed in FP32, chunks in FP64.
+constexpr int kRWBlock = 1024;
+constexpr int kRWLoads = 16;      // field loads per thread and chunk held in registers
+constexpr int kRWTerms = 64, kRWQ = 16;
+
+struct RedWideTables {
+  double coef[kRWTerms];
+  int f1[kRWTerms], g[kRWTerms];
+  int q_t0[kRWQ], q_t1[kRWQ], q_f2[kRWQ];
+};
+
+__global__ void __launch_bounds__(kRWBlock) reduce_mfma_wide_kernel(RedArgs<float> a, RedWideTables tb) {
+  extern __shared__ char smem[];
+  const int C = a.chunk;
+  const int CP = C + 1;
+  float* Fv = (float*)smem;                      // [nb][nfc][CP]
+  float* Gv = Fv + (size_t)a.nb * a.nfc * CP;    // [ngc][CP]
+  float* Qv = Gv + (size_t)a.ngc * CP;           // [nq][nb][CP]
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  double acc[16];
+#pragma unroll
+  for (int r = 0; r < 16; ++r) acc[r] = 0.0;
+  const int nslot = a.nb * a.nkinds;
+  const int nload = nslot * C + a.ngrid * C;     // complex elements staged per chunk
+  for (int64_t ch = blockIdx.x; ch < a.nchunks; ch += gridDim.x) {
+    const int64_t c0 = ch * C;
+    // every load of this thread first, then the stores
+    for (int base = 0; base < nload; base += kRWLoads * kRWBlock) {
+      float2 v[kRWLoads];
+#pragma unroll
+      for (int j = 0; j < kRWLoads; ++j) {
+        const int idx = base + tid + j * kRWBlock;
+        v[j] = make_float2(0.f, 0.f);
+        if (idx < nload) {
+          const int slot = idx / C, c = idx - slot * C;
+          v[j] = a.fields[(int64_t)slot * a.M3 + c0 + c];
+        }
+      }
+#pragma unroll
+      for (int j = 0; j < kRWLoads; ++j) {
+        const int idx = base + tid + j * kRWBlock;
+        if (idx >= nload) break;
+        const int slot = idx / C, c = idx - slot * C;
+        if (slot < nslot) {
+          const int b = slot / a.nkinds, k = slot - b * a.nkinds;
+          const int fr = a.kre[k], fi = a.kim[k];
+          if (fr >= 0) Fv[((size_t)b * a.nfc + fr) * CP + c] = v[j].x;
+          if (fi >= 0) Fv[((size_t)b * a.nfc + fi) * CP + c] = v[j].y;
+        } else {
+          const int g = slot - nslot;
+          const int fr = a.gre[g], fi = a.gim[g];
+          if (fr >= 0) Gv[(size_t)fr * CP + c] = v[j].x;
+          if (fi >= 0) Gv[(size_t)fi * CP + c] = v[j].y;
+        }
+      }
+    }
+    __syncthreads();
+    // Q_q(x; b1), one group at a time: its terms are uniform across the workgroup
+    for (int q = 0; q < a.nq; ++q) {
+      const int t0 = tb.q_t0[q], t1 = tb.q_t1[q];
+      for (int idx = tid; idx < a.nb * C; idx += kRWBlock) {
+        const int b1 = idx / C, c = idx - b1 * C;
+        double s = 0.0;
+        for (int t = t0; t < t1; ++t)
+          s += tb.coef[t] * (double)Fv[((size_t)b1 * a.nfc + tb.f1[t]) * CP + c] * (double)Gv[(size_t)tb.g[t] * CP + c];
+        Qv[((size_t)q * a.nb + b1) * CP + c] = (float)s;
+      }
+    }
+    __syncthreads();
+    if (wave < a.nq) {
+      const int q = wave;
+      const int b = lane & 31, kh = lane >> 5;
+      const bool live = b < a.nb;
+      const float* qr = Qv + ((size_t)q * a.nb + (live ? b : 0)) * CP + kh;
+      const float* fr = Fv + ((size_t)(live ? b : 0) * a.nfc + tb.q_f2[q]) * CP + kh;
+      floatx16 c = {};
+      for (int kk = 0; kk < C; kk += 8) {
+        float av[4], bv[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          av[j] = live ? qr[kk + 2 * j] : 0.f;
+          bv[j] = live ? fr[kk + 2 * j] : 0.f;
+        }
+#pragma unroll
+        for (int j = 0; j < 4; ++j) c = __builtin_amdgcn_mfma_f32_32x32x2f32(av[j], bv[j], c, 0, 0, 0);
+      }
+#pragma unroll
+      for (int r = 0; r < 16; ++r) acc[r] += (double)c[r];
+    }
+    __syncthreads();   // the next chunk overwrites the staged rows
+  }
+  double* Ct = (double*)smem;   // [nq][32][32]
+  if (wave < a.nq) {
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const int i = 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3), j = lane & 31;
+      Ct[((size_t)wave * 32 + i) * 32 + j] = acc[r];
+    }
+  }
+  __syncthreads();
+  for (int o = tid; o < a.nout_all; o += kRWBlock) {
+    const OutEntry e = a.outs[o];
+    double v = 0.0;
+    for (int q = e.q0; q < e.q1; ++q) v += Ct[((size_t)q * 32 + e.b1) * 32 + e.b2];
+    a.partials[(size_t)o * gridDim.x + blockIdx.x] = v;
+  }
+}
+
 // One block per output: each thread sums a fixed subset of the workgroup
 // partials, then a fixed-shape tree; the order never depends on scheduling.
 __global__ void __launch_bounds__(kBlock) reduce_final_kernel(const double* partials, int nwg,
@@ -265,6 +380,23 @@ int reduce_impl(Plan& P, hipStream_t s) {
       for (size_t f = 0; f < P.gcomp.size(); ++f) (P.gcomp[f].part ? a.gim : a.gre)[P.gcomp[f].slot] = (int)f;
       a.out0 = 0;
       a.nout = nout_all;
+      if (P.red_mfma == 8) {
+        RedWideTables tb{};
+        for (size_t t = 0; t < P.terms.size(); ++t) {
+          tb.coef[t] = P.terms[t].coef;
+          tb.f1[t] = P.terms[t].f1;
+          tb.g[t] = P.terms[t].g;
+        }
+        for (size_t q = 0; q < P.qgroups.size(); ++q) {
+          tb.q_t0[q] = P.qgroups[q].t0;
+          tb.q_t1[q] = P.qgroups[q].t1;
+          tb.q_f2[q] = P.qgroups[q].f2;
+        }
+        hipLaunchKernelGGL(reduce_mfma_wide_kernel, dim3(P.red_wg), dim3(kRWBlock), lds_m, s, a, tb);
+        prof_end(P, kStReduce, s);
+        TSB_HIP(hipGetLastError());
+        return run_reduce_final(P, s);
+      }
       if (P.red_mfma == 1)
         hipLaunchKernelGGL(reduce_mfma_kernel<1>, dim3(P.red_wg), dim3(kBlock), lds_m, s, a);
       else if (P.red_mfma == 2)
