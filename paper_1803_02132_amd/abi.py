@@ -268,13 +268,15 @@ def tsb_plan_set_profiling(h, stages=True):
 
 def tsb_plan_autotune(h, data, randoms, stream, reps=3):
     """Tune the plan's launch schedule; returns {stage: lines per workgroup
-    (0 = LDS rule)} for the tuned FFT stages, 'tile_wgs' and 'reduce_row_tasks'
-    (1, 0, or -1 when the one-pass reduction is not used)."""
-    choice = (ctypes.c_int32 * 17)()
+    (0 = LDS rule)} for the tuned FFT stages, 'tile_wgs', 'reduce_row_tasks'
+    (1, 0, or -1 when the one-pass reduction is not used) and 'reduce_block'
+    (512, 1024, or -1 when the unfused matrix-core reduction is not used)."""
+    choice = (ctypes.c_int32 * 18)()
     _check(_lib.tsb_plan_autotune(h, data, randoms, ctypes.c_void_p(stream), int(reps), choice))
     out = {name: int(choice[i]) for i, name in enumerate(STAGES) if choice[i]}
     out["tile_wgs"] = int(choice[len(STAGES)])
     out["reduce_row_tasks"] = int(choice[len(STAGES) + 1])
+    out["reduce_block"] = int(choice[len(STAGES) + 2])
     return out
 
 
@@ -303,11 +305,12 @@ def tsb_masked_bispectrum(l1, l2, zeta_ptr, r_ptr, w_ptr, n_r, k_ptr, n_k, B_ptr
 
 def tsb_plan_set_schedule(h, choice):
     """Apply a schedule in the layout tsb_plan_autotune returns (a dict)."""
-    arr = (ctypes.c_int32 * 17)()
+    arr = (ctypes.c_int32 * 18)()
     for i, name in enumerate(STAGES):
         arr[i] = int(choice.get(name, 0))
     arr[len(STAGES)] = int(choice.get("tile_wgs", 0))
     arr[len(STAGES) + 1] = int(choice.get("reduce_row_tasks", -1))
+    arr[len(STAGES) + 2] = int(choice.get("reduce_block", -1))
     _check(_lib.tsb_plan_set_schedule(h, arr))
 
 

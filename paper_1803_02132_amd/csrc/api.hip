@@ -903,9 +903,14 @@ int tsb_plan_set_schedule(tsb_plan* plan, const int32_t* choice) {
   if (choice[kNumStages] < 0) return fail(TSB_E_ARG, "tile-kernel workgroups must be >= 0 (0: the occupancy default)");
   const int rt = choice[kNumStages + 1];
   if (rt < -1 || rt > 1) return fail(TSB_E_ARG, "reduction split must be -1, 0 or 1");
+  const int rb = choice[kNumStages + 2];
+  if (rb != -1 && rb != 512 && rb != 1024) return fail(TSB_E_ARG, "reduction workgroup must be -1, 512 or 1024");
+  if (rb == 512 && !P.fused && P.red_mfma == 8 && !reduce_pair_fits(P))
+    return fail(TSB_E_ARG, "two 512-thread reduction workgroups do not fit a CU for this plan");
   for (int st = 0; st < kNumStages; ++st) P.lpw_tune[st] = choice[st];
   P.tile_wgs = choice[kNumStages];
   if (rt >= 0) P.fused_rt = rt;
+  if (rb > 0 && !P.fused && P.red_mfma == 8) P.red_block = rb;
   ++P.tune_gen;
   return TSB_OK;
 }
@@ -1035,6 +1040,26 @@ int tsb_plan_autotune(tsb_plan* plan, const tsb_catalog* data, const tsb_catalog
     P.fused_rt = best_rt;
     ++P.tune_gen;
   }
+  // workgroup size of the unfused matrix-core reduction (two 512-thread
+  // workgroups per CU, or one of 1024)
+  if (!rc && !P.fused && P.red_mfma == 8) {
+    const int base = P.red_block;
+    double best = 0.0;
+    int best_b = base;
+    for (int c : {base, base == 512 ? 1024 : 512}) {
+      if (c == 512 && !reduce_pair_fits(P)) continue;
+      P.red_block = c;
+      ++P.tune_gen;
+      double ms = 0.0;
+      if ((rc = stage_time(kStReduce, &ms))) break;
+      if (c == base || ms < kTuneGain * best) {
+        best = ms;
+        best_b = c;
+      }
+    }
+    P.red_block = best_b;
+    ++P.tune_gen;
+  }
   P.prof = prof_saved;
   clear_times();
   if (rc) return rc;
@@ -1042,6 +1067,7 @@ int tsb_plan_autotune(tsb_plan* plan, const tsb_catalog* data, const tsb_catalog
     for (int st = 0; st < kNumStages; ++st) choice[st] = P.lpw_tune[st];
     choice[kNumStages] = P.tile_wgs;
     choice[kNumStages + 1] = P.fused && P.fused_wide ? P.fused_rt : -1;
+    choice[kNumStages + 2] = !P.fused && P.red_mfma == 8 ? P.red_block : -1;
   }
   return TSB_OK;
 }

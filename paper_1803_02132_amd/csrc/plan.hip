@@ -501,6 +501,8 @@ int plan_build(Plan& P) {
         P.red_chunk = Cm;
         P.red_wg = (int)std::min<int64_t>((int64_t)P.M * P.M * P.M / Cm, 1024);
       }
+      // two 512-thread workgroups per CU when both sets of staged rows fit its LDS
+      P.red_block = reduce_pair_fits(P) ? 512 : 1024;
     }
   }
   P.g_offset = P.fused ? 0 : (int64_t)P.nb * (int64_t)P.fkinds.size() * P.M * P.M * P.M;

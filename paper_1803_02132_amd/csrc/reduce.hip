@@ -213,14 +213,15 @@ __global__ void __launch_bounds__(kBlock) reduce_mfma_kernel(RedArgs<float> a) {
 }
 
 // The same reduction for FP32 plans with at most 32 shells, 16 Q groups and 64
-// terms, in 1024-thread workgroups (four wavefronts per SIMD with one
-// workgroup per CU): each thread issues its share of a chunk's field loads
+// terms, in workgroups of RB = 1024 threads (four wavefronts per SIMD with one
+// workgroup per CU), or of 512 for at most 8 Q groups when two workgroups'
+// staged rows fit the LDS of a CU (two interleaved chunk pipelines): each
+// thread issues its share of a chunk's field loads
 // before it stores any of them, the Q rows are formed one group at a time with
 // the group's terms in the kernel arguments (uniform loops, scalar loads), and
 // one wavefront per Q group runs its 32 x 32 (b1, b2) tile on the matrix cores.
 // The arithmetic is that of reduce_mfma_kernel: Q in FP64 rounded to FP32, the
 // products of a chunk summed in FP32, chunks in FP64.
-constexpr int kRWBlock = 1024;
 constexpr int kRWLoads = 16;      // field loads per thread and chunk held in registers
 constexpr int kRWTerms = 64, kRWQ = 16;
 
@@ -230,7 +231,8 @@ struct RedWideTables {
   int q_t0[kRWQ], q_t1[kRWQ], q_f2[kRWQ];
 };
 
-__global__ void __launch_bounds__(kRWBlock) reduce_mfma_wide_kernel(RedArgs<float> a, RedWideTables tb) {
+template <int kRWBlock, int kUnits>   // kUnits: Q groups per wavefront, at most
+__global__ void __launch_bounds__(kRWBlock, 1024 / kRWBlock) reduce_mfma_wide_kernel(RedArgs<float> a, RedWideTables tb) {
   extern __shared__ char smem[];
   const int C = a.chunk;
   const int CP = C + 1;
@@ -238,9 +240,11 @@ __global__ void __launch_bounds__(kRWBlock) reduce_mfma_wide_kernel(RedArgs<floa
   float* Gv = Fv + (size_t)a.nb * a.nfc * CP;    // [ngc][CP]
   float* Qv = Gv + (size_t)a.ngc * CP;           // [nq][nb][CP]
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-  double acc[16];
+  double acc[kUnits][16];
 #pragma unroll
-  for (int r = 0; r < 16; ++r) acc[r] = 0.0;
+  for (int u = 0; u < kUnits; ++u)
+#pragma unroll
+    for (int r = 0; r < 16; ++r) acc[u][r] = 0.0;
   const int nslot = a.nb * a.nkinds;
   const int nload = nslot * C + a.ngrid * C;     // complex elements staged per chunk
   for (int64_t ch = blockIdx.x; ch < a.nchunks; ch += gridDim.x) {
@@ -288,8 +292,10 @@ __global__ void __launch_bounds__(kRWBlock) reduce_mfma_wide_kernel(RedArgs<floa
       }
     }
     __syncthreads();
-    if (wave < a.nq) {
-      const int q = wave;
+#pragma unroll
+    for (int u = 0; u < kUnits; ++u) {
+      const int q = wave + u * (kRWBlock / 64);
+      if (q >= a.nq) break;   // uniform in the wavefront
       const int b = lane & 31, kh = lane >> 5;
       const bool live = b < a.nb;
       const float* qr = Qv + ((size_t)q * a.nb + (live ? b : 0)) * CP + kh;
@@ -306,16 +312,19 @@ __global__ void __launch_bounds__(kRWBlock) reduce_mfma_wide_kernel(RedArgs<floa
         for (int j = 0; j < 4; ++j) c = __builtin_amdgcn_mfma_f32_32x32x2f32(av[j], bv[j], c, 0, 0, 0);
       }
 #pragma unroll
-      for (int r = 0; r < 16; ++r) acc[r] += (double)c[r];
+      for (int r = 0; r < 16; ++r) acc[u][r] += (double)c[r];
     }
     __syncthreads();   // the next chunk overwrites the staged rows
   }
   double* Ct = (double*)smem;   // [nq][32][32]
-  if (wave < a.nq) {
+#pragma unroll
+  for (int u = 0; u < kUnits; ++u) {
+    const int q = wave + u * (kRWBlock / 64);
+    if (q >= a.nq) break;
 #pragma unroll
     for (int r = 0; r < 16; ++r) {
       const int i = 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3), j = lane & 31;
-      Ct[((size_t)wave * 32 + i) * 32 + j] = acc[r];
+      Ct[((size_t)q * 32 + i) * 32 + j] = acc[u][r];
     }
   }
   __syncthreads();
@@ -392,7 +401,10 @@ int reduce_impl(Plan& P, hipStream_t s) {
           tb.q_t1[q] = P.qgroups[q].t1;
           tb.q_f2[q] = P.qgroups[q].f2;
         }
-        hipLaunchKernelGGL(reduce_mfma_wide_kernel, dim3(P.red_wg), dim3(kRWBlock), lds_m, s, a, tb);
+        if (P.red_block == 512 && a.nq <= 8)
+          hipLaunchKernelGGL((reduce_mfma_wide_kernel<512, 1>), dim3(P.red_wg), dim3(512), lds_m, s, a, tb);
+        else
+          hipLaunchKernelGGL((reduce_mfma_wide_kernel<1024, 1>), dim3(P.red_wg), dim3(1024), lds_m, s, a, tb);
         prof_end(P, kStReduce, s);
         TSB_HIP(hipGetLastError());
         return run_reduce_final(P, s);
@@ -419,6 +431,17 @@ int reduce_impl(Plan& P, hipStream_t s) {
 }
 
 }  // namespace
+
+int64_t reduce_lds_bytes(const Plan& P) {
+  const int64_t esz = P.precision == TSB_FP64 ? 8 : 4;
+  return esz * (P.red_chunk + 1) *
+         ((int64_t)P.nb * (int64_t)P.fcomp.size() + (int64_t)P.gcomp.size() + (int64_t)P.qgroups.size() * P.nb);
+}
+
+bool reduce_pair_fits(const Plan& P) {
+  const int64_t lds = std::max<int64_t>(reduce_lds_bytes(P), (int64_t)P.qgroups.size() * 32 * 32 * 8);
+  return P.red_mfma == 8 && P.qgroups.size() <= 8 && 2 * lds <= 160 * 1024;
+}
 
 int run_reduce_final(Plan& P, hipStream_t s) {
   const int nout_all = (int)P.outs.size();

@@ -207,7 +207,9 @@ struct Plan {
   void* d_hostcat = nullptr;    // device copies of host catalogues: [2][5][hostcat_cap] float
   int64_t hostcat_cap = 0;
   int red_chunk = 64, red_wg = 1024;
-  int red_mfma = 0;             // unfused FP32 reduction on the matrix cores: Q-group tiles per wavefront (0: off)
+  int red_mfma = 0;             // unfused FP32 reduction on the matrix cores: Q-group tiles per wavefront (0: off;
+                                // 8: the wide kernel)
+  int red_block = 1024;         // wide kernel: threads per workgroup, 1024 or 512 (two per CU; autotuned)
   int64_t bytes = 0;
 
   // fused last F pass + reduction
@@ -267,6 +269,8 @@ int run_assign(Plan& P, const tsb_catalog* data, const tsb_catalog* rand, hipStr
 int run_forward(Plan& P, hipStream_t s);
 int run_inverse(Plan& P, hipStream_t s);
 int run_separation_kernels(Plan& P, hipStream_t s);   // 3PCF: fills d_kslot
+int64_t reduce_lds_bytes(const Plan& P);                // staged rows of the unfused reduction, reduce.hip
+bool reduce_pair_fits(const Plan& P);                   // two 512-thread workgroups of it per CU
 int run_reduce(Plan& P, hipStream_t s);
 int run_reduce_final(Plan& P, hipStream_t s);
 void plan_fused(Plan& P);                   // fused.hip

@@ -168,7 +168,7 @@ def test_autotune_keeps_results_bitwise():
     assert choice["tile_wgs"] >= 1
     assert choice["reduce_row_tasks"] == -1   # this plan (M = 48) does not run the one-pass reduction
     assert all(v in (8, 16, 32, 64) for k, v in choice.items()
-               if k not in ("tile_wgs", "reduce_row_tasks"))   # 0 (the rule) is not listed
+               if k not in ("tile_wgs", "reduce_row_tasks", "reduce_block"))   # 0 (the rule) is not listed
     assert _same(plan_b.measure(dev)["B"], ref)
     plan_b.set_graphs(False)
     assert _same(plan_b.measure(dev)["B"], ref)
@@ -198,3 +198,18 @@ def test_reduction_split_and_schedule_reuse_are_bitwise(mults, n_bins, dk_kf):
     other = tsb.Plan(**req)
     other.set_schedule(choice)
     assert _same(other.measure(dev)["B"], out[1])
+
+
+def test_unfused_reduction_workgroup_size_is_bitwise():
+    # the unfused matrix-core reduction in two 512-thread workgroups per CU or
+    # one of 1024: the same chunks per workgroup, the same arithmetic
+    req = box_request(n=64, n_bins=6, unfused=True)
+    dev = tsb.catalog_to_device(_cat(64, 44, 40000))
+    plan = tsb.Plan(**req)
+    assert plan.info.fused == 0
+    out = {}
+    for rb in (512, 1024):
+        plan.set_schedule({"reduce_block": rb})
+        out[rb] = plan.measure(dev)["B"]
+    _say("unfused reduction 512 vs 1024 threads bitwise", _same(out[512], out[1024]))
+    assert _same(out[512], out[1024])
