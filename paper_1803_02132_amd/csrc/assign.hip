@@ -8,16 +8,20 @@
 // fixed point and added with integer LDS atomics, so every grid value is
 // independent of thread and bucket order: the result is bitwise reproducible.
 // One 64-bit word per channel at a plan-wide scale 2^e, with sum|w| 2^e below
-// 2^61 (FP64 plans) or 2^51 (FP32 plans); in FP32 box plans, tiles that run
-// as a single work item instead add the two channels of a complex grid into
-// one word as two 32-bit sums at a per-tile scale (half the atomics). Survey
-// plans keep the plan-wide scale: their dn is the small difference of two
-// window-shaped fields (galaxies and alpha randoms), so a relative bias
-// between the two of 1e-7 already shows at the lowest k, and rounding at the
-// coarse per-tile step is biased at that level (many contributions are a
-// fraction of the step, and their fractional parts are not uniform). The
-// survey randoms channel, which feeds the normalisation, always keeps its own
-// word at the plan-wide scale.
+// 2^61 (FP64 plans) or 2^51 (FP32 plans); in FP32 plans, tiles that run as a
+// single work item instead add the two channels of a complex grid into one
+// word as two 32-bit sums at a per-tile scale (half the atomics). Rounding to
+// the nearest step is biased at that coarse step (many contributions are a
+// fraction of it, and their fractional parts are not uniform), by about 1% of
+// a step per contribution. A box plan's dn only scales by it; a survey's dn is
+// the small difference of two window-shaped fields (galaxies and alpha
+// randoms), where a relative bias of 1e-7 between the two already shows at
+// the lowest k. Survey plans therefore round each packed contribution up with
+// probability equal to its fractional part, the uniform variate a hash of the
+// particle's stencil parameters and the node (deterministic, so results stay
+// bitwise reproducible): unbiased to 2^-24 of a step. The survey randoms
+// channel, which feeds the normalisation, always keeps its own word at the
+// plan-wide scale.
 #include <cmath>
 
 #include "serve_policy.h"
@@ -395,6 +399,29 @@ __device__ inline void channel_values(const ChanInfo& ci, double x, double y, do
   }
 }
 
+// Survey plans store each channel weight in FP32 by rounding up or down with
+// probability given by the distance to the two neighbouring FP32 values (the
+// uniform variate a hash of the particle's catalogue index and the channel),
+// so that weights shared by many particles (n-bar takes few values) carry no
+// common rounding error into the cancellation of galaxies against randoms.
+__device__ inline unsigned wmix32(unsigned x) {
+  x ^= x >> 16;
+  x *= 0x7feb352dU;
+  x ^= x >> 15;
+  x *= 0x846ca68bU;
+  x ^= x >> 16;
+  return x;
+}
+
+__device__ inline float stochastic_f32(double x, unsigned h) {
+  const float f = (float)x;
+  if ((double)f == x || !isfinite(f)) return f;
+  const float lo = (double)f < x ? f : nextafterf(f, -INFINITY);
+  const float hi = (double)f < x ? nextafterf(f, INFINITY) : f;
+  const double pr = (x - (double)lo) / ((double)hi - (double)lo);
+  return (double)h * 2.3283064365386963e-10 < pr ? hi : lo;   // h 2^-32
+}
+
 // Particle records in bucket order, one contiguous record each: the grid
 // coordinate u (3 FP64; NaN in u_x marks a particle that takes no part), then
 // its channel weights in the plan precision in slot order: slots 2g and 2g+1
@@ -452,9 +479,16 @@ __global__ void __launch_bounds__(kBlock) bucket_fill_kernel(FillArgs<T, NCH> a)
     // the w^2 pass builds no normalisation: its randoms channel stays empty
     if (a.b.d.wpow == 2 && a.ci.nch < NCH) cv[a.ci.nch] = 0.0;
     T* rc = a.rec.c(slot);
+    if (sizeof(T) == 4 && !a.b.box_mode) {
+      const unsigned pk = wmix32((unsigned)i * 0x9E3779B9U ^ (unsigned)(i >> 32));
 #pragma unroll
-    for (int ch = 0; ch < NCH; ++ch)
-      if (ch < a.nchx) rc[a.slot_of[ch]] = (T)cv[ch];
+      for (int ch = 0; ch < NCH; ++ch)
+        if (ch < a.nchx) rc[a.slot_of[ch]] = (T)stochastic_f32(cv[ch], wmix32(pk + (unsigned)ch * 0x85EBCA6BU));
+    } else {
+#pragma unroll
+      for (int ch = 0; ch < NCH; ++ch)
+        if (ch < a.nchx) rc[a.slot_of[ch]] = (T)cv[ch];
+    }
     if (a.zslot >= 0) rc[a.zslot] = (T)0;
   }
 }
@@ -584,6 +618,23 @@ __device__ inline double stencil_param(double u, int p, int* j0) {
   const double j = floor(u + 0.5);
   *j0 = (int)j - (p == 3 ? 1 : 0);
   return u - j;
+}
+
+// A 32-bit mix with full avalanche (two multiply-xorshift rounds).
+__device__ inline unsigned mix32(unsigned x) {
+  x ^= x >> 16;
+  x *= 0x7feb352dU;
+  x ^= x >> 15;
+  x *= 0x846ca68bU;
+  x ^= x >> 16;
+  return x;
+}
+
+// floor(x) + 1 with probability frac(x) given a uniform u in [0, 1): the
+// expectation is x (frac(x) = x - floor(x) is exact in FP32).
+__device__ inline int dither_round(float x, float u) {
+  const float f = floorf(x);
+  return (int)f + ((x - f) > u ? 1 : 0);
 }
 
 // Fixed-point rounding to the nearest integer. FP64 plans: llrint. FP32 plans:
@@ -802,8 +853,8 @@ __global__ void __launch_bounds__(kTileBlock, (sizeof(T) == 4 && NCH <= 8) ? 4 :
   // into the slot (the shift plan_e - et is never negative then).
   const int plan_e = ilogb(scale);
   const int et_item = tile_exponent(hs >= 0 ? kPartVisits : v1 - v0, cmax * a.wmax);
-  const bool packed =
-      sizeof(T) == 4 && a.box_mode && (r_off[cb][64] <= kPartVisits || (hs >= 0 && plan_e >= et_item));
+  const bool packed = sizeof(T) == 4 && (r_off[cb][64] <= kPartVisits || (hs >= 0 && plan_e >= et_item));
+  const unsigned tile_key = mix32((unsigned)tile * 0x9E3779B9U + 0x85EBCA6BU);
   const int et = packed ? et_item : 0;
   const float tscale = ldexpf(1.0f, et);
   const int ncp = packed ? a.copies : 1;                 // grid copies per pass
@@ -916,6 +967,12 @@ __global__ void __launch_bounds__(kTileBlock, (sizeof(T) == 4 && NCH <= 8) ? 4 :
         const T wxs = packed ? wx * (T)tscale : wx;   // packed: the tile scale folded into the x weight
         unsigned long long* cbase = acc + (packed ? (size_t)cp * npair * T3 : 0);
         const bool randoms = wrw >= 0 && g0 + cp == 0;
+        // survey plans: the particle's key for the dithered rounding (its
+        // stencil parameters of this copy, the tile, the copy)
+        unsigned pkey = 0U;
+        if (sizeof(T) == 4 && packed && !a.box_mode)
+          pkey = mix32(__float_as_uint((float)V.d[0]) ^ mix32(__float_as_uint((float)V.d[1]) ^
+                       mix32(__float_as_uint((float)V.d[2]) ^ tile_key)) ^ (unsigned)(g0 + cp));
 #pragma unroll
         for (int sy = 0; sy < 3; ++sy) {
           if (sy >= cy) break;
@@ -926,7 +983,16 @@ __global__ void __launch_bounds__(kTileBlock, (sizeof(T) == 4 && NCH <= 8) ? 4 :
             if (sz >= cz) break;
             const T Wt = wxy * wz[sz];
             unsigned long long* cellp = cbase + base + oz[sz];
-            if (sizeof(T) == 4 && packed) {
+            if (sizeof(T) == 4 && packed && !a.box_mode) {
+              const unsigned h = mix32(pkey ^ (unsigned)(base + oz[sz]) * 0x9E3779B9U);
+              const float u = (float)(h >> 8) * 5.9604644775390625e-8f;   // 2^-24
+#pragma unroll
+              for (int k = 0; k < NCH / 2; ++k) {
+                if (k >= npair) break;
+                atomicAdd(cellp + (size_t)k * T3, pack2(dither_round((float)c[2 * k] * (float)Wt, u),
+                                                        dither_round((float)c[2 * k + 1] * (float)Wt, u)));
+              }
+            } else if (sizeof(T) == 4 && packed) {
 #pragma unroll
               for (int k = 0; k < NCH / 2; ++k) {
                 if (k >= npair) break;
