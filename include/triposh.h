@@ -141,8 +141,11 @@ typedef struct {
                          (eqs. 44-46: the four coincident-index terms) */
 } tsb_options;
 /* FP32 plans, precisely: channel weights are computed in FP64 and stored in
- * FP32; assignment contributions are rounded to 64-bit fixed point (exact
- * integer sums); every grid, spectrum and field is FP32 (the interlace
+ * FP32 (survey plans round each one up or down with probability given by its
+ * distance to the two neighbouring FP32 values, so that the many particles
+ * sharing an n-bar share no rounding error); assignment contributions are
+ * rounded to 64-bit fixed point (exact integer sums; survey plans round the
+ * per-tile packed sums the same unbiased way, deterministically); every grid, spectrum and field is FP32 (the interlace
  * combination and the W_mass division compute in FP64). The fused reduction
  * forms each Q row (a 3j-weighted sum of F G products, coefficients rounded to
  * FP32) and multiplies it with the right factor in FP32, summing the products
