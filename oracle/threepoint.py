@@ -41,13 +41,23 @@ Readings:
   T3  Window multipoles: the channels are built from the randoms alone with
       weight +alpha w y_L^M*(x^) (nbar of eq. 32), galaxies only fix alpha; I is
       the survey normalisation (R8).
-  T4  The 3PCF shot noise (eq. 51, which lives on r1 = r2 only) is not
-      subtracted.
+  T4  The 3PCF shot noise is the bispectrum's coincident-index terms
+      (eqs. 44-46, readings S1-S5 of oracle/shotnoise.py) with the separation
+      kernels K in place of the shell filters: the shell averages of y_l^m*
+      become Kbar = (1/V) sum_k K_l^m(k; b), which vanishes unless the bin
+      holds r = 0 (where only l = 0 survives), the two-point sums become
+      (1/V) sum_k K [dn N_L^M* - Sbar C/W^2], and the unit shell fields become
+      the kernel fields (1/V) sum_k e^{ik.x} K. For bins without r = 0 only the
+      i = j != k term is left, and it lives on b1 = b2: the grid form of eq. 51,
+      (N^3/V)(N H/I) sum_m 3j (-1)^{l1+l2} (1/N_r^2) sum_{n in b}
+      y_l1^m1*(n^) y_l2^m2*(n^) H_L^M(Hn).
 
 Pins (tests/test_oracle_threepoint.py): the FFT form against the direct sum
 over grid points and separation vectors above; the Legendre form at L = 0
 (eq. 50); the exact value Q_000 = 1 of a uniform density (I = nbar^3 V);
-transpose symmetry.
+transpose symmetry; the shot noise's i = j != k term against the real-space
+form of eq. 51 above, and the vanishing of the other terms and of the
+off-diagonal pairs for bins without r = 0.
 """
 import numpy as np
 
@@ -229,3 +239,113 @@ def measure(plan, data, randoms=None, pairs=None, window=False):
         I, alpha = info["I"], info["alpha"]
     zr, zi = reduce_fft(plan, spec, I, pairs=pairs)
     return {"zeta": zr, "zeta_imag": zi, "I": I, "alpha": alpha, "n_r": n_r(plan), "spectra": spec}
+
+
+def shot_noise(plan, spec, nk, sb, cw2, I, pairs=None):
+    """T4: the four coincident-index terms with separation kernels. Arguments as
+    shotnoise.shot_noise (spec: dn_L^M(k), nk: N_L^M(k), sb: Sbar_L^M, cw2: C/W^2).
+    Returns dict of (n_mult, n_bins, n_bins) arrays 'iii', 'jk', 'ik', 'ij', 'S'."""
+    n = plan.n
+    nb = plan.n_bins
+    sep = separation_vectors(plan)
+    if pairs is None:
+        pairs = [(b1, b2) for b1 in range(nb) for b2 in range(nb)]
+    pairs = list(pairs)
+    nmult = len(plan.multipoles)
+    out = {k: np.full((nmult, nb, nb), np.nan) for k in ("iii", "jk", "ik", "ij", "S")}
+    dv = plan.volume / n ** 3
+    nx, ny, nz = est.mode_vectors(n)
+    nyq = (np.abs(nx) == n // 2) | (np.abs(ny) == n // 2) | (np.abs(nz) == n // 2)
+    kc, hc = {}, {}
+
+    def K(l, m, b):
+        if (l, m, b) not in kc:
+            kc[(l, m, b)] = kernel(plan, l, m, b, sep)
+        return kc[(l, m, b)]
+
+    def Kbar(l, m, b):
+        return complex(np.sum(K(l, m, b)) / plan.volume)
+
+    def A(l, m, L, M, b):
+        v = spec[(0, 0)] * np.conj(nk[(L, M)]) - sb[(L, M)] * cw2
+        return complex(np.sum(K(l, m, b) * v) / plan.volume)
+
+    def f(l, m, b):
+        return (n ** 3 / plan.volume) * np.fft.ifftn(K(l, m, b))
+
+    def H(L, M):
+        if (L, M) not in hc:
+            src = spec[(L, M)] if (L, M) in spec else None
+            if src is None:   # global LOS (R10)
+                d = np.asarray(plan.los_dir, np.float64)
+                d = d / np.linalg.norm(d)
+                src = complex(np.conj(ang.ylm(L, M, d[0], d[1], d[2]))) * spec[(0, 0)]
+            h = src * np.conj(nk[(0, 0)]) - sb[(L, M)] * cw2
+            h[nyq] = 0.0
+            hc[(L, M)] = (n ** 3 / plan.volume) * np.fft.ifftn(h)
+        return hc[(L, M)]
+
+    for mu, (l1, l2, L) in enumerate(plan.multipoles):
+        terms = ang.reduction_terms(l1, l2, L, los="local")
+        pref = ang.n_factor(l1, l2, L) * ang.h_factor(l1, l2, L) / I
+        for (b1, b2) in pairs:
+            t = {"iii": 0j, "jk": 0j, "ik": 0j, "ij": 0j}
+            for (m1, m2, M, w3j) in terms:
+                t["iii"] += w3j * Kbar(l1, m1, b1) * Kbar(l2, m2, b2) * sb[(L, M)]
+                t["jk"] += w3j * A(l1, m1, L, M, b1) * Kbar(l2, m2, b2)
+                t["ik"] += w3j * Kbar(l1, m1, b1) * A(l2, m2, L, M, b2)
+                t["ij"] += w3j * dv * np.sum(f(l1, m1, b1) * f(l2, m2, b2) * H(L, M))
+            for k in t:
+                out[k][mu, b1, b2] = (pref * t[k]).real
+            out["S"][mu, b1, b2] = sum(out[k][mu, b1, b2] for k in ("iii", "jk", "ik", "ij"))
+    return out
+
+
+def shot_noise_eq51(plan, spec, nk, sb, cw2, I):
+    """The grid form of eq. 51 for bins without r = 0: diagonal pairs only,
+    (N^3/V)(N H/I) sum_m 3j (-1)^{l1+l2} (1/N_r^2) sum_{n in b} y* y* H_L^M(Hn),
+    H evaluated at the grid point of each separation vector (T4)."""
+    n = plan.n
+    nx, ny, nz, rb = separation_vectors(plan)
+    ux, uy, uz, zero = separation_units(nx, ny, nz)
+    mnx, mny, mnz = est.mode_vectors(n)
+    nyq = (np.abs(mnx) == n // 2) | (np.abs(mny) == n // 2) | (np.abs(mnz) == n // 2)
+    out = np.full((len(plan.multipoles), plan.n_bins, plan.n_bins), np.nan)
+    for mu, (l1, l2, L) in enumerate(plan.multipoles):
+        pref = ang.n_factor(l1, l2, L) * ang.h_factor(l1, l2, L) / I
+        for b in range(plan.n_bins):
+            sel = np.nonzero(rb == b)
+            if len(sel[0]) == 0:
+                continue
+            tot = 0j
+            for (m1, m2, M, w3j) in ang.reduction_terms(l1, l2, L, los="local"):
+                if (L, M) in spec:
+                    src = spec[(L, M)]
+                else:   # global LOS (R10)
+                    d = np.asarray(plan.los_dir, np.float64)
+                    d = d / np.linalg.norm(d)
+                    src = complex(np.conj(ang.ylm(L, M, d[0], d[1], d[2]))) * spec[(0, 0)]
+                h = src * np.conj(nk[(0, 0)]) - sb[(L, M)] * cw2
+                h[nyq] = 0.0
+                Hx = (n ** 3 / plan.volume) * np.fft.ifftn(h)
+                y1 = sep_ylm_conj(l1, m1, ux[sel], uy[sel], uz[sel], zero[sel])
+                y2 = sep_ylm_conj(l2, m2, ux[sel], uy[sel], uz[sel], zero[sel])
+                hv = Hx[nx[sel] % n, ny[sel] % n, nz[sel] % n]
+                tot += w3j * np.sum(y1 * y2 * hv)
+            val = (n ** 3 / plan.volume) * pref * (-1) ** (l1 + l2) * tot / len(sel[0]) ** 2
+            out[mu, b, b] = val.real
+    return out
+
+
+def measure_shot_noise(plan, data, randoms=None, pairs=None):
+    """zeta (eq. 48) and its shot noise (T4) end to end; zeta - S is the
+    shot-noise-subtracted multipole."""
+    from . import shotnoise as sn
+    res = measure(plan, data, randoms, pairs=pairs)
+    nk = sn.n_spectra(plan, data, randoms)
+    sb = sn.sbar(plan, data, randoms)
+    out = shot_noise(plan, res["spectra"], nk, sb, sn.shot_window(plan), res["I"], pairs=pairs)
+    out["zeta"] = res["zeta"]
+    out["I"] = res["I"]
+    out["alpha"] = res["alpha"]
+    return out

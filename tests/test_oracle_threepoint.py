@@ -117,3 +117,46 @@ def test_transpose_symmetry():
     z, _ = tp.reduce_fft(plan, spec, info["I"])
     assert np.allclose(z[0], z[1].T, rtol=1e-11, atol=1e-13 * np.max(np.abs(z[0])))
     assert np.allclose(z[2], z[2].T, rtol=1e-11, atol=1e-13 * np.max(np.abs(z[2])))
+
+
+def _shot_inputs(plan, seed=7, randoms=None, data=None):
+    from oracle import shotnoise as sn
+    if data is None:
+        data = lognormal_box(plan.n, plan.box_len, 2500, seed, rsd="local", observer=plan.observer,
+                             pk=lambda k: 4e3 * np.where(k > 0, (np.maximum(k, 1e-9) / 0.1) ** -1.5, 0))
+    grids, info = est.assign_channels(plan, data, randoms)
+    spec = est.spectra(plan, grids)
+    return spec, sn.n_spectra(plan, data, randoms), sn.sbar(plan, data, randoms), sn.shot_window(plan), info["I"]
+
+
+@pytest.mark.parametrize("los", ["local", "global"])
+def test_shot_noise_is_the_grid_form_of_eq51(los):
+    # bins without r = 0: only i = j != k survives (the shell-average analogues
+    # Kbar vanish) and only on b1 = b2, where it equals the real-space form of
+    # eq. 51 with (-1)^{l1+l2}
+    plan = _plan(los=los)
+    spec, nk, sb, cw2, I = _shot_inputs(plan)
+    out = tp.shot_noise(plan, spec, nk, sb, cw2, I)
+    eq51 = tp.shot_noise_eq51(plan, spec, nk, sb, cw2, I)
+    for mu in range(len(plan.multipoles)):
+        scale = np.nanmax(np.abs(out["ij"][mu]))
+        assert scale > 0
+        for k in ("iii", "jk", "ik"):
+            assert np.max(np.abs(out[k][mu])) <= 1e-12 * scale
+        diag = np.eye(plan.n_bins, dtype=bool)
+        assert np.max(np.abs(out["ij"][mu][~diag])) <= 1e-12 * scale
+        assert np.max(np.abs(out["ij"][mu][diag] - eq51[mu][diag])) <= 1e-11 * scale
+
+
+def test_shot_noise_zero_separation_bin():
+    # a bin holding r = 0: Kbar_0^0 = N^3 / (V N_r) there (the zero separation's
+    # y = delta_l0), so the i = j = k term of the monopole is
+    # (N H / I) Kbar^2 Sbar_0^0 on that pair
+    plan = _plan(k_min=0.0, dk=14.0, multipoles=[(0, 0, 0), (2, 0, 2)])
+    spec, nk, sb, cw2, I = _shot_inputs(plan, seed=8)
+    out = tp.shot_noise(plan, spec, nk, sb, cw2, I, pairs=[(0, 0), (0, 1)])
+    nr = tp.n_r(plan)
+    kbar = plan.n ** 3 / (plan.volume * nr[0])
+    want = kbar * kbar * sb[(0, 0)].real / I
+    assert out["iii"][0, 0, 0] == pytest.approx(want, rel=1e-12)
+    assert abs(out["iii"][0, 0, 1]) <= 1e-12 * abs(want)   # bin 1 holds no zero separation
