@@ -73,8 +73,11 @@ enum { TSB_PAIRS_PAPER = 0,      /* b1 <= b2 when l1 == l2, else every (b1, b2) 
  * eq. 48 with F_l^m(x; b) = (1/V) sum_k e^{ik.x} dn(k) K_l^m(k; b) and
  * K_l^m(k; b) = (1/N_r) sum_{n in b} y_l^m*(n^) e^{ik.Hn} (eq. 49 on the grid).
  * N_r and the mean |r| per bin are what tsb_plan_nmode reports for them. The
- * window multipoles need survey mode; the 3PCF shot noise (eq. 51) is not
- * subtracted. */
+ * window multipoles need survey mode. The 3PCF shot noise is eq. 51 on the
+ * grid: for r-bins without the zero separation only its i = j != k term is
+ * left, on r1 = r2 bins, (N H / I)(N^3/V) sum_m 3j (-1)^{l1+l2} N_r^-2
+ * sum_{n in b} y_l1^m1*(n^) y_l2^m2*(n^) H_L^M(H n) with the H field of
+ * eq. 45; bins holding r = 0 are refused for it. */
 enum { TSB_BISPECTRUM = 0,       /* B_{l1 l2 L}(k1, k2) (Sec. 4.2, eq. 41) */
        TSB_3PCF = 1,             /* zeta_{l1 l2 L}(r1, r2) (Sec. 4.3, eqs. 47-48) */
        TSB_WINDOW = 2 };         /* Q_{l1 l2 L}(r1, r2) from the randoms alone (Sec. 6.1, eq. 58):
@@ -137,8 +140,9 @@ typedef struct {
                          plan fits (default); 1: always write the F fields and
                          reduce separately (same result to rounding) */
   int32_t estimator;  /* TSB_BISPECTRUM, TSB_3PCF or TSB_WINDOW */
-  int32_t shot_noise; /* bispectrum: 1 subtracts the shot noise S of Sec. 4.2
-                         (eqs. 44-46: the four coincident-index terms) */
+  int32_t shot_noise; /* 1 subtracts the shot noise S: the bispectrum's of Sec. 4.2
+                         (eqs. 44-46: the four coincident-index terms), the
+                         3PCF's of eq. 51 (third-vertex LOS, not window plans) */
 } tsb_options;
 /* FP32 plans, precisely: channel weights are computed in FP64 and stored in
  * FP32 (survey plans round each one up or down with probability given by its
@@ -204,8 +208,9 @@ typedef struct tsb_plan tsb_plan;
  * memory until tsb_plan_destroy. Errors: TSB_E_ARG (NULL pointers, sizes),
  * TSB_E_UNSUPPORTED (N not 2^a 3^b, multipole outside Table 1's rules, shells
  * reaching the Nyquist frequency or r-bins reaching half the box, l > 8, a
- * grid shape the library does not cover, window multipoles in box mode, the
- * 3PCF with shot_noise), TSB_E_NOMEM, TSB_E_DEVICE. 3PCF and window plans
+ * grid shape the library does not cover, window multipoles in box mode,
+ * shot_noise with window plans, the first-vertex LOS or a 3PCF r-bin holding
+ * r = 0), TSB_E_NOMEM, TSB_E_DEVICE. 3PCF and window plans
  * build their separation kernels K here (one inverse transform per F slot). */
 int tsb_plan_create(const tsb_grid* grid, const tsb_los* los, const tsb_kbins* bins,
                     const tsb_multipole* multipoles, int32_t n_multipoles,
@@ -274,8 +279,9 @@ int tsb_measure_noalloc(tsb_plan* plan, const tsb_catalog* data, const tsb_catal
  * coincident-index terms of eq. 45 with the scalars and the w^2-weighted
  * fields of eq. 46) that the plan's last tsb_measure subtracted, into a host
  * array laid out as B_out, with the i = j != k term (the only one that
- * depends on both k1 and k2) separately in S_ijk_out (may be NULL). Only for
- * plans created with shot_noise = 1 (else TSB_E_ARG). */
+ * depends on both k1 and k2) separately in S_ijk_out (may be NULL). For 3PCF
+ * plans S(r1, r2) of eq. 51, which is that term alone and zero off r1 = r2.
+ * Only for plans created with shot_noise = 1 (else TSB_E_ARG). */
 int tsb_plan_shot_noise(const tsb_plan* plan, double* S_out, double* S_ijk_out);
 
 /* Stage entry point for checking the assignment: writes the y-weighted,

@@ -50,7 +50,9 @@ Readings:
       the kernel fields (1/V) sum_k e^{ik.x} K. For bins without r = 0 only the
       i = j != k term is left, and it lives on b1 = b2: the grid form of eq. 51,
       (N^3/V)(N H/I) sum_m 3j (-1)^{l1+l2} (1/N_r^2) sum_{n in b}
-      y_l1^m1*(n^) y_l2^m2*(n^) H_L^M(Hn).
+      y_l1^m1*(n^) y_l2^m2*(n^) H_L^M(Hn). The kernels are taken over every
+      mode of the grid, Nyquist planes included, so that the kernel fields are
+      combs of points at the separation vectors (eq. 51 holds exactly).
 
 Pins (tests/test_oracle_threepoint.py): the FFT form against the direct sum
 over grid points and separation vectors above; the Legendre form at L = 0

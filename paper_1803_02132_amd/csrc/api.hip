@@ -191,8 +191,9 @@ int plan_alloc(Plan& P, bool dry) {
     if ((rc = dalloc((void**)&P.d_Braw, std::max<int64_t>((int64_t)P.outs.size(), 1) * 8, B, dry))) return rc;
     if ((rc = dalloc((void**)&P.d_ssums, std::max<int64_t>((int64_t)P.sn_combos.size() * P.nb * 2, 1) * 8, B, dry)))
       return rc;
-    const int64_t pf3 = (int64_t)P.PF * P.PF * P.PF;
-    if (P.precision == TSB_FP64) {
+    const int64_t pf3 = P.estimator == TSB_BISPECTRUM ? (int64_t)P.PF * P.PF * P.PF : 0;
+    if (pf3 == 0) {   // (the 3PCF's term needs no unit shell fields)
+    } else if (P.precision == TSB_FP64) {
       std::vector<double> ones(2 * pf3, 0.0);
       for (int64_t i = 0; i < pf3; ++i) ones[2 * i] = 1.0;
       if ((rc = upload((double**)&P.d_ucube, ones, B, dry))) return rc;
@@ -537,7 +538,12 @@ int run_shot_measure(Plan& P, const tsb_catalog* data, const tsb_catalog* rand, 
   if (!P.outs.empty())
     TSB_HIP(hipMemcpyAsync(P.d_Braw, P.d_B, P.outs.size() * 8, hipMemcpyDeviceToDevice, s));
   P.spass = 1;
-  rc = run_reduction_part(P, s);
+  if (P.d_kslot) {   // 3PCF: the H fields, then the sum over separation vectors
+    rc = run_inverse(P, s);
+    if (!rc) rc = run_separation_shot(P, s);
+  } else {
+    rc = run_reduction_part(P, s);
+  }
   P.spass = 0;
   return rc;
 }

@@ -684,6 +684,7 @@ int inverse_impl(Plan& P, hipStream_t s) {
     if ((rc = inverse_chain<T>(P, kStInvGX, (const T2*)gsrc, pg3, ngi, P.RG, pre, fields + P.g_offset, true, s)))
       return rc;
   }
+  if (P.spass && P.d_kslot) return TSB_OK;   // the 3PCF's shot-noise term needs the H fields only
   // F slots: shell filter of dn_0^0 times y_l^m*(k^) (eq. 42), or for the 3PCF
   // dn_0^0 times the slot's separation kernel (eq. 48)
   {

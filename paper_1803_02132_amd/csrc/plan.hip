@@ -101,7 +101,8 @@ int plan_build(Plan& P) {
     return fail(TSB_E_UNSUPPORTED, "the first-vertex LOS is built for the bispectrum");
   if (x1 && P.shot_noise) return fail(TSB_E_UNSUPPORTED, "the shot noise is built for the third-vertex LOS");
   const bool xi = P.estimator != TSB_BISPECTRUM;   // separation bins (Sec. 4.3, 6.1)
-  if (xi && P.shot_noise) return fail(TSB_E_UNSUPPORTED, "the 3PCF shot noise (eq. 51) is not subtracted");
+  if (P.estimator == TSB_WINDOW && P.shot_noise)
+    return fail(TSB_E_UNSUPPORTED, "shot-noise subtraction is for the bispectrum and the 3PCF");
   if (P.estimator == TSB_WINDOW && P.box_mode)
     return fail(TSB_E_UNSUPPORTED, "window multipoles need a random catalogue (survey mode)");
   if (P.mult.empty()) return fail(TSB_E_ARG, "no multipoles");
@@ -150,6 +151,10 @@ int plan_build(Plan& P) {
   }
   bool any_bin = false;
   for (int64_t n2 = 0; n2 <= n2all; ++n2) any_bin = any_bin || lut[n2] >= 0;
+  // the 3PCF shot noise: for bins without the zero separation only its
+  // i = j != k term is left (eq. 51); a bin holding r = 0 would need the others
+  if (xi && P.shot_noise && lut[0] >= 0)
+    return fail(TSB_E_UNSUPPORTED, "the 3PCF shot noise is built for r-bins without the zero separation");
   if (!any_bin) return fail(TSB_E_UNSUPPORTED, xi ? "no grid separation falls in any r-bin"
                                                   : "no grid mode falls in any k-shell");
   // no shell may hold a mode with an index component of N/2 (those are zeroed);
@@ -507,7 +512,6 @@ int plan_build(Plan& P) {
   }
   P.g_offset = P.fused ? 0 : (int64_t)P.nb * (int64_t)P.fkinds.size() * P.M * P.M * P.M;
   if (P.shot_noise) {
-    if (P.estimator != TSB_BISPECTRUM) return fail(TSB_E_UNSUPPORTED, "shot-noise subtraction is for the bispectrum");
     if (int rc = shot_plan(P)) return rc;
     P.use_graph = false;   // its passes are launched directly
   }

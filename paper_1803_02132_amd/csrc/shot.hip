@@ -194,6 +194,117 @@ __global__ void __launch_bounds__(kBlock) shell_sums_kernel(SumArgs a) {
   }
 }
 
+struct SepArgs {
+  const void* gfields;     // real-space fields of the H spectra [ngrid][N^3]
+  const int* sep;          // F-cube indices of the separation vectors, bin by bin
+  const int* start;        // [nb + 1]
+  const OutEntry* outs;
+  const QGroup* qg;
+  const Term* terms;
+  const Component* fcomp;
+  const Component* gcomp;
+  const FKind* kinds;
+  const double* out_norm;
+  const DevScalars* scal;
+  double* B;
+  int N, RF;
+  double ynorm[45];
+};
+
+// Real or imaginary part of sum_p c_p i^-l_p y_lp^mp*(n^) for an F slot kind:
+// the slot's separation kernel at the separation vector n, per unit weight.
+__device__ inline double kind_at(const FKind& k, int part, double ux, double uy, double uz, const double* ynorm) {
+  double sr = 0.0, si = 0.0;
+  for (int p = 0; p < k.nparts; ++p) {
+    const FPart& fp = k.part[p];
+    const int am = fp.m < 0 ? -fp.m : fp.m;
+    double yr, yi;
+    ylm_pos_m(fp.l, am, ux, uy, uz, ynorm, &yr, &yi);
+    double ur = yr, ui = -yi;   // y_l^m*
+    if (fp.m < 0) {
+      const double sg = (am & 1) ? -1.0 : 1.0;
+      ur = sg * yr;
+      ui = sg * yi;
+    }
+    static constexpr double ire[4] = {1, 0, -1, 0}, iim[4] = {0, -1, 0, 1};   // i^-l
+    const int l4 = fp.l & 3;
+    const double cr = fp.fr * ire[l4] - fp.fi * iim[l4], ci = fp.fr * iim[l4] + fp.fi * ire[l4];
+    sr += cr * ur - ci * ui;
+    si += cr * ui + ci * ur;
+  }
+  return part ? si : sr;
+}
+
+// The 3PCF's i = j != k term (eq. 51). With the full separation kernels the
+// kernel field of slot kind k in bin b is a comb of points: the inverse
+// transform of sum_{n in b} Y_k(n) e^{2 pi i k.n / N} is N^3 Y_k(n) at node -n.
+// The sum over cells of f f H then runs over the bin's separation vectors and
+// vanishes unless b1 = b2. One block per output, a fixed-shape tree; the
+// plan's terms, coefficients and output norms are those of the reduction.
+template <typename T>
+__global__ void __launch_bounds__(kBlock) separation_shot_kernel(SepArgs a) {
+  typedef typename cplx<T>::type T2;
+  __shared__ double sh[kBlock];
+  const OutEntry e = a.outs[blockIdx.x];
+  const int N = a.N, RF = a.RF, PF = 2 * RF + 1;
+  const int64_t N3 = (int64_t)N * N * N;
+  const T2* g = (const T2*)a.gfields;
+  double acc = 0.0;
+  if (e.b1 == e.b2 && e.q1 > e.q0) {
+    const int t0 = a.qg[e.q0].t0, t1 = a.qg[e.q1 - 1].t1;
+    for (int q = a.start[e.b1] + threadIdx.x; q < a.start[e.b1 + 1]; q += kBlock) {
+      const int i = a.sep[q];
+      const int nx = i / (PF * PF) - RF, ny = (i / PF) % PF - RF, nz = i % PF - RF;
+      const double r = sqrt((double)nx * nx + (double)ny * ny + (double)nz * nz);
+      const double ux = nx / r, uy = ny / r, uz = nz / r;
+      const int jx = nx > 0 ? N - nx : -nx, jy = ny > 0 ? N - ny : -ny, jz = nz > 0 ? N - nz : -nz;
+      const int64_t node = ((int64_t)jx * N + jy) * N + jz;
+      for (int t = t0; t < t1; ++t) {
+        const Term tm = a.terms[t];
+        const Component c1 = a.fcomp[tm.f1], c2 = a.fcomp[tm.f2], cg = a.gcomp[tm.g];
+        const double f1 = kind_at(a.kinds[c1.slot], c1.part, ux, uy, uz, a.ynorm);
+        const double f2 = kind_at(a.kinds[c2.slot], c2.part, ux, uy, uz, a.ynorm);
+        const T2 gv = g[(int64_t)cg.slot * N3 + node];
+        acc += tm.coef * f1 * f2 * (double)(cg.part ? gv.y : gv.x);
+      }
+    }
+  }
+  sh[threadIdx.x] = acc;
+  __syncthreads();
+  for (int st = kBlock / 2; st > 0; st >>= 1) {
+    if (threadIdx.x < st) sh[threadIdx.x] += sh[threadIdx.x + st];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    const double n3 = (double)N3;
+    a.B[blockIdx.x] = sh[0] * n3 * n3 * a.out_norm[blockIdx.x] / a.scal->I;
+  }
+}
+
+template <typename T>
+int separation_shot_impl(Plan& P, hipStream_t s) {
+  if (P.outs.empty()) return TSB_OK;
+  SepArgs a{};
+  a.gfields = (const typename cplx<T>::type*)P.d_fields + P.g_offset;
+  a.sep = P.d_shell_modes;
+  a.start = P.d_shell_start;
+  a.outs = P.d_outs;
+  a.qg = P.d_qgroups;
+  a.terms = P.d_terms;
+  a.fcomp = P.d_fcomp;
+  a.gcomp = P.d_gcomp;
+  a.kinds = P.d_fkinds;
+  a.out_norm = P.d_out_norm;
+  a.scal = P.d_scal;
+  a.B = P.d_B;
+  a.N = P.N;
+  a.RF = P.RF;
+  ylm_norm_table(a.ynorm);
+  hipLaunchKernelGGL(separation_shot_kernel<T>, dim3((unsigned)P.outs.size()), dim3(kBlock), 0, s, a);
+  TSB_HIP(hipGetLastError());
+  return TSB_OK;
+}
+
 // Where Nt_L^|M| (and the channels of Sbar_L^|M|) sit in the plan's grids.
 void lm_sources(const Plan& P, LMSrc* src, int* sre, int* sim) {
   for (int k = 0; k < 81; ++k) {
@@ -255,7 +366,8 @@ int kspace_impl(Plan& P, hipStream_t s) {
   a.interlace = P.interlace;
   ylm_norm_table(a.ynorm);
   a.out = P.d_ssums;
-  if (!P.sn_combos.empty())
+  // (the 3PCF's r-bins have no shell sums: their kernel averages vanish)
+  if (!P.sn_combos.empty() && !P.d_kslot)
     hipLaunchKernelGGL(shell_sums_kernel<T>, dim3((unsigned)P.sn_combos.size(), (unsigned)P.nb), dim3(kBlock), 0, s,
                        a);
   TSB_HIP(hipGetLastError());
@@ -280,6 +392,10 @@ double alias_b(int p, double x) {
 
 int run_shot_kspace(Plan& P, hipStream_t s) {
   return P.precision == TSB_FP64 ? kspace_impl<double>(P, s) : kspace_impl<float>(P, s);
+}
+
+int run_separation_shot(Plan& P, hipStream_t s) {
+  return P.precision == TSB_FP64 ? separation_shot_impl<double>(P, s) : separation_shot_impl<float>(P, s);
 }
 
 // Host tables of a shot-noise plan: the complex terms of eq. 45 with the
@@ -310,7 +426,10 @@ int shot_plan(Plan& P) {
         P.sn_terms.push_back({mu, m1, m2, M, w, combo(l1, m1, L, M), combo(l2, m2, L, M)});
       }
   }
-  // lattice shell averages ybar_l^m*(b) for every l of the multipoles, all m
+  // lattice shell averages ybar_l^m*(b) for every l of the multipoles, all m.
+  // The 3PCF's r-bins (none holds r = 0) have separation-kernel averages
+  // (1/V) sum_k K = 0, which zero the other three terms: only the i = j != k
+  // term remains, a sum over each bin's separation vectors (the list below).
   double norm[64];
   ylm_norm_table(norm);
   P.sn_ybar.assign((size_t)(kMaxEll + 1) * (kMaxEll + 1) * P.nb * 2, 0.0);
@@ -318,6 +437,7 @@ int shot_plan(Plan& P) {
   for (auto& mp : P.mult) need[mp.l1] = need[mp.l2] = 1;
   const int RF = P.RF, PF = P.PF;
   std::vector<std::vector<int>> modes(P.nb);
+  const bool xi = P.estimator != TSB_BISPECTRUM;
   for (int x = -RF; x <= RF; ++x)
     for (int y = -RF; y <= RF; ++y)
       for (int z = -RF; z <= RF; ++z) {
@@ -326,6 +446,7 @@ int shot_plan(Plan& P) {
         const int b = P.bin_lut[n2];
         if (b < 0) continue;
         modes[b].push_back(((x + RF) * PF + (y + RF)) * PF + (z + RF));
+        if (xi) continue;
         const double r = std::sqrt((double)n2), d[3] = {x / r, y / r, z / r};
         for (int l = 0; l <= kMaxEll; ++l) {
           if (!need[l]) continue;
@@ -346,7 +467,8 @@ int shot_plan(Plan& P) {
           P.sn_ybar[k + 1] /= (double)P.nmode[b];
         }
       }
-  // shell mode list (device table built by the caller from these vectors)
+  // shell mode list, or for the 3PCF the separation vectors of each r-bin
+  // (device table built by the caller from these vectors)
   P.sn_mode_list.clear();
   P.sn_mode_start.assign(P.nb + 1, 0);
   for (int b = 0; b < P.nb; ++b) {
@@ -399,13 +521,14 @@ void shot_finish(Plan& P, const double* sbar, const double* sums, const double* 
     if (P.los_kind == TSB_LOS_GLOBAL) v *= std::conj(ylm_any(L, M, P.los_dir, norm));
     return v;
   };
+  const bool xi = P.estimator != TSB_BISPECTRUM;   // only the i = j != k term
   for (size_t o = 0; o < P.outs.size(); ++o) {
     const OutEntry& e = P.outs[o];
     const int l1 = P.mult[e.mu].l1, l2 = P.mult[e.mu].l2, L = P.mult[e.mu].L;
     const double pref = P.mu_pref[e.mu] / I;
     cd t(0.0, 0.0);
     for (const Plan::SnTerm& st : P.sn_terms) {
-      if (st.mu != e.mu) continue;
+      if (st.mu != e.mu || xi) continue;
       const cd y1 = ybar(l1, st.m1, e.b1), y2 = ybar(l2, st.m2, e.b2);
       t += st.w3j * (y1 * y2 * sbar_lm(L, st.M) + A(st.cjk, L, st.M, e.b1) * y2 + y1 * A(st.cik, L, st.M, e.b2));
     }

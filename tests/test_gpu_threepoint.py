@@ -1,7 +1,8 @@
-"""GPU parity of the three-point-function multipoles zeta (Sec. 4.3, eq. 48) and
-the window multipoles Q (Sec. 6.1, eq. 58) through the C ABI, against the
-FP64 oracle (oracle/threepoint.py): box and survey mode, local and global LOS,
-a bin holding the zero separation, FP32 and FP64 plans. Tolerance 1e-4
+"""GPU parity of the three-point-function multipoles zeta (Sec. 4.3, eq. 48),
+their shot noise (eq. 51) and the window multipoles Q (Sec. 6.1, eq. 58)
+through the C ABI, against the FP64 oracle (oracle/threepoint.py): box and
+survey mode, local and global LOS, a bin holding the zero separation, FP32 and
+FP64 plans. Tolerance 1e-4
 normwise per multipole for FP32 plans (the bispectrum's bound: the same
 assignment, transforms and reduction, with the separation kernels built in
 the plan precision), 1e-9 for FP64."""
@@ -145,3 +146,38 @@ def test_masked_model_from_measured_window():
     report("masked model from the measured window: normwise", errs, "zeta_bar", zb, zb_o)
     assert np.all(errs <= 1e-4)
     assert zb == pytest.approx(zb_o, rel=1e-4)
+
+
+
+@pytest.mark.parametrize("precision,tol", [("f32", 1e-4), ("f64", 1e-9)])
+def test_zeta_shot_noise_box(precision, tol):
+    # eq. 51 on the grid: zeta - S, S (the i = j != k term, on b1 = b2 only)
+    req = _box(precision=precision, pair_mode="all")
+    cat = lognormal_box(32, 320.0, 30000, 32, rsd="local", observer=req["observer"])
+    plan = tsb.Plan(**dict(req, estimator="3pcf", shot_noise=True))
+    got = plan.measure(tsb.catalog_to_device(cat))
+    S, Sij = plan.shot_noise()
+    ref = tp.measure_shot_noise(oracle_plan(**req), cat)
+    mask = pair_mask(req["multipoles"], req["n_bins"], "all")
+    e1 = normwise_errors(got["B"], ref["zeta"] - ref["S"], mask)
+    e2 = normwise_errors(S, ref["S"], mask)
+    report("3pcf shot noise", precision, "zeta - S", e1, "S", e2)
+    assert np.all(e1 <= tol) and np.all(e2 <= tol)
+    off = ~np.eye(req["n_bins"], dtype=bool)
+    for mu in range(len(req["multipoles"])):
+        assert np.max(np.abs(S[mu][off])) <= 1e-6 * np.max(np.abs(S[mu]))
+
+
+def test_zeta_shot_noise_survey_global_los():
+    req = _box(box_mode=False, P0=2000.0, observer=(160.0, 160.0, 160.0), los="global", los_dir=(0.2, 0.1, 1.0),
+               k_min=8.0, dk=20.0, n_bins=4, pair_mode="all", multipoles=[(0, 0, 0), (2, 0, 2), (1, 1, 0)])
+    data, rand = _shell_catalogues((160.0, 160.0, 160.0), 40.0, 140.0, 20000, 80000, 33)
+    plan = tsb.Plan(**dict(req, estimator="3pcf", shot_noise=True))
+    got = plan.measure(tsb.catalog_to_device(data), tsb.catalog_to_device(rand))
+    S, _ = plan.shot_noise()
+    ref = tp.measure_shot_noise(oracle_plan(**req), data, rand)
+    mask = pair_mask(req["multipoles"], req["n_bins"], "all")
+    e1 = normwise_errors(got["B"], ref["zeta"] - ref["S"], mask)
+    e2 = normwise_errors(S, ref["S"], mask)
+    report("3pcf shot noise survey", "zeta - S", e1, "S", e2)
+    assert np.all(e1 <= 1e-4) and np.all(e2 <= 1e-4)
