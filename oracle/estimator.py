@@ -60,12 +60,13 @@ Readings where the paper is silent or ambiguous:
       G_L^M = y_L^M*(d) G_0^0 (Sec. 4.4 takes d = z, where y_L^M*(z) = delta_M0).
   R11 The multipole is the real part of eq. 41; its imaginary part vanishes for
       l1 + l2 + L even and is returned for checking.
-  R12 LOS at the first vertex (App. B names x1, x2 and x3 as choices and
-      gives no formula): the weight y_L^M*(x^) rides on the density of the
-      first, shell-filtered field instead of the third, so eq. 41 takes
-        F_{l1 L}^{m1 M}(x; k1) = shell average of e^{ik.x} y_l1^m1*(k^) dn_L^M(k)/W
-      in place of F_l1^m1 and G_0^0 in place of G_L^M; under a global LOS the
-      two vertices give the same estimator.
+  R12 LOS at the first or second vertex (App. B names x1, x2 and x3 as
+      choices and gives no formula): the weight y_L^M*(x^) rides on the
+      density of the first (x1) or second (x2) shell-filtered field instead of
+      the third, so eq. 41 takes
+        F_{l L}^{m M}(x; k) = shell average of e^{ik.x} y_l^m*(k^) dn_L^M(k)/W
+      in place of F_l1^m1 (x1) or F_l2^m2 (x2), and G_0^0 in place of G_L^M;
+      under a global LOS every vertex gives the same estimator.
 
 The conventions R5 (interlace phase), R7 (box-mode node term) and R8 (value
 of I) are definitions, each pinned by a property it implies: R5 by the exact
@@ -103,7 +104,7 @@ class Plan:
     box_mode: bool = True        # periodic box, no randoms
     P0: float = 0.0              # FKP; <= 0 disables
     edges: Optional[tuple] = None  # explicit bin edges (n_bins + 1); replaces k_min + b dk
-    vertex: str = "x3"           # local LOS at the third vertex (main text) or the first ("x1", App. B)
+    vertex: str = "x3"           # local LOS at the third vertex (main text), the first ("x1") or second ("x2", App. B)
 
     @property
     def volume(self):
@@ -384,7 +385,7 @@ def g_field(plan, spec, L, M):
 
 def f_field(plan, spec, l, m, b, bg=None, units=None, nm=None, src=(0, 0)):
     """O9 (eq. 42 with eq. 38): F_l^m(x; b) = (N^3/N_mode(b)) ifftn(1_b y_l^m*(k^) dn/W);
-    with src = (L, M) the shell filter acts on dn_L^M (R12, first-vertex LOS)."""
+    with src = (L, M) the shell filter acts on dn_L^M (R12, LOS at x1 or x2)."""
     n = plan.n
     bg = bin_grid(plan) if bg is None else bg
     ux, uy, uz = mode_unit_vectors(plan) if units is None else units
@@ -450,6 +451,7 @@ def reduce_fft(plan, spec, I, pairs=None):
         return F
 
     first_vertex = plan.vertex == "x1" and plan.los != "global"   # R12
+    second_vertex = plan.vertex == "x2" and plan.los != "global"
 
     for b1 in sorted({p[0] for p in pairs}):
         f1 = {}
@@ -463,9 +465,12 @@ def reduce_fft(plan, spec, I, pairs=None):
                     if (mu, t) not in prod:
                         if first_vertex:
                             prod[(mu, t)] = (F1(l1, m1, (L, M)) * G(0, 0)).ravel()
+                        elif second_vertex:
+                            prod[(mu, t)] = (F1(l1, m1) * G(0, 0)).ravel()
                         else:
                             prod[(mu, t)] = (F1(l1, m1) * G(L, M)).ravel()
-                    acc += w3j * dv * np.dot(prod[(mu, t)], F2(l2, m2).ravel())
+                    f2 = F2(l2, m2, (L, M)) if second_vertex else F2(l2, m2)
+                    acc += w3j * dv * np.dot(prod[(mu, t)], f2.ravel())
                 Bre[mu, b1, b2] = (pref * acc).real
                 Bim[mu, b1, b2] = (pref * acc).imag
         del f1, prod
@@ -490,8 +495,9 @@ def brute_force(plan, spec, I, pairs=None, chunk=4096):
     """O12 (eq. 35 with eq. 38): for each multipole and shell pair,
     (N H/I) sum_m 3j (1/(N_mode1 N_mode2)) sum_{n1 in b1} sum_{n2 in b2}
         y_l1^m1*(n1^) y_l2^m2*(n2^) dn(n1) dn(n2) dn_L^M(n3),  n3 = -n1-n2 mod N.
-    Global LOS: dn_L^M = y_L^M*(d) dn (R10). First-vertex LOS (R12): dn_L^M(n1)
-    dn(n2) dn(n3) in place of dn(n1) dn(n2) dn_L^M(n3)."""
+    Global LOS: dn_L^M = y_L^M*(d) dn (R10). LOS at x1 (R12): dn_L^M(n1)
+    dn(n2) dn(n3) in place of dn(n1) dn(n2) dn_L^M(n3); at x2: dn(n1)
+    dn_L^M(n2) dn(n3)."""
     n = plan.n
     nb = plan.n_bins
     bg = bin_grid(plan)
@@ -527,12 +533,13 @@ def brute_force(plan, spec, I, pairs=None, chunk=4096):
                 else:
                     c3 = 1.0
                     s3 = spec[(L, M)]
-                if plan.vertex == "x1" and plan.los != "global":
+                d1, d2 = shells[b1][4], shells[b2][4]
+                if plan.vertex in ("x1", "x2") and plan.los != "global":
                     s3 = spec[(0, 0)]
-                    sel1 = np.nonzero(bg == b1)
-                    d1 = spec[(L, M)][sel1]
-                else:
-                    d1 = shells[b1][4]
+                    if plan.vertex == "x1":
+                        d1 = spec[(L, M)][np.nonzero(bg == b1)]
+                    else:
+                        d2 = spec[(L, M)][np.nonzero(bg == b2)]
                 a1 = np.conj(ang.ylm(l1, m1, x1, y1, z1)) * d1
                 a2 = np.conj(ang.ylm(l2, m2, x2, y2, z2)) * d2
                 s = 0j

@@ -534,3 +534,54 @@ def test_first_vertex_far_observer_matches_global_los():
     B1 = _measure_B(small_plan(los="local", vertex="x1", observer=(50.0, 50.0, -1e9), multipoles=mps), cat)
     for mu in range(len(mps)):
         assert np.max(np.abs(B1[mu] - Bg[mu])) <= 1e-6 * np.max(np.abs(Bg[mu]))
+
+
+# second-vertex LOS (App. B; reading R12 with the weight on the second field)
+
+def test_second_vertex_fft_route_equals_triangle_sum():
+    # eq. 35 with y_L^M*(x^) on the second field's density, summed directly
+    plan = small_plan(vertex="x2", multipoles=X1_MULTIPOLES)
+    cat = small_cat(seed=23)
+    Bf, If, Bb, Ib, _, _ = _both_routes(plan, cat)
+    for mu in range(len(X1_MULTIPOLES)):
+        scale = np.nanmax(np.abs(Bb[mu]))
+        assert scale > 0
+        assert np.nanmax(np.abs(Bf[mu] - Bb[mu])) <= 1e-11 * scale
+        assert np.nanmax(np.abs(If[mu])) <= 1e-11 * scale
+
+
+def test_second_vertex_is_the_first_with_the_fields_exchanged():
+    # 3j(l2 l1 L; m2 m1 M) = (-1)^{l1+l2+L} 3j(l1 l2 L; m1 m2 M), and H_{l1 l2 L}
+    # takes the same sign: B^{x2}_{l1 l2 L}(k1, k2) = B^{x1}_{l2 l1 L}(k2, k1)
+    obs = (50.0, 50.0, -30.0)
+    cat = small_cat(seed=24, observer=obs)
+    B1 = _measure_B(small_plan(vertex="x1", multipoles=X1_MULTIPOLES, observer=obs), cat)
+    B2 = _measure_B(small_plan(vertex="x2", multipoles=X1_MULTIPOLES, observer=obs), cat)
+    for mu, (l1, l2, L) in enumerate(X1_MULTIPOLES):
+        nu = X1_MULTIPOLES.index((l2, l1, L))
+        scale = np.max(np.abs(B1[nu]))
+        assert scale > 0
+        assert np.max(np.abs(B2[mu] - B1[nu].T)) <= 1e-12 * scale
+    # and it is not the first vertex itself where l1 != l2
+    mu = X1_MULTIPOLES.index((2, 0, 2))
+    assert np.max(np.abs(B2[mu] - B1[mu])) >= 1e-3 * np.max(np.abs(B1[mu]))
+
+
+def test_second_vertex_equals_third_vertex_at_L0_and_far_observer_matches_global_los():
+    obs = (50.0, 50.0, -30.0)
+    cat = small_cat(seed=25, observer=obs)
+    B2 = _measure_B(small_plan(vertex="x2", multipoles=X1_MULTIPOLES, observer=obs), cat)
+    B3 = _measure_B(small_plan(vertex="x3", multipoles=X1_MULTIPOLES, observer=obs), cat)
+    for mu, (l1, l2, L) in enumerate(X1_MULTIPOLES):
+        scale = np.max(np.abs(B3[mu]))
+        d = np.max(np.abs(B2[mu] - B3[mu]))
+        if L == 0:
+            assert d <= 1e-12 * scale
+        else:
+            assert d >= 1e-3 * scale
+    mps = [(0, 0, 0), (2, 0, 2), (0, 2, 2), (1, 1, 2)]
+    cat = small_cat(seed=16, rsd="global")
+    Bg = _measure_B(small_plan(los="global", multipoles=mps), cat)
+    B2 = _measure_B(small_plan(los="local", vertex="x2", observer=(50.0, 50.0, -1e9), multipoles=mps), cat)
+    for mu in range(len(mps)):
+        assert np.max(np.abs(B2[mu] - Bg[mu])) <= 1e-6 * np.max(np.abs(Bg[mu]))
