@@ -58,7 +58,8 @@ typedef enum {
 
 enum { TSB_LOS_GLOBAL = 0, TSB_LOS_LOCAL = 1 };
 enum { TSB_VERTEX_X3 = 0,        /* LOS at the vertex of the third field (Sec. 4.1, the main text) */
-       TSB_VERTEX_X1 = 1 };      /* LOS at the vertex of the first field (App. B) */
+       TSB_VERTEX_X1 = 1,        /* LOS at the vertex of the first field (App. B) */
+       TSB_VERTEX_X2 = 2 };      /* LOS at the vertex of the second field (App. B) */
 enum { TSB_NGP = 1, TSB_CIC = 2, TSB_TSC = 3 };
 enum { TSB_FP32 = 0, TSB_FP64 = 1 };
 enum { TSB_PAIRS_PAPER = 0,      /* b1 <= b2 when l1 == l2, else every (b1, b2) (Sec. 5.2) */
@@ -104,9 +105,10 @@ typedef struct {
   double dir[3];       /* global: LOS direction (normalised by the library) */
   double observer[3];  /* local: observer position; the LOS of a particle is
                           the unit vector from the observer to it */
-  int32_t vertex;      /* local: TSB_VERTEX_X3 (0, the paper's choice) or
-                          TSB_VERTEX_X1 (the y_L^M* weight rides on the first
-                          field of the triangle, App. B) */
+  int32_t vertex;      /* local: TSB_VERTEX_X3 (0, the paper's choice),
+                          TSB_VERTEX_X1 or TSB_VERTEX_X2 (the y_L^M* weight
+                          rides on the first or second field of the triangle,
+                          App. B; bispectrum plans without shot noise) */
 } tsb_los;
 
 /* Bins (eq. 38). Bispectrum: k-shells [k_min + b dk, k_min + (b+1) dk) in |k|,

@@ -18,7 +18,7 @@ _PAIR = {"paper": abi.TSB_PAIRS_PAPER, "upper": abi.TSB_PAIRS_UPPER, "diagonal":
 
 
 _ESTIMATOR = {"bispectrum": abi.TSB_BISPECTRUM, "3pcf": abi.TSB_3PCF, "window": abi.TSB_WINDOW}
-_VERTEX = {"x3": abi.TSB_VERTEX_X3, "x1": abi.TSB_VERTEX_X1}
+_VERTEX = {"x3": abi.TSB_VERTEX_X3, "x1": abi.TSB_VERTEX_X1, "x2": abi.TSB_VERTEX_X2}
 
 
 def _axes(v, typ):

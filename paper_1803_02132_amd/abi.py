@@ -25,7 +25,7 @@ TSB_LOS_GLOBAL, TSB_LOS_LOCAL = 0, 1
 TSB_NGP, TSB_CIC, TSB_TSC = 1, 2, 3
 TSB_FP32, TSB_FP64 = 0, 1
 TSB_PAIRS_PAPER, TSB_PAIRS_UPPER, TSB_PAIRS_DIAGONAL, TSB_PAIRS_ALL = 0, 1, 2, 3
-TSB_VERTEX_X3, TSB_VERTEX_X1 = 0, 1
+TSB_VERTEX_X3, TSB_VERTEX_X1, TSB_VERTEX_X2 = 0, 1, 2
 TSB_BISPECTRUM, TSB_3PCF, TSB_WINDOW = 0, 1, 2
 
 _STATUS = {TSB_E_ARG: "TSB_E_ARG", TSB_E_UNSUPPORTED: "TSB_E_UNSUPPORTED", TSB_E_NOMEM: "TSB_E_NOMEM",

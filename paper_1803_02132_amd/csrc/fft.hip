@@ -672,7 +672,7 @@ int inverse_impl(Plan& P, hipStream_t s) {
   int rc;
   // G grids first: band-limited spectra (eq. 42). The F chain runs last so that,
   // with the fused reduction, its y-pass output is still in d_u2 afterwards.
-  // (The first-vertex LOS needs G_0^0 only: grid 0.)
+  // (The LOS at the first or second vertex needs G_0^0 only: grid 0.)
   {
     PassArgs<T> pre{};
     pre.pre = P.n2maxG >= 0 ? 1 : 0;
@@ -680,7 +680,7 @@ int inverse_impl(Plan& P, hipStream_t s) {
     const int64_t pg3 = (int64_t)P.PG * P.PG * P.PG;
     // the shot noise's i = j != k term takes the H spectra in place of dn_L^M
     const void* gsrc = P.spass ? P.d_hspec : P.d_spec;
-    const int ngi = P.first_vertex ? 1 : (int)P.grids.size();
+    const int ngi = P.g00_only ? 1 : (int)P.grids.size();
     if ((rc = inverse_chain<T>(P, kStInvGX, (const T2*)gsrc, pg3, ngi, P.RG, pre, fields + P.g_offset, true, s)))
       return rc;
   }

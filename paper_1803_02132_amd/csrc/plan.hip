@@ -90,16 +90,18 @@ int plan_build(Plan& P) {
       if (!std::isfinite(P.edges[b]) || P.edges[b] < 0 || (b > 0 && !(P.edges[b] > P.edges[b - 1])))
         return fail(TSB_E_ARG, "edges must be finite, >= 0 and strictly increasing");
   }
-  if (P.vertex != TSB_VERTEX_X3 && P.vertex != TSB_VERTEX_X1) return fail(TSB_E_ARG, "los vertex must be 0 (x3) or 1 (x1)");
+  if (P.vertex != TSB_VERTEX_X3 && P.vertex != TSB_VERTEX_X1 && P.vertex != TSB_VERTEX_X2)
+    return fail(TSB_E_ARG, "los vertex must be 0 (x3), 1 (x1) or 2 (x2)");
   if (P.estimator < TSB_BISPECTRUM || P.estimator > TSB_WINDOW) return fail(TSB_E_ARG, "estimator must be 0, 1 or 2");
   if (P.shot_noise != 0 && P.shot_noise != 1) return fail(TSB_E_ARG, "shot_noise must be 0 or 1");
-  // LOS at the first vertex (App. B): the y_L^M* weight moves from G onto the
-  // first shell field; under a global LOS both vertices are the same estimator
+  // LOS at the first or second vertex (App. B): the y_L^M* weight moves from G
+  // onto that shell field; under a global LOS every vertex is the same estimator
   const bool x1 = P.vertex == TSB_VERTEX_X1 && P.los_kind == TSB_LOS_LOCAL;
-  P.first_vertex = x1;
-  if (x1 && P.estimator != TSB_BISPECTRUM)
-    return fail(TSB_E_UNSUPPORTED, "the first-vertex LOS is built for the bispectrum");
-  if (x1 && P.shot_noise) return fail(TSB_E_UNSUPPORTED, "the shot noise is built for the third-vertex LOS");
+  const bool x2 = P.vertex == TSB_VERTEX_X2 && P.los_kind == TSB_LOS_LOCAL;
+  P.g00_only = x1 || x2;
+  if (P.g00_only && P.estimator != TSB_BISPECTRUM)
+    return fail(TSB_E_UNSUPPORTED, "the first- and second-vertex LOS are built for the bispectrum");
+  if (P.g00_only && P.shot_noise) return fail(TSB_E_UNSUPPORTED, "the shot noise is built for the third-vertex LOS");
   const bool xi = P.estimator != TSB_BISPECTRUM;   // separation bins (Sec. 4.3, 6.1)
   if (P.estimator == TSB_WINDOW && P.shot_noise)
     return fail(TSB_E_UNSUPPORTED, "shot-noise subtraction is for the bispectrum and the 3PCF");
@@ -240,8 +242,9 @@ int plan_build(Plan& P) {
       P.chans.push_back({L, M, 1});
       P.grids.push_back({c, c + 1});
     }
-  // (L, M, part) -> G component (grid, part); the first-vertex LOS needs G_0^0
-  // only (grid 0, real part), the other grids feed its first shell fields
+  // (L, M, part) -> G component (grid, part); the LOS at the first or second
+  // vertex needs G_0^0 only (grid 0, real part), the other grids feed the
+  // weighted shell fields
   std::map<std::tuple<int, int, int>, int> gkey;
   P.gcomp.clear();
   for (int g = 0; g < (int)P.grids.size(); ++g) {
@@ -249,7 +252,7 @@ int plan_build(Plan& P) {
       int c = part ? P.grids[g].im : P.grids[g].re;
       if (c < 0) continue;
       const RealChannel& ch = P.chans[c];
-      if (x1 && (ch.L != 0 || ch.M != 0)) continue;
+      if (P.g00_only && (ch.L != 0 || ch.M != 0)) continue;
       gkey[std::make_tuple(ch.L, ch.M, ch.part)] = (int)P.gcomp.size();
       P.gcomp.push_back({g, part});
     }
@@ -260,7 +263,8 @@ int plan_build(Plan& P) {
   ylm_norm_table(norm);
   // logical F components: (l, m, part, L, M) for the shell field of
   // y_l^m*(k^) dn_L^M(k); dn_0^0 (L = M = 0) for every field of the
-  // third-vertex LOS and for the second field of the first-vertex one. Of
+  // third-vertex LOS and for the unweighted field of the first- or
+  // second-vertex one. Of
   // each conjugate pair, F_{l L}^{-m -M} = (-1)^{l+m+M} conj(F_{l L}^{m M})
   // (real catalogue weights), the member with M > 0, or M = 0 and m >= 0, is
   // kept: part 0/1 = its Re/Im, or for m = M = 0 part 0 = the real field
@@ -286,7 +290,7 @@ int plan_build(Plan& P) {
   };
   auto gfactor = [&](int L, int M) {
     std::vector<std::pair<int, cd>> out;
-    if (x1) {   // the weight sits in the first field
+    if (P.g00_only) {   // the weight sits in the first or second field
       out.push_back({gkey.at(std::make_tuple(0, 0, 0)), cd(1, 0)});
       return out;
     }
@@ -326,7 +330,7 @@ int plan_build(Plan& P) {
         double w = three_j(l1, l2, L, m1, m2, M);
         if (w == 0.0) continue;
         for (auto& a : (x1 ? ffactor(l1, m1, L, M) : ffactor(l1, m1)))
-          for (auto& b : ffactor(l2, m2))
+          for (auto& b : (x2 ? ffactor(l2, m2, L, M) : ffactor(l2, m2)))
             for (auto& c : gfactor(L, M)) {
               double re = (phase * w * a.second * b.second * c.second).real();
               acc[std::make_tuple(mu, a.first, b.first, c.first)] += re;

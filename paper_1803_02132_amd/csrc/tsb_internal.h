@@ -92,7 +92,7 @@ struct Plan {
   std::vector<tsb_multipole> mult;
   int precision = TSB_FP32, pair_mode = TSB_PAIRS_PAPER, box_mode = 1, unfused = 0;
   int vertex = TSB_VERTEX_X3, estimator = TSB_BISPECTRUM, shot_noise = 0;
-  bool first_vertex = false;    // local LOS at the first vertex (App. B)
+  bool g00_only = false;        // local LOS at the first or second vertex (App. B): G_0^0 is the one G field
   bool fsources = false;        // some F slot part filters a channel other than dn_0^0
   double P0 = 0;
   int device = 0;

@@ -122,6 +122,7 @@ def test_paper_pair_counts_for_eleven_shells():
     (dict(los="global", los_dir=(0.0, 0.0, 0.0)), tsb.abi.TSB_E_ARG),
     (dict(box_len=(1000.0, 1000.0, 1200.0)), tsb.abi.TSB_E_UNSUPPORTED),   # one fundamental frequency needed
     (dict(n_bins=2, edges=[0.01, 0.02, 0.02]), tsb.abi.TSB_E_ARG),         # edges not increasing
+    (dict(vertex="x2", shot_noise=True), tsb.abi.TSB_E_UNSUPPORTED),       # shot noise: third vertex only
 ])
 def test_invalid_requests(bad, code):
     with pytest.raises(tsb.TsbError) as e:
@@ -154,6 +155,7 @@ def test_separation_bins_of_the_3pcf_match_the_oracle():
     (dict(estimator="window", shot_noise=True, box_mode=False), tsb.abi.TSB_E_UNSUPPORTED),
     (dict(estimator="3pcf", dk=30.0), tsb.abi.TSB_E_UNSUPPORTED),          # r-bins reach half the box
     (dict(estimator="3pcf", k_min=500.0), tsb.abi.TSB_E_UNSUPPORTED),      # no separation in any bin
+    (dict(estimator="3pcf", vertex="x2", k_min=5.0), tsb.abi.TSB_E_UNSUPPORTED),   # LOS at x2: bispectrum only
 ])
 def test_invalid_3pcf_requests(bad, code):
     r = dict(n=16, box_len=160.0, multipoles=[(0, 0, 0)], n_bins=3, dk=11.0, k_min=0.0, box_mode=True)

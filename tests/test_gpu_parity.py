@@ -184,12 +184,13 @@ def test_survey_fkp():
 X1_MULTS = [(0, 0, 0), (2, 0, 2), (0, 2, 2), (1, 1, 2), (2, 2, 2), (1, 1, 0)]
 
 
+@pytest.mark.parametrize("vertex", ["x1", "x2"])
 @pytest.mark.parametrize("precision,tol", [("f32", 1e-4), ("f64", 1e-9)])
-def test_first_vertex_los_box(precision, tol):
-    # App. B: the y_L^M* weight on the first shell field (grid spectra of every
-    # channel as sources, packed real channels split by Hermitian symmetry,
-    # m < 0 harmonics), G_0^0 only; the observer near the box
-    req = box_request(n=32, n_bins=6, vertex="x1", multipoles=X1_MULTS, precision=precision,
+def test_first_vertex_los_box(precision, tol, vertex):
+    # App. B: the y_L^M* weight on the first (second) shell field (grid spectra
+    # of every channel as sources, packed real channels split by Hermitian
+    # symmetry, m < 0 harmonics), G_0^0 only; the observer near the box
+    req = box_request(n=32, n_bins=6, vertex=vertex, multipoles=X1_MULTS, precision=precision,
                       observer=(500.0, 400.0, -300.0))
     cat = small_cat(seed=31, observer=(500.0, 400.0, -300.0))
     plan, g, o = run_both(req, cat)
@@ -198,19 +199,20 @@ def test_first_vertex_los_box(precision, tol):
     # and it is a different estimator from the third-vertex one at L > 0
     b3 = tsb.Plan(**dict(req, vertex="x3")).measure(tsb.catalog_to_device(cat))["B"]
     diff = normwise_errors(b3, o["B"], mask)
-    _say("first vertex", precision, "errors", err, "x3 vs x1 oracle", diff)
+    _say(vertex, "vertex", precision, "errors", err, "x3 vs its oracle", diff)
     assert np.all(err <= tol)
     assert all(diff[mu] > 1e-3 for mu, m in enumerate(X1_MULTS) if m[2] > 0)
 
 
-def test_first_vertex_los_survey_with_hexadecapole():
-    req = box_request(n=32, box_mode=False, P0=1e4, interlace=True, observer=(500.0, 500.0, 500.0), vertex="x1",
+@pytest.mark.parametrize("vertex", ["x1", "x2"])
+def test_first_vertex_los_survey_with_hexadecapole(vertex):
+    req = box_request(n=32, box_mode=False, P0=1e4, interlace=True, observer=(500.0, 500.0, 500.0), vertex=vertex,
                       multipoles=[(0, 0, 0), (2, 0, 2), (4, 0, 4), (2, 2, 4)], precision="f32", n_bins=6)
     data, rand = survey_inputs()
     plan, g, o = run_both(req, data, rand)
     mask = pair_mask(req["multipoles"], req["n_bins"])
     err = normwise_errors(g["B"], o["B"], mask)
-    _say("first vertex survey errors", err)
+    _say(vertex, "vertex survey errors", err)
     assert np.all(err <= 1e-4)
 
 
