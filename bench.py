@@ -61,31 +61,58 @@ def workload_request(name):
     return req
 
 
-def stage_bytes(info, copies, n_particles, fused=True, esz=4, n_bins=None):
+def live_lines(r, r2):
+    """Lines of a pruned cube (frequencies |n_i| <= r) that the inverse chain
+    reads or writes under the sparsity rule (zero beyond |n|^2 = r2): the
+    (n_a, n_b) pairs of the x pass and the n_b values of the y pass."""
+    f = np.arange(-r, r + 1)
+    return int(np.sum(f[:, None] ** 2 + f[None, :] ** 2 <= r2)), int(np.sum(f * f <= r2))
+
+
+def shell_r2(info, req):
+    """Largest |n|^2 of the modes of each k-shell (the library's bin rule)."""
+    kf = 2.0 * math.pi / req["box_len"]
+    n2 = np.arange(3 * info.r_f ** 2 + 1)
+    b = np.floor((kf * np.sqrt(n2) - req["k_min"]) / req["dk"]).astype(np.int64)
+    return [int(n2[b == i].max()) if np.any(b == i) else -1 for i in range(req["n_bins"])]
+
+
+def stage_bytes(info, copies, n_particles, req, fused=True, esz=4):
     """Algorithmic HBM bytes per launch of each single-kernel stage: every input
     read once and every output written once in the stated layout (particle
-    records: 12 B of position plus 4 B per channel)."""
+    records: 12 B of position plus 4 B per channel). The inverse transforms of
+    shell-filtered and band-limited spectra count the lines and entries that
+    can be non-zero: for shell b, the (n_y, n_z) lines of the x pass and the
+    n_z entries after it with |n|^2 within the shell's largest |n|^2."""
     c = 2 * esz
     N, M = info.n, info.m
     PG, PF = 2 * info.r_g + 1, 2 * info.r_f + 1
     ng = info.n_grids
     nbc = copies * ng
-    nf = info.n_fslots * (WORKLOAD["n_bins"] if n_bins is None else n_bins)
+    nk = info.n_fslots
+    nf = nk * req["n_bins"]
+    lf = [live_lines(info.r_f, r2) for r2 in shell_r2(info, req)]
+    lf1 = nk * sum(x[0] for x in lf)       # live x-pass lines over every F slot
+    lf2 = nk * sum(x[1] for x in lf)       # live y-pass lines per x over every F slot
+    if 4 * info.r_f < info.n:   # band-limited G (the reduced-grid rule): |n|^2 <= 4 n2max of the shells
+        g1, g2 = live_lines(info.r_g, 4 * max(shell_r2(info, req)))
+    else:
+        g1, g2 = PG * PG, PG
     out = {
         "assign": nbc * N ** 3 * c + (24 + 4 * info.n_channels) * n_particles,
         "fwd_z": nbc * N ** 3 * c + nbc * N * N * PG * c,
         "fwd_y": nbc * N * N * PG * c + nbc * N * PG * PG * c,
         "fwd_x": nbc * N * PG * PG * c + nbc * PG ** 3 * c,
-        "invF_x": PF ** 3 * c + nf * M * PF * PF * c,
-        "invF_y": nf * M * PF * PF * c + nf * M * M * PF * c,
-        "invG_x": ng * PG ** 3 * c + ng * M * PG * PG * c,
-        "invG_y": ng * M * PG * PG * c + ng * M * M * PG * c,
-        "invG_z": ng * M * M * PG * c + ng * M ** 3 * c,
+        "invF_x": PF ** 3 * c + lf1 * M * c,
+        "invF_y": lf1 * M * c + lf2 * M * M * c,
+        "invG_x": ng * PG ** 3 * c + ng * M * g1 * c,
+        "invG_y": ng * M * g1 * c + ng * M * M * g2 * c,
+        "invG_z": ng * M * M * g2 * c + ng * M ** 3 * c,
     }
     if fused:   # last F transform inside the reduction: reads the y-pass output and G
-        out["reduce"] = nf * M * M * PF * c + ng * M ** 3 * c
+        out["reduce"] = lf2 * M * M * c + ng * M ** 3 * c
     else:
-        out["invF_z"] = nf * M * M * PF * c + nf * M ** 3 * c
+        out["invF_z"] = lf2 * M * M * c + nf * M ** 3 * c
         out["reduce"] = (nf + ng) * M ** 3 * c
     return out
 
@@ -604,7 +631,7 @@ def main():
     if rands is not None:
         n_mean += float(rands[0]["x"].numel())
     fused = times["invF_z"][1] == 0
-    bytes_alg = stage_bytes(info, 1 + int(bool(req["interlace"])), n_mean, fused=fused, n_bins=req["n_bins"])
+    bytes_alg = stage_bytes(info, 1 + int(bool(req["interlace"])), n_mean, req, fused=fused)
     per_launch = {k: (ms / calls if calls else 0.0) for k, (ms, calls) in times.items()}
     log("stage mean ms per launch: " + ", ".join(f"{k}={v:.3f}" for k, v in per_launch.items()))
     dom = max((k for k in bytes_alg), key=lambda k: times[k][0])

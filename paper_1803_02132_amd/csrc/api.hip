@@ -157,6 +157,12 @@ int plan_alloc(Plan& P, bool dry) {
   if ((rc = twiddles(&P.d_tw_m, P.M, f64, B, dry))) return rc;
   if ((rc = upload(&P.d_bin_lut, P.bin_lut, B, dry))) return rc;
   {
+    std::vector<int> r2(std::max(P.nb, 1), -1);   // -1: a bin with no mode
+    for (size_t n2 = 0; n2 < P.bin_lut.size(); ++n2)
+      if (P.bin_lut[n2] >= 0) r2[P.bin_lut[n2]] = (int)n2;
+    if ((rc = upload(&P.d_bin_r2, r2, B, dry))) return rc;
+  }
+  {
     // combine-step tables (eq. 39 and the interlace phase, per axis)
     std::vector<double> tab(3 * (size_t)PG);
     for (int64_t j = 0; j < PG; ++j) {
@@ -222,7 +228,7 @@ void plan_free(Plan& P) {
   P.cap_stream = P.own_stream = nullptr;
   P.h_res = nullptr;
   void* ptrs[] = {P.d_grid, P.d_t1, P.d_t2, P.d_t3, P.d_spec, P.d_dcube, P.d_u1, P.d_u2, P.d_fields,
-                  P.d_tw_n, P.d_tw_m, P.d_bin_lut, P.d_fkinds, P.d_fcomp, P.d_gcomp, P.d_terms,
+                  P.d_tw_n, P.d_tw_m, P.d_bin_lut, P.d_bin_r2, P.d_fkinds, P.d_fcomp, P.d_gcomp, P.d_terms,
                   P.d_qgroups, P.d_outs, P.d_out_norm, P.d_partials, P.d_B, P.d_scal, P.d_sum_partials,
                   P.d_bk_count, P.d_bk_start, P.d_scan_part, P.d_keys, P.d_rec,
                   P.d_f2idx, P.d_yspec, P.d_axis_tab, P.d_tile_hslot, P.d_heavy_tile,

@@ -49,8 +49,53 @@ struct PassArgs {
   int64_t kslot_bs;
   const void* spec;        // pre 4: spectra [grid][PG^3], frequency n at n + RG per axis
   int RG;
+  // Sparsity of shell-filtered or band-limited spectra: a line, or an entry,
+  // whose frequency coordinates alone give |n|^2 above r2 holds zeros; such a
+  // line is neither read nor written, such an entry not read (every consumer
+  // of the pass buffers applies the same rule). r2 = sp_r2[batch / sp_div], or
+  // sp_c when sp_r2 is null; sp_a, sp_b, sp_e: the offset that turns index a,
+  // b, e into a frequency (-1: the index is a position and does not count).
+  int sp;
+  const int* sp_r2;
+  int sp_div;
+  int64_t sp_c;
+  int sp_a, sp_b, sp_e;
   double ynorm[45];
 };
+
+// Live lines [*lo, *hi) of a workgroup's lines [b0, b0 + nl) under the
+// sparsity rule, and the squared frequency of index a (false: none live).
+template <typename T>
+__device__ inline bool sparse_lines(const PassArgs<T>& a, int batch, int ia, int b0, int nl, int64_t* r2,
+                                    int64_t* fa2, int* lo, int* hi) {
+  *lo = b0;
+  *hi = b0 + nl;
+  *fa2 = 0;
+  *r2 = 0;
+  if (!a.sp) return true;
+  *r2 = a.sp_r2 ? (int64_t)a.sp_r2[batch / a.sp_div] : a.sp_c;
+  if (a.sp_a >= 0) *fa2 = (int64_t)(ia - a.sp_a) * (ia - a.sp_a);
+  const int64_t rem = *r2 - *fa2;
+  if (rem < 0) return false;
+  if (a.sp_b >= 0) {
+    int h = (int)sqrt((double)rem);
+    while ((int64_t)h * h > rem) --h;
+    while ((int64_t)(h + 1) * (h + 1) <= rem) ++h;
+    *lo = max(*lo, a.sp_b - h);
+    *hi = min(*hi, a.sp_b + h + 1);
+  }
+  return *lo < *hi;
+}
+
+// Whether stored entry e of line b is a zero of the sparsity rule.
+template <typename T>
+__device__ inline bool sparse_zero(const PassArgs<T>& a, int64_t r2, int64_t fa2, int b, int e) {
+  if (!a.sp) return false;
+  int64_t f = fa2;
+  if (a.sp_b >= 0) f += (int64_t)(b - a.sp_b) * (b - a.sp_b);
+  if (a.sp_e >= 0) f += (int64_t)(e - a.sp_e) * (e - a.sp_e);
+  return f > r2;
+}
 
 template <typename T2, typename T>
 __device__ inline T2 cmul(T2 a, T2 b) {
@@ -196,9 +241,14 @@ __global__ void __launch_bounds__(kBlock) fft_pass_kernel(PassArgs<T> a) {
   const int64_t rest = blk / nbb;
   const int ia = (int)(rest % a.dA);
   const int batch = (int)(rest / a.dA);
-  const int b0 = bb * a.lpw;
-  const int nl = min(a.lpw, a.dB - b0);
+  int b0 = bb * a.lpw;
+  int nl = min(a.lpw, a.dB - b0);
   const int tid = threadIdx.x;
+  int64_t r2, fa2;
+  int blo, bhi;
+  if (!sparse_lines(a, batch, ia, b0, nl, &r2, &fa2, &blo, &bhi)) return;   // uniform: no live line
+  b0 = blo;
+  nl = bhi - blo;
 
   T2 zero;
   zero.x = 0;
@@ -218,8 +268,11 @@ __global__ void __launch_bounds__(kBlock) fft_pass_kernel(PassArgs<T> a) {
       e = idx / nl;
       j = idx - e * nl;
     }
-    T2 v = inb[(int64_t)(b0 + j) * a.in_sb + (int64_t)e * a.in_se];
-    if (a.pre) v = apply_pre<T>(a, batch, ia, b0 + j, e, v);
+    T2 v = zero;
+    if (!sparse_zero(a, r2, fa2, b0 + j, e)) {
+      v = inb[(int64_t)(b0 + j) * a.in_sb + (int64_t)e * a.in_se];
+      if (a.pre) v = apply_pre<T>(a, batch, ia, b0 + j, e, v);
+    }
     int pos = e - a.in_off;
     if (pos < 0) pos += N;
     buf0[j * NP + pos] = v;
@@ -403,8 +456,13 @@ __global__ void __launch_bounds__(kBlock) fft4_kernel(PassArgs<T> a) {
   const int64_t rest = blk / nbb;
   const int ia = (int)(rest % a.dA);
   const int batch = (int)(rest / a.dA);
-  const int b0 = bb * a.lpw;
-  const int nl = min(a.lpw, a.dB - b0);
+  int b0 = bb * a.lpw;
+  int nl = min(a.lpw, a.dB - b0);
+  int64_t r2, fa2;
+  int blo, bhi;
+  if (!sparse_lines(a, batch, ia, b0, nl, &r2, &fa2, &blo, &bhi)) return;   // uniform: no live line
+  b0 = blo;
+  nl = bhi - blo;
   const T2* inb = a.in + (int64_t)batch * a.in_bs + (int64_t)ia * a.in_sa;
   T2* outb = a.out + (int64_t)batch * a.out_bs + (int64_t)ia * a.out_sa;
 
@@ -427,7 +485,7 @@ __global__ void __launch_bounds__(kBlock) fft4_kernel(PassArgs<T> a) {
       T2 x;
       x.x = 0;
       x.y = 0;
-      if (e < a.in_cnt) {
+      if (e < a.in_cnt && !sparse_zero(a, r2, fa2, b0 + j, e)) {
         x = inb[(int64_t)(b0 + j) * a.in_sb + (int64_t)e * a.in_se];
         if (a.pre) x = apply_pre<T>(a, batch, ia, b0 + j, e, x);
       }
@@ -619,9 +677,31 @@ int inverse_chain(Plan& P, int stage0, const typename cplx<T>::type* cube, int64
   const int M = P.M, PR = 2 * R + 1;
   const int64_t M2 = (int64_t)M * M, PR2 = (int64_t)PR * PR, PRs = pad_line(PR);
   int rc;
+  // Sparsity: shell-filtered slots vanish outside the largest |n|^2 of their
+  // bin, band-limited grids outside n2max; lines beyond them are skipped.
+  PassArgs<T> sp{};
+  if (pre.pre == 2 || pre.pre == 4) {
+    sp.sp = 1;
+    sp.sp_r2 = P.d_bin_r2;
+    sp.sp_div = pre.nkinds;
+  } else if (pre.pre == 1) {
+    sp.sp = 1;
+    sp.sp_c = pre.n2max;
+    sp.sp_div = 1;
+  }
+  auto sparse = [&](PassArgs<T>& a, int oa, int ob, int oe) {
+    a.sp = sp.sp;
+    a.sp_r2 = sp.sp_r2;
+    a.sp_div = sp.sp_div;
+    a.sp_c = sp.sp_c;
+    a.sp_a = oa;
+    a.sp_b = ob;
+    a.sp_e = oe;
+  };
   // x with the pre-operation: [b][qx][qy][qz] -> [b][x][qy][qz]
   {
     PassArgs<T> a = pre;
+    sparse(a, R, R, R);
     a.in = cube;
     a.out = (T2*)P.d_u1;
     a.tw = (const T2*)P.d_tw_m;
@@ -645,6 +725,7 @@ int inverse_chain(Plan& P, int stage0, const typename cplx<T>::type* cube, int64
     a.out_bs = M2 * PRs; a.out_sa = (int64_t)M * PRs; a.out_sb = 1; a.out_se = PRs;
     a.in_cnt = PR; a.in_off = R; a.out_cnt = M; a.out_off = 0;
     a.N = M; a.dir = 1; a.contiguous = 0;
+    sparse(a, -1, R, R);
     if ((rc = launch_pass<T>(P, stage0 + 1, a, s))) return rc;
   }
   // z (contiguous): [b][x][y][qz] -> [b][x][y][z]
@@ -658,6 +739,7 @@ int inverse_chain(Plan& P, int stage0, const typename cplx<T>::type* cube, int64
     a.out_bs = M2 * M; a.out_sa = M2; a.out_sb = M; a.out_se = 1;
     a.in_cnt = PR; a.in_off = R; a.out_cnt = M; a.out_off = 0;
     a.N = M; a.dir = 1; a.contiguous = 1;
+    sparse(a, -1, -1, R);
     if ((rc = launch_pass<T>(P, stage0 + 2, a, s))) return rc;
   }
   return TSB_OK;

@@ -33,6 +33,8 @@ template <typename T>
 struct FusedArgs {
   typedef typename cplx<T>::type T2;
   const T2* u2;        // F slots after the x and y passes: [nf][M][M][PF]
+  const int* bin_r2;   // per bin the largest |n|^2: entries beyond it were not written (zeros);
+                       // null for the 3PCF, whose separation kernels fill every mode
   const T2* gfields;   // G grids [ngrid][M^3]
   const T2* tw;        // e^{-2 pi i k / M}
   int RF, PF, PFs, nb, nkinds, ngrid, ngc, nq, nf2, bpg;   // PFs: stored line stride of u2
@@ -103,6 +105,7 @@ __global__ void __launch_bounds__(kBlock) fz_reduce_kernel(FusedArgs<T> a) {
         const int sl = task / N1, n1 = task - sl * N1;
         const int64_t slot = (int64_t)b0 * nk + sl;
         const T2* src = a.u2 + (slot * M * M + line) * a.PFs;
+        const int r2 = a.bin_r2 ? a.bin_r2[b0 + sl / nk] : 0x7fffffff;
         T2 v[N2];
 #pragma unroll
         for (int n2 = 0; n2 < N2; ++n2) {
@@ -111,7 +114,7 @@ __global__ void __launch_bounds__(kBlock) fz_reduce_kernel(FusedArgs<T> a) {
           T2 x;
           x.x = 0;
           x.y = 0;
-          if (e < a.PF) x = src[e];
+          if (e < a.PF && (e - a.RF) * (e - a.RF) <= r2) x = src[e];
           v[n2] = x;
         }
         reg_fft<T, T2, N2>(v, 1);
@@ -330,6 +333,7 @@ __global__ void __launch_bounds__(kWBlock) fz_reduce_wide_kernel(FusedArgs<float
   auto prefetch = [&](int64_t line, int g) {
     if (sl < group_slots(g)) {
       const T2* src = a.u2 + ((int64_t)(g * bpg * nk + sl) * M * M + line) * a.PFs;
+      const int r2 = a.bin_r2 ? a.bin_r2[g * bpg + sl / nk] : 0x7fffffff;
 #pragma unroll
       for (int n2 = 0; n2 < N2; ++n2) {
         int e = n1 + N1 * n2 + a.RF;
@@ -337,7 +341,7 @@ __global__ void __launch_bounds__(kWBlock) fz_reduce_wide_kernel(FusedArgs<float
         T2 x;
         x.x = 0.f;
         x.y = 0.f;
-        if (e < a.PF) x = src[e];
+        if (e < a.PF && (e - a.RF) * (e - a.RF) <= r2) x = src[e];
         pv[n2] = x;
       }
     }
@@ -633,6 +637,7 @@ int fused_launch(Plan& P, hipStream_t s) {
   typedef typename cplx<T>::type T2;
   FusedArgs<T> a{};
   a.u2 = (const T2*)P.d_u2;
+  a.bin_r2 = P.d_kslot ? nullptr : P.d_bin_r2;   // separation kernels fill every mode
   a.gfields = (const T2*)P.d_fields + P.g_offset;
   a.tw = (const T2*)P.d_tw_m;
   a.RF = P.RF;

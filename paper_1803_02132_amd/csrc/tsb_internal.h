@@ -133,6 +133,7 @@ struct Plan {
   void* d_tw_n = nullptr;     // twiddles e^{-2 pi i k/N}
   void* d_tw_m = nullptr;     // twiddles e^{-2 pi i k/M}
   int* d_bin_lut = nullptr;
+  int* d_bin_r2 = nullptr;    // per bin: the largest |n|^2 of its modes (sparsity of the F chain)
   FKind* d_fkinds = nullptr;
   Component* d_fcomp = nullptr;
   Component* d_gcomp = nullptr;
