@@ -111,7 +111,7 @@ int carve_workspace(Plan& P, Carver& cv, int64_t& B) {
   const int64_t PGs = pad_line(PG), PFs = pad_line(PF);
   ALLOC(P.d_t1, nbc * N * N * PGs * c);
   ALLOC(P.d_t2, nbc * N * PG * PGs * c);
-  ALLOC(P.d_t3, nbc * PG * PG * PG * c);
+  ALLOC(P.d_t3, combine_fusable((int)N) ? 0 : nbc * PG * PG * PG * c);   // x-pass output before combine_kernel
   ALLOC(P.d_spec, ng * PG * PG * PG * c);
   ALLOC(P.d_dcube, PF * PF * PF * c);
   ALLOC(P.d_u1, std::max(nf * PF * PFs * M, ng * PG * PGs * M) * c);

@@ -60,6 +60,15 @@ struct PassArgs {
   int sp_div;
   int64_t sp_c;
   int sp_a, sp_b, sp_e;
+  // forward x pass with the combination (fft4_combine_kernel): copies of each
+  // grid, the input stride between them, the per-axis table of combine_kernel,
+  // the box-mode mean term (or null), the scalars holding its mean, DC zeroing
+  int cb_copies;
+  int64_t cb_copy_bs;
+  const double* cb_tab;
+  const T2* cb_yspec;
+  const DevScalars* cb_scal;
+  int cb_box;
   double ynorm[45];
 };
 
@@ -531,6 +540,160 @@ __global__ void __launch_bounds__(kBlock) fft4_kernel(PassArgs<T> a) {
   }
 }
 
+// The forward x pass fused with combine_kernel's work: a workgroup transforms
+// a run of lines of one grid in both interlaced copies and writes
+// (D1 + e^{i pi (nx+ny+nz)/N} D2)/2 / W(n), minus the box-mode mean term, with
+// the DC mode of dn_0^0 zeroed in box mode, straight into the spectra (the
+// arithmetic of combine_kernel on the same FP32 transform outputs), so the
+// copies' x-pass output never reaches HBM. The copies go through the same LDS
+// one after the other; each thread keeps its first-copy outputs in registers
+// (one step-C task per thread: lpw N2 <= the workgroup size). Lines: (grid,
+// n_y, n_z) with n_z consecutive in a workgroup; stored entry e of an axis
+// holds frequency e - R.
+template <typename T, int N1, int N2>
+__global__ void __launch_bounds__(kBlock) fft4_combine_kernel(PassArgs<T> a) {
+  typedef typename cplx<T>::type T2;
+  constexpr int N = N1 * N2;
+  constexpr int LS = N2 * (N1 + 1) + 1;
+  extern __shared__ char smem[];
+  const int R = a.out_off, P = a.out_cnt;
+  double* tab = (double*)smem;            // [3][P]: 1/W, cos and sin of pi n/N per axis entry
+  T2* lds = (T2*)(smem + ((size_t)3 * P * sizeof(double) + 15) / 16 * 16);   // [line][LS]
+  const int nbb = (a.dB + a.lpw - 1) / a.lpw;
+  const int64_t blk = blockIdx.x;
+  const int bb = (int)(blk % nbb);
+  const int64_t rest = blk / nbb;
+  const int ia = (int)(rest % a.dA);
+  const int g = (int)(rest / a.dA);
+  const int b0 = bb * a.lpw;
+  const int nl = min(a.lpw, a.dB - b0);
+  const int nc = a.cb_copies;
+  const int tid = threadIdx.x;
+  for (int i = tid; i < 3 * P; i += kBlock) tab[i] = a.cb_tab[i];   // read after the barriers below
+  const bool has_task = tid < nl * N2;
+  const int k2 = tid / nl, j = tid - (tid / nl) * nl;   // this thread's step-C task
+  T2 u[N1], u2[N1];
+  for (int c = 0; c < nc; ++c) {
+    if (c) __syncthreads();   // the first copy's step C has read the LDS
+    // ---- step A: N2-point transforms of the copy's lines ---------------------
+    const T2* inb = a.in + (int64_t)g * a.in_bs + (int64_t)c * a.cb_copy_bs + (int64_t)ia * a.in_sa;
+    for (int task = tid; task < nl * N1; task += kBlock) {
+      const int n1 = task / nl, jj = task - n1 * nl;
+      const T2* src = inb + (int64_t)(b0 + jj) * a.in_sb;
+      T2 v[N2];
+#pragma unroll
+      for (int n2 = 0; n2 < N2; ++n2) v[n2] = src[(int64_t)(n1 + N1 * n2) * a.in_se];
+      reg_fft<T, T2, N2>(v, a.dir);
+      T2* line = lds + jj * LS;
+#pragma unroll
+      for (int i = 0; i < N2; ++i) {
+        const int kk = bit_reverse<N2>(i);
+        T2 w = a.tw[(n1 * kk) % N];
+        if (a.dir > 0) w.y = -w.y;
+        T2 o;
+        o.x = v[i].x * w.x - v[i].y * w.y;
+        o.y = v[i].x * w.y + v[i].y * w.x;
+        line[kk * (N1 + 1) + n1] = o;
+      }
+    }
+    __syncthreads();
+    // ---- step C: N1-point transforms across n1 -----------------------------------
+    if (has_task) {
+      const T2* line = lds + j * LS + k2 * (N1 + 1);
+      if (c == 0) {
+#pragma unroll
+        for (int n1 = 0; n1 < N1; ++n1) u[n1] = line[n1];
+        reg_fft<T, T2, N1>(u, a.dir);
+      } else {
+#pragma unroll
+        for (int n1 = 0; n1 < N1; ++n1) u2[n1] = line[n1];
+        reg_fft<T, T2, N1>(u2, a.dir);
+      }
+    }
+  }
+  if (!has_task) return;
+  // ---- the combination ----------------------------------------------------------
+  const double* iw = tab;
+  const double* pc = tab + P;
+  const double* ps = tab + 2 * P;
+  const double mean = a.cb_yspec ? a.cb_scal->mean_cell : 0.0;
+  const int iy = ia, iz = b0 + j;
+  const double czz = pc[iz], szz = ps[iz], wz = iw[iz];
+  const double cy = pc[iy], sy = ps[iy], wy = iw[iy];
+#pragma unroll
+  for (int i = 0; i < N1; ++i) {
+    const int k = k2 + N2 * bit_reverse<N1>(i);
+    int ix = k + R;
+    if (ix >= N) ix -= N;
+    if (ix >= P) continue;
+    const int64_t o_at = (int64_t)ix * a.out_se + (int64_t)iy * a.out_sa + (int64_t)iz * a.out_sb;
+    double re = u[i].x, im = u[i].y;
+    if (nc == 2) {
+      const double cxy = pc[ix] * cy - ps[ix] * sy, sxy = pc[ix] * sy + ps[ix] * cy;
+      const double cc = cxy * czz - sxy * szz, sn = cxy * szz + sxy * czz;
+      re = 0.5 * (re + cc * (double)u2[i].x - sn * (double)u2[i].y);
+      im = 0.5 * (im + cc * (double)u2[i].y + sn * (double)u2[i].x);
+    }
+    const double inv_w = iw[ix] * wy * wz;
+    re *= inv_w;
+    im *= inv_w;
+    if (a.cb_yspec) {
+      const T2 y = a.cb_yspec[(int64_t)g * a.out_bs + o_at];
+      re -= mean * (double)y.x;
+      im -= mean * (double)y.y;
+    }
+    if (a.cb_box && g == 0 && ix == R && iy == R && iz == R) re = 0.0;
+    T2 o;
+    o.x = (T)re;
+    o.y = (T)im;
+    a.out[(int64_t)g * a.out_bs + o_at] = o;
+  }
+}
+
+template <typename T, int N1, int N2>
+int launch_fft4_combine(PassArgs<T>& a, hipStream_t s, int lpw_req) {
+  typedef typename cplx<T>::type T2;
+  constexpr int LS = N2 * (N1 + 1) + 1;
+  // lines per workgroup: one step-C task per thread (lpw N2 <= kBlock), at most
+  // 40 KiB of LDS by default, a tuned value within 64 KiB
+  const int64_t per_line = LS * (int64_t)sizeof(T2);
+  const int64_t tab_bytes = ((int64_t)3 * a.out_cnt * 8 + 15) / 16 * 16;
+  int lpw = kBlock / N2;
+  while (lpw > 1 && lpw * per_line > 40 * 1024) lpw /= 2;
+  if (lpw_req > 0) {
+    lpw = std::min(lpw_req, kBlock / N2);
+    while (lpw > 1 && lpw * per_line > 64 * 1024) lpw /= 2;
+  }
+  a.lpw = lpw;
+  const int64_t nbb = (a.dB + a.lpw - 1) / a.lpw;
+  const int64_t blocks = (int64_t)a.nbatch * a.dA * nbb;
+  if (blocks > 2147483647LL) return fail(TSB_E_UNSUPPORTED, "FFT pass too large");
+  hipLaunchKernelGGL((fft4_combine_kernel<T, N1, N2>), dim3((unsigned)blocks), dim3(kBlock),
+                     (size_t)(tab_bytes + lpw * per_line), s, a);
+  return TSB_OK;
+}
+
+template <typename T>
+int launch_combine_pass(Plan& P, int stage, PassArgs<T>& a, hipStream_t s) {
+  if (a.nbatch <= 0 || a.dA <= 0 || a.dB <= 0) return TSB_OK;
+  prof_begin(P, stage, s);
+  int rc = TSB_OK;
+  const int req = P.lpw_tune[stage];
+  switch (a.N) {
+    case 16: rc = launch_fft4_combine<T, 4, 4>(a, s, req); break;
+    case 32: rc = launch_fft4_combine<T, 4, 8>(a, s, req); break;
+    case 64: rc = launch_fft4_combine<T, 8, 8>(a, s, req); break;
+    case 128: rc = launch_fft4_combine<T, 8, 16>(a, s, req); break;
+    case 256: rc = launch_fft4_combine<T, 16, 16>(a, s, req); break;
+    case 512: rc = launch_fft4_combine<T, 16, 32>(a, s, req); break;
+    default: rc = launch_fft4_combine<T, 32, 32>(a, s, req); break;
+  }
+  prof_end(P, stage, s);
+  if (rc) return rc;
+  TSB_HIP(hipGetLastError());
+  return TSB_OK;
+}
+
 int pick_lpw(int N, int esz) {
   // two LDS line buffers of (N+1) complex each, at most 64 KiB
   int lpw = 16;
@@ -630,7 +793,10 @@ int forward_impl(Plan& P, hipStream_t s) {
     a.N = N; a.dir = -1; a.contiguous = 0;
     if ((rc = launch_pass<T>(P, kStFwdY, a, s))) return rc;
   }
-  // x (strided): [nbc][N][PG][PG] -> [nbc][PG][PG][PG]
+  // x (strided): [nbc][N][PG][PG] -> [nbc][PG][PG][PG], or for the
+  // register-FFT lengths the x pass and the combination in one kernel:
+  // [copies][ngrid][N][PG][PG] -> spectra [ngrid][PG][PG][PG]
+  const bool fused_x = combine_fusable(N);
   {
     PassArgs<T> a{};
     a.in = (const T2*)P.d_t2;
@@ -641,23 +807,40 @@ int forward_impl(Plan& P, hipStream_t s) {
     a.out_bs = (int64_t)PG * PG * PG; a.out_sa = PG; a.out_sb = 1; a.out_se = (int64_t)PG * PG;
     a.in_cnt = N; a.in_off = 0; a.out_cnt = PG; a.out_off = RG;
     a.N = N; a.dir = -1; a.contiguous = 0;
-    if ((rc = launch_pass<T>(P, kStFwdX, a, s))) return rc;
+    if (fused_x) {
+      a.nbatch = (int)P.grids.size();
+      a.out = (T2*)(P.wpass ? P.d_nspec : P.d_spec);
+      a.cb_copies = P.copies;
+      a.cb_copy_bs = (int64_t)P.grids.size() * a.in_bs;
+      a.cb_tab = (const double*)P.d_axis_tab;
+      a.cb_yspec = (!P.wpass && P.yspec_ready) ? (const T2*)P.d_yspec : nullptr;
+      a.cb_scal = P.wpass ? (const DevScalars*)P.d_scal_n : (const DevScalars*)P.d_scal;
+      a.cb_box = P.wpass ? 0 : P.box_mode;
+      if ((rc = launch_combine_pass<T>(P, kStFwdX, a, s))) return rc;
+    } else if ((rc = launch_pass<T>(P, kStFwdX, a, s))) {
+      return rc;
+    }
   }
   prof_begin(P, kStCombine, s);
   const int64_t row_pairs = ((int64_t)P.grids.size() * PG * PG + 1) / 2;   // two rows per workgroup
   if (P.wpass) {
     // the w^2-weighted N fields of the shot noise: a pure particle sum (no mean
     // term, DC kept), into their own spectra
-    hipLaunchKernelGGL(combine_kernel<T>, dim3((int)std::min<int64_t>(row_pairs, 8192)), dim3(kBlock), 0, s,
-                       (const T2*)P.d_t3, (T2*)P.d_nspec, (int)P.grids.size(), P.copies, RG, 0,
-                       (const double*)P.d_axis_tab, (const T2*)nullptr, (const DevScalars*)P.d_scal_n);
+    if (!fused_x) {
+      hipLaunchKernelGGL(combine_kernel<T>, dim3((int)std::min<int64_t>(row_pairs, 8192)), dim3(kBlock), 0, s,
+                         (const T2*)P.d_t3, (T2*)P.d_nspec, (int)P.grids.size(), P.copies, RG, 0,
+                         (const double*)P.d_axis_tab, (const T2*)nullptr, (const DevScalars*)P.d_scal_n);
+    }
     prof_end(P, kStCombine, s);
     TSB_HIP(hipGetLastError());
     return TSB_OK;
   }
-  hipLaunchKernelGGL(combine_kernel<T>, dim3((int)std::min<int64_t>(row_pairs, 8192)), dim3(kBlock), 0, s,
-                     (const T2*)P.d_t3, (T2*)P.d_spec, (int)P.grids.size(), P.copies, RG, P.box_mode, (const double*)P.d_axis_tab,
-                     P.yspec_ready ? (const T2*)P.d_yspec : (const T2*)nullptr, (const DevScalars*)P.d_scal);
+  if (!fused_x) {
+    hipLaunchKernelGGL(combine_kernel<T>, dim3((int)std::min<int64_t>(row_pairs, 8192)), dim3(kBlock), 0, s,
+                       (const T2*)P.d_t3, (T2*)P.d_spec, (int)P.grids.size(), P.copies, RG, P.box_mode,
+                       (const double*)P.d_axis_tab, P.yspec_ready ? (const T2*)P.d_yspec : (const T2*)nullptr,
+                       (const DevScalars*)P.d_scal);
+  }
   const int64_t pf3 = (int64_t)P.PF * P.PF * P.PF;
   hipLaunchKernelGGL(dcube_kernel<T>, dim3(grid_blocks(pf3)), dim3(kBlock), 0, s, (const T2*)P.d_spec,
                      (T2*)P.d_dcube, RG, P.RF);
@@ -885,6 +1068,10 @@ int separation_impl(Plan& P, hipStream_t s) {
 }
 
 }  // namespace
+
+bool combine_fusable(int N) {
+  return N == 16 || N == 32 || N == 64 || N == 128 || N == 256 || N == 512 || N == 1024;
+}
 
 int run_separation_kernels(Plan& P, hipStream_t s) {
   if (!P.d_kslot) return TSB_OK;

@@ -288,7 +288,10 @@ int run_unpack_grids(Plan& P, void* out, hipStream_t s);
 int run_fill_zero(void* p, int64_t bytes, hipStream_t s);        // kernel fill, bytes % 8 == 0
 int run_sbar(Plan& P, const tsb_catalog* data, const tsb_catalog* rand, hipStream_t s);   // Sbar per channel
 int run_shot_kspace(Plan& P, hipStream_t s);
-int run_separation_shot(Plan& P, hipStream_t s);   // the 3PCF's i = j != k term (shot.hip)   // H spectra and the shell sums (shot.hip)
+int run_separation_shot(Plan& P, hipStream_t s);   // the 3PCF's i = j != k term (shot.hip)
+// Whether the forward x pass of an N grid runs fused with the combination of
+// the interlaced copies (register-FFT lengths; else a pass buffer and combine_kernel).
+bool combine_fusable(int N);   // H spectra and the shell sums (shot.hip)
 int shot_plan(Plan& P);                        // host tables of the shot noise (shot.hip)
 void shot_finish(Plan& P, const double* sbar, const double* sums, const double* Braw, const double* Sij,
                  double I, double* B_out);      // host: S and B - S (shot.hip)
