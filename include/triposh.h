@@ -323,16 +323,17 @@ int tsb_plan_set_profiling(tsb_plan* plan, int32_t stages);
  *   - the persistent grid of the assignment tile kernel (0.5 to 2 times its
  *     occupancy-sized default);
  *   - for the one-pass FP32 reduction, how its second phase is split: one task
- *     per (row, shell, k2), a row being one Q group or one right factor, or
- *     one task per (shell, k2) covering every row;
+ *     per (row, shell, k2), a row being one Q group or one right factor, one
+ *     task per (shell, k2) covering every row, or every (slot, k2) column
+ *     transformed once in LDS and then one task per (row, shell, k2);
  *   - for the unfused FP32 matrix-core reduction, its workgroup size: two of
  *     512 threads per CU (when their staged rows fit the LDS) or one of 1024.
  * These change how work is split, not the arithmetic: results stay bitwise
  * the same. The choices stay with the plan (the captured graph is rebuilt).
  * choice (may be NULL) receives 18 values: lines per workgroup per stage
  * (index as in tsb_plan_stage_times; 0 = the LDS rule), then the tile-kernel
- * workgroups, then the reduction split (1 row tasks, 0 shell tasks, -1 when
- * the plan does not use the one-pass kernel), then the unfused reduction's
+ * workgroups, then the reduction split (1 row tasks, 0 shell tasks, 2 columns
+ * then rows, -1 when the plan does not use the one-pass kernel), then the unfused reduction's
  * workgroup size (512 or 1024; -1 when the plan does not use that kernel). Clears the stage-time
  * accumulators and keeps the profiling setting. Errors as tsb_measure. */
 int tsb_plan_autotune(tsb_plan* plan, const tsb_catalog* data, const tsb_catalog* randoms, void* stream,
@@ -344,7 +345,7 @@ int tsb_plan_autotune(tsb_plan* plan, const tsb_catalog* data, const tsb_catalog
  * values in tsb_plan_autotune's layout: lines per workgroup per stage (0, 8,
  * 16, 32 or 64; ignored by passes whose length is not a power of two), the
  * tile-kernel workgroups (0: the occupancy default), the reduction split (1,
- * 0, or -1 to leave it), the unfused reduction's workgroup size (512, 1024, or
+ * 0, 2, or -1 to leave it), the unfused reduction's workgroup size (512, 1024, or
  * -1 to leave it). Results stay bitwise the same. Errors: TSB_E_ARG. */
 int tsb_plan_set_schedule(tsb_plan* plan, const int32_t* choice);
 int tsb_plan_stage_times(tsb_plan* plan, int32_t n, double* ms, int64_t* calls, int32_t reset);

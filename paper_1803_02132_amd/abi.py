@@ -269,7 +269,8 @@ def tsb_plan_set_profiling(h, stages=True):
 def tsb_plan_autotune(h, data, randoms, stream, reps=3):
     """Tune the plan's launch schedule; returns {stage: lines per workgroup
     (0 = LDS rule)} for the tuned FFT stages, 'tile_wgs', 'reduce_row_tasks'
-    (1, 0, or -1 when the one-pass reduction is not used) and 'reduce_block'
+    (1 row tasks, 0 shell tasks, 2 columns then rows, or -1 when the one-pass
+    reduction is not used) and 'reduce_block'
     (512, 1024, or -1 when the unfused matrix-core reduction is not used)."""
     choice = (ctypes.c_int32 * 18)()
     _check(_lib.tsb_plan_autotune(h, data, randoms, ctypes.c_void_p(stream), int(reps), choice))

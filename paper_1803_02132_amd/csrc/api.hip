@@ -914,7 +914,7 @@ int tsb_plan_set_schedule(tsb_plan* plan, const int32_t* choice) {
   }
   if (choice[kNumStages] < 0) return fail(TSB_E_ARG, "tile-kernel workgroups must be >= 0 (0: the occupancy default)");
   const int rt = choice[kNumStages + 1];
-  if (rt < -1 || rt > 1) return fail(TSB_E_ARG, "reduction split must be -1, 0 or 1");
+  if (rt < -1 || rt > 2) return fail(TSB_E_ARG, "reduction split must be -1, 0, 1 or 2");
   const int rb = choice[kNumStages + 2];
   if (rb != -1 && rb != 512 && rb != 1024) return fail(TSB_E_ARG, "reduction workgroup must be -1, 512 or 1024");
   if (rb == 512 && !P.fused && P.red_mfma == 8 && !reduce_pair_fits(P))
@@ -1035,11 +1035,12 @@ int tsb_plan_autotune(tsb_plan* plan, const tsb_catalog* data, const tsb_catalog
     P.tile_wgs = best_wgs;
     ++P.tune_gen;
   }
-  // second phase of the one-pass reduction: (row, shell, k2) tasks or (shell, k2) tasks
+  // second phase of the one-pass reduction: (row, shell, k2) tasks, (shell, k2)
+  // tasks, or every column transformed once and then the rows
   if (!rc && P.fused && P.fused_wide) {
     double best = 0.0;
     int best_rt = 1;
-    for (int c : {1, 0}) {
+    for (int c : {1, 0, 2}) {
       P.fused_rt = c;
       ++P.tune_gen;
       double ms = 0.0;

@@ -279,6 +279,17 @@ __device__ inline void put_row(float* frow, const float2 (&row)[N1], int part) {
   for (int i = 0; i < N1; ++i) frow[N2 * bit_reverse<N1>(i)] = part ? row[i].y : row[i].x;
 }
 
+// The same from a row already transformed in LDS (entry i holds cell c_i).
+template <int N1, int N2>
+__device__ inline void add_term_lds(float (&sq)[N1], const float2* row, int part, float cf, const float* gr) {
+#pragma unroll
+  for (int i = 0; i < N1; ++i) {
+    const float2 v = row[i];
+    const float f = part ? v.y : v.x;
+    sq[i] += cf * f * gr[N2 * bit_reverse<N1>(i)];
+  }
+}
+
 template <int N1, int N2>
 __device__ inline void put_row(float* frow, const float (&row)[N1]) {
 #pragma unroll
@@ -296,7 +307,11 @@ constexpr int kWKinds = 4;     // slot kinds per shell held in registers at once
 // still fill the workgroup; each task transforms the kinds its row needs.
 // The terms of a row are added in the same order as without RT (term order
 // with KR, kind by kind without), so RT changes only the split of the work.
-template <int N1, int N2, int NQ, bool KR, bool GR, bool RT>
+// KT: the second phase first transforms every (slot, k2) column once, in
+// place in LDS, then forms the rows from the transformed columns (no
+// transform repeated per row; the same term order as KR for at most kWKinds
+// kinds, kind by kind beyond, so KT too changes only the split of the work).
+template <int N1, int N2, int NQ, bool KR, bool GR, bool RT, bool KT = false>
 __global__ void __launch_bounds__(kWBlock) fz_reduce_wide_kernel(FusedArgs<float> a) {
   typedef float2 T2;
   constexpr int M = N1 * N2;
@@ -388,7 +403,55 @@ __global__ void __launch_bounds__(kWBlock) fz_reduce_wide_kernel(FusedArgs<float
       __syncthreads();
       if (g + 1 < ngrp) prefetch(line, g + 1);
       else if (line + gridDim.x < lines) prefetch(line + gridDim.x, 0);
-      if constexpr (RT) {
+      if constexpr (KT) {
+      // second-level transforms of every (slot, k2) column, in place
+      for (int task = tid; task < nbg * nk * N2; task += kWBlock) {
+        const int sk = task / N2, k2 = task - sk * N2;
+        T2* st = stage + (size_t)sk * LS + k2 * (N1 + 1);
+        T2 u[N1];
+#pragma unroll
+        for (int j = 0; j < N1; ++j) u[j] = st[j];
+        reg_fft<float, T2, N1>(u, 1);
+#pragma unroll
+        for (int j = 0; j < N1; ++j) st[j] = u[j];
+      }
+      __syncthreads();
+      const int per_row = nbg * N2, nrow = nq + a.nf2;
+      const bool korder = nk <= kWKinds;
+      for (int task = tid; task < nrow * per_row; task += kWBlock) {
+        const int r = task / per_row, rest = task - r * per_row;
+        const int bl = rest / N2, k2 = rest - bl * N2, b = b0 + bl;
+        const T2* col = stage + (size_t)(bl * nk) * LS + k2 * (N1 + 1);   // kind k at col + k LS
+        if (r < nq) {
+          float sq[N1];
+#pragma unroll
+          for (int i = 0; i < N1; ++i) sq[i] = 0.f;
+          if (korder) {
+            for (int t = a.tb.q_t0[r]; t < a.tb.q_t1[r]; ++t)
+              add_term_lds<N1, N2>(sq, col + (size_t)a.tb.f1kind[t] * LS, a.tb.f1part[t], (float)a.tb.coef[t],
+                                   Gv + (size_t)a.tb.g[t] * CP + k2);
+          } else {
+            const unsigned kmask = a.tb.q_kmask[r];
+            for (int k = 0; k < nk; ++k) {
+              if (!((kmask >> k) & 1u)) continue;
+              for (int t = a.tb.q_t0[r]; t < a.tb.q_t1[r]; ++t) {
+                if (a.tb.f1kind[t] != k) continue;
+                add_term_lds<N1, N2>(sq, col + (size_t)k * LS, a.tb.f1part[t], (float)a.tb.coef[t],
+                                     Gv + (size_t)a.tb.g[t] * CP + k2);
+              }
+            }
+          }
+          put_row<N1, N2>(Q + ((size_t)r * nb + b) * CP + k2, sq);
+        } else {
+          const int rr = r - nq;
+          const T2* src = col + (size_t)a.tb.f2_kind[rr] * LS;
+          T2 u[N1];
+#pragma unroll
+          for (int j = 0; j < N1; ++j) u[j] = src[j];
+          put_row<N1, N2>(F2 + ((size_t)rr * nb + b) * CP + k2, u, a.tb.f2_part[rr]);
+        }
+      }
+      } else if constexpr (RT) {
       const int per_row = nbg * N2, nrow = nq + a.nf2;
       for (int task = tid; task < nrow * per_row; task += kWBlock) {
         const int r = task / per_row, rest = task - r * per_row;
@@ -685,7 +748,11 @@ int fused_launch(Plan& P, hipStream_t s) {
       const size_t wl = wide_lds_bytes(P, P.fused_bpg);
       const bool grouped = P.fused_bpg < P.nb;
       const dim3 grid(P.red_wg), block(kWBlock);
-      if (P.fused_rt && a.nkinds <= kWKinds && !grouped)
+      if (P.fused_rt == 2 && !grouped)
+        hipLaunchKernelGGL((fz_reduce_wide_kernel<N1, N2, 1, false, false, false, true>), grid, block, wl, s, a);
+      else if (P.fused_rt == 2)
+        hipLaunchKernelGGL((fz_reduce_wide_kernel<N1, N2, 1, false, true, false, true>), grid, block, wl, s, a);
+      else if (P.fused_rt && a.nkinds <= kWKinds && !grouped)
         hipLaunchKernelGGL((fz_reduce_wide_kernel<N1, N2, 1, true, false, true>), grid, block, wl, s, a);
       else if (P.fused_rt && a.nkinds <= kWKinds)
         hipLaunchKernelGGL((fz_reduce_wide_kernel<N1, N2, 1, true, true, true>), grid, block, wl, s, a);

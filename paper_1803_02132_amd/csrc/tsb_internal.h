@@ -217,7 +217,8 @@ struct Plan {
   bool fused = false;
   bool fused_wide = false;      // one-pass FP32 kernel (all shells of a line at once)
   int fused_bpg = 1;            // shells per group inside the fused kernel
-  int fused_rt = 1;             // one-pass kernel: second phase as (row, shell, k2) tasks (autotuned)
+  int fused_rt = 1;             // one-pass kernel's second phase: 1 (row, shell, k2) tasks, 0 (shell, k2)
+                                // tasks, 2 columns transformed once, then the rows (autotuned)
   int nf2 = 0;                  // F components used as right factors
   std::vector<int> f2idx;       // per F component: its right-factor row or -1
   int* d_f2idx = nullptr;

@@ -180,19 +180,22 @@ def test_autotune_keeps_results_bitwise():
     ([(0, 0, 0), (1, 1, 0), (2, 0, 2), (1, 1, 2)], 16, 0.9),          # kind by kind, shell groups
 ])
 def test_reduction_split_and_schedule_reuse_are_bitwise(mults, n_bins, dk_kf):
-    # the one-pass reduction's second phase as row tasks or shell tasks, and a
-    # schedule applied from another plan: the same arithmetic, bitwise
+    # the one-pass reduction's second phase as row tasks, shell tasks or
+    # columns transformed once, and a schedule applied from another plan: the
+    # same arithmetic, bitwise
     import math
     req = box_request(n=64, n_bins=n_bins, dk=dk_kf * 2.0 * math.pi / 1000.0, multipoles=mults)
     dev = tsb.catalog_to_device(_cat(64, 43, 40000))
     plan = tsb.Plan(**req)
     assert plan.info.fused == 2
     out = {}
-    for rt in (0, 1):
+    for rt in (0, 1, 2):
         plan.set_schedule({"reduce_row_tasks": rt})
         out[rt] = plan.measure(dev)["B"]
-    _say("split", mults, n_bins, "row tasks vs shell tasks bitwise", _same(out[0], out[1]))
+    _say("split", mults, n_bins, "row tasks vs shell tasks vs columns bitwise", _same(out[0], out[1]),
+         _same(out[2], out[1]))
     assert _same(out[0], out[1])
+    assert _same(out[2], out[1])
     tuned = tsb.Plan(**req)
     choice = tuned.autotune(dev, reps=1)
     other = tsb.Plan(**req)
