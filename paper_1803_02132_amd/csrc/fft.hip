@@ -60,6 +60,13 @@ struct PassArgs {
   int sp_div;
   int64_t sp_c;
   int sp_a, sp_b, sp_e;
+  // Output-side band limit of the forward passes: an output entry e of line
+  // (a, b) whose frequencies (a - so_a, b - so_b, e - so_e; -1: not counted)
+  // give |n|^2 above so_r2 is never read (the inverse chains and the
+  // combination stop at the band limit) and is not written (so_on = 0: off).
+  int so_on;
+  int64_t so_r2;
+  int so_a, so_b, so_e;
   // forward x pass with the combination (fft4_combine_kernel): copies of each
   // grid, the input stride between them, the per-axis table of combine_kernel,
   // the box-mode mean term (or null), the scalars holding its mean, DC zeroing
@@ -94,6 +101,17 @@ __device__ inline bool sparse_lines(const PassArgs<T>& a, int batch, int ia, int
     *hi = min(*hi, a.sp_b + h + 1);
   }
   return *lo < *hi;
+}
+
+// Whether output entry e of line (ia, b) lies beyond the output band limit.
+template <typename T>
+__device__ inline bool beyond_out(const PassArgs<T>& a, int ia, int b, int e) {
+  if (!a.so_on) return false;
+  int64_t f = 0;
+  if (a.so_a >= 0) f += (int64_t)(ia - a.so_a) * (ia - a.so_a);
+  if (a.so_b >= 0) f += (int64_t)(b - a.so_b) * (b - a.so_b);
+  if (a.so_e >= 0) f += (int64_t)(e - a.so_e) * (e - a.so_e);
+  return f > a.so_r2;
 }
 
 // Whether stored entry e of line b is a zero of the sparsity rule.
@@ -367,7 +385,7 @@ __global__ void __launch_bounds__(kBlock) fft_pass_kernel(PassArgs<T> a) {
     }
     int pos = e - a.out_off;
     if (pos < 0) pos += N;
-    outb[(int64_t)(b0 + j) * a.out_sb + (int64_t)e * a.out_se] = src[j * NP + pos];
+    if (!beyond_out(a, ia, b0 + j, e)) outb[(int64_t)(b0 + j) * a.out_sb + (int64_t)e * a.out_se] = src[j * NP + pos];
   }
 }
 
@@ -535,7 +553,8 @@ __global__ void __launch_bounds__(kBlock) fft4_kernel(PassArgs<T> a) {
       const int k = k2 + N2 * bit_reverse<N1>(i);   // output position
       int e = k + a.out_off;                          // stored entry
       if (e >= N) e -= N;
-      if (e < a.out_cnt) outb[(int64_t)(b0 + j) * a.out_sb + (int64_t)e * a.out_se] = u[i];
+      if (e < a.out_cnt && !beyond_out(a, ia, b0 + j, e))
+        outb[(int64_t)(b0 + j) * a.out_sb + (int64_t)e * a.out_se] = u[i];
     }
   }
 }
@@ -565,8 +584,19 @@ __global__ void __launch_bounds__(kBlock) fft4_combine_kernel(PassArgs<T> a) {
   const int64_t rest = blk / nbb;
   const int ia = (int)(rest % a.dA);
   const int g = (int)(rest / a.dA);
-  const int b0 = bb * a.lpw;
-  const int nl = min(a.lpw, a.dB - b0);
+  int b0 = bb * a.lpw;
+  int nl = min(a.lpw, a.dB - b0);
+  if (a.so_on) {   // lines beyond the band limit are never read: skip them (uniform)
+    const int64_t rem = a.so_r2 - (int64_t)(ia - a.so_a) * (ia - a.so_a);
+    if (rem < 0) return;
+    int h = (int)sqrt((double)rem);
+    while ((int64_t)h * h > rem) --h;
+    while ((int64_t)(h + 1) * (h + 1) <= rem) ++h;
+    const int lo = max(b0, a.so_b - h), hi = min(b0 + nl, a.so_b + h + 1);
+    if (lo >= hi) return;
+    b0 = lo;
+    nl = hi - lo;
+  }
   const int nc = a.cb_copies;
   const int tid = threadIdx.x;
   for (int i = tid; i < 3 * P; i += kBlock) tab[i] = a.cb_tab[i];   // read after the barriers below
@@ -625,7 +655,7 @@ __global__ void __launch_bounds__(kBlock) fft4_combine_kernel(PassArgs<T> a) {
     const int k = k2 + N2 * bit_reverse<N1>(i);
     int ix = k + R;
     if (ix >= N) ix -= N;
-    if (ix >= P) continue;
+    if (ix >= P || beyond_out(a, ia, iz, ix)) continue;
     const int64_t o_at = (int64_t)ix * a.out_se + (int64_t)iy * a.out_sa + (int64_t)iz * a.out_sb;
     double re = u[i].x, im = u[i].y;
     if (nc == 2) {
@@ -767,6 +797,18 @@ int forward_impl(Plan& P, hipStream_t s) {
   const int nbc = P.copies * (int)P.grids.size();
   const int64_t N2 = (int64_t)N * N, N3 = N2 * N;
   int rc;
+  // Band limit of the spectra: with the reduced-grid rule nothing beyond
+  // |n|^2 = n2maxG is read (the G chain masks it, the F cube and the shells
+  // lie inside), so the y pass does not write the (n_y, n_z) entries beyond it
+  // and the fused x pass neither transforms those lines nor writes beyond it.
+  auto band = [&](PassArgs<T>& a, int oa, int ob, int oe) {
+    if (P.n2maxG < 0) return;
+    a.so_on = 1;
+    a.so_r2 = P.n2maxG;
+    a.so_a = oa;
+    a.so_b = ob;
+    a.so_e = oe;
+  };
   // z (contiguous): [nbc][N][N][N] -> [nbc][N][N][PG]
   {
     PassArgs<T> a{};
@@ -791,6 +833,7 @@ int forward_impl(Plan& P, hipStream_t s) {
     a.out_bs = (int64_t)N * PG * PGs; a.out_sa = (int64_t)PG * PGs; a.out_sb = 1; a.out_se = PGs;
     a.in_cnt = N; a.in_off = 0; a.out_cnt = PG; a.out_off = RG;
     a.N = N; a.dir = -1; a.contiguous = 0;
+    if (combine_fusable(N)) band(a, -1, RG, RG);   // (n_y, n_z) beyond the band: the fused x pass skips the line
     if ((rc = launch_pass<T>(P, kStFwdY, a, s))) return rc;
   }
   // x (strided): [nbc][N][PG][PG] -> [nbc][PG][PG][PG], or for the
@@ -808,6 +851,7 @@ int forward_impl(Plan& P, hipStream_t s) {
     a.in_cnt = N; a.in_off = 0; a.out_cnt = PG; a.out_off = RG;
     a.N = N; a.dir = -1; a.contiguous = 0;
     if (fused_x) {
+      band(a, RG, RG, RG);
       a.nbatch = (int)P.grids.size();
       a.out = (T2*)(P.wpass ? P.d_nspec : P.d_spec);
       a.cb_copies = P.copies;
