@@ -504,8 +504,12 @@ int plan_build(Plan& P) {
       const bool wide = P.qgroups.size() <= 16 && P.terms.size() <= 64;
       if (wide) P.red_mfma = 8;
       const int64_t cap = wide ? 150 * 1024 : 96 * 1024;
+      // the 1024-thread kernel stages whole complex rows of every F slot and G grid
+      const int64_t cell = wide ? 2 * ((int64_t)P.nb * (int64_t)P.fkinds.size() + (int64_t)P.grids.size()) +
+                                      (int64_t)P.qgroups.size() * P.nb
+                                : per_cell;
       int Cm = 64;
-      while (Cm > 8 && per_cell * (Cm + 1) * esz > cap) Cm /= 2;
+      while (Cm > 8 && cell * (Cm + 1) * esz > cap) Cm /= 2;
       if (Cm > P.red_chunk) {
         P.red_chunk = Cm;
         P.red_wg = (int)std::min<int64_t>((int64_t)P.M * P.M * P.M / Cm, 1024);

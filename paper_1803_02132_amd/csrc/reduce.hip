@@ -215,40 +215,45 @@ __global__ void __launch_bounds__(kBlock) reduce_mfma_kernel(RedArgs<float> a) {
 // The same reduction for FP32 plans with at most 32 shells, 16 Q groups and 64
 // terms, in workgroups of RB = 1024 threads (four wavefronts per SIMD with one
 // workgroup per CU), or of 512 for at most 8 Q groups when two workgroups'
-// staged rows fit the LDS of a CU (two interleaved chunk pipelines): each
-// thread issues its share of a chunk's field loads
-// before it stores any of them, the Q rows are formed one group at a time with
-// the group's terms in the kernel arguments (uniform loops, scalar loads), and
-// one wavefront per Q group runs its 32 x 32 (b1, b2) tile on the matrix cores.
-// The arithmetic is that of reduce_mfma_kernel: Q in FP64 rounded to FP32, the
-// products of a chunk summed in FP32, chunks in FP64.
-constexpr int kRWLoads = 16;      // field loads per thread and chunk held in registers
+// staged rows fit the LDS of a CU (two interleaved chunk pipelines). The chunk
+// length C is a template constant, so that every cell and slot index is a
+// shift or a mask: each thread issues its share of a chunk's field loads
+// before it stores any of them, as whole complex values into [slot][C] rows
+// (F slots, then G grids, in their order in HBM); the Q rows are formed one
+// group at a time from the (slot kind, part) and (grid, part) of each term in
+// the kernel arguments (uniform loops, scalar loads), and one wavefront per Q
+// group runs its 32 x 32 (b1, b2) tile on the matrix cores, reading the right
+// factor's part from the staged rows. The arithmetic is that of
+// reduce_mfma_kernel: Q in FP64 rounded to FP32, the products of a chunk
+// summed in FP32, chunks in FP64.
+constexpr int kRWLoads = 8;       // field loads per thread and chunk held in registers
 constexpr int kRWTerms = 64, kRWQ = 16;
 
 struct RedWideTables {
   double coef[kRWTerms];
-  int f1[kRWTerms], g[kRWTerms];
-  int q_t0[kRWQ], q_t1[kRWQ], q_f2[kRWQ];
+  int f1k[kRWTerms], f1p[kRWTerms], gk[kRWTerms], gp[kRWTerms];   // slot kind / grid and part of each term
+  int q_t0[kRWQ], q_t1[kRWQ], q_f2k[kRWQ], q_f2p[kRWQ];           // terms and right factor of each Q group
 };
 
-template <int kRWBlock, int kUnits>   // kUnits: Q groups per wavefront, at most
-__global__ void __launch_bounds__(kRWBlock, 1024 / kRWBlock) reduce_mfma_wide_kernel(RedArgs<float> a, RedWideTables tb) {
+template <int kRWBlock, int kUnits, int kC>   // kUnits: Q groups per wavefront; kC: cells per chunk
+__global__ void __launch_bounds__(kRWBlock, 4) reduce_mfma_wide_kernel(RedArgs<float> a, RedWideTables tb) {
+  static_assert((kC & (kC - 1)) == 0 && kC >= 8 && kC <= 64, "chunk: a power of two in [8, 64]");
+  constexpr int LC = kC == 8 ? 3 : (kC == 16 ? 4 : (kC == 32 ? 5 : 6));
+  constexpr int CP = kC + 1;                     // row pitch (complex rows: odd in 8-byte units)
   extern __shared__ char smem[];
-  const int C = a.chunk;
-  const int CP = C + 1;
-  float* Fv = (float*)smem;                      // [nb][nfc][CP]
-  float* Gv = Fv + (size_t)a.nb * a.nfc * CP;    // [ngc][CP]
-  float* Qv = Gv + (size_t)a.ngc * CP;           // [nq][nb][CP]
+  const int nslot = a.nb * a.nkinds;
+  const int nrow = nslot + a.ngrid;              // staged complex rows: F slots, then G grids
+  float2* Sv = (float2*)smem;                    // [nrow][CP]
+  float* Qv = (float*)(Sv + (size_t)nrow * CP);  // [nq][nb][CP]
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   double acc[kUnits][16];
 #pragma unroll
   for (int u = 0; u < kUnits; ++u)
 #pragma unroll
     for (int r = 0; r < 16; ++r) acc[u][r] = 0.0;
-  const int nslot = a.nb * a.nkinds;
-  const int nload = nslot * C + a.ngrid * C;     // complex elements staged per chunk
+  const int nload = nrow << LC;                  // complex elements staged per chunk
   for (int64_t ch = blockIdx.x; ch < a.nchunks; ch += gridDim.x) {
-    const int64_t c0 = ch * C;
+    const float2* src = a.fields + (ch << LC);
     // every load of this thread first, then the stores
     for (int base = 0; base < nload; base += kRWLoads * kRWBlock) {
       float2 v[kRWLoads];
@@ -256,38 +261,25 @@ __global__ void __launch_bounds__(kRWBlock, 1024 / kRWBlock) reduce_mfma_wide_ke
       for (int j = 0; j < kRWLoads; ++j) {
         const int idx = base + tid + j * kRWBlock;
         v[j] = make_float2(0.f, 0.f);
-        if (idx < nload) {
-          const int slot = idx / C, c = idx - slot * C;
-          v[j] = a.fields[(int64_t)slot * a.M3 + c0 + c];
-        }
+        if (idx < nload) v[j] = src[(int64_t)(idx >> LC) * a.M3 + (idx & (kC - 1))];
       }
 #pragma unroll
       for (int j = 0; j < kRWLoads; ++j) {
         const int idx = base + tid + j * kRWBlock;
-        if (idx >= nload) break;
-        const int slot = idx / C, c = idx - slot * C;
-        if (slot < nslot) {
-          const int b = slot / a.nkinds, k = slot - b * a.nkinds;
-          const int fr = a.kre[k], fi = a.kim[k];
-          if (fr >= 0) Fv[((size_t)b * a.nfc + fr) * CP + c] = v[j].x;
-          if (fi >= 0) Fv[((size_t)b * a.nfc + fi) * CP + c] = v[j].y;
-        } else {
-          const int g = slot - nslot;
-          const int fr = a.gre[g], fi = a.gim[g];
-          if (fr >= 0) Gv[(size_t)fr * CP + c] = v[j].x;
-          if (fi >= 0) Gv[(size_t)fi * CP + c] = v[j].y;
-        }
+        if (idx < nload) Sv[(idx >> LC) * CP + (idx & (kC - 1))] = v[j];
       }
     }
     __syncthreads();
     // Q_q(x; b1), one group at a time: its terms are uniform across the workgroup
     for (int q = 0; q < a.nq; ++q) {
       const int t0 = tb.q_t0[q], t1 = tb.q_t1[q];
-      for (int idx = tid; idx < a.nb * C; idx += kRWBlock) {
-        const int b1 = idx / C, c = idx - b1 * C;
+      for (int idx = tid; idx < (a.nb << LC); idx += kRWBlock) {
+        const int b1 = idx >> LC, c = idx & (kC - 1);
+        const float* frow = (const float*)(Sv + (size_t)b1 * a.nkinds * CP + c);
+        const float* grow = (const float*)(Sv + (size_t)nslot * CP + c);
         double s = 0.0;
         for (int t = t0; t < t1; ++t)
-          s += tb.coef[t] * (double)Fv[((size_t)b1 * a.nfc + tb.f1[t]) * CP + c] * (double)Gv[(size_t)tb.g[t] * CP + c];
+          s += tb.coef[t] * (double)frow[2 * tb.f1k[t] * CP + tb.f1p[t]] * (double)grow[2 * tb.gk[t] * CP + tb.gp[t]];
         Qv[((size_t)q * a.nb + b1) * CP + c] = (float)s;
       }
     }
@@ -299,14 +291,14 @@ __global__ void __launch_bounds__(kRWBlock, 1024 / kRWBlock) reduce_mfma_wide_ke
       const int b = lane & 31, kh = lane >> 5;
       const bool live = b < a.nb;
       const float* qr = Qv + ((size_t)q * a.nb + (live ? b : 0)) * CP + kh;
-      const float* fr = Fv + ((size_t)(live ? b : 0) * a.nfc + tb.q_f2[q]) * CP + kh;
+      const float* fr = (const float*)(Sv + ((size_t)(live ? b : 0) * a.nkinds + tb.q_f2k[q]) * CP + kh) + tb.q_f2p[q];
       floatx16 c = {};
-      for (int kk = 0; kk < C; kk += 8) {
+      for (int kk = 0; kk < kC; kk += 8) {
         float av[4], bv[4];
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
           av[j] = live ? qr[kk + 2 * j] : 0.f;
-          bv[j] = live ? fr[kk + 2 * j] : 0.f;
+          bv[j] = live ? fr[2 * (kk + 2 * j)] : 0.f;
         }
 #pragma unroll
         for (int j = 0; j < 4; ++j) c = __builtin_amdgcn_mfma_f32_32x32x2f32(av[j], bv[j], c, 0, 0, 0);
@@ -393,18 +385,36 @@ int reduce_impl(Plan& P, hipStream_t s) {
         RedWideTables tb{};
         for (size_t t = 0; t < P.terms.size(); ++t) {
           tb.coef[t] = P.terms[t].coef;
-          tb.f1[t] = P.terms[t].f1;
-          tb.g[t] = P.terms[t].g;
+          tb.f1k[t] = P.fcomp[P.terms[t].f1].slot;
+          tb.f1p[t] = P.fcomp[P.terms[t].f1].part;
+          tb.gk[t] = P.gcomp[P.terms[t].g].slot;
+          tb.gp[t] = P.gcomp[P.terms[t].g].part;
         }
         for (size_t q = 0; q < P.qgroups.size(); ++q) {
           tb.q_t0[q] = P.qgroups[q].t0;
           tb.q_t1[q] = P.qgroups[q].t1;
-          tb.q_f2[q] = P.qgroups[q].f2;
+          tb.q_f2k[q] = P.fcomp[P.qgroups[q].f2].slot;
+          tb.q_f2p[q] = P.fcomp[P.qgroups[q].f2].part;
         }
-        if (P.red_block == 512 && a.nq <= 8)
-          hipLaunchKernelGGL((reduce_mfma_wide_kernel<512, 1>), dim3(P.red_wg), dim3(512), lds_m, s, a, tb);
-        else
-          hipLaunchKernelGGL((reduce_mfma_wide_kernel<1024, 1>), dim3(P.red_wg), dim3(1024), lds_m, s, a, tb);
+        const size_t lds_w = std::max<size_t>((size_t)reduce_lds_bytes(P), (size_t)a.nq * 32 * 32 * sizeof(double));
+        const bool pair = P.red_block == 512 && a.nq <= 8;
+        const dim3 grid(P.red_wg), block(pair ? 512 : 1024);
+        switch (P.red_chunk) {
+#define TSB_RW(C)                                                                              \
+  case C:                                                                                      \
+    if (pair)                                                                                  \
+      hipLaunchKernelGGL((reduce_mfma_wide_kernel<512, 1, C>), grid, block, lds_w, s, a, tb);  \
+    else                                                                                       \
+      hipLaunchKernelGGL((reduce_mfma_wide_kernel<1024, 1, C>), grid, block, lds_w, s, a, tb); \
+    break;
+          TSB_RW(8)
+          TSB_RW(16)
+          TSB_RW(32)
+          TSB_RW(64)
+#undef TSB_RW
+          default:
+            return fail(TSB_E_UNSUPPORTED, "matrix-core reduction: chunk length not 8, 16, 32 or 64");
+        }
         prof_end(P, kStReduce, s);
         TSB_HIP(hipGetLastError());
         return run_reduce_final(P, s);
@@ -434,6 +444,9 @@ int reduce_impl(Plan& P, hipStream_t s) {
 
 int64_t reduce_lds_bytes(const Plan& P) {
   const int64_t esz = P.precision == TSB_FP64 ? 8 : 4;
+  if (P.red_mfma == 8)   // complex rows of every F slot and G grid, then the Q rows
+    return 4 * (P.red_chunk + 1) * (2 * ((int64_t)P.nb * (int64_t)P.fkinds.size() + (int64_t)P.grids.size()) +
+                                    (int64_t)P.qgroups.size() * P.nb);
   return esz * (P.red_chunk + 1) *
          ((int64_t)P.nb * (int64_t)P.fcomp.size() + (int64_t)P.gcomp.size() + (int64_t)P.qgroups.size() * P.nb);
 }
