@@ -150,7 +150,10 @@ def load_traffic(workload, geometry, stage):
 COPY_PROBE_BYTES = 512 << 20
 # stage -> kernels whose dispatches make up one launch of the stage
 STAGE_KERNELS = {"assign": ("tile_parts_kernel", "assign_tile_kernel", "heavy_final_kernel"),
-                 "reduce": ("fz_reduce_wide_kernel", "fz_reduce_kernel", "reduce_kernel", "reduce_mfma_kernel")}
+                 "reduce": ("fz_reduce_wide_kernel", "fz_reduce_kernel", "reduce_kernel", "reduce_mfma_kernel",
+                            "reduce_mfma_wide_kernel")}
+# kernels of the FFT passes (the fused forward x pass with the combination included)
+FFT_KERNELS = ("fft4_kernel", "fft4_combine_kernel", "fft_pass_kernel")
 # order of the FFT-pass dispatches inside one measurement (fused plan)
 FFT_ORDER = ["fwd_z", "fwd_y", "fwd_x", "invG_x", "invG_y", "invG_z", "invF_x", "invF_y"]
 
@@ -202,7 +205,7 @@ def ingest_pmc(fetch_csv, write_csv, command, workload="box256"):
         n_meas = len(starts)
         for j, s0 in enumerate(starts):
             s1 = starts[j + 1] if j + 1 < len(starts) else len(disp)
-            ffts = [v for (_, k, v) in disp[s0:s1] if "fft4_kernel" in k or "fft_pass_kernel" in k]
+            ffts = [v for (_, k, v) in disp[s0:s1] if any(n in k for n in FFT_KERNELS)]
             for name, v in zip(order, ffts):
                 per[name] = per.get(name, 0.0) + v
             for stage, names in STAGE_KERNELS.items():
