@@ -22,3 +22,22 @@ def test_admission_policy(tmp_path):
     res = subprocess.run([str(exe)], capture_output=True, text=True)
     assert res.returncode == 0, res.stdout + res.stderr
     assert res.stdout.strip().startswith("ok")
+
+
+@pytest.mark.skipif(shutil.which("g++") is None, reason="g++ not available")
+def test_admission_policy_under_address_and_undefined_behaviour_sanitizers(tmp_path):
+    # the same scenarios in a host build with AddressSanitizer and UBSan: no
+    # out-of-bounds access, use after free, leak or undefined behaviour
+    exe = tmp_path / "serve_policy_test_san"
+    src = os.path.join(ROOT, "tests", "serve_policy_test.cpp")
+    inc = os.path.join(ROOT, "paper_1803_02132_amd", "csrc")
+    flags = ["-fsanitize=address,undefined", "-fno-sanitize-recover=all", "-fno-omit-frame-pointer", "-g", "-O1"]
+    try:
+        subprocess.run(["g++", "-std=c++17", "-Wall", *flags, "-I", inc, src, "-o", str(exe)], check=True,
+                       capture_output=True, text=True)
+    except subprocess.CalledProcessError as e:
+        pytest.skip("no sanitizer runtime for g++ here: " + e.stderr[-200:])
+    env = dict(os.environ, ASAN_OPTIONS="detect_leaks=1:abort_on_error=1", UBSAN_OPTIONS="print_stacktrace=1")
+    res = subprocess.run([str(exe)], capture_output=True, text=True, env=env)
+    assert res.returncode == 0, res.stdout + res.stderr
+    assert res.stdout.strip().startswith("ok")
