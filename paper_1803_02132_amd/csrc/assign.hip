@@ -677,6 +677,19 @@ __device__ inline int tile_exponent(int visits, double cw) {
   return min(100, max(-100, 30 - ex));
 }
 
+// A grid value that this kernel never reads back: streamed past the caches
+// (nontemporal store) for FP32, a plain store for FP64.
+template <typename T>
+__device__ inline void store_stream(typename cplx<T>::type* p, typename cplx<T>::type v) {
+  if constexpr (sizeof(T) == 4) {
+    unsigned long long bits;
+    __builtin_memcpy(&bits, &v, 8);
+    __builtin_nontemporal_store(bits, (unsigned long long*)p);
+  } else {
+    *p = v;
+  }
+}
+
 // One grid copy's fixed-point words of a node -> the complex output grids:
 // packed (word g holds grid g, tile scale) or one word per channel slot
 // (words 2g and 2g+1, plan-wide scale). With clear, the words read are set
@@ -698,7 +711,7 @@ __device__ inline void put_node(unsigned long long* w, size_t wstride, int ngrid
       o.y = (T)((double)(long long)w[(size_t)(2 * gr + 1) * wstride] * inv_scale);
       if (clear) w[(size_t)(2 * gr) * wstride] = w[(size_t)(2 * gr + 1) * wstride] = 0ull;
     }
-    out[(size_t)gr * gstride] = o;
+    store_stream<T>(out + (size_t)gr * gstride, o);
   }
 }
 
