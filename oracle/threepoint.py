@@ -52,7 +52,12 @@ Readings:
       (N^3/V)(N H/I) sum_m 3j (-1)^{l1+l2} (1/N_r^2) sum_{n in b}
       y_l1^m1*(n^) y_l2^m2*(n^) H_L^M(Hn). The kernels are taken over every
       mode of the grid, Nyquist planes included, so that the kernel fields are
-      combs of points at the separation vectors (eq. 51 holds exactly).
+      combs of points at the separation vectors (eq. 51 holds exactly); the
+      fields they meet (H, and the two-point spectra dn N_L^M* - Sbar C/W^2 of
+      the j = k and i = k terms) are zero on the Nyquist planes like every
+      field of the grid (R6). For a bin holding r = 0 the two-point sums are
+      (1/(V N_r)) sum_{n in b} y_l^m*(n^) v(Hn), v the inverse transform of the
+      two-point spectrum, and Kbar_0^0 = N^3/(V N_r).
 
 Pins (tests/test_oracle_threepoint.py): the FFT form against the direct sum
 over grid points and separation vectors above; the Legendre form at L = 0
@@ -243,6 +248,20 @@ def measure(plan, data, randoms=None, pairs=None, window=False):
     return {"zeta": zr, "zeta_imag": zi, "I": I, "alpha": alpha, "n_r": n_r(plan), "spectra": spec}
 
 
+def two_point_spectrum(plan, spec, nk, sb, cw2, L, M):
+    """dn(k) N_L^M*(k) - Sbar_L^M C(k)/W^2(k), zero on the Nyquist planes (T4, R6)."""
+    n = plan.n
+    nx, ny, nz = est.mode_vectors(n)
+    v = spec[(0, 0)] * np.conj(nk[(L, M)]) - sb[(L, M)] * cw2
+    v[(np.abs(nx) == n // 2) | (np.abs(ny) == n // 2) | (np.abs(nz) == n // 2)] = 0.0
+    return v
+
+
+def two_point_sum(plan, spec, nk, sb, cw2, Kb, L, M):
+    """(1/V) sum_k K(k; b) [dn N_L^M* - Sbar C/W^2](k) for the kernel Kb (T4)."""
+    return complex(np.sum(Kb * two_point_spectrum(plan, spec, nk, sb, cw2, L, M)) / plan.volume)
+
+
 def shot_noise(plan, spec, nk, sb, cw2, I, pairs=None):
     """T4: the four coincident-index terms with separation kernels. Arguments as
     shotnoise.shot_noise (spec: dn_L^M(k), nk: N_L^M(k), sb: Sbar_L^M, cw2: C/W^2).
@@ -269,8 +288,7 @@ def shot_noise(plan, spec, nk, sb, cw2, I, pairs=None):
         return complex(np.sum(K(l, m, b)) / plan.volume)
 
     def A(l, m, L, M, b):
-        v = spec[(0, 0)] * np.conj(nk[(L, M)]) - sb[(L, M)] * cw2
-        return complex(np.sum(K(l, m, b) * v) / plan.volume)
+        return two_point_sum(plan, spec, nk, sb, cw2, K(l, m, b), L, M)
 
     def f(l, m, b):
         return (n ** 3 / plan.volume) * np.fft.ifftn(K(l, m, b))

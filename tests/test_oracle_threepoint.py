@@ -160,3 +160,28 @@ def test_shot_noise_zero_separation_bin():
     want = kbar * kbar * sb[(0, 0)].real / I
     assert out["iii"][0, 0, 0] == pytest.approx(want, rel=1e-12)
     assert abs(out["iii"][0, 0, 1]) <= 1e-12 * abs(want)   # bin 1 holds no zero separation
+
+
+@pytest.mark.parametrize("b", [0, 1])
+def test_two_point_sums_in_real_space(b):
+    # (1/V) sum_k K(k; b) v(k) = (1/(V N_r)) sum_{n in b} y*(n^) v(Hn) with v the
+    # inverse transform of the two-point spectrum (Parseval with the comb of
+    # separation vectors; the zero separation of bin 0 enters with y = delta_l0)
+    plan = _plan(k_min=0.0, dk=14.0, multipoles=[(0, 0, 0), (2, 0, 2), (1, 1, 0)])
+    spec, nk, sb, cw2, I = _shot_inputs(plan, seed=9)
+    nx, ny, nz, rb = tp.separation_vectors(plan)
+    ux, uy, uz, zero = tp.separation_units(nx, ny, nz)
+    sel = rb == b
+    assert np.any(zero[sel]) == (b == 0)
+    n = plan.n
+    got = []
+    for (l, m, L, M) in [(0, 0, 0, 0), (2, 1, 2, -1), (2, 0, 2, 0), (1, -1, 2, 1), (0, 0, 2, 2)]:
+        v = (n ** 3) * np.fft.ifftn(tp.two_point_spectrum(plan, spec, nk, sb, cw2, L, M))   # sum_k v e^{ik.Hn}
+        y = tp.sep_ylm_conj(l, m, ux[sel], uy[sel], uz[sel], zero[sel])
+        real = np.sum(y * v[nx[sel] % n, ny[sel] % n, nz[sel] % n]) / (plan.volume * np.sum(sel))
+        kspace = tp.two_point_sum(plan, spec, nk, sb, cw2, tp.kernel(plan, l, m, b), L, M)
+        got.append((kspace, real))
+    scale = max(abs(r) for _, r in got)
+    assert scale > 0
+    for kspace, real in got:
+        assert abs(kspace - real) <= 1e-12 * scale
