@@ -78,7 +78,10 @@ enum { TSB_PAIRS_PAPER = 0,      /* b1 <= b2 when l1 == l2, else every (b1, b2) 
  * grid: for r-bins without the zero separation only its i = j != k term is
  * left, on r1 = r2 bins, (N H / I)(N^3/V) sum_m 3j (-1)^{l1+l2} N_r^-2
  * sum_{n in b} y_l1^m1*(n^) y_l2^m2*(n^) H_L^M(H n) with the H field of
- * eq. 45; bins holding r = 0 are refused for it. */
+ * eq. 45. A bin holding r = 0 adds, on its row and column, the terms with
+ * the kernel average Kbar_0^0 = N^3/(V N_r): Kbar Kbar Sbar and the two-point
+ * sums (1/(V N_r)) sum_{n in b} y_l^m*(n^) v(H n), v the inverse transform of
+ * dn N_L^M* - Sbar C/W^2. */
 enum { TSB_BISPECTRUM = 0,       /* B_{l1 l2 L}(k1, k2) (Sec. 4.2, eq. 41) */
        TSB_3PCF = 1,             /* zeta_{l1 l2 L}(r1, r2) (Sec. 4.3, eqs. 47-48) */
        TSB_WINDOW = 2 };         /* Q_{l1 l2 L}(r1, r2) from the randoms alone (Sec. 6.1, eq. 58):
@@ -211,8 +214,8 @@ typedef struct tsb_plan tsb_plan;
  * TSB_E_UNSUPPORTED (N not 2^a 3^b, multipole outside Table 1's rules, shells
  * reaching the Nyquist frequency or r-bins reaching half the box, l > 8, a
  * grid shape the library does not cover, window multipoles in box mode,
- * shot_noise with window plans, the first-vertex LOS or a 3PCF r-bin holding
- * r = 0), TSB_E_NOMEM, TSB_E_DEVICE. 3PCF and window plans
+ * shot_noise with window plans or the first- or second-vertex LOS),
+ * TSB_E_NOMEM, TSB_E_DEVICE. 3PCF and window plans
  * build their separation kernels K here (one inverse transform per F slot). */
 int tsb_plan_create(const tsb_grid* grid, const tsb_los* los, const tsb_kbins* bins,
                     const tsb_multipole* multipoles, int32_t n_multipoles,

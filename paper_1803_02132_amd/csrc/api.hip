@@ -114,8 +114,9 @@ int carve_workspace(Plan& P, Carver& cv, int64_t& B) {
   ALLOC(P.d_t3, combine_fusable((int)N) ? 0 : nbc * PG * PG * PG * c);   // x-pass output before combine_kernel
   ALLOC(P.d_spec, ng * PG * PG * PG * c);
   ALLOC(P.d_dcube, PF * PF * PF * c);
-  ALLOC(P.d_u1, std::max(nf * PF * PFs * M, ng * PG * PGs * M) * c);
-  ALLOC(P.d_u2, std::max(nf * PFs * M * M, ng * PGs * M * M) * c);
+  const int64_t nv = (int64_t)P.sn_vlm.size();   // the 3PCF shot noise's two-point spectra (zero-separation bin)
+  ALLOC(P.d_u1, std::max(std::max(nf * PF * PFs * M, ng * PG * PGs * M), nv * PG * PGs * M) * c);
+  ALLOC(P.d_u2, std::max(std::max(nf * PFs * M * M, ng * PGs * M * M), nv * PGs * M * M) * c);
   ALLOC(P.d_fields, ((P.fused ? 0 : nf) + ng) * M * M * M * c);
   const int64_t ntiles = (int64_t)P.NT * P.NT * P.NT;
   P.nbk = ntiles * 27;
@@ -212,6 +213,12 @@ int plan_alloc(Plan& P, bool dry) {
     if ((rc = upload(&P.d_shell_start, P.sn_mode_start, B, dry))) return rc;
     if ((rc = upload(&P.d_cw2_tab, P.sn_alias, B, dry))) return rc;
     if ((rc = upload(&P.d_sn_combos, P.sn_combos, B, dry))) return rc;
+    if (!P.sn_vlm.empty()) {
+      const int64_t nv = (int64_t)P.sn_vlm.size();
+      if ((rc = upload(&P.d_sn_combo_v, P.sn_combo_v, B, dry))) return rc;
+      if ((rc = dalloc(&P.d_vspec, nv * (int64_t)P.PF * P.PF * P.PF * c, B, dry))) return rc;
+      if ((rc = dalloc(&P.d_vfields, nv * (int64_t)P.M * P.M * P.M * c, B, dry))) return rc;
+    }
   }
   return TSB_OK;
 }
@@ -234,7 +241,7 @@ void plan_free(Plan& P) {
                   P.d_f2idx, P.d_yspec, P.d_axis_tab, P.d_tile_hslot, P.d_heavy_tile,
                   P.d_heavy, P.d_work, P.d_hostcat, P.d_scal_n, P.d_nspec, P.d_hspec, P.d_ucube,
                   P.d_sbar, P.d_Braw, P.d_ssums, P.d_shell_modes, P.d_shell_start, P.d_cw2_tab,
-                  P.d_sn_combos, P.d_kslot};
+                  P.d_sn_combos, P.d_kslot, P.d_sn_combo_v, P.d_vspec, P.d_vfields};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
 }

@@ -1113,6 +1113,16 @@ int separation_impl(Plan& P, hipStream_t s) {
 
 }  // namespace
 
+int run_inverse_cube(Plan& P, const void* cube, int nbatch, void* out, hipStream_t s) {
+  const int64_t pg3 = (int64_t)P.PG * P.PG * P.PG;
+  if (P.precision == TSB_FP64) {
+    PassArgs<double> pre{};
+    return inverse_chain<double>(P, kStInvGX, (const double2*)cube, pg3, nbatch, P.RG, pre, (double2*)out, true, s);
+  }
+  PassArgs<float> pre{};
+  return inverse_chain<float>(P, kStInvGX, (const float2*)cube, pg3, nbatch, P.RG, pre, (float2*)out, true, s);
+}
+
 bool combine_fusable(int N) {
   return N == 16 || N == 32 || N == 64 || N == 128 || N == 256 || N == 512 || N == 1024;
 }

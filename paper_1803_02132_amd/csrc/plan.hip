@@ -153,10 +153,6 @@ int plan_build(Plan& P) {
   }
   bool any_bin = false;
   for (int64_t n2 = 0; n2 <= n2all; ++n2) any_bin = any_bin || lut[n2] >= 0;
-  // the 3PCF shot noise: for bins without the zero separation only its
-  // i = j != k term is left (eq. 51); a bin holding r = 0 would need the others
-  if (xi && P.shot_noise && lut[0] >= 0)
-    return fail(TSB_E_UNSUPPORTED, "the 3PCF shot noise is built for r-bins without the zero separation");
   if (!any_bin) return fail(TSB_E_UNSUPPORTED, xi ? "no grid separation falls in any r-bin"
                                                   : "no grid mode falls in any k-shell");
   // no shell may hold a mode with an index component of N/2 (those are zeroed);

@@ -212,19 +212,28 @@ struct SepArgs {
 };
 
 // Real or imaginary part of sum_p c_p i^-l_p y_lp^mp*(n^) for an F slot kind:
-// the slot's separation kernel at the separation vector n, per unit weight.
-__device__ inline double kind_at(const FKind& k, int part, double ux, double uy, double uz, const double* ynorm) {
+// the slot's separation kernel at the separation vector n, per unit weight
+// (the zero separation has y_l^m = delta_l0).
+__device__ inline double kind_at(const FKind& k, int part, bool zero, double ux, double uy, double uz,
+                                 const double* ynorm) {
   double sr = 0.0, si = 0.0;
   for (int p = 0; p < k.nparts; ++p) {
     const FPart& fp = k.part[p];
     const int am = fp.m < 0 ? -fp.m : fp.m;
-    double yr, yi;
-    ylm_pos_m(fp.l, am, ux, uy, uz, ynorm, &yr, &yi);
-    double ur = yr, ui = -yi;   // y_l^m*
-    if (fp.m < 0) {
-      const double sg = (am & 1) ? -1.0 : 1.0;
-      ur = sg * yr;
-      ui = sg * yi;
+    double ur, ui;   // y_l^m*
+    if (zero) {
+      ur = fp.l == 0 ? 1.0 : 0.0;
+      ui = 0.0;
+    } else {
+      double yr, yi;
+      ylm_pos_m(fp.l, am, ux, uy, uz, ynorm, &yr, &yi);
+      ur = yr;
+      ui = -yi;
+      if (fp.m < 0) {
+        const double sg = (am & 1) ? -1.0 : 1.0;
+        ur = sg * yr;
+        ui = sg * yi;
+      }
     }
     static constexpr double ire[4] = {1, 0, -1, 0}, iim[4] = {0, -1, 0, 1};   // i^-l
     const int l4 = fp.l & 3;
@@ -255,15 +264,16 @@ __global__ void __launch_bounds__(kBlock) separation_shot_kernel(SepArgs a) {
     for (int q = a.start[e.b1] + threadIdx.x; q < a.start[e.b1 + 1]; q += kBlock) {
       const int i = a.sep[q];
       const int nx = i / (PF * PF) - RF, ny = (i / PF) % PF - RF, nz = i % PF - RF;
-      const double r = sqrt((double)nx * nx + (double)ny * ny + (double)nz * nz);
+      const bool zero = nx == 0 && ny == 0 && nz == 0;
+      const double r = zero ? 1.0 : sqrt((double)nx * nx + (double)ny * ny + (double)nz * nz);
       const double ux = nx / r, uy = ny / r, uz = nz / r;
       const int jx = nx > 0 ? N - nx : -nx, jy = ny > 0 ? N - ny : -ny, jz = nz > 0 ? N - nz : -nz;
       const int64_t node = ((int64_t)jx * N + jy) * N + jz;
       for (int t = t0; t < t1; ++t) {
         const Term tm = a.terms[t];
         const Component c1 = a.fcomp[tm.f1], c2 = a.fcomp[tm.f2], cg = a.gcomp[tm.g];
-        const double f1 = kind_at(a.kinds[c1.slot], c1.part, ux, uy, uz, a.ynorm);
-        const double f2 = kind_at(a.kinds[c2.slot], c2.part, ux, uy, uz, a.ynorm);
+        const double f1 = kind_at(a.kinds[c1.slot], c1.part, zero, ux, uy, uz, a.ynorm);
+        const double f2 = kind_at(a.kinds[c2.slot], c2.part, zero, ux, uy, uz, a.ynorm);
         const T2 gv = g[(int64_t)cg.slot * N3 + node];
         acc += tm.coef * f1 * f2 * (double)(cg.part ? gv.y : gv.x);
       }
@@ -303,6 +313,118 @@ int separation_shot_impl(Plan& P, hipStream_t s) {
   hipLaunchKernelGGL(separation_shot_kernel<T>, dim3((unsigned)P.outs.size()), dim3(kBlock), 0, s, a);
   TSB_HIP(hipGetLastError());
   return TSB_OK;
+}
+
+// Two-point spectra of the 3PCF's j = k and i = k terms, for each (L, M) in
+// the list: v(k) = dn(k) N_L^M*(k) - Sbar_L^M C(k)/W^2(k) on the F cube (which
+// for the 3PCF is the whole grid without its Nyquist planes, where every field
+// is zero).
+constexpr int kMaxV = 81;
+struct VArgs {
+  const void* dcube;   // dn_0^0 on the F cube [PF^3]
+  const void* nspec;   // N spectra on the G cube
+  void* vspec;         // out [nv][PF^3]
+  const double* sbar;
+  const double* tab, *iw;
+  int RF, RG, nv, interlace;
+  LMSrc src[kMaxV];    // N source of each (L, M)
+  short sre[kMaxV], sim[kMaxV], sgn[kMaxV];   // channels of Sbar_L^|M|; M < 0: (-1)^|M| conj
+};
+
+template <typename T>
+__global__ void __launch_bounds__(kBlock) vspec_kernel(VArgs a) {
+  typedef typename cplx<T>::type T2;
+  const int PF = 2 * a.RF + 1, PG = 2 * a.RG + 1;
+  const int64_t PF3 = (int64_t)PF * PF * PF, PG3 = (int64_t)PG * PG * PG;
+  const T2* dc = (const T2*)a.dcube;
+  const T2* ns = (const T2*)a.nspec;
+  T2* out = (T2*)a.vspec;
+  for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < (int64_t)a.nv * PF3;
+       i += (int64_t)gridDim.x * kBlock) {
+    const int v = (int)(i / PF3);
+    const int64_t c = i - (int64_t)v * PF3;
+    const int fx = (int)(c / ((int64_t)PF * PF)) - a.RF, fy = (int)((c / PF) % PF) - a.RF, fz = (int)(c % PF) - a.RF;
+    const int ix = fx + a.RG, iy = fy + a.RG, iz = fz + a.RG;
+    const int64_t cp = ((int64_t)ix * PG + iy) * PG + iz;
+    const int64_t cm = ((int64_t)(PG - 1 - ix) * PG + (PG - 1 - iy)) * PG + (PG - 1 - iz);
+    double sbr = a.sre[v] >= 0 ? a.sbar[a.sre[v]] : 0.0, sbi = a.sim[v] >= 0 ? a.sbar[a.sim[v]] : 0.0;
+    if (a.sgn[v] != 0) {   // M < 0: Sbar_L^M = (-1)^|M| conj(Sbar_L^|M|)
+      sbr *= a.sgn[v];
+      sbi *= -a.sgn[v];
+    }
+    const double2 d = ld(dc, c);
+    const double2 n = nstar(ns, PG3, a.src[v], cp, cm);
+    const double cw = cw2_at(a.tab, a.iw, PG, ix, iy, iz, a.interlace);
+    T2 o;
+    o.x = (T)(d.x * n.x - d.y * n.y - sbr * cw);
+    o.y = (T)(d.x * n.y + d.y * n.x - sbi * cw);
+    out[i] = o;
+  }
+}
+
+struct TwoArgs {
+  const void* vfields;   // inverse transforms of the two-point spectra [nv][N^3]
+  const int* sep;        // F-cube indices of the separation vectors, bin by bin
+  const int* start;      // [nb + 1]
+  const Plan::SnCombo* combos;
+  int N, RF, nb;
+  double ynorm[45];
+  double* out;           // [combo][bin][2]
+};
+
+// Two-point sums of the 3PCF (the shell sums' counterpart): one block per
+// (combo, bin), sum over the bin's separation vectors n of y_l^m*(n^) v(Hn)
+// with v the inverse transform of the combo's two-point spectrum (node +n;
+// the zero separation has y = delta_l0), a fixed-shape tree.
+template <typename T>
+__global__ void __launch_bounds__(kBlock) twopoint_sums_kernel(TwoArgs a, const int* combo_v) {
+  typedef typename cplx<T>::type T2;
+  __shared__ double shr[kBlock], shi[kBlock];
+  const int combo = blockIdx.x, b = blockIdx.y;
+  const Plan::SnCombo cb = a.combos[combo];
+  const int N = a.N, RF = a.RF, PF = 2 * RF + 1;
+  const int64_t N3 = (int64_t)N * N * N;
+  const T2* vf = (const T2*)a.vfields + (int64_t)combo_v[combo] * N3;
+  double accr = 0.0, acci = 0.0;
+  for (int q = a.start[b] + threadIdx.x; q < a.start[b + 1]; q += kBlock) {
+    const int i = a.sep[q];
+    const int nx = i / (PF * PF) - RF, ny = (i / PF) % PF - RF, nz = i % PF - RF;
+    double ur, ui;   // y_l^m*(n^)
+    if (nx == 0 && ny == 0 && nz == 0) {
+      ur = cb.l == 0 ? 1.0 : 0.0;
+      ui = 0.0;
+    } else {
+      const double r = sqrt((double)nx * nx + (double)ny * ny + (double)nz * nz);
+      const int am = cb.m < 0 ? -cb.m : cb.m;
+      double yr, yi;
+      ylm_pos_m(cb.l, am, nx / r, ny / r, nz / r, a.ynorm, &yr, &yi);
+      ur = yr;
+      ui = -yi;
+      if (cb.m < 0) {
+        const double sg = (am & 1) ? -1.0 : 1.0;
+        ur = sg * yr;
+        ui = sg * yi;
+      }
+    }
+    const int jx = nx < 0 ? nx + N : nx, jy = ny < 0 ? ny + N : ny, jz = nz < 0 ? nz + N : nz;
+    const T2 v = vf[((int64_t)jx * N + jy) * N + jz];
+    accr += ur * (double)v.x - ui * (double)v.y;
+    acci += ur * (double)v.y + ui * (double)v.x;
+  }
+  shr[threadIdx.x] = accr;
+  shi[threadIdx.x] = acci;
+  __syncthreads();
+  for (int st = kBlock / 2; st > 0; st >>= 1) {
+    if (threadIdx.x < st) {
+      shr[threadIdx.x] += shr[threadIdx.x + st];
+      shi[threadIdx.x] += shi[threadIdx.x + st];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    a.out[((size_t)combo * a.nb + b) * 2] = shr[0];
+    a.out[((size_t)combo * a.nb + b) * 2 + 1] = shi[0];
+  }
 }
 
 // Where Nt_L^|M| (and the channels of Sbar_L^|M|) sit in the plan's grids.
@@ -374,6 +496,54 @@ int kspace_impl(Plan& P, hipStream_t s) {
   return TSB_OK;
 }
 
+template <typename T>
+int twopoint_impl(Plan& P, hipStream_t s) {
+  const int nv = (int)P.sn_vlm.size();
+  if (P.sn_zero_bin < 0 || nv == 0 || P.sn_combos.empty()) return TSB_OK;
+  if (nv > kMaxV) return fail(TSB_E_UNSUPPORTED, "3PCF shot noise: too many two-point spectra");
+  VArgs v{};
+  v.dcube = P.d_dcube;
+  v.nspec = P.d_nspec;
+  v.vspec = P.d_vspec;
+  v.sbar = P.d_sbar;
+  v.tab = P.d_cw2_tab;
+  v.iw = P.d_axis_tab;
+  v.RF = P.RF;
+  v.RG = P.RG;
+  v.nv = nv;
+  v.interlace = P.interlace;
+  LMSrc src[81];
+  int sre[81], sim[81];
+  lm_sources(P, src, sre, sim);
+  for (int k = 0; k < nv; ++k) {
+    const int L = P.sn_vlm[k].L, M = P.sn_vlm[k].M, aM = M < 0 ? -M : M;
+    v.src[k] = src[L * (L + 1) + M];
+    v.sre[k] = (short)sre[L * (L + 1) + aM];
+    v.sim[k] = (short)sim[L * (L + 1) + aM];
+    v.sgn[k] = (short)(M < 0 ? ((aM & 1) ? -1 : 1) : 0);
+  }
+  const int64_t pf3 = (int64_t)P.PF * P.PF * P.PF;
+  hipLaunchKernelGGL(vspec_kernel<T>, dim3((int)std::min<int64_t>((nv * pf3 + kBlock - 1) / kBlock, 8192)),
+                     dim3(kBlock), 0, s, v);
+  TSB_HIP(hipGetLastError());
+  int rc;
+  if ((rc = run_inverse_cube(P, P.d_vspec, nv, P.d_vfields, s))) return rc;
+  TwoArgs t{};
+  t.vfields = P.d_vfields;
+  t.sep = P.d_shell_modes;
+  t.start = P.d_shell_start;
+  t.combos = P.d_sn_combos;
+  t.N = P.N;
+  t.RF = P.RF;
+  t.nb = P.nb;
+  ylm_norm_table(t.ynorm);
+  t.out = P.d_ssums;
+  hipLaunchKernelGGL(twopoint_sums_kernel<T>, dim3((unsigned)P.sn_combos.size(), (unsigned)P.nb), dim3(kBlock), 0, s,
+                     t, (const int*)P.d_sn_combo_v);
+  TSB_HIP(hipGetLastError());
+  return TSB_OK;
+}
+
 double alias_a(int p, double x) {
   const double s2 = std::sin(x) * std::sin(x);
   if (p == 1) return 1.0;
@@ -395,7 +565,9 @@ int run_shot_kspace(Plan& P, hipStream_t s) {
 }
 
 int run_separation_shot(Plan& P, hipStream_t s) {
-  return P.precision == TSB_FP64 ? separation_shot_impl<double>(P, s) : separation_shot_impl<float>(P, s);
+  int rc = P.precision == TSB_FP64 ? separation_shot_impl<double>(P, s) : separation_shot_impl<float>(P, s);
+  if (rc) return rc;
+  return P.precision == TSB_FP64 ? twopoint_impl<double>(P, s) : twopoint_impl<float>(P, s);
 }
 
 // Host tables of a shot-noise plan: the complex terms of eq. 45 with the
@@ -442,7 +614,7 @@ int shot_plan(Plan& P) {
     for (int y = -RF; y <= RF; ++y)
       for (int z = -RF; z <= RF; ++z) {
         const int64_t n2 = (int64_t)x * x + (int64_t)y * y + (int64_t)z * z;
-        if (n2 == 0 || n2 > P.n2maxF) continue;
+        if ((n2 == 0 && !xi) || n2 > P.n2maxF) continue;   // (the zero separation is in its r-bin's list)
         const int b = P.bin_lut[n2];
         if (b < 0) continue;
         modes[b].push_back(((x + RF) * PF + (y + RF)) * PF + (z + RF));
@@ -476,6 +648,25 @@ int shot_plan(Plan& P) {
     P.sn_mode_list.insert(P.sn_mode_list.end(), modes[b].begin(), modes[b].end());
   }
   P.sn_mode_start[P.nb] = (int)P.sn_mode_list.size();
+  // 3PCF: an r-bin holding the zero separation has the kernel average
+  // Kbar_0^0 = N^3/(V N_r); the j = k and i = k terms then need the two-point
+  // sums of every combo, from the inverse transforms of its (L, M) spectrum
+  P.sn_zero_bin = -1;
+  P.sn_vlm.clear();
+  P.sn_combo_v.clear();
+  if (xi && !P.bin_lut.empty() && P.bin_lut[0] >= 0) {
+    P.sn_zero_bin = P.bin_lut[0];
+    for (const Plan::SnCombo& c : P.sn_combos) {
+      int v = -1;
+      for (size_t k = 0; k < P.sn_vlm.size(); ++k)
+        if (P.sn_vlm[k].L == c.L && P.sn_vlm[k].M == c.M) v = (int)k;
+      if (v < 0) {
+        v = (int)P.sn_vlm.size();
+        P.sn_vlm.push_back({0, 0, c.L, c.M});
+      }
+      P.sn_combo_v.push_back(v);
+    }
+  }
   // alias sums per stored G-cube axis entry, x = pi n / N
   P.sn_alias.assign(2 * (size_t)P.PG, 0.0);
   for (int j = 0; j < P.PG; ++j) {
@@ -511,24 +702,29 @@ void shot_finish(Plan& P, const double* sbar, const double* sums, const double* 
     if (M < 0) v = ((aM & 1) ? -1.0 : 1.0) * std::conj(v);
     return v;
   };
+  // The 3PCF (reading of eq. 51): the kernel averages (1/V) sum_k K vanish but
+  // for the zero separation's bin, where Kbar_0^0 = N^3 / (V N_r); the
+  // two-point sums carry 1/(V N_r) instead of the shell average's 1/N_mode.
+  const bool xi = P.estimator != TSB_BISPECTRUM;
+  const double V = P.L * P.L * P.L, N3 = (double)P.N * P.N * P.N;
   auto ybar = [&](int l, int m, int b) {
+    if (xi) return cd(b == P.sn_zero_bin && l == 0 && m == 0 ? N3 / (V * (double)P.nmode[b]) : 0.0, 0.0);
     const size_t k = ((size_t)(l * (l + 1) + m) * P.nb + b) * 2;
     return cd(P.sn_ybar[k], P.sn_ybar[k + 1]);
   };
   auto A = [&](int combo, int L, int M, int b) {
     cd v(sums[((size_t)combo * P.nb + b) * 2], sums[((size_t)combo * P.nb + b) * 2 + 1]);
-    v /= (double)P.nmode[b];
+    v /= (double)P.nmode[b] * (xi ? V : 1.0);
     if (P.los_kind == TSB_LOS_GLOBAL) v *= std::conj(ylm_any(L, M, P.los_dir, norm));
     return v;
   };
-  const bool xi = P.estimator != TSB_BISPECTRUM;   // only the i = j != k term
   for (size_t o = 0; o < P.outs.size(); ++o) {
     const OutEntry& e = P.outs[o];
     const int l1 = P.mult[e.mu].l1, l2 = P.mult[e.mu].l2, L = P.mult[e.mu].L;
     const double pref = P.mu_pref[e.mu] / I;
     cd t(0.0, 0.0);
     for (const Plan::SnTerm& st : P.sn_terms) {
-      if (st.mu != e.mu || xi) continue;
+      if (st.mu != e.mu || (xi && P.sn_zero_bin < 0)) continue;   // (3PCF without the zero bin: i = j != k only)
       const cd y1 = ybar(l1, st.m1, e.b1), y2 = ybar(l2, st.m2, e.b2);
       t += st.w3j * (y1 * y2 * sbar_lm(L, st.M) + A(st.cjk, L, st.M, e.b1) * y2 + y1 * A(st.cik, L, st.M, e.b2));
     }

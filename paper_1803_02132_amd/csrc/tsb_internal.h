@@ -168,6 +168,15 @@ struct Plan {
   std::vector<double> h_sn;             // host copies after a measurement: Sbar, sums, raw B, S_ij
   std::vector<double> last_S, last_Sij; // the last measurement's S and S_ij ([n_mult][nb][nb])
   std::vector<int> sn_mode_list, sn_mode_start;   // host copies of the shell mode list
+  // 3PCF with an r-bin holding the zero separation: that bin, the (L, M) of
+  // the two-point spectra dn N_L^M* - Sbar C/W^2 the other terms need, and
+  // each combo's index among them
+  int sn_zero_bin = -1;
+  std::vector<SnCombo> sn_vlm;
+  std::vector<int> sn_combo_v;
+  void* d_vspec = nullptr;      // those two-point spectra on the F cube [nv][PF^3]
+  void* d_vfields = nullptr;    // their inverse transforms [nv][M^3]
+  int* d_sn_combo_v = nullptr;
   std::vector<double> sn_alias;                   // host copy of the alias-sum table
   double* d_sum_partials = nullptr;   // per-block partial sums (prep and I)
   double* d_axis_tab = nullptr;   // per stored axis mode: 1/W_axis, cos and sin of pi n/N
@@ -292,7 +301,10 @@ int run_shot_kspace(Plan& P, hipStream_t s);
 int run_separation_shot(Plan& P, hipStream_t s);   // the 3PCF's i = j != k term (shot.hip)
 // Whether the forward x pass of an N grid runs fused with the combination of
 // the interlaced copies (register-FFT lengths; else a pass buffer and combine_kernel).
-bool combine_fusable(int N);   // H spectra and the shell sums (shot.hip)
+bool combine_fusable(int N);
+// The inverse chain of nbatch complex cubes of half-width RG (G-cube layout)
+// into full fields [nbatch][M^3] (fft.hip).
+int run_inverse_cube(Plan& P, const void* cube, int nbatch, void* out, hipStream_t s);   // H spectra and the shell sums (shot.hip)
 int shot_plan(Plan& P);                        // host tables of the shot noise (shot.hip)
 void shot_finish(Plan& P, const double* sbar, const double* sums, const double* Braw, const double* Sij,
                  double I, double* B_out);      // host: S and B - S (shot.hip)

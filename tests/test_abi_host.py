@@ -151,7 +151,6 @@ def test_separation_bins_of_the_3pcf_match_the_oracle():
 
 @pytest.mark.parametrize("bad,code", [
     (dict(estimator="window"), tsb.abi.TSB_E_UNSUPPORTED),                  # window needs randoms
-    (dict(estimator="3pcf", shot_noise=True), tsb.abi.TSB_E_UNSUPPORTED),  # a bin holding r = 0
     (dict(estimator="window", shot_noise=True, box_mode=False), tsb.abi.TSB_E_UNSUPPORTED),
     (dict(estimator="3pcf", dk=30.0), tsb.abi.TSB_E_UNSUPPORTED),          # r-bins reach half the box
     (dict(estimator="3pcf", k_min=500.0), tsb.abi.TSB_E_UNSUPPORTED),      # no separation in any bin

@@ -168,9 +168,31 @@ def test_zeta_shot_noise_box(precision, tol):
         assert np.max(np.abs(S[mu][off])) <= 1e-6 * np.max(np.abs(S[mu]))
 
 
-def test_zeta_shot_noise_survey_global_los():
+@pytest.mark.parametrize("precision,tol", [("f32", 1e-4), ("f64", 1e-9)])
+def test_zeta_shot_noise_with_the_zero_separation_bin(precision, tol):
+    # a bin holding r = 0: Kbar_0^0 = N^3/(V N_r) there, so the i = j = k term and
+    # the two-point sums (j = k, i = k) join the i = j != k term on its pairs
+    req = _box(precision=precision, pair_mode="all", k_min=0.0, dk=25.0, n_bins=3)
+    cat = lognormal_box(32, 320.0, 30000, 34, rsd="local", observer=req["observer"])
+    plan = tsb.Plan(**dict(req, estimator="3pcf", shot_noise=True))
+    got = plan.measure(tsb.catalog_to_device(cat))
+    S, Sij = plan.shot_noise()
+    ref = tp.measure_shot_noise(oracle_plan(**req), cat)
+    mask = pair_mask(req["multipoles"], req["n_bins"], "all")
+    e1 = normwise_errors(got["B"], ref["zeta"] - ref["S"], mask)
+    e2 = normwise_errors(S, ref["S"], mask)
+    e3 = normwise_errors(Sij, ref["ij"], mask)
+    report("3pcf shot noise, zero-separation bin", precision, "zeta - S", e1, "S", e2, "S_ij", e3)
+    assert np.all(e1 <= tol) and np.all(e2 <= tol) and np.all(e3 <= tol)
+    # the other terms are not zero on the zero bin's row and column
+    other = ref["S"] - ref["ij"]
+    assert np.max(np.abs(other[0][0, :])) > 1e-3 * np.max(np.abs(ref["S"][0]))
+
+
+@pytest.mark.parametrize("k_min", [8.0, 0.0])   # 0: the first bin holds the zero separation
+def test_zeta_shot_noise_survey_global_los(k_min):
     req = _box(box_mode=False, P0=2000.0, observer=(160.0, 160.0, 160.0), los="global", los_dir=(0.2, 0.1, 1.0),
-               k_min=8.0, dk=20.0, n_bins=4, pair_mode="all", multipoles=[(0, 0, 0), (2, 0, 2), (1, 1, 0)])
+               k_min=k_min, dk=20.0, n_bins=4, pair_mode="all", multipoles=[(0, 0, 0), (2, 0, 2), (1, 1, 0)])
     data, rand = _shell_catalogues((160.0, 160.0, 160.0), 40.0, 140.0, 20000, 80000, 33)
     plan = tsb.Plan(**dict(req, estimator="3pcf", shot_noise=True))
     got = plan.measure(tsb.catalog_to_device(data), tsb.catalog_to_device(rand))
@@ -179,5 +201,5 @@ def test_zeta_shot_noise_survey_global_los():
     mask = pair_mask(req["multipoles"], req["n_bins"], "all")
     e1 = normwise_errors(got["B"], ref["zeta"] - ref["S"], mask)
     e2 = normwise_errors(S, ref["S"], mask)
-    report("3pcf shot noise survey", "zeta - S", e1, "S", e2)
+    report("3pcf shot noise survey, r_min", k_min, "zeta - S", e1, "S", e2)
     assert np.all(e1 <= 1e-4) and np.all(e2 <= 1e-4)
