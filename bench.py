@@ -238,6 +238,65 @@ def ingest_pmc(fetch_csv, write_csv, command, workload="box256"):
     print("\n".join(lines))
 
 
+SQ_KERNELS = (("assign_tile_kernel", "assign"), ("fz_reduce_wide_kernel", "reduce (one pass)"),
+              ("fz_reduce_kernel", "reduce (one pass, general)"), ("reduce_mfma_wide_kernel", "reduce (matrix cores)"),
+              ("fft4_combine_kernel", "fwd_x + combination"), ("fft4_kernel", "FFT passes"),
+              ("bucket_fill_kernel", "bucket fill"))
+
+
+def summarize_sq(csvs, command, out_name, clock_ghz=2.4, simds=1024):
+    """Occupancy and issue counters (rocprofv3 --pmc SQ_* runs) per kernel: mean
+    resident wavefronts per SIMD = 4 SQ_WAVE_CYCLES / (duration x clock x SIMDs)
+    (the SQ counts wave cycles in units of 4 clocks), the shares of a wave's
+    lifetime with a VALU instruction active (SQ_ACTIVE_INST_VALU / SQ_WAVE_CYCLES)
+    and waiting (SQ_WAIT_ANY / SQ_WAVE_CYCLES), instructions per wave, LDS bank
+    conflict cycles per LDS instruction and the MFMA-busy share of the SIMDs."""
+    import csv
+    per = {}   # (kernel label) -> {counter: [values per dispatch]}, durations
+    for path in csvs:
+        with open(path) as fh:
+            for r in csv.DictReader(fh):
+                label = next((lab for key, lab in SQ_KERNELS if key + "<" in r["Kernel_Name"]
+                              or r["Kernel_Name"].endswith(key)), None)
+                if label is None:
+                    continue
+                d = per.setdefault(label, {"dur": {}, "vgpr": r.get("VGPR_Count"), "lds": r.get("LDS_Block_Size"),
+                                           "wg": r.get("Workgroup_Size")})
+                d.setdefault(r["Counter_Name"], []).append(float(r["Counter_Value"]))
+                d["dur"][(path, r["Dispatch_Id"])] = (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) * 1e-9
+    lines = [f"# Occupancy and issue counters: {out_name}", "", "Command:", "", "    " + command, "",
+             "Per dispatch means. Waves/SIMD: mean resident wavefronts per SIMD (4 SQ_WAVE_CYCLES over the "
+             f"dispatch's duration x {clock_ghz} GHz x {simds} SIMDs). VALU active and waiting: shares of the "
+             "wavefronts' lifetime (SQ_ACTIVE_INST_VALU and SQ_WAIT_ANY over SQ_WAVE_CYCLES). MFMA busy: "
+             "SQ_VALU_MFMA_BUSY_CYCLES over the SIMD cycles of the dispatch.", "",
+             "| kernel | VGPRs | workgroup | waves/SIMD | VALU active | waiting | VALU instr/wave | LDS instr/wave | "
+             "bank-conflict cycles per LDS instr | MFMA busy |",
+             "|---|---|---|---|---|---|---|---|---|---|"]
+
+    def mean(d, k):
+        v = d.get(k)
+        return sum(v) / len(v) if v else float("nan")
+
+    for key, label in SQ_KERNELS:
+        d = per.get(label)
+        if not d:
+            continue
+        dur = sum(d["dur"].values()) / len(d["dur"])
+        wc, waves = mean(d, "SQ_WAVE_CYCLES"), mean(d, "SQ_WAVES")
+        occ = 4 * wc / (dur * clock_ghz * 1e9 * simds)
+        valu = mean(d, "SQ_ACTIVE_INST_VALU") / wc
+        wait = mean(d, "SQ_WAIT_ANY") / wc
+        lds = mean(d, "SQ_INSTS_LDS")
+        mfma = mean(d, "SQ_VALU_MFMA_BUSY_CYCLES") / (dur * clock_ghz * 1e9 * simds)
+        lines.append(f"| {label} (`{key}`) | {d['vgpr']} | {d['wg']} | {occ:.2f} | {valu:.1%} | {wait:.1%} | "
+                     f"{mean(d, 'SQ_INSTS_VALU') / waves:.0f} | {lds / waves:.0f} | "
+                     f"{mean(d, 'SQ_LDS_BANK_CONFLICT') / max(lds, 1):.2f} | {mfma:.1%} |")
+    path = os.path.join(ROOT, "profiles", out_name + ".md")
+    with open(path, "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+    print("\n".join(lines))
+
+
 def summarize_trace(stats_csv, command, out_name, trace_csv=None, timed=0, bench_log=None):
     """A short text summary of a rocprofv3 --kernel-trace --stats run."""
     import csv
@@ -557,6 +616,9 @@ def main():
                          "`bench.py --copy-probe --workload <workload>` and exit")
     ap.add_argument("--summarize-trace", nargs=3, metavar=("STATS_CSV", "COMMAND", "NAME"),
                     help="write profiles/NAME.md from a rocprofv3 kernel-stats CSV and exit")
+    ap.add_argument("--summarize-sq", nargs=4, metavar=("CSV1", "CSV2", "COMMAND", "NAME"),
+                    help="write profiles/NAME.md from two rocprofv3 --pmc SQ_* counter runs (occupancy, VALU "
+                         "activity, waits, LDS conflicts, MFMA busy per kernel)")
     ap.add_argument("--trace-csv", default=None,
                     help="with --summarize-trace: the run's kernel-trace CSV, for the timed-region table")
     ap.add_argument("--timed-launches", type=int, default=0,
@@ -566,6 +628,9 @@ def main():
     args = ap.parse_args()
     if args.ingest_pmc:
         ingest_pmc(*args.ingest_pmc, workload=args.workload)
+        return
+    if args.summarize_sq:
+        summarize_sq(args.summarize_sq[:2], args.summarize_sq[2], args.summarize_sq[3])
         return
     if args.summarize_trace:
         summarize_trace(*args.summarize_trace, trace_csv=args.trace_csv, timed=args.timed_launches,
