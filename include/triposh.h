@@ -141,9 +141,14 @@ typedef struct {
   int32_t pair_mode;  /* TSB_PAIRS_* */
   int32_t box_mode;   /* 1: periodic box without randoms; 0: survey with randoms */
   double P0;          /* FKP P0; <= 0 disables the FKP factor */
-  int32_t unfused;    /* 0: run the last F transform inside the reduction when the
-                         plan fits (default); 1: always write the F fields and
-                         reduce separately (same result to rounding) */
+  int32_t unfused;    /* 0 (default): run the last F transform inside the
+                         reduction when the plan fits, except FP32 plans whose
+                         one-pass reduction would take its shells in groups and
+                         whose F fields take at most 4 GiB, which write the F
+                         fields and reduce them on the matrix cores (faster
+                         there); 1: always write the F fields and reduce
+                         separately; 2: the one-pass path whenever the plan
+                         fits. The paths agree to rounding. */
   int32_t estimator;  /* TSB_BISPECTRUM, TSB_3PCF or TSB_WINDOW */
   int32_t shot_noise; /* 1 subtracts the shot noise S: the bispectrum's of Sec. 4.2
                          (eqs. 44-46: the four coincident-index terms), the

@@ -42,7 +42,7 @@ def _request(n, box_len, multipoles, n_bins, dk=1.0, k_min=0.0, edges=None, orig
     bins = abi.tsb_kbins(int(n_bins), float(k_min), float(dk), earr)
     mps = [abi.tsb_multipole(*map(int, m)) for m in multipoles]
     opts = abi.tsb_options(abi.TSB_FP64 if precision == "f64" else abi.TSB_FP32, _PAIR[pair_mode],
-                           int(bool(box_mode)), float(P0), int(bool(unfused)), _ESTIMATOR[estimator],
+                           int(bool(box_mode)), float(P0), int(unfused), _ESTIMATOR[estimator],
                            int(bool(shot_noise)))
     return grid, lo, bins, mps, opts, earr
 

@@ -685,7 +685,8 @@ static int copy_request(Plan& P, const tsb_grid* grid, const tsb_los* los, const
   P.pair_mode = options->pair_mode;
   P.box_mode = options->box_mode ? 1 : 0;
   P.P0 = options->P0;
-  P.unfused = options->unfused ? 1 : 0;
+  if (options->unfused < 0 || options->unfused > 2) return fail(TSB_E_ARG, "unfused must be 0, 1 or 2");
+  P.unfused = options->unfused;
   P.estimator = options->estimator;
   P.shot_noise = options->shot_noise;
   return plan_build(P);

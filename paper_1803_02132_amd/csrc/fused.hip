@@ -803,7 +803,7 @@ int fused_impl(Plan& P, hipStream_t s) {
 // Planning: whether the fused path applies and its bin-group size.
 void plan_fused(Plan& P) {
   P.fused = false;
-  if (P.unfused) return;
+  if (P.unfused == 1) return;
   const int M = P.M;
   if (!(M == 16 || M == 32 || M == 64 || M == 128 || M == 256)) return;
   if ((int)P.outs.size() > kOutPerThread * kBlock || P.outs.empty()) return;
@@ -812,6 +812,14 @@ void plan_fused(Plan& P) {
     return;
   const int wide_bpg = wide_group(P);
   P.fused_wide = wide_bpg > 0;
+  // Shells in groups make the one-pass kernel re-stage every line per group;
+  // when the F fields are affordable the unfused matrix-core reduction is
+  // faster (the 128^3 box with {000, 110, 202, 112}: 1.84 against 2.14 ms)
+  const int64_t f_bytes = (int64_t)P.nb * (int64_t)P.fkinds.size() * M * M * M * 8;
+  if (P.unfused == 0 && P.fused_wide && wide_bpg < P.nb && unfused_mfma_applies(P) && f_bytes <= (4LL << 30)) {
+    P.fused_wide = false;
+    return;
+  }
   if (P.fused_wide) {
     // one workgroup of 512 threads per compute unit (its LDS fills one): 256 on MI355X
     P.fused = true;

@@ -73,6 +73,13 @@ void ylm_norm_table(double* norm) {
     }
 }
 
+// Whether an unfused FP32 plan reduces on the matrix cores in the kernel with
+// its terms in the kernel arguments (at most 32 shells, 16 Q groups, 64 terms).
+bool unfused_mfma_applies(const Plan& P) {
+  return P.precision == TSB_FP32 && P.nb <= 32 && P.red_chunk % 8 == 0 && P.fkinds.size() <= 32 &&
+         P.grids.size() <= 32 && P.qgroups.size() >= 1 && P.qgroups.size() <= 16 && P.terms.size() <= 64;
+}
+
 int plan_build(Plan& P) {
   const int N = P.N;
   if (N < 16 || N > 1024 || N % 4 != 0 || !is_2a3b(N))
@@ -490,7 +497,7 @@ int plan_build(Plan& P) {
   // the matrix cores (32 x 32 tiles, k steps of 8 cells), up to 16 Q groups
   P.red_mfma = 0;
   if (!P.fused && P.precision == TSB_FP32 && P.nb <= 32 && P.red_chunk % 8 == 0 && P.fkinds.size() <= 32 &&
-      P.grids.size() <= 32) {
+      P.grids.size() <= 32) {   // (unfused_mfma_applies holds the same conditions for the wide kernel)
     const int upw = ((int)P.qgroups.size() + 3) / 4;
     if (upw >= 1 && upw <= 4) P.red_mfma = upw == 1 ? 1 : (upw == 2 ? 2 : 4);
     // fewer, longer chunks: up to 96 KiB of staged rows (one workgroup per CU

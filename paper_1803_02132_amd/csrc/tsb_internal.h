@@ -302,6 +302,7 @@ int run_separation_shot(Plan& P, hipStream_t s);   // the 3PCF's i = j != k term
 // Whether the forward x pass of an N grid runs fused with the combination of
 // the interlaced copies (register-FFT lengths; else a pass buffer and combine_kernel).
 bool combine_fusable(int N);
+bool unfused_mfma_applies(const Plan& P);   // plan.hip
 // The inverse chain of nbatch complex cubes of half-width RG (G-cube layout)
 // into full fields [nbatch][M^3] (fft.hip).
 int run_inverse_cube(Plan& P, const void* cube, int nbatch, void* out, hipStream_t s);   // H spectra and the shell sums (shot.hip)

@@ -80,6 +80,21 @@ def test_reduction_grid_rule():
     assert info.m == 32 and info.r_g == 15
 
 
+def test_reduction_path_rule():
+    # 128^3, {000, 110, 202, 112}, 20 shells: the one-pass reduction would take
+    # its shells in groups, so the rule writes the F fields and reduces them on
+    # the matrix cores; 256^3 {000, 202} fits one group and stays one-pass
+    mults = [(0, 0, 0), (1, 1, 0), (2, 0, 2), (1, 1, 2)]
+    r = req(n=128, n_bins=20, dk=0.01, multipoles=mults, interlace=True)
+    assert tsb.query(**r)[0].fused == 0
+    assert tsb.query(**dict(r, unfused=2))[0].fused == 2
+    assert tsb.query(**dict(r, unfused=1))[0].fused == 0
+    assert tsb.query(**req(n=256, n_bins=20, dk=0.01, interlace=True))[0].fused == 2
+    with pytest.raises(tsb.TsbError) as e:
+        tsb.query(**dict(r, unfused=3))
+    assert e.value.code == tsb.abi.TSB_E_ARG
+
+
 def test_channel_and_field_counts():
     # local LOS {000, 202}: channels (0,0), (2,0), (2,1)re/im, (2,2)re/im
     info, _, _ = tsb.query(**req())

@@ -184,7 +184,7 @@ def test_reduction_split_and_schedule_reuse_are_bitwise(mults, n_bins, dk_kf):
     # columns transformed once, and a schedule applied from another plan: the
     # same arithmetic, bitwise
     import math
-    req = box_request(n=64, n_bins=n_bins, dk=dk_kf * 2.0 * math.pi / 1000.0, multipoles=mults)
+    req = box_request(n=64, n_bins=n_bins, dk=dk_kf * 2.0 * math.pi / 1000.0, multipoles=mults, unfused=2)
     dev = tsb.catalog_to_device(_cat(64, 43, 40000))
     plan = tsb.Plan(**req)
     assert plan.info.fused == 2
