@@ -515,7 +515,7 @@ struct TileArgs {
   int nr;
   int rd[kMaxRanges], rcl[kMaxRanges], rch[kMaxRanges];
   // work items: the extra parts of split tiles (a tile with more than
-  // kPartVisits visits), then part 0 of every tile
+  // part_visits visits), then part 0 of every tile
   const int2* work;            // extra parts (tile, part >= 1)
   const int* nextra;           // number of extra parts (device)
   int ntiles;
@@ -562,7 +562,14 @@ __device__ inline void node_dir(const double* origin, double h, const double* ob
 }
 
 constexpr int kVisitChunk = 128;  // particles staged in LDS at a time (a power of two)
-constexpr int kPartVisits = 256;  // visits per work item; busier tiles are split
+// Visits per work item; busier tiles are split. A packed FP32 item's
+// fixed-point step grows with its visits: box plans take 512 (half the slots
+// and slot atomics of 256), survey plans, whose density is the small
+// difference of two window-shaped fields and whose packed contributions are
+// rounded stochastically, keep 256 (one more fraction bit).
+constexpr int kPartVisits = 256;
+constexpr int kPartVisitsBox = 512;
+__host__ __device__ inline int part_visits(int box_mode) { return box_mode ? kPartVisitsBox : kPartVisits; }
 constexpr int kTileBlock = 256;    // threads per workgroup of the tile kernel
 constexpr int kMinHeavy = 2048;   // split-tile slots at least (or one per tile); others run whole
 
@@ -667,7 +674,7 @@ __device__ inline void unpack2(unsigned long long v, int* lo, int* hi) {
 // weight of the kernel), and the scale maps that bound below 2^30. A
 // contribution is the FP32 product c W 2^e rounded to the nearest integer
 // (ties to even), so the rounding errors carry no bias. Packing is used for
-// work items of at most kPartVisits visits (a whole tile, or a part of a
+// work items of at most part_visits visits (a whole tile, or a part of a
 // split one), so the fixed-point step is at most 2^-21 max |c| W_max.
 __device__ inline int tile_exponent(int visits, double cw) {
   const double bound = (double)visits * cw;
@@ -754,6 +761,7 @@ __global__ void __launch_bounds__(kTileBlock, (sizeof(T) == 4 && NCH <= 8) ? 4 :
   T2* out = (T2*)a.out;
   const size_t N3 = (size_t)N * N * N;
   const double scale = a.scal->scale, inv_scale = a.scal->inv_scale, cmax = a.scal->cmax, alpha = a.scal->alpha;
+  const int part_v = part_visits(a.box_mode);
 
   // Work-item pipeline: the ranges of the next-but-one item are fetched into
   // the first wavefront's registers, and the first chunk of particle records
@@ -813,8 +821,8 @@ __global__ void __launch_bounds__(kTileBlock, (sizeof(T) == 4 && NCH <= 8) ? 4 :
   };
   auto window = [&](int b, int* v0, int* v1) {   // visits of the item in table b
     const int total = r_off[b][64], hs = item[b][2];
-    *v0 = hs >= 0 ? item[b][1] * kPartVisits : 0;
-    *v1 = hs >= 0 ? min(total, *v0 + kPartVisits) : total;
+    *v0 = hs >= 0 ? item[b][1] * part_v : 0;
+    *v1 = hs >= 0 ? min(total, *v0 + part_v) : total;
   };
   auto load_rec = [&](int b, int idx, double* u, T* cv) {   // visit idx of table b
     int lo = 0, hi = a.nr;   // r_off[lo] <= idx < r_off[hi]
@@ -857,16 +865,16 @@ __global__ void __launch_bounds__(kTileBlock, (sizeof(T) == 4 && NCH <= 8) ? 4 :
   const int o3[3] = {tx * TS, ty * TS, tz * TS};
   int v0, v1;
   window(cb, &v0, &v1);
-  // FP32 work items of at most kPartVisits visits pack two channels per word,
+  // FP32 work items of at most part_v visits pack two channels per word,
   // both grid copies in one pass (word of copy c, grid k: c * npair + k), at
   // a scale of their own: a whole tile (from its visits), or a part of a
-  // split tile (from kPartVisits, the same for every part: which part a
+  // split tile (from part_v, the same for every part: which part a
   // particle falls in depends on the bucket order, its rounding must not).
   // A part converts its sums to the plan's scale, exactly, when it adds them
   // into the slot (the shift plan_e - et is never negative then).
   const int plan_e = ilogb(scale);
-  const int et_item = tile_exponent(hs >= 0 ? kPartVisits : v1 - v0, cmax * a.wmax);
-  const bool packed = sizeof(T) == 4 && (r_off[cb][64] <= kPartVisits || (hs >= 0 && plan_e >= et_item));
+  const int et_item = tile_exponent(hs >= 0 ? part_v : v1 - v0, cmax * a.wmax);
+  const bool packed = sizeof(T) == 4 && (r_off[cb][64] <= part_v || (hs >= 0 && plan_e >= et_item));
   const unsigned tile_key = mix32((unsigned)tile * 0x9E3779B9U + 0x85EBCA6BU);
   const int et = packed ? et_item : 0;
   const float tscale = ldexpf(1.0f, et);
@@ -1180,7 +1188,8 @@ __global__ void __launch_bounds__(kBlock) tile_parts_kernel(TileArgs a, int ntil
   }
   for (int off = 32; off > 0; off >>= 1) len += __shfl_xor(len, off);
   if (lane != 0) return;
-  const int np = (len + kPartVisits - 1) / kPartVisits;
+  const int pv = part_visits(a.box_mode);
+  const int np = (len + pv - 1) / pv;
   int hs = -1;
   if (np > 1) {
     const int sl = atomicAdd(nheavy, 1);
@@ -1348,7 +1357,7 @@ int64_t assign_work_cap(const Plan& P, int64_t particles) {
   return work_capacity((int64_t)P.NT * P.NT * P.NT, particles, kPartVisits);
 }
 
-int assign_part_visits() { return kPartVisits; }
+int assign_part_visits() { return kPartVisits; }   // the smaller of the two: more work items
 
 int64_t assign_heavy_bytes(const Plan& P) {
   return (int64_t)P.heavy_slots * P.copies * assign_words(P) * P.T * P.T * P.T * 8;
@@ -1427,7 +1436,8 @@ int assign_front_impl(Plan& P, const BucketArgs& b, const ChanInfo& ci, hipStrea
   const int nchx = ci.nch + (P.box_mode ? 0 : 1);
   const size_t lds = (size_t)assign_words(P) * P.T * P.T * P.T * sizeof(unsigned long long);
   // upper bound of the work items: a particle is visited by at most 8 tiles
-  const int64_t work_bound = (int64_t)ntiles + (8 * ntot + kPartVisits - 1) / kPartVisits + 1;
+  const int pv = part_visits(P.box_mode);
+  const int64_t work_bound = (int64_t)ntiles + (8 * ntot + pv - 1) / pv + 1;
   if (work_bound > P.work_cap) return fail(TSB_E_UNSUPPORTED, "assignment: work list too small");
   if (P.tile_wgs <= 0) {
     // persistent workgroups of the tile kernel: as many as are resident at once
@@ -1505,7 +1515,7 @@ int assign_back_impl(Plan& P, const ChanInfo& ci, hipStream_t s) {
   a.heavy = (unsigned long long*)P.d_heavy;
   a.max_heavy = P.heavy_slots;
   prof_begin(P, kStAssign, s);
-  // work items: tiles with more than kPartVisits visits are split into parts
+  // work items: tiles with more than part_visits visits are split into parts
   hipLaunchKernelGGL(tile_parts_kernel, dim3((ntiles + kBlock / 64 - 1) / (kBlock / 64)), dim3(kBlock), 0, s, a,
                      ntiles, P.d_tile_hslot, P.d_heavy_tile, nheavy, nextra, (int2*)P.d_work);
   const size_t lds = (size_t)nw * P.T * P.T * P.T * sizeof(unsigned long long);
