@@ -80,7 +80,10 @@ def shell_r2(info, req):
 def stage_bytes(info, copies, n_particles, req, fused=True, esz=4):
     """Algorithmic HBM bytes per launch of each single-kernel stage: every input
     read once and every output written once in the stated layout (particle
-    records: 12 B of position plus 4 B per channel). The inverse transforms of
+    records: 12 B of position plus 4 B per channel). A plan that assigns by
+    columns writes the z pass's output from the assignment (the grids are
+    never stored), so its assign stage holds the records and that output and
+    it has no fwd_z stage. The inverse transforms of
     shell-filtered and band-limited spectra count the lines and entries that
     can be non-zero: for shell b, the (n_y, n_z) lines of the x pass and the
     n_z entries after it with |n|^2 within the shell's largest |n|^2."""
@@ -109,6 +112,9 @@ def stage_bytes(info, copies, n_particles, req, fused=True, esz=4):
         "invG_y": ng * M * g1 * c + ng * M * M * g2 * c,
         "invG_z": ng * M * M * g2 * c + ng * M ** 3 * c,
     }
+    if getattr(info, "assign_columns", 0):
+        out["assign"] = nbc * N * N * PG * c + (24 + 4 * info.n_channels) * n_particles
+        del out["fwd_z"]
     if fused:   # last F transform inside the reduction: reads the y-pass output and G
         out["reduce"] = lf2 * M * M * c + ng * M ** 3 * c
     else:
@@ -149,7 +155,7 @@ def load_traffic(workload, geometry, stage):
 
 COPY_PROBE_BYTES = 512 << 20
 # stage -> kernels whose dispatches make up one launch of the stage
-STAGE_KERNELS = {"assign": ("tile_parts_kernel", "assign_tile_kernel", "heavy_final_kernel"),
+STAGE_KERNELS = {"assign": ("tile_parts_kernel", "assign_tile_kernel", "heavy_final_kernel", "zcol_kernel"),
                  "reduce": ("fz_reduce_wide_kernel", "fz_reduce_kernel", "reduce_kernel", "reduce_mfma_kernel",
                             "reduce_mfma_wide_kernel")}
 # kernels of the FFT passes (the fused forward x pass with the combination included)
@@ -192,7 +198,7 @@ def ingest_pmc(fetch_csv, write_csv, command, workload="box256"):
     info = tsb.query(**req)[0]
     geometry = plan_geometry(info, req)
     fused = bool(info.fused)
-    order = FFT_ORDER + ([] if fused else ["invF_z"])
+    order = [st for st in FFT_ORDER if st != "fwd_z" or not info.assign_columns] + ([] if fused else ["invF_z"])
     out = {}
     for label, path in (("fetch", fetch_csv), ("write", write_csv)):
         disp = _read_counters(path)

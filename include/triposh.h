@@ -153,6 +153,14 @@ typedef struct {
   int32_t shot_noise; /* 1 subtracts the shot noise S: the bispectrum's of Sec. 4.2
                          (eqs. 44-46: the four coincident-index terms), the
                          3PCF's of eq. 51 (third-vertex LOS, not window plans) */
+  int32_t assign_tiles; /* 0 (default): box-mode FP32 plans on grids of 32, 64,
+                         128 or 256 points with up to four complex grids per
+                         copy assign by columns of 2 x 2 x N nodes and
+                         transform each column's z lines before anything
+                         reaches device memory (the grids are never stored);
+                         1: always assign by tiles and store the grids. The
+                         paths agree to rounding (the column path's
+                         fixed-point step follows each column's visit count). */
 } tsb_options;
 /* FP32 plans, precisely: channel weights are computed in FP64 and stored in
  * FP32 (survey plans round each one up or down with probability given by its
@@ -209,6 +217,8 @@ typedef struct {
                               contraction, 3 per (shell, term, cell) forming the
                               Q rows, and, when fused, 5 M log2 M per line of the
                               last F transform */
+  int32_t assign_columns;  /* 1: measurements assign by columns with the z
+                              transform (see tsb_options.assign_tiles) */
 } tsb_plan_info;
 
 typedef struct tsb_plan tsb_plan;

@@ -28,7 +28,7 @@ def _axes(v, typ):
 def _request(n, box_len, multipoles, n_bins, dk=1.0, k_min=0.0, edges=None, origin=(0.0, 0.0, 0.0), assign_p=3,
              interlace=False, los="local", los_dir=(0.0, 0.0, 1.0), observer=(0.0, 0.0, 0.0), vertex="x3",
              box_mode=True, P0=0.0, precision="f32", pair_mode="paper", unfused=False, estimator="bispectrum",
-             shot_noise=False):
+             shot_noise=False, assign_tiles=False):
     """The C structs of a request. `n` and `box_len` are one value or three (per
     axis); `edges` (n_bins + 1 values) overrides k_min / dk. The returned tuple
     keeps the edges array alive."""
@@ -43,7 +43,7 @@ def _request(n, box_len, multipoles, n_bins, dk=1.0, k_min=0.0, edges=None, orig
     mps = [abi.tsb_multipole(*map(int, m)) for m in multipoles]
     opts = abi.tsb_options(abi.TSB_FP64 if precision == "f64" else abi.TSB_FP32, _PAIR[pair_mode],
                            int(bool(box_mode)), float(P0), int(unfused), _ESTIMATOR[estimator],
-                           int(bool(shot_noise)))
+                           int(bool(shot_noise)), int(assign_tiles))
     return grid, lo, bins, mps, opts, earr
 
 

@@ -61,7 +61,7 @@ class tsb_multipole(ctypes.Structure):
 class tsb_options(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int32), ("pair_mode", ctypes.c_int32), ("box_mode", ctypes.c_int32),
                 ("P0", ctypes.c_double), ("unfused", ctypes.c_int32), ("estimator", ctypes.c_int32),
-                ("shot_noise", ctypes.c_int32)]
+                ("shot_noise", ctypes.c_int32), ("assign_tiles", ctypes.c_int32)]
 
 
 class tsb_catalog(ctypes.Structure):
@@ -75,7 +75,7 @@ class tsb_plan_info(ctypes.Structure):
                 ("n_channels", ctypes.c_int32), ("n_fields_f", ctypes.c_int32), ("n_fields_g", ctypes.c_int32),
                 ("n_outputs", ctypes.c_int32), ("n_grids", ctypes.c_int32), ("n_fslots", ctypes.c_int32),
                 ("fused", ctypes.c_int32), ("n_terms", ctypes.c_int32), ("workspace_bytes", ctypes.c_int64),
-                ("reduce_flops", ctypes.c_int64)]
+                ("reduce_flops", ctypes.c_int64), ("assign_columns", ctypes.c_int32)]
 
 
 _P = ctypes.POINTER

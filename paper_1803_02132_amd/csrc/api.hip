@@ -119,7 +119,7 @@ int carve_workspace(Plan& P, Carver& cv, int64_t& B) {
   ALLOC(P.d_u2, std::max(std::max(nf * PFs * M * M, ng * PGs * M * M), nv * PGs * M * M) * c);
   ALLOC(P.d_fields, ((P.fused ? 0 : nf) + ng) * M * M * M * c);
   const int64_t ntiles = (int64_t)P.NT * P.NT * P.NT;
-  P.nbk = ntiles * 27;
+  P.nbk = assign_bucket_keys(P);
   ALLOC(P.d_bk_count, (2 * P.nbk + 2) * 4);   // counts, cursors, heavy-slot and extra-part counters
   P.d_bk_cursor = P.d_bk_count ? P.d_bk_count + P.nbk : nullptr;
   ALLOC(P.d_bk_start, (P.nbk + 1) * 4);
@@ -689,6 +689,8 @@ static int copy_request(Plan& P, const tsb_grid* grid, const tsb_los* los, const
   P.unfused = options->unfused;
   P.estimator = options->estimator;
   P.shot_noise = options->shot_noise;
+  if (options->assign_tiles < 0 || options->assign_tiles > 1) return fail(TSB_E_ARG, "assign_tiles must be 0 or 1");
+  P.assign_tiles = options->assign_tiles;
   return plan_build(P);
 }
 
@@ -712,6 +714,7 @@ static void fill_info(const Plan& P, tsb_plan_info* info) {
   fl += 3.0 * P.nb * (double)P.terms.size() * M3;
   if (P.fused) fl += (double)P.nb * P.fkinds.size() * P.M * P.M * 5.0 * P.M * std::log2((double)P.M);
   info->reduce_flops = (int64_t)fl;
+  info->assign_columns = P.zcol ? 1 : 0;
 }
 
 int tsb_request_query(const tsb_grid* grid, const tsb_los* los, const tsb_kbins* bins,
@@ -819,8 +822,11 @@ int tsb_assign(tsb_plan* plan, const tsb_catalog* data, const tsb_catalog* rando
   Plan& P = plan->p;
   hipStream_t s = (hipStream_t)stream;
   int rc;
-  if ((rc = run_front(P, data, randoms, s))) return rc;
-  if ((rc = run_assign_back(P, s))) return rc;
+  P.tiles_only = 1;   // the grids themselves: the tile assignment
+  rc = run_front(P, data, randoms, s);
+  if (!rc) rc = run_assign_back(P, s);
+  P.tiles_only = 0;
+  if (rc) return rc;
   if ((rc = run_unpack_grids(P, grids_out, s))) return rc;
   DevScalars h{};
   TSB_HIP(hipMemcpyAsync(&h, P.d_scal, sizeof(h), hipMemcpyDeviceToHost, s));
@@ -1150,6 +1156,7 @@ std::string request_key(const tsb_plan& t) {
   i32(t.opts.unfused);
   i32(t.opts.estimator);
   i32(t.opts.shot_noise);
+  i32(t.opts.assign_tiles);
   for (const tsb_multipole& m : t.mult) {
     i32(m.l1);
     i32(m.l2);

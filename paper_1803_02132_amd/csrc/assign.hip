@@ -24,6 +24,7 @@
 // plan-wide scale.
 #include <cmath>
 
+#include "fft_reg.h"
 #include "serve_policy.h"
 #include "tsb_internal.h"
 
@@ -204,6 +205,7 @@ struct BucketArgs {
   CatPtrs d, r;
   double inv_h, origin[3], P0;
   int N, T, NT, p, copies, box_mode;
+  int colmode;        // 1: keys of the (x, y) columns of the column assignment
   int* count;         // [nbk]
   int* cursor;        // [nbk]
   const int* start;   // [nbk + 1]
@@ -260,6 +262,33 @@ __device__ inline int bucket_key(const BucketArgs& a, const double* u) {
   return tile * kClasses + cls;
 }
 
+// Columns of the column assignment: kColW x kColW nodes in (x, y), all N in
+// z. A particle is bucketed by the column of its lowest stencil node (over
+// both grid copies) on each of x and y, and by how many columns up its
+// stencil reaches there (0, 1 or 2: a stencil spans at most four nodes).
+constexpr int kColW = 2;
+constexpr int kColClasses = 9;
+
+__device__ inline int column_key(const BucketArgs& a, const double* u) {
+  const int NC = a.N / kColW;
+  int col = 0, cls = 0;
+  for (int ax = 0; ax < 2; ++ax) {
+    int lo = 1 << 30, hi = -(1 << 30);
+    for (int g = 0; g < a.copies; ++g) {
+      double wt[3];
+      const int j0 = axis_stencil(u[ax] + 0.5 * g, a.p, wt);
+      lo = min(lo, j0);
+      hi = max(hi, j0 + a.p - 1);
+    }
+    int lw = lo % a.N;
+    if (lw < 0) lw += a.N;
+    const int hc = lw / kColW;
+    col = col * NC + hc;
+    cls = cls * 3 + (lw - hc * kColW + hi - lo) / kColW;
+  }
+  return col * kColClasses + cls;
+}
+
 // Wavefront runs of equal keys: lanes holding the same key in a row take one
 // atomic between them (catalogues are often stored in spatial order).
 __device__ inline int run_end(unsigned long long heads, int lane) {
@@ -281,7 +310,10 @@ __global__ void __launch_bounds__(kBlock) bucket_count_kernel(BucketArgs a) {
     if (i < ntot) {
       double u[3], w;
       bool ran;
-      key = particle_u(a, i, u, &w, &ran) ? bucket_key(a, u) : kClasses / 2;   // tile 0, middle class
+      if (a.colmode)
+        key = particle_u(a, i, u, &w, &ran) ? column_key(a, u) : 0;              // column 0, class 0
+      else
+        key = particle_u(a, i, u, &w, &ran) ? bucket_key(a, u) : kClasses / 2;   // tile 0, middle class
       a.keys[i] = key;
     }
     const int prev = __shfl_up(key, 1);
@@ -1203,6 +1235,170 @@ __global__ void __launch_bounds__(kBlock) tile_parts_kernel(TileArgs a, int ntil
   hslot[t] = hs;
 }
 
+// ----------------------------------------------------------------------------
+// column assignment with the z transform (box-mode FP32 plans)
+//
+// A workgroup owns one column (kColW x kColW nodes in x and y, every z). The
+// particles that reach it add their fixed-point contributions to the
+// column's words in LDS, both grid copies at once, two channels per 64-bit
+// word (as packed tiles do) at a scale of the column's own, from its visit
+// count (order-free, so the result is bitwise reproducible). Every z line of
+// the column is then transformed in LDS by the four-step scheme of the FFT
+// passes (Sec. 2 sign convention) and only the kept frequencies |n_z| <= R_G
+// are written, in the z pass's output layout: the assignment grids never
+// reach device memory.
+
+constexpr int kZBlock = 256;
+constexpr int kColMaxRanges = 16;
+constexpr int kZMaxGrids = 4;
+constexpr int kZMaxLines = 2 * kZMaxGrids * kColW * kColW;
+
+struct ZColArgs {
+  int N, NC, p, copies, ngrid, RG, PG, nlines;
+  int64_t PGs;                 // stored innermost extent of the output
+  double wmax;                 // largest node weight of the kernel
+  const int* start;            // bucket starts [NC^2 * 9 + 1]
+  const DevScalars* scal;
+  const float2* tw;            // e^{-2 pi i j / N}, j < N
+  float2* out;                 // [copies * ngrid][N][N][PGs]
+  // reads of one column: home column (cx - dx, cy - dy) and class range
+  int nr;
+  int rdx[kColMaxRanges], rdy[kColMaxRanges], rlo[kColMaxRanges], rhi[kColMaxRanges];
+};
+
+template <int N1, int N2>
+__global__ void __launch_bounds__(kZBlock) zcol_kernel(ZColArgs a, Records<float> rec) {
+  constexpr int N = N1 * N2;
+  constexpr int LS = N2 * (N1 + 1) + 1;                     // LDS line stride (odd)
+  constexpr int TPT = (kZMaxLines * N1 + kZBlock - 1) / kZBlock;   // step-A tasks per thread
+  extern __shared__ unsigned long long zacc[];              // [nlines][LS]
+  __shared__ int r_st[kColMaxRanges], r_off[kColMaxRanges + 1];
+  const int nb = a.NC * a.NC;
+  int col = blockIdx.x;
+  if (nb % 8 == 0) col = (col % 8) * (nb / 8) + col / 8;   // a band of neighbouring columns per XCD
+  const int cx = col / a.NC, cy = col - cx * a.NC;
+  const int x0 = cx * kColW, y0 = cy * kColW;
+  for (int i = threadIdx.x; i < a.nlines * LS; i += kZBlock) zacc[i] = 0ull;
+  if (threadIdx.x < a.nr) {
+    const int r = threadIdx.x;
+    const int hx = (cx - a.rdx[r] + a.NC) % a.NC, hy = (cy - a.rdy[r] + a.NC) % a.NC;
+    const int key = (hx * a.NC + hy) * kColClasses;
+    const int st = a.start[key + a.rlo[r]];
+    r_st[r] = st;
+    r_off[r + 1] = a.start[key + a.rhi[r]] - st;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    r_off[0] = 0;
+    for (int r = 0; r < a.nr; ++r) r_off[r + 1] += r_off[r];
+  }
+  __syncthreads();
+  const int nv = r_off[a.nr];
+  const int et = tile_exponent(nv, a.scal->cmax * a.wmax);
+  const float tscale = ldexpf(1.0f, et);
+  const int lg = kColW * kColW * LS;   // words between the lines of consecutive grids
+  for (int v = threadIdx.x; v < nv; v += kZBlock) {
+    int r = 0;
+    while (r + 1 < a.nr && r_off[r + 1] <= v) ++r;
+    const int64_t slot = (int64_t)r_st[r] + (v - r_off[r]);
+    const double* ru = rec.u(slot);
+    const double u[3] = {ru[0], ru[1], ru[2]};
+    if (!isfinite(u[0])) continue;
+    const float* rc = rec.c(slot);
+    float c[2 * kZMaxGrids];
+#pragma unroll
+    for (int k = 0; k < 2 * kZMaxGrids; ++k) c[k] = k < 2 * a.ngrid ? rc[k] : 0.0f;
+    for (int g = 0; g < a.copies; ++g) {
+      int j[3];
+      float w[3][3];
+#pragma unroll
+      for (int ax = 0; ax < 3; ++ax) stencil_weights<float>(a.p, (float)stencil_param(u[ax] + 0.5 * g, a.p, &j[ax]), w[ax]);
+      for (int sx = 0; sx < a.p; ++sx) {
+        int ix = j[0] + sx;
+        ix += ix < 0 ? N : (ix >= N ? -N : 0);
+        const int lx = ix - x0;
+        if (lx < 0 || lx >= kColW) continue;
+        const float wxs = pick3(w[0], sx) * tscale;   // the column scale folded into the x weight
+        for (int sy = 0; sy < a.p; ++sy) {
+          int iy = j[1] + sy;
+          iy += iy < 0 ? N : (iy >= N ? -N : 0);
+          const int ly = iy - y0;
+          if (ly < 0 || ly >= kColW) continue;
+          const float wxy = wxs * pick3(w[1], sy);
+          unsigned long long* line = zacc + (size_t)((g * a.ngrid * kColW + lx) * kColW + ly) * LS;
+          for (int sz = 0; sz < a.p; ++sz) {
+            int iz = j[2] + sz;
+            iz += iz < 0 ? N : (iz >= N ? -N : 0);
+            const float W = wxy * pick3(w[2], sz);
+#pragma unroll
+            for (int k = 0; k < kZMaxGrids; ++k) {
+              if (k >= a.ngrid) break;
+              atomicAdd(line + (size_t)k * lg + iz, pack2(__float2int_rn(c[2 * k] * W), __float2int_rn(c[2 * k + 1] * W)));
+            }
+          }
+        }
+      }
+    }
+  }
+  __syncthreads();
+
+  // step A: N2-point transforms of the strided subsequences of each line
+  // (words converted on load), twiddled; written back transposed once every
+  // thread holds its tasks in registers
+  float2 vv[TPT][N2];
+  const int ntA = a.nlines * N1;
+#pragma unroll
+  for (int q = 0; q < TPT; ++q) {
+    const int t = threadIdx.x + q * kZBlock;
+    if (t < ntA) {
+      const int jl = t / N1, n1 = t - jl * N1;
+      const unsigned long long* line = zacc + (size_t)jl * LS;
+#pragma unroll
+      for (int n2 = 0; n2 < N2; ++n2) {
+        int lo, hi;
+        unpack2(line[n1 + N1 * n2], &lo, &hi);
+        vv[q][n2] = make_float2(ldexpf((float)lo, -et), ldexpf((float)hi, -et));
+      }
+      reg_fft<float, float2, N2>(vv[q], -1);
+    }
+  }
+  __syncthreads();
+  float2* lds = (float2*)zacc;
+#pragma unroll
+  for (int q = 0; q < TPT; ++q) {
+    const int t = threadIdx.x + q * kZBlock;
+    if (t < ntA) {
+      const int jl = t / N1, n1 = t - jl * N1;
+      float2* line = lds + (size_t)jl * LS;
+#pragma unroll
+      for (int i = 0; i < N2; ++i) {
+        const int k2 = bit_reverse<N2>(i);
+        const float2 tw = a.tw[(n1 * k2) % N];
+        line[k2 * (N1 + 1) + n1] = make_float2(vv[q][i].x * tw.x - vv[q][i].y * tw.y, vv[q][i].x * tw.y + vv[q][i].y * tw.x);
+      }
+    }
+  }
+  __syncthreads();
+
+  // step C: N1-point transforms across n1; kept frequencies only
+  for (int t = threadIdx.x; t < a.nlines * N2; t += kZBlock) {
+    const int jl = t / N2, k2 = t - jl * N2;
+    const float2* line = lds + (size_t)jl * LS + k2 * (N1 + 1);
+    float2 uu[N1];
+#pragma unroll
+    for (int n1 = 0; n1 < N1; ++n1) uu[n1] = line[n1];
+    reg_fft<float, float2, N1>(uu, -1);
+    const int ly = jl % kColW, lx = (jl / kColW) % kColW, b = jl / (kColW * kColW);   // b = copy * ngrid + grid
+    float2* ob = a.out + ((int64_t)b * N + (x0 + lx)) * N * a.PGs + (int64_t)(y0 + ly) * a.PGs;
+#pragma unroll
+    for (int i = 0; i < N1; ++i) {
+      int e = k2 + N2 * bit_reverse<N1>(i) + a.RG;   // stored entry of frequency k (n = e - R_G)
+      if (e >= N) e -= N;
+      if (e < a.PG) ob[e] = uu[i];
+    }
+  }
+}
+
 // y_L^M*(x^_node) on both grid copies in the complex-grid layout of the
 // assignment output; transformed once per plan, it carries the box-mode mean
 // subtraction into spectrum space.
@@ -1533,6 +1729,105 @@ int assign_back_impl(Plan& P, const ChanInfo& ci, hipStream_t s) {
   return TSB_OK;
 }
 
+// Reads of one column: home columns (cx - dx, cy - dy), dx, dy in 0..2, and
+// the classes whose stencils reach at least dx columns up on x and dy on y,
+// as contiguous class ranges (15 of them).
+static int column_ranges(int* rdx, int* rdy, int* rlo, int* rhi) {
+  int nr = 0;
+  for (int dx = 0; dx <= 2; ++dx)
+    for (int dy = 0; dy <= 2; ++dy)
+      for (int rx = dx; rx <= 2; ++rx) {
+        const int lo = rx * 3 + dy, hi = rx * 3 + 3;
+        if (nr > 0 && rdx[nr - 1] == dx && rdy[nr - 1] == dy && rhi[nr - 1] == lo) {
+          rhi[nr - 1] = hi;   // extends the previous range
+          continue;
+        }
+        rdx[nr] = dx;
+        rdy[nr] = dy;
+        rlo[nr] = lo;
+        rhi[nr] = hi;
+        ++nr;
+      }
+  return nr;
+}
+
+static int zcol_lines(const Plan& P) { return P.copies * (int)P.grids.size() * kColW * kColW; }
+
+static bool zcol_split(int N, int* n1, int* n2) {
+  switch (N) {
+    case 32: *n1 = 4; *n2 = 8; return true;
+    case 64: *n1 = 8; *n2 = 8; return true;
+    case 128: *n1 = 8; *n2 = 16; return true;
+    case 256: *n1 = 16; *n2 = 16; return true;
+    default: return false;
+  }
+}
+
+int64_t zcol_lds_bytes(const Plan& P) {
+  int n1 = 0, n2 = 0;
+  if (!zcol_split(P.N, &n1, &n2)) return 0;
+  return (int64_t)zcol_lines(P) * (n2 * (n1 + 1) + 1) * 8;
+}
+
+// Box-mode FP32 plans on a power-of-two grid of 32 to 256 points with at
+// most four complex grids per copy.
+bool zcol_applies(const Plan& P) {
+  int n1 = 0, n2 = 0;
+  if (P.precision != TSB_FP32 || !P.box_mode || !zcol_split(P.N, &n1, &n2)) return false;
+  if ((int)P.grids.size() > kZMaxGrids || record_slots(P) != 2 * (int)P.grids.size()) return false;
+  return zcol_lds_bytes(P) <= 96 * 1024;
+}
+
+// Bucket keys of the plan's assignment: the tiles' (tile, class) keys, or the
+// columns' (column, class) keys if more.
+int64_t assign_bucket_keys(const Plan& P) {
+  const int64_t tiles = (int64_t)P.NT * P.NT * P.NT * kClasses;
+  const int64_t NC = P.N / kColW;
+  return P.zcol ? std::max(tiles, NC * NC * kColClasses) : tiles;
+}
+
+template <int N1, int N2>
+static int launch_zcol(Plan& P, hipStream_t s) {
+  ZColArgs a{};
+  a.N = P.N;
+  a.NC = P.N / kColW;
+  a.p = P.p;
+  a.copies = P.copies;
+  a.ngrid = (int)P.grids.size();
+  a.RG = P.RG;
+  a.PG = P.PG;
+  a.nlines = zcol_lines(P);
+  a.PGs = pad_line(P.PG);
+  a.wmax = P.p == 3 ? 0.421875 : 1.0;
+  a.start = P.d_bk_start;
+  a.scal = pass_scalars(P);
+  a.tw = (const float2*)P.d_tw_n;
+  a.out = (float2*)P.d_t1;
+  a.nr = column_ranges(a.rdx, a.rdy, a.rlo, a.rhi);
+  if (a.nr > kColMaxRanges || a.nlines > kZMaxLines) return fail(TSB_E_UNSUPPORTED, "column assignment: bad shape");
+  Records<float> rec;
+  rec.cap = P.particle_cap;
+  rec.base = (char*)P.d_rec;
+  rec.stride = record_stride(P);
+  const size_t lds = (size_t)zcol_lds_bytes(P);
+  prof_begin(P, kStAssign, s);
+  hipLaunchKernelGGL((zcol_kernel<N1, N2>), dim3(a.NC * a.NC), dim3(kZBlock), lds, s, a, rec);
+  prof_end(P, kStAssign, s);
+  TSB_HIP(hipGetLastError());
+  P.zcol_pass = 1;   // the forward transform starts at the y pass
+  return TSB_OK;
+}
+
+static int run_zcol(Plan& P, hipStream_t s) {
+  switch (P.N) {
+    case 32: return launch_zcol<4, 8>(P, s);
+    case 64: return launch_zcol<8, 8>(P, s);
+    case 128: return launch_zcol<8, 16>(P, s);
+    case 256: return launch_zcol<16, 16>(P, s);
+    default: return fail(TSB_E_UNSUPPORTED, "column assignment: unsupported grid");
+  }
+}
+
 int run_assign(Plan& P, const tsb_catalog* data, const tsb_catalog* rand, hipStream_t s) {
   BucketArgs b{};
   b.d = cat_ptrs(P, data);
@@ -1550,13 +1845,14 @@ int run_assign(Plan& P, const tsb_catalog* data, const tsb_catalog* rand, hipStr
   b.cursor = P.d_bk_cursor;
   b.start = P.d_bk_start;
   b.keys = P.d_keys;
+  b.colmode = zcol_active(P) ? 1 : 0;
   const int64_t ntot = b.d.n + b.r.n;
-  const int64_t nbk = P.nbk;
+  const int64_t nbk = b.colmode ? (int64_t)(P.N / kColW) * (P.N / kColW) * kColClasses : P.nbk;
   const int nparts = (int)((nbk + kScanChunk - 1) / kScanChunk);
   prof_begin(P, kStBucket, s);
   // counts, cursors and the heavy-slot counter are adjacent: one fill clears them
-  hipLaunchKernelGGL(zero_ints_kernel, dim3(grid_blocks(2 * nbk + 2)), dim3(kBlock), 0, s, P.d_bk_count,
-                     2 * nbk + 2);
+  hipLaunchKernelGGL(zero_ints_kernel, dim3(grid_blocks(2 * P.nbk + 2)), dim3(kBlock), 0, s, P.d_bk_count,
+                     2 * P.nbk + 2);
   if (ntot > 0)
     hipLaunchKernelGGL(bucket_count_kernel, dim3(grid_blocks(ntot)), dim3(kBlock), 0, s, b);
   hipLaunchKernelGGL(scan_sums_kernel, dim3(nparts), dim3(kBlock), 0, s, (const int*)P.d_bk_count, nbk,
@@ -1578,6 +1874,7 @@ int run_assign(Plan& P, const tsb_catalog* data, const tsb_catalog* rand, hipStr
 }
 
 int run_assign_back(Plan& P, hipStream_t s) {
+  if (zcol_active(P)) return run_zcol(P, s);
   ChanInfo ci;
   if (int rc = chan_info(P, &ci)) return rc;
   const int nreg = record_slots(P);

@@ -809,8 +809,11 @@ int forward_impl(Plan& P, hipStream_t s) {
     a.so_b = ob;
     a.so_e = oe;
   };
-  // z (contiguous): [nbc][N][N][N] -> [nbc][N][N][PG]
-  {
+  // z (contiguous): [nbc][N][N][N] -> [nbc][N][N][PG], unless the column
+  // assignment has just written its output
+  const bool zdone = P.zcol_pass != 0;
+  P.zcol_pass = 0;
+  if (!zdone) {
     PassArgs<T> a{};
     a.in = (const T2*)P.d_grid;
     a.out = (T2*)P.d_t1;

@@ -492,6 +492,7 @@ int plan_build(Plan& P) {
   for (auto& q : P.qgroups)
     if (P.f2idx[q.f2] < 0) P.f2idx[q.f2] = P.nf2++;
   plan_fused(P);
+  P.zcol = !P.assign_tiles && zcol_applies(P);
   if (P.fused && !P.fused_wide) P.red_wg = (int)std::min<int64_t>((int64_t)P.M * P.M, 1024);
   // unfused FP32 plans with at most 32 shells: the sum over a chunk's cells on
   // the matrix cores (32 x 32 tiles, k steps of 8 cells), up to 16 Q groups

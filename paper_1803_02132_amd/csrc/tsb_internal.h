@@ -146,6 +146,10 @@ struct Plan {
   DevScalars* d_scal = nullptr;
   // shot noise (Sec. 4.2, eqs. 44-46)
   int wpass = 0;                // 1 while the w^2-weighted fields N are assigned and transformed
+  int assign_tiles = 0;         // request: 1 keeps the tile assignment (no column assignment)
+  int zcol = 0;                 // measurements assign by columns, with the z transform
+  int tiles_only = 0;           // 1 while the assignment grids themselves are wanted
+  int zcol_pass = 0;            // set by the column assignment: the next forward transform skips its z pass
   int spass = 0;                // 1 while the i = j != k term runs the inverse transforms and reduction
   DevScalars* d_scal_n = nullptr;   // scalars of the w^2 pass
   void* d_nspec = nullptr;      // combined spectra of the N channels [ngrid][PG^3]
@@ -288,6 +292,12 @@ void plan_fused(Plan& P);                   // fused.hip
 int run_fused(Plan& P, hipStream_t s);
 int run_ynode_fill(Plan& P, hipStream_t s);
 int run_assign_back(Plan& P, hipStream_t s);
+bool zcol_applies(const Plan& P);      // the plan can assign by columns with the z transform
+int64_t zcol_lds_bytes(const Plan& P);
+int64_t assign_bucket_keys(const Plan& P);
+// a measurement's assignment runs by columns (not for the w^2 fields of the
+// shot noise, nor when the grids themselves are returned)
+inline bool zcol_active(const Plan& P) { return P.zcol && !P.wpass && !P.tiles_only; }
 int64_t assign_work_cap(const Plan& P, int64_t particles);
 int assign_part_visits();   // visits per assignment work item
 int record_stride(const Plan& P);

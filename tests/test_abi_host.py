@@ -95,6 +95,25 @@ def test_reduction_path_rule():
     assert e.value.code == tsb.abi.TSB_E_ARG
 
 
+def test_column_assignment_rule():
+    # box FP32 plans on 32..256 grids with up to four complex grids per copy
+    # assign by columns with the z transform; FP64, survey, other sizes and
+    # assign_tiles keep the tile assignment
+    assert tsb.query(**req(n=64))[0].assign_columns == 1
+    assert tsb.query(**req(n=256, n_bins=20, dk=0.01))[0].assign_columns == 1
+    assert tsb.query(**req(n=32, los="global", interlace=False, assign_p=1))[0].assign_columns == 1
+    assert tsb.query(**req(n=64, precision="f64"))[0].assign_columns == 0
+    assert tsb.query(**req(n=64, box_mode=False, P0=1e4))[0].assign_columns == 0
+    assert tsb.query(**req(n=48))[0].assign_columns == 0
+    assert tsb.query(**req(n=512, box_len=3500.0, n_bins=11, dk=0.02))[0].assign_columns == 0
+    assert tsb.query(**req(n=64, assign_tiles=True))[0].assign_columns == 0
+    # {000, 202, 404} with a local LOS: 15 channels, 8 grids per copy
+    assert tsb.query(**req(n=64, multipoles=[(0, 0, 0), (2, 0, 2), (4, 0, 4)]))[0].assign_columns == 0
+    with pytest.raises(tsb.TsbError) as e:
+        tsb.query(**req(assign_tiles=2))
+    assert e.value.code == tsb.abi.TSB_E_ARG
+
+
 def test_channel_and_field_counts():
     # local LOS {000, 202}: channels (0,0), (2,0), (2,1)re/im, (2,2)re/im
     info, _, _ = tsb.query(**req())
