@@ -1278,7 +1278,8 @@ __global__ void __launch_bounds__(kZBlock) zcol_kernel(ZColArgs a, Records<float
   if (nb % 8 == 0) col = (col % 8) * (nb / 8) + col / 8;   // a band of neighbouring columns per XCD
   const int cx = col / a.NC, cy = col - cx * a.NC;
   const int x0 = cx * kColW, y0 = cy * kColW;
-  for (int i = threadIdx.x; i < a.nlines * LS; i += kZBlock) zacc[i] = 0ull;
+  for (int i = threadIdx.x; i < a.nlines * LS / 2; i += kZBlock)   // nlines is a multiple of 4
+    reinterpret_cast<ulonglong2*>(zacc)[i] = make_ulonglong2(0ull, 0ull);
   if (threadIdx.x < a.nr) {
     const int r = threadIdx.x;
     const int hx = (cx - a.rdx[r] + a.NC) % a.NC, hy = (cy - a.rdy[r] + a.NC) % a.NC;
@@ -1297,8 +1298,8 @@ __global__ void __launch_bounds__(kZBlock) zcol_kernel(ZColArgs a, Records<float
   const int et = tile_exponent(nv, a.scal->cmax * a.wmax);
   const float tscale = ldexpf(1.0f, et);
   const int lg = kColW * kColW * LS;   // words between the lines of consecutive grids
+  int r = 0;   // the range holding visit v (v only grows)
   for (int v = threadIdx.x; v < nv; v += kZBlock) {
-    int r = 0;
     while (r + 1 < a.nr && r_off[r + 1] <= v) ++r;
     const int64_t slot = (int64_t)r_st[r] + (v - r_off[r]);
     const double* ru = rec.u(slot);
@@ -1313,17 +1314,18 @@ __global__ void __launch_bounds__(kZBlock) zcol_kernel(ZColArgs a, Records<float
       float w[3][3];
 #pragma unroll
       for (int ax = 0; ax < 3; ++ax) stencil_weights<float>(a.p, (float)stencil_param(u[ax] + 0.5 * g, a.p, &j[ax]), w[ax]);
-      for (int sx = 0; sx < a.p; ++sx) {
-        int ix = j[0] + sx;
-        ix += ix < 0 ? N : (ix >= N ? -N : 0);
-        const int lx = ix - x0;
-        if (lx < 0 || lx >= kColW) continue;
+      // the stencil nodes inside the column are consecutive: node j + s sits at
+      // column-local index d + s, with d = j - (column start) taken periodically
+      // into [-N/2, N/2); the loops run over those nodes only
+      int dx = j[0] - x0, dy = j[1] - y0;
+      dx += dx < -N / 2 ? N : (dx >= N / 2 ? -N : 0);
+      dy += dy < -N / 2 ? N : (dy >= N / 2 ? -N : 0);
+      const int sx1 = min(a.p, kColW - dx), sy0 = max(0, -dy), sy1 = min(a.p, kColW - dy);
+      for (int sx = max(0, -dx); sx < sx1; ++sx) {
+        const int lx = dx + sx;
         const float wxs = pick3(w[0], sx) * tscale;   // the column scale folded into the x weight
-        for (int sy = 0; sy < a.p; ++sy) {
-          int iy = j[1] + sy;
-          iy += iy < 0 ? N : (iy >= N ? -N : 0);
-          const int ly = iy - y0;
-          if (ly < 0 || ly >= kColW) continue;
+        for (int sy = sy0; sy < sy1; ++sy) {
+          const int ly = dy + sy;
           const float wxy = wxs * pick3(w[1], sy);
           unsigned long long* line = zacc + (size_t)((g * a.ngrid * kColW + lx) * kColW + ly) * LS;
           for (int sz = 0; sz < a.p; ++sz) {

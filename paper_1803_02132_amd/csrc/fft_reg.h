@@ -7,8 +7,10 @@
 namespace tsb {
 namespace {
 
-// e^{-2 pi i j/32}, j < 32: twiddles of the in-register transforms (R <= 32)
-static __constant__ double kW32[32][2] = {
+// e^{-2 pi i j/32}, j < 32: twiddles of the in-register transforms (R <= 32).
+// constexpr: with the unrolled loops every index is a constant, so each
+// twiddle becomes an immediate operand of the working precision.
+constexpr double kW32[32][2] = {
     {1.0, -0.0}, {0.98078528040323043, -0.19509032201612825}, {0.92387953251128674, -0.38268343236508978},
     {0.83146961230254524, -0.55557023301960218}, {0.70710678118654757, -0.70710678118654746},
     {0.55557023301960229, -0.83146961230254524}, {0.38268343236508984, -0.92387953251128674},
