@@ -1270,7 +1270,7 @@ template <int N1, int N2>
 __global__ void __launch_bounds__(kZBlock) zcol_kernel(ZColArgs a, Records<float> rec) {
   constexpr int N = N1 * N2;
   constexpr int LS = N2 * (N1 + 1) + 1;                     // LDS line stride (odd)
-  constexpr int TPT = (kZMaxLines * N1 + kZBlock - 1) / kZBlock;   // step-A tasks per thread
+  static_assert(64 % N1 == 0, "a line's step-A tasks share a wavefront");
   extern __shared__ unsigned long long zacc[];              // [nlines][LS]
   __shared__ int r_st[kColMaxRanges], r_off[kColMaxRanges + 1];
   const int nb = a.NC * a.NC;
@@ -1278,15 +1278,19 @@ __global__ void __launch_bounds__(kZBlock) zcol_kernel(ZColArgs a, Records<float
   if (nb % 8 == 0) col = (col % 8) * (nb / 8) + col / 8;   // a band of neighbouring columns per XCD
   const int cx = col / a.NC, cy = col - cx * a.NC;
   const int x0 = cx * kColW, y0 = cy * kColW;
-  for (int i = threadIdx.x; i < a.nlines * LS / 2; i += kZBlock)   // nlines is a multiple of 4
-    reinterpret_cast<ulonglong2*>(zacc)[i] = make_ulonglong2(0ull, 0ull);
-  if (threadIdx.x < a.nr) {
+  int st = 0, en = 0;
+  if (threadIdx.x < a.nr) {   // the column's bucket ranges, in flight while the words are cleared
     const int r = threadIdx.x;
     const int hx = (cx - a.rdx[r] + a.NC) % a.NC, hy = (cy - a.rdy[r] + a.NC) % a.NC;
     const int key = (hx * a.NC + hy) * kColClasses;
-    const int st = a.start[key + a.rlo[r]];
-    r_st[r] = st;
-    r_off[r + 1] = a.start[key + a.rhi[r]] - st;
+    st = a.start[key + a.rlo[r]];
+    en = a.start[key + a.rhi[r]];
+  }
+  for (int i = threadIdx.x; i < a.nlines * LS / 2; i += kZBlock)   // nlines is a multiple of 4
+    reinterpret_cast<ulonglong2*>(zacc)[i] = make_ulonglong2(0ull, 0ull);
+  if (threadIdx.x < a.nr) {
+    r_st[threadIdx.x] = st;
+    r_off[threadIdx.x + 1] = en - st;
   }
   __syncthreads();
   if (threadIdx.x == 0) {
@@ -1345,39 +1349,28 @@ __global__ void __launch_bounds__(kZBlock) zcol_kernel(ZColArgs a, Records<float
   __syncthreads();
 
   // step A: N2-point transforms of the strided subsequences of each line
-  // (words converted on load), twiddled; written back transposed once every
-  // thread holds its tasks in registers
-  float2 vv[TPT][N2];
-  const int ntA = a.nlines * N1;
-#pragma unroll
-  for (int q = 0; q < TPT; ++q) {
-    const int t = threadIdx.x + q * kZBlock;
-    if (t < ntA) {
-      const int jl = t / N1, n1 = t - jl * N1;
-      const unsigned long long* line = zacc + (size_t)jl * LS;
-#pragma unroll
-      for (int n2 = 0; n2 < N2; ++n2) {
-        int lo, hi;
-        unpack2(line[n1 + N1 * n2], &lo, &hi);
-        vv[q][n2] = make_float2(ldexpf((float)lo, -et), ldexpf((float)hi, -et));
-      }
-      reg_fft<float, float2, N2>(vv[q], -1);
-    }
-  }
-  __syncthreads();
+  // (words converted on load), twiddled and written back transposed. The N1
+  // tasks of a line are consecutive lanes of one wavefront (N1 divides 64),
+  // whose reads of the line all precede its writes: no barrier inside.
   float2* lds = (float2*)zacc;
+#pragma unroll 1
+  for (int t = threadIdx.x; t < a.nlines * N1; t += kZBlock) {
+    const int jl = t / N1, n1 = t - jl * N1;
+    float2 vv[N2];
+    const unsigned long long* wline = zacc + (size_t)jl * LS;
 #pragma unroll
-  for (int q = 0; q < TPT; ++q) {
-    const int t = threadIdx.x + q * kZBlock;
-    if (t < ntA) {
-      const int jl = t / N1, n1 = t - jl * N1;
-      float2* line = lds + (size_t)jl * LS;
+    for (int n2 = 0; n2 < N2; ++n2) {
+      int lo, hi;
+      unpack2(wline[n1 + N1 * n2], &lo, &hi);
+      vv[n2] = make_float2(ldexpf((float)lo, -et), ldexpf((float)hi, -et));
+    }
+    reg_fft<float, float2, N2>(vv, -1);
+    float2* line = lds + (size_t)jl * LS;
 #pragma unroll
-      for (int i = 0; i < N2; ++i) {
-        const int k2 = bit_reverse<N2>(i);
-        const float2 tw = a.tw[(n1 * k2) % N];
-        line[k2 * (N1 + 1) + n1] = make_float2(vv[q][i].x * tw.x - vv[q][i].y * tw.y, vv[q][i].x * tw.y + vv[q][i].y * tw.x);
-      }
+    for (int i = 0; i < N2; ++i) {
+      const int k2 = bit_reverse<N2>(i);
+      const float2 tw = a.tw[(n1 * k2) % N];
+      line[k2 * (N1 + 1) + n1] = make_float2(vv[i].x * tw.x - vv[i].y * tw.y, vv[i].x * tw.y + vv[i].y * tw.x);
     }
   }
   __syncthreads();
