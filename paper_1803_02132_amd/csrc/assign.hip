@@ -1302,17 +1302,36 @@ __global__ void __launch_bounds__(kZBlock) zcol_kernel(ZColArgs a, Records<float
   const int et = tile_exponent(nv, a.scal->cmax * a.wmax);
   const float tscale = ldexpf(1.0f, et);
   const int lg = kColW * kColW * LS;   // words between the lines of consecutive grids
-  int r = 0;   // the range holding visit v (v only grows)
-  for (int v = threadIdx.x; v < nv; v += kZBlock) {
-    while (r + 1 < a.nr && r_off[r + 1] <= v) ++r;
+  // visits in a scrambled order (a multiplier prime to their number): the
+  // lanes of a wavefront take particles far apart in the bucket order, which
+  // follows the catalogue's, so that their atomics rarely share a word
+  const int vmult = nv % 97 ? 97 : (nv % 101 ? 101 : (nv % 103 ? 103 : 1));
+  // a thread's next visit is loaded while the current one is added
+  auto load_visit = [&](int v0, double* u, float* c) {
+    const int v = (int)(((int64_t)v0 * vmult) % nv);
+    int r = 0;   // the range holding visit v: r_off[r] <= v < r_off[r + 1]
+    for (int step = 8; step > 0; step >>= 1)
+      if (r + step < a.nr && r_off[r + step] <= v) r += step;
     const int64_t slot = (int64_t)r_st[r] + (v - r_off[r]);
     const double* ru = rec.u(slot);
-    const double u[3] = {ru[0], ru[1], ru[2]};
-    if (!isfinite(u[0])) continue;
+    u[0] = ru[0];
+    u[1] = ru[1];
+    u[2] = ru[2];
     const float* rc = rec.c(slot);
-    float c[2 * kZMaxGrids];
 #pragma unroll
     for (int k = 0; k < 2 * kZMaxGrids; ++k) c[k] = k < 2 * a.ngrid ? rc[k] : 0.0f;
+  };
+  double nu[3] = {NAN, 0.0, 0.0};
+  float nc[2 * kZMaxGrids];
+  if (threadIdx.x < nv) load_visit(threadIdx.x, nu, nc);
+#pragma unroll 1
+  for (int v0 = threadIdx.x; v0 < nv; v0 += kZBlock) {
+    const double u[3] = {nu[0], nu[1], nu[2]};
+    float c[2 * kZMaxGrids];
+#pragma unroll
+    for (int k = 0; k < 2 * kZMaxGrids; ++k) c[k] = nc[k];
+    if (v0 + kZBlock < nv) load_visit(v0 + kZBlock, nu, nc);
+    if (!isfinite(u[0])) continue;
     for (int g = 0; g < a.copies; ++g) {
       int j[3];
       float w[3][3];
