@@ -244,7 +244,8 @@ def ingest_pmc(fetch_csv, write_csv, command, workload="box256"):
     print("\n".join(lines))
 
 
-SQ_KERNELS = (("assign_tile_kernel", "assign"), ("fz_reduce_wide_kernel", "reduce (one pass)"),
+SQ_KERNELS = (("zcol_kernel", "assign by columns + z pass"), ("assign_tile_kernel", "assign"),
+              ("fz_reduce_wide_kernel", "reduce (one pass)"),
               ("fz_reduce_kernel", "reduce (one pass, general)"), ("reduce_mfma_wide_kernel", "reduce (matrix cores)"),
               ("fft4_combine_kernel", "fwd_x + combination"), ("fft4_kernel", "FFT passes"),
               ("bucket_fill_kernel", "bucket fill"))
