@@ -167,7 +167,9 @@ typedef struct {
  * distance to the two neighbouring FP32 values, so that the many particles
  * sharing an n-bar share no rounding error); assignment contributions are
  * rounded to 64-bit fixed point (exact integer sums; survey plans round the
- * per-tile packed sums the same unbiased way, deterministically); every grid, spectrum and field is FP32 (the interlace
+ * per-tile packed sums the same unbiased way, deterministically; column plans
+ * pack at a scale of each column's own, whose step grows with the column's
+ * visit count); every grid, spectrum and field is FP32 (the interlace
  * combination and the W_mass division compute in FP64). The fused reduction
  * forms each Q row (a 3j-weighted sum of F G products, coefficients rounded to
  * FP32) and multiplies it with the right factor in FP32, summing the products
