@@ -603,27 +603,43 @@ __global__ void __launch_bounds__(kBlock) fft4_combine_kernel(PassArgs<T> a) {
   const bool has_task = tid < nl * N2;
   const int k2 = tid / nl, j = tid - (tid / nl) * nl;   // this thread's step-C task
   T2 u[N1], u2[N1];
-  for (int c = 0; c < nc; ++c) {
+  // step-A task of this thread (lpw N1 <= lpw N2 <= kBlock: at most one). For
+  // lines of up to 256 points the inputs of both copies are loaded at once, so
+  // the second copy's loads are in flight while the first copy is transformed
+  // (longer lines would hold too many registers).
+  constexpr bool kBoth = N2 <= 16;
+  const bool has_a = tid < nl * N1;
+  const int n1a = tid / nl, jja = tid - (tid / nl) * nl;
+  auto load_a = [&](int c, T2 (&v)[N2]) {
+    const T2* src = a.in + (int64_t)g * a.in_bs + (int64_t)c * a.cb_copy_bs + (int64_t)ia * a.in_sa +
+                    (int64_t)(b0 + jja) * a.in_sb;
+#pragma unroll
+    for (int n2 = 0; n2 < N2; ++n2) v[n2] = src[(int64_t)(n1a + N1 * n2) * a.in_se];
+  };
+  T2 va[kBoth ? 2 : 1][N2];
+  if (kBoth && has_a) {
+    load_a(0, va[0]);
+    if (nc == 2) load_a(1, va[kBoth ? 1 : 0]);
+  }
+#pragma unroll
+  for (int c = 0; c < 2; ++c) {
+    if (c >= nc) break;
     if (c) __syncthreads();   // the first copy's step C has read the LDS
     // ---- step A: N2-point transforms of the copy's lines ---------------------
-    const T2* inb = a.in + (int64_t)g * a.in_bs + (int64_t)c * a.cb_copy_bs + (int64_t)ia * a.in_sa;
-    for (int task = tid; task < nl * N1; task += kBlock) {
-      const int n1 = task / nl, jj = task - n1 * nl;
-      const T2* src = inb + (int64_t)(b0 + jj) * a.in_sb;
-      T2 v[N2];
-#pragma unroll
-      for (int n2 = 0; n2 < N2; ++n2) v[n2] = src[(int64_t)(n1 + N1 * n2) * a.in_se];
+    if (has_a) {
+      T2 (&v)[N2] = va[kBoth ? c : 0];
+      if (!kBoth) load_a(c, v);
       reg_fft<T, T2, N2>(v, a.dir);
-      T2* line = lds + jj * LS;
+      T2* line = lds + jja * LS;
 #pragma unroll
       for (int i = 0; i < N2; ++i) {
         const int kk = bit_reverse<N2>(i);
-        T2 w = a.tw[(n1 * kk) % N];
+        T2 w = a.tw[(n1a * kk) % N];
         if (a.dir > 0) w.y = -w.y;
         T2 o;
         o.x = v[i].x * w.x - v[i].y * w.y;
         o.y = v[i].x * w.y + v[i].y * w.x;
-        line[kk * (N1 + 1) + n1] = o;
+        line[kk * (N1 + 1) + n1a] = o;
       }
     }
     __syncthreads();
