@@ -207,9 +207,8 @@ struct BucketArgs {
   int N, T, NT, p, copies, box_mode;
   int colmode;        // 1: keys of the (x, y) columns of the column assignment
   int* count;         // [nbk]
-  int* cursor;        // [nbk]
   const int* start;   // [nbk + 1]
-  int* keys;          // [particles]
+  int* keys;          // [particles] offset of each particle inside its bucket
 };
 
 // Grid coordinate (wrapped into [0, N) in box mode) and weight of particle i
@@ -301,25 +300,31 @@ __device__ inline int run_head(unsigned long long heads, int lane) {
   return 63 - __clzll((long long)(heads & upto));
 }
 
+// Bucket key of particle i (one that takes no part goes to a fixed bucket).
+__device__ inline int particle_key(const BucketArgs& a, int64_t i) {
+  double u[3], w;
+  bool ran;
+  if (a.colmode) return particle_u(a, i, u, &w, &ran) ? column_key(a, u) : 0;   // column 0, class 0
+  return particle_u(a, i, u, &w, &ran) ? bucket_key(a, u) : kClasses / 2;       // tile 0, middle class
+}
+
+// Counts per bucket; each particle keeps its offset inside its bucket (in
+// keys[]), so the fill needs no atomics: a run of equal keys in a wavefront
+// takes one atomic, whose old value its lanes extend.
 __global__ void __launch_bounds__(kBlock) bucket_count_kernel(BucketArgs a) {
   const int64_t ntot = a.d.n + a.r.n;
   const int lane = threadIdx.x & 63;
   for (int64_t base = (int64_t)blockIdx.x * kBlock; base < ntot; base += (int64_t)gridDim.x * kBlock) {
     const int64_t i = base + threadIdx.x;
-    int key = -1;
-    if (i < ntot) {
-      double u[3], w;
-      bool ran;
-      if (a.colmode)
-        key = particle_u(a, i, u, &w, &ran) ? column_key(a, u) : 0;              // column 0, class 0
-      else
-        key = particle_u(a, i, u, &w, &ran) ? bucket_key(a, u) : kClasses / 2;   // tile 0, middle class
-      a.keys[i] = key;
-    }
+    const int key = i < ntot ? particle_key(a, i) : -1;
     const int prev = __shfl_up(key, 1);
     const bool head = lane == 0 || key != prev;
     const unsigned long long heads = __ballot(head);
-    if (head && key >= 0) atomicAdd(&a.count[key], run_end(heads, lane) - lane);
+    int off = 0;
+    if (head && key >= 0) off = atomicAdd(&a.count[key], run_end(heads, lane) - lane);
+    const int hl = run_head(heads, lane);
+    off = __shfl(off, hl) + (lane - hl);
+    if (i < ntot) a.keys[i] = off;
   }
 }
 
@@ -484,22 +489,13 @@ template <typename T, int NCH>
 __global__ void __launch_bounds__(kBlock) bucket_fill_kernel(FillArgs<T, NCH> a) {
   const int64_t ntot = a.b.d.n + a.b.r.n;
   const double alpha = a.scal->alpha;
-  const int lane = threadIdx.x & 63;
-  for (int64_t base = (int64_t)blockIdx.x * kBlock; base < ntot; base += (int64_t)gridDim.x * kBlock) {
-    const int64_t i = base + threadIdx.x;
-    const int key = i < ntot ? a.b.keys[i] : -1;
-    const int prev = __shfl_up(key, 1);
-    const bool head = lane == 0 || key != prev;
-    const unsigned long long heads = __ballot(head);
-    int off = 0;
-    if (head && key >= 0) off = atomicAdd(&a.b.cursor[key], run_end(heads, lane) - lane);
-    const int hl = run_head(heads, lane);
-    off = __shfl(off, hl) + (lane - hl);
-    if (key < 0) continue;
-    const int64_t slot = (int64_t)a.b.start[key] + off;
+  for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < ntot; i += (int64_t)gridDim.x * kBlock) {
     double u[3], w;
     bool ran;
     const bool ok = particle_u(a.b, i, u, &w, &ran);
+    // the key again (as particle_key forms it) and the offset the count kept
+    const int key = ok ? (a.b.colmode ? column_key(a.b, u) : bucket_key(a.b, u)) : (a.b.colmode ? 0 : kClasses / 2);
+    const int64_t slot = (int64_t)a.b.start[key] + a.b.keys[i];
     const CatPtrs& c = ran ? a.b.r : a.b.d;
     const int64_t j = ran ? i - a.b.d.n : i;
     double* ru = a.rec.u(slot);
@@ -1856,7 +1852,6 @@ int run_assign(Plan& P, const tsb_catalog* data, const tsb_catalog* rand, hipStr
   b.copies = P.copies;
   b.box_mode = P.box_mode;
   b.count = P.d_bk_count;
-  b.cursor = P.d_bk_cursor;
   b.start = P.d_bk_start;
   b.keys = P.d_keys;
   b.colmode = zcol_active(P) ? 1 : 0;
