@@ -120,8 +120,7 @@ int carve_workspace(Plan& P, Carver& cv, int64_t& B) {
   ALLOC(P.d_fields, ((P.fused ? 0 : nf) + ng) * M * M * M * c);
   const int64_t ntiles = (int64_t)P.NT * P.NT * P.NT;
   P.nbk = assign_bucket_keys(P);
-  ALLOC(P.d_bk_count, (2 * P.nbk + 2) * 4);   // counts, cursors, heavy-slot and extra-part counters
-  P.d_bk_cursor = P.d_bk_count ? P.d_bk_count + P.nbk : nullptr;
+  ALLOC(P.d_bk_count, (P.nbk + 2) * 4);   // counts, then the heavy-slot and extra-part counters
   ALLOC(P.d_bk_start, (P.nbk + 1) * 4);
   ALLOC(P.d_scan_part, ((P.nbk + kScanChunk - 1) / kScanChunk + 1) * 4);
   ALLOC(P.d_tile_hslot, ntiles * 4);
@@ -1573,7 +1572,7 @@ int scratch_base(int dev, char** out) {
 // pointed into the scratch and put back afterwards.
 struct WorkspaceState {
   void *grid, *t1, *t2, *t3, *spec, *dcube, *u1, *u2, *fields, *heavy, *rec, *work;
-  int *bk_count, *bk_cursor, *bk_start, *scan_part, *tile_hslot, *heavy_tile, *keys;
+  int *bk_count, *bk_start, *scan_part, *tile_hslot, *heavy_tile, *keys;
   double *partials, *B, *sum_partials;
   DevScalars* scal;
   int64_t nbk, particle_cap, work_cap;
@@ -1582,7 +1581,7 @@ struct WorkspaceState {
   explicit WorkspaceState(const Plan& P)
       : grid(P.d_grid), t1(P.d_t1), t2(P.d_t2), t3(P.d_t3), spec(P.d_spec), dcube(P.d_dcube), u1(P.d_u1),
         u2(P.d_u2), fields(P.d_fields), heavy(P.d_heavy), rec(P.d_rec), work(P.d_work), bk_count(P.d_bk_count),
-        bk_cursor(P.d_bk_cursor), bk_start(P.d_bk_start), scan_part(P.d_scan_part), tile_hslot(P.d_tile_hslot),
+        bk_start(P.d_bk_start), scan_part(P.d_scan_part), tile_hslot(P.d_tile_hslot),
         heavy_tile(P.d_heavy_tile), keys(P.d_keys), partials(P.d_partials), B(P.d_B),
         sum_partials(P.d_sum_partials), scal(P.d_scal), nbk(P.nbk), particle_cap(P.particle_cap),
         work_cap(P.work_cap), prof(P.prof) {}
@@ -1590,7 +1589,7 @@ struct WorkspaceState {
   void restore(Plan& P) const {
     P.d_grid = grid; P.d_t1 = t1; P.d_t2 = t2; P.d_t3 = t3; P.d_spec = spec; P.d_dcube = dcube;
     P.d_u1 = u1; P.d_u2 = u2; P.d_fields = fields; P.d_heavy = heavy; P.d_rec = rec; P.d_work = work;
-    P.d_bk_count = bk_count; P.d_bk_cursor = bk_cursor; P.d_bk_start = bk_start; P.d_scan_part = scan_part;
+    P.d_bk_count = bk_count; P.d_bk_start = bk_start; P.d_scan_part = scan_part;
     P.d_tile_hslot = tile_hslot; P.d_heavy_tile = heavy_tile; P.d_keys = keys; P.d_partials = partials;
     P.d_B = B; P.d_sum_partials = sum_partials; P.d_scal = scal; P.nbk = nbk; P.particle_cap = particle_cap;
     P.work_cap = work_cap; P.prof = prof;

@@ -1712,7 +1712,7 @@ int assign_back_impl(Plan& P, const ChanInfo& ci, hipStream_t s) {
   a.tile_I = P.d_sum_partials;
   a.nr = tile_ranges(P.NT, a.rd, a.rcl, a.rch);
   if (a.nr > kMaxRanges) return fail(TSB_E_UNSUPPORTED, "assignment: too many bucket ranges");
-  int* nheavy = P.d_bk_count + 2 * P.nbk;   // heavy slots and extra parts: cleared with the bucket counters
+  int* nheavy = P.d_bk_count + P.nbk;   // heavy slots and extra parts: cleared with the bucket counts
   int* nextra = nheavy + 1;
   a.work = (const int2*)P.d_work;
   a.nextra = nextra;
@@ -1859,9 +1859,8 @@ int run_assign(Plan& P, const tsb_catalog* data, const tsb_catalog* rand, hipStr
   const int64_t nbk = b.colmode ? (int64_t)(P.N / kColW) * (P.N / kColW) * kColClasses : P.nbk;
   const int nparts = (int)((nbk + kScanChunk - 1) / kScanChunk);
   prof_begin(P, kStBucket, s);
-  // counts, cursors and the heavy-slot counter are adjacent: one fill clears them
-  hipLaunchKernelGGL(zero_ints_kernel, dim3(grid_blocks(2 * P.nbk + 2)), dim3(kBlock), 0, s, P.d_bk_count,
-                     2 * P.nbk + 2);
+  // counts and the heavy-slot counters are adjacent: one fill clears them
+  hipLaunchKernelGGL(zero_ints_kernel, dim3(grid_blocks(P.nbk + 2)), dim3(kBlock), 0, s, P.d_bk_count, P.nbk + 2);
   if (ntot > 0)
     hipLaunchKernelGGL(bucket_count_kernel, dim3(grid_blocks(ntot)), dim3(kBlock), 0, s, b);
   hipLaunchKernelGGL(scan_sums_kernel, dim3(nparts), dim3(kBlock), 0, s, (const int*)P.d_bk_count, nbk,

@@ -188,7 +188,6 @@ struct Plan {
   void* d_yspec = nullptr;      // box mode, local LOS: combined spectra of y_L^M*(x^_node) [ngrid][PG^3]
   bool yspec_ready = false;     // subtract mean * d_yspec in the combine step
   int* d_bk_count = nullptr;    // particles per (tile, reach class) bucket [nbk]
-  int* d_bk_cursor = nullptr;   // fill cursors [nbk] (directly after d_bk_count)
   int* d_bk_start = nullptr;    // bucket starts [nbk + 1]
   int* d_scan_part = nullptr;   // per-workgroup sums of the bucket scan
   int64_t nbk = 0;              // tiles * 27
