@@ -1298,17 +1298,19 @@ __global__ void __launch_bounds__(kZBlock) zcol_kernel(ZColArgs a, Records<float
   const int et = tile_exponent(nv, a.scal->cmax * a.wmax);
   const float tscale = ldexpf(1.0f, et);
   const int lg = kColW * kColW * LS;   // words between the lines of consecutive grids
-  // visits in a scrambled order (a multiplier prime to their number): the
-  // lanes of a wavefront take particles far apart in the bucket order, which
-  // follows the catalogue's, so that their atomics rarely share a word
-  const int vmult = nv % 97 ? 97 : (nv % 101 ? 101 : (nv % 103 ? 103 : 1));
+  // visits range by range (the lanes of a wavefront mostly share a range, so
+  // their stencils cross the column alike), each range in a scrambled order (a
+  // multiplier prime to its length): neighbouring lanes take particles far
+  // apart in the bucket order, which follows the catalogue's, so that their
+  // atomics rarely share a word
   // a thread's next visit is loaded while the current one is added
-  auto load_visit = [&](int v0, double* u, float* c) {
-    const int v = (int)(((int64_t)v0 * vmult) % nv);
+  auto load_visit = [&](int v, double* u, float* c) {
     int r = 0;   // the range holding visit v: r_off[r] <= v < r_off[r + 1]
     for (int step = 8; step > 0; step >>= 1)
       if (r + step < a.nr && r_off[r + step] <= v) r += step;
-    const int64_t slot = (int64_t)r_st[r] + (v - r_off[r]);
+    const int len = r_off[r + 1] - r_off[r];
+    const int mult = len % 97 ? 97 : (len % 101 ? 101 : (len % 103 ? 103 : 1));
+    const int64_t slot = (int64_t)r_st[r] + (int)(((int64_t)(v - r_off[r]) * mult) % len);
     const double* ru = rec.u(slot);
     u[0] = ru[0];
     u[1] = ru[1];
